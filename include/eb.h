@@ -1,0 +1,223 @@
+/*
+ * eb.h — edge-based grid metrics on one MI355X (gfx950), C ABI.
+ *
+ * Computes, for a triangle (dim = 2) or tetrahedral (dim = 3) grid, the
+ * metrics of the node-centred edge-based discretization (Nishikawa,
+ * "An Efficient Implementation of Edge-Based Discretization without Forming
+ * Dual Control Volumes", Section 2, eq. threed_fv_semidiscrete_system_00)
+ * directly from element geometry, never forming a median dual:
+ *
+ *   n_e  lumped directed-area vector of every edge e = {j,k}, j < k, pointing
+ *        from j to k (Section 2: edges run from the smaller node number);
+ *          n_jk = 2/(D(D+1)) * sum_{E contains jk} n_j^E        (eq.
+ *                 efficient_njk_formula_general_D, Section 3.2.3)
+ *               + 1/(D(D+1)) * sum_{boundary elements B containing jk} n_B
+ *        where n_j^E is the outward area vector of the face of E opposite j;
+ *   b_j  dual-face area vector at boundary node j: (1/D) sum_{B contains j}
+ *        n_B (the boundary term of the closure check, Section 3.2.3);
+ *   V_j  median-dual volume: sum_{E contains j} |E|/(D+1) (Section 4.2), or
+ *        by the edge loop (1/(2D)) sum_k (x_k - x_j).n_jk (Section 4.1).
+ *
+ * and the topology those loops need (unique edges, element -> edge map with
+ * orientation signs, boundary elements, incidence lists), plus the adjoint of
+ * n, b and V with respect to the node coordinates.
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer on the current HIP device
+ *     unless its name ends in _host.  Pointers must be 16-byte aligned
+ *     (hipMalloc and torch allocations are); lengths are element counts.
+ *   - coords is structure-of-arrays FP64 [dim][n_nodes]; elem is int32
+ *     [n_elems][dim+1] with any local vertex order (either orientation).
+ *   - All outputs are overwritten, never accumulated into; inputs are const.
+ *   - ne = 3 (dim 2) or 6 (dim 3) local edges per element, in the local pair
+ *     order 2D (0,1)(0,2)(1,2); 3D (0,1)(0,2)(0,3)(1,2)(1,3)(2,3).
+ *   - Calls enqueue work on `stream` and return at once, except
+ *     eb_build_edges and eb_check_errors, which synchronize `stream`.
+ *   - The caller owns every buffer.  The library allocates no device memory
+ *     and keeps no state between calls except a thread-local error detail
+ *     string and the gather launch shape (eb_set_gather_shape); scratch
+ *     lives in the caller's workspace `ws`.
+ *   - Returns EB_OK (0) or a negative eb_status.  Errors found on the host
+ *     (bad arguments, sizes beyond int32 indexing, workspace too small) return
+ *     at once and enqueue nothing.  Errors found by kernels (node id out of
+ *     range, zero-measure element, a face shared by more than two elements,
+ *     a node beyond the per-node capacity) set a sticky status word in `ws`;
+ *     eb_build_edges reports it, other calls leave it for eb_check_errors.
+ *     Outputs are undefined after any error.  HIP failures return EB_EHIP
+ *     with hipGetErrorString text in eb_last_error_detail().
+ *   - Calls that share one `ws` must not run concurrently on different
+ *     streams.
+ */
+#ifndef EB_H
+#define EB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EB_OK = 0,
+  EB_EINVAL = -1,       /* null pointer, bad dim/mode, misaligned, negative size */
+  EB_ERANGE = -2,       /* element references a node id outside [0, n_nodes) */
+  EB_EDEGENERATE = -3,  /* element of zero measure */
+  EB_ENONMANIFOLD = -4, /* face (3D) or edge (2D) shared by more than two elements */
+  EB_EWORKSPACE = -5,   /* ws_bytes below eb_workspace_bytes() */
+  EB_EOVERFLOW = -6,    /* counts that would overflow int32 indexing */
+  EB_EHIP = -7,         /* HIP runtime error */
+  EB_ECAPACITY = -8     /* a node has more than EB_MAX_OUT_EDGES higher-numbered
+                           neighbours, or more than EB_MAX_NODE_FACES faces with
+                           it as smallest vertex */
+} eb_status;
+
+#define EB_MAX_OUT_EDGES 32
+#define EB_MAX_NODE_FACES 64
+
+typedef enum { EB_REDUCE_ATOMIC = 0, EB_REDUCE_GATHER = 1 } eb_reduce;
+typedef enum { EB_VOL_ELEMENT = 0, EB_VOL_EDGE = 1 } eb_vol_mode;
+
+/* Sizes of one grid; filled by eb_build_edges. */
+typedef struct {
+  int32_t dim;
+  int64_t n_nodes, n_elems, n_edges, n_bfaces, n_bnodes;
+} eb_sizes;
+
+/* Topology arrays (device).  Every integer output is uniquely defined, so two
+ * builds of the same grid give identical bits.
+ *   edge           [2][n_edges]   row 0 tails, row 1 heads (tail < head), in
+ *                                 ascending (tail, head) order (the paper's
+ *                                 edge(e,1), edge(e,2), Section 2)
+ *   node_edge_off  [n_nodes+1]    edges with tail j are [off[j], off[j+1])
+ *   elem_edge      [n_elems][ne]  edge id of each local edge
+ *   elem_edge_sign [n_elems][ne]  +1 iff elem[p] < elem[q] (local p -> q is
+ *                                 the edge direction), else -1
+ *   edge_inc_off   [n_edges+1]    optional (NULL skips): elements of each edge
+ *   edge_inc       [ne*n_elems]     as elem*ne + local, ascending per edge
+ *   node_inc_off   [n_nodes+1]    elements of each node as elem*(dim+1) +
+ *   node_inc       [(dim+1)*n_elems]  local vertex, ascending per node
+ *   node_in_off    [n_nodes+1]    ids of edges whose head is the node,
+ *   node_in_edge   [n_edges]        ascending per node
+ *   bface          [n_bfaces][dim] boundary elements (faces of exactly one
+ *                                 element), ascending by sorted vertex ids;
+ *                                 vertices ordered so that the area vector
+ *                                 2D (dy,-dx) of v0->v1, 3D (1/2)(v1-v0)x(v2-v0)
+ *                                 points out of the domain; 3D rotated so the
+ *                                 smallest id comes first
+ *   bface_owner    [n_bfaces]     elem*(dim+1) + local index of the owner's
+ *                                 vertex opposite the face
+ *   bface_edge     [n_bfaces][dim*(dim-1)/2]  edge ids of (v0,v1) | (v0,v1),
+ *                                 (v0,v2), (v1,v2)
+ *   bnode          [n_bnodes]     ascending ids of nodes on boundary faces
+ *   node_bnode     [n_nodes]      index into bnode, or -1 for interior nodes
+ *   bnode_face_off [n_bnodes+1]   boundary faces of each boundary node,
+ *   bnode_face     [dim*n_bfaces]   ascending per node
+ */
+typedef struct {
+  int32_t *edge;
+  int32_t *node_edge_off;
+  int32_t *elem_edge;
+  int8_t *elem_edge_sign;
+  int32_t *edge_inc_off, *edge_inc;
+  int32_t *node_inc_off, *node_inc;
+  int32_t *node_in_off, *node_in_edge;
+  int32_t *bface;
+  int32_t *bface_owner;
+  int32_t *bface_edge;
+  int32_t *bnode;
+  int32_t *node_bnode;
+  int32_t *bnode_face_off, *bnode_face;
+} eb_topology;
+
+/* Bytes of workspace every call below needs for a grid of this size. */
+size_t eb_workspace_bytes(int dim, int64_t n_nodes, int64_t n_elems);
+
+/* Edge extraction, phase 1 (Section 2: the edge array; Section 3.2: boundary
+ * elements).  Validates the grid, builds the node -> element lists into the
+ * caller's node_inc_off [n_nodes+1] and node_inc [(dim+1)*n_elems] (their
+ * sizes are known in advance), counts unique edges, boundary faces and
+ * boundary nodes into ws, and fills *sizes_host.  Synchronizes `stream` once
+ * and returns the sticky device status.  coords [dim][n_nodes] are needed to
+ * orient boundary faces outward and to reject zero-measure elements. */
+int eb_build_edges(int dim, int64_t n_nodes, int64_t n_elems, const int32_t *elem,
+                   const double *coords, int32_t *node_inc_off, int32_t *node_inc,
+                   void *ws, size_t ws_bytes, eb_sizes *sizes_host, hipStream_t stream);
+
+/* Edge extraction, phase 2: writes every other eb_topology array (sized from
+ * *sizes) using the counts eb_build_edges left in ws.  topo->node_inc_off and
+ * topo->node_inc must be the arrays phase 1 filled.  edge_inc_off/edge_inc may
+ * be NULL. */
+int eb_build_edges_emit(const eb_sizes *sizes, const int32_t *elem, const double *coords,
+                        const eb_topology *topo, void *ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* Lumped directed-area vectors n_edge [dim][n_edges] (eq.
+ * efficient_njk_formula_general_D plus the boundary correction, Section
+ * 3.2.3), boundary dual-face normals b_node [dim][n_bnodes] (NULL to skip)
+ * and element-based dual volumes vol [n_nodes] (Section 4.2; NULL to skip),
+ * in one pass over the grid.
+ *   EB_REDUCE_ATOMIC: one thread per element, FP64 atomic adds into zeroed
+ *     outputs (summation order varies from run to run).
+ *   EB_REDUCE_GATHER: one thread per node gathers over its elements in
+ *     node_inc order and owns the edges it is the tail of; every output is
+ *     written once, bitwise reproducible.  Needs node_inc, node_edge_off,
+ *     edge, node_bnode, bnode_face_off/bnode_face, bface. */
+int eb_directed_areas(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
+                      const double *coords, int reduce, double *n_edge, double *b_node,
+                      double *vol, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Dual volumes vol [n_nodes].
+ *   EB_VOL_ELEMENT: sum of |E|/(D+1) over the elements of each node
+ *     (Section 4.2); n_edge unused.
+ *   EB_VOL_EDGE: the edge loop V_j = (1/(2D)) sum_k (x_k - x_j).n_jk over the
+ *     edges of j (Section 4.1), from the boundary-corrected n_edge
+ *     [dim][n_edges] of eb_directed_areas.  ATOMIC: thread per edge, FP64
+ *     atomics to both ends; GATHER: thread per node over node_edge_off and
+ *     node_in rows. */
+int eb_dual_volumes(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
+                    const double *coords, int mode, const double *n_edge, int reduce,
+                    double *vol, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Adjoint: given grad_n = dL/dn [dim][n_edges], grad_b = dL/db [dim][n_bnodes]
+ * and grad_vol = dL/dV [n_nodes] (any may be NULL = zero), writes
+ * grad_coords = dL/dx [dim][n_nodes] for the metrics eb_directed_areas
+ * computes (element-based V).  Derivative of the element and boundary
+ * formulas above; the orientation sign of each element is held fixed.
+ * ATOMIC: thread per element/boundary face with FP64 atomics; GATHER: thread
+ * per node, bitwise reproducible. */
+int eb_directed_areas_backward(const eb_sizes *sizes, const eb_topology *topo,
+                               const int32_t *elem, const double *coords,
+                               const double *grad_n, const double *grad_b,
+                               const double *grad_vol, int reduce, double *grad_coords,
+                               void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Launch shape of the node-centred (EB_REDUCE_GATHER) kernels: nodes per
+ * block (64, 128 or 256), incidences whose loads are issued together per
+ * thread (1, 2 or 4), and whether consecutive node tiles are kept on one XCD
+ * (0/1).  Process-wide setting (the one piece of state the library keeps,
+ * besides the error detail), meant to be set once from a tuning run; it
+ * changes speed only, never results.  Returns EB_EINVAL for other values. */
+int eb_set_gather_shape(int tile, int unroll, int xcd_remap);
+void eb_get_gather_shape(int *tile, int *unroll, int *xcd_remap);
+
+/* Synchronizes `stream`, returns the sticky device status in ws and resets it
+ * to EB_OK. */
+int eb_check_errors(void *ws, hipStream_t stream);
+
+/* Static text for a status code. */
+const char *eb_status_string(int status);
+
+/* Thread-local detail of the last error returned on this thread ("" if none). */
+const char *eb_last_error_detail(void);
+
+/* Library version string. */
+const char *eb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EB_H */

@@ -1,0 +1,96 @@
+"""ctypes loader for ``libeb.so`` — argument marshalling only.
+
+The library must have been built (``python -m paper_2502_00778_amd.build`` or
+``__graft_entry__.build()``); there is no fallback: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libeb.so")
+
+EB_OK = 0
+EB_REDUCE_ATOMIC, EB_REDUCE_GATHER = 0, 1
+EB_VOL_ELEMENT, EB_VOL_EDGE = 0, 1
+STATUS_NAMES = {0: "EB_OK", -1: "EB_EINVAL", -2: "EB_ERANGE", -3: "EB_EDEGENERATE",
+                -4: "EB_ENONMANIFOLD", -5: "EB_EWORKSPACE", -6: "EB_EOVERFLOW",
+                -7: "EB_EHIP", -8: "EB_ECAPACITY"}
+
+# every symbol declared in include/eb.h
+EXPORTS = ("eb_workspace_bytes", "eb_build_edges", "eb_build_edges_emit",
+           "eb_directed_areas", "eb_dual_volumes", "eb_directed_areas_backward",
+           "eb_set_gather_shape", "eb_get_gather_shape", "eb_check_errors",
+           "eb_status_string", "eb_last_error_detail", "eb_version")
+
+TOPO_FIELDS = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign",
+               "edge_inc_off", "edge_inc", "node_inc_off", "node_inc",
+               "node_in_off", "node_in_edge", "bface", "bface_owner",
+               "bface_edge", "bnode", "node_bnode", "bnode_face_off",
+               "bnode_face")
+
+
+class EbSizes(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n_nodes", ctypes.c_int64),
+                ("n_elems", ctypes.c_int64), ("n_edges", ctypes.c_int64),
+                ("n_bfaces", ctypes.c_int64), ("n_bnodes", ctypes.c_int64)]
+
+
+class EbTopology(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in TOPO_FIELDS]
+
+
+class EbError(RuntimeError):
+    def __init__(self, code: int, call: str, detail: str = ""):
+        name = STATUS_NAMES.get(code, str(code))
+        super().__init__(f"{call} failed: {name}"
+                         + (f" ({detail})" if detail else ""))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python -m paper_2502_00778_amd.build); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, sz = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                       ctypes.c_size_t)
+    L.eb_workspace_bytes.argtypes = [i32, i64, i64]
+    L.eb_workspace_bytes.restype = sz
+    L.eb_build_edges.argtypes = [i32, i64, i64, P, P, P, P, P, sz,
+                                 ctypes.POINTER(EbSizes), P]
+    L.eb_build_edges_emit.argtypes = [ctypes.POINTER(EbSizes), P, P,
+                                      ctypes.POINTER(EbTopology), P, sz, P]
+    L.eb_directed_areas.argtypes = [ctypes.POINTER(EbSizes),
+                                    ctypes.POINTER(EbTopology), P, P, i32, P,
+                                    P, P, P, sz, P]
+    L.eb_dual_volumes.argtypes = [ctypes.POINTER(EbSizes),
+                                  ctypes.POINTER(EbTopology), P, P, i32, P,
+                                  i32, P, P, sz, P]
+    L.eb_directed_areas_backward.argtypes = [ctypes.POINTER(EbSizes),
+                                             ctypes.POINTER(EbTopology), P, P,
+                                             P, P, P, i32, P, P, sz, P]
+    L.eb_set_gather_shape.argtypes = [i32, i32, i32]
+    L.eb_get_gather_shape.argtypes = [ctypes.POINTER(ctypes.c_int)] * 3
+    L.eb_get_gather_shape.restype = None
+    L.eb_check_errors.argtypes = [P, P]
+    L.eb_status_string.argtypes = [i32]
+    L.eb_status_string.restype = ctypes.c_char_p
+    L.eb_last_error_detail.restype = ctypes.c_char_p
+    L.eb_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def check(rc: int, call: str):
+    if rc != EB_OK:
+        detail = lib().eb_last_error_detail().decode(errors="replace")
+        raise EbError(rc, call, detail)

@@ -1,0 +1,231 @@
+// Adjoint of the metrics with respect to the node coordinates.
+//
+// For a loss L = sum_e w_e.n_e + sum_j c_j V_j + sum_j beta_j.b_j the
+// forward formulas give, per element E (orientation sign s held fixed),
+//   L_E = sum_t W_t.n_t + C_E |E|,
+//   W_t = 2/(D(D+1)) * sum of w_e over the local edges whose tail is t,
+//   C_E = (1/(D+1)) sum_{i in E} c_i,
+// and per boundary element B
+//   L_B = W_B.n_B,  W_B = 1/(D(D+1)) sum_{e in B} w_e + (1/D) sum_{i in B} beta_i.
+// Derivatives (3D, face (a,b,c) in cyclic outward order, N = s/2 (x_b-x_a) x
+// (x_c-x_a)):  d(W.N)/dx_a = s/2 (x_b - x_c) x W, and cyclically;
+//        (2D, N = s rot(x_c - x_b), rot(d) = (d_y, -d_x)):
+//              d(W.N)/dx_c = s R(W), d(W.N)/dx_b = -s R(W), R(W) = (-W_y, W_x);
+// and d|E|/dx_i = -n_i/D (moving a vertex against its opposite face's
+// outward normal grows the element).
+#include "eb_geom.h"
+#include "eb_kernels.h"
+
+namespace eb {
+
+template <int D>
+__device__ __forceinline__ V3 load_row3(const double *x, const double *y, const double *z,
+                                        int64_t i) {
+  if (D == 3) return {x[i], y[i], z[i]};
+  return {x[i], y[i], 0.0};
+}
+
+// W_t for every local vertex t and C_E of element e
+template <int D>
+__device__ __forceinline__ void elem_weights(const FwdArgs &a, int64_t e, const int32_t (&v)[D + 1],
+                                             V3 (&W)[D + 1], double &C) {
+  constexpr int NE = EL<D>::NE;
+  constexpr double kN = 2.0 / (D * (D + 1));
+#pragma unroll
+  for (int t = 0; t <= D; ++t) W[t] = {0.0, 0.0, 0.0};
+  if (a.w_x) {
+#pragma unroll
+    for (int le = 0; le < NE; ++le) {
+      const int p = pair_p<D>(le), q = pair_q<D>(le);
+      const int32_t ed = a.elem_edge[e * NE + le];
+      const V3 w = load_row3<D>(a.w_x, a.w_y, a.w_z, ed);
+      const int tl = v[p] < v[q] ? p : q;
+      W[tl] = W[tl] + kN * w;
+    }
+  }
+  C = 0.0;
+  if (a.c) {
+#pragma unroll
+    for (int i = 0; i <= D; ++i) C += a.c[v[i]];
+    C *= 1.0 / (D + 1);
+  }
+}
+
+// dL_E/dx_l for local vertex l
+template <int D>
+__device__ __forceinline__ V3 elem_grad(const V3 (&P)[D + 1], const V3 (&n)[D + 1], double det,
+                                        const V3 (&W)[D + 1], double C, int l) {
+  V3 G = (-C / D) * n[l];
+  if constexpr (D == 3) {
+    const double hs = det > 0 ? 0.5 : -0.5;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t == l) continue;
+      int p = 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (face3(t, k) == l) p = k;
+      const int nx = face3(t, (p + 1) % 3), pv = face3(t, (p + 2) % 3);
+      G = G + hs * cross(P[nx] - P[pv], W[t]);
+    }
+  } else {
+    const double s = det > 0 ? 1.0 : -1.0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      if (t == l) continue;
+      const V3 R = s * rotW(W[t]);
+      if (l == (t + 2) % 3) G = G + R;
+      else G = G - R;
+    }
+  }
+  return G;
+}
+
+template <int D>
+__device__ __forceinline__ V3 bface_weight(const FwdArgs &a, int64_t f, const int32_t (&fv)[D]) {
+  constexpr int NBE = D == 2 ? 1 : 3;
+  V3 W = {0.0, 0.0, 0.0};
+  if (a.w_x) {
+    constexpr double kB = 1.0 / (D * (D + 1));
+#pragma unroll
+    for (int i = 0; i < NBE; ++i) {
+      const int32_t ed = a.bface_edge[f * NBE + i];
+      W = W + kB * load_row3<D>(a.w_x, a.w_y, a.w_z, ed);
+    }
+  }
+  if (a.be_x) {
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+      const int32_t bi = a.node_bnode[fv[s]];
+      W = W + (1.0 / D) * load_row3<D>(a.be_x, a.be_y, a.be_z, bi);
+    }
+  }
+  return W;
+}
+
+// d(W.n_B)/dx of face vertex p
+template <int D>
+__device__ __forceinline__ V3 bface_grad(const V3 (&P)[D], V3 W, int p) {
+  if constexpr (D == 3) {
+    const int nx = (p + 1) % 3, pv = (p + 2) % 3;
+    return 0.5 * cross(P[nx] - P[pv], W);
+  } else {
+    const V3 R = rotW(W);
+    return p == 1 ? R : -R;
+  }
+}
+
+// ------------------------------------------------------------- atomic path
+
+template <int D>
+__global__ __launch_bounds__(256) void k_bwd_atomic_elem(FwdArgs a) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nelem) return;
+  int32_t v[D + 1];
+  load_conn<D>(a.elem, e, v);
+  V3 P[D + 1], n[D + 1], W[D + 1];
+#pragma unroll
+  for (int i = 0; i <= D; ++i) P[i] = load_pt<D>(a.X, v[i]);
+  const double det = elem_normals<D>(P, n);
+  double C;
+  elem_weights<D>(a, e, v, W, C);
+#pragma unroll
+  for (int l = 0; l <= D; ++l) {
+    const V3 G = elem_grad<D>(P, n, det, W, C, l);
+    unsafeAtomicAdd(&a.g_x[v[l]], G.x);
+    unsafeAtomicAdd(&a.g_y[v[l]], G.y);
+    if (D == 3) unsafeAtomicAdd(&a.g_z[v[l]], G.z);
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_bwd_atomic_bface(FwdArgs a) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= a.nbface) return;
+  int32_t fv[D];
+  V3 P[D];
+#pragma unroll
+  for (int s = 0; s < D; ++s) {
+    fv[s] = a.bface[f * D + s];
+    P[s] = load_pt<D>(a.X, fv[s]);
+  }
+  const V3 W = bface_weight<D>(a, f, fv);
+#pragma unroll
+  for (int p = 0; p < D; ++p) {
+    const V3 G = bface_grad<D>(P, W, p);
+    unsafeAtomicAdd(&a.g_x[fv[p]], G.x);
+    unsafeAtomicAdd(&a.g_y[fv[p]], G.y);
+    if (D == 3) unsafeAtomicAdd(&a.g_z[fv[p]], G.z);
+  }
+}
+
+// ------------------------------------------------------------- gather path
+
+template <int D>
+__global__ __launch_bounds__(256) void k_bwd_gather(FwdArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.nv) return;
+  V3 g = {0.0, 0.0, 0.0};
+  for (int32_t r = a.node_inc_off[j]; r < a.node_inc_off[j + 1]; ++r) {
+    const int32_t inc = a.node_inc[r];
+    const int64_t e = inc / (D + 1);
+    const int l = inc - (int)(e * (D + 1));
+    int32_t v[D + 1];
+    load_conn<D>(a.elem, e, v);
+    V3 P[D + 1], n[D + 1], W[D + 1];
+#pragma unroll
+    for (int i = 0; i <= D; ++i) P[i] = load_pt<D>(a.X, v[i]);
+    const double det = elem_normals<D>(P, n);
+    double C;
+    elem_weights<D>(a, e, v, W, C);
+    g = g + elem_grad<D>(P, n, det, W, C, l);
+  }
+  const int32_t bj = a.node_bnode ? a.node_bnode[j] : -1;
+  if (bj >= 0 && (a.w_x || a.be_x)) {
+    for (int32_t r = a.bnode_face_off[bj]; r < a.bnode_face_off[bj + 1]; ++r) {
+      const int32_t f = a.bnode_face[r];
+      int32_t fv[D];
+      V3 P[D];
+      int p = 0;
+#pragma unroll
+      for (int s = 0; s < D; ++s) {
+        fv[s] = a.bface[(int64_t)f * D + s];
+        P[s] = load_pt<D>(a.X, fv[s]);
+        if (fv[s] == j) p = s;
+      }
+      g = g + bface_grad<D>(P, bface_weight<D>(a, f, fv), p);
+    }
+  }
+  a.g_x[j] = g.x;
+  a.g_y[j] = g.y;
+  if (D == 3) a.g_z[j] = g.z;
+}
+
+template <int D>
+int backward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_t s) {
+  (void)cfg;
+  if (reduce == EB_REDUCE_ATOMIC) {
+    EB_TRY(fill_f64(a.g_x, a.nv, 0.0, s));
+    EB_TRY(fill_f64(a.g_y, a.nv, 0.0, s));
+    if (D == 3) EB_TRY(fill_f64(a.g_z, a.nv, 0.0, s));
+    if (a.nelem > 0 && (a.w_x || a.c)) {
+      hipLaunchKernelGGL(k_bwd_atomic_elem<D>, dim3(grid_for(a.nelem, 256)), dim3(256), 0, s,
+                         a);
+      EB_LAUNCH_CHECK();
+    }
+    if (a.nbface > 0 && (a.w_x || a.be_x)) {
+      hipLaunchKernelGGL(k_bwd_atomic_bface<D>, dim3(grid_for(a.nbface, 256)), dim3(256), 0, s,
+                         a);
+      EB_LAUNCH_CHECK();
+    }
+    return EB_OK;
+  }
+  hipLaunchKernelGGL(k_bwd_gather<D>, dim3(grid_for(a.nv, 256)), dim3(256), 0, s, a);
+  EB_LAUNCH_CHECK();
+  return EB_OK;
+}
+
+template int backward_impl<2>(const FwdArgs &, int, const LaunchCfg &, hipStream_t);
+template int backward_impl<3>(const FwdArgs &, int, const LaunchCfg &, hipStream_t);
+
+}  // namespace eb

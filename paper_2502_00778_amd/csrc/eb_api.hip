@@ -1,0 +1,185 @@
+// C-ABI entry points for the metric, volume and adjoint calls: host-side
+// validation, argument packing, launch-shape choice.
+#include "eb_kernels.h"
+
+namespace eb {
+
+namespace {
+LaunchCfg g_cfg;  // process-wide launch shape of the gather kernels
+}
+
+LaunchCfg default_cfg() { return g_cfg; }
+
+namespace {
+
+int pack(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem, const double *coords,
+         void *ws, size_t ws_bytes, FwdArgs &a) {
+  EB_TRY(check_sizes(sz));
+  if (!tp || !coords || (sz->n_elems > 0 && !elem)) {
+    set_detail("null pointer");
+    return EB_EINVAL;
+  }
+  if (!aligned16(elem) || !aligned16(coords)) {
+    set_detail("arrays must be 16-byte aligned");
+    return EB_EINVAL;
+  }
+  EB_TRY(check_ws(sz->dim, sz->n_nodes, sz->n_elems, ws, ws_bytes));
+  a = FwdArgs{};
+  a.nv = sz->n_nodes;
+  a.nelem = sz->n_elems;
+  a.nedge = sz->n_edges;
+  a.nbface = sz->n_bfaces;
+  a.nbnode = sz->n_bnodes;
+  a.elem = elem;
+  a.X = coords_rows(coords, sz->dim, sz->n_nodes);
+  a.elem_edge = tp->elem_edge;
+  a.node_inc_off = tp->node_inc_off;
+  a.node_inc = tp->node_inc;
+  a.node_edge_off = tp->node_edge_off;
+  a.edge_tail = tp->edge;
+  a.edge_head = tp->edge ? tp->edge + sz->n_edges : nullptr;
+  a.node_in_off = tp->node_in_off;
+  a.node_in_edge = tp->node_in_edge;
+  a.bface = tp->bface;
+  a.bface_edge = tp->bface_edge;
+  a.node_bnode = tp->node_bnode;
+  a.bnode_face_off = tp->bnode_face_off;
+  a.bnode_face = tp->bnode_face;
+  a.st = ws_at<StatusBlock>(ws, 0);
+  return EB_OK;
+}
+
+int need(bool ok, const char *what) {
+  if (ok) return EB_OK;
+  set_detail("missing topology array for this call: %s", what);
+  return EB_EINVAL;
+}
+
+void rows(double *p, int dim, int64_t n, double *&x, double *&y, double *&z) {
+  x = p;
+  y = p ? p + n : nullptr;
+  z = (p && dim == 3) ? p + 2 * n : nullptr;
+}
+void crows(const double *p, int dim, int64_t n, const double *&x, const double *&y,
+           const double *&z) {
+  x = p;
+  y = p ? p + n : nullptr;
+  z = (p && dim == 3) ? p + 2 * n : nullptr;
+}
+
+}  // namespace
+}  // namespace eb
+
+using namespace eb;
+
+extern "C" {
+
+int eb_directed_areas(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
+                      const double *coords, int reduce, double *n_edge, double *b_node,
+                      double *vol, void *ws, size_t ws_bytes, hipStream_t stream) {
+  clear_detail();
+  FwdArgs a;
+  EB_TRY(pack(sizes, topo, elem, coords, ws, ws_bytes, a));
+  if (reduce != EB_REDUCE_ATOMIC && reduce != EB_REDUCE_GATHER) {
+    set_detail("reduce must be EB_REDUCE_ATOMIC or EB_REDUCE_GATHER");
+    return EB_EINVAL;
+  }
+  if (!n_edge) {
+    set_detail("n_edge is required");
+    return EB_EINVAL;
+  }
+  const int D = sizes->dim;
+  rows(n_edge, D, sizes->n_edges, a.n_x, a.n_y, a.n_z);
+  rows(sizes->n_bnodes > 0 ? b_node : nullptr, D, sizes->n_bnodes, a.b_x, a.b_y, a.b_z);
+  a.vol = vol;
+  if (reduce == EB_REDUCE_ATOMIC) {
+    EB_TRY(need(a.elem_edge != nullptr, "elem_edge"));
+    if (sizes->n_bfaces > 0) EB_TRY(need(a.bface && a.bface_edge && a.node_bnode, "bface, bface_edge, node_bnode"));
+  } else {
+    EB_TRY(need(a.node_inc_off && a.node_inc && a.node_edge_off && a.edge_head && a.node_bnode &&
+                    a.bnode_face_off,
+                "node_inc, node_edge_off, edge, node_bnode, bnode_face_off"));
+    if (sizes->n_bfaces > 0) EB_TRY(need(a.bface && a.bnode_face, "bface, bnode_face"));
+  }
+  const LaunchCfg cfg = default_cfg();
+  a.xcd_remap = cfg.xcd_remap;
+  return D == 2 ? forward_impl<2>(a, reduce, cfg, stream) : forward_impl<3>(a, reduce, cfg, stream);
+}
+
+int eb_dual_volumes(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
+                    const double *coords, int mode, const double *n_edge, int reduce,
+                    double *vol, void *ws, size_t ws_bytes, hipStream_t stream) {
+  clear_detail();
+  FwdArgs a;
+  EB_TRY(pack(sizes, topo, elem, coords, ws, ws_bytes, a));
+  if ((mode != EB_VOL_ELEMENT && mode != EB_VOL_EDGE) ||
+      (reduce != EB_REDUCE_ATOMIC && reduce != EB_REDUCE_GATHER) || !vol) {
+    set_detail("bad mode / reduce, or vol is null");
+    return EB_EINVAL;
+  }
+  if (mode == EB_VOL_EDGE) {
+    if (!n_edge) {
+      set_detail("EB_VOL_EDGE needs n_edge");
+      return EB_EINVAL;
+    }
+    EB_TRY(need(a.edge_tail && a.edge_head, "edge"));
+    if (reduce == EB_REDUCE_GATHER)
+      EB_TRY(need(a.node_edge_off && a.node_in_off && a.node_in_edge, "node_edge_off, node_in"));
+  } else if (reduce == EB_REDUCE_GATHER) {
+    EB_TRY(need(a.node_inc_off && a.node_inc, "node_inc"));
+  }
+  a.vol = vol;
+  return sizes->dim == 2 ? volumes_impl<2>(a, mode, reduce, n_edge, stream)
+                         : volumes_impl<3>(a, mode, reduce, n_edge, stream);
+}
+
+int eb_directed_areas_backward(const eb_sizes *sizes, const eb_topology *topo,
+                               const int32_t *elem, const double *coords, const double *grad_n,
+                               const double *grad_b, const double *grad_vol, int reduce,
+                               double *grad_coords, void *ws, size_t ws_bytes,
+                               hipStream_t stream) {
+  clear_detail();
+  FwdArgs a;
+  EB_TRY(pack(sizes, topo, elem, coords, ws, ws_bytes, a));
+  if ((reduce != EB_REDUCE_ATOMIC && reduce != EB_REDUCE_GATHER) || !grad_coords) {
+    set_detail("bad reduce, or grad_coords is null");
+    return EB_EINVAL;
+  }
+  const int D = sizes->dim;
+  crows(grad_n, D, sizes->n_edges, a.w_x, a.w_y, a.w_z);
+  crows(sizes->n_bnodes > 0 ? grad_b : nullptr, D, sizes->n_bnodes, a.be_x, a.be_y, a.be_z);
+  a.c = grad_vol;
+  rows(grad_coords, D, sizes->n_nodes, a.g_x, a.g_y, a.g_z);
+  if (a.w_x) EB_TRY(need(a.elem_edge != nullptr, "elem_edge"));
+  if (sizes->n_bfaces > 0 && (a.w_x || a.be_x))
+    EB_TRY(need(a.bface && a.bface_edge && a.node_bnode, "bface, bface_edge, node_bnode"));
+  if (reduce == EB_REDUCE_GATHER) {
+    EB_TRY(need(a.node_inc_off && a.node_inc, "node_inc"));
+    if (sizes->n_bfaces > 0 && (a.w_x || a.be_x))
+      EB_TRY(need(a.bnode_face_off && a.bnode_face, "bnode_face"));
+  }
+  const LaunchCfg cfg = default_cfg();
+  a.xcd_remap = cfg.xcd_remap;
+  return D == 2 ? backward_impl<2>(a, reduce, cfg, stream) : backward_impl<3>(a, reduce, cfg, stream);
+}
+
+int eb_set_gather_shape(int tile, int unroll, int xcd_remap) {
+  clear_detail();
+  if ((tile != 64 && tile != 128 && tile != 256) || (unroll != 1 && unroll != 2 && unroll != 4) ||
+      (xcd_remap != 0 && xcd_remap != 1)) {
+    set_detail("tile must be 64/128/256, unroll 1/2/4, xcd_remap 0/1");
+    return EB_EINVAL;
+  }
+  g_cfg.tile = tile;
+  g_cfg.unroll = unroll;
+  g_cfg.xcd_remap = xcd_remap;
+  return EB_OK;
+}
+
+void eb_get_gather_shape(int *tile, int *unroll, int *xcd_remap) {
+  if (tile) *tile = g_cfg.tile;
+  if (unroll) *unroll = g_cfg.unroll;
+  if (xcd_remap) *xcd_remap = g_cfg.xcd_remap;
+}
+
+}  // extern "C"

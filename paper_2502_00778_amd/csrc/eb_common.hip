@@ -1,0 +1,297 @@
+// Status handling, workspace checks and the device primitives the topology
+// build is made of: exclusive/inclusive scans, per-row sorts, fills.
+#include <cstdarg>
+#include <cstring>
+
+#include "eb_internal.h"
+
+namespace eb {
+
+namespace {
+thread_local char g_detail[512] = "";
+}
+
+void set_detail(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_detail, sizeof(g_detail), fmt, ap);
+  va_end(ap);
+}
+void clear_detail() { g_detail[0] = 0; }
+
+int check_ws(int dim, int64_t n_nodes, int64_t n_elems, const void *ws, size_t ws_bytes) {
+  if (!ws) {
+    set_detail("workspace pointer is null");
+    return EB_EINVAL;
+  }
+  if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) {
+    set_detail("workspace must be 256-byte aligned");
+    return EB_EINVAL;
+  }
+  size_t need = ws_layout(dim, n_nodes, n_elems).total;
+  if (ws_bytes < need) {
+    set_detail("workspace has %zu bytes, needs %zu", ws_bytes, need);
+    return EB_EWORKSPACE;
+  }
+  return EB_OK;
+}
+
+int check_sizes(const eb_sizes *s) {
+  if (!s) {
+    set_detail("sizes pointer is null");
+    return EB_EINVAL;
+  }
+  if (s->dim != 2 && s->dim != 3) {
+    set_detail("dim must be 2 or 3, got %d", s->dim);
+    return EB_EINVAL;
+  }
+  if (s->n_nodes <= 0 || s->n_elems < 0 || s->n_edges < 0 || s->n_bfaces < 0 ||
+      s->n_bnodes < 0) {
+    set_detail("negative or empty sizes");
+    return EB_EINVAL;
+  }
+  const int64_t ne = s->dim == 2 ? 3 : 6;
+  if (ne * s->n_elems >= (int64_t(1) << 31) || s->n_nodes >= (int64_t(1) << 31) - 1) {
+    set_detail("grid too large for int32 indexing");
+    return EB_EOVERFLOW;
+  }
+  return EB_OK;
+}
+
+// ------------------------------------------------------------------ scans
+
+__device__ inline int32_t wave_incl_scan(int32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__device__ inline int32_t wave_sum(int32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// exclusive scan of one value per thread across the block; returns the
+// block total through *total
+__device__ inline int32_t block_excl_scan(int32_t v, int32_t *total) {
+  __shared__ int32_t wsum[SCAN_BLOCK / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int32_t inc = wave_incl_scan(v);
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  int32_t base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < SCAN_BLOCK / 64; ++w) {
+    int32_t s = wsum[w];
+    if (w < wid) base += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - v;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const int32_t *in, int64_t n,
+                                                            int32_t *tmp) {
+  __shared__ int32_t wsum[SCAN_BLOCK / 64];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  int32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    int64_t idx = base + (int64_t)i * SCAN_BLOCK + threadIdx.x;
+    if (idx < n) s += in[idx];
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t t = 0;
+    for (int w = 0; w < SCAN_BLOCK / 64; ++w) t += wsum[w];
+    tmp[blockIdx.x] = t;
+  }
+}
+
+// exclusive scan of the nb block sums, in place, by one block
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_partials(int32_t *tmp, int64_t nb,
+                                                              int32_t *total_dev) {
+  int32_t carry = 0;
+  for (int64_t b = 0; b < nb; b += SCAN_BLOCK) {
+    int64_t i = b + threadIdx.x;
+    int32_t v = i < nb ? tmp[i] : 0;
+    int32_t tot;
+    int32_t ex = block_excl_scan(v, &tot);
+    if (i < nb) tmp[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total_dev) *total_dev = carry;
+}
+
+template <bool INCLUSIVE>
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int32_t *in, int32_t *out,
+                                                           int64_t n, const int32_t *tmp) {
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int32_t v[SCAN_ITEMS];
+  int32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    int64_t idx = base + i;
+    v[i] = idx < n ? in[idx] : 0;
+    s += v[i];
+  }
+  int32_t tot;
+  int32_t run = block_excl_scan(s, &tot) + tmp[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    int64_t idx = base + i;
+    int32_t x = v[i];
+    if (INCLUSIVE) run += x;
+    if (idx < n) out[idx] = run;
+    if (!INCLUSIVE) run += x;
+  }
+}
+
+template <bool INCLUSIVE>
+static int scan_impl(const int32_t *in, int32_t *out, int64_t n, int32_t *total_dev,
+                     int32_t *tmp, hipStream_t s) {
+  if (n <= 0) {
+    if (total_dev) return fill_i32(total_dev, 1, 0, s);
+    return EB_OK;
+  }
+  const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n, tmp);
+  EB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_BLOCK), 0, s, tmp, nb, total_dev);
+  EB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_scan_apply<INCLUSIVE>, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in,
+                     out, n, (const int32_t *)tmp);
+  EB_LAUNCH_CHECK();
+  return EB_OK;
+}
+
+int scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *total_dev,
+                   int32_t *tmp, hipStream_t s) {
+  return scan_impl<false>(in, out, n, total_dev, tmp, s);
+}
+int scan_inclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *total_dev,
+                   int32_t *tmp, hipStream_t s) {
+  return scan_impl<true>(in, out, n, total_dev, tmp, s);
+}
+
+// -------------------------------------------------------------- row sort
+// One thread per row; rows up to RS_CAP long are sorted in LDS (column per
+// thread, conflict-free), longer rows by insertion sort in global memory.
+constexpr int RS_BLOCK = 128;
+constexpr int RS_CAP = 32;
+
+__global__ __launch_bounds__(RS_BLOCK) void k_rowsort(const int32_t *off, int32_t *val,
+                                                      int64_t nrows) {
+  __shared__ int32_t buf[RS_CAP][RS_BLOCK];
+  const int t = threadIdx.x;
+  const int64_t row = (int64_t)blockIdx.x * RS_BLOCK + t;
+  if (row >= nrows) return;
+  const int32_t b = off[row], e = off[row + 1];
+  const int32_t len = e - b;
+  if (len <= 1) return;
+  if (len <= RS_CAP) {
+    for (int i = 0; i < len; ++i) buf[i][t] = val[b + i];
+    for (int i = 1; i < len; ++i) {
+      int32_t x = buf[i][t];
+      int k = i - 1;
+      while (k >= 0 && buf[k][t] > x) {
+        buf[k + 1][t] = buf[k][t];
+        --k;
+      }
+      buf[k + 1][t] = x;
+    }
+    for (int i = 0; i < len; ++i) val[b + i] = buf[i][t];
+  } else {
+    for (int32_t i = b + 1; i < e; ++i) {
+      int32_t x = val[i];
+      int32_t k = i - 1;
+      while (k >= b && val[k] > x) {
+        val[k + 1] = val[k];
+        --k;
+      }
+      val[k + 1] = x;
+    }
+  }
+}
+
+int rowsort(const int32_t *off, int32_t *val, int64_t nrows, hipStream_t s) {
+  if (nrows <= 0) return EB_OK;
+  hipLaunchKernelGGL(k_rowsort, dim3(grid_for(nrows, RS_BLOCK)), dim3(RS_BLOCK), 0, s, off,
+                     val, nrows);
+  EB_LAUNCH_CHECK();
+  return EB_OK;
+}
+
+// ------------------------------------------------------------------ fills
+
+template <class T> __global__ void k_fill(T *p, int64_t n, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+template <class T> static int fill_impl(T *p, int64_t n, T v, hipStream_t s) {
+  if (n <= 0) return EB_OK;
+  int64_t g = std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)g), dim3(256), 0, s, p, n, v);
+  EB_LAUNCH_CHECK();
+  return EB_OK;
+}
+int fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) { return fill_impl(p, n, v, s); }
+int fill_f64(double *p, int64_t n, double v, hipStream_t s) { return fill_impl(p, n, v, s); }
+
+}  // namespace eb
+
+// =================================================================== C ABI
+
+extern "C" {
+
+size_t eb_workspace_bytes(int dim, int64_t n_nodes, int64_t n_elems) {
+  if ((dim != 2 && dim != 3) || n_nodes <= 0 || n_elems < 0) return 0;
+  return eb::ws_layout(dim, n_nodes, n_elems).total;
+}
+
+int eb_check_errors(void *ws, hipStream_t stream) {
+  eb::clear_detail();
+  if (!ws) {
+    eb::set_detail("workspace pointer is null");
+    return EB_EINVAL;
+  }
+  eb::StatusBlock hst;
+  EB_HIP_CHECK(hipMemcpyAsync(&hst, ws, sizeof(hst), hipMemcpyDeviceToHost, stream));
+  EB_HIP_CHECK(hipStreamSynchronize(stream));
+  EB_TRY(eb::fill_i32(static_cast<int32_t *>(ws), 4, 0, stream));
+  if (hst.status != EB_OK)
+    eb::set_detail("device reported %s (detail %lld)", eb_status_string(hst.status),
+                   (long long)hst.detail);
+  return hst.status;
+}
+
+const char *eb_status_string(int status) {
+  switch (status) {
+    case EB_OK: return "ok";
+    case EB_EINVAL: return "invalid argument";
+    case EB_ERANGE: return "node id out of range";
+    case EB_EDEGENERATE: return "element of zero measure";
+    case EB_ENONMANIFOLD: return "face shared by more than two elements";
+    case EB_EWORKSPACE: return "workspace too small";
+    case EB_EOVERFLOW: return "sizes overflow int32 indexing";
+    case EB_EHIP: return "HIP runtime error";
+    case EB_ECAPACITY: return "node exceeds the per-node neighbour capacity";
+    default: return "unknown status";
+  }
+}
+
+const char *eb_last_error_detail(void) { return eb::g_detail; }
+
+const char *eb_version(void) { return "eb 0.1 (gfx950)"; }
+
+}  // extern "C"

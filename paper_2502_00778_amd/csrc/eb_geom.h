@@ -1,0 +1,115 @@
+// Device-side geometry helpers for the metric and adjoint kernels.
+//
+// Face-normal conventions (Section 3.2 of the paper writes the face area
+// vectors for the orientation of its figures; here any local vertex order is
+// accepted and the orientation comes from the sign s of the element's signed
+// measure):
+//   3D: s = sign det[x1-x0, x2-x0, x3-x0];
+//       n_t = s * (1/2) (x_b - x_a) x (x_c - x_a) for (t,a,b,c) an even
+//       permutation of (0,1,2,3): t=0:(1,2,3) t=1:(0,3,2) t=2:(0,1,3)
+//       t=3:(0,2,1).  |E| = |det|/6 and sum_t n_t = 0.
+//   2D: s = sign cross(x1-x0, x2-x0);
+//       n_t = s * rot(x_c - x_b), b=(t+1)%3, c=(t+2)%3, rot(d) = (d_y, -d_x).
+//       |E| = |cross|/2.
+// n_t is the outward area vector of the face opposite local vertex t.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "eb_internal.h"
+
+namespace eb {
+
+struct V3 {
+  double x, y, z;
+};
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ V3 operator-(V3 a) { return {-a.x, -a.y, -a.z}; }
+__device__ __forceinline__ V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ V3 cross(V3 a, V3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+// 2D: outward-rotated segment normal (d_y, -d_x); z stays 0
+__device__ __forceinline__ V3 rot2(V3 d) { return {d.y, -d.x, 0.0}; }
+// 2D: R(W) = (-W_y, W_x), the gradient of W.rot2(d) with respect to d
+__device__ __forceinline__ V3 rotW(V3 w) { return {-w.y, w.x, 0.0}; }
+
+template <int D> __device__ __forceinline__ V3 load_pt(const Coords &X, int32_t v) {
+  if (D == 3) return {X.x[v], X.y[v], X.z[v]};
+  return {X.x[v], X.y[v], 0.0};
+}
+
+template <int D> __device__ __forceinline__ void load_conn(const int32_t *elem, int64_t e,
+                                                           int32_t (&v)[D + 1]) {
+  if constexpr (D == 3) {
+    int4 c = reinterpret_cast<const int4 *>(elem)[e];
+    v[0] = c.x;
+    v[1] = c.y;
+    v[2] = c.z;
+    v[3] = c.w;
+  } else {
+    const int32_t *p = elem + 3 * e;
+    v[0] = p[0];
+    v[1] = p[1];
+    v[2] = p[2];
+  }
+}
+
+// even-permutation faces of a tetrahedron: vertex k (0..2) of the face
+// opposite local vertex t, ordered (a, b, c) so that (t, a, b, c) is an even
+// permutation of (0, 1, 2, 3)
+__device__ __forceinline__ int face3(int t, int k) {
+  // rows: t=0 (1,2,3)  t=1 (0,3,2)  t=2 (0,1,3)  t=3 (0,2,1)
+  const unsigned tab = (1u << 0) | (2u << 2) | (3u << 4) |      // t = 0
+                       (0u << 6) | (3u << 8) | (2u << 10) |     // t = 1
+                       (0u << 12) | (1u << 14) | (3u << 16) |   // t = 2
+                       (0u << 18) | (2u << 20) | (1u << 22);    // t = 3
+  return (tab >> (2 * (3 * t + k))) & 3u;
+}
+
+template <int D> struct EL {
+  static constexpr int NN = D + 1;
+  static constexpr int NE = D == 2 ? 3 : 6;
+};
+
+template <int D> __device__ __forceinline__ int pair_p(int le) {
+  if constexpr (D == 2) return le < 2 ? 0 : 1;
+  else return le < 3 ? 0 : (le < 5 ? 1 : 2);
+}
+template <int D> __device__ __forceinline__ int pair_q(int le) {
+  if constexpr (D == 2) return le == 0 ? 1 : 2;
+  else {
+    constexpr int q[6] = {1, 2, 3, 2, 3, 3};
+    return q[le];
+  }
+}
+
+// signed measure times D! (det), and the outward face normals n_t (true
+// area vectors, i.e. with the 1/2 in 3D)
+template <int D>
+__device__ __forceinline__ double elem_normals(const V3 (&P)[D + 1], V3 (&n)[D + 1]) {
+  if constexpr (D == 3) {
+    const V3 a = P[1] - P[0], b = P[2] - P[0], c = P[3] - P[0];
+    const double det = dot(a, cross(b, c));
+    const double hs = det > 0 ? 0.5 : -0.5;
+    n[0] = hs * cross(P[2] - P[1], P[3] - P[1]);
+    n[1] = hs * cross(c, b);
+    n[2] = hs * cross(a, c);
+    n[3] = hs * cross(b, a);
+    return det;
+  } else {
+    const V3 a = P[1] - P[0], b = P[2] - P[0];
+    const double det = a.x * b.y - a.y * b.x;
+    const double s = det > 0 ? 1.0 : -1.0;
+    n[0] = s * rot2(P[2] - P[1]);
+    n[1] = s * rot2(P[0] - P[2]);
+    n[2] = s * rot2(P[1] - P[0]);
+    return det;
+  }
+}
+
+}  // namespace eb

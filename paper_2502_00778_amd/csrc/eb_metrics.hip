@@ -1,0 +1,420 @@
+// Lumped directed-area vectors, boundary dual normals and dual volumes.
+//
+//   n_jk = 2/(D(D+1)) sum_{E contains jk} n_j^E  (j = tail = smaller id)
+//          + 1/(D(D+1)) sum_{B contains jk} n_B  (eq.
+//          efficient_njk_formula_general_D and the boundary correction)
+//   b_j  = (1/D) sum_{B contains j} n_B          (closure, Section 3.2.3)
+//   V_j  = sum_{E contains j} |E|/(D+1)          (Section 4.2)
+//   V_j  = 1/(2D) sum_k (x_k - x_j).n_jk         (edge loop, Section 4.1)
+//
+// Two reductions:
+//   atomic  one thread per element (and per boundary face); FP64 atomic adds
+//           into zeroed n, V, b.
+//   gather  one thread per node j.  It walks j's elements in node_inc order,
+//           forms the one face vector n_j^E each element needs for the edges
+//           whose tail is j (the paper's remark that n_j^E serves every edge
+//           leaving j, Section 3.3), and |E| from the same cross product; the
+//           edges with tail j are a contiguous range owned by j's block, which
+//           accumulates them in LDS and writes them once, coalesced.  No
+//           memset, no atomics, a fixed summation order: bitwise reproducible.
+#include "eb_geom.h"
+#include "eb_kernels.h"
+
+namespace eb {
+
+// ------------------------------------------------------------- atomic path
+
+template <int D>
+__global__ __launch_bounds__(256) void k_fwd_atomic_elem(FwdArgs a) {
+  constexpr int NN = D + 1, NE = EL<D>::NE;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nelem) return;
+  int32_t v[NN];
+  load_conn<D>(a.elem, e, v);
+  V3 P[NN], n[NN];
+#pragma unroll
+  for (int i = 0; i < NN; ++i) P[i] = load_pt<D>(a.X, v[i]);
+  const double det = elem_normals<D>(P, n);
+  if (det == 0.0) raise_status(a.st, EB_EDEGENERATE, e);
+  constexpr double kN = 2.0 / (D * (D + 1));
+  if (a.n_x) {
+#pragma unroll
+    for (int le = 0; le < NE; ++le) {
+      const int p = pair_p<D>(le), q = pair_q<D>(le);
+      const V3 nt = v[p] < v[q] ? n[p] : n[q];
+      const int32_t id = a.elem_edge[e * NE + le];
+      unsafeAtomicAdd(&a.n_x[id], kN * nt.x);
+      unsafeAtomicAdd(&a.n_y[id], kN * nt.y);
+      if (D == 3) unsafeAtomicAdd(&a.n_z[id], kN * nt.z);
+    }
+  }
+  if (a.vol) {
+    const double share = (D == 3 ? fabs(det) / 24.0 : fabs(det) / 6.0);
+#pragma unroll
+    for (int i = 0; i < NN; ++i) unsafeAtomicAdd(&a.vol[v[i]], share);
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_fwd_atomic_bface(FwdArgs a) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= a.nbface) return;
+  V3 nB;
+  int32_t fv[D];
+#pragma unroll
+  for (int s = 0; s < D; ++s) fv[s] = a.bface[f * D + s];
+  if constexpr (D == 3) {
+    const V3 A = load_pt<D>(a.X, fv[0]), B = load_pt<D>(a.X, fv[1]), C = load_pt<D>(a.X, fv[2]);
+    nB = 0.5 * cross(B - A, C - A);
+  } else {
+    nB = rot2(load_pt<D>(a.X, fv[1]) - load_pt<D>(a.X, fv[0]));
+  }
+  constexpr double kB = 1.0 / (D * (D + 1));
+  constexpr int NBE = D == 2 ? 1 : 3;
+  if (a.n_x) {
+#pragma unroll
+    for (int i = 0; i < NBE; ++i) {
+      const int32_t id = a.bface_edge[f * NBE + i];
+      unsafeAtomicAdd(&a.n_x[id], kB * nB.x);
+      unsafeAtomicAdd(&a.n_y[id], kB * nB.y);
+      if (D == 3) unsafeAtomicAdd(&a.n_z[id], kB * nB.z);
+    }
+  }
+  if (a.b_x) {
+    constexpr double kb = 1.0 / D;
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+      const int32_t bi = a.node_bnode[fv[s]];
+      unsafeAtomicAdd(&a.b_x[bi], kb * nB.x);
+      unsafeAtomicAdd(&a.b_y[bi], kb * nB.y);
+      if (D == 3) unsafeAtomicAdd(&a.b_z[bi], kb * nB.z);
+    }
+  }
+}
+
+// ------------------------------------------------------------- gather path
+//
+// Raw accumulator per edge: sum over elements of c = the cross product the
+// thread forms (3D: c = 2 n_j^E; 2D: c = n_j^E), plus the boundary term in
+// the same units; the final scale kN turns it into n.
+//   3D: n = (1/12)[sum c + sum n_B];  2D: n = (1/3)[sum c + (1/2) sum n_B]
+//   d = c.(x_a - x_j) = D! |E|;  V_j = sum d * kV, kV = 1/24 (3D), 1/6 (2D)
+
+template <int D> struct GK {
+  static constexpr double kN = D == 3 ? 1.0 / 12.0 : 1.0 / 3.0;
+  static constexpr double kBraw = D == 3 ? 1.0 : 0.5;  // n_B in raw units
+  static constexpr double kV = D == 3 ? 1.0 / 24.0 : 1.0 / 6.0;
+};
+
+// The tile of nodes a block handles.  Blocks are dealt round-robin to the 8
+// XCDs (block b runs on XCD b % 8); with remapping, XCD x takes one
+// contiguous run of tiles in order, so neighbouring tiles (which share
+// elements and coordinates) meet in the same L2.  A bijection for any count.
+__device__ __forceinline__ int64_t tile_of_block(int64_t nblocks, int xcd_remap) {
+  const int64_t b = blockIdx.x;
+  if (!xcd_remap || nblocks < 16) return b;
+  const int64_t per = nblocks >> 3, rem = nblocks & 7;
+  const int64_t x = b & 7, k = b >> 3;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
+template <int D, int TN, int CAP, int U>
+__global__ __launch_bounds__(TN) void k_fwd_gather(FwdArgs a) {
+  __shared__ double acc[D][CAP];
+  __shared__ int32_t hd[CAP];
+  const int t = threadIdx.x;
+  const int64_t nblocks = gridDim.x;
+  const int64_t tile = tile_of_block(nblocks, a.xcd_remap);
+  const int64_t j0 = tile * TN;
+  if (j0 >= a.nv) return;  // whole block leaves together
+  const int64_t jend = min(j0 + (int64_t)TN, a.nv);
+  const int32_t e0 = a.node_edge_off[j0], e1 = a.node_edge_off[jend];
+  const int32_t cnt = e1 - e0;
+  const bool in_lds = cnt <= CAP;
+  const int32_t *__restrict__ head = a.edge_head;
+  if (in_lds) {
+    for (int i = t; i < cnt; i += TN) {
+      hd[i] = head[e0 + i];
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc[c][i] = 0.0;
+    }
+  }
+  __syncthreads();
+  double *nout[3] = {a.n_x, a.n_y, a.n_z};
+  const int64_t j = j0 + t;
+  if (j < a.nv) {
+    const int32_t my0 = a.node_edge_off[j], my1 = a.node_edge_off[j + 1];
+    if (!in_lds)
+      for (int32_t ed = my0; ed < my1; ++ed)
+#pragma unroll
+        for (int c = 0; c < D; ++c) nout[c][ed] = 0.0;
+    const V3 xj = load_pt<D>(a.X, (int32_t)j);
+    double vs = 0.0;
+    const int32_t r0 = a.node_inc_off[j], r1 = a.node_inc_off[j + 1];
+    for (int32_t r = r0; r < r1; r += U) {
+      int32_t inc[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) inc[u] = a.node_inc[min(r + u, r1 - 1)];
+      int32_t vv[U][D + 1];
+#pragma unroll
+      for (int u = 0; u < U; ++u) load_conn<D>(a.elem, inc[u] / (D + 1), vv[u]);
+      int32_t ov[U][D];
+      V3 P[U][D];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int l = inc[u] % (D + 1);
+        int k = 0;
+#pragma unroll
+        for (int q = 0; q <= D; ++q)
+          if (q != l) ov[u][k++] = vv[u][q];
+#pragma unroll
+        for (int k2 = 0; k2 < D; ++k2) P[u][k2] = load_pt<D>(a.X, ov[u][k2]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (r + u >= r1) break;
+        V3 c;
+        if constexpr (D == 3)
+          c = cross(P[u][1] - P[u][0], P[u][2] - P[u][0]);
+        else
+          c = rot2(P[u][1] - P[u][0]);
+        double d = dot(c, P[u][0] - xj);
+        if (d < 0.0) {
+          c = -c;
+          d = -d;
+        } else if (d == 0.0) {
+          raise_status(a.st, EB_EDEGENERATE, inc[u] / (D + 1));
+        }
+        vs += d;
+#pragma unroll
+        for (int k2 = 0; k2 < D; ++k2) {
+          const int32_t kk = ov[u][k2];
+          if (kk <= j || my1 == my0) continue;
+          if (in_lds) {
+            int s = my0 - e0;
+            while (hd[s] != kk && s < my1 - e0 - 1) ++s;
+            acc[0][s] += c.x;
+            acc[1][s] += c.y;
+            if (D == 3) acc[2][s] += c.z;
+          } else {
+            int32_t s = my0;
+            while (head[s] != kk && s < my1 - 1) ++s;
+            nout[0][s] += c.x;
+            nout[1][s] += c.y;
+            if (D == 3) nout[2][s] += c.z;
+          }
+        }
+      }
+    }
+    if (a.vol) a.vol[j] = vs * GK<D>::kV;
+    // boundary elements containing j: b_j and the boundary correction of
+    // the edges of B whose tail is j
+    const int32_t bj = a.node_bnode[j];
+    if (bj >= 0) {
+      V3 bs = {0.0, 0.0, 0.0};
+      const int32_t f0 = a.bnode_face_off[bj], f1 = a.bnode_face_off[bj + 1];
+      for (int32_t r = f0; r < f1; ++r) {
+        const int32_t f = a.bnode_face[r];
+        int32_t fv[D];
+#pragma unroll
+        for (int s = 0; s < D; ++s) fv[s] = a.bface[(int64_t)f * D + s];
+        V3 nB;
+        if constexpr (D == 3) {
+          const V3 A = load_pt<D>(a.X, fv[0]), B = load_pt<D>(a.X, fv[1]),
+                   C = load_pt<D>(a.X, fv[2]);
+          nB = 0.5 * cross(B - A, C - A);
+        } else {
+          nB = rot2(load_pt<D>(a.X, fv[1]) - load_pt<D>(a.X, fv[0]));
+        }
+        bs = bs + nB;
+        const V3 cB = GK<D>::kBraw * nB;
+#pragma unroll
+        for (int s2 = 0; s2 < D; ++s2) {
+          const int32_t kk = fv[s2];
+          if (kk <= j || my1 == my0) continue;
+          if (in_lds) {
+            int s = my0 - e0;
+            while (hd[s] != kk && s < my1 - e0 - 1) ++s;
+            acc[0][s] += cB.x;
+            acc[1][s] += cB.y;
+            if (D == 3) acc[2][s] += cB.z;
+          } else {
+            int32_t s = my0;
+            while (head[s] != kk && s < my1 - 1) ++s;
+            nout[0][s] += cB.x;
+            nout[1][s] += cB.y;
+            if (D == 3) nout[2][s] += cB.z;
+          }
+        }
+      }
+      if (a.b_x) {
+        constexpr double kb = 1.0 / D;
+        a.b_x[bj] = kb * bs.x;
+        a.b_y[bj] = kb * bs.y;
+        if (D == 3) a.b_z[bj] = kb * bs.z;
+      }
+    }
+    if (!in_lds)
+      for (int32_t ed = my0; ed < my1; ++ed)
+#pragma unroll
+        for (int c = 0; c < D; ++c) nout[c][ed] *= GK<D>::kN;
+  }
+  if (in_lds) {
+    __syncthreads();
+    for (int i = t; i < cnt; i += TN)
+#pragma unroll
+      for (int c = 0; c < D; ++c) nout[c][e0 + i] = acc[c][i] * GK<D>::kN;
+  }
+}
+
+// ----------------------------------------------------- volumes on their own
+
+template <int D>
+__global__ __launch_bounds__(256) void k_vol_elem_gather(FwdArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.nv) return;
+  double vs = 0.0;
+  for (int32_t r = a.node_inc_off[j]; r < a.node_inc_off[j + 1]; ++r) {
+    const int64_t e = a.node_inc[r] / (D + 1);
+    int32_t v[D + 1];
+    load_conn<D>(a.elem, e, v);
+    V3 P[D + 1], n[D + 1];
+#pragma unroll
+    for (int i = 0; i <= D; ++i) P[i] = load_pt<D>(a.X, v[i]);
+    vs += fabs(elem_normals<D>(P, n));
+  }
+  a.vol[j] = vs * (D == 3 ? 1.0 / 24.0 : 1.0 / 6.0);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_vol_edge_atomic(FwdArgs a, const double *__restrict__ nx,
+                                                         const double *__restrict__ ny,
+                                                         const double *__restrict__ nz) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nedge) return;
+  const int32_t j = a.edge_tail[e], k = a.edge_head[e];
+  const V3 d = load_pt<D>(a.X, k) - load_pt<D>(a.X, j);
+  double s = d.x * nx[e] + d.y * ny[e];
+  if (D == 3) s += d.z * nz[e];
+  s *= 1.0 / (2 * D);
+  unsafeAtomicAdd(&a.vol[j], s);
+  unsafeAtomicAdd(&a.vol[k], s);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_vol_edge_gather(FwdArgs a, const double *__restrict__ nx,
+                                                         const double *__restrict__ ny,
+                                                         const double *__restrict__ nz) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.nv) return;
+  const V3 xj = load_pt<D>(a.X, (int32_t)j);
+  double s = 0.0;
+  for (int32_t e = a.node_edge_off[j]; e < a.node_edge_off[j + 1]; ++e) {
+    const V3 d = load_pt<D>(a.X, a.edge_head[e]) - xj;
+    s += d.x * nx[e] + d.y * ny[e] + (D == 3 ? d.z * nz[e] : 0.0);
+  }
+  for (int32_t r = a.node_in_off[j]; r < a.node_in_off[j + 1]; ++r) {
+    const int32_t e = a.node_in_edge[r];
+    const V3 d = xj - load_pt<D>(a.X, a.edge_tail[e]);
+    s += d.x * nx[e] + d.y * ny[e] + (D == 3 ? d.z * nz[e] : 0.0);
+  }
+  a.vol[j] = s * (1.0 / (2 * D));
+}
+
+// ------------------------------------------------------------- launchers
+
+template <int D>
+int launch_fwd_gather(const FwdArgs &a, const LaunchCfg &cfg, hipStream_t s) {
+  const int64_t ntiles = (a.nv + cfg.tile - 1) / cfg.tile;
+  const dim3 grid((unsigned)ntiles);
+#define EB_GATHER_CASE(TN_, CAP_, U_)                                                 \
+  if (cfg.tile == TN_ && cfg.unroll == U_) {                                          \
+    hipLaunchKernelGGL((k_fwd_gather<D, TN_, CAP_, U_>), grid, dim3(TN_), 0, s, a);   \
+    EB_LAUNCH_CHECK();                                                                \
+    return EB_OK;                                                                     \
+  }
+  EB_GATHER_CASE(64, 640, 1)
+  EB_GATHER_CASE(64, 640, 2)
+  EB_GATHER_CASE(64, 640, 4)
+  EB_GATHER_CASE(128, 1152, 1)
+  EB_GATHER_CASE(128, 1152, 2)
+  EB_GATHER_CASE(128, 1152, 4)
+  EB_GATHER_CASE(256, 2176, 1)
+  EB_GATHER_CASE(256, 2176, 2)
+  EB_GATHER_CASE(256, 2176, 4)
+#undef EB_GATHER_CASE
+  set_detail("unsupported gather tile %d / unroll %d", cfg.tile, cfg.unroll);
+  return EB_EINVAL;
+}
+
+template <int D>
+int forward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_t s) {
+  if (reduce == EB_REDUCE_ATOMIC) {
+    if (a.n_x) {
+      EB_TRY(fill_f64(a.n_x, a.nedge, 0.0, s));
+      EB_TRY(fill_f64(a.n_y, a.nedge, 0.0, s));
+      if (D == 3) EB_TRY(fill_f64(a.n_z, a.nedge, 0.0, s));
+    }
+    if (a.vol) EB_TRY(fill_f64(a.vol, a.nv, 0.0, s));
+    if (a.b_x) {
+      EB_TRY(fill_f64(a.b_x, a.nbnode, 0.0, s));
+      EB_TRY(fill_f64(a.b_y, a.nbnode, 0.0, s));
+      if (D == 3) EB_TRY(fill_f64(a.b_z, a.nbnode, 0.0, s));
+    }
+    if (a.nelem > 0) {
+      hipLaunchKernelGGL(k_fwd_atomic_elem<D>, dim3(grid_for(a.nelem, 256)), dim3(256), 0, s,
+                         a);
+      EB_LAUNCH_CHECK();
+    }
+    if (a.nbface > 0 && (a.n_x || a.b_x)) {
+      hipLaunchKernelGGL(k_fwd_atomic_bface<D>, dim3(grid_for(a.nbface, 256)), dim3(256), 0, s,
+                         a);
+      EB_LAUNCH_CHECK();
+    }
+    return EB_OK;
+  }
+  return launch_fwd_gather<D>(a, cfg, s);
+}
+
+template int forward_impl<2>(const FwdArgs &, int, const LaunchCfg &, hipStream_t);
+template int forward_impl<3>(const FwdArgs &, int, const LaunchCfg &, hipStream_t);
+
+template <int D>
+int volumes_impl(const FwdArgs &a, int mode, int reduce, const double *n_edge, hipStream_t s) {
+  if (mode == EB_VOL_ELEMENT) {
+    if (reduce == EB_REDUCE_ATOMIC) {
+      FwdArgs b = a;
+      b.n_x = b.n_y = b.n_z = nullptr;
+      b.b_x = b.b_y = b.b_z = nullptr;
+      EB_TRY(fill_f64(b.vol, b.nv, 0.0, s));
+      if (b.nelem > 0) {
+        hipLaunchKernelGGL(k_fwd_atomic_elem<D>, dim3(grid_for(b.nelem, 256)), dim3(256), 0, s,
+                           b);
+        EB_LAUNCH_CHECK();
+      }
+      return EB_OK;
+    }
+    hipLaunchKernelGGL(k_vol_elem_gather<D>, dim3(grid_for(a.nv, 256)), dim3(256), 0, s, a);
+    EB_LAUNCH_CHECK();
+    return EB_OK;
+  }
+  const double *nx = n_edge, *ny = n_edge + a.nedge, *nz = D == 3 ? n_edge + 2 * a.nedge : nullptr;
+  if (reduce == EB_REDUCE_ATOMIC) {
+    EB_TRY(fill_f64(a.vol, a.nv, 0.0, s));
+    if (a.nedge > 0) {
+      hipLaunchKernelGGL(k_vol_edge_atomic<D>, dim3(grid_for(a.nedge, 256)), dim3(256), 0, s, a,
+                         nx, ny, nz);
+      EB_LAUNCH_CHECK();
+    }
+    return EB_OK;
+  }
+  hipLaunchKernelGGL(k_vol_edge_gather<D>, dim3(grid_for(a.nv, 256)), dim3(256), 0, s, a, nx,
+                     ny, nz);
+  EB_LAUNCH_CHECK();
+  return EB_OK;
+}
+
+template int volumes_impl<2>(const FwdArgs &, int, int, const double *, hipStream_t);
+template int volumes_impl<3>(const FwdArgs &, int, int, const double *, hipStream_t);
+
+}  // namespace eb

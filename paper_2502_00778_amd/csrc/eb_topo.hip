@@ -1,0 +1,627 @@
+// Edge extraction and boundary elements (the edge array of Section 2 and the
+// boundary-element loops of Sections 3.2.1-3.2.3), built on the GPU.
+//
+// The build is a bucket (counting) sort keyed by node followed by small
+// per-bucket sorts, instead of a multi-pass global radix sort of edge keys:
+//   1. count the elements of every node (histogram), scan, scatter
+//      elem*(D+1)+local into node_inc (a one-digit radix sort with radix
+//      n_nodes), then sort every bucket so the order is unique;
+//   2. per node j, the edges with tail j are the distinct neighbours k > j in
+//      j's elements: collect them sorted and unique in LDS (count pass, scan,
+//      emit pass) -> edges come out in ascending (tail, head) order;
+//   3. per node j, the faces whose smallest vertex is j are counted in j's
+//      elements (each face lies in one or two elements, both containing j);
+//      faces met once are boundary faces, three or more is an error;
+//   4. element -> edge map by binary search in the tail's head list; the
+//      edge -> element and other CSR lists by count / scan / scatter / row
+//      sort.
+// Every integer output is thus uniquely defined (bit-exact across runs).
+#include "eb_geom.h"
+
+namespace eb {
+
+namespace {
+
+constexpr int TB = 128;  // threads per block of the per-node topology kernels
+constexpr int MAXH = EB_MAX_OUT_EDGES;
+constexpr int MAXF = EB_MAX_NODE_FACES;
+static_assert(MAXH <= 32 && MAXH * MAXH < 0x8000, "face codes fit 15 bits");
+
+// ----------------------------------------------------- node incidences
+
+// Later build kernels do nothing once a kernel has recorded an error: their
+// inputs may then be incomplete.
+__device__ __forceinline__ bool build_failed(const StatusBlock *st) {
+  return *reinterpret_cast<const volatile int32_t *>(&st->status) != 0;
+}
+
+template <int D>
+__device__ __forceinline__ bool conn_valid(const int32_t (&v)[D + 1], int64_t nv) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i <= D; ++i) ok = ok && v[i] >= 0 && v[i] < nv;
+  return ok;
+}
+
+template <int D>
+__global__ void k_count_nodes(const int32_t *__restrict__ elem, int64_t nelem, int64_t nv,
+                              Coords X, int32_t *cnt, StatusBlock *st) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nelem) return;
+  int32_t v[D + 1];
+  load_conn<D>(elem, e, v);
+  if (!conn_valid<D>(v, nv)) {
+    raise_status(st, EB_ERANGE, e);
+    return;
+  }
+  V3 P[D + 1];
+#pragma unroll
+  for (int i = 0; i <= D; ++i) P[i] = load_pt<D>(X, v[i]);
+  double det;
+  if constexpr (D == 3)
+    det = dot(P[1] - P[0], cross(P[2] - P[0], P[3] - P[0]));
+  else
+    det = (P[1].x - P[0].x) * (P[2].y - P[0].y) - (P[1].y - P[0].y) * (P[2].x - P[0].x);
+  if (det == 0.0) raise_status(st, EB_EDEGENERATE, e);
+#pragma unroll
+  for (int i = 0; i <= D; ++i) atomicAdd(&cnt[v[i]], 1);
+}
+
+// cur holds inclusive (end) offsets; each slot taken decrements it, so it
+// ends as the exclusive (start) offsets
+template <int D>
+__global__ void k_scatter_nodes(const int32_t *__restrict__ elem, int64_t nelem, int64_t nv,
+                                int32_t *cur, int32_t *node_inc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nelem) return;
+  int32_t v[D + 1];
+  load_conn<D>(elem, e, v);
+  if (!conn_valid<D>(v, nv)) return;
+#pragma unroll
+  for (int i = 0; i <= D; ++i) {
+    int32_t pos = atomicSub(&cur[v[i]], 1) - 1;
+    node_inc[pos] = (int32_t)(e * (D + 1) + i);
+  }
+}
+
+// ------------------------------------------------- per-node edge / faces
+
+struct TopoArgs {
+  int64_t nv;
+  const int32_t *elem;
+  Coords X;
+  const int32_t *node_inc_off, *node_inc;
+  // count pass (workspace)
+  int32_t *outdeg, *fmin, *bflag, *bfn, *ein;
+  // emit pass
+  const int32_t *eoff, *foff;
+  int32_t *edge_tail, *edge_head;
+  int32_t *bface, *bface_owner;
+  int32_t *in_cur, *node_in_edge;
+  int32_t *bf_cur, *bnode_face;
+  StatusBlock *st;
+};
+
+// slot of head k in the thread's sorted head column (k must be present)
+__device__ __forceinline__ int head_slot(const int32_t (*hs)[TB], int t, int nh, int32_t k) {
+  int s = 0;
+  while (s < nh - 1 && hs[s][t] != k) ++s;
+  return s;
+}
+
+template <int D, bool EMIT>
+__global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
+  __shared__ int32_t hs[MAXH][TB];
+  __shared__ uint16_t fc[MAXF][TB];
+  const int t = threadIdx.x;
+  const int64_t j64 = (int64_t)blockIdx.x * TB + t;
+  if (j64 >= a.nv || build_failed(a.st)) return;
+  const int32_t j = (int32_t)j64;
+  const int32_t r0 = a.node_inc_off[j], r1 = a.node_inc_off[j + 1];
+
+  // 1. distinct higher-numbered neighbours, ascending
+  int nh = 0;
+  bool overflow = false;
+  for (int32_t r = r0; r < r1; ++r) {
+    const int32_t inc = a.node_inc[r];
+    const int64_t e = inc / (D + 1);
+    const int l = inc - (int)(e * (D + 1));
+    int32_t v[D + 1];
+    load_conn<D>(a.elem, e, v);
+#pragma unroll
+    for (int q = 0; q <= D; ++q) {
+      const int32_t k = v[q];
+      if (q == l || k <= j) continue;
+      int pos = 0;
+      while (pos < nh && hs[pos][t] < k) ++pos;
+      if (pos < nh && hs[pos][t] == k) continue;
+      if (nh == MAXH) {
+        overflow = true;
+        continue;
+      }
+      for (int s = nh; s > pos; --s) hs[s][t] = hs[s - 1][t];
+      hs[pos][t] = k;
+      ++nh;
+    }
+  }
+  if (overflow) {
+    raise_status(a.st, EB_ECAPACITY, j);
+    return;
+  }
+  if constexpr (!EMIT) {
+    a.outdeg[j] = nh;
+    for (int s = 0; s < nh; ++s) atomicAdd(&a.ein[hs[s][t]], 1);
+  } else {
+    const int32_t e0 = a.eoff[j];
+    for (int s = 0; s < nh; ++s) {
+      const int32_t k = hs[s][t];
+      a.edge_tail[e0 + s] = j;
+      a.edge_head[e0 + s] = k;
+      const int32_t pos = atomicSub(&a.in_cur[k], 1) - 1;
+      a.node_in_edge[pos] = e0 + s;
+    }
+  }
+
+  // 2. candidate faces with j as smallest vertex, coded by head slots
+  int nf = 0;
+  for (int32_t r = r0; r < r1; ++r) {
+    const int32_t inc = a.node_inc[r];
+    const int64_t e = inc / (D + 1);
+    const int l = inc - (int)(e * (D + 1));
+    int32_t v[D + 1];
+    load_conn<D>(a.elem, e, v);
+    int sl[D];
+    int ns = 0;
+#pragma unroll
+    for (int q = 0; q <= D; ++q)
+      if (q != l && v[q] > j) sl[ns++] = head_slot(hs, t, nh, v[q]);
+    if constexpr (D == 3) {
+      // order the (up to 3) slots ascending
+      if (ns >= 2 && sl[0] > sl[1]) { int x = sl[0]; sl[0] = sl[1]; sl[1] = x; }
+      if (ns == 3) {
+        if (sl[1] > sl[2]) { int x = sl[1]; sl[1] = sl[2]; sl[2] = x; }
+        if (sl[0] > sl[1]) { int x = sl[0]; sl[0] = sl[1]; sl[1] = x; }
+      }
+      for (int p = 0; p < ns; ++p)
+        for (int q = p + 1; q < ns; ++q) {
+          if (nf == MAXF) {
+            overflow = true;
+            continue;
+          }
+          fc[nf++][t] = (uint16_t)(sl[p] * MAXH + sl[q]);
+        }
+    } else {
+      for (int p = 0; p < ns; ++p) {
+        if (nf == MAXF) {
+          overflow = true;
+          continue;
+        }
+        fc[nf++][t] = (uint16_t)sl[p];
+      }
+    }
+  }
+  if (overflow) {
+    raise_status(a.st, EB_ECAPACITY, j);
+    return;
+  }
+
+  // 3. multiplicity of each candidate: 1 = boundary face, 2 = interior
+  int nb = 0;
+  for (int i = 0; i < nf; ++i) {
+    const uint16_t c = fc[i][t] & 0x7fff;
+    int m = 0;
+    for (int i2 = 0; i2 < nf; ++i2) m += (fc[i2][t] & 0x7fff) == c;
+    if (m > 2) {
+      raise_status(a.st, EB_ENONMANIFOLD, j);
+      return;
+    }
+    if (m == 1) {
+      fc[i][t] = c | 0x8000;
+      ++nb;
+    }
+  }
+  if constexpr (!EMIT) {
+    a.fmin[j] = nb;
+    for (int i = 0; i < nf; ++i) {
+      const uint16_t c = fc[i][t];
+      if (!(c & 0x8000)) continue;
+      int32_t fv[D];
+      fv[0] = j;
+      if constexpr (D == 3) {
+        fv[1] = hs[(c & 0x7fff) / MAXH][t];
+        fv[2] = hs[(c & 0x7fff) % MAXH][t];
+      } else {
+        fv[1] = hs[c & 0x7fff][t];
+      }
+#pragma unroll
+      for (int s = 0; s < D; ++s) {
+        a.bflag[fv[s]] = 1;
+        atomicAdd(&a.bfn[fv[s]], 1);
+      }
+    }
+  } else {
+    // 4. emit boundary faces in ascending code order (= ascending sorted ids)
+    int32_t f = a.foff[j];
+    int last = -1;
+    for (int done = 0; done < nb; ++done) {
+      int best = 0x7fff + 1;
+      for (int i = 0; i < nf; ++i) {
+        const uint16_t c = fc[i][t];
+        if (!(c & 0x8000)) continue;
+        const int cc = c & 0x7fff;
+        if (cc > last && cc < best) best = cc;
+      }
+      last = best;
+      int32_t fv[D];
+      fv[0] = j;
+      if constexpr (D == 3) {
+        fv[1] = hs[best / MAXH][t];
+        fv[2] = hs[best % MAXH][t];
+      } else {
+        fv[1] = hs[best][t];
+      }
+      // owner: the one element of j holding the face; opposite = its other vertex
+      int64_t own = -1;
+      int opp = -1;
+      int32_t vo = -1;
+      for (int32_t r = r0; r < r1 && own < 0; ++r) {
+        const int32_t inc = a.node_inc[r];
+        const int64_t e = inc / (D + 1);
+        int32_t v[D + 1];
+        load_conn<D>(a.elem, e, v);
+        int hit = 0, o = -1;
+#pragma unroll
+        for (int q = 0; q <= D; ++q) {
+          bool in = false;
+#pragma unroll
+          for (int s = 0; s < D; ++s) in = in || v[q] == fv[s];
+          if (in) ++hit;
+          else o = q;
+        }
+        if (hit == D) {
+          own = e;
+          opp = o;
+          vo = v[o];
+        }
+      }
+      if (own < 0) {  // cannot happen for a consistent node_inc
+        raise_status(a.st, EB_EINVAL, j);
+        return;
+      }
+      // outward orientation: the expression, operand order and FP64 rounding
+      // of the definition in eb.h (v0 = smallest id), without contraction
+      {
+#pragma clang fp contract(off)
+        const V3 A = load_pt<D>(a.X, fv[0]), B = load_pt<D>(a.X, fv[1]);
+        const V3 Xo = load_pt<D>(a.X, vo);
+        if constexpr (D == 3) {
+          const V3 C = load_pt<D>(a.X, fv[2]);
+          const V3 u = B - A, v = C - A, w = A - Xo;
+          const double cx = u.y * v.z - u.z * v.y;
+          const double cy = u.z * v.x - u.x * v.z;
+          const double cz = u.x * v.y - u.y * v.x;
+          const double s = cx * w.x + cy * w.y + cz * w.z;
+          const bool keep = s > 0;
+          a.bface[(int64_t)f * 3 + 0] = fv[0];
+          a.bface[(int64_t)f * 3 + 1] = keep ? fv[1] : fv[2];
+          a.bface[(int64_t)f * 3 + 2] = keep ? fv[2] : fv[1];
+        } else {
+          const V3 d = B - A, w = A - Xo;
+          const double s = d.y * w.x - d.x * w.y;
+          const bool keep = s > 0;
+          a.bface[(int64_t)f * 2 + 0] = keep ? fv[0] : fv[1];
+          a.bface[(int64_t)f * 2 + 1] = keep ? fv[1] : fv[0];
+        }
+      }
+      a.bface_owner[f] = (int32_t)(own * (D + 1) + opp);
+#pragma unroll
+      for (int s = 0; s < D; ++s) {
+        const int32_t pos = atomicSub(&a.bf_cur[fv[s]], 1) - 1;
+        a.bnode_face[pos] = f;
+      }
+      ++f;
+    }
+  }
+}
+
+// per-node bookkeeping before the emit pass
+struct EmitNodeArgs {
+  int64_t nv;
+  int dim;
+  const int32_t *eoff, *bidx, *bfn, *bfn_scan, *ein_scan;
+  int32_t *node_edge_off, *node_bnode, *bnode, *bnode_face_off, *node_in_off;
+  const StatusBlock *st;
+};
+
+__global__ void k_emit_nodes(EmitNodeArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > a.nv || build_failed(a.st)) return;
+  a.node_edge_off[j] = a.eoff[j];
+  if (j == a.nv) {
+    const int32_t nbn = a.bidx[a.nv];
+    a.bnode_face_off[nbn] = a.dim * a.st->totals[T_BFACES];
+    a.node_in_off[a.nv] = a.eoff[a.nv];
+    return;
+  }
+  const int32_t b0 = a.bidx[j], b1 = a.bidx[j + 1];
+  if (b1 > b0) {
+    a.node_bnode[j] = b0;
+    a.bnode[b0] = (int32_t)j;
+    a.bnode_face_off[b0] = a.bfn_scan[j] - a.bfn[j];
+  } else {
+    a.node_bnode[j] = -1;
+  }
+  a.node_in_off[j] = a.ein_scan[j];
+}
+
+// ------------------------------------------------- element -> edge map
+
+__device__ __forceinline__ int32_t find_edge(const int32_t *__restrict__ node_edge_off,
+                                             const int32_t *__restrict__ head, int32_t a,
+                                             int32_t b) {
+  const int32_t t = a < b ? a : b, h = a < b ? b : a;
+  int32_t lo = node_edge_off[t], hi = node_edge_off[t + 1];
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (head[mid] < h) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < node_edge_off[t + 1] && head[lo] == h) ? lo : -1;
+}
+
+template <int D>
+__global__ void k_elem_edge(const int32_t *__restrict__ elem, int64_t nelem,
+                            const int32_t *__restrict__ node_edge_off,
+                            const int32_t *__restrict__ head, int32_t *elem_edge,
+                            int8_t *elem_edge_sign, int32_t *edge_cnt, StatusBlock *st) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nelem || build_failed(st)) return;
+  int32_t v[D + 1];
+  load_conn<D>(elem, e, v);
+  constexpr int NE = EL<D>::NE;
+#pragma unroll
+  for (int le = 0; le < NE; ++le) {
+    const int32_t p = v[pair_p<D>(le)], q = v[pair_q<D>(le)];
+    const int32_t id = find_edge(node_edge_off, head, p, q);
+    elem_edge[e * NE + le] = id;
+    elem_edge_sign[e * NE + le] = p < q ? 1 : -1;
+    if (id < 0) raise_status(st, EB_EINVAL, e);
+    else if (edge_cnt) atomicAdd(&edge_cnt[id], 1);
+  }
+}
+
+template <int D>
+__global__ void k_bface_edge(const int32_t *__restrict__ bface, int64_t nb,
+                             const int32_t *__restrict__ node_edge_off,
+                             const int32_t *__restrict__ head, int32_t *bface_edge,
+                             const StatusBlock *st) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nb || build_failed(st)) return;
+  if constexpr (D == 2) {
+    bface_edge[f] = find_edge(node_edge_off, head, bface[2 * f], bface[2 * f + 1]);
+  } else {
+    const int32_t a = bface[3 * f], b = bface[3 * f + 1], c = bface[3 * f + 2];
+    bface_edge[3 * f + 0] = find_edge(node_edge_off, head, a, b);
+    bface_edge[3 * f + 1] = find_edge(node_edge_off, head, a, c);
+    bface_edge[3 * f + 2] = find_edge(node_edge_off, head, b, c);
+  }
+}
+
+template <int D>
+__global__ void k_scatter_edge_inc(int64_t nelem, const int32_t *__restrict__ elem_edge,
+                                   int32_t *cur, int32_t *edge_inc, const StatusBlock *st) {
+  constexpr int NE = EL<D>::NE;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nelem * NE || build_failed(st)) return;
+  const int32_t id = elem_edge[i];
+  if (id < 0) return;
+  const int32_t pos = atomicSub(&cur[id], 1) - 1;
+  edge_inc[pos] = (int32_t)i;
+}
+
+template <int D>
+int build_edges_impl(int64_t nv, int64_t nelem, const int32_t *elem, const double *coords,
+                     int32_t *node_inc_off, int32_t *node_inc, void *ws, eb_sizes *sizes,
+                     hipStream_t s) {
+  const WsLayout L = ws_layout(D, nv, nelem);
+  StatusBlock *st = ws_at<StatusBlock>(ws, 0);
+  int32_t *eoff = ws_at<int32_t>(ws, L.eoff), *foff = ws_at<int32_t>(ws, L.foff);
+  int32_t *bidx = ws_at<int32_t>(ws, L.bidx), *bfn = ws_at<int32_t>(ws, L.bfn);
+  int32_t *bfn_scan = ws_at<int32_t>(ws, L.bfn_scan), *ein = ws_at<int32_t>(ws, L.ein_scan);
+  int32_t *tmp = ws_at<int32_t>(ws, L.scan_tmp);
+  const Coords X = coords_rows(coords, D, nv);
+
+  EB_TRY(fill_i32(reinterpret_cast<int32_t *>(st), sizeof(StatusBlock) / 4, 0, s));
+  // the six per-node arrays are contiguous lines of the workspace
+  EB_TRY(fill_i32(eoff, (int64_t)((L.scan_tmp - L.eoff) / 4), 0, s));
+  EB_TRY(fill_i32(node_inc_off, nv + 1, 0, s));
+
+  // node -> element lists
+  if (nelem > 0) {
+    hipLaunchKernelGGL(k_count_nodes<D>, dim3(grid_for(nelem, 256)), dim3(256), 0, s, elem,
+                       nelem, nv, X, node_inc_off, st);
+    EB_LAUNCH_CHECK();
+  }
+  // the row ends must be the scan total of what was counted: elements
+  // rejected above are neither counted nor scattered
+  EB_TRY(scan_inclusive(node_inc_off, node_inc_off, nv, node_inc_off + nv, tmp, s));
+  if (nelem > 0) {
+    hipLaunchKernelGGL(k_scatter_nodes<D>, dim3(grid_for(nelem, 256)), dim3(256), 0, s, elem,
+                       nelem, nv, node_inc_off, node_inc);
+    EB_LAUNCH_CHECK();
+  }
+  EB_TRY(rowsort(node_inc_off, node_inc, nv, s));
+
+  // per-node counts of edges, boundary faces, boundary nodes
+  TopoArgs ta{};
+  ta.nv = nv;
+  ta.elem = elem;
+  ta.X = X;
+  ta.node_inc_off = node_inc_off;
+  ta.node_inc = node_inc;
+  ta.outdeg = eoff;
+  ta.fmin = foff;
+  ta.bflag = bidx;
+  ta.bfn = bfn;
+  ta.ein = ein;
+  ta.st = st;
+  hipLaunchKernelGGL((k_node_topo<D, false>), dim3(grid_for(nv, TB)), dim3(TB), 0, s, ta);
+  EB_LAUNCH_CHECK();
+  EB_TRY(scan_exclusive(eoff, eoff, nv + 1, &st->totals[T_EDGES], tmp, s));
+  EB_TRY(scan_exclusive(foff, foff, nv + 1, &st->totals[T_BFACES], tmp, s));
+  EB_TRY(scan_exclusive(bidx, bidx, nv + 1, &st->totals[T_BNODES], tmp, s));
+  EB_TRY(scan_inclusive(bfn, bfn_scan, nv + 1, nullptr, tmp, s));
+  EB_TRY(scan_inclusive(ein, ein, nv + 1, nullptr, tmp, s));
+
+  StatusBlock h;
+  EB_HIP_CHECK(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
+  EB_HIP_CHECK(hipStreamSynchronize(s));
+  sizes->dim = D;
+  sizes->n_nodes = nv;
+  sizes->n_elems = nelem;
+  sizes->n_edges = h.totals[T_EDGES];
+  sizes->n_bfaces = h.totals[T_BFACES];
+  sizes->n_bnodes = h.totals[T_BNODES];
+  if (h.status != EB_OK)
+    set_detail("%s at %s %lld", eb_status_string(h.status),
+               h.status == EB_ERANGE || h.status == EB_EDEGENERATE ? "element" : "node",
+               (long long)h.detail);
+  return h.status;
+}
+
+template <int D>
+int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
+              const eb_topology *tp, void *ws, hipStream_t s) {
+  const int64_t nv = sz->n_nodes, nelem = sz->n_elems;
+  const WsLayout L = ws_layout(D, nv, nelem);
+  StatusBlock *st = ws_at<StatusBlock>(ws, 0);
+  int32_t *eoff = ws_at<int32_t>(ws, L.eoff), *foff = ws_at<int32_t>(ws, L.foff);
+  int32_t *bidx = ws_at<int32_t>(ws, L.bidx), *bfn = ws_at<int32_t>(ws, L.bfn);
+  int32_t *bfn_scan = ws_at<int32_t>(ws, L.bfn_scan), *ein = ws_at<int32_t>(ws, L.ein_scan);
+  int32_t *tmp = ws_at<int32_t>(ws, L.scan_tmp);
+  constexpr int NE = EL<D>::NE;
+
+  EmitNodeArgs en{nv, D, eoff, bidx, bfn, bfn_scan, ein, tp->node_edge_off, tp->node_bnode,
+                  tp->bnode, tp->bnode_face_off, tp->node_in_off, st};
+  hipLaunchKernelGGL(k_emit_nodes, dim3(grid_for(nv + 1, 256)), dim3(256), 0, s, en);
+  EB_LAUNCH_CHECK();
+
+  TopoArgs ta{};
+  ta.nv = nv;
+  ta.elem = elem;
+  ta.X = coords_rows(coords, D, nv);
+  ta.node_inc_off = tp->node_inc_off;
+  ta.node_inc = tp->node_inc;
+  ta.eoff = eoff;
+  ta.foff = foff;
+  ta.edge_tail = tp->edge;
+  ta.edge_head = tp->edge + sz->n_edges;
+  ta.bface = tp->bface;
+  ta.bface_owner = tp->bface_owner;
+  ta.in_cur = tp->node_in_off;
+  ta.node_in_edge = tp->node_in_edge;
+  ta.bf_cur = bfn_scan;
+  ta.bnode_face = tp->bnode_face;
+  ta.st = st;
+  hipLaunchKernelGGL((k_node_topo<D, true>), dim3(grid_for(nv, TB)), dim3(TB), 0, s, ta);
+  EB_LAUNCH_CHECK();
+  EB_TRY(rowsort(tp->node_in_off, tp->node_in_edge, nv, s));
+  EB_TRY(rowsort(tp->bnode_face_off, tp->bnode_face, sz->n_bnodes, s));
+
+  const bool want_inc = tp->edge_inc_off && tp->edge_inc;
+  if (want_inc) EB_TRY(fill_i32(tp->edge_inc_off, sz->n_edges + 1, 0, s));
+  if (nelem > 0) {
+    hipLaunchKernelGGL(k_elem_edge<D>, dim3(grid_for(nelem, 256)), dim3(256), 0, s, elem,
+                       nelem, (const int32_t *)tp->node_edge_off,
+                       (const int32_t *)(tp->edge + sz->n_edges), tp->elem_edge,
+                       tp->elem_edge_sign, want_inc ? tp->edge_inc_off : nullptr, st);
+    EB_LAUNCH_CHECK();
+  }
+  if (sz->n_bfaces > 0) {
+    hipLaunchKernelGGL(k_bface_edge<D>, dim3(grid_for(sz->n_bfaces, 256)), dim3(256), 0, s,
+                       (const int32_t *)tp->bface, sz->n_bfaces,
+                       (const int32_t *)tp->node_edge_off,
+                       (const int32_t *)(tp->edge + sz->n_edges), tp->bface_edge, st);
+    EB_LAUNCH_CHECK();
+  }
+  if (want_inc) {
+    EB_TRY(scan_inclusive(tp->edge_inc_off, tp->edge_inc_off, sz->n_edges, nullptr, tmp, s));
+    EB_TRY(fill_i32(tp->edge_inc_off + sz->n_edges, 1, (int32_t)(NE * nelem), s));
+    if (nelem > 0) {
+      hipLaunchKernelGGL(k_scatter_edge_inc<D>, dim3(grid_for(nelem * NE, 256)), dim3(256), 0,
+                         s, nelem, (const int32_t *)tp->elem_edge, tp->edge_inc_off,
+                         tp->edge_inc, st);
+      EB_LAUNCH_CHECK();
+    }
+    EB_TRY(rowsort(tp->edge_inc_off, tp->edge_inc, sz->n_edges, s));
+  }
+  return EB_OK;
+}
+
+}  // namespace
+}  // namespace eb
+
+using namespace eb;
+
+extern "C" {
+
+int eb_build_edges(int dim, int64_t n_nodes, int64_t n_elems, const int32_t *elem,
+                   const double *coords, int32_t *node_inc_off, int32_t *node_inc, void *ws,
+                   size_t ws_bytes, eb_sizes *sizes_host, hipStream_t stream) {
+  clear_detail();
+  if (dim != 2 && dim != 3) {
+    set_detail("dim must be 2 or 3, got %d", dim);
+    return EB_EINVAL;
+  }
+  if (n_nodes <= 0 || n_elems < 0 || !sizes_host || !coords || !node_inc_off ||
+      (n_elems > 0 && (!elem || !node_inc))) {
+    set_detail("null pointer or negative size");
+    return EB_EINVAL;
+  }
+  const int64_t ne = dim == 2 ? 3 : 6;
+  if (ne * n_elems >= (int64_t(1) << 31) || n_nodes >= (int64_t(1) << 31) - 1) {
+    set_detail("grid too large for int32 indexing");
+    return EB_EOVERFLOW;
+  }
+  if (!aligned16(elem) || !aligned16(coords) || !aligned16(node_inc_off) ||
+      !aligned16(node_inc)) {
+    set_detail("arrays must be 16-byte aligned");
+    return EB_EINVAL;
+  }
+  EB_TRY(check_ws(dim, n_nodes, n_elems, ws, ws_bytes));
+  return dim == 2 ? build_edges_impl<2>(n_nodes, n_elems, elem, coords, node_inc_off, node_inc,
+                                        ws, sizes_host, stream)
+                  : build_edges_impl<3>(n_nodes, n_elems, elem, coords, node_inc_off, node_inc,
+                                        ws, sizes_host, stream);
+}
+
+int eb_build_edges_emit(const eb_sizes *sizes, const int32_t *elem, const double *coords,
+                        const eb_topology *topo, void *ws, size_t ws_bytes,
+                        hipStream_t stream) {
+  clear_detail();
+  EB_TRY(check_sizes(sizes));
+  if (!topo || !coords || (sizes->n_elems > 0 && !elem)) {
+    set_detail("null pointer");
+    return EB_EINVAL;
+  }
+  const eb_topology &t = *topo;
+  const bool has_e = sizes->n_edges > 0, has_el = sizes->n_elems > 0;
+  const bool has_f = sizes->n_bfaces > 0, has_bn = sizes->n_bnodes > 0;
+  if (!t.node_edge_off || !t.node_inc_off || !t.node_in_off || !t.node_bnode ||
+      !t.bnode_face_off || (has_e && (!t.edge || !t.node_in_edge)) ||
+      (has_el && (!t.elem_edge || !t.elem_edge_sign || !t.node_inc)) ||
+      (has_f && (!t.bface || !t.bface_owner || !t.bface_edge)) ||
+      (has_bn && (!t.bnode || !t.bnode_face))) {
+    set_detail("a required topology array is null");
+    return EB_EINVAL;
+  }
+  if ((t.edge_inc_off == nullptr) != (t.edge_inc == nullptr)) {
+    set_detail("edge_inc_off and edge_inc must both be set or both be null");
+    return EB_EINVAL;
+  }
+  EB_TRY(check_ws(sizes->dim, sizes->n_nodes, sizes->n_elems, ws, ws_bytes));
+  return sizes->dim == 2 ? emit_impl<2>(sizes, elem, coords, topo, ws, stream)
+                         : emit_impl<3>(sizes, elem, coords, topo, ws, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/eb.h declares, and host-side validation rejects bad arguments with
+the documented status codes before any device work is enqueued."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "eb.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(eb_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2502_00778_amd import _lib
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    from paper_2502_00778_amd import _lib
+    names = declared_functions()
+    assert "eb_directed_areas" in names and len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_status_strings(L):
+    for code in range(0, -9, -1):
+        s = L.eb_status_string(code).decode()
+        assert s and s != "unknown status"
+    assert L.eb_status_string(-99).decode() == "unknown status"
+
+
+def test_workspace_bytes(L):
+    assert L.eb_workspace_bytes(4, 10, 10) == 0
+    assert L.eb_workspace_bytes(3, 0, 10) == 0
+    small = L.eb_workspace_bytes(3, 100, 300)
+    big = L.eb_workspace_bytes(3, 161 ** 3, 6 * 160 ** 3)
+    assert 256 < small < big
+    # per-node arrays plus scan scratch: well under 1 KB per node
+    assert big < 161 ** 3 * 64
+
+
+def test_host_validation(L):
+    from paper_2502_00778_amd._lib import EbSizes, EbTopology
+    sz = EbSizes()
+    P = ctypes.c_void_p
+    fake = P(256)  # never dereferenced: validation fails first
+    rc = L.eb_build_edges(4, 10, 10, fake, fake, fake, fake, fake, 10 ** 6,
+                          ctypes.byref(sz), None)
+    assert rc == -1
+    rc = L.eb_build_edges(3, 10, 2 ** 30, fake, fake, fake, fake, fake, 10 ** 6,
+                          ctypes.byref(sz), None)
+    assert rc == -6  # 6 * 2^30 local edges overflow int32 indexing
+    rc = L.eb_build_edges(3, 10, 10, P(258), fake, fake, fake, fake, 10 ** 6,
+                          ctypes.byref(sz), None)
+    assert rc == -1  # misaligned
+    rc = L.eb_build_edges(3, 10, 10, fake, fake, fake, fake, fake, 16,
+                          ctypes.byref(sz), None)
+    assert rc == -5  # workspace too small
+    assert b"workspace" in L.eb_last_error_detail()
+    sz = EbSizes(dim=3, n_nodes=8, n_elems=6, n_edges=19, n_bfaces=12, n_bnodes=8)
+    tp = EbTopology()
+    rc = L.eb_directed_areas(ctypes.byref(sz), ctypes.byref(tp), fake, fake, 7, fake,
+                             None, None, fake, 10 ** 6, None)
+    assert rc == -1  # bad reduce
+    rc = L.eb_directed_areas(ctypes.byref(sz), ctypes.byref(tp), fake, fake, 1, fake,
+                             None, None, fake, 10 ** 6, None)
+    assert rc == -1  # gather needs node_inc etc.
+    assert b"missing topology" in L.eb_last_error_detail()
+    rc = L.eb_dual_volumes(ctypes.byref(sz), ctypes.byref(tp), fake, fake, 1, None, 0,
+                           fake, fake, 10 ** 6, None)
+    assert rc == -1  # edge mode needs n
+    rc = L.eb_set_gather_shape(100, 2, 1)
+    assert rc == -1
+    sz.dim = 5
+    rc = L.eb_directed_areas_backward(ctypes.byref(sz), ctypes.byref(tp), fake, fake,
+                                      None, None, None, 0, fake, fake, 10 ** 6, None)
+    assert rc == -1
+
+
+def test_package_import_does_not_touch_gpu():
+    import paper_2502_00778_amd as eb
+    assert callable(eb.directed_areas)
+    assert eb.get_gather_shape()[0] in (64, 128, 256)
