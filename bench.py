@@ -1,0 +1,312 @@
+#!/usr/bin/env python3
+"""Benchmark of the edge-based metric path on one MI355X.
+
+One step = the whole hot path over the 161^3 stretched Kuhn grid
+(24,576,000 tets): edge extraction and boundary elements (eb_build_edges +
+eb_build_edges_emit), the fused forward pass n, b, V (eb_directed_areas,
+deterministic gather), the edge-loop dual volumes (eb_dual_volumes EDGE) and
+the adjoint dL/dx (eb_directed_areas_backward).  Inputs are resident in HBM
+before the timed region.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("Melements/s & HBM GB/s (% peak) for directed-area+dual-volume build; "
+          "batched+adjoint vs plain")
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def alg_bytes_forward(dim, nv, nel, ne_, nb, nbn):
+    """Algorithmic bytes of one fused forward pass (n, b, V): every input read
+    once, every output written once, plus one element->edge addressing array.
+      coords 8D Nv + elems 4(D+1) NE + addressing 4 ne NE + n 8D Ne + V 8 Nv
+      + b 8D Nbn + boundary elements 4(D + ne_B) NB"""
+    ne = 3 if dim == 2 else 6
+    neb = 1 if dim == 2 else 3
+    return (8 * dim * nv + 4 * (dim + 1) * nel + 4 * ne * nel + 8 * dim * ne_ + 8 * nv
+            + 8 * dim * nbn + 4 * (dim + neb) * nb)
+
+
+def alg_bytes_backward(dim, nv, nel, ne_, nb, nbn):
+    """coords + elems + elem_edge + boundary elements + dL/dn + dL/db + dL/dV
+    + dL/dx (each once)."""
+    ne = 3 if dim == 2 else 6
+    neb = 1 if dim == 2 else 3
+    return (8 * dim * nv + 4 * (dim + 1) * nel + 4 * ne * nel + 4 * (dim + neb) * nb
+            + 8 * dim * ne_ + 8 * dim * nbn + 8 * nv + 8 * dim * nv)
+
+
+def alg_bytes_edge_volume(dim, nv, ne_):
+    """edges 8 Ne + n 8D Ne + coords 8D Nv + V 8 Nv."""
+    return 8 * ne_ + 8 * dim * ne_ + 8 * dim * nv + 8 * nv
+
+
+def source_digest(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2502_00778_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_key, digest):
+    """HBM bytes per dispatch measured with rocprofv3 counters, if the kernel
+    source is unchanged since (profiles/hbm_traffic_*.md)."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{kernel_key}.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"source digest:\s*`?([0-9a-f]+)`?", txt)
+    b = re.search(r"traffic bytes per dispatch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != digest:
+        return None
+    return float(b.group(1))
+
+
+class Timer:
+    def __init__(self, torch):
+        self.torch = torch
+
+    def time(self, fn, reps):
+        t = self.torch
+        s = t.cuda.current_stream()
+        ev = [(t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:
+            a.record(s)
+            fn()
+            b.record(s)
+        t.cuda.synchronize()
+        ms = np.array([a.elapsed_time(b) for a, b in ev])
+        return float(np.mean(ms)), float(np.median(ms)), float(np.min(ms))
+
+
+def cpu_baseline(mesh_full, n_layers=24):
+    """The oracle on a slab of the same grid: the first n_layers node layers
+    in z (all tets between them).  Same rows as a GPU step: topology, n, b, V,
+    and the gradient of the same loss (all nodes)."""
+    import meshgen
+    import oracle
+    n = mesh_full.meta["n"]
+    nv_slab = n * n * n_layers
+    ne_slab = 6 * (n - 1) ** 2 * (n_layers - 1)
+    X = np.ascontiguousarray(mesh_full.coords[:, :nv_slab])
+    E = np.ascontiguousarray(mesh_full.elems[:ne_slab])
+    threads = oracle.num_threads()
+    t0 = time.perf_counter()
+    ot = oracle.topology(3, X, E)
+    t1 = time.perf_counter()
+    oracle.metrics(ot, X, E)
+    t2 = time.perf_counter()
+    w, c, beta = meshgen.loss_weights(0, 3, ot.n_edges, ot.n_nodes, ot.n_bnodes)
+    oracle.node_grad(ot, X, E, w, c, beta)
+    t3 = time.perf_counter()
+    total = t3 - t0
+    return {
+        "value": round(ne_slab / total / 1e6, 3),
+        "unit": "Melements/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"first {n_layers} of {n} z node layers of the same grid: {ne_slab} tets; "
+                   f"topology {t1 - t0:.2f} s, n/b/V {t2 - t1:.2f} s, gradient {t3 - t2:.2f} s"),
+    }
+
+
+def calibrate_copy(nbytes=1 << 30, reps=5):
+    """A plain device copy of known size (for scaling the HBM counters)."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="3d-scale")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--phase-reps", type=int, default=10)
+    ap.add_argument("--only", default="", help="profiling: run only this phase "
+                    "(topo|fwd|fwd_atomic|vol_edge|bwd|bwd_gather) --steps times")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding "
+                          "is a design note, not an implementation", "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+
+    import torch
+
+    import meshgen
+    import paper_2502_00778_amd as eb
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    t0 = time.perf_counter()
+    mesh = meshgen.make(args.config, args.seed)
+    log(f"[bench] grid {mesh.name}: {mesh.n_nodes} nodes, {mesh.n_elems} elements "
+        f"({time.perf_counter() - t0:.1f} s to generate)")
+    dim = mesh.dim
+    X = torch.from_numpy(mesh.coords).cuda()
+    E = torch.from_numpy(mesh.elems).cuda()
+    topo = eb.build_edges(E, X, edge_inc=False)
+    nv, nel, ne_, nb, nbn = (topo.n_nodes, topo.n_elems, topo.n_edges, topo.n_bfaces,
+                             topo.n_bnodes)
+    w, c, beta = meshgen.loss_weights(args.seed, dim, ne_, nv, nbn)
+    W = torch.from_numpy(w).cuda()
+    C = torch.from_numpy(c).cuda()
+    B = torch.from_numpy(beta).cuda()
+    n = torch.empty(dim, ne_, dtype=torch.float64, device="cuda")
+    b = torch.empty(dim, nbn, dtype=torch.float64, device="cuda")
+    V = torch.empty(nv, dtype=torch.float64, device="cuda")
+    Ve = torch.empty(nv, dtype=torch.float64, device="cuda")
+    g = torch.empty(dim, nv, dtype=torch.float64, device="cuda")
+    bwd_reduce = "atomic"
+
+    def ph_topo():
+        eb.build_edges(E, X, edge_inc=False)
+
+    def ph_fwd():
+        eb.directed_areas(X, topo, E, "gather", n_out=n, b_out=b, v_out=V)
+
+    def ph_fwd_atomic():
+        eb.directed_areas(X, topo, E, "atomic", n_out=n, b_out=b, v_out=V)
+
+    def ph_vol_edge():
+        eb.dual_volumes(X, topo, E, "edge", n=n, reduce="gather", out=Ve)
+
+    def ph_bwd():
+        eb.directed_areas_backward(X, topo, E, W, B, C, reduce=bwd_reduce, out=g)
+
+    def ph_bwd_gather():
+        eb.directed_areas_backward(X, topo, E, W, B, C, reduce="gather", out=g)
+
+    phases = {"topo": ph_topo, "fwd": ph_fwd, "fwd_atomic": ph_fwd_atomic,
+              "vol_edge": ph_vol_edge, "bwd": ph_bwd, "bwd_gather": ph_bwd_gather}
+
+    if args.only:
+        fn = phases[args.only]
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        log(f"[bench] ran {args.only} x{args.steps}")
+        return
+
+    def step():
+        t = eb.build_edges(E, X, edge_inc=False)
+        nn_, bb, vv = eb.directed_areas(X, t, E, "gather")
+        eb.dual_volumes(X, t, E, "edge", n=nn_, reduce="gather")
+        eb.directed_areas_backward(X, t, E, W, B, C, reduce=bwd_reduce)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[bench] warmup {args.warmup} done; timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    eb.check_errors(topo)
+    log(f"[bench] {dt * 1e3:.3f} ms/step")
+
+    # per-phase event timings on the stream the kernels run on
+    tm = Timer(torch)
+    res = {}
+    for name, fn in phases.items():
+        fn()
+        res[name] = tm.time(fn, args.phase_reps)
+        log(f"[bench] phase {name}: mean {res[name][0]:.3f} ms, median {res[name][1]:.3f}, "
+            f"min {res[name][2]:.3f}")
+    eb.check_errors(topo)
+
+    bf = alg_bytes_forward(dim, nv, nel, ne_, nb, nbn)
+    bb_ = alg_bytes_backward(dim, nv, nel, ne_, nb, nbn)
+    bv = alg_bytes_edge_volume(dim, nv, ne_)
+    t_fwd = res["fwd"][0] * 1e-3
+    achieved = bf / t_fwd / 1e9
+    digest = source_digest("eb_metrics.hip", "eb_geom.h", "eb_kernels.h")
+    traffic = read_traffic("fwd_gather_161", digest)
+
+    def ph(name, bytes_):
+        ms = res[name][0]
+        out = {"ms": round(ms, 4), "Melements_per_s": round(nel / (ms * 1e-3) / 1e6, 1)}
+        if bytes_:
+            out["alg_GBps"] = round(bytes_ / (ms * 1e-3) / 1e9, 1)
+            out["frac_hbm_peak"] = round(bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        return out
+
+    line = {
+        "metric": METRIC,
+        "value": round(nel / dt / 1e6, 3),
+        "unit": "Melements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{args.config}: {mesh.name} grid, {nel} elements, {nv} nodes, "
+                         f"{ne_} edges; step = edge extraction + fused n/b/V forward (gather) "
+                         f"+ edge-loop V + adjoint ({bwd_reduce})"),
+            "elements": nel, "nodes": nv, "edges": ne_, "seed": args.seed,
+        },
+        "roofline": {
+            "kernel": "k_fwd_gather (eb_directed_areas, gather: n, b, V fused)",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "alg_bytes": bf,
+        },
+        "phases": {
+            "edge_extraction": ph("topo", None),
+            "forward_gather": ph("fwd", bf),
+            "forward_atomic": ph("fwd_atomic", bf),
+            "edge_volume_gather": ph("vol_edge", bv),
+            f"adjoint_{bwd_reduce}": ph("bwd", bb_),
+            "adjoint_gather": ph("bwd_gather", bb_),
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a slab of the same grid")
+        line["cpu_baseline"] = cpu_baseline(mesh)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -74,7 +74,7 @@ typedef enum {
                            it as smallest vertex */
 } eb_status;
 
-#define EB_MAX_OUT_EDGES 32
+#define EB_MAX_OUT_EDGES 31
 #define EB_MAX_NODE_FACES 64
 
 typedef enum { EB_REDUCE_ATOMIC = 0, EB_REDUCE_GATHER = 1 } eb_reduce;
@@ -99,6 +99,14 @@ typedef struct {
  *   edge_inc       [ne*n_elems]     as elem*ne + local, ascending per edge
  *   node_inc_off   [n_nodes+1]    elements of each node as elem*(dim+1) +
  *   node_inc       [(dim+1)*n_elems]  local vertex, ascending per node
+ *   node_inc_slot  [(dim+1)*n_elems]  uint16, one per node_inc entry (node j,
+ *                                 element E, local index l): for m = 0..dim-1
+ *                                 let o_m = elem[E][m], except o_l =
+ *                                 elem[E][dim] (j's place taken by the last
+ *                                 vertex); bits 5m..5m+4 hold the position of
+ *                                 edge (j, o_m) among j's out-edges (those
+ *                                 with tail j, in node_edge_off order), or 31
+ *                                 when o_m < j; higher bits are zero
  *   node_in_off    [n_nodes+1]    ids of edges whose head is the node,
  *   node_in_edge   [n_edges]        ascending per node
  *   bface          [n_bfaces][dim] boundary elements (faces of exactly one
@@ -123,6 +131,7 @@ typedef struct {
   int8_t *elem_edge_sign;
   int32_t *edge_inc_off, *edge_inc;
   int32_t *node_inc_off, *node_inc;
+  uint16_t *node_inc_slot;
   int32_t *node_in_off, *node_in_edge;
   int32_t *bface;
   int32_t *bface_owner;

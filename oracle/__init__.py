@@ -33,7 +33,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "node id out of range",
           -6: "size overflow"}
 
 TOPO_ARRAYS = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign",
-               "edge_inc_off", "edge_inc", "node_inc_off", "node_inc",
+               "edge_inc_off", "edge_inc", "node_inc_off", "node_inc", "node_inc_slot",
                "node_in_off", "node_in_edge", "bface", "bface_owner",
                "bface_edge", "bnode", "node_bnode", "bnode_face_off",
                "bnode_face")
@@ -113,7 +113,7 @@ class Topology:
         self.arrays = {}
         for name in TOPO_ARRAYS:
             cnt = L.oracle_topo_get(self._h, name.encode(), None)
-            dt = np.int8 if name == "elem_edge_sign" else np.int32
+            dt = {"elem_edge_sign": np.int8, "node_inc_slot": np.uint16}.get(name, np.int32)
             a = np.empty(cnt, dtype=dt)
             L.oracle_topo_get(self._h, name.encode(), _ptr(a))
             self.arrays[name] = a

@@ -42,6 +42,10 @@
 //   elem_edge_sign [NE][ne]  +1 iff elem[p] < elem[q]
 //   edge_inc    CSR over edges of elem*ne+local, ascending
 //   node_inc    CSR over nodes of elem*(D+1)+local, ascending
+//   node_inc_slot  per node_inc entry (node j, element E, local l): for
+//               m < D, o_m = E's vertex m, except that j's own place l is
+//               taken by vertex D; 5 bits per m give the rank of edge (j, o_m)
+//               among the edges whose tail is j, or 31 when o_m < j
 //   node_edge_off  CSR offsets of edges by tail
 //   node_in     CSR over nodes of the ids of edges whose head is the node
 //   bface       [NB][D] faces owned by one element, in ascending sorted-id
@@ -247,6 +251,7 @@ struct Topo {
   std::vector<int32_t> node_edge_off, elem_edge, edge_inc_off, edge_inc;
   std::vector<int8_t> elem_edge_sign;
   std::vector<int32_t> node_inc_off, node_inc, node_in_off, node_in_edge;
+  std::vector<uint16_t> node_inc_slot;
   std::vector<int32_t> bface, bface_owner, bface_edge, bnode, node_bnode;
   std::vector<int32_t> bnode_face_off, bnode_face;
 };
@@ -362,6 +367,22 @@ int build_topology(Topo &t, int dim, int64_t nv, int64_t nelem, const int32_t *e
         np[e * nn + i] = KeyPay{(uint64_t)elem[e * nn + i], (uint32_t)(e * nn + i)};
     csr_from_pairs(np, nv, t.node_inc_off, t.node_inc);
   }
+
+  // out-edge ranks of each incidence's other vertices
+  t.node_inc_slot.assign(t.node_inc.size(), 0);
+  for (int64_t v = 0; v < nv; ++v)
+    for (int32_t r = t.node_inc_off[v]; r < t.node_inc_off[v + 1]; ++r) {
+      const int64_t e = t.node_inc[r] / nn;
+      const int l = t.node_inc[r] % nn;
+      uint32_t code = 0;
+      for (int m = 0; m < dim; ++m) {
+        const int32_t om = elem[e * nn + (m == l ? dim : m)];
+        uint32_t rank = 31;
+        if (om > v) rank = (uint32_t)(find_edge(t, (int32_t)v, om) - t.node_edge_off[v]);
+        code |= rank << (5 * m);
+      }
+      t.node_inc_slot[r] = (uint16_t)code;
+    }
 
   // faces: sorted vertex ids of the face opposite each local vertex
   struct FaceKey {
@@ -584,6 +605,7 @@ int64_t oracle_topo_get(const void *h, const char *name, void *dst) {
       {"edge_inc", t.edge_inc.data(), t.edge_inc.size(), 4},
       {"node_inc_off", t.node_inc_off.data(), t.node_inc_off.size(), 4},
       {"node_inc", t.node_inc.data(), t.node_inc.size(), 4},
+      {"node_inc_slot", t.node_inc_slot.data(), t.node_inc_slot.size(), 2},
       {"node_in_off", t.node_in_off.data(), t.node_in_off.size(), 4},
       {"node_in_edge", t.node_in_edge.data(), t.node_in_edge.size(), 4},
       {"bface", t.bface.data(), t.bface.size(), 4},

@@ -25,7 +25,7 @@ EXPORTS = ("eb_workspace_bytes", "eb_build_edges", "eb_build_edges_emit",
            "eb_status_string", "eb_last_error_detail", "eb_version")
 
 TOPO_FIELDS = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign",
-               "edge_inc_off", "edge_inc", "node_inc_off", "node_inc",
+               "edge_inc_off", "edge_inc", "node_inc_off", "node_inc", "node_inc_slot",
                "node_in_off", "node_in_edge", "bface", "bface_owner",
                "bface_edge", "bnode", "node_bnode", "bnode_face_off",
                "bnode_face")

@@ -75,7 +75,8 @@ class Topology:
         out = {}
         for k, v in self.arrays.items():
             if v is not None:
-                out[k] = v.cpu().numpy()
+                a = v.cpu().numpy()
+                out[k] = a.view("uint16") if k == "node_inc_slot" else a
         return out
 
 
@@ -114,6 +115,7 @@ def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True
         edge_inc=torch.empty(max(ne * nel, 1), **i32) if edge_inc else None,
         node_inc_off=node_inc_off,
         node_inc=node_inc,
+        node_inc_slot=torch.empty(max((dim + 1) * nel, 1), dtype=torch.int16, device=dev),
         node_in_off=torch.empty(nv + 1, **i32),
         node_in_edge=torch.empty(max(ne_, 1), **i32),
         bface=torch.empty(nb, dim, **i32),
@@ -129,6 +131,7 @@ def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True
                                 ctypes.byref(st), _ptr(ws), wsb, s), "eb_build_edges_emit")
     # trim the placeholder lengths used for empty arrays
     arr["node_inc"] = arr["node_inc"][: (dim + 1) * nel]
+    arr["node_inc_slot"] = arr["node_inc_slot"][: (dim + 1) * nel]
     arr["node_in_edge"] = arr["node_in_edge"][:ne_]
     arr["bnode_face"] = arr["bnode_face"][: dim * nb]
     if edge_inc:

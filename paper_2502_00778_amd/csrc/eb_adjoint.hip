@@ -25,7 +25,9 @@ __device__ __forceinline__ V3 load_row3(const double *x, const double *y, const 
   return {x[i], y[i], 0.0};
 }
 
-// W_t for every local vertex t and C_E of element e
+// W_t for every local vertex t and C_E of element e.  All indices are
+// compile-time constants (the tail of each local edge is chosen with a
+// select), so nothing lands in scratch memory.
 template <int D>
 __device__ __forceinline__ void elem_weights(const FwdArgs &a, int64_t e, const int32_t (&v)[D + 1],
                                              V3 (&W)[D + 1], double &C) {
@@ -38,9 +40,11 @@ __device__ __forceinline__ void elem_weights(const FwdArgs &a, int64_t e, const 
     for (int le = 0; le < NE; ++le) {
       const int p = pair_p<D>(le), q = pair_q<D>(le);
       const int32_t ed = a.elem_edge[e * NE + le];
-      const V3 w = load_row3<D>(a.w_x, a.w_y, a.w_z, ed);
-      const int tl = v[p] < v[q] ? p : q;
-      W[tl] = W[tl] + kN * w;
+      const V3 w = kN * load_row3<D>(a.w_x, a.w_y, a.w_z, ed);
+      const V3 z = {0.0, 0.0, 0.0};
+      const bool tail_p = v[p] < v[q];
+      W[p] = W[p] + (tail_p ? w : z);
+      W[q] = W[q] + (tail_p ? z : w);
     }
   }
   C = 0.0;
@@ -51,34 +55,43 @@ __device__ __forceinline__ void elem_weights(const FwdArgs &a, int64_t e, const 
   }
 }
 
-// dL_E/dx_l for local vertex l
+// dL_E/dx_i for every local vertex i (compile-time indices only)
 template <int D>
-__device__ __forceinline__ V3 elem_grad(const V3 (&P)[D + 1], const V3 (&n)[D + 1], double det,
-                                        const V3 (&W)[D + 1], double C, int l) {
-  V3 G = (-C / D) * n[l];
+__device__ __forceinline__ void elem_grad_all(const V3 (&P)[D + 1], const V3 (&n)[D + 1], double det,
+                                              const V3 (&W)[D + 1], double C, V3 (&G)[D + 1]) {
+#pragma unroll
+  for (int i = 0; i <= D; ++i) G[i] = (-C / D) * n[i];
   if constexpr (D == 3) {
     const double hs = det > 0 ? 0.5 : -0.5;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      if (t == l) continue;
-      int p = 0;
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-        if (face3(t, k) == l) p = k;
-      const int nx = face3(t, (p + 1) % 3), pv = face3(t, (p + 2) % 3);
-      G = G + hs * cross(P[nx] - P[pv], W[t]);
+      const int fa = face3(t, 0), fb = face3(t, 1), fc = face3(t, 2);
+      G[fa] = G[fa] + hs * cross(P[fb] - P[fc], W[t]);
+      G[fb] = G[fb] + hs * cross(P[fc] - P[fa], W[t]);
+      G[fc] = G[fc] + hs * cross(P[fa] - P[fb], W[t]);
     }
   } else {
     const double s = det > 0 ? 1.0 : -1.0;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
-      if (t == l) continue;
       const V3 R = s * rotW(W[t]);
-      if (l == (t + 2) % 3) G = G + R;
-      else G = G - R;
+      const int b = (t + 1) % 3, c = (t + 2) % 3;
+      G[c] = G[c] + R;
+      G[b] = G[b] - R;
     }
   }
-  return G;
+}
+
+// the entry of G[] at runtime index l, by masked sums (no indexed access)
+template <int N>
+__device__ __forceinline__ V3 pick(const V3 (&G)[N], int l) {
+  V3 r = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const double m = (l == i) ? 1.0 : 0.0;
+    r = r + m * G[i];
+  }
+  return r;
 }
 
 template <int D>
@@ -103,15 +116,17 @@ __device__ __forceinline__ V3 bface_weight(const FwdArgs &a, int64_t f, const in
   return W;
 }
 
-// d(W.n_B)/dx of face vertex p
+// d(W.n_B)/dx of every face vertex
 template <int D>
-__device__ __forceinline__ V3 bface_grad(const V3 (&P)[D], V3 W, int p) {
+__device__ __forceinline__ void bface_grad_all(const V3 (&P)[D], V3 W, V3 (&G)[D]) {
   if constexpr (D == 3) {
-    const int nx = (p + 1) % 3, pv = (p + 2) % 3;
-    return 0.5 * cross(P[nx] - P[pv], W);
+    G[0] = 0.5 * cross(P[1] - P[2], W);
+    G[1] = 0.5 * cross(P[2] - P[0], W);
+    G[2] = 0.5 * cross(P[0] - P[1], W);
   } else {
     const V3 R = rotW(W);
-    return p == 1 ? R : -R;
+    G[1] = R;
+    G[0] = -R;
   }
 }
 
@@ -129,12 +144,13 @@ __global__ __launch_bounds__(256) void k_bwd_atomic_elem(FwdArgs a) {
   const double det = elem_normals<D>(P, n);
   double C;
   elem_weights<D>(a, e, v, W, C);
+  V3 G[D + 1];
+  elem_grad_all<D>(P, n, det, W, C, G);
 #pragma unroll
   for (int l = 0; l <= D; ++l) {
-    const V3 G = elem_grad<D>(P, n, det, W, C, l);
-    unsafeAtomicAdd(&a.g_x[v[l]], G.x);
-    unsafeAtomicAdd(&a.g_y[v[l]], G.y);
-    if (D == 3) unsafeAtomicAdd(&a.g_z[v[l]], G.z);
+    unsafeAtomicAdd(&a.g_x[v[l]], G[l].x);
+    unsafeAtomicAdd(&a.g_y[v[l]], G[l].y);
+    if (D == 3) unsafeAtomicAdd(&a.g_z[v[l]], G[l].z);
   }
 }
 
@@ -149,13 +165,13 @@ __global__ __launch_bounds__(256) void k_bwd_atomic_bface(FwdArgs a) {
     fv[s] = a.bface[f * D + s];
     P[s] = load_pt<D>(a.X, fv[s]);
   }
-  const V3 W = bface_weight<D>(a, f, fv);
+  V3 G[D];
+  bface_grad_all<D>(P, bface_weight<D>(a, f, fv), G);
 #pragma unroll
   for (int p = 0; p < D; ++p) {
-    const V3 G = bface_grad<D>(P, W, p);
-    unsafeAtomicAdd(&a.g_x[fv[p]], G.x);
-    unsafeAtomicAdd(&a.g_y[fv[p]], G.y);
-    if (D == 3) unsafeAtomicAdd(&a.g_z[fv[p]], G.z);
+    unsafeAtomicAdd(&a.g_x[fv[p]], G[p].x);
+    unsafeAtomicAdd(&a.g_y[fv[p]], G[p].y);
+    if (D == 3) unsafeAtomicAdd(&a.g_z[fv[p]], G[p].z);
   }
 }
 
@@ -178,7 +194,9 @@ __global__ __launch_bounds__(256) void k_bwd_gather(FwdArgs a) {
     const double det = elem_normals<D>(P, n);
     double C;
     elem_weights<D>(a, e, v, W, C);
-    g = g + elem_grad<D>(P, n, det, W, C, l);
+    V3 G[D + 1];
+    elem_grad_all<D>(P, n, det, W, C, G);
+    g = g + pick(G, l);
   }
   const int32_t bj = a.node_bnode ? a.node_bnode[j] : -1;
   if (bj >= 0 && (a.w_x || a.be_x)) {
@@ -193,7 +211,9 @@ __global__ __launch_bounds__(256) void k_bwd_gather(FwdArgs a) {
         P[s] = load_pt<D>(a.X, fv[s]);
         if (fv[s] == j) p = s;
       }
-      g = g + bface_grad<D>(P, bface_weight<D>(a, f, fv), p);
+      V3 G[D];
+      bface_grad_all<D>(P, bface_weight<D>(a, f, fv), G);
+      g = g + pick(G, p);
     }
   }
   a.g_x[j] = g.x;

@@ -71,6 +71,19 @@ __device__ __forceinline__ int face3(int t, int k) {
   return (tab >> (2 * (3 * t + k))) & 3u;
 }
 
+// The element's vertices other than local vertex l, in local order with l's
+// place taken by the last vertex (o_m = v[m], except o_l = v[D]).  Written
+// with selects on l, never an index, so nothing is placed in scratch memory.
+template <int D>
+__device__ __forceinline__ void others_of(const int32_t (&v)[D + 1], int l, int32_t (&o)[D]) {
+#pragma unroll
+  for (int m = 0; m < D; ++m) o[m] = (l == m) ? v[D] : v[m];
+}
+
+// 5-bit out-edge slot m of a node_inc_slot code; 31 = none
+constexpr int kNoSlot = 31;
+__device__ __forceinline__ int slot_of(uint32_t code, int m) { return (code >> (5 * m)) & 31; }
+
 template <int D> struct EL {
   static constexpr int NN = D + 1;
   static constexpr int NE = D == 2 ? 3 : 6;

@@ -13,6 +13,7 @@ struct FwdArgs {
   Coords X;
   const int32_t *elem_edge;
   const int32_t *node_inc_off, *node_inc;
+  const uint16_t *node_inc_slot;
   const int32_t *node_edge_off, *edge_tail, *edge_head;
   const int32_t *node_in_off, *node_in_edge;
   const int32_t *bface, *bface_edge, *node_bnode, *bnode_face_off, *bnode_face;

@@ -118,57 +118,83 @@ __device__ __forceinline__ int64_t tile_of_block(int64_t nblocks, int xcd_remap)
   return x * per + (x < rem ? x : rem) + k;
 }
 
+// Add to a thread-owned LDS accumulator.  Only the owning thread ever adds
+// to a slot, and one wave's LDS operations complete in issue order, so the
+// sum is taken in program order (deterministic); the atomic form lets the
+// add go without waiting for a read.
+__device__ __forceinline__ void lds_add(double *p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// position of head k among the out-edges [b, e) of a node (k is present)
+__device__ __forceinline__ int32_t find_head(const int32_t *__restrict__ head, int32_t b, int32_t e,
+                                             int32_t k) {
+  int32_t s = b;
+  while (s < e - 1 && head[s] != k) ++s;
+  return s - b;
+}
+
 template <int D, int TN, int CAP, int U>
 __global__ __launch_bounds__(TN) void k_fwd_gather(FwdArgs a) {
   __shared__ double acc[D][CAP];
-  __shared__ int32_t hd[CAP];
   const int t = threadIdx.x;
-  const int64_t nblocks = gridDim.x;
-  const int64_t tile = tile_of_block(nblocks, a.xcd_remap);
+  const int64_t tile = tile_of_block(gridDim.x, a.xcd_remap);
   const int64_t j0 = tile * TN;
   if (j0 >= a.nv) return;  // whole block leaves together
   const int64_t jend = min(j0 + (int64_t)TN, a.nv);
-  const int32_t e0 = a.node_edge_off[j0], e1 = a.node_edge_off[jend];
-  const int32_t cnt = e1 - e0;
+  const int32_t e0 = a.node_edge_off[j0];
+  const int32_t cnt = a.node_edge_off[jend] - e0;
   const bool in_lds = cnt <= CAP;
-  const int32_t *__restrict__ head = a.edge_head;
-  if (in_lds) {
-    for (int i = t; i < cnt; i += TN) {
-      hd[i] = head[e0 + i];
+  if (in_lds)
+    for (int i = t; i < cnt; i += TN)
 #pragma unroll
       for (int c = 0; c < D; ++c) acc[c][i] = 0.0;
-    }
-  }
   __syncthreads();
-  double *nout[3] = {a.n_x, a.n_y, a.n_z};
+  double *const nx = a.n_x, *const ny = a.n_y, *const nz = a.n_z;
   const int64_t j = j0 + t;
   if (j < a.nv) {
     const int32_t my0 = a.node_edge_off[j], my1 = a.node_edge_off[j + 1];
+    // accumulator of slot s: LDS acc[.][base + s], or the output itself
+    const int32_t base = in_lds ? my0 - e0 : my0;
+    auto add = [&](int s, const V3 &c) {
+      if (in_lds) {
+        lds_add(&acc[0][base + s], c.x);
+        lds_add(&acc[1][base + s], c.y);
+        if (D == 3) lds_add(&acc[2][base + s], c.z);
+      } else {
+        nx[base + s] += c.x;
+        ny[base + s] += c.y;
+        if (D == 3) nz[base + s] += c.z;
+      }
+    };
     if (!in_lds)
-      for (int32_t ed = my0; ed < my1; ++ed)
-#pragma unroll
-        for (int c = 0; c < D; ++c) nout[c][ed] = 0.0;
+      for (int32_t ed = my0; ed < my1; ++ed) {
+        nx[ed] = 0.0;
+        ny[ed] = 0.0;
+        if (D == 3) nz[ed] = 0.0;
+      }
     const V3 xj = load_pt<D>(a.X, (int32_t)j);
     double vs = 0.0;
     const int32_t r0 = a.node_inc_off[j], r1 = a.node_inc_off[j + 1];
     for (int32_t r = r0; r < r1; r += U) {
       int32_t inc[U];
+      uint32_t code[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) inc[u] = a.node_inc[min(r + u, r1 - 1)];
-      int32_t vv[U][D + 1];
-#pragma unroll
-      for (int u = 0; u < U; ++u) load_conn<D>(a.elem, inc[u] / (D + 1), vv[u]);
-      int32_t ov[U][D];
+      for (int u = 0; u < U; ++u) {
+        const int32_t rr = min(r + u, r1 - 1);
+        inc[u] = a.node_inc[rr];
+        code[u] = a.node_inc_slot[rr];
+      }
       V3 P[U][D];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int l = inc[u] % (D + 1);
-        int k = 0;
+        const int32_t e = inc[u] / (D + 1);
+        const int l = inc[u] - e * (D + 1);
+        int32_t v[D + 1], o[D];
+        load_conn<D>(a.elem, e, v);
+        others_of<D>(v, l, o);
 #pragma unroll
-        for (int q = 0; q <= D; ++q)
-          if (q != l) ov[u][k++] = vv[u][q];
-#pragma unroll
-        for (int k2 = 0; k2 < D; ++k2) P[u][k2] = load_pt<D>(a.X, ov[u][k2]);
+        for (int m = 0; m < D; ++m) P[u][m] = load_pt<D>(a.X, o[m]);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -187,22 +213,9 @@ __global__ __launch_bounds__(TN) void k_fwd_gather(FwdArgs a) {
         }
         vs += d;
 #pragma unroll
-        for (int k2 = 0; k2 < D; ++k2) {
-          const int32_t kk = ov[u][k2];
-          if (kk <= j || my1 == my0) continue;
-          if (in_lds) {
-            int s = my0 - e0;
-            while (hd[s] != kk && s < my1 - e0 - 1) ++s;
-            acc[0][s] += c.x;
-            acc[1][s] += c.y;
-            if (D == 3) acc[2][s] += c.z;
-          } else {
-            int32_t s = my0;
-            while (head[s] != kk && s < my1 - 1) ++s;
-            nout[0][s] += c.x;
-            nout[1][s] += c.y;
-            if (D == 3) nout[2][s] += c.z;
-          }
+        for (int m = 0; m < D; ++m) {
+          const int s = slot_of(code[u], m);
+          if (s != kNoSlot) add(s, c);
         }
       }
     }
@@ -229,23 +242,8 @@ __global__ __launch_bounds__(TN) void k_fwd_gather(FwdArgs a) {
         bs = bs + nB;
         const V3 cB = GK<D>::kBraw * nB;
 #pragma unroll
-        for (int s2 = 0; s2 < D; ++s2) {
-          const int32_t kk = fv[s2];
-          if (kk <= j || my1 == my0) continue;
-          if (in_lds) {
-            int s = my0 - e0;
-            while (hd[s] != kk && s < my1 - e0 - 1) ++s;
-            acc[0][s] += cB.x;
-            acc[1][s] += cB.y;
-            if (D == 3) acc[2][s] += cB.z;
-          } else {
-            int32_t s = my0;
-            while (head[s] != kk && s < my1 - 1) ++s;
-            nout[0][s] += cB.x;
-            nout[1][s] += cB.y;
-            if (D == 3) nout[2][s] += cB.z;
-          }
-        }
+        for (int s2 = 0; s2 < D; ++s2)
+          if (fv[s2] > j && my1 > my0) add(find_head(a.edge_head, my0, my1, fv[s2]), cB);
       }
       if (a.b_x) {
         constexpr double kb = 1.0 / D;
@@ -255,15 +253,19 @@ __global__ __launch_bounds__(TN) void k_fwd_gather(FwdArgs a) {
       }
     }
     if (!in_lds)
-      for (int32_t ed = my0; ed < my1; ++ed)
-#pragma unroll
-        for (int c = 0; c < D; ++c) nout[c][ed] *= GK<D>::kN;
+      for (int32_t ed = my0; ed < my1; ++ed) {
+        nx[ed] *= GK<D>::kN;
+        ny[ed] *= GK<D>::kN;
+        if (D == 3) nz[ed] *= GK<D>::kN;
+      }
   }
   if (in_lds) {
     __syncthreads();
-    for (int i = t; i < cnt; i += TN)
-#pragma unroll
-      for (int c = 0; c < D; ++c) nout[c][e0 + i] = acc[c][i] * GK<D>::kN;
+    for (int i = t; i < cnt; i += TN) {
+      nx[e0 + i] = acc[0][i] * GK<D>::kN;
+      ny[e0 + i] = acc[1][i] * GK<D>::kN;
+      if (D == 3) nz[e0 + i] = acc[2][i] * GK<D>::kN;
+    }
   }
 }
 
@@ -333,15 +335,15 @@ int launch_fwd_gather(const FwdArgs &a, const LaunchCfg &cfg, hipStream_t s) {
     EB_LAUNCH_CHECK();                                                                \
     return EB_OK;                                                                     \
   }
-  EB_GATHER_CASE(64, 640, 1)
-  EB_GATHER_CASE(64, 640, 2)
-  EB_GATHER_CASE(64, 640, 4)
-  EB_GATHER_CASE(128, 1152, 1)
-  EB_GATHER_CASE(128, 1152, 2)
-  EB_GATHER_CASE(128, 1152, 4)
-  EB_GATHER_CASE(256, 2176, 1)
-  EB_GATHER_CASE(256, 2176, 2)
-  EB_GATHER_CASE(256, 2176, 4)
+  EB_GATHER_CASE(64, 512, 1)
+  EB_GATHER_CASE(64, 512, 2)
+  EB_GATHER_CASE(64, 512, 4)
+  EB_GATHER_CASE(128, 1024, 1)
+  EB_GATHER_CASE(128, 1024, 2)
+  EB_GATHER_CASE(128, 1024, 4)
+  EB_GATHER_CASE(256, 2048, 1)
+  EB_GATHER_CASE(256, 2048, 2)
+  EB_GATHER_CASE(256, 2048, 4)
 #undef EB_GATHER_CASE
   set_detail("unsupported gather tile %d / unroll %d", cfg.tile, cfg.unroll);
   return EB_EINVAL;

@@ -25,7 +25,8 @@ namespace {
 constexpr int TB = 128;  // threads per block of the per-node topology kernels
 constexpr int MAXH = EB_MAX_OUT_EDGES;
 constexpr int MAXF = EB_MAX_NODE_FACES;
-static_assert(MAXH <= 32 && MAXH * MAXH < 0x8000, "face codes fit 15 bits");
+static_assert(MAXH <= 31, "slots are 5-bit with 31 reserved");
+constexpr int FCODE = 32;  // face code = lo_slot * FCODE + hi_slot
 
 // ----------------------------------------------------- node incidences
 
@@ -99,6 +100,7 @@ struct TopoArgs {
   int32_t *bface, *bface_owner;
   int32_t *in_cur, *node_in_edge;
   int32_t *bf_cur, *bnode_face;
+  uint16_t *node_inc_slot;
   StatusBlock *st;
 };
 
@@ -162,41 +164,44 @@ __global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
     }
   }
 
-  // 2. candidate faces with j as smallest vertex, coded by head slots
+  // 2. out-edge slot of each other vertex of every element of j (emitted as
+  //    node_inc_slot) and the candidate faces with j as smallest vertex,
+  //    coded by the slots of their two other vertices
   int nf = 0;
   for (int32_t r = r0; r < r1; ++r) {
     const int32_t inc = a.node_inc[r];
     const int64_t e = inc / (D + 1);
     const int l = inc - (int)(e * (D + 1));
-    int32_t v[D + 1];
+    int32_t v[D + 1], o[D];
     load_conn<D>(a.elem, e, v);
-    int sl[D];
-    int ns = 0;
-#pragma unroll
-    for (int q = 0; q <= D; ++q)
-      if (q != l && v[q] > j) sl[ns++] = head_slot(hs, t, nh, v[q]);
-    if constexpr (D == 3) {
-      // order the (up to 3) slots ascending
-      if (ns >= 2 && sl[0] > sl[1]) { int x = sl[0]; sl[0] = sl[1]; sl[1] = x; }
-      if (ns == 3) {
-        if (sl[1] > sl[2]) { int x = sl[1]; sl[1] = sl[2]; sl[2] = x; }
-        if (sl[0] > sl[1]) { int x = sl[0]; sl[0] = sl[1]; sl[1] = x; }
+    others_of<D>(v, l, o);
+    int s0 = o[0] > j ? head_slot(hs, t, nh, o[0]) : kNoSlot;
+    int s1 = o[1] > j ? head_slot(hs, t, nh, o[1]) : kNoSlot;
+    int s2 = kNoSlot;
+    if constexpr (D == 3) s2 = o[2] > j ? head_slot(hs, t, nh, o[2]) : kNoSlot;
+    if constexpr (EMIT) a.node_inc_slot[r] = (uint16_t)(s0 | (s1 << 5) | (D == 3 ? s2 << 10 : 0));
+    auto add_face = [&](int p, int q) {
+      if (p == kNoSlot || q == kNoSlot) return;
+      if (nf == MAXF) {
+        overflow = true;
+        return;
       }
-      for (int p = 0; p < ns; ++p)
-        for (int q = p + 1; q < ns; ++q) {
-          if (nf == MAXF) {
-            overflow = true;
-            continue;
-          }
-          fc[nf++][t] = (uint16_t)(sl[p] * MAXH + sl[q]);
-        }
+      const int lo = p < q ? p : q, hi = p < q ? q : p;
+      fc[nf++][t] = (uint16_t)(lo * FCODE + hi);
+    };
+    if constexpr (D == 3) {
+      add_face(s0, s1);
+      add_face(s0, s2);
+      add_face(s1, s2);
     } else {
-      for (int p = 0; p < ns; ++p) {
+      for (int p2 = 0; p2 < 2; ++p2) {
+        const int sp = p2 == 0 ? s0 : s1;
+        if (sp == kNoSlot) continue;
         if (nf == MAXF) {
           overflow = true;
           continue;
         }
-        fc[nf++][t] = (uint16_t)sl[p];
+        fc[nf++][t] = (uint16_t)sp;
       }
     }
   }
@@ -228,8 +233,8 @@ __global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
       int32_t fv[D];
       fv[0] = j;
       if constexpr (D == 3) {
-        fv[1] = hs[(c & 0x7fff) / MAXH][t];
-        fv[2] = hs[(c & 0x7fff) % MAXH][t];
+        fv[1] = hs[(c & 0x7fff) / FCODE][t];
+        fv[2] = hs[(c & 0x7fff) % FCODE][t];
       } else {
         fv[1] = hs[c & 0x7fff][t];
       }
@@ -255,8 +260,8 @@ __global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
       int32_t fv[D];
       fv[0] = j;
       if constexpr (D == 3) {
-        fv[1] = hs[best / MAXH][t];
-        fv[2] = hs[best % MAXH][t];
+        fv[1] = hs[best / FCODE][t];
+        fv[2] = hs[best % FCODE][t];
       } else {
         fv[1] = hs[best][t];
       }
@@ -522,6 +527,7 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
   ta.node_in_edge = tp->node_in_edge;
   ta.bf_cur = bfn_scan;
   ta.bnode_face = tp->bnode_face;
+  ta.node_inc_slot = tp->node_inc_slot;
   ta.st = st;
   hipLaunchKernelGGL((k_node_topo<D, true>), dim3(grid_for(nv, TB)), dim3(TB), 0, s, ta);
   EB_LAUNCH_CHECK();
@@ -609,7 +615,7 @@ int eb_build_edges_emit(const eb_sizes *sizes, const int32_t *elem, const double
   const bool has_f = sizes->n_bfaces > 0, has_bn = sizes->n_bnodes > 0;
   if (!t.node_edge_off || !t.node_inc_off || !t.node_in_off || !t.node_bnode ||
       !t.bnode_face_off || (has_e && (!t.edge || !t.node_in_edge)) ||
-      (has_el && (!t.elem_edge || !t.elem_edge_sign || !t.node_inc)) ||
+      (has_el && (!t.elem_edge || !t.elem_edge_sign || !t.node_inc || !t.node_inc_slot)) ||
       (has_f && (!t.bface || !t.bface_owner || !t.bface_edge)) ||
       (has_bn && (!t.bnode || !t.bnode_face))) {
     set_detail("a required topology array is null");
