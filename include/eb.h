@@ -70,21 +70,27 @@ typedef enum {
   EB_EOVERFLOW = -6,    /* counts that would overflow int32 indexing */
   EB_EHIP = -7,         /* HIP runtime error */
   EB_ECAPACITY = -8     /* a node has more than EB_MAX_OUT_EDGES higher-numbered
-                           neighbours, or more than EB_MAX_NODE_FACES faces with
-                           it as smallest vertex */
+                           neighbours, or more than EB_MAX_NODE_FACES candidate
+                           faces with it as smallest vertex (faces counted once
+                           per element holding them) */
 } eb_status;
 
-#define EB_MAX_OUT_EDGES 31
-#define EB_MAX_NODE_FACES 64
+#define EB_MAX_OUT_EDGES 128
+#define EB_MAX_NODE_FACES 256
 
 typedef enum { EB_REDUCE_ATOMIC = 0, EB_REDUCE_GATHER = 1 } eb_reduce;
 typedef enum { EB_VOL_ELEMENT = 0, EB_VOL_EDGE = 1 } eb_vol_mode;
 
-/* Sizes of one grid; filled by eb_build_edges. */
+/* Sizes of one grid; filled by eb_build_edges.  n_sell counts the entries
+ * of node_sell (padding included); sell_wide selects its entry format. */
 typedef struct {
   int32_t dim;
   int64_t n_nodes, n_elems, n_edges, n_bfaces, n_bnodes;
+  int64_t n_sell;
+  int32_t sell_wide;
 } eb_sizes;
+
+#define EB_SELL_SLICE 64
 
 /* Topology arrays (device).  Every integer output is uniquely defined, so two
  * builds of the same grid give identical bits.
@@ -99,14 +105,29 @@ typedef struct {
  *   edge_inc       [ne*n_elems]     as elem*ne + local, ascending per edge
  *   node_inc_off   [n_nodes+1]    elements of each node as elem*(dim+1) +
  *   node_inc       [(dim+1)*n_elems]  local vertex, ascending per node
- *   node_inc_slot  [(dim+1)*n_elems]  uint16, one per node_inc entry (node j,
- *                                 element E, local index l): for m = 0..dim-1
+ *   node_sell_off  [ceil(n_nodes/64)+1]  incidences of each node in sliced
+ *   node_sell      [n_sell * (1 + sell_wide)] ELL form, uint64 words: nodes are
+ *                                 taken in slices of 64 (node j is lane j%64 of
+ *                                 slice j/64); a slice holds L = its longest
+ *                                 node_inc row, column-major: entry (r, lane)
+ *                                 at node_sell_off[slice] + 64 r + lane for
+ *                                 r < L (entries past a node's row are 0).
+ *                                 Entry r of node j describes node_inc row
+ *                                 entry r (element E, local l): for m < dim
  *                                 let o_m = elem[E][m], except o_l =
  *                                 elem[E][dim] (j's place taken by the last
- *                                 vertex); bits 5m..5m+4 hold the position of
+ *                                 vertex), and let slot_m = the position of
  *                                 edge (j, o_m) among j's out-edges (those
- *                                 with tail j, in node_edge_off order), or 31
- *                                 when o_m < j; higher bits are zero
+ *                                 with tail j, in node_edge_off order), or the
+ *                                 field's all-ones value when o_m < j; code =
+ *                                 sum_m slot_m << (B m).  Narrow (sell_wide =
+ *                                 0): B = 5, one word, bits 16m..16m+15 =
+ *                                 o_m - j as int16, bits 48..62 = code.  Wide
+ *                                 (sell_wide = 1, when some |o_m - j| > 32767
+ *                                 or some node has more than 31 out-edges):
+ *                                 B = 10, two words per entry (entry index
+ *                                 times 2), word 0 = o_0 | o_1 << 32, word 1
+ *                                 = o_2 | code << 32 (o_2 = 0 in 2D).
  *   node_in_off    [n_nodes+1]    ids of edges whose head is the node,
  *   node_in_edge   [n_edges]        ascending per node
  *   bface          [n_bfaces][dim] boundary elements (faces of exactly one
@@ -131,7 +152,8 @@ typedef struct {
   int8_t *elem_edge_sign;
   int32_t *edge_inc_off, *edge_inc;
   int32_t *node_inc_off, *node_inc;
-  uint16_t *node_inc_slot;
+  int32_t *node_sell_off;
+  uint64_t *node_sell;
   int32_t *node_in_off, *node_in_edge;
   int32_t *bface;
   int32_t *bface_owner;

@@ -33,7 +33,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "node id out of range",
           -6: "size overflow"}
 
 TOPO_ARRAYS = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign",
-               "edge_inc_off", "edge_inc", "node_inc_off", "node_inc", "node_inc_slot",
+               "edge_inc_off", "edge_inc", "node_inc_off", "node_inc", "node_sell_off",
+               "node_sell",
                "node_in_off", "node_in_edge", "bface", "bface_owner",
                "bface_edge", "bnode", "node_bnode", "bnode_face_off",
                "bnode_face")
@@ -106,14 +107,14 @@ class Topology:
             L.oracle_topo_free(self._h)
             self._h = None
             raise OracleError(rc, "topology")
-        s = np.zeros(6, dtype=np.int64)
+        s = np.zeros(8, dtype=np.int64)
         L.oracle_topo_sizes(self._h, _ptr(s))
         (_, self.n_nodes, self.n_elems, self.n_edges, self.n_bfaces,
-         self.n_bnodes) = (int(x) for x in s)
+         self.n_bnodes, self.n_sell, self.sell_wide) = (int(x) for x in s)
         self.arrays = {}
         for name in TOPO_ARRAYS:
             cnt = L.oracle_topo_get(self._h, name.encode(), None)
-            dt = {"elem_edge_sign": np.int8, "node_inc_slot": np.uint16}.get(name, np.int32)
+            dt = {"elem_edge_sign": np.int8, "node_sell": np.uint64}.get(name, np.int32)
             a = np.empty(cnt, dtype=dt)
             L.oracle_topo_get(self._h, name.encode(), _ptr(a))
             self.arrays[name] = a

@@ -42,10 +42,17 @@
 //   elem_edge_sign [NE][ne]  +1 iff elem[p] < elem[q]
 //   edge_inc    CSR over edges of elem*ne+local, ascending
 //   node_inc    CSR over nodes of elem*(D+1)+local, ascending
-//   node_inc_slot  per node_inc entry (node j, element E, local l): for
-//               m < D, o_m = E's vertex m, except that j's own place l is
-//               taken by vertex D; 5 bits per m give the rank of edge (j, o_m)
-//               among the edges whose tail is j, or 31 when o_m < j
+//   node_sell   node_inc rows in sliced ELL form: slices of 64 nodes, each
+//               as long as its longest row, column-major (entry (r, lane) at
+//               slice offset + 64 r + lane, zero past a row's end).  Entry r
+//               of node j (element E, local l): o_m = E's vertex m for m < D,
+//               except that j's own place l is taken by vertex D; slot_m =
+//               rank of edge (j, o_m) among the edges whose tail is j, or 31
+//               (all ones) when o_m < j; code = sum slot_m << (B m).  Narrow
+//               (B = 5): one word with o_m - j as int16 in bits 16m.. and
+//               code in bits 48..; wide (B = 10; when some |o_m - j| >
+//               32767 or some node has more than 31 out-edges): two words
+//               o_0 | o_1 << 32 and o_2 | code << 32
 //   node_edge_off  CSR offsets of edges by tail
 //   node_in     CSR over nodes of the ids of edges whose head is the node
 //   bface       [NB][D] faces owned by one element, in ascending sorted-id
@@ -251,7 +258,10 @@ struct Topo {
   std::vector<int32_t> node_edge_off, elem_edge, edge_inc_off, edge_inc;
   std::vector<int8_t> elem_edge_sign;
   std::vector<int32_t> node_inc_off, node_inc, node_in_off, node_in_edge;
-  std::vector<uint16_t> node_inc_slot;
+  std::vector<int32_t> node_sell_off;
+  std::vector<uint64_t> node_sell;
+  int64_t n_sell = 0;
+  int sell_wide = 0;
   std::vector<int32_t> bface, bface_owner, bface_edge, bnode, node_bnode;
   std::vector<int32_t> bnode_face_off, bnode_face;
 };
@@ -368,21 +378,64 @@ int build_topology(Topo &t, int dim, int64_t nv, int64_t nelem, const int32_t *e
     csr_from_pairs(np, nv, t.node_inc_off, t.node_inc);
   }
 
-  // out-edge ranks of each incidence's other vertices
-  t.node_inc_slot.assign(t.node_inc.size(), 0);
-  for (int64_t v = 0; v < nv; ++v)
-    for (int32_t r = t.node_inc_off[v]; r < t.node_inc_off[v + 1]; ++r) {
-      const int64_t e = t.node_inc[r] / nn;
-      const int l = t.node_inc[r] % nn;
-      uint32_t code = 0;
-      for (int m = 0; m < dim; ++m) {
-        const int32_t om = elem[e * nn + (m == l ? dim : m)];
-        uint32_t rank = 31;
-        if (om > v) rank = (uint32_t)(find_edge(t, (int32_t)v, om) - t.node_edge_off[v]);
-        code |= rank << (5 * m);
+  // node_inc rows in sliced ELL form with each entry's other vertices and
+  // their out-edge ranks
+  {
+    const int64_t nsl = (nv + 63) / 64;
+    std::vector<int64_t> slen(nsl, 0);
+    for (int64_t v = 0; v < nv; ++v)
+      slen[v / 64] = std::max<int64_t>(slen[v / 64], t.node_inc_off[v + 1] - t.node_inc_off[v]);
+    t.node_sell_off.assign(nsl + 1, 0);
+    for (int64_t sl = 0; sl < nsl; ++sl)
+      t.node_sell_off[sl + 1] = (int32_t)(t.node_sell_off[sl] + 64 * slen[sl]);
+    t.n_sell = t.node_sell_off[nsl];
+    // format: wide when a neighbour id differs by more than int16 range or a
+    // node has more than 31 out-edges; slot fields are 5 (narrow) or 10 bits
+    int64_t maxdelta = 0, maxout = 0;
+    for (int64_t v = 0; v < nv; ++v) {
+      maxout = std::max<int64_t>(maxout, t.node_edge_off[v + 1] - t.node_edge_off[v]);
+      for (int32_t r = t.node_inc_off[v]; r < t.node_inc_off[v + 1]; ++r) {
+        const int64_t e = t.node_inc[r] / nn;
+        for (int q = 0; q < nn; ++q)
+          maxdelta = std::max<int64_t>(maxdelta, std::llabs((int64_t)elem[e * nn + q] - v));
       }
-      t.node_inc_slot[r] = (uint16_t)code;
     }
+    t.sell_wide = (maxdelta > 32767 || maxout > 31) ? 1 : 0;
+    const int B = t.sell_wide ? 10 : 5;
+    const uint32_t none = (1u << B) - 1;
+    std::vector<int32_t> others((size_t)t.node_inc.size() * dim);
+    std::vector<uint32_t> codes(t.node_inc.size());
+    for (int64_t v = 0; v < nv; ++v)
+      for (int32_t r = t.node_inc_off[v]; r < t.node_inc_off[v + 1]; ++r) {
+        const int64_t e = t.node_inc[r] / nn;
+        const int l = t.node_inc[r] % nn;
+        uint32_t code = 0;
+        for (int m = 0; m < dim; ++m) {
+          const int32_t om = elem[e * nn + (m == l ? dim : m)];
+          uint32_t rank = none;
+          if (om > v) rank = (uint32_t)(find_edge(t, (int32_t)v, om) - t.node_edge_off[v]);
+          code |= rank << (B * m);
+          others[(size_t)r * dim + m] = om;
+        }
+        codes[r] = code;
+      }
+    t.node_sell.assign((size_t)t.n_sell * (t.sell_wide ? 2 : 1), 0);
+    for (int64_t v = 0; v < nv; ++v)
+      for (int32_t r = t.node_inc_off[v]; r < t.node_inc_off[v + 1]; ++r) {
+        const int64_t pos = t.node_sell_off[v / 64] + 64 * (r - t.node_inc_off[v]) + v % 64;
+        const int32_t *o = &others[(size_t)r * dim];
+        if (!t.sell_wide) {
+          uint64_t w = (uint64_t)codes[r] << 48;
+          for (int m = 0; m < dim; ++m)
+            w |= (uint64_t)(uint16_t)(int16_t)(o[m] - v) << (16 * m);
+          t.node_sell[pos] = w;
+        } else {
+          t.node_sell[2 * pos] = (uint64_t)(uint32_t)o[0] | ((uint64_t)(uint32_t)o[1] << 32);
+          t.node_sell[2 * pos + 1] =
+              (uint64_t)(uint32_t)(dim == 3 ? o[2] : 0) | ((uint64_t)codes[r] << 32);
+        }
+      }
+  }
 
   // faces: sorted vertex ids of the face opposite each local vertex
   struct FaceKey {
@@ -576,7 +629,7 @@ int oracle_topology(void *h, int dim, int64_t nv, int64_t nelem, const int32_t *
   return build_topology(*static_cast<Topo *>(h), dim, nv, nelem, elem, X);
 }
 
-// sizes: dim, nv, nelem, nedge, nbface, nbnode
+// sizes: dim, nv, nelem, nedge, nbface, nbnode, n_sell, sell_wide
 void oracle_topo_sizes(const void *h, int64_t *out) {
   const Topo &t = *static_cast<const Topo *>(h);
   out[0] = t.dim;
@@ -585,6 +638,8 @@ void oracle_topo_sizes(const void *h, int64_t *out) {
   out[3] = t.nedge;
   out[4] = t.nbface;
   out[5] = t.nbnode;
+  out[6] = t.n_sell;
+  out[7] = t.sell_wide;
 }
 
 // Copy one named array out; returns element count, or -1 for an unknown name.
@@ -605,7 +660,8 @@ int64_t oracle_topo_get(const void *h, const char *name, void *dst) {
       {"edge_inc", t.edge_inc.data(), t.edge_inc.size(), 4},
       {"node_inc_off", t.node_inc_off.data(), t.node_inc_off.size(), 4},
       {"node_inc", t.node_inc.data(), t.node_inc.size(), 4},
-      {"node_inc_slot", t.node_inc_slot.data(), t.node_inc_slot.size(), 2},
+      {"node_sell_off", t.node_sell_off.data(), t.node_sell_off.size(), 4},
+      {"node_sell", t.node_sell.data(), t.node_sell.size(), 8},
       {"node_in_off", t.node_in_off.data(), t.node_in_off.size(), 4},
       {"node_in_edge", t.node_in_edge.data(), t.node_in_edge.size(), 4},
       {"bface", t.bface.data(), t.bface.size(), 4},

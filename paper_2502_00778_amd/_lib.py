@@ -25,7 +25,8 @@ EXPORTS = ("eb_workspace_bytes", "eb_build_edges", "eb_build_edges_emit",
            "eb_status_string", "eb_last_error_detail", "eb_version")
 
 TOPO_FIELDS = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign",
-               "edge_inc_off", "edge_inc", "node_inc_off", "node_inc", "node_inc_slot",
+               "edge_inc_off", "edge_inc", "node_inc_off", "node_inc", "node_sell_off",
+               "node_sell",
                "node_in_off", "node_in_edge", "bface", "bface_owner",
                "bface_edge", "bnode", "node_bnode", "bnode_face_off",
                "bnode_face")
@@ -34,7 +35,8 @@ TOPO_FIELDS = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign",
 class EbSizes(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n_nodes", ctypes.c_int64),
                 ("n_elems", ctypes.c_int64), ("n_edges", ctypes.c_int64),
-                ("n_bfaces", ctypes.c_int64), ("n_bnodes", ctypes.c_int64)]
+                ("n_bfaces", ctypes.c_int64), ("n_bnodes", ctypes.c_int64),
+                ("n_sell", ctypes.c_int64), ("sell_wide", ctypes.c_int32)]
 
 
 class EbTopology(ctypes.Structure):

@@ -59,6 +59,8 @@ class Topology:
     n_edges: int
     n_bfaces: int
     n_bnodes: int
+    n_sell: int
+    sell_wide: int
     arrays: dict
     ws: torch.Tensor
     sizes: EbSizes = field(repr=False, default=None)
@@ -76,7 +78,7 @@ class Topology:
         for k, v in self.arrays.items():
             if v is not None:
                 a = v.cpu().numpy()
-                out[k] = a.view("uint16") if k == "node_inc_slot" else a
+                out[k] = a.view("uint64") if k == "node_sell" else a
         return out
 
 
@@ -115,7 +117,9 @@ def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True
         edge_inc=torch.empty(max(ne * nel, 1), **i32) if edge_inc else None,
         node_inc_off=node_inc_off,
         node_inc=node_inc,
-        node_inc_slot=torch.empty(max((dim + 1) * nel, 1), dtype=torch.int16, device=dev),
+        node_sell_off=torch.empty((nv + 63) // 64 + 1, **i32),
+        node_sell=torch.empty(max(int(sizes.n_sell) * (1 + int(sizes.sell_wide)), 1),
+                              dtype=torch.int64, device=dev),
         node_in_off=torch.empty(nv + 1, **i32),
         node_in_edge=torch.empty(max(ne_, 1), **i32),
         bface=torch.empty(nb, dim, **i32),
@@ -131,12 +135,13 @@ def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True
                                 ctypes.byref(st), _ptr(ws), wsb, s), "eb_build_edges_emit")
     # trim the placeholder lengths used for empty arrays
     arr["node_inc"] = arr["node_inc"][: (dim + 1) * nel]
-    arr["node_inc_slot"] = arr["node_inc_slot"][: (dim + 1) * nel]
+    arr["node_sell"] = arr["node_sell"][: int(sizes.n_sell) * (1 + int(sizes.sell_wide))]
     arr["node_in_edge"] = arr["node_in_edge"][:ne_]
     arr["bnode_face"] = arr["bnode_face"][: dim * nb]
     if edge_inc:
         arr["edge_inc"] = arr["edge_inc"][: ne * nel]
-    return Topology(dim, nv, nel, ne_, nb, nbn, arr, ws, sizes, st)
+    return Topology(dim, nv, nel, ne_, nb, nbn, int(sizes.n_sell), int(sizes.sell_wide), arr,
+                    ws, sizes, st)
 
 
 def _out(shape, like, out):

@@ -35,7 +35,9 @@ int pack(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem, const d
   a.elem_edge = tp->elem_edge;
   a.node_inc_off = tp->node_inc_off;
   a.node_inc = tp->node_inc;
-  a.node_inc_slot = tp->node_inc_slot;
+  a.node_sell_off = tp->node_sell_off;
+  a.node_sell = tp->node_sell;
+  a.sell_wide = sz->sell_wide;
   a.node_edge_off = tp->node_edge_off;
   a.edge_tail = tp->edge;
   a.edge_head = tp->edge ? tp->edge + sz->n_edges : nullptr;
@@ -44,6 +46,7 @@ int pack(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem, const d
   a.bface = tp->bface;
   a.bface_edge = tp->bface_edge;
   a.node_bnode = tp->node_bnode;
+  a.bnode = tp->bnode;
   a.bnode_face_off = tp->bnode_face_off;
   a.bnode_face = tp->bnode_face;
   a.st = ws_at<StatusBlock>(ws, 0);
@@ -97,10 +100,11 @@ int eb_directed_areas(const eb_sizes *sizes, const eb_topology *topo, const int3
     EB_TRY(need(a.elem_edge != nullptr, "elem_edge"));
     if (sizes->n_bfaces > 0) EB_TRY(need(a.bface && a.bface_edge && a.node_bnode, "bface, bface_edge, node_bnode"));
   } else {
-    EB_TRY(need(a.node_inc_off && a.node_inc && a.node_inc_slot && a.node_edge_off && a.edge_head &&
-                    a.node_bnode && a.bnode_face_off,
-                "node_inc, node_inc_slot, node_edge_off, edge, node_bnode, bnode_face_off"));
-    if (sizes->n_bfaces > 0) EB_TRY(need(a.bface && a.bnode_face, "bface, bnode_face"));
+    EB_TRY(need(a.node_inc_off && a.node_sell_off && (a.node_sell || sizes->n_elems == 0) &&
+                    a.node_edge_off && a.edge_head && a.bnode_face_off,
+                "node_inc_off, node_sell, node_edge_off, edge, bnode_face_off"));
+    if (sizes->n_bfaces > 0)
+      EB_TRY(need(a.bface && a.bnode && a.bnode_face, "bface, bnode, bnode_face"));
   }
   const LaunchCfg cfg = default_cfg();
   a.xcd_remap = cfg.xcd_remap;

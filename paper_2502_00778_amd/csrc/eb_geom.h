@@ -80,9 +80,12 @@ __device__ __forceinline__ void others_of(const int32_t (&v)[D + 1], int l, int3
   for (int m = 0; m < D; ++m) o[m] = (l == m) ? v[D] : v[m];
 }
 
-// 5-bit out-edge slot m of a node_inc_slot code; 31 = none
-constexpr int kNoSlot = 31;
-__device__ __forceinline__ int slot_of(uint32_t code, int m) { return (code >> (5 * m)) & 31; }
+// out-edge slot m of a sliced-ELL slot code: 5-bit fields (narrow entries,
+// 31 = none) or 10-bit fields (wide entries, 1023 = none)
+template <bool WIDE> __device__ __forceinline__ int slot_of(uint32_t code, int m) {
+  return WIDE ? (int)((code >> (10 * m)) & 1023u) : (int)((code >> (5 * m)) & 31u);
+}
+template <bool WIDE> constexpr int no_slot() { return WIDE ? 1023 : 31; }
 
 template <int D> struct EL {
   static constexpr int NN = D + 1;

@@ -24,17 +24,23 @@ struct StatusBlock {
 };
 static_assert(sizeof(StatusBlock) == 256, "status block is 256 bytes");
 
-enum TotalSlot { T_EDGES = 0, T_BFACES = 1, T_BNODES = 2, T_SCRATCH = 3 };
+enum TotalSlot {
+  T_EDGES = 0, T_BFACES = 1, T_BNODES = 2, T_SELL_ROWS = 3, T_MAXDELTA = 4, T_MAXOUT = 5,
+  T_QUEUE = 6
+};
+
+constexpr int SELL = EB_SELL_SLICE;  // nodes per sliced-ELL slice (one wave)
+__host__ __device__ inline int64_t n_slices(int64_t n_nodes) { return (n_nodes + SELL - 1) / SELL; }
 
 __device__ inline void raise_status(StatusBlock *st, int code, int64_t detail) {
   if (atomicCAS(&st->status, 0, code) == 0) st->detail = detail;
 }
 
 // ------------------------------------------------------ workspace layout
-// [status 256 B][eoff][foff][bidx][bfn][bfn_scan][ein_scan][scan scratch]
+// [status 256 B][eoff][foff][bidx][bfn][bfn_scan][ein_scan][slen][queue][scan scratch]
 // Each per-node array holds n_nodes+1 int32 and starts on a 256-byte line.
 struct WsLayout {
-  size_t eoff, foff, bidx, bfn, bfn_scan, ein_scan, scan_tmp, total;
+  size_t eoff, foff, bidx, bfn, bfn_scan, ein_scan, slen, queue, scan_tmp, total;
   int64_t scan_tmp_count;
 };
 
@@ -54,6 +60,8 @@ inline WsLayout ws_layout(int dim, int64_t n_nodes, int64_t n_elems) {
   L.bfn = off; off += per;
   L.bfn_scan = off; off += per;
   L.ein_scan = off; off += per;
+  L.slen = off; off += align256(sizeof(int32_t) * (size_t)(n_slices(n_nodes) + 1));
+  L.queue = off; off += per;
   // the longest array any call scans: ne*n_elems incidences
   const int64_t ne = dim == 2 ? 3 : 6;
   int64_t longest = std::max<int64_t>(n_nodes + 1, ne * n_elems + 1);

@@ -13,10 +13,12 @@ struct FwdArgs {
   Coords X;
   const int32_t *elem_edge;
   const int32_t *node_inc_off, *node_inc;
-  const uint16_t *node_inc_slot;
+  const int32_t *node_sell_off;
+  const uint64_t *node_sell;
+  int sell_wide;
   const int32_t *node_edge_off, *edge_tail, *edge_head;
   const int32_t *node_in_off, *node_in_edge;
-  const int32_t *bface, *bface_edge, *node_bnode, *bnode_face_off, *bnode_face;
+  const int32_t *bface, *bface_edge, *node_bnode, *bnode, *bnode_face_off, *bnode_face;
   double *n_x, *n_y, *n_z;  // [D][Ne] rows
   double *b_x, *b_y, *b_z;  // [D][Nbn] rows
   double *vol;              // [Nv]

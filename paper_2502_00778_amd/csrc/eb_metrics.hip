@@ -134,8 +134,29 @@ __device__ __forceinline__ int32_t find_head(const int32_t *__restrict__ head, i
   return s - b;
 }
 
-template <int D, int TN, int CAP, int U>
+// One incidence of node j from the sliced-ELL layout: the element's other
+// vertices o[] and the out-edge slot code.
+template <int D, bool WIDE>
+__device__ __forceinline__ void sell_entry(const uint64_t *__restrict__ sell, int64_t pos,
+                                           int32_t j, int32_t (&o)[D], uint32_t &code) {
+  if constexpr (!WIDE) {
+    const uint64_t w = __builtin_nontemporal_load(sell + pos);
+#pragma unroll
+    for (int m = 0; m < D; ++m) o[m] = j + (int32_t)(int16_t)(uint16_t)(w >> (16 * m));
+    code = (uint32_t)(w >> 48) & 0x7fffu;
+  } else {
+    const uint64_t w0 = __builtin_nontemporal_load(sell + 2 * pos);
+    const uint64_t w1 = __builtin_nontemporal_load(sell + 2 * pos + 1);
+    o[0] = (int32_t)(uint32_t)w0;
+    o[1] = (int32_t)(uint32_t)(w0 >> 32);
+    if constexpr (D == 3) o[2] = (int32_t)(uint32_t)w1;
+    code = (uint32_t)(w1 >> 32);
+  }
+}
+
+template <int D, int TN, int CAP, int U, bool WIDE>
 __global__ __launch_bounds__(TN) void k_fwd_gather(FwdArgs a) {
+  static_assert(TN % SELL == 0, "a tile is whole slices");
   __shared__ double acc[D][CAP];
   const int t = threadIdx.x;
   const int64_t tile = tile_of_block(gridDim.x, a.xcd_remap);
@@ -175,30 +196,39 @@ __global__ __launch_bounds__(TN) void k_fwd_gather(FwdArgs a) {
       }
     const V3 xj = load_pt<D>(a.X, (int32_t)j);
     double vs = 0.0;
-    const int32_t r0 = a.node_inc_off[j], r1 = a.node_inc_off[j + 1];
-    for (int32_t r = r0; r < r1; r += U) {
-      int32_t inc[U];
+    const int32_t len = a.node_inc_off[j + 1] - a.node_inc_off[j];
+    const int64_t p0 = (int64_t)a.node_sell_off[j / SELL] + (j % SELL);
+    // chunks of U incidences; the next chunk's entries are loaded while the
+    // current chunk's coordinates are in flight
+    int32_t on[U][D];
+    uint32_t cn[U];
+    if (len > 0)
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(u, len - 1), (int32_t)j, on[u],
+                            cn[u]);
+    for (int32_t r = 0; r < len; r += U) {
+      int32_t o[U][D];
       uint32_t code[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int32_t rr = min(r + u, r1 - 1);
-        inc[u] = a.node_inc[rr];
-        code[u] = a.node_inc_slot[rr];
+        code[u] = cn[u];
+#pragma unroll
+        for (int m = 0; m < D; ++m) o[u][m] = on[u][m];
       }
       V3 P[U][D];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int32_t e = inc[u] / (D + 1);
-        const int l = inc[u] - e * (D + 1);
-        int32_t v[D + 1], o[D];
-        load_conn<D>(a.elem, e, v);
-        others_of<D>(v, l, o);
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int m = 0; m < D; ++m) P[u][m] = load_pt<D>(a.X, o[m]);
-      }
+        for (int m = 0; m < D; ++m) P[u][m] = load_pt<D>(a.X, o[u][m]);
+      if (r + U < len)
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(r + U + u, len - 1),
+                              (int32_t)j, on[u], cn[u]);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (r + u >= r1) break;
+        if (r + u >= len) break;
         V3 c;
         if constexpr (D == 3)
           c = cross(P[u][1] - P[u][0], P[u][2] - P[u][0]);
@@ -209,49 +239,17 @@ __global__ __launch_bounds__(TN) void k_fwd_gather(FwdArgs a) {
           c = -c;
           d = -d;
         } else if (d == 0.0) {
-          raise_status(a.st, EB_EDEGENERATE, inc[u] / (D + 1));
+          raise_status(a.st, EB_EDEGENERATE, j);
         }
         vs += d;
 #pragma unroll
         for (int m = 0; m < D; ++m) {
-          const int s = slot_of(code[u], m);
-          if (s != kNoSlot) add(s, c);
+          const int s = slot_of<WIDE>(code[u], m);
+          if (s != no_slot<WIDE>()) add(s, c);
         }
       }
     }
     if (a.vol) a.vol[j] = vs * GK<D>::kV;
-    // boundary elements containing j: b_j and the boundary correction of
-    // the edges of B whose tail is j
-    const int32_t bj = a.node_bnode[j];
-    if (bj >= 0) {
-      V3 bs = {0.0, 0.0, 0.0};
-      const int32_t f0 = a.bnode_face_off[bj], f1 = a.bnode_face_off[bj + 1];
-      for (int32_t r = f0; r < f1; ++r) {
-        const int32_t f = a.bnode_face[r];
-        int32_t fv[D];
-#pragma unroll
-        for (int s = 0; s < D; ++s) fv[s] = a.bface[(int64_t)f * D + s];
-        V3 nB;
-        if constexpr (D == 3) {
-          const V3 A = load_pt<D>(a.X, fv[0]), B = load_pt<D>(a.X, fv[1]),
-                   C = load_pt<D>(a.X, fv[2]);
-          nB = 0.5 * cross(B - A, C - A);
-        } else {
-          nB = rot2(load_pt<D>(a.X, fv[1]) - load_pt<D>(a.X, fv[0]));
-        }
-        bs = bs + nB;
-        const V3 cB = GK<D>::kBraw * nB;
-#pragma unroll
-        for (int s2 = 0; s2 < D; ++s2)
-          if (fv[s2] > j && my1 > my0) add(find_head(a.edge_head, my0, my1, fv[s2]), cB);
-      }
-      if (a.b_x) {
-        constexpr double kb = 1.0 / D;
-        a.b_x[bj] = kb * bs.x;
-        a.b_y[bj] = kb * bs.y;
-        if (D == 3) a.b_z[bj] = kb * bs.z;
-      }
-    }
     if (!in_lds)
       for (int32_t ed = my0; ed < my1; ++ed) {
         nx[ed] *= GK<D>::kN;
@@ -266,6 +264,48 @@ __global__ __launch_bounds__(TN) void k_fwd_gather(FwdArgs a) {
       ny[e0 + i] = acc[1][i] * GK<D>::kN;
       if (D == 3) nz[e0 + i] = acc[2][i] * GK<D>::kN;
     }
+  }
+}
+
+// Boundary elements, after the element pass: for each boundary node j, b_j
+// and the boundary correction n_B/(D(D+1)) of the edges of B whose tail is
+// j.  Only j's thread touches those edges, and faces are taken in
+// bnode_face order, so the result is deterministic.
+template <int D>
+__global__ __launch_bounds__(256) void k_fwd_boundary_gather(FwdArgs a) {
+  const int64_t bj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (bj >= a.nbnode) return;
+  const int32_t j = a.bnode[bj];
+  const int32_t my0 = a.node_edge_off[j], my1 = a.node_edge_off[j + 1];
+  constexpr double kB = 1.0 / (D * (D + 1));
+  V3 bs = {0.0, 0.0, 0.0};
+  for (int32_t r = a.bnode_face_off[bj]; r < a.bnode_face_off[bj + 1]; ++r) {
+    const int32_t f = a.bnode_face[r];
+    int32_t fv[D];
+#pragma unroll
+    for (int s = 0; s < D; ++s) fv[s] = a.bface[(int64_t)f * D + s];
+    V3 nB;
+    if constexpr (D == 3) {
+      const V3 A = load_pt<D>(a.X, fv[0]), B = load_pt<D>(a.X, fv[1]), C = load_pt<D>(a.X, fv[2]);
+      nB = 0.5 * cross(B - A, C - A);
+    } else {
+      nB = rot2(load_pt<D>(a.X, fv[1]) - load_pt<D>(a.X, fv[0]));
+    }
+    bs = bs + nB;
+#pragma unroll
+    for (int s2 = 0; s2 < D; ++s2) {
+      if (fv[s2] <= j || my1 <= my0) continue;
+      const int32_t ed = my0 + find_head(a.edge_head, my0, my1, fv[s2]);
+      a.n_x[ed] += kB * nB.x;
+      a.n_y[ed] += kB * nB.y;
+      if (D == 3) a.n_z[ed] += kB * nB.z;
+    }
+  }
+  if (a.b_x) {
+    constexpr double kb = 1.0 / D;
+    a.b_x[bj] = kb * bs.x;
+    a.b_y[bj] = kb * bs.y;
+    if (D == 3) a.b_z[bj] = kb * bs.z;
   }
 }
 
@@ -329,11 +369,14 @@ template <int D>
 int launch_fwd_gather(const FwdArgs &a, const LaunchCfg &cfg, hipStream_t s) {
   const int64_t ntiles = (a.nv + cfg.tile - 1) / cfg.tile;
   const dim3 grid((unsigned)ntiles);
-#define EB_GATHER_CASE(TN_, CAP_, U_)                                                 \
-  if (cfg.tile == TN_ && cfg.unroll == U_) {                                          \
-    hipLaunchKernelGGL((k_fwd_gather<D, TN_, CAP_, U_>), grid, dim3(TN_), 0, s, a);   \
-    EB_LAUNCH_CHECK();                                                                \
-    return EB_OK;                                                                     \
+#define EB_GATHER_CASE(TN_, CAP_, U_)                                                   \
+  if (cfg.tile == TN_ && cfg.unroll == U_) {                                            \
+    if (a.sell_wide)                                                                    \
+      hipLaunchKernelGGL((k_fwd_gather<D, TN_, CAP_, U_, true>), grid, dim3(TN_), 0, s, a); \
+    else                                                                                \
+      hipLaunchKernelGGL((k_fwd_gather<D, TN_, CAP_, U_, false>), grid, dim3(TN_), 0, s, a); \
+    EB_LAUNCH_CHECK();                                                                  \
+    return launch_fwd_boundary<D>(a, s);                                                \
   }
   EB_GATHER_CASE(64, 512, 1)
   EB_GATHER_CASE(64, 512, 2)
@@ -347,6 +390,15 @@ int launch_fwd_gather(const FwdArgs &a, const LaunchCfg &cfg, hipStream_t s) {
 #undef EB_GATHER_CASE
   set_detail("unsupported gather tile %d / unroll %d", cfg.tile, cfg.unroll);
   return EB_EINVAL;
+}
+
+template <int D>
+int launch_fwd_boundary(const FwdArgs &a, hipStream_t s) {
+  if (a.nbnode <= 0) return EB_OK;
+  hipLaunchKernelGGL(k_fwd_boundary_gather<D>, dim3(grid_for(a.nbnode, 256)), dim3(256), 0, s,
+                     a);
+  EB_LAUNCH_CHECK();
+  return EB_OK;
 }
 
 template <int D>

@@ -22,11 +22,18 @@ namespace eb {
 
 namespace {
 
-constexpr int TB = 128;  // threads per block of the per-node topology kernels
-constexpr int MAXH = EB_MAX_OUT_EDGES;
-constexpr int MAXF = EB_MAX_NODE_FACES;
-static_assert(MAXH <= 31, "slots are 5-bit with 31 reserved");
-constexpr int FCODE = 32;  // face code = lo_slot * FCODE + hi_slot
+// Per-node topology work keeps each node's sorted head list and its
+// candidate faces in LDS.  A fast kernel with small per-node capacities
+// handles almost every node; nodes beyond them are queued and handled by a
+// second kernel with large capacities (a few threads per block).
+constexpr int TB = 128;                   // fast kernel: threads per block
+constexpr int MAXH = 32;                  //   heads per node
+constexpr int MAXF = 64;                  //   candidate faces per node
+constexpr int TBS = 32;                   // queued nodes: threads per block
+constexpr int MAXH_S = EB_MAX_OUT_EDGES;  //   heads per node
+constexpr int MAXF_S = EB_MAX_NODE_FACES; //   candidate faces per node
+static_assert(MAXH_S * MAXH_S <= 0x8000, "face codes fit 15 bits");
+static_assert(MAXH <= MAXH_S && MAXF <= MAXF_S, "queued capacities are the larger");
 
 // ----------------------------------------------------- node incidences
 
@@ -100,44 +107,51 @@ struct TopoArgs {
   int32_t *bface, *bface_owner;
   int32_t *in_cur, *node_in_edge;
   int32_t *bf_cur, *bnode_face;
-  uint16_t *node_inc_slot;
+  const int32_t *node_sell_off;
+  uint64_t *node_sell;
+  int sell_wide;
+  int32_t *queue;  // nodes beyond the fast kernel's capacities
   StatusBlock *st;
 };
 
 // slot of head k in the thread's sorted head column (k must be present)
-__device__ __forceinline__ int head_slot(const int32_t (*hs)[TB], int t, int nh, int32_t k) {
+template <int TBK>
+__device__ __forceinline__ int head_slot(const int32_t (*hs)[TBK], int t, int nh, int32_t k) {
   int s = 0;
   while (s < nh - 1 && hs[s][t] != k) ++s;
   return s;
 }
 
-template <int D, bool EMIT>
-__global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
-  __shared__ int32_t hs[MAXH][TB];
-  __shared__ uint16_t fc[MAXF][TB];
-  const int t = threadIdx.x;
-  const int64_t j64 = (int64_t)blockIdx.x * TB + t;
-  if (j64 >= a.nv || build_failed(a.st)) return;
-  const int32_t j = (int32_t)j64;
+template <int D, bool EMIT, int TBK, int MH, int MF, bool SLOW>
+__device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, int32_t (*hs)[TBK],
+                               uint16_t (*fc)[TBK]) {
   const int32_t r0 = a.node_inc_off[j], r1 = a.node_inc_off[j + 1];
 
-  // 1. distinct higher-numbered neighbours, ascending
-  int nh = 0;
+  // 1. distinct higher-numbered neighbours, ascending, and the number of
+  //    candidate faces with j as smallest vertex; nothing is written before
+  //    both are known to fit (a node beyond the capacities is queued whole).
+  //    The count pass also notes the largest |neighbour - j| (sliced-ELL
+  //    format).
+  int nh = 0, nfc = 0;
   bool overflow = false;
+  int32_t maxdelta = 0;
   for (int32_t r = r0; r < r1; ++r) {
     const int32_t inc = a.node_inc[r];
     const int64_t e = inc / (D + 1);
     const int l = inc - (int)(e * (D + 1));
     int32_t v[D + 1];
     load_conn<D>(a.elem, e, v);
+    int higher = 0;
 #pragma unroll
     for (int q = 0; q <= D; ++q) {
       const int32_t k = v[q];
+      if (!EMIT) maxdelta = max(maxdelta, k > j ? k - j : j - k);
       if (q == l || k <= j) continue;
+      ++higher;
       int pos = 0;
       while (pos < nh && hs[pos][t] < k) ++pos;
       if (pos < nh && hs[pos][t] == k) continue;
-      if (nh == MAXH) {
+      if (nh == MH) {
         overflow = true;
         continue;
       }
@@ -145,14 +159,24 @@ __global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
       hs[pos][t] = k;
       ++nh;
     }
+    nfc += D == 3 ? higher * (higher - 1) / 2 : higher;
   }
-  if (overflow) {
-    raise_status(a.st, EB_ECAPACITY, j);
+  if (overflow || nfc > MF) {
+    if constexpr (SLOW) {
+      raise_status(a.st, EB_ECAPACITY, j);
+    } else if constexpr (!EMIT) {
+      const int32_t q = atomicAdd(&a.st->totals[T_QUEUE], 1);
+      a.queue[q] = j;
+    }
     return;
   }
   if constexpr (!EMIT) {
     a.outdeg[j] = nh;
     for (int s = 0; s < nh; ++s) atomicAdd(&a.ein[hs[s][t]], 1);
+    // only whether some neighbour lies beyond int16 range, or some node has
+    // more than 31 out-edges, matters (either selects the wide format)
+    if (maxdelta > 32767) atomicMax(&a.st->totals[T_MAXDELTA], maxdelta);
+    if (nh > 31) atomicMax(&a.st->totals[T_MAXOUT], nh);
   } else {
     const int32_t e0 = a.eoff[j];
     for (int s = 0; s < nh; ++s) {
@@ -165,7 +189,7 @@ __global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
   }
 
   // 2. out-edge slot of each other vertex of every element of j (emitted as
-  //    node_inc_slot) and the candidate faces with j as smallest vertex,
+  //    in node_sell) and the candidate faces with j as smallest vertex,
   //    coded by the slots of their two other vertices
   int nf = 0;
   for (int32_t r = r0; r < r1; ++r) {
@@ -175,39 +199,53 @@ __global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
     int32_t v[D + 1], o[D];
     load_conn<D>(a.elem, e, v);
     others_of<D>(v, l, o);
-    int s0 = o[0] > j ? head_slot(hs, t, nh, o[0]) : kNoSlot;
-    int s1 = o[1] > j ? head_slot(hs, t, nh, o[1]) : kNoSlot;
-    int s2 = kNoSlot;
-    if constexpr (D == 3) s2 = o[2] > j ? head_slot(hs, t, nh, o[2]) : kNoSlot;
-    if constexpr (EMIT) a.node_inc_slot[r] = (uint16_t)(s0 | (s1 << 5) | (D == 3 ? s2 << 10 : 0));
-    auto add_face = [&](int p, int q) {
-      if (p == kNoSlot || q == kNoSlot) return;
-      if (nf == MAXF) {
-        overflow = true;
-        return;
+    // slot of each other vertex among j's out-edges, -1 below j
+    const int s0 = o[0] > j ? head_slot<TBK>(hs, t, nh, o[0]) : -1;
+    const int s1 = o[1] > j ? head_slot<TBK>(hs, t, nh, o[1]) : -1;
+    int s2 = -1;
+    if constexpr (D == 3) s2 = o[2] > j ? head_slot<TBK>(hs, t, nh, o[2]) : -1;
+    if constexpr (EMIT) {
+      const int B = a.sell_wide ? 10 : 5;
+      const int none = (1 << B) - 1;
+      const uint64_t code = (uint64_t)((s0 < 0 ? none : s0) | ((s1 < 0 ? none : s1) << B) |
+                                       (D == 3 ? (s2 < 0 ? none : s2) << (2 * B) : 0));
+      const int64_t pos = (int64_t)a.node_sell_off[j / SELL] + (int64_t)SELL * (r - r0) + (j % SELL);
+      if (!a.sell_wide) {
+        uint64_t w = code << 48;
+#pragma unroll
+        for (int m = 0; m < D; ++m) w |= (uint64_t)(uint16_t)(int16_t)(o[m] - j) << (16 * m);
+        a.node_sell[pos] = w;
+      } else {
+        a.node_sell[2 * pos] = (uint64_t)(uint32_t)o[0] | ((uint64_t)(uint32_t)o[1] << 32);
+        a.node_sell[2 * pos + 1] = (uint64_t)(uint32_t)(D == 3 ? o[D - 1] : 0) | (code << 32);
       }
+    }
+    auto add_face = [&](int p, int q) {
+      if (p < 0 || q < 0) return;
       const int lo = p < q ? p : q, hi = p < q ? q : p;
-      fc[nf++][t] = (uint16_t)(lo * FCODE + hi);
+      fc[nf++][t] = (uint16_t)(lo * MH + hi);
     };
     if constexpr (D == 3) {
       add_face(s0, s1);
       add_face(s0, s2);
       add_face(s1, s2);
     } else {
-      for (int p2 = 0; p2 < 2; ++p2) {
-        const int sp = p2 == 0 ? s0 : s1;
-        if (sp == kNoSlot) continue;
-        if (nf == MAXF) {
-          overflow = true;
-          continue;
-        }
-        fc[nf++][t] = (uint16_t)sp;
-      }
+      if (s0 >= 0) fc[nf++][t] = (uint16_t)s0;
+      if (s1 >= 0) fc[nf++][t] = (uint16_t)s1;
     }
   }
-  if (overflow) {
-    raise_status(a.st, EB_ECAPACITY, j);
-    return;
+  if constexpr (EMIT) {  // zero the slice entries past j's row
+    const int32_t sl0 = a.node_sell_off[j / SELL], sl1 = a.node_sell_off[j / SELL + 1];
+    const int32_t slen = (sl1 - sl0) / SELL;
+    for (int32_t rl = r1 - r0; rl < slen; ++rl) {
+      const int64_t pos = (int64_t)sl0 + (int64_t)SELL * rl + (j % SELL);
+      if (!a.sell_wide) {
+        a.node_sell[pos] = 0;
+      } else {
+        a.node_sell[2 * pos] = 0;
+        a.node_sell[2 * pos + 1] = 0;
+      }
+    }
   }
 
   // 3. multiplicity of each candidate: 1 = boundary face, 2 = interior
@@ -233,8 +271,8 @@ __global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
       int32_t fv[D];
       fv[0] = j;
       if constexpr (D == 3) {
-        fv[1] = hs[(c & 0x7fff) / FCODE][t];
-        fv[2] = hs[(c & 0x7fff) % FCODE][t];
+        fv[1] = hs[(c & 0x7fff) / MH][t];
+        fv[2] = hs[(c & 0x7fff) % MH][t];
       } else {
         fv[1] = hs[c & 0x7fff][t];
       }
@@ -260,8 +298,8 @@ __global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
       int32_t fv[D];
       fv[0] = j;
       if constexpr (D == 3) {
-        fv[1] = hs[best / FCODE][t];
-        fv[2] = hs[best % FCODE][t];
+        fv[1] = hs[best / MH][t];
+        fv[2] = hs[best % MH][t];
       } else {
         fv[1] = hs[best][t];
       }
@@ -327,6 +365,56 @@ __global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
       ++f;
     }
   }
+}
+
+template <int D, bool EMIT>
+__global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
+  __shared__ int32_t hs[MAXH][TB];
+  __shared__ uint16_t fc[MAXF][TB];
+  const int t = threadIdx.x;
+  const int64_t j64 = (int64_t)blockIdx.x * TB + t;
+  if (build_failed(a.st)) return;
+  if (j64 >= a.nv) {
+    if constexpr (EMIT) {  // lanes of the last slice past the last node
+      if (j64 < n_slices(a.nv) * SELL) {
+        const int32_t sl0 = a.node_sell_off[j64 / SELL], sl1 = a.node_sell_off[j64 / SELL + 1];
+        const int w = a.sell_wide ? 2 : 1;
+        for (int32_t rl = 0; rl < (sl1 - sl0) / SELL; ++rl)
+          for (int k = 0; k < w; ++k)
+            a.node_sell[w * ((int64_t)sl0 + (int64_t)SELL * rl + (j64 % SELL)) + k] = 0;
+      }
+    }
+    return;
+  }
+  node_topo_body<D, EMIT, TB, MAXH, MAXF, false>(a, (int32_t)j64, t, hs, fc);
+}
+
+// the queued nodes, with the large capacities
+template <int D, bool EMIT>
+__global__ __launch_bounds__(TBS) void k_node_topo_queued(TopoArgs a) {
+  __shared__ int32_t hs[MAXH_S][TBS];
+  __shared__ uint16_t fc[MAXF_S][TBS];
+  if (build_failed(a.st)) return;
+  const int32_t n = *reinterpret_cast<const volatile int32_t *>(&a.st->totals[T_QUEUE]);
+  for (int64_t i = (int64_t)blockIdx.x * TBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * TBS)
+    node_topo_body<D, EMIT, TBS, MAXH_S, MAXF_S, true>(a, a.queue[i], threadIdx.x, hs, fc);
+}
+
+// longest node_inc row of every 64-node slice
+__global__ void k_slice_len(const int32_t *__restrict__ node_inc_off, int64_t nv, int32_t *slen) {
+  const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= n_slices(nv)) return;
+  int32_t m = 0;
+  const int64_t j1 = min((sl + 1) * SELL, nv);
+  for (int64_t j = sl * SELL; j < j1; ++j) m = max(m, node_inc_off[j + 1] - node_inc_off[j]);
+  slen[sl] = m;
+}
+
+__global__ void k_emit_slices(const int32_t *__restrict__ slen_scan, int64_t nsl,
+                              int32_t *node_sell_off, const StatusBlock *st) {
+  const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl > nsl || build_failed(st)) return;
+  node_sell_off[sl] = SELL * slen_scan[sl];
 }
 
 // per-node bookkeeping before the emit pass
@@ -438,6 +526,7 @@ int build_edges_impl(int64_t nv, int64_t nelem, const int32_t *elem, const doubl
 
   EB_TRY(fill_i32(reinterpret_cast<int32_t *>(st), sizeof(StatusBlock) / 4, 0, s));
   // the six per-node arrays are contiguous lines of the workspace
+  // the per-node arrays and slice lengths are contiguous lines of the workspace
   EB_TRY(fill_i32(eoff, (int64_t)((L.scan_tmp - L.eoff) / 4), 0, s));
   EB_TRY(fill_i32(node_inc_off, nv + 1, 0, s));
 
@@ -469,14 +558,23 @@ int build_edges_impl(int64_t nv, int64_t nelem, const int32_t *elem, const doubl
   ta.bflag = bidx;
   ta.bfn = bfn;
   ta.ein = ein;
+  ta.queue = ws_at<int32_t>(ws, L.queue);
   ta.st = st;
   hipLaunchKernelGGL((k_node_topo<D, false>), dim3(grid_for(nv, TB)), dim3(TB), 0, s, ta);
+  EB_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_node_topo_queued<D, false>), dim3(256), dim3(TBS), 0, s, ta);
   EB_LAUNCH_CHECK();
   EB_TRY(scan_exclusive(eoff, eoff, nv + 1, &st->totals[T_EDGES], tmp, s));
   EB_TRY(scan_exclusive(foff, foff, nv + 1, &st->totals[T_BFACES], tmp, s));
   EB_TRY(scan_exclusive(bidx, bidx, nv + 1, &st->totals[T_BNODES], tmp, s));
   EB_TRY(scan_inclusive(bfn, bfn_scan, nv + 1, nullptr, tmp, s));
   EB_TRY(scan_inclusive(ein, ein, nv + 1, nullptr, tmp, s));
+  const int64_t nsl = n_slices(nv);
+  int32_t *slen = ws_at<int32_t>(ws, L.slen);
+  hipLaunchKernelGGL(k_slice_len, dim3(grid_for(nsl, 256)), dim3(256), 0, s,
+                     (const int32_t *)node_inc_off, nv, slen);
+  EB_LAUNCH_CHECK();
+  EB_TRY(scan_exclusive(slen, slen, nsl + 1, &st->totals[T_SELL_ROWS], tmp, s));
 
   StatusBlock h;
   EB_HIP_CHECK(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -487,6 +585,8 @@ int build_edges_impl(int64_t nv, int64_t nelem, const int32_t *elem, const doubl
   sizes->n_edges = h.totals[T_EDGES];
   sizes->n_bfaces = h.totals[T_BFACES];
   sizes->n_bnodes = h.totals[T_BNODES];
+  sizes->n_sell = (int64_t)SELL * h.totals[T_SELL_ROWS];
+  sizes->sell_wide = (h.totals[T_MAXDELTA] > 32767 || h.totals[T_MAXOUT] > 31) ? 1 : 0;
   if (h.status != EB_OK)
     set_detail("%s at %s %lld", eb_status_string(h.status),
                h.status == EB_ERANGE || h.status == EB_EDEGENERATE ? "element" : "node",
@@ -511,6 +611,12 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
   hipLaunchKernelGGL(k_emit_nodes, dim3(grid_for(nv + 1, 256)), dim3(256), 0, s, en);
   EB_LAUNCH_CHECK();
 
+  const int64_t nsl = n_slices(nv);
+  hipLaunchKernelGGL(k_emit_slices, dim3(grid_for(nsl + 1, 256)), dim3(256), 0, s,
+                     (const int32_t *)ws_at<int32_t>(ws, L.slen), nsl, tp->node_sell_off,
+                     (const StatusBlock *)st);
+  EB_LAUNCH_CHECK();
+
   TopoArgs ta{};
   ta.nv = nv;
   ta.elem = elem;
@@ -527,9 +633,14 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
   ta.node_in_edge = tp->node_in_edge;
   ta.bf_cur = bfn_scan;
   ta.bnode_face = tp->bnode_face;
-  ta.node_inc_slot = tp->node_inc_slot;
+  ta.node_sell_off = tp->node_sell_off;
+  ta.node_sell = tp->node_sell;
+  ta.sell_wide = sz->sell_wide;
+  ta.queue = ws_at<int32_t>(ws, L.queue);
   ta.st = st;
   hipLaunchKernelGGL((k_node_topo<D, true>), dim3(grid_for(nv, TB)), dim3(TB), 0, s, ta);
+  EB_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_node_topo_queued<D, true>), dim3(256), dim3(TBS), 0, s, ta);
   EB_LAUNCH_CHECK();
   EB_TRY(rowsort(tp->node_in_off, tp->node_in_edge, nv, s));
   EB_TRY(rowsort(tp->bnode_face_off, tp->bnode_face, sz->n_bnodes, s));
@@ -615,7 +726,8 @@ int eb_build_edges_emit(const eb_sizes *sizes, const int32_t *elem, const double
   const bool has_f = sizes->n_bfaces > 0, has_bn = sizes->n_bnodes > 0;
   if (!t.node_edge_off || !t.node_inc_off || !t.node_in_off || !t.node_bnode ||
       !t.bnode_face_off || (has_e && (!t.edge || !t.node_in_edge)) ||
-      (has_el && (!t.elem_edge || !t.elem_edge_sign || !t.node_inc || !t.node_inc_slot)) ||
+      (has_el && (!t.elem_edge || !t.elem_edge_sign || !t.node_inc || !t.node_sell)) ||
+      !t.node_sell_off ||
       (has_f && (!t.bface || !t.bface_owner || !t.bface_edge)) ||
       (has_bn && (!t.bnode || !t.bnode_face))) {
     set_detail("a required topology array is null");

@@ -47,13 +47,15 @@ def dev(mesh):
 
 
 TOPO_NAMES = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign", "edge_inc_off",
-              "edge_inc", "node_inc_off", "node_inc", "node_inc_slot", "node_in_off", "node_in_edge",
+              "edge_inc", "node_inc_off", "node_inc", "node_sell_off", "node_sell", "node_in_off",
+              "node_in_edge",
               "bface", "bface_owner", "bface_edge", "bnode", "node_bnode",
               "bnode_face_off", "bnode_face")
 
 
 def assert_topo_equal(gt, ot):
-    assert (gt.n_edges, gt.n_bfaces, gt.n_bnodes) == (ot.n_edges, ot.n_bfaces, ot.n_bnodes)
+    assert (gt.n_edges, gt.n_bfaces, gt.n_bnodes, gt.n_sell, gt.sell_wide) == (
+        ot.n_edges, ot.n_bfaces, ot.n_bnodes, ot.n_sell, ot.sell_wide)
     g = gt.to_numpy()
     for name in TOPO_NAMES:
         a = g[name].reshape(-1)
@@ -129,6 +131,15 @@ def with_isolated_nodes(mesh, extra=5, seed=0):
     return meshgen.Mesh(mesh.dim, np.ascontiguousarray(X), mesh.elems, mesh.name + "-iso")
 
 
+def relabelled(mesh, seed):
+    # random node numbering: neighbours far apart in id (wide sliced-ELL
+    # entries once the grid has more than 32768 nodes)
+    lab = np.random.default_rng(seed).permutation(mesh.n_nodes).astype(np.int32)
+    X = np.empty_like(mesh.coords)
+    X[:, lab] = mesh.coords
+    return meshgen.Mesh(mesh.dim, X, np.ascontiguousarray(lab[mesh.elems]), mesh.name + "-relab")
+
+
 def single(dim):
     if dim == 2:
         return meshgen.Mesh(2, np.array([[0., 1, 0], [0, 0, 1]]), np.array([[0, 2, 1]], np.int32))
@@ -148,6 +159,7 @@ CASES = {
     "2d-single": lambda: single(2),
     "3d-single": lambda: single(3),
     "3d-batched-4": lambda: meshgen.batched_kuhn(4, 0, lo=3, hi=9),
+    "3d-33-relabel": lambda: relabelled(meshgen.cube_kuhn(33, 1), 7),
 }
 
 _cache = {}
@@ -171,6 +183,8 @@ def test_topology_bit_exact(name):
     X, E = dev(mesh)
     gt = eb().build_edges(E, X)
     assert_topo_equal(gt, ot)
+    if name.endswith("relabel"):
+        assert gt.sell_wide == 1
 
 
 @pytest.mark.parametrize("reduce", ["gather", "atomic"])
@@ -346,16 +360,41 @@ def test_errors_reported():
         eb().build_edges(torch.tensor([[0, 1, 2, 3], [0, 1, 2, 4], [0, 2, 1, 5]],
                                       dtype=torch.int32, device="cuda"), X)
     assert e.value.code == -4
-    say("[errors] capacity: a node with 40 higher neighbours")
-    k = 40
+    say("[errors] capacity: a node with 140 higher neighbours")
+    with pytest.raises(EbError) as e:
+        Xf, Ef = fan(140)
+        eb().build_edges(torch.from_numpy(Ef).cuda(), torch.from_numpy(Xf).cuda())
+    assert e.value.code == -8
+
+
+def fan(k):
+    # node 0 at the centre of k triangles: k higher-numbered neighbours
     ang = np.linspace(0, 2 * np.pi, k, endpoint=False)
     Xf = np.zeros((2, k + 1))
     Xf[:, 1:] = 1 + np.stack([np.cos(ang), np.sin(ang)])
     Xf[:, 0] = 1
     Ef = np.array([[0, 1 + i, 1 + (i + 1) % k] for i in range(k)], np.int32)
-    with pytest.raises(EbError) as e:
-        eb().build_edges(torch.from_numpy(Ef).cuda(), torch.from_numpy(Xf).cuda())
-    assert e.value.code == -8
+    return Xf, Ef
+
+
+def test_high_degree_node_queued():
+    """A node beyond the fast kernel's per-node capacities (40 out-edges) is
+    handled by the queued kernel, and its 40 out-edges select the wide
+    sliced-ELL format; results match the oracle."""
+    Xf, Ef = fan(40)
+    mesh = meshgen.Mesh(2, Xf, Ef, "fan40")
+    ot = oracle.topology(2, Xf, Ef)
+    X, E = dev(mesh)
+    gt = eb().build_edges(E, X)
+    assert gt.sell_wide == 1
+    assert_topo_equal(gt, ot)
+    n0, b0, V0 = oracle.metrics(ot, Xf, Ef)
+    S_e, S_b = piece_scales(ot, Xf, Ef)
+    for reduce in ("gather", "atomic"):
+        n, b, V = (t.cpu().numpy() for t in eb().directed_areas(X, gt, E, reduce))
+        assert_vec_close(n, n0, S_e, "n")
+        assert_vec_close(b, b0, S_b, "b")
+        assert_vol_close(V, V0, "V")
 
 
 # ------------------------------------------------------------ full size
