@@ -11,5 +11,6 @@ from .api import (REDUCE, VOL_MODE, Topology, build_edges, check_errors,  # noqa
                   directed_areas, directed_areas_backward, dual_volumes,
                   get_gather_shape, set_gather_shape, workspace_bytes)
 from ._lib import EbError  # noqa: F401
+from .autograd import EdgeMetrics, edge_metrics  # noqa: F401
 
 __version__ = "0.1.0"

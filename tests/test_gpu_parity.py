@@ -285,6 +285,24 @@ def test_backward_matches_oracle_gradient(dim, n, reduce):
     assert (rel <= GTOL).all()
 
 
+@pytest.mark.parametrize("reduce", ["atomic", "gather"])
+def test_autograd_function(reduce):
+    """torch.autograd through EdgeMetrics: the gradient of
+    L = sum w.n + sum c V + sum beta.b equals the oracle's reference."""
+    mesh, ot, w, c, beta = grad_case(3, 9, 5)
+    _, gref = oracle.node_grad(ot, mesh.coords, mesh.elems, w, c, beta)
+    X, E = dev(mesh)
+    gt = eb().build_edges(E, X)
+    Xg = X.clone().requires_grad_(True)
+    n, b, V = eb().EdgeMetrics.apply(Xg, gt, E, reduce)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    L = (T(w) * n).sum() + (T(c) * V).sum() + (T(beta) * b).sum()
+    (g,) = torch.autograd.grad(L, Xg)
+    g = g.cpu().numpy().T
+    rel = np.linalg.norm(g - gref, axis=1) / np.linalg.norm(gref, axis=1)
+    assert (rel <= GTOL).all()
+
+
 def test_backward_volume_only_interior_zero():
     mesh = meshgen.cube_kuhn(9, 3)
     X, E = dev(mesh)
