@@ -99,11 +99,39 @@ class Timer:
         ms = np.array([a.elapsed_time(b) for a, b in ev])
         return float(np.mean(ms)), float(np.median(ms)), float(np.min(ms))
 
+    def time_principal(self, eb, fn, reps):
+        """Duration of the call's principal kernel alone: the library records
+        the armed events around that one launch (eb_time_next_launch)."""
+        t = self.torch
+        ev = [(t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:  # create the events on the device
+            a.record()
+            b.record()
+        t.cuda.synchronize()
+        for a, b in ev:
+            eb.time_next_launch(a, b)
+            fn()
+        t.cuda.synchronize()
+        ms = np.array([a.elapsed_time(b) for a, b in ev])
+        return float(np.mean(ms)), float(np.median(ms)), float(np.min(ms))
 
-def cpu_baseline(mesh_full, n_layers=24):
-    """The oracle on a slab of the same grid: the first n_layers node layers
-    in z (all tets between them).  Same rows as a GPU step: topology, n, b, V,
-    and the gradient of the same loss (all nodes)."""
+
+def cpu_baseline(mesh_full, n_layers=24, target_s=15.0):
+    """The oracle on a slab of the same grid: the first node layers in z (all
+    tets between them), grown from n_layers until one run takes about
+    target_s.  Same rows as a GPU step: topology, n, b, V, and the gradient
+    of the same loss (all nodes)."""
+    n = mesh_full.meta["n"]
+    r = _cpu_slab(mesh_full, n_layers)
+    if r["seconds"] < target_s / 1.5 and n_layers < n:
+        grow = int(np.ceil(n_layers * target_s / max(r["seconds"], 1e-3)))
+        r = _cpu_slab(mesh_full, min(n, max(grow, n_layers + 1)))
+    r.pop("seconds")
+    return r
+
+
+def _cpu_slab(mesh_full, n_layers):
     import meshgen
     import oracle
     n = mesh_full.meta["n"]
@@ -128,6 +156,7 @@ def cpu_baseline(mesh_full, n_layers=24):
         "kind": "oracle",
         "sample": (f"first {n_layers} of {n} z node layers of the same grid: {ne_slab} tets; "
                    f"topology {t1 - t0:.2f} s, n/b/V {t2 - t1:.2f} s, gradient {t3 - t2:.2f} s"),
+        "seconds": total,
     }
 
 
@@ -152,7 +181,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phase-reps", type=int, default=10)
     ap.add_argument("--only", default="", help="profiling: run only this phase "
-                    "(topo|fwd|fwd_atomic|vol_edge|bwd|bwd_gather) --steps times")
+                    "(topo|fwd|fwd_atomic|vol_edge|bwd|bwd_atomic) --steps times")
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
 
@@ -189,7 +218,7 @@ def main():
     V = torch.empty(nv, dtype=torch.float64, device="cuda")
     Ve = torch.empty(nv, dtype=torch.float64, device="cuda")
     g = torch.empty(dim, nv, dtype=torch.float64, device="cuda")
-    bwd_reduce = "atomic"
+    bwd_reduce = "gather"
 
     def ph_topo():
         eb.build_edges(E, X, edge_inc=False)
@@ -206,11 +235,11 @@ def main():
     def ph_bwd():
         eb.directed_areas_backward(X, topo, E, W, B, C, reduce=bwd_reduce, out=g)
 
-    def ph_bwd_gather():
-        eb.directed_areas_backward(X, topo, E, W, B, C, reduce="gather", out=g)
+    def ph_bwd_atomic():
+        eb.directed_areas_backward(X, topo, E, W, B, C, reduce="atomic", out=g)
 
     phases = {"topo": ph_topo, "fwd": ph_fwd, "fwd_atomic": ph_fwd_atomic,
-              "vol_edge": ph_vol_edge, "bwd": ph_bwd, "bwd_gather": ph_bwd_gather}
+              "vol_edge": ph_vol_edge, "bwd": ph_bwd, "bwd_atomic": ph_bwd_atomic}
 
     if args.only:
         fn = phases[args.only]
@@ -246,13 +275,23 @@ def main():
         res[name] = tm.time(fn, args.phase_reps)
         log(f"[bench] phase {name}: mean {res[name][0]:.3f} ms, median {res[name][1]:.3f}, "
             f"min {res[name][2]:.3f}")
+    kern = {}
+    for name in ("fwd", "fwd_atomic", "vol_edge", "bwd", "bwd_atomic"):
+        kern[name] = tm.time_principal(eb, phases[name], args.phase_reps)
+        log(f"[bench] principal kernel of {name}: mean {kern[name][0]:.4f} ms, "
+            f"median {kern[name][1]:.4f}, min {kern[name][2]:.4f}")
     eb.check_errors(topo)
 
     bf = alg_bytes_forward(dim, nv, nel, ne_, nb, nbn)
     bb_ = alg_bytes_backward(dim, nv, nel, ne_, nb, nbn)
     bv = alg_bytes_edge_volume(dim, nv, ne_)
-    t_fwd = res["fwd"][0] * 1e-3
-    achieved = bf / t_fwd / 1e9
+    # roofline of the dominant kernel: the forward node pass alone; its
+    # algorithmic bytes exclude the boundary-element terms, which the small
+    # boundary kernel after it handles
+    neb = 1 if dim == 2 else 3
+    bf_main = bf - 8 * dim * nbn - 4 * (dim + neb) * nb
+    t_fwd = kern["fwd"][0] * 1e-3
+    achieved = bf_main / t_fwd / 1e9
     digest = source_digest("eb_metrics.hip", "eb_geom.h", "eb_kernels.h")
     traffic = read_traffic("fwd_gather_161", digest)
 
@@ -262,6 +301,8 @@ def main():
         if bytes_:
             out["alg_GBps"] = round(bytes_ / (ms * 1e-3) / 1e9, 1)
             out["frac_hbm_peak"] = round(bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        if name in kern:
+            out["principal_kernel_ms"] = round(kern[name][0], 4)
         return out
 
     line = {
@@ -284,14 +325,15 @@ def main():
             "elements": nel, "nodes": nv, "edges": ne_, "seed": args.seed,
         },
         "roofline": {
-            "kernel": "k_fwd_gather (eb_directed_areas, gather: n, b, V fused)",
+            "kernel": "k_fwd_gather (eb_directed_areas, gather: n and V fused, node pass)",
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "alg_bytes": bf,
+            "alg_bytes": bf_main,
+            "kernel_ms": round(kern["fwd"][0], 4),
         },
         "phases": {
             "edge_extraction": ph("topo", None),
@@ -299,7 +341,7 @@ def main():
             "forward_atomic": ph("fwd_atomic", bf),
             "edge_volume_gather": ph("vol_edge", bv),
             f"adjoint_{bwd_reduce}": ph("bwd", bb_),
-            "adjoint_gather": ph("bwd_gather", bb_),
+            "adjoint_atomic": ph("bwd_atomic", bb_),
         },
     }
     if not args.no_cpu_baseline:

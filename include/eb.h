@@ -35,7 +35,8 @@
  *     eb_build_edges and eb_check_errors, which synchronize `stream`.
  *   - The caller owns every buffer.  The library allocates no device memory
  *     and keeps no state between calls except a thread-local error detail
- *     string and the gather launch shape (eb_set_gather_shape); scratch
+ *     string, the events armed by eb_time_next_launch (thread-local) and the
+ *     gather launch shape (eb_set_gather_shape); scratch
  *     lives in the caller's workspace `ws`.
  *   - Returns EB_OK (0) or a negative eb_status.  Errors found on the host
  *     (bad arguments, sizes beyond int32 indexing, workspace too small) return
@@ -128,6 +129,10 @@ typedef struct {
  *                                 B = 10, two words per entry (entry index
  *                                 times 2), word 0 = o_0 | o_1 << 32, word 1
  *                                 = o_2 | code << 32 (o_2 = 0 in 2D).
+ *   inc_sell       [(dim+1)*n_elems]  optional (NULL skips; the gather
+ *                                 adjoint needs it): entry index in node_sell
+ *                                 of incidence elem*(dim+1) + local, i.e. the
+ *                                 inverse of the sliced layout
  *   node_in_off    [n_nodes+1]    ids of edges whose head is the node,
  *   node_in_edge   [n_edges]        ascending per node
  *   bface          [n_bfaces][dim] boundary elements (faces of exactly one
@@ -154,6 +159,7 @@ typedef struct {
   int32_t *node_inc_off, *node_inc;
   int32_t *node_sell_off;
   uint64_t *node_sell;
+  int32_t *inc_sell;
   int32_t *node_in_off, *node_in_edge;
   int32_t *bface;
   int32_t *bface_owner;
@@ -165,6 +171,13 @@ typedef struct {
 
 /* Bytes of workspace every call below needs for a grid of this size. */
 size_t eb_workspace_bytes(int dim, int64_t n_nodes, int64_t n_elems);
+
+/* Bytes of workspace eb_directed_areas_backward needs with EB_REDUCE_GATHER:
+ * the above plus 8*(dim == 3 ? 4 : 2) bytes per node_sell entry for the
+ * per-incidence gradients.  A workspace this large serves every call; the
+ * sticky status word sits at its start in either case, so the same
+ * workspace is passed to every call on one grid. */
+size_t eb_backward_workspace_bytes(const eb_sizes *sizes);
 
 /* Edge extraction, phase 1 (Section 2: the edge array; Section 3.2: boundary
  * elements).  Validates the grid, builds the node -> element lists into the
@@ -217,13 +230,30 @@ int eb_dual_volumes(const eb_sizes *sizes, const eb_topology *topo, const int32_
  * grad_coords = dL/dx [dim][n_nodes] for the metrics eb_directed_areas
  * computes (element-based V).  Derivative of the element and boundary
  * formulas above; the orientation sign of each element is held fixed.
- * ATOMIC: thread per element/boundary face with FP64 atomics; GATHER: thread
- * per node, bitwise reproducible. */
+ * ATOMIC: thread per element/boundary face with FP64 atomics.  GATHER: an
+ * element pass writes each element's gradient with respect to each of its
+ * vertices into the workspace at that incidence's node_sell position
+ * (topo->inc_sell), then one thread per node sums its column in node_inc
+ * order and adds its boundary faces in bnode_face order: no atomics, bitwise
+ * reproducible.  GATHER needs topo->inc_sell and ws_bytes >=
+ * eb_backward_workspace_bytes(sizes) (else EB_EINVAL / EB_EWORKSPACE). */
 int eb_directed_areas_backward(const eb_sizes *sizes, const eb_topology *topo,
                                const int32_t *elem, const double *coords,
                                const double *grad_n, const double *grad_b,
                                const double *grad_vol, int reduce, double *grad_coords,
                                void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Profiling aid.  Arms two events (created by the caller, e.g. with
+ * hipEventCreate) for the principal kernel of the next eb_directed_areas,
+ * eb_dual_volumes or eb_directed_areas_backward call made on this thread:
+ * the element- or node-pass kernel that carries the call's main traffic
+ * (gather forward: the node pass; gather adjoint: the element pass; atomic
+ * paths: the element pass; volumes: the one kernel).  That launch records
+ * `start` just before the kernel and `stop` just after it on the call's
+ * stream (hipExtLaunchKernelGGL), so hipEventElapsedTime gives the kernel's
+ * own duration.  The next such call consumes the events whether or not it
+ * launches; NULL, NULL disarms.  Returns EB_EINVAL if only one is NULL. */
+int eb_time_next_launch(hipEvent_t start, hipEvent_t stop);
 
 /* Launch shape of the node-centred (EB_REDUCE_GATHER) kernels: nodes per
  * block (64, 128 or 256), incidences whose loads are issued together per

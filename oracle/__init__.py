@@ -34,7 +34,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "node id out of range",
 
 TOPO_ARRAYS = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign",
                "edge_inc_off", "edge_inc", "node_inc_off", "node_inc", "node_sell_off",
-               "node_sell",
+               "node_sell", "inc_sell",
                "node_in_off", "node_in_edge", "bface", "bface_owner",
                "bface_edge", "bnode", "node_bnode", "bnode_face_off",
                "bnode_face")

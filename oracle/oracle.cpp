@@ -53,6 +53,8 @@
 //               code in bits 48..; wide (B = 10; when some |o_m - j| >
 //               32767 or some node has more than 31 out-edges): two words
 //               o_0 | o_1 << 32 and o_2 | code << 32
+//   inc_sell    [(D+1) NE] entry index in node_sell of each incidence
+//               e*(D+1)+l (the inverse of the sliced layout)
 //   node_edge_off  CSR offsets of edges by tail
 //   node_in     CSR over nodes of the ids of edges whose head is the node
 //   bface       [NB][D] faces owned by one element, in ascending sorted-id
@@ -260,6 +262,7 @@ struct Topo {
   std::vector<int32_t> node_inc_off, node_inc, node_in_off, node_in_edge;
   std::vector<int32_t> node_sell_off;
   std::vector<uint64_t> node_sell;
+  std::vector<int32_t> inc_sell;
   int64_t n_sell = 0;
   int sell_wide = 0;
   std::vector<int32_t> bface, bface_owner, bface_edge, bnode, node_bnode;
@@ -420,9 +423,11 @@ int build_topology(Topo &t, int dim, int64_t nv, int64_t nelem, const int32_t *e
         codes[r] = code;
       }
     t.node_sell.assign((size_t)t.n_sell * (t.sell_wide ? 2 : 1), 0);
+    t.inc_sell.assign(t.node_inc.size(), -1);
     for (int64_t v = 0; v < nv; ++v)
       for (int32_t r = t.node_inc_off[v]; r < t.node_inc_off[v + 1]; ++r) {
         const int64_t pos = t.node_sell_off[v / 64] + 64 * (r - t.node_inc_off[v]) + v % 64;
+        t.inc_sell[t.node_inc[r]] = (int32_t)pos;
         const int32_t *o = &others[(size_t)r * dim];
         if (!t.sell_wide) {
           uint64_t w = (uint64_t)codes[r] << 48;
@@ -662,6 +667,7 @@ int64_t oracle_topo_get(const void *h, const char *name, void *dst) {
       {"node_inc", t.node_inc.data(), t.node_inc.size(), 4},
       {"node_sell_off", t.node_sell_off.data(), t.node_sell_off.size(), 4},
       {"node_sell", t.node_sell.data(), t.node_sell.size(), 8},
+      {"inc_sell", t.inc_sell.data(), t.inc_sell.size(), 4},
       {"node_in_off", t.node_in_off.data(), t.node_in_off.size(), 4},
       {"node_in_edge", t.node_in_edge.data(), t.node_in_edge.size(), 4},
       {"bface", t.bface.data(), t.bface.size(), 4},

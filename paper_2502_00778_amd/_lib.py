@@ -19,14 +19,14 @@ STATUS_NAMES = {0: "EB_OK", -1: "EB_EINVAL", -2: "EB_ERANGE", -3: "EB_EDEGENERAT
                 -7: "EB_EHIP", -8: "EB_ECAPACITY"}
 
 # every symbol declared in include/eb.h
-EXPORTS = ("eb_workspace_bytes", "eb_build_edges", "eb_build_edges_emit",
+EXPORTS = ("eb_workspace_bytes", "eb_backward_workspace_bytes", "eb_build_edges", "eb_build_edges_emit",
            "eb_directed_areas", "eb_dual_volumes", "eb_directed_areas_backward",
-           "eb_set_gather_shape", "eb_get_gather_shape", "eb_check_errors",
+           "eb_set_gather_shape", "eb_get_gather_shape", "eb_time_next_launch", "eb_check_errors",
            "eb_status_string", "eb_last_error_detail", "eb_version")
 
 TOPO_FIELDS = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign",
                "edge_inc_off", "edge_inc", "node_inc_off", "node_inc", "node_sell_off",
-               "node_sell",
+               "node_sell", "inc_sell",
                "node_in_off", "node_in_edge", "bface", "bface_owner",
                "bface_edge", "bnode", "node_bnode", "bnode_face_off",
                "bnode_face")
@@ -67,6 +67,8 @@ def lib():
                        ctypes.c_size_t)
     L.eb_workspace_bytes.argtypes = [i32, i64, i64]
     L.eb_workspace_bytes.restype = sz
+    L.eb_backward_workspace_bytes.argtypes = [ctypes.POINTER(EbSizes)]
+    L.eb_backward_workspace_bytes.restype = sz
     L.eb_build_edges.argtypes = [i32, i64, i64, P, P, P, P, P, sz,
                                  ctypes.POINTER(EbSizes), P]
     L.eb_build_edges_emit.argtypes = [ctypes.POINTER(EbSizes), P, P,
@@ -84,6 +86,7 @@ def lib():
     L.eb_get_gather_shape.argtypes = [ctypes.POINTER(ctypes.c_int)] * 3
     L.eb_get_gather_shape.restype = None
     L.eb_check_errors.argtypes = [P, P]
+    L.eb_time_next_launch.argtypes = [P, P]
     L.eb_status_string.argtypes = [i32]
     L.eb_status_string.restype = ctypes.c_char_p
     L.eb_last_error_detail.restype = ctypes.c_char_p

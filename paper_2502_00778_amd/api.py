@@ -17,7 +17,8 @@ from ._lib import EbSizes, EbTopology, check, lib
 
 __all__ = ["Topology", "build_edges", "directed_areas", "dual_volumes",
            "directed_areas_backward", "check_errors", "set_gather_shape",
-           "get_gather_shape", "workspace_bytes", "REDUCE", "VOL_MODE"]
+           "get_gather_shape", "workspace_bytes", "time_next_launch", "REDUCE",
+           "VOL_MODE"]
 
 REDUCE = {"atomic": _lib.EB_REDUCE_ATOMIC, "gather": _lib.EB_REDUCE_GATHER}
 VOL_MODE = {"element": _lib.EB_VOL_ELEMENT, "edge": _lib.EB_VOL_EDGE}
@@ -83,8 +84,11 @@ class Topology:
 
 
 def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True,
-                stream=None) -> Topology:
-    """Edge extraction and boundary elements (eb_build_edges + _emit)."""
+                adjoint: bool = True, stream=None) -> Topology:
+    """Edge extraction and boundary elements (eb_build_edges + _emit).
+
+    ``adjoint`` also builds inc_sell and sizes the workspace for the gather
+    adjoint (eb_backward_workspace_bytes)."""
     if elems.dim() != 2 or elems.shape[1] not in (3, 4):
         raise ValueError("elems must be [NE, D+1] with D in {2, 3}")
     dim = int(elems.shape[1]) - 1
@@ -105,6 +109,15 @@ def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True
     check(L.eb_build_edges(dim, nv, nel, _ptr(elems), _ptr(coords), _ptr(node_inc_off),
                            _ptr(node_inc), _ptr(ws), wsb, ctypes.byref(sizes), s),
           "eb_build_edges")
+    if adjoint:
+        # the emit pass still reads the build's temporaries: carry them over
+        wsb2 = int(L.eb_backward_workspace_bytes(ctypes.byref(sizes)))
+        if wsb2 > wsb:
+            with torch.cuda.stream(stream if stream is not None
+                                   else torch.cuda.current_stream()):
+                ws2 = torch.empty(wsb2, dtype=torch.uint8, device=dev)
+                ws2[:wsb].copy_(ws)
+            ws, wsb = ws2, wsb2
     ne_, nb, nbn = int(sizes.n_edges), int(sizes.n_bfaces), int(sizes.n_bnodes)
     ne = 3 if dim == 2 else 6
     nbe = 1 if dim == 2 else 3
@@ -120,6 +133,7 @@ def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True
         node_sell_off=torch.empty((nv + 63) // 64 + 1, **i32),
         node_sell=torch.empty(max(int(sizes.n_sell) * (1 + int(sizes.sell_wide)), 1),
                               dtype=torch.int64, device=dev),
+        inc_sell=torch.empty(max((dim + 1) * nel, 1), **i32) if adjoint else None,
         node_in_off=torch.empty(nv + 1, **i32),
         node_in_edge=torch.empty(max(ne_, 1), **i32),
         bface=torch.empty(nb, dim, **i32),
@@ -140,6 +154,8 @@ def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True
     arr["bnode_face"] = arr["bnode_face"][: dim * nb]
     if edge_inc:
         arr["edge_inc"] = arr["edge_inc"][: ne * nel]
+    if adjoint:
+        arr["inc_sell"] = arr["inc_sell"][: (dim + 1) * nel]
     return Topology(dim, nv, nel, ne_, nb, nbn, int(sizes.n_sell), int(sizes.sell_wide), arr,
                     ws, sizes, st)
 
@@ -219,3 +235,11 @@ def get_gather_shape():
     a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     lib().eb_get_gather_shape(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
     return a.value, b.value, c.value
+
+
+def time_next_launch(start, stop):
+    """Arm two ``torch.cuda.Event(enable_timing=True)`` for the principal
+    kernel of the next metric / volume / adjoint call (eb_time_next_launch).
+    The events must already exist on the device (record each once)."""
+    check(lib().eb_time_next_launch(ctypes.c_void_p(start.cuda_event),
+                                    ctypes.c_void_p(stop.cuda_event)), "eb_time_next_launch")

@@ -176,49 +176,93 @@ __global__ __launch_bounds__(256) void k_bwd_atomic_bface(FwdArgs a) {
 }
 
 // ------------------------------------------------------------- gather path
+//
+// Two passes, no atomics.  The element pass forms dL_E/dx_i for every vertex
+// i of element E once and stores it at the node_sell position of incidence
+// (E, i) (inc_sell), so the pieces of node j's column sit where the sliced
+// layout puts j's elements: slice-major, 64 lanes side by side.  The node
+// pass then sums j's column in node_inc order with coalesced loads, and the
+// boundary pass adds j's boundary faces in bnode_face order.
+
+template <int D> struct GP {  // one gradient piece: 3D double4 (pad), 2D double2
+  static constexpr int W = D == 3 ? 4 : 2;
+};
 
 template <int D>
-__global__ __launch_bounds__(256) void k_bwd_gather(FwdArgs a) {
+__global__ __launch_bounds__(256) void k_bwd_elem_pieces(FwdArgs a) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nelem) return;
+  int32_t v[D + 1], pos[D + 1];
+  load_conn<D>(a.elem, e, v);
+  load_conn<D>(a.inc_sell, e, pos);
+  V3 P[D + 1], n[D + 1], W[D + 1];
+#pragma unroll
+  for (int i = 0; i <= D; ++i) P[i] = load_pt<D>(a.X, v[i]);
+  const double det = elem_normals<D>(P, n);
+  double C;
+  elem_weights<D>(a, e, v, W, C);
+  V3 G[D + 1];
+  elem_grad_all<D>(P, n, det, W, C, G);
+#pragma unroll
+  for (int l = 0; l <= D; ++l) {
+    double *q = a.gpiece + (int64_t)GP<D>::W * pos[l];
+    if constexpr (D == 3) {
+      *reinterpret_cast<double4 *>(q) = make_double4(G[l].x, G[l].y, G[l].z, 0.0);
+    } else {
+      *reinterpret_cast<double2 *>(q) = make_double2(G[l].x, G[l].y);
+    }
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_bwd_node_gather(FwdArgs a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.nv) return;
+  const int32_t len = a.node_inc_off[j + 1] - a.node_inc_off[j];
+  const double *q = a.gpiece + (int64_t)GP<D>::W * ((int64_t)a.node_sell_off[j / SELL] + (j % SELL));
+  constexpr int64_t step = (int64_t)GP<D>::W * SELL;
   V3 g = {0.0, 0.0, 0.0};
-  for (int32_t r = a.node_inc_off[j]; r < a.node_inc_off[j + 1]; ++r) {
-    const int32_t inc = a.node_inc[r];
-    const int64_t e = inc / (D + 1);
-    const int l = inc - (int)(e * (D + 1));
-    int32_t v[D + 1];
-    load_conn<D>(a.elem, e, v);
-    V3 P[D + 1], n[D + 1], W[D + 1];
-#pragma unroll
-    for (int i = 0; i <= D; ++i) P[i] = load_pt<D>(a.X, v[i]);
-    const double det = elem_normals<D>(P, n);
-    double C;
-    elem_weights<D>(a, e, v, W, C);
-    V3 G[D + 1];
-    elem_grad_all<D>(P, n, det, W, C, G);
-    g = g + pick(G, l);
-  }
-  const int32_t bj = a.node_bnode ? a.node_bnode[j] : -1;
-  if (bj >= 0 && (a.w_x || a.be_x)) {
-    for (int32_t r = a.bnode_face_off[bj]; r < a.bnode_face_off[bj + 1]; ++r) {
-      const int32_t f = a.bnode_face[r];
-      int32_t fv[D];
-      V3 P[D];
-      int p = 0;
-#pragma unroll
-      for (int s = 0; s < D; ++s) {
-        fv[s] = a.bface[(int64_t)f * D + s];
-        P[s] = load_pt<D>(a.X, fv[s]);
-        if (fv[s] == j) p = s;
-      }
-      V3 G[D];
-      bface_grad_all<D>(P, bface_weight<D>(a, f, fv), G);
-      g = g + pick(G, p);
+  // one accumulator, fixed order: the result does not depend on unrolling
+#pragma unroll 4
+  for (int32_t r = 0; r < len; ++r) {
+    if constexpr (D == 3) {
+      const double4 p = *reinterpret_cast<const double4 *>(q + step * r);
+      g = g + V3{p.x, p.y, p.z};
+    } else {
+      const double2 p = *reinterpret_cast<const double2 *>(q + step * r);
+      g = g + V3{p.x, p.y, 0.0};
     }
   }
   a.g_x[j] = g.x;
   a.g_y[j] = g.y;
   if (D == 3) a.g_z[j] = g.z;
+}
+
+// boundary faces of each boundary node, added after the node pass
+template <int D>
+__global__ __launch_bounds__(256) void k_bwd_boundary_gather(FwdArgs a) {
+  const int64_t bj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (bj >= a.nbnode) return;
+  const int32_t j = a.bnode[bj];
+  V3 g = {0.0, 0.0, 0.0};
+  for (int32_t r = a.bnode_face_off[bj]; r < a.bnode_face_off[bj + 1]; ++r) {
+    const int32_t f = a.bnode_face[r];
+    int32_t fv[D];
+    V3 P[D];
+    int p = 0;
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+      fv[s] = a.bface[(int64_t)f * D + s];
+      P[s] = load_pt<D>(a.X, fv[s]);
+      if (fv[s] == j) p = s;
+    }
+    V3 G[D];
+    bface_grad_all<D>(P, bface_weight<D>(a, f, fv), G);
+    g = g + pick(G, p);
+  }
+  a.g_x[j] += g.x;
+  a.g_y[j] += g.y;
+  if (D == 3) a.g_z[j] += g.z;
 }
 
 template <int D>
@@ -229,7 +273,7 @@ int backward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_
     EB_TRY(fill_f64(a.g_y, a.nv, 0.0, s));
     if (D == 3) EB_TRY(fill_f64(a.g_z, a.nv, 0.0, s));
     if (a.nelem > 0 && (a.w_x || a.c)) {
-      hipLaunchKernelGGL(k_bwd_atomic_elem<D>, dim3(grid_for(a.nelem, 256)), dim3(256), 0, s,
+      launch_principal(k_bwd_atomic_elem<D>, dim3(grid_for(a.nelem, 256)), dim3(256), 0, s,
                          a);
       EB_LAUNCH_CHECK();
     }
@@ -240,8 +284,17 @@ int backward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_
     }
     return EB_OK;
   }
-  hipLaunchKernelGGL(k_bwd_gather<D>, dim3(grid_for(a.nv, 256)), dim3(256), 0, s, a);
+  if (a.nelem > 0) {
+    launch_principal(k_bwd_elem_pieces<D>, dim3(grid_for(a.nelem, 256)), dim3(256), 0, s, a);
+    EB_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_bwd_node_gather<D>, dim3(grid_for(a.nv, 256)), dim3(256), 0, s, a);
   EB_LAUNCH_CHECK();
+  if (a.nbnode > 0 && (a.w_x || a.be_x)) {
+    hipLaunchKernelGGL(k_bwd_boundary_gather<D>, dim3(grid_for(a.nbnode, 256)), dim3(256), 0, s,
+                       a);
+    EB_LAUNCH_CHECK();
+  }
   return EB_OK;
 }
 

@@ -11,6 +11,27 @@ LaunchCfg g_cfg;  // process-wide launch shape of the gather kernels
 LaunchCfg default_cfg() { return g_cfg; }
 
 namespace {
+thread_local TimedLaunch t_armed;    // set by eb_time_next_launch
+thread_local TimedLaunch t_current;  // the events of the call in progress
+
+// Moves the armed events to the call in progress; whatever the call does not
+// consume is dropped when it returns.
+struct PrincipalScope {
+  PrincipalScope() {
+    t_current = t_armed;
+    t_armed = TimedLaunch{};
+  }
+  ~PrincipalScope() { t_current = TimedLaunch{}; }
+};
+}  // namespace
+
+TimedLaunch take_principal_events() {
+  const TimedLaunch t = t_current;
+  t_current = TimedLaunch{};
+  return t;
+}
+
+namespace {
 
 int pack(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem, const double *coords,
          void *ws, size_t ws_bytes, FwdArgs &a) {
@@ -37,6 +58,7 @@ int pack(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem, const d
   a.node_inc = tp->node_inc;
   a.node_sell_off = tp->node_sell_off;
   a.node_sell = tp->node_sell;
+  a.inc_sell = tp->inc_sell;
   a.sell_wide = sz->sell_wide;
   a.node_edge_off = tp->node_edge_off;
   a.edge_tail = tp->edge;
@@ -81,6 +103,7 @@ extern "C" {
 int eb_directed_areas(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
                       const double *coords, int reduce, double *n_edge, double *b_node,
                       double *vol, void *ws, size_t ws_bytes, hipStream_t stream) {
+  PrincipalScope scope;
   clear_detail();
   FwdArgs a;
   EB_TRY(pack(sizes, topo, elem, coords, ws, ws_bytes, a));
@@ -114,6 +137,7 @@ int eb_directed_areas(const eb_sizes *sizes, const eb_topology *topo, const int3
 int eb_dual_volumes(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
                     const double *coords, int mode, const double *n_edge, int reduce,
                     double *vol, void *ws, size_t ws_bytes, hipStream_t stream) {
+  PrincipalScope scope;
   clear_detail();
   FwdArgs a;
   EB_TRY(pack(sizes, topo, elem, coords, ws, ws_bytes, a));
@@ -143,6 +167,7 @@ int eb_directed_areas_backward(const eb_sizes *sizes, const eb_topology *topo,
                                const double *grad_b, const double *grad_vol, int reduce,
                                double *grad_coords, void *ws, size_t ws_bytes,
                                hipStream_t stream) {
+  PrincipalScope scope;
   clear_detail();
   FwdArgs a;
   EB_TRY(pack(sizes, topo, elem, coords, ws, ws_bytes, a));
@@ -159,13 +184,35 @@ int eb_directed_areas_backward(const eb_sizes *sizes, const eb_topology *topo,
   if (sizes->n_bfaces > 0 && (a.w_x || a.be_x))
     EB_TRY(need(a.bface && a.bface_edge && a.node_bnode, "bface, bface_edge, node_bnode"));
   if (reduce == EB_REDUCE_GATHER) {
-    EB_TRY(need(a.node_inc_off && a.node_inc, "node_inc"));
+    EB_TRY(need(a.node_inc_off && a.node_sell_off && (sizes->n_elems == 0 || a.inc_sell),
+                "node_inc_off, node_sell_off, inc_sell"));
+    if (!aligned16(a.inc_sell)) {
+      set_detail("inc_sell must be 16-byte aligned");
+      return EB_EINVAL;
+    }
     if (sizes->n_bfaces > 0 && (a.w_x || a.be_x))
-      EB_TRY(need(a.bnode_face_off && a.bnode_face, "bnode_face"));
+      EB_TRY(need(a.bnode && a.bnode_face_off && a.bnode_face, "bnode, bnode_face"));
+    const size_t want = backward_ws_total(D, sizes->n_nodes, sizes->n_elems, sizes->n_sell);
+    if (ws_bytes < want) {
+      set_detail("the gather adjoint needs %zu workspace bytes, got %zu", want, ws_bytes);
+      return EB_EWORKSPACE;
+    }
+    a.gpiece = ws_at<double>(ws, gpiece_offset(D, sizes->n_nodes, sizes->n_elems));
   }
   const LaunchCfg cfg = default_cfg();
   a.xcd_remap = cfg.xcd_remap;
   return D == 2 ? backward_impl<2>(a, reduce, cfg, stream) : backward_impl<3>(a, reduce, cfg, stream);
+}
+
+int eb_time_next_launch(hipEvent_t start, hipEvent_t stop) {
+  clear_detail();
+  if ((start == nullptr) != (stop == nullptr)) {
+    set_detail("start and stop must both be set or both be null");
+    return EB_EINVAL;
+  }
+  t_armed.start = start;
+  t_armed.stop = stop;
+  return EB_OK;
 }
 
 int eb_set_gather_shape(int tile, int unroll, int xcd_remap) {

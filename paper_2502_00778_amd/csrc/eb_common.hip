@@ -259,6 +259,11 @@ size_t eb_workspace_bytes(int dim, int64_t n_nodes, int64_t n_elems) {
   return eb::ws_layout(dim, n_nodes, n_elems).total;
 }
 
+size_t eb_backward_workspace_bytes(const eb_sizes *sizes) {
+  if (eb::check_sizes(sizes) != EB_OK) return 0;
+  return eb::backward_ws_total(sizes->dim, sizes->n_nodes, sizes->n_elems, sizes->n_sell);
+}
+
 int eb_check_errors(void *ws, hipStream_t stream) {
   eb::clear_detail();
   if (!ws) {

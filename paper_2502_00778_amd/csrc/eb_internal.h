@@ -71,6 +71,16 @@ inline WsLayout ws_layout(int dim, int64_t n_nodes, int64_t n_elems) {
   return L;
 }
 
+// The gather adjoint's per-incidence gradient pieces follow the layout above:
+// 2 (2D) or 4 (3D, padded) doubles per node_sell entry.
+inline size_t gpiece_offset(int dim, int64_t n_nodes, int64_t n_elems) {
+  return align256(ws_layout(dim, n_nodes, n_elems).total);
+}
+inline size_t backward_ws_total(int dim, int64_t n_nodes, int64_t n_elems, int64_t n_sell) {
+  return gpiece_offset(dim, n_nodes, n_elems) +
+         align256(sizeof(double) * (size_t)(dim == 3 ? 4 : 2) * (size_t)n_sell);
+}
+
 template <class T> inline T *ws_at(void *ws, size_t off) {
   return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
 }

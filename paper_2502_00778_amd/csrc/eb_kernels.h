@@ -1,6 +1,8 @@
 // Kernel argument packs and launchers shared by the C-ABI entry points.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "eb_internal.h"
 
 namespace eb {
@@ -15,6 +17,7 @@ struct FwdArgs {
   const int32_t *node_inc_off, *node_inc;
   const int32_t *node_sell_off;
   const uint64_t *node_sell;
+  const int32_t *inc_sell;  // incidence -> node_sell entry index
   int sell_wide;
   const int32_t *node_edge_off, *edge_tail, *edge_head;
   const int32_t *node_in_off, *node_in_edge;
@@ -27,6 +30,7 @@ struct FwdArgs {
   const double *be_x, *be_y, *be_z;  // dL/db rows
   const double *c;                   // dL/dV
   double *g_x, *g_y, *g_z;           // dL/dx rows
+  double *gpiece;  // workspace: per-incidence gradient pieces at node_sell positions
   StatusBlock *st;
   int xcd_remap;
 };
@@ -40,6 +44,22 @@ struct LaunchCfg {
 };
 
 LaunchCfg default_cfg();
+
+// Events armed by eb_time_next_launch for the principal kernel of the current
+// call (consumed by its first launch_principal; cleared when the call ends).
+struct TimedLaunch {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+TimedLaunch take_principal_events();
+
+template <class K, class... A>
+void launch_principal(K kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, A... args) {
+  const TimedLaunch t = take_principal_events();
+  if (t.start)
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, t.start, t.stop, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+}
 
 template <int D> int forward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_t s);
 template <int D>

@@ -372,9 +372,9 @@ int launch_fwd_gather(const FwdArgs &a, const LaunchCfg &cfg, hipStream_t s) {
 #define EB_GATHER_CASE(TN_, CAP_, U_)                                                   \
   if (cfg.tile == TN_ && cfg.unroll == U_) {                                            \
     if (a.sell_wide)                                                                    \
-      hipLaunchKernelGGL((k_fwd_gather<D, TN_, CAP_, U_, true>), grid, dim3(TN_), 0, s, a); \
+      launch_principal((k_fwd_gather<D, TN_, CAP_, U_, true>), grid, dim3(TN_), 0, s, a); \
     else                                                                                \
-      hipLaunchKernelGGL((k_fwd_gather<D, TN_, CAP_, U_, false>), grid, dim3(TN_), 0, s, a); \
+      launch_principal((k_fwd_gather<D, TN_, CAP_, U_, false>), grid, dim3(TN_), 0, s, a); \
     EB_LAUNCH_CHECK();                                                                  \
     return launch_fwd_boundary<D>(a, s);                                                \
   }
@@ -416,7 +416,7 @@ int forward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_t
       if (D == 3) EB_TRY(fill_f64(a.b_z, a.nbnode, 0.0, s));
     }
     if (a.nelem > 0) {
-      hipLaunchKernelGGL(k_fwd_atomic_elem<D>, dim3(grid_for(a.nelem, 256)), dim3(256), 0, s,
+      launch_principal(k_fwd_atomic_elem<D>, dim3(grid_for(a.nelem, 256)), dim3(256), 0, s,
                          a);
       EB_LAUNCH_CHECK();
     }
@@ -442,13 +442,13 @@ int volumes_impl(const FwdArgs &a, int mode, int reduce, const double *n_edge, h
       b.b_x = b.b_y = b.b_z = nullptr;
       EB_TRY(fill_f64(b.vol, b.nv, 0.0, s));
       if (b.nelem > 0) {
-        hipLaunchKernelGGL(k_fwd_atomic_elem<D>, dim3(grid_for(b.nelem, 256)), dim3(256), 0, s,
+        launch_principal(k_fwd_atomic_elem<D>, dim3(grid_for(b.nelem, 256)), dim3(256), 0, s,
                            b);
         EB_LAUNCH_CHECK();
       }
       return EB_OK;
     }
-    hipLaunchKernelGGL(k_vol_elem_gather<D>, dim3(grid_for(a.nv, 256)), dim3(256), 0, s, a);
+    launch_principal(k_vol_elem_gather<D>, dim3(grid_for(a.nv, 256)), dim3(256), 0, s, a);
     EB_LAUNCH_CHECK();
     return EB_OK;
   }
@@ -456,13 +456,13 @@ int volumes_impl(const FwdArgs &a, int mode, int reduce, const double *n_edge, h
   if (reduce == EB_REDUCE_ATOMIC) {
     EB_TRY(fill_f64(a.vol, a.nv, 0.0, s));
     if (a.nedge > 0) {
-      hipLaunchKernelGGL(k_vol_edge_atomic<D>, dim3(grid_for(a.nedge, 256)), dim3(256), 0, s, a,
+      launch_principal(k_vol_edge_atomic<D>, dim3(grid_for(a.nedge, 256)), dim3(256), 0, s, a,
                          nx, ny, nz);
       EB_LAUNCH_CHECK();
     }
     return EB_OK;
   }
-  hipLaunchKernelGGL(k_vol_edge_gather<D>, dim3(grid_for(a.nv, 256)), dim3(256), 0, s, a, nx,
+  launch_principal(k_vol_edge_gather<D>, dim3(grid_for(a.nv, 256)), dim3(256), 0, s, a, nx,
                      ny, nz);
   EB_LAUNCH_CHECK();
   return EB_OK;

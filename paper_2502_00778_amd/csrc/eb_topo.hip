@@ -109,6 +109,7 @@ struct TopoArgs {
   int32_t *bf_cur, *bnode_face;
   const int32_t *node_sell_off;
   uint64_t *node_sell;
+  int32_t *inc_sell;  // optional inverse of the sliced layout
   int sell_wide;
   int32_t *queue;  // nodes beyond the fast kernel's capacities
   StatusBlock *st;
@@ -210,6 +211,7 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, int32_t (*hs
       const uint64_t code = (uint64_t)((s0 < 0 ? none : s0) | ((s1 < 0 ? none : s1) << B) |
                                        (D == 3 ? (s2 < 0 ? none : s2) << (2 * B) : 0));
       const int64_t pos = (int64_t)a.node_sell_off[j / SELL] + (int64_t)SELL * (r - r0) + (j % SELL);
+      if (a.inc_sell) a.inc_sell[inc] = (int32_t)pos;
       if (!a.sell_wide) {
         uint64_t w = code << 48;
 #pragma unroll
@@ -635,6 +637,7 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
   ta.bnode_face = tp->bnode_face;
   ta.node_sell_off = tp->node_sell_off;
   ta.node_sell = tp->node_sell;
+  ta.inc_sell = tp->inc_sell;
   ta.sell_wide = sz->sell_wide;
   ta.queue = ws_at<int32_t>(ws, L.queue);
   ta.st = st;

@@ -50,6 +50,19 @@ def test_workspace_bytes(L):
     assert big < 161 ** 3 * 64
 
 
+def test_backward_workspace_bytes(L):
+    from paper_2502_00778_amd._lib import EbSizes
+    for dim, per in ((3, 32), (2, 16)):
+        sz = EbSizes(dim=dim, n_nodes=1000, n_elems=5000, n_edges=6000, n_bfaces=10,
+                     n_bnodes=10, n_sell=64 * 400, sell_wide=0)
+        base = L.eb_workspace_bytes(dim, 1000, 5000)
+        got = L.eb_backward_workspace_bytes(ctypes.byref(sz))
+        # the build layout, then one padded gradient piece per sliced entry
+        assert base + per * 64 * 400 <= got <= base + per * 64 * 400 + 512
+    bad = EbSizes(dim=4, n_nodes=10, n_elems=10)
+    assert L.eb_backward_workspace_bytes(ctypes.byref(bad)) == 0
+
+
 def test_host_validation(L):
     from paper_2502_00778_amd._lib import EbSizes, EbTopology
     sz = EbSizes()

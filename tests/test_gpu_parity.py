@@ -47,7 +47,7 @@ def dev(mesh):
 
 
 TOPO_NAMES = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign", "edge_inc_off",
-              "edge_inc", "node_inc_off", "node_inc", "node_sell_off", "node_sell", "node_in_off",
+              "edge_inc", "node_inc_off", "node_inc", "node_sell_off", "node_sell", "inc_sell", "node_in_off",
               "node_in_edge",
               "bface", "bface_owner", "bface_edge", "bnode", "node_bnode",
               "bnode_face_off", "bnode_face")

@@ -231,6 +231,104 @@ def test_efficient_formula_exact(dim, seed):
         np.testing.assert_allclose(nb, ref, atol=1e-15)
 
 
+def _brute_sell(dim, nv, elems, edges):
+    """Sliced-ELL layout written out from its definition (the node_sell and
+    inc_sell entries of eb.h): rows of elements per node, other vertices with
+    j's place taken by the last vertex, out-edge ranks, 64-node slices."""
+    nn = dim + 1
+    rows = [[] for _ in range(nv)]
+    for e, el in enumerate(elems):
+        for l, v in enumerate(el):
+            rows[v].append(e * nn + l)
+    outs = [[] for _ in range(nv)]
+    for a, b in edges:
+        outs[a].append(b)
+    nsl = (nv + 63) // 64
+    slen = [max([len(rows[j]) for j in range(64 * s, min(64 * s + 64, nv))] + [0])
+            for s in range(nsl)]
+    off = [0]
+    for s in range(nsl):
+        off.append(off[-1] + 64 * slen[s])
+    maxdelta = max([abs(int(v) - j) for j in range(nv) for inc in rows[j]
+                    for v in elems[inc // nn]] + [0])
+    wide = maxdelta > 32767 or max(len(o) for o in outs) > 31
+    B = 10 if wide else 5
+    none = (1 << B) - 1
+    entries, inc_sell = {}, {}
+    for j in range(nv):
+        for r, inc in enumerate(rows[j]):
+            e, l = divmod(inc, nn)
+            o = [int(elems[e][dim if m == l else m]) for m in range(dim)]
+            code = 0
+            for m, om in enumerate(o):
+                code |= (outs[j].index(om) if om > j else none) << (B * m)
+            pos = off[j // 64] + 64 * r + j % 64
+            entries[pos] = (o, code)
+            inc_sell[inc] = pos
+    return wide, off, entries, inc_sell
+
+
+@pytest.mark.parametrize("case", ["3d-kuhn", "2d-tri", "2d-fan-wide", "3d-relabel"])
+def test_sliced_layout_brute(case):
+    """node_sell_off / node_sell / inc_sell against a plain re-statement of
+    the layout; narrow and wide formats, padding zero."""
+    rng = np.random.default_rng(7)
+    if case == "3d-kuhn":
+        m = meshgen.cube_kuhn(5, 1)
+        dim, X, E = 3, m.coords, m.elems
+    elif case == "3d-relabel":
+        m = meshgen.cube_kuhn(4, 2)
+        perm = rng.permutation(m.n_nodes)
+        dim, X, E = 3, np.empty_like(m.coords), perm[m.elems].astype(np.int32)
+        X[:, perm] = m.coords
+    elif case == "2d-tri":
+        m = meshgen.square_tri(7, 1)
+        dim, X, E = 2, m.coords, m.elems
+    else:  # 34 triangles around node 0: 34 out-edges select the wide format
+        k = 34
+        ang = np.linspace(0, 2 * np.pi, k, endpoint=False)
+        X = np.zeros((2, k + 1))
+        X[:, 1:] = 1 + np.stack([np.cos(ang), np.sin(ang)])
+        X[:, 0] = 1
+        E = np.array([[0, 1 + i, 1 + (i + 1) % k] for i in range(k)], np.int32)
+        dim = 2
+    t = oracle.topology(dim, X, E)
+    nv = X.shape[1]
+    edges = [tuple(x) for x in t["edge"].T.tolist()]
+    wide, off, entries, inc_sell = _brute_sell(dim, nv, E.tolist(), edges)
+    assert t.sell_wide == int(wide)
+    assert t["node_sell_off"].tolist() == off
+    assert t.n_sell == off[-1]
+    words = t["node_sell"]
+    assert words.size == t.n_sell * (2 if wide else 1)
+    B = 10 if wide else 5
+    for pos in range(t.n_sell):
+        if wide:
+            w0, w1 = int(words[2 * pos]), int(words[2 * pos + 1])
+            o = [w0 & 0xffffffff, w0 >> 32, w1 & 0xffffffff][:dim]
+            code = w1 >> 32
+            got = ([np.int32(np.uint32(x)) for x in o], code)
+            if pos not in entries:
+                assert w0 == 0 and w1 == 0
+                continue
+        else:
+            w = int(words[pos])
+            if pos not in entries:
+                assert w == 0
+                continue
+            j = (pos - off[max(i for i in range(len(off)) if off[i] <= pos and
+                                i < len(off) - 1)]) % 64
+            j += 64 * max(i for i in range(len(off) - 1) if off[i] <= pos)
+            o = [j + int(np.int16(np.uint16((w >> (16 * m)) & 0xffff))) for m in range(dim)]
+            code = (w >> 48) & 0x7fff
+            got = (o, code)
+        ref_o, ref_code = entries[pos]
+        assert [int(x) for x in got[0]] == ref_o, pos
+        assert got[1] == ref_code, pos
+    assert t["inc_sell"].tolist() == [inc_sell[i] for i in range((dim + 1) * E.shape[0])]
+    assert B in (5, 10)
+
+
 def test_local_identity_fe_form():
     # per element: traditional piece of edge (j,k) == (n_j - n_k)/(D(D+1))
     for dim, mesh in [(2, meshgen.square_tri(9, 3)), (3, meshgen.cube_kuhn(6, 3))]:
