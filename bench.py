@@ -160,6 +160,93 @@ def _cpu_slab(mesh_full, n_layers):
     }
 
 
+def alg_bytes_fused(dim, nv, nel, ne_, nb, nbn):
+    """Forward + adjoint with the shared inputs (coords, elems, element->edge
+    addressing, boundary elements) counted once."""
+    ne = 3 if dim == 2 else 6
+    neb = 1 if dim == 2 else 3
+    shared = 8 * dim * nv + 4 * (dim + 1) * nel + 4 * ne * nel + 4 * (dim + neb) * nb
+    return (alg_bytes_forward(dim, nv, nel, ne_, nb, nbn)
+            + alg_bytes_backward(dim, nv, nel, ne_, nb, nbn) - shared)
+
+
+def bench_batched(torch, eb, meshgen, seed, reps, tm):
+    """The 64-mesh batch: forward + adjoint as one fused persistent launch
+    (eager and replayed from a captured graph) against 64 x (plain gather
+    forward + plain gather adjoint) on the meshes one by one."""
+    t0 = time.perf_counter()
+    bm = meshgen.batched_kuhn(64, seed)
+    log(f"[bench] batch of 64 meshes: {bm.n_elems} tets ({time.perf_counter() - t0:.1f} s)")
+    X = torch.from_numpy(bm.coords).cuda()
+    E = torch.from_numpy(bm.elems).cuda()
+    topo = eb.build_edges(E, X, edge_inc=False)
+    batch = eb.batch_offsets(topo, E, bm.node_off, bm.elem_off)
+    nv, nel, ne_, nb, nbn = (topo.n_nodes, topo.n_elems, topo.n_edges, topo.n_bfaces,
+                             topo.n_bnodes)
+    w, c, beta = meshgen.loss_weights(seed, 3, ne_, nv, nbn)
+    W, C, B = (torch.from_numpy(a).cuda() for a in (w, c, beta))
+    outs = dict(n=torch.empty(3, ne_, dtype=torch.float64, device="cuda"),
+                b=torch.empty(3, nbn, dtype=torch.float64, device="cuda"),
+                V=torch.empty(nv, dtype=torch.float64, device="cuda"),
+                g=torch.empty(3, nv, dtype=torch.float64, device="cuda"))
+    tune = eb.autotune(X, topo, E, W, B, C, reps=3, out=outs)
+    log(f"[bench] autotune (batch): {tune}")
+
+    def fused():
+        eb.forward_backward(X, topo, E, W, B, C, out=outs)
+
+    gr = eb.ForwardBackwardGraph(X, topo, E, W, B, C)
+    fused()
+    t_fused = tm.time(fused, reps)
+    k_fused = tm.time_principal(eb, fused, reps)
+    gr.launch()
+    t_graph = tm.time(gr.launch, reps)
+    eb.check_errors(topo)
+    gr.close()
+
+    # the same meshes one at a time, each with its own topology
+    per = []
+    for m in range(64):
+        v0, v1 = int(bm.node_off[m]), int(bm.node_off[m + 1])
+        e0, e1 = int(bm.elem_off[m]), int(bm.elem_off[m + 1])
+        Xm = X[:, v0:v1].contiguous()
+        Em = (E[e0:e1] - v0).contiguous()
+        tmm = eb.build_edges(Em, Xm, edge_inc=False)
+        sl = lambda t, k: batch.split(t, k)[m].contiguous()
+        per.append((Xm, Em, tmm, sl(W, "edge"), sl(B, "bnode"), sl(C, "node"),
+                    torch.empty(3, tmm.n_edges, dtype=torch.float64, device="cuda"),
+                    torch.empty(3, tmm.n_bnodes, dtype=torch.float64, device="cuda"),
+                    torch.empty(tmm.n_nodes, dtype=torch.float64, device="cuda"),
+                    torch.empty(3, tmm.n_nodes, dtype=torch.float64, device="cuda")))
+
+    def plain():
+        for Xm, Em, tmm, Wm, Bm, Cm, n_, b_, V_, g_ in per:
+            eb.directed_areas(Xm, tmm, Em, "gather", n_out=n_, b_out=b_, v_out=V_)
+            eb.directed_areas_backward(Xm, tmm, Em, Wm, Bm, Cm, reduce="gather", out=g_)
+
+    plain()
+    t_plain = tm.time(plain, reps)
+    bytes_ = alg_bytes_fused(3, nv, nel, ne_, nb, nbn)
+    res = {
+        "workload": (f"64 Kuhn cubes, n log-uniform in [9, 65] (seed {seed}): {nel} tets, "
+                     f"{nv} nodes, {ne_} edges; forward n/b/V + adjoint dL/dx"),
+        "fused_ms": round(t_fused[0], 4),
+        "fused_kernel_ms": round(k_fused[0], 4),
+        "graph_ms": round(t_graph[0], 4),
+        "per_mesh_plain_ms": round(t_plain[0], 4),
+        "speedup_graph_vs_per_mesh": round(t_plain[0] / t_graph[0], 2),
+        "Melements_per_s_graph": round(nel / (t_graph[0] * 1e-3) / 1e6, 1),
+        "Melements_per_s_per_mesh": round(nel / (t_plain[0] * 1e-3) / 1e6, 1),
+        "alg_GBps_graph": round(bytes_ / (t_graph[0] * 1e-3) / 1e9, 1),
+        "frac_hbm_peak_graph": round(bytes_ / (t_graph[0] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "alg_bytes": bytes_,
+        "tuned_shape": {k: tune[k] for k in ("fused_tile", "fused_unroll",
+                                             "fused_blocks_per_cu")},
+    }
+    log(f"[bench] batched: {res}")
+    return res
+
+
 def calibrate_copy(nbytes=1 << 30, reps=5):
     """A plain device copy of known size (for scaling the HBM counters)."""
     import torch
@@ -181,8 +268,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phase-reps", type=int, default=10)
     ap.add_argument("--only", default="", help="profiling: run only this phase "
-                    "(topo|fwd|fwd_atomic|vol_edge|bwd|bwd_atomic) --steps times")
+                    "(topo|fwd|fwd_atomic|vol_edge|bwd|bwd_atomic|fused) --steps times")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -238,8 +326,14 @@ def main():
     def ph_bwd_atomic():
         eb.directed_areas_backward(X, topo, E, W, B, C, reduce="atomic", out=g)
 
+    fouts = dict(n=n, b=b, V=V, g=g)
+
+    def ph_fused():
+        eb.forward_backward(X, topo, E, W, B, C, out=fouts)
+
     phases = {"topo": ph_topo, "fwd": ph_fwd, "fwd_atomic": ph_fwd_atomic,
-              "vol_edge": ph_vol_edge, "bwd": ph_bwd, "bwd_atomic": ph_bwd_atomic}
+              "vol_edge": ph_vol_edge, "bwd": ph_bwd, "bwd_atomic": ph_bwd_atomic,
+              "fused": ph_fused}
 
     if args.only:
         fn = phases[args.only]
@@ -276,7 +370,7 @@ def main():
         log(f"[bench] phase {name}: mean {res[name][0]:.3f} ms, median {res[name][1]:.3f}, "
             f"min {res[name][2]:.3f}")
     kern = {}
-    for name in ("fwd", "fwd_atomic", "vol_edge", "bwd", "bwd_atomic"):
+    for name in ("fwd", "fwd_atomic", "vol_edge", "bwd", "bwd_atomic", "fused"):
         kern[name] = tm.time_principal(eb, phases[name], args.phase_reps)
         log(f"[bench] principal kernel of {name}: mean {kern[name][0]:.4f} ms, "
             f"median {kern[name][1]:.4f}, min {kern[name][2]:.4f}")
@@ -342,8 +436,11 @@ def main():
             "edge_volume_gather": ph("vol_edge", bv),
             f"adjoint_{bwd_reduce}": ph("bwd", bb_),
             "adjoint_atomic": ph("bwd_atomic", bb_),
+            "fused_forward_adjoint": ph("fused", alg_bytes_fused(dim, nv, nel, ne_, nb, nbn)),
         },
     }
+    if not args.no_batched:
+        line["batched"] = bench_batched(torch, eb, meshgen, args.seed, args.phase_reps, tm)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a slab of the same grid")
         line["cpu_baseline"] = cpu_baseline(mesh)

@@ -70,10 +70,13 @@ typedef enum {
   EB_EWORKSPACE = -5,   /* ws_bytes below eb_workspace_bytes() */
   EB_EOVERFLOW = -6,    /* counts that would overflow int32 indexing */
   EB_EHIP = -7,         /* HIP runtime error */
-  EB_ECAPACITY = -8     /* a node has more than EB_MAX_OUT_EDGES higher-numbered
+  EB_ECAPACITY = -8,    /* a node has more than EB_MAX_OUT_EDGES higher-numbered
                            neighbours, or more than EB_MAX_NODE_FACES candidate
                            faces with it as smallest vertex (faces counted once
                            per element holding them) */
+  EB_ETIMEOUT = -9      /* the fused persistent kernel gave up waiting for an
+                           earlier phase (its waits are bounded; outputs are
+                           then undefined) */
 } eb_status;
 
 #define EB_MAX_OUT_EDGES 128
@@ -263,6 +266,96 @@ int eb_time_next_launch(hipEvent_t start, hipEvent_t stop);
  * changes speed only, never results.  Returns EB_EINVAL for other values. */
 int eb_set_gather_shape(int tile, int unroll, int xcd_remap);
 void eb_get_gather_shape(int *tile, int *unroll, int *xcd_remap);
+
+/* ------------------------------------------------------------------------
+ * Batches of grids, the fused forward + adjoint, graphs, tuning.
+ *
+ * A batch of meshes is passed as ONE grid: node ids of mesh m are offset by
+ * node_off[m] and its elements follow those of mesh m-1 (elem_off[m]).  The
+ * meshes are disconnected, so eb_build_edges / _emit and every call above
+ * treat the whole batch in one launch each, and each mesh's edges, boundary
+ * nodes and boundary faces form contiguous ranges of the outputs.  Results
+ * per mesh equal those of the mesh on its own (same ids up to the offsets). */
+
+/* Per-mesh output ranges of a batch (host arrays of n_mesh+1 entries):
+ * edge_off (n_edge, grad_n rows), bnode_off (b_node, bnode), bface_off
+ * (bface), from node_off / elem_off (host, n_mesh+1 entries each, starting
+ * at 0, node_off strictly increasing to n_nodes, elem_off non-decreasing to
+ * n_elems).  Checks on the device that every element of mesh m references
+ * only mesh m's nodes (EB_EINVAL with the element in the detail otherwise).
+ * Uses the gather-adjoint part of ws as scratch (needs ws_bytes >=
+ * eb_workspace_bytes + 40 (n_mesh+1) rounded; eb_backward_workspace_bytes
+ * is always enough for n_mesh <= n_nodes / 4).  Synchronizes `stream` and
+ * returns (and clears) the sticky device status, like eb_check_errors. */
+int eb_batch_offsets(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
+                     int n_mesh, const int64_t *node_off_host, const int64_t *elem_off_host,
+                     int64_t *edge_off_host, int64_t *bnode_off_host, int64_t *bface_off_host,
+                     void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Forward and adjoint together: n_edge, b_node, vol as eb_directed_areas
+ * with EB_REDUCE_GATHER, and grad_coords as eb_directed_areas_backward with
+ * EB_REDUCE_GATHER, for the loss weights grad_n / grad_b / grad_vol (any may
+ * be NULL = zero; the loss is linear, so its adjoint needs no forward
+ * output).  One persistent kernel takes work items from a counter in ws:
+ * forward node tiles and adjoint element tiles, then forward boundary and
+ * adjoint node tiles, then adjoint boundary tiles; a block entering a later
+ * phase waits (bounded, EB_ETIMEOUT) for the earlier one.  A small reset
+ * kernel runs first, so the enqueue is two kernels and no memset (safe to
+ * capture in a graph).  Same bits as the two separate gather calls up to
+ * floating-point contraction; bitwise reproducible for any launch shape.
+ * Needs everything both gather calls need, including ws_bytes >=
+ * eb_backward_workspace_bytes(sizes).  Calls on one ws must not overlap. */
+int eb_batch_forward_backward(const eb_sizes *sizes, const eb_topology *topo,
+                              const int32_t *elem, const double *coords, const double *grad_n,
+                              const double *grad_b, const double *grad_vol, double *n_edge,
+                              double *b_node, double *vol, double *grad_coords, void *ws,
+                              size_t ws_bytes, hipStream_t stream);
+
+/* A HIP graph of eb_batch_forward_backward with these exact pointers,
+ * captured on a private stream (so the caller's stream may be the null
+ * stream).  Launching it recomputes every output from the current contents
+ * of the inputs (e.g. coordinates updated in place on a deforming grid).
+ * The shape in force at creation is baked in.  Destroy with
+ * eb_graph_destroy; launches on one graph or ws must not overlap. */
+typedef struct eb_graph_s *eb_graph;
+int eb_batch_graph_create(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
+                          const double *coords, const double *grad_n, const double *grad_b,
+                          const double *grad_vol, double *n_edge, double *b_node, double *vol,
+                          double *grad_coords, void *ws, size_t ws_bytes, eb_graph *graph);
+int eb_graph_launch(eb_graph graph, hipStream_t stream);
+int eb_graph_destroy(eb_graph graph);
+
+/* Launch shape of the fused kernel: threads per block (64/128/256; = nodes
+ * per node tile), loads in flight per thread (1/2/4) and resident blocks per
+ * compute unit (1..32, capped by occupancy; 0 = as many as fit).
+ * Process-wide, speed only. */
+int eb_set_fused_shape(int tile, int unroll, int blocks_per_cu);
+void eb_get_fused_shape(int *tile, int *unroll, int *blocks_per_cu);
+
+/* Bound of the fused kernel's phase waits, in polls of about a microsecond
+ * (0 restores the default of 2^22).  A wait that runs out records
+ * EB_ETIMEOUT and its block exits; every wave still ends. */
+int eb_set_fused_wait_limit(int64_t spins);
+
+/* Launch-shape tuner.  Times (reps runs each, after one warm-up, hipEvents
+ * on `stream`) every gather shape of eb_directed_areas (tile x unroll x
+ * xcd_remap) and every fused shape of eb_batch_forward_backward (tile x
+ * unroll x blocks_per_cu in {1,2,4,8,0}) on the caller's grid and buffers,
+ * sets the fastest of each (eb_set_gather_shape / eb_set_fused_shape) and
+ * reports them.  Outputs hold valid results afterwards (all shapes give the
+ * same bits).  Synchronizes `stream`. */
+typedef struct {
+  int32_t gather_tile, gather_unroll, gather_xcd_remap;
+  float gather_ms;
+  int32_t fused_tile, fused_unroll, fused_blocks_per_cu;
+  float fused_ms;
+  int32_t n_tried;
+} eb_tuning;
+int eb_autotune(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
+                const double *coords, const double *grad_n, const double *grad_b,
+                const double *grad_vol, double *n_edge, double *b_node, double *vol,
+                double *grad_coords, void *ws, size_t ws_bytes, int reps, hipStream_t stream,
+                eb_tuning *out);
 
 /* Synchronizes `stream`, returns the sticky device status in ws and resets it
  * to EB_OK. */

@@ -16,13 +16,16 @@ EB_REDUCE_ATOMIC, EB_REDUCE_GATHER = 0, 1
 EB_VOL_ELEMENT, EB_VOL_EDGE = 0, 1
 STATUS_NAMES = {0: "EB_OK", -1: "EB_EINVAL", -2: "EB_ERANGE", -3: "EB_EDEGENERATE",
                 -4: "EB_ENONMANIFOLD", -5: "EB_EWORKSPACE", -6: "EB_EOVERFLOW",
-                -7: "EB_EHIP", -8: "EB_ECAPACITY"}
+                -7: "EB_EHIP", -8: "EB_ECAPACITY", -9: "EB_ETIMEOUT"}
 
 # every symbol declared in include/eb.h
 EXPORTS = ("eb_workspace_bytes", "eb_backward_workspace_bytes", "eb_build_edges", "eb_build_edges_emit",
            "eb_directed_areas", "eb_dual_volumes", "eb_directed_areas_backward",
            "eb_set_gather_shape", "eb_get_gather_shape", "eb_time_next_launch", "eb_check_errors",
-           "eb_status_string", "eb_last_error_detail", "eb_version")
+           "eb_status_string", "eb_last_error_detail", "eb_version",
+           "eb_batch_offsets", "eb_batch_forward_backward", "eb_batch_graph_create",
+           "eb_graph_launch", "eb_graph_destroy", "eb_set_fused_shape", "eb_get_fused_shape",
+           "eb_set_fused_wait_limit", "eb_autotune")
 
 TOPO_FIELDS = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign",
                "edge_inc_off", "edge_inc", "node_inc_off", "node_inc", "node_sell_off",
@@ -41,6 +44,14 @@ class EbSizes(ctypes.Structure):
 
 class EbTopology(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p) for name in TOPO_FIELDS]
+
+
+class EbTuning(ctypes.Structure):
+    _fields_ = [("gather_tile", ctypes.c_int32), ("gather_unroll", ctypes.c_int32),
+                ("gather_xcd_remap", ctypes.c_int32), ("gather_ms", ctypes.c_float),
+                ("fused_tile", ctypes.c_int32), ("fused_unroll", ctypes.c_int32),
+                ("fused_blocks_per_cu", ctypes.c_int32), ("fused_ms", ctypes.c_float),
+                ("n_tried", ctypes.c_int32)]
 
 
 class EbError(RuntimeError):
@@ -87,6 +98,20 @@ def lib():
     L.eb_get_gather_shape.restype = None
     L.eb_check_errors.argtypes = [P, P]
     L.eb_time_next_launch.argtypes = [P, P]
+    SZ, TP = ctypes.POINTER(EbSizes), ctypes.POINTER(EbTopology)
+    I64P = ctypes.POINTER(ctypes.c_int64)
+    L.eb_batch_offsets.argtypes = [SZ, TP, P, i32, I64P, I64P, I64P, I64P, I64P, P, sz, P]
+    L.eb_batch_forward_backward.argtypes = [SZ, TP, P, P, P, P, P, P, P, P, P, P, sz, P]
+    L.eb_batch_graph_create.argtypes = [SZ, TP, P, P, P, P, P, P, P, P, P, P, sz,
+                                        ctypes.POINTER(ctypes.c_void_p)]
+    L.eb_graph_launch.argtypes = [P, P]
+    L.eb_graph_destroy.argtypes = [P]
+    L.eb_set_fused_shape.argtypes = [i32, i32, i32]
+    L.eb_get_fused_shape.argtypes = [ctypes.POINTER(ctypes.c_int)] * 3
+    L.eb_get_fused_shape.restype = None
+    L.eb_set_fused_wait_limit.argtypes = [i64]
+    L.eb_autotune.argtypes = [SZ, TP, P, P, P, P, P, P, P, P, P, P, sz, i32, P,
+                              ctypes.POINTER(EbTuning)]
     L.eb_status_string.argtypes = [i32]
     L.eb_status_string.restype = ctypes.c_char_p
     L.eb_last_error_detail.restype = ctypes.c_char_p

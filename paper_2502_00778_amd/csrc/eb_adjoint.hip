@@ -1,134 +1,7 @@
-// Adjoint of the metrics with respect to the node coordinates.
-//
-// For a loss L = sum_e w_e.n_e + sum_j c_j V_j + sum_j beta_j.b_j the
-// forward formulas give, per element E (orientation sign s held fixed),
-//   L_E = sum_t W_t.n_t + C_E |E|,
-//   W_t = 2/(D(D+1)) * sum of w_e over the local edges whose tail is t,
-//   C_E = (1/(D+1)) sum_{i in E} c_i,
-// and per boundary element B
-//   L_B = W_B.n_B,  W_B = 1/(D(D+1)) sum_{e in B} w_e + (1/D) sum_{i in B} beta_i.
-// Derivatives (3D, face (a,b,c) in cyclic outward order, N = s/2 (x_b-x_a) x
-// (x_c-x_a)):  d(W.N)/dx_a = s/2 (x_b - x_c) x W, and cyclically;
-//        (2D, N = s rot(x_c - x_b), rot(d) = (d_y, -d_x)):
-//              d(W.N)/dx_c = s R(W), d(W.N)/dx_b = -s R(W), R(W) = (-W_y, W_x);
-// and d|E|/dx_i = -n_i/D (moving a vertex against its opposite face's
-// outward normal grows the element).
-#include "eb_geom.h"
-#include "eb_kernels.h"
+// Adjoint kernels and launcher (the derivation is in eb_adjoint.h).
+#include "eb_adjoint.h"
 
 namespace eb {
-
-template <int D>
-__device__ __forceinline__ V3 load_row3(const double *x, const double *y, const double *z,
-                                        int64_t i) {
-  if (D == 3) return {x[i], y[i], z[i]};
-  return {x[i], y[i], 0.0};
-}
-
-// W_t for every local vertex t and C_E of element e.  All indices are
-// compile-time constants (the tail of each local edge is chosen with a
-// select), so nothing lands in scratch memory.
-template <int D>
-__device__ __forceinline__ void elem_weights(const FwdArgs &a, int64_t e, const int32_t (&v)[D + 1],
-                                             V3 (&W)[D + 1], double &C) {
-  constexpr int NE = EL<D>::NE;
-  constexpr double kN = 2.0 / (D * (D + 1));
-#pragma unroll
-  for (int t = 0; t <= D; ++t) W[t] = {0.0, 0.0, 0.0};
-  if (a.w_x) {
-#pragma unroll
-    for (int le = 0; le < NE; ++le) {
-      const int p = pair_p<D>(le), q = pair_q<D>(le);
-      const int32_t ed = a.elem_edge[e * NE + le];
-      const V3 w = kN * load_row3<D>(a.w_x, a.w_y, a.w_z, ed);
-      const V3 z = {0.0, 0.0, 0.0};
-      const bool tail_p = v[p] < v[q];
-      W[p] = W[p] + (tail_p ? w : z);
-      W[q] = W[q] + (tail_p ? z : w);
-    }
-  }
-  C = 0.0;
-  if (a.c) {
-#pragma unroll
-    for (int i = 0; i <= D; ++i) C += a.c[v[i]];
-    C *= 1.0 / (D + 1);
-  }
-}
-
-// dL_E/dx_i for every local vertex i (compile-time indices only)
-template <int D>
-__device__ __forceinline__ void elem_grad_all(const V3 (&P)[D + 1], const V3 (&n)[D + 1], double det,
-                                              const V3 (&W)[D + 1], double C, V3 (&G)[D + 1]) {
-#pragma unroll
-  for (int i = 0; i <= D; ++i) G[i] = (-C / D) * n[i];
-  if constexpr (D == 3) {
-    const double hs = det > 0 ? 0.5 : -0.5;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int fa = face3(t, 0), fb = face3(t, 1), fc = face3(t, 2);
-      G[fa] = G[fa] + hs * cross(P[fb] - P[fc], W[t]);
-      G[fb] = G[fb] + hs * cross(P[fc] - P[fa], W[t]);
-      G[fc] = G[fc] + hs * cross(P[fa] - P[fb], W[t]);
-    }
-  } else {
-    const double s = det > 0 ? 1.0 : -1.0;
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      const V3 R = s * rotW(W[t]);
-      const int b = (t + 1) % 3, c = (t + 2) % 3;
-      G[c] = G[c] + R;
-      G[b] = G[b] - R;
-    }
-  }
-}
-
-// the entry of G[] at runtime index l, by masked sums (no indexed access)
-template <int N>
-__device__ __forceinline__ V3 pick(const V3 (&G)[N], int l) {
-  V3 r = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    const double m = (l == i) ? 1.0 : 0.0;
-    r = r + m * G[i];
-  }
-  return r;
-}
-
-template <int D>
-__device__ __forceinline__ V3 bface_weight(const FwdArgs &a, int64_t f, const int32_t (&fv)[D]) {
-  constexpr int NBE = D == 2 ? 1 : 3;
-  V3 W = {0.0, 0.0, 0.0};
-  if (a.w_x) {
-    constexpr double kB = 1.0 / (D * (D + 1));
-#pragma unroll
-    for (int i = 0; i < NBE; ++i) {
-      const int32_t ed = a.bface_edge[f * NBE + i];
-      W = W + kB * load_row3<D>(a.w_x, a.w_y, a.w_z, ed);
-    }
-  }
-  if (a.be_x) {
-#pragma unroll
-    for (int s = 0; s < D; ++s) {
-      const int32_t bi = a.node_bnode[fv[s]];
-      W = W + (1.0 / D) * load_row3<D>(a.be_x, a.be_y, a.be_z, bi);
-    }
-  }
-  return W;
-}
-
-// d(W.n_B)/dx of every face vertex
-template <int D>
-__device__ __forceinline__ void bface_grad_all(const V3 (&P)[D], V3 W, V3 (&G)[D]) {
-  if constexpr (D == 3) {
-    G[0] = 0.5 * cross(P[1] - P[2], W);
-    G[1] = 0.5 * cross(P[2] - P[0], W);
-    G[2] = 0.5 * cross(P[0] - P[1], W);
-  } else {
-    const V3 R = rotW(W);
-    G[1] = R;
-    G[0] = -R;
-  }
-}
 
 // ------------------------------------------------------------- atomic path
 
@@ -176,93 +49,23 @@ __global__ __launch_bounds__(256) void k_bwd_atomic_bface(FwdArgs a) {
 }
 
 // ------------------------------------------------------------- gather path
-//
-// Two passes, no atomics.  The element pass forms dL_E/dx_i for every vertex
-// i of element E once and stores it at the node_sell position of incidence
-// (E, i) (inc_sell), so the pieces of node j's column sit where the sliced
-// layout puts j's elements: slice-major, 64 lanes side by side.  The node
-// pass then sums j's column in node_inc order with coalesced loads, and the
-// boundary pass adds j's boundary faces in bnode_face order.
-
-template <int D> struct GP {  // one gradient piece: 3D double4 (pad), 2D double2
-  static constexpr int W = D == 3 ? 4 : 2;
-};
 
 template <int D>
 __global__ __launch_bounds__(256) void k_bwd_elem_pieces(FwdArgs a) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= a.nelem) return;
-  int32_t v[D + 1], pos[D + 1];
-  load_conn<D>(a.elem, e, v);
-  load_conn<D>(a.inc_sell, e, pos);
-  V3 P[D + 1], n[D + 1], W[D + 1];
-#pragma unroll
-  for (int i = 0; i <= D; ++i) P[i] = load_pt<D>(a.X, v[i]);
-  const double det = elem_normals<D>(P, n);
-  double C;
-  elem_weights<D>(a, e, v, W, C);
-  V3 G[D + 1];
-  elem_grad_all<D>(P, n, det, W, C, G);
-#pragma unroll
-  for (int l = 0; l <= D; ++l) {
-    double *q = a.gpiece + (int64_t)GP<D>::W * pos[l];
-    if constexpr (D == 3) {
-      *reinterpret_cast<double4 *>(q) = make_double4(G[l].x, G[l].y, G[l].z, 0.0);
-    } else {
-      *reinterpret_cast<double2 *>(q) = make_double2(G[l].x, G[l].y);
-    }
-  }
+  if (e < a.nelem) bwd_elem_piece<D>(a, e);
 }
 
 template <int D>
 __global__ __launch_bounds__(256) void k_bwd_node_gather(FwdArgs a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= a.nv) return;
-  const int32_t len = a.node_inc_off[j + 1] - a.node_inc_off[j];
-  const double *q = a.gpiece + (int64_t)GP<D>::W * ((int64_t)a.node_sell_off[j / SELL] + (j % SELL));
-  constexpr int64_t step = (int64_t)GP<D>::W * SELL;
-  V3 g = {0.0, 0.0, 0.0};
-  // one accumulator, fixed order: the result does not depend on unrolling
-#pragma unroll 4
-  for (int32_t r = 0; r < len; ++r) {
-    if constexpr (D == 3) {
-      const double4 p = *reinterpret_cast<const double4 *>(q + step * r);
-      g = g + V3{p.x, p.y, p.z};
-    } else {
-      const double2 p = *reinterpret_cast<const double2 *>(q + step * r);
-      g = g + V3{p.x, p.y, 0.0};
-    }
-  }
-  a.g_x[j] = g.x;
-  a.g_y[j] = g.y;
-  if (D == 3) a.g_z[j] = g.z;
+  if (j < a.nv) bwd_node_sum<D>(a, j);
 }
 
-// boundary faces of each boundary node, added after the node pass
 template <int D>
 __global__ __launch_bounds__(256) void k_bwd_boundary_gather(FwdArgs a) {
   const int64_t bj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (bj >= a.nbnode) return;
-  const int32_t j = a.bnode[bj];
-  V3 g = {0.0, 0.0, 0.0};
-  for (int32_t r = a.bnode_face_off[bj]; r < a.bnode_face_off[bj + 1]; ++r) {
-    const int32_t f = a.bnode_face[r];
-    int32_t fv[D];
-    V3 P[D];
-    int p = 0;
-#pragma unroll
-    for (int s = 0; s < D; ++s) {
-      fv[s] = a.bface[(int64_t)f * D + s];
-      P[s] = load_pt<D>(a.X, fv[s]);
-      if (fv[s] == j) p = s;
-    }
-    V3 G[D];
-    bface_grad_all<D>(P, bface_weight<D>(a, f, fv), G);
-    g = g + pick(G, p);
-  }
-  a.g_x[j] += g.x;
-  a.g_y[j] += g.y;
-  if (D == 3) a.g_z[j] += g.z;
+  if (bj < a.nbnode) bwd_boundary_node<D>(a, bj);
 }
 
 template <int D>

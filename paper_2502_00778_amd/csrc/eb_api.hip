@@ -9,29 +9,33 @@ LaunchCfg g_cfg;  // process-wide launch shape of the gather kernels
 }
 
 LaunchCfg default_cfg() { return g_cfg; }
+void set_gather_cfg(const LaunchCfg &c) { g_cfg = c; }
+
+namespace {
+FusedCfg g_fused;  // process-wide launch shape of the fused kernel
+}
+FusedCfg fused_cfg() { return g_fused; }
+void set_fused_cfg(const FusedCfg &c) { g_fused = c; }
 
 namespace {
 thread_local TimedLaunch t_armed;    // set by eb_time_next_launch
 thread_local TimedLaunch t_current;  // the events of the call in progress
-
-// Moves the armed events to the call in progress; whatever the call does not
-// consume is dropped when it returns.
-struct PrincipalScope {
-  PrincipalScope() {
-    t_current = t_armed;
-    t_armed = TimedLaunch{};
-  }
-  ~PrincipalScope() { t_current = TimedLaunch{}; }
-};
 }  // namespace
+
+// The armed events move to the call in progress; whatever the call does not
+// consume is dropped when it returns.
+void principal_begin() {
+  t_current = t_armed;
+  t_armed = TimedLaunch{};
+}
+void principal_end() { t_current = TimedLaunch{}; }
+void clear_armed_events() { t_armed = TimedLaunch{}; }
 
 TimedLaunch take_principal_events() {
   const TimedLaunch t = t_current;
   t_current = TimedLaunch{};
   return t;
 }
-
-namespace {
 
 int pack(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem, const double *coords,
          void *ws, size_t ws_bytes, FwdArgs &a) {
@@ -93,7 +97,36 @@ void crows(const double *p, int dim, int64_t n, const double *&x, const double *
   z = (p && dim == 3) ? p + 2 * n : nullptr;
 }
 
-}  // namespace
+int check_fwd_gather(const eb_sizes *sizes, const FwdArgs &a) {
+  EB_TRY(need(a.node_inc_off && a.node_sell_off && (a.node_sell || sizes->n_elems == 0) &&
+                  a.node_edge_off && a.edge_head && a.bnode_face_off,
+              "node_inc_off, node_sell, node_edge_off, edge, bnode_face_off"));
+  if (sizes->n_bfaces > 0) EB_TRY(need(a.bface && a.bnode && a.bnode_face, "bface, bnode, bnode_face"));
+  return EB_OK;
+}
+
+int check_bwd_gather(const eb_sizes *sizes, FwdArgs &a, void *ws, size_t ws_bytes) {
+  const int D = sizes->dim;
+  if (a.w_x) EB_TRY(need(a.elem_edge != nullptr, "elem_edge"));
+  EB_TRY(need(a.node_inc_off && a.node_sell_off && (sizes->n_elems == 0 || a.inc_sell),
+              "node_inc_off, node_sell_off, inc_sell"));
+  if (!aligned16(a.inc_sell)) {
+    set_detail("inc_sell must be 16-byte aligned");
+    return EB_EINVAL;
+  }
+  if (sizes->n_bfaces > 0 && (a.w_x || a.be_x))
+    EB_TRY(need(a.bface && a.bface_edge && a.node_bnode && a.bnode && a.bnode_face_off &&
+                    a.bnode_face,
+                "bface, bface_edge, node_bnode, bnode, bnode_face"));
+  const size_t want = backward_ws_total(D, sizes->n_nodes, sizes->n_elems, sizes->n_sell);
+  if (ws_bytes < want) {
+    set_detail("the gather adjoint needs %zu workspace bytes, got %zu", want, ws_bytes);
+    return EB_EWORKSPACE;
+  }
+  a.gpiece = ws_at<double>(ws, gpiece_offset(D, sizes->n_nodes, sizes->n_elems));
+  return EB_OK;
+}
+
 }  // namespace eb
 
 using namespace eb;
@@ -123,11 +156,7 @@ int eb_directed_areas(const eb_sizes *sizes, const eb_topology *topo, const int3
     EB_TRY(need(a.elem_edge != nullptr, "elem_edge"));
     if (sizes->n_bfaces > 0) EB_TRY(need(a.bface && a.bface_edge && a.node_bnode, "bface, bface_edge, node_bnode"));
   } else {
-    EB_TRY(need(a.node_inc_off && a.node_sell_off && (a.node_sell || sizes->n_elems == 0) &&
-                    a.node_edge_off && a.edge_head && a.bnode_face_off,
-                "node_inc_off, node_sell, node_edge_off, edge, bnode_face_off"));
-    if (sizes->n_bfaces > 0)
-      EB_TRY(need(a.bface && a.bnode && a.bnode_face, "bface, bnode, bnode_face"));
+    EB_TRY(check_fwd_gather(sizes, a));
   }
   const LaunchCfg cfg = default_cfg();
   a.xcd_remap = cfg.xcd_remap;
@@ -183,22 +212,7 @@ int eb_directed_areas_backward(const eb_sizes *sizes, const eb_topology *topo,
   if (a.w_x) EB_TRY(need(a.elem_edge != nullptr, "elem_edge"));
   if (sizes->n_bfaces > 0 && (a.w_x || a.be_x))
     EB_TRY(need(a.bface && a.bface_edge && a.node_bnode, "bface, bface_edge, node_bnode"));
-  if (reduce == EB_REDUCE_GATHER) {
-    EB_TRY(need(a.node_inc_off && a.node_sell_off && (sizes->n_elems == 0 || a.inc_sell),
-                "node_inc_off, node_sell_off, inc_sell"));
-    if (!aligned16(a.inc_sell)) {
-      set_detail("inc_sell must be 16-byte aligned");
-      return EB_EINVAL;
-    }
-    if (sizes->n_bfaces > 0 && (a.w_x || a.be_x))
-      EB_TRY(need(a.bnode && a.bnode_face_off && a.bnode_face, "bnode, bnode_face"));
-    const size_t want = backward_ws_total(D, sizes->n_nodes, sizes->n_elems, sizes->n_sell);
-    if (ws_bytes < want) {
-      set_detail("the gather adjoint needs %zu workspace bytes, got %zu", want, ws_bytes);
-      return EB_EWORKSPACE;
-    }
-    a.gpiece = ws_at<double>(ws, gpiece_offset(D, sizes->n_nodes, sizes->n_elems));
-  }
+  if (reduce == EB_REDUCE_GATHER) EB_TRY(check_bwd_gather(sizes, a, ws, ws_bytes));
   const LaunchCfg cfg = default_cfg();
   a.xcd_remap = cfg.xcd_remap;
   return D == 2 ? backward_impl<2>(a, reduce, cfg, stream) : backward_impl<3>(a, reduce, cfg, stream);

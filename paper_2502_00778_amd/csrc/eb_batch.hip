@@ -1,0 +1,580 @@
+// Fused forward + adjoint in one persistent launch, per-grid offsets of a
+// batch of grids, graph capture of the fused enqueue, and launch-shape tuning.
+//
+// A batch of grids is one grid whose node ids are concatenated: the meshes
+// are disconnected, so the edge extraction, the sliced incidence layout and
+// every gather kernel treat the whole batch at once, and each mesh's edges,
+// boundary nodes and boundary faces come out as one contiguous range (edges
+// are ordered by tail id, boundary lists by smallest vertex id).
+//
+// The fused kernel runs the deterministic forward (n, b, V) and the gather
+// adjoint (dL/dx for a loss linear in n, b, V, whose weights do not depend on
+// the forward outputs) as one stream of work items taken from a counter:
+//   phase 0: forward node tiles, interleaved with adjoint element-piece tiles
+//   phase 1: forward boundary tiles, interleaved with adjoint node tiles
+//   phase 2: adjoint boundary tiles
+// A block that takes its first item of a later phase waits (bounded) until
+// every item of the earlier phase is complete.  Items are handed out in
+// increasing order, so every earlier item was already taken by a running
+// block that waits on nothing later: the waits always end.
+#include <hip/hip_runtime.h>
+
+#include "eb_adjoint.h"
+#include "eb_gather.h"
+
+namespace eb {
+namespace {
+
+constexpr int EPT = 4;                       // elements per thread in a piece item
+constexpr int64_t kDefaultSpinLimit = 1 << 22;  // ~ seconds of s_sleep polling
+int64_t g_spin_limit = kDefaultSpinLimit;
+
+struct FusedPlan {
+  int64_t nF, nP, nB, nG, nH;  // item counts of each kind
+  int64_t spin_limit;
+};
+
+__global__ void k_fused_reset(StatusBlock *st) {
+  if (threadIdx.x < 4) st->fq[threadIdx.x] = 0u;
+}
+
+// Item k of a merged run of nX items of one kind and nXY - nX of another,
+// spread evenly: the first kind iff the running count k*nX/nXY steps at k.
+__device__ __forceinline__ bool first_kind(int64_t k, int64_t nX, int64_t nXY, int64_t &idx) {
+  const int64_t c0 = k * nX / nXY, c1 = (k + 1) * nX / nXY;
+  if (c1 > c0) {
+    idx = c0;
+    return true;
+  }
+  idx = k - c0;
+  return false;
+}
+
+template <int D, int TN, int CAP, int U, bool WIDE>
+__global__ __launch_bounds__(TN) void k_fused(FwdArgs a, FusedPlan p) {
+  __shared__ double acc[D][CAP];
+  __shared__ int64_t s_item;
+  __shared__ int s_phase, s_stop;
+  uint32_t *const q = a.st->fq;  // q[0] next item; q[1 + ph] completed items of phase ph
+  const int t = threadIdx.x;
+  const int64_t nA = p.nF + p.nP, nB = p.nB + p.nG, total = nA + nB + p.nH;
+  const uint32_t target[2] = {(uint32_t)nA, (uint32_t)nB};
+  int cur = 0;             // phase of this block's current items (same in every thread)
+  uint32_t done_here = 0;  // thread 0: items of phase cur this block has completed
+  int known = 0;           // thread 0: phases seen complete
+  for (;;) {
+    if (t == 0) {
+      const int64_t item =
+          __hip_atomic_fetch_add(&q[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_item = item;
+      s_phase = item >= total ? 3 : (item < nA ? 0 : (item < nA + nB ? 1 : 2));
+    }
+    __syncthreads();
+    const int64_t item = s_item;
+    const int ph = s_phase;
+    if (ph != cur) {
+      // Leaving phase cur: publish this block's completed items of it (every
+      // wave's writes made visible on all XCDs, then one counted release),
+      // then wait until every earlier phase is complete.
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      if (t == 0) {
+        if (done_here)
+          __hip_atomic_fetch_add(&q[1 + cur], done_here, __ATOMIC_RELEASE,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+        done_here = 0;
+        int stop = 0;
+        for (; ph < 3 && known < ph && !stop; ++known) {
+          int64_t spins = 0;
+          while (__hip_atomic_load(&q[1 + known], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                 target[known]) {
+            __builtin_amdgcn_s_sleep(8);
+            if (++spins > p.spin_limit) {
+              raise_status(a.st, EB_ETIMEOUT, item);
+              stop = 1;
+              break;
+            }
+          }
+        }
+        s_stop = stop;
+      }
+      __syncthreads();
+      if (ph == 3 || s_stop) break;
+      // see every write of the completed phases, made on any XCD
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      cur = ph;
+    }
+    int64_t idx;
+    if (ph == 0) {
+      if (first_kind(item, p.nF, nA, idx)) {
+        fwd_node_tile<D, TN, CAP, U, WIDE>(a, idx, acc);
+      } else {
+        const int64_t e0 = idx * (int64_t)TN * EPT;
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+          const int64_t e = e0 + (int64_t)k * TN + t;
+          if (e < a.nelem) bwd_elem_piece<D>(a, e);
+        }
+      }
+    } else if (ph == 1) {
+      if (first_kind(item - nA, p.nB, nB, idx)) {
+        const int64_t bj = idx * TN + t;
+        if (bj < a.nbnode) fwd_boundary_node<D>(a, bj);
+      } else {
+        const int64_t j = idx * TN + t;
+        if (j < a.nv) bwd_node_sum<D>(a, j);
+      }
+    } else {
+      const int64_t bj = (item - nA - nB) * TN + t;
+      if (bj < a.nbnode) bwd_boundary_node<D>(a, bj);
+    }
+    if (t == 0) ++done_here;
+    __syncthreads();  // the LDS accumulator and s_item are free again
+  }
+}
+
+int g_num_cus = 0;
+
+int num_cus() {
+  if (g_num_cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&g_num_cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+            hipSuccess ||
+        g_num_cus <= 0)
+      g_num_cus = 256;
+  }
+  return g_num_cus;
+}
+
+template <class K>
+int launch_fused_kernel(K kernel, int tn, const FwdArgs &a, const FusedPlan &p, int blocks_per_cu,
+                        hipStream_t s) {
+  int occ = 0;
+  EB_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, tn, 0));
+  if (occ <= 0) occ = 1;
+  const int per_cu = blocks_per_cu > 0 ? std::min(blocks_per_cu, occ) : occ;
+  const int64_t total = p.nF + p.nP + p.nB + p.nG + p.nH;
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(total, (int64_t)per_cu * num_cus()));
+  launch_principal(kernel, dim3((unsigned)grid), dim3(tn), 0, s, a, p);
+  EB_LAUNCH_CHECK();
+  return EB_OK;
+}
+
+template <int D>
+int fused_impl(const FwdArgs &a, const FusedCfg &cfg, hipStream_t s) {
+  const int64_t tn = cfg.tile;
+  FusedPlan p{};
+  p.nF = (a.nv + tn - 1) / tn;
+  p.nP = (a.nelem + tn * EPT - 1) / (tn * EPT);
+  p.nB = (a.nbnode + tn - 1) / tn;
+  p.nG = p.nF;
+  p.nH = (a.w_x || a.be_x) ? p.nB : 0;
+  p.spin_limit = g_spin_limit;
+  if (p.nF + p.nP + p.nB + p.nG + p.nH >= (int64_t)1 << 31) {
+    set_detail("too many work items for the fused kernel");
+    return EB_EOVERFLOW;
+  }
+  hipLaunchKernelGGL(k_fused_reset, dim3(1), dim3(64), 0, s, a.st);
+  EB_LAUNCH_CHECK();
+#define EB_FUSED_CASE(TN_, CAP_, U_)                                                        \
+  if (cfg.tile == TN_ && cfg.unroll == U_) {                                                \
+    if (a.sell_wide)                                                                        \
+      return launch_fused_kernel(k_fused<D, TN_, CAP_, U_, true>, TN_, a, p, cfg.blocks_per_cu, s); \
+    return launch_fused_kernel(k_fused<D, TN_, CAP_, U_, false>, TN_, a, p, cfg.blocks_per_cu, s); \
+  }
+  EB_FUSED_CASE(64, 512, 1)
+  EB_FUSED_CASE(64, 512, 2)
+  EB_FUSED_CASE(64, 512, 4)
+  EB_FUSED_CASE(128, 1024, 1)
+  EB_FUSED_CASE(128, 1024, 2)
+  EB_FUSED_CASE(128, 1024, 4)
+  EB_FUSED_CASE(256, 2048, 1)
+  EB_FUSED_CASE(256, 2048, 2)
+  EB_FUSED_CASE(256, 2048, 4)
+#undef EB_FUSED_CASE
+  set_detail("unsupported fused tile %d / unroll %d", cfg.tile, cfg.unroll);
+  return EB_EINVAL;
+}
+
+// -------------------------------------------------------- batch offsets
+
+// lower bound of v in the non-decreasing sequence key(0..n-1)
+template <class Key>
+__device__ __forceinline__ int64_t lower_bound_by(int64_t n, int64_t v, Key key) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (key(mid) < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// out = [edge_off | bnode_off | bface_off], n_mesh+1 each
+__global__ void k_batch_offsets(int n_mesh, const int64_t *__restrict__ node_off,
+                                const int32_t *__restrict__ node_edge_off,
+                                const int32_t *__restrict__ bnode, int64_t nbn,
+                                const int32_t *__restrict__ bface, int dim, int64_t nbf,
+                                int64_t *out) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m > n_mesh) return;
+  const int64_t v = node_off[m];
+  out[m] = node_edge_off[v];
+  out[n_mesh + 1 + m] = lower_bound_by(nbn, v, [&](int64_t i) { return (int64_t)bnode[i]; });
+  out[2 * (n_mesh + 1) + m] = lower_bound_by(nbf, v, [&](int64_t f) {
+    int64_t k = bface[f * dim];
+    for (int s = 1; s < dim; ++s) k = min(k, (int64_t)bface[f * dim + s]);
+    return k;
+  });
+}
+
+// every element of mesh m references only mesh m's nodes
+template <int D>
+__global__ void k_batch_check(int n_mesh, const int64_t *__restrict__ node_off,
+                              const int64_t *__restrict__ elem_off,
+                              const int32_t *__restrict__ elem, int64_t nelem, StatusBlock *st) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nelem) return;
+  // the mesh m with elem_off[m] <= e < elem_off[m+1]
+  int64_t lo = 0, hi = n_mesh;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (elem_off[mid] <= e) lo = mid;
+    else hi = mid;
+  }
+  int32_t v[D + 1];
+  load_conn<D>(elem, e, v);
+#pragma unroll
+  for (int i = 0; i <= D; ++i)
+    if (v[i] < node_off[lo] || v[i] >= node_off[lo + 1]) raise_status(st, EB_EINVAL, e);
+}
+
+int pack_fused(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
+               const double *coords, const double *grad_n, const double *grad_b,
+               const double *grad_vol, double *n_edge, double *b_node, double *vol,
+               double *grad_coords, void *ws, size_t ws_bytes, FwdArgs &a) {
+  EB_TRY(pack(sizes, topo, elem, coords, ws, ws_bytes, a));
+  if (!n_edge || !grad_coords) {
+    set_detail("n_edge and grad_coords are required");
+    return EB_EINVAL;
+  }
+  const int D = sizes->dim;
+  rows(n_edge, D, sizes->n_edges, a.n_x, a.n_y, a.n_z);
+  rows(sizes->n_bnodes > 0 ? b_node : nullptr, D, sizes->n_bnodes, a.b_x, a.b_y, a.b_z);
+  a.vol = vol;
+  crows(grad_n, D, sizes->n_edges, a.w_x, a.w_y, a.w_z);
+  crows(sizes->n_bnodes > 0 ? grad_b : nullptr, D, sizes->n_bnodes, a.be_x, a.be_y, a.be_z);
+  a.c = grad_vol;
+  rows(grad_coords, D, sizes->n_nodes, a.g_x, a.g_y, a.g_z);
+  EB_TRY(check_fwd_gather(sizes, a));
+  EB_TRY(check_bwd_gather(sizes, a, ws, ws_bytes));
+  return EB_OK;
+}
+
+}  // namespace
+}  // namespace eb
+
+using namespace eb;
+
+struct eb_graph_s {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+extern "C" {
+
+int eb_batch_forward_backward(const eb_sizes *sizes, const eb_topology *topo,
+                              const int32_t *elem, const double *coords, const double *grad_n,
+                              const double *grad_b, const double *grad_vol, double *n_edge,
+                              double *b_node, double *vol, double *grad_coords, void *ws,
+                              size_t ws_bytes, hipStream_t stream) {
+  PrincipalScope scope;
+  clear_detail();
+  FwdArgs a;
+  EB_TRY(pack_fused(sizes, topo, elem, coords, grad_n, grad_b, grad_vol, n_edge, b_node, vol,
+                    grad_coords, ws, ws_bytes, a));
+  const FusedCfg cfg = fused_cfg();
+  return sizes->dim == 2 ? fused_impl<2>(a, cfg, stream) : fused_impl<3>(a, cfg, stream);
+}
+
+int eb_batch_offsets(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
+                     int n_mesh, const int64_t *node_off_host, const int64_t *elem_off_host,
+                     int64_t *edge_off_host, int64_t *bnode_off_host, int64_t *bface_off_host,
+                     void *ws, size_t ws_bytes, hipStream_t stream) {
+  clear_detail();
+  EB_TRY(check_sizes(sizes));
+  if (!topo || !node_off_host || !elem_off_host || !edge_off_host || !bnode_off_host ||
+      !bface_off_host || n_mesh <= 0 || (sizes->n_elems > 0 && !elem)) {
+    set_detail("null pointer or n_mesh <= 0");
+    return EB_EINVAL;
+  }
+  if (!topo->node_edge_off || (sizes->n_bnodes > 0 && !topo->bnode) ||
+      (sizes->n_bfaces > 0 && !topo->bface)) {
+    set_detail("node_edge_off, bnode and bface are required");
+    return EB_EINVAL;
+  }
+  if (node_off_host[0] != 0 || elem_off_host[0] != 0 ||
+      node_off_host[n_mesh] != sizes->n_nodes || elem_off_host[n_mesh] != sizes->n_elems) {
+    set_detail("offsets must start at 0 and end at n_nodes / n_elems");
+    return EB_EINVAL;
+  }
+  for (int m = 0; m < n_mesh; ++m)
+    if (node_off_host[m + 1] <= node_off_host[m] || elem_off_host[m + 1] < elem_off_host[m]) {
+      set_detail("mesh %d: node offsets must increase, element offsets must not decrease", m);
+      return EB_EINVAL;
+    }
+  EB_TRY(check_ws(sizes->dim, sizes->n_nodes, sizes->n_elems, ws, ws_bytes));
+  const size_t off = gpiece_offset(sizes->dim, sizes->n_nodes, sizes->n_elems);
+  const size_t need_b = off + sizeof(int64_t) * 5 * (size_t)(n_mesh + 1);
+  if (ws_bytes < need_b) {
+    set_detail("eb_batch_offsets needs %zu workspace bytes, got %zu", need_b, ws_bytes);
+    return EB_EWORKSPACE;
+  }
+  int64_t *d_node = ws_at<int64_t>(ws, off);
+  int64_t *d_elem = d_node + (n_mesh + 1);
+  int64_t *d_out = d_elem + (n_mesh + 1);
+  StatusBlock *st = ws_at<StatusBlock>(ws, 0);
+  const size_t nb = sizeof(int64_t) * (size_t)(n_mesh + 1);
+  EB_HIP_CHECK(hipMemcpyAsync(d_node, node_off_host, nb, hipMemcpyHostToDevice, stream));
+  EB_HIP_CHECK(hipMemcpyAsync(d_elem, elem_off_host, nb, hipMemcpyHostToDevice, stream));
+  hipLaunchKernelGGL(k_batch_offsets, dim3(grid_for(n_mesh + 1, 256)), dim3(256), 0, stream,
+                     n_mesh, (const int64_t *)d_node, (const int32_t *)topo->node_edge_off,
+                     (const int32_t *)topo->bnode, sizes->n_bnodes, (const int32_t *)topo->bface,
+                     (int)sizes->dim, sizes->n_bfaces, d_out);
+  EB_LAUNCH_CHECK();
+  if (sizes->n_elems > 0) {
+    if (sizes->dim == 2)
+      hipLaunchKernelGGL(k_batch_check<2>, dim3(grid_for(sizes->n_elems, 256)), dim3(256), 0,
+                         stream, n_mesh, (const int64_t *)d_node, (const int64_t *)d_elem, elem,
+                         sizes->n_elems, st);
+    else
+      hipLaunchKernelGGL(k_batch_check<3>, dim3(grid_for(sizes->n_elems, 256)), dim3(256), 0,
+                         stream, n_mesh, (const int64_t *)d_node, (const int64_t *)d_elem, elem,
+                         sizes->n_elems, st);
+    EB_LAUNCH_CHECK();
+  }
+  EB_HIP_CHECK(hipMemcpyAsync(edge_off_host, d_out, nb, hipMemcpyDeviceToHost, stream));
+  EB_HIP_CHECK(
+      hipMemcpyAsync(bnode_off_host, d_out + (n_mesh + 1), nb, hipMemcpyDeviceToHost, stream));
+  EB_HIP_CHECK(hipMemcpyAsync(bface_off_host, d_out + 2 * (n_mesh + 1), nb,
+                              hipMemcpyDeviceToHost, stream));
+  StatusBlock h;
+  EB_HIP_CHECK(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, stream));
+  EB_HIP_CHECK(hipStreamSynchronize(stream));
+  if (h.status != EB_OK) {  // reported here, so cleared like eb_check_errors does
+    set_detail("%s (element %lld)", eb_status_string(h.status), (long long)h.detail);
+    EB_HIP_CHECK(hipMemsetAsync(st, 0, 16, stream));
+    EB_HIP_CHECK(hipStreamSynchronize(stream));
+    return h.status;
+  }
+  return EB_OK;
+}
+
+int eb_batch_graph_create(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
+                          const double *coords, const double *grad_n, const double *grad_b,
+                          const double *grad_vol, double *n_edge, double *b_node, double *vol,
+                          double *grad_coords, void *ws, size_t ws_bytes, eb_graph *out) {
+  clear_detail();
+  if (!out) {
+    set_detail("out is null");
+    return EB_EINVAL;
+  }
+  *out = nullptr;
+  clear_armed_events();  // a captured launch records no timing events
+  hipStream_t cs = nullptr;
+  EB_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    set_detail("hipStreamBeginCapture: %s", hipGetErrorString(e));
+    return EB_EHIP;
+  }
+  const int rc = eb_batch_forward_backward(sizes, topo, elem, coords, grad_n, grad_b, grad_vol,
+                                           n_edge, b_node, vol, grad_coords, ws, ws_bytes, cs);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(cs, &g);
+  (void)hipStreamDestroy(cs);
+  if (rc != EB_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    if (rc != EB_OK) return rc;
+    set_detail("hipStreamEndCapture: %s", hipGetErrorString(e));
+    return EB_EHIP;
+  }
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    set_detail("hipGraphInstantiate: %s", hipGetErrorString(e));
+    return EB_EHIP;
+  }
+  *out = new eb_graph_s{g, x};
+  return EB_OK;
+}
+
+int eb_graph_launch(eb_graph graph, hipStream_t stream) {
+  clear_detail();
+  if (!graph) {
+    set_detail("graph is null");
+    return EB_EINVAL;
+  }
+  EB_HIP_CHECK(hipGraphLaunch(graph->exec, stream));
+  return EB_OK;
+}
+
+int eb_graph_destroy(eb_graph graph) {
+  clear_detail();
+  if (!graph) return EB_OK;
+  hipError_t e1 = hipGraphExecDestroy(graph->exec);
+  hipError_t e2 = hipGraphDestroy(graph->graph);
+  delete graph;
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    set_detail("graph destroy: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    return EB_EHIP;
+  }
+  return EB_OK;
+}
+
+int eb_set_fused_shape(int tile, int unroll, int blocks_per_cu) {
+  clear_detail();
+  if ((tile != 64 && tile != 128 && tile != 256) || (unroll != 1 && unroll != 2 && unroll != 4) ||
+      blocks_per_cu < 0 || blocks_per_cu > 32) {
+    set_detail("tile must be 64/128/256, unroll 1/2/4, blocks_per_cu 0..32");
+    return EB_EINVAL;
+  }
+  FusedCfg c;
+  c.tile = tile;
+  c.unroll = unroll;
+  c.blocks_per_cu = blocks_per_cu;
+  set_fused_cfg(c);
+  return EB_OK;
+}
+
+void eb_get_fused_shape(int *tile, int *unroll, int *blocks_per_cu) {
+  const FusedCfg c = fused_cfg();
+  if (tile) *tile = c.tile;
+  if (unroll) *unroll = c.unroll;
+  if (blocks_per_cu) *blocks_per_cu = c.blocks_per_cu;
+}
+
+int eb_set_fused_wait_limit(int64_t spins) {
+  clear_detail();
+  if (spins < 0) {
+    set_detail("spins must be >= 0 (0 restores the default)");
+    return EB_EINVAL;
+  }
+  g_spin_limit = spins == 0 ? kDefaultSpinLimit : spins;
+  return EB_OK;
+}
+
+int eb_autotune(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
+                const double *coords, const double *grad_n, const double *grad_b,
+                const double *grad_vol, double *n_edge, double *b_node, double *vol,
+                double *grad_coords, void *ws, size_t ws_bytes, int reps, hipStream_t stream,
+                eb_tuning *out) {
+  clear_detail();
+  if (!out || reps < 1 || reps > 100) {
+    set_detail("out is null or reps outside 1..100");
+    return EB_EINVAL;
+  }
+  {  // validate everything once, before any timing
+    FwdArgs a;
+    EB_TRY(pack_fused(sizes, topo, elem, coords, grad_n, grad_b, grad_vol, n_edge, b_node, vol,
+                      grad_coords, ws, ws_bytes, a));
+  }
+  clear_armed_events();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  EB_HIP_CHECK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    set_detail("hipEventCreate failed");
+    return EB_EHIP;
+  }
+  const LaunchCfg g0 = default_cfg();
+  const FusedCfg f0 = fused_cfg();
+  auto time_it = [&](auto &&run, float &ms) -> int {
+    EB_TRY(run());  // warm-up
+    EB_HIP_CHECK(hipEventRecord(e0, stream));
+    for (int r = 0; r < reps; ++r) EB_TRY(run());
+    EB_HIP_CHECK(hipEventRecord(e1, stream));
+    EB_HIP_CHECK(hipEventSynchronize(e1));
+    EB_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    ms /= reps;
+    return EB_OK;
+  };
+  const int tiles[3] = {64, 128, 256}, unrolls[3] = {1, 2, 4}, per_cu[5] = {1, 2, 4, 8, 0};
+  eb_tuning best{};
+  best.gather_ms = best.fused_ms = 1e30f;
+  int rc = EB_OK, tried = 0;
+  for (int ti = 0; ti < 3 && rc == EB_OK; ++ti)
+    for (int ui = 0; ui < 3 && rc == EB_OK; ++ui)
+      for (int x = 0; x < 2 && rc == EB_OK; ++x) {
+        LaunchCfg c;
+        c.tile = tiles[ti];
+        c.unroll = unrolls[ui];
+        c.xcd_remap = x;
+        set_gather_cfg(c);
+        float ms = 0.f;
+        rc = time_it(
+            [&]() {
+              return eb_directed_areas(sizes, topo, elem, coords, EB_REDUCE_GATHER, n_edge,
+                                       b_node, vol, ws, ws_bytes, stream);
+            },
+            ms);
+        ++tried;
+        if (rc == EB_OK && ms < best.gather_ms) {
+          best.gather_ms = ms;
+          best.gather_tile = c.tile;
+          best.gather_unroll = c.unroll;
+          best.gather_xcd_remap = c.xcd_remap;
+        }
+      }
+  for (int ti = 0; ti < 3 && rc == EB_OK; ++ti)
+    for (int ui = 0; ui < 3 && rc == EB_OK; ++ui)
+      for (int pi = 0; pi < 5 && rc == EB_OK; ++pi) {
+        FusedCfg c;
+        c.tile = tiles[ti];
+        c.unroll = unrolls[ui];
+        c.blocks_per_cu = per_cu[pi];
+        set_fused_cfg(c);
+        float ms = 0.f;
+        rc = time_it(
+            [&]() {
+              return eb_batch_forward_backward(sizes, topo, elem, coords, grad_n, grad_b,
+                                               grad_vol, n_edge, b_node, vol, grad_coords, ws,
+                                               ws_bytes, stream);
+            },
+            ms);
+        ++tried;
+        if (rc == EB_OK && ms < best.fused_ms) {
+          best.fused_ms = ms;
+          best.fused_tile = c.tile;
+          best.fused_unroll = c.unroll;
+          best.fused_blocks_per_cu = c.blocks_per_cu;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != EB_OK) {
+    set_gather_cfg(g0);
+    set_fused_cfg(f0);
+    return rc;
+  }
+  LaunchCfg g;
+  g.tile = best.gather_tile;
+  g.unroll = best.gather_unroll;
+  g.xcd_remap = best.gather_xcd_remap;
+  set_gather_cfg(g);
+  FusedCfg f;
+  f.tile = best.fused_tile;
+  f.unroll = best.fused_unroll;
+  f.blocks_per_cu = best.fused_blocks_per_cu;
+  set_fused_cfg(f);
+  best.n_tried = tried;
+  *out = best;
+  // leave the outputs as the chosen shape computes them (identical bits)
+  return eb_batch_forward_backward(sizes, topo, elem, coords, grad_n, grad_b, grad_vol, n_edge,
+                                   b_node, vol, grad_coords, ws, ws_bytes, stream);
+}
+
+}  // extern "C"

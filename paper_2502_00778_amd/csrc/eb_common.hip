@@ -291,6 +291,7 @@ const char *eb_status_string(int status) {
     case EB_EOVERFLOW: return "sizes overflow int32 indexing";
     case EB_EHIP: return "HIP runtime error";
     case EB_ECAPACITY: return "node exceeds the per-node neighbour capacity";
+    case EB_ETIMEOUT: return "a persistent kernel's bounded wait ran out";
     default: return "unknown status";
   }
 }

@@ -43,6 +43,18 @@ struct LaunchCfg {
   int xcd_remap = 1;
 };
 
+// Launch shape of the fused persistent forward + adjoint kernel: threads per
+// block (= nodes per node tile), loads in flight per thread, and resident
+// blocks per compute unit (0: as many as occupancy allows).
+struct FusedCfg {
+  int tile = 128;
+  int unroll = 2;
+  int blocks_per_cu = 0;
+};
+FusedCfg fused_cfg();
+void set_fused_cfg(const FusedCfg &c);
+void set_gather_cfg(const LaunchCfg &c);
+
 LaunchCfg default_cfg();
 
 // Events armed by eb_time_next_launch for the principal kernel of the current
@@ -51,6 +63,15 @@ struct TimedLaunch {
   hipEvent_t start = nullptr, stop = nullptr;
 };
 TimedLaunch take_principal_events();
+void principal_begin();      // the armed events become the current call's
+void principal_end();        // the current call's unused events are dropped
+void clear_armed_events();   // disarm (graph capture, tuning)
+struct PrincipalScope {
+  PrincipalScope() { principal_begin(); }
+  ~PrincipalScope() { principal_end(); }
+  PrincipalScope(const PrincipalScope &) = delete;
+  PrincipalScope &operator=(const PrincipalScope &) = delete;
+};
 
 template <class K, class... A>
 void launch_principal(K kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, A... args) {
@@ -60,6 +81,17 @@ void launch_principal(K kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream
   else
     hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
 }
+
+// Host-side argument packing and validation shared by the entry points.
+int pack(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem, const double *coords,
+         void *ws, size_t ws_bytes, FwdArgs &a);
+int need(bool ok, const char *what);
+void rows(double *p, int dim, int64_t n, double *&x, double *&y, double *&z);
+void crows(const double *p, int dim, int64_t n, const double *&x, const double *&y,
+           const double *&z);
+int check_fwd_gather(const eb_sizes *sizes, const FwdArgs &a);
+// also points a.gpiece into the workspace
+int check_bwd_gather(const eb_sizes *sizes, FwdArgs &a, void *ws, size_t ws_bytes);
 
 template <int D> int forward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_t s);
 template <int D>

@@ -17,8 +17,7 @@
 //           edges with tail j are a contiguous range owned by j's block, which
 //           accumulates them in LDS and writes them once, coalesced.  No
 //           memset, no atomics, a fixed summation order: bitwise reproducible.
-#include "eb_geom.h"
-#include "eb_kernels.h"
+#include "eb_gather.h"
 
 namespace eb {
 
@@ -93,220 +92,18 @@ __global__ __launch_bounds__(256) void k_fwd_atomic_bface(FwdArgs a) {
 }
 
 // ------------------------------------------------------------- gather path
-//
-// Raw accumulator per edge: sum over elements of c = the cross product the
-// thread forms (3D: c = 2 n_j^E; 2D: c = n_j^E), plus the boundary term in
-// the same units; the final scale kN turns it into n.
-//   3D: n = (1/12)[sum c + sum n_B];  2D: n = (1/3)[sum c + (1/2) sum n_B]
-//   d = c.(x_a - x_j) = D! |E|;  V_j = sum d * kV, kV = 1/24 (3D), 1/6 (2D)
-
-template <int D> struct GK {
-  static constexpr double kN = D == 3 ? 1.0 / 12.0 : 1.0 / 3.0;
-  static constexpr double kBraw = D == 3 ? 1.0 : 0.5;  // n_B in raw units
-  static constexpr double kV = D == 3 ? 1.0 / 24.0 : 1.0 / 6.0;
-};
-
-// The tile of nodes a block handles.  Blocks are dealt round-robin to the 8
-// XCDs (block b runs on XCD b % 8); with remapping, XCD x takes one
-// contiguous run of tiles in order, so neighbouring tiles (which share
-// elements and coordinates) meet in the same L2.  A bijection for any count.
-__device__ __forceinline__ int64_t tile_of_block(int64_t nblocks, int xcd_remap) {
-  const int64_t b = blockIdx.x;
-  if (!xcd_remap || nblocks < 16) return b;
-  const int64_t per = nblocks >> 3, rem = nblocks & 7;
-  const int64_t x = b & 7, k = b >> 3;
-  return x * per + (x < rem ? x : rem) + k;
-}
-
-// Add to a thread-owned LDS accumulator.  Only the owning thread ever adds
-// to a slot, and one wave's LDS operations complete in issue order, so the
-// sum is taken in program order (deterministic); the atomic form lets the
-// add go without waiting for a read.
-__device__ __forceinline__ void lds_add(double *p, double v) {
-  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// position of head k among the out-edges [b, e) of a node (k is present)
-__device__ __forceinline__ int32_t find_head(const int32_t *__restrict__ head, int32_t b, int32_t e,
-                                             int32_t k) {
-  int32_t s = b;
-  while (s < e - 1 && head[s] != k) ++s;
-  return s - b;
-}
-
-// One incidence of node j from the sliced-ELL layout: the element's other
-// vertices o[] and the out-edge slot code.
-template <int D, bool WIDE>
-__device__ __forceinline__ void sell_entry(const uint64_t *__restrict__ sell, int64_t pos,
-                                           int32_t j, int32_t (&o)[D], uint32_t &code) {
-  if constexpr (!WIDE) {
-    const uint64_t w = __builtin_nontemporal_load(sell + pos);
-#pragma unroll
-    for (int m = 0; m < D; ++m) o[m] = j + (int32_t)(int16_t)(uint16_t)(w >> (16 * m));
-    code = (uint32_t)(w >> 48) & 0x7fffu;
-  } else {
-    const uint64_t w0 = __builtin_nontemporal_load(sell + 2 * pos);
-    const uint64_t w1 = __builtin_nontemporal_load(sell + 2 * pos + 1);
-    o[0] = (int32_t)(uint32_t)w0;
-    o[1] = (int32_t)(uint32_t)(w0 >> 32);
-    if constexpr (D == 3) o[2] = (int32_t)(uint32_t)w1;
-    code = (uint32_t)(w1 >> 32);
-  }
-}
+// (device bodies in eb_gather.h)
 
 template <int D, int TN, int CAP, int U, bool WIDE>
 __global__ __launch_bounds__(TN) void k_fwd_gather(FwdArgs a) {
-  static_assert(TN % SELL == 0, "a tile is whole slices");
   __shared__ double acc[D][CAP];
-  const int t = threadIdx.x;
-  const int64_t tile = tile_of_block(gridDim.x, a.xcd_remap);
-  const int64_t j0 = tile * TN;
-  if (j0 >= a.nv) return;  // whole block leaves together
-  const int64_t jend = min(j0 + (int64_t)TN, a.nv);
-  const int32_t e0 = a.node_edge_off[j0];
-  const int32_t cnt = a.node_edge_off[jend] - e0;
-  const bool in_lds = cnt <= CAP;
-  if (in_lds)
-    for (int i = t; i < cnt; i += TN)
-#pragma unroll
-      for (int c = 0; c < D; ++c) acc[c][i] = 0.0;
-  __syncthreads();
-  double *const nx = a.n_x, *const ny = a.n_y, *const nz = a.n_z;
-  const int64_t j = j0 + t;
-  if (j < a.nv) {
-    const int32_t my0 = a.node_edge_off[j], my1 = a.node_edge_off[j + 1];
-    // accumulator of slot s: LDS acc[.][base + s], or the output itself
-    const int32_t base = in_lds ? my0 - e0 : my0;
-    auto add = [&](int s, const V3 &c) {
-      if (in_lds) {
-        lds_add(&acc[0][base + s], c.x);
-        lds_add(&acc[1][base + s], c.y);
-        if (D == 3) lds_add(&acc[2][base + s], c.z);
-      } else {
-        nx[base + s] += c.x;
-        ny[base + s] += c.y;
-        if (D == 3) nz[base + s] += c.z;
-      }
-    };
-    if (!in_lds)
-      for (int32_t ed = my0; ed < my1; ++ed) {
-        nx[ed] = 0.0;
-        ny[ed] = 0.0;
-        if (D == 3) nz[ed] = 0.0;
-      }
-    const V3 xj = load_pt<D>(a.X, (int32_t)j);
-    double vs = 0.0;
-    const int32_t len = a.node_inc_off[j + 1] - a.node_inc_off[j];
-    const int64_t p0 = (int64_t)a.node_sell_off[j / SELL] + (j % SELL);
-    // chunks of U incidences; the next chunk's entries are loaded while the
-    // current chunk's coordinates are in flight
-    int32_t on[U][D];
-    uint32_t cn[U];
-    if (len > 0)
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(u, len - 1), (int32_t)j, on[u],
-                            cn[u]);
-    for (int32_t r = 0; r < len; r += U) {
-      int32_t o[U][D];
-      uint32_t code[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        code[u] = cn[u];
-#pragma unroll
-        for (int m = 0; m < D; ++m) o[u][m] = on[u][m];
-      }
-      V3 P[U][D];
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int m = 0; m < D; ++m) P[u][m] = load_pt<D>(a.X, o[u][m]);
-      if (r + U < len)
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-          sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(r + U + u, len - 1),
-                              (int32_t)j, on[u], cn[u]);
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (r + u >= len) break;
-        V3 c;
-        if constexpr (D == 3)
-          c = cross(P[u][1] - P[u][0], P[u][2] - P[u][0]);
-        else
-          c = rot2(P[u][1] - P[u][0]);
-        double d = dot(c, P[u][0] - xj);
-        if (d < 0.0) {
-          c = -c;
-          d = -d;
-        } else if (d == 0.0) {
-          raise_status(a.st, EB_EDEGENERATE, j);
-        }
-        vs += d;
-#pragma unroll
-        for (int m = 0; m < D; ++m) {
-          const int s = slot_of<WIDE>(code[u], m);
-          if (s != no_slot<WIDE>()) add(s, c);
-        }
-      }
-    }
-    if (a.vol) a.vol[j] = vs * GK<D>::kV;
-    if (!in_lds)
-      for (int32_t ed = my0; ed < my1; ++ed) {
-        nx[ed] *= GK<D>::kN;
-        ny[ed] *= GK<D>::kN;
-        if (D == 3) nz[ed] *= GK<D>::kN;
-      }
-  }
-  if (in_lds) {
-    __syncthreads();
-    for (int i = t; i < cnt; i += TN) {
-      nx[e0 + i] = acc[0][i] * GK<D>::kN;
-      ny[e0 + i] = acc[1][i] * GK<D>::kN;
-      if (D == 3) nz[e0 + i] = acc[2][i] * GK<D>::kN;
-    }
-  }
+  fwd_node_tile<D, TN, CAP, U, WIDE>(a, tile_of_block(gridDim.x, a.xcd_remap), acc);
 }
 
-// Boundary elements, after the element pass: for each boundary node j, b_j
-// and the boundary correction n_B/(D(D+1)) of the edges of B whose tail is
-// j.  Only j's thread touches those edges, and faces are taken in
-// bnode_face order, so the result is deterministic.
 template <int D>
 __global__ __launch_bounds__(256) void k_fwd_boundary_gather(FwdArgs a) {
   const int64_t bj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (bj >= a.nbnode) return;
-  const int32_t j = a.bnode[bj];
-  const int32_t my0 = a.node_edge_off[j], my1 = a.node_edge_off[j + 1];
-  constexpr double kB = 1.0 / (D * (D + 1));
-  V3 bs = {0.0, 0.0, 0.0};
-  for (int32_t r = a.bnode_face_off[bj]; r < a.bnode_face_off[bj + 1]; ++r) {
-    const int32_t f = a.bnode_face[r];
-    int32_t fv[D];
-#pragma unroll
-    for (int s = 0; s < D; ++s) fv[s] = a.bface[(int64_t)f * D + s];
-    V3 nB;
-    if constexpr (D == 3) {
-      const V3 A = load_pt<D>(a.X, fv[0]), B = load_pt<D>(a.X, fv[1]), C = load_pt<D>(a.X, fv[2]);
-      nB = 0.5 * cross(B - A, C - A);
-    } else {
-      nB = rot2(load_pt<D>(a.X, fv[1]) - load_pt<D>(a.X, fv[0]));
-    }
-    bs = bs + nB;
-#pragma unroll
-    for (int s2 = 0; s2 < D; ++s2) {
-      if (fv[s2] <= j || my1 <= my0) continue;
-      const int32_t ed = my0 + find_head(a.edge_head, my0, my1, fv[s2]);
-      a.n_x[ed] += kB * nB.x;
-      a.n_y[ed] += kB * nB.y;
-      if (D == 3) a.n_z[ed] += kB * nB.z;
-    }
-  }
-  if (a.b_x) {
-    constexpr double kb = 1.0 / D;
-    a.b_x[bj] = kb * bs.x;
-    a.b_y[bj] = kb * bs.y;
-    if (D == 3) a.b_z[bj] = kb * bs.z;
-  }
+  if (bj < a.nbnode) fwd_boundary_node<D>(a, bj);
 }
 
 // ----------------------------------------------------- volumes on their own
@@ -364,6 +161,8 @@ __global__ __launch_bounds__(256) void k_vol_edge_gather(FwdArgs a, const double
 }
 
 // ------------------------------------------------------------- launchers
+
+template <int D> int launch_fwd_boundary(const FwdArgs &a, hipStream_t s);
 
 template <int D>
 int launch_fwd_gather(const FwdArgs &a, const LaunchCfg &cfg, hipStream_t s) {

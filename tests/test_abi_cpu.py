@@ -34,7 +34,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_status_strings(L):
-    for code in range(0, -9, -1):
+    for code in range(0, -10, -1):
         s = L.eb_status_string(code).decode()
         assert s and s != "unknown status"
     assert L.eb_status_string(-99).decode() == "unknown status"
