@@ -386,7 +386,8 @@ def main():
     bf_main = bf - 8 * dim * nbn - 4 * (dim + neb) * nb
     t_fwd = kern["fwd"][0] * 1e-3
     achieved = bf_main / t_fwd / 1e9
-    digest = source_digest("eb_metrics.hip", "eb_geom.h", "eb_kernels.h")
+    digest = source_digest("eb_metrics.hip", "eb_gather.h", "eb_geom.h", "eb_kernels.h",
+                           "eb_internal.h")
     traffic = read_traffic("fwd_gather_161", digest)
 
     def ph(name, bytes_):
