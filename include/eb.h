@@ -70,7 +70,7 @@ typedef enum {
   EB_EWORKSPACE = -5,   /* ws_bytes below eb_workspace_bytes() */
   EB_EOVERFLOW = -6,    /* counts that would overflow int32 indexing */
   EB_EHIP = -7,         /* HIP runtime error */
-  EB_ECAPACITY = -8,    /* a node has more than EB_MAX_OUT_EDGES higher-numbered
+  EB_ECAPACITY = -8,    /* a node has more than EB_MAX_NEIGHBOURS distinct
                            neighbours, or more than EB_MAX_NODE_FACES candidate
                            faces with it as smallest vertex (faces counted once
                            per element holding them) */
@@ -79,7 +79,7 @@ typedef enum {
                            then undefined) */
 } eb_status;
 
-#define EB_MAX_OUT_EDGES 128
+#define EB_MAX_NEIGHBOURS 128
 #define EB_MAX_NODE_FACES 256
 
 typedef enum { EB_REDUCE_ATOMIC = 0, EB_REDUCE_GATHER = 1 } eb_reduce;
@@ -183,20 +183,22 @@ size_t eb_workspace_bytes(int dim, int64_t n_nodes, int64_t n_elems);
 size_t eb_backward_workspace_bytes(const eb_sizes *sizes);
 
 /* Edge extraction, phase 1 (Section 2: the edge array; Section 3.2: boundary
- * elements).  Validates the grid, builds the node -> element lists into the
- * caller's node_inc_off [n_nodes+1] and node_inc [(dim+1)*n_elems] (their
- * sizes are known in advance), counts unique edges, boundary faces and
- * boundary nodes into ws, and fills *sizes_host.  Synchronizes `stream` once
- * and returns the sticky device status.  coords [dim][n_nodes] are needed to
- * orient boundary faces outward and to reject zero-measure elements. */
+ * elements).  Validates the grid, fills the caller's node_inc_off [n_nodes+1]
+ * (their sizes are known in advance) and keeps the node -> element lists in
+ * ws, counts unique edges, boundary faces and boundary nodes into ws, and
+ * fills *sizes_host.  node_inc [(dim+1)*n_elems] is written by phase 2.
+ * Synchronizes `stream` once and returns the sticky device status.  coords
+ * [dim][n_nodes] are needed to orient boundary faces outward and to reject
+ * zero-measure elements. */
 int eb_build_edges(int dim, int64_t n_nodes, int64_t n_elems, const int32_t *elem,
                    const double *coords, int32_t *node_inc_off, int32_t *node_inc,
                    void *ws, size_t ws_bytes, eb_sizes *sizes_host, hipStream_t stream);
 
 /* Edge extraction, phase 2: writes every other eb_topology array (sized from
- * *sizes) using the counts eb_build_edges left in ws.  topo->node_inc_off and
- * topo->node_inc must be the arrays phase 1 filled.  edge_inc_off/edge_inc may
- * be NULL. */
+ * *sizes), node_inc included, from what eb_build_edges left in ws (the same
+ * ws, untouched in between).  topo->node_inc_off must be the array phase 1
+ * filled and topo->node_inc the one passed to it.  edge_inc_off/edge_inc and
+ * inc_sell may be NULL. */
 int eb_build_edges_emit(const eb_sizes *sizes, const int32_t *elem, const double *coords,
                         const eb_topology *topo, void *ws, size_t ws_bytes,
                         hipStream_t stream);

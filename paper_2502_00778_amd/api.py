@@ -109,15 +109,6 @@ def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True
     check(L.eb_build_edges(dim, nv, nel, _ptr(elems), _ptr(coords), _ptr(node_inc_off),
                            _ptr(node_inc), _ptr(ws), wsb, ctypes.byref(sizes), s),
           "eb_build_edges")
-    if adjoint:
-        # the emit pass still reads the build's temporaries: carry them over
-        wsb2 = int(L.eb_backward_workspace_bytes(ctypes.byref(sizes)))
-        if wsb2 > wsb:
-            with torch.cuda.stream(stream if stream is not None
-                                   else torch.cuda.current_stream()):
-                ws2 = torch.empty(wsb2, dtype=torch.uint8, device=dev)
-                ws2[:wsb].copy_(ws)
-            ws, wsb = ws2, wsb2
     ne_, nb, nbn = int(sizes.n_edges), int(sizes.n_bfaces), int(sizes.n_bnodes)
     ne = 3 if dim == 2 else 6
     nbe = 1 if dim == 2 else 3
@@ -147,6 +138,16 @@ def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True
     st = EbTopology(**{k: (v.data_ptr() if v is not None else None) for k, v in arr.items()})
     check(L.eb_build_edges_emit(ctypes.byref(sizes), _ptr(elems), _ptr(coords),
                                 ctypes.byref(st), _ptr(ws), wsb, s), "eb_build_edges_emit")
+    if adjoint:
+        # after the emit pass only the status block of ws is live; the gather
+        # adjoint needs a larger workspace (eb_backward_workspace_bytes)
+        wsb2 = int(L.eb_backward_workspace_bytes(ctypes.byref(sizes)))
+        if wsb2 > wsb:
+            with torch.cuda.stream(stream if stream is not None
+                                   else torch.cuda.current_stream()):
+                ws2 = torch.empty(wsb2, dtype=torch.uint8, device=dev)
+                ws2[:256].copy_(ws[:256])
+            ws, wsb = ws2, wsb2
     # trim the placeholder lengths used for empty arrays
     arr["node_inc"] = arr["node_inc"][: (dim + 1) * nel]
     arr["node_sell"] = arr["node_sell"][: int(sizes.n_sell) * (1 + int(sizes.sell_wide))]

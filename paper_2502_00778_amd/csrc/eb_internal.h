@@ -39,9 +39,10 @@ __device__ inline void raise_status(StatusBlock *st, int code, int64_t detail) {
 
 // ------------------------------------------------------ workspace layout
 // [status 256 B][eoff][foff][bidx][bfn][bfn_scan][ein_scan][slen][queue][scan scratch]
+// [incidence rows (build) | gradient pieces (gather adjoint)]
 // Each per-node array holds n_nodes+1 int32 and starts on a 256-byte line.
 struct WsLayout {
-  size_t eoff, foff, bidx, bfn, bfn_scan, ein_scan, slen, queue, scan_tmp, total;
+  size_t eoff, foff, bidx, bfn, bfn_scan, ein_scan, slen, queue, scan_tmp, rows4, total;
   int64_t scan_tmp_count;
 };
 
@@ -68,18 +69,23 @@ inline WsLayout ws_layout(int dim, int64_t n_nodes, int64_t n_elems) {
   int64_t longest = std::max<int64_t>(n_nodes + 1, ne * n_elems + 1);
   L.scan_tmp_count = (longest + SCAN_TILE - 1) / SCAN_TILE + 64;
   L.scan_tmp = off; off += align256(sizeof(int32_t) * (size_t)L.scan_tmp_count);
+  // build only: one 16-byte entry per incidence (the adjoint reuses the space)
+  L.rows4 = off; off += align256(16 * (size_t)(dim + 1) * (size_t)n_elems);
   L.total = off;
   return L;
 }
 
 // The gather adjoint's per-incidence gradient pieces follow the layout above:
 // 2 (2D) or 4 (3D, padded) doubles per node_sell entry.
+// The build's incidence rows are dead once the emit pass is done, so the
+// pieces take their place.
 inline size_t gpiece_offset(int dim, int64_t n_nodes, int64_t n_elems) {
-  return align256(ws_layout(dim, n_nodes, n_elems).total);
+  return ws_layout(dim, n_nodes, n_elems).rows4;
 }
 inline size_t backward_ws_total(int dim, int64_t n_nodes, int64_t n_elems, int64_t n_sell) {
-  return gpiece_offset(dim, n_nodes, n_elems) +
-         align256(sizeof(double) * (size_t)(dim == 3 ? 4 : 2) * (size_t)n_sell);
+  const WsLayout L = ws_layout(dim, n_nodes, n_elems);
+  return std::max(L.total,
+                  L.rows4 + align256(sizeof(double) * (size_t)(dim == 3 ? 4 : 2) * (size_t)n_sell));
 }
 
 template <class T> inline T *ws_at(void *ws, size_t off) {

@@ -3,18 +3,20 @@
 //
 // The build is a bucket (counting) sort keyed by node followed by small
 // per-bucket sorts, instead of a multi-pass global radix sort of edge keys:
-//   1. count the elements of every node (histogram), scan, scatter
-//      elem*(D+1)+local into node_inc (a one-digit radix sort with radix
-//      n_nodes), then sort every bucket so the order is unique;
-//   2. per node j, the edges with tail j are the distinct neighbours k > j in
-//      j's elements: collect them sorted and unique in LDS (count pass, scan,
-//      emit pass) -> edges come out in ascending (tail, head) order;
+//   1. count the elements of every node (histogram, aggregated per block in
+//      LDS), scan, scatter elem*(D+1)+local into node_inc (a one-digit radix
+//      sort with radix n_nodes), then sort every bucket so the order is
+//      unique;
+//   2. per node j, the distinct neighbours of j in j's elements, sorted in
+//      LDS (count pass, scan, emit pass): those above j are its out-edges,
+//      emitted in ascending (tail, head) order, those below its in-edges;
+//      the emit pass also writes each element's edge ids for the local edges
+//      whose tail is j, and j's sliced incidence entries;
 //   3. per node j, the faces whose smallest vertex is j are counted in j's
 //      elements (each face lies in one or two elements, both containing j);
 //      faces met once are boundary faces, three or more is an error;
-//   4. element -> edge map by binary search in the tail's head list; the
-//      edge -> element and other CSR lists by count / scan / scatter / row
-//      sort.
+//   4. in-edge ids by binary search in each tail's out-edges; the other CSR
+//      lists by count / scan / scatter / row sort.
 // Every integer output is thus uniquely defined (bit-exact across runs).
 #include "eb_geom.h"
 
@@ -22,15 +24,16 @@ namespace eb {
 
 namespace {
 
-// Per-node topology work keeps each node's sorted head list and its
+// Per-node topology work keeps each node's sorted neighbour list and its
 // candidate faces in LDS.  A fast kernel with small per-node capacities
 // handles almost every node; nodes beyond them are queued and handled by a
 // second kernel with large capacities (a few threads per block).
 constexpr int TB = 128;                   // fast kernel: threads per block
-constexpr int MAXH = 32;                  //   heads per node
+constexpr int MAXH = 24;                  //   neighbours per node (registers)
 constexpr int MAXF = 64;                  //   candidate faces per node
+constexpr int MAXR = 32;                  //   incidences per node (emit ranking)
 constexpr int TBS = 32;                   // queued nodes: threads per block
-constexpr int MAXH_S = EB_MAX_OUT_EDGES;  //   heads per node
+constexpr int MAXH_S = EB_MAX_NEIGHBOURS; //   neighbours per node
 constexpr int MAXF_S = EB_MAX_NODE_FACES; //   candidate faces per node
 static_assert(MAXH_S * MAXH_S <= 0x8000, "face codes fit 15 bits");
 static_assert(MAXH <= MAXH_S && MAXF <= MAXF_S, "queued capacities are the larger");
@@ -51,44 +54,133 @@ __device__ __forceinline__ bool conn_valid(const int32_t (&v)[D + 1], int64_t nv
   return ok;
 }
 
-template <int D>
-__global__ void k_count_nodes(const int32_t *__restrict__ elem, int64_t nelem, int64_t nv,
-                              Coords X, int32_t *cnt, StatusBlock *st) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nelem) return;
-  int32_t v[D + 1];
-  load_conn<D>(elem, e, v);
-  if (!conn_valid<D>(v, nv)) {
-    raise_status(st, EB_ERANGE, e);
-    return;
+// Incidences are aggregated per block before touching global counters: a
+// block of AGG_TB threads takes AGG_EPT * AGG_TB consecutive elements and
+// gathers its (node, count) pairs in an LDS hash table (open addressing),
+// then adds each node's count once.  Grids numbered with locality (most
+// generators, and any cell-by-cell split) see several times fewer global
+// atomics; an incidence that finds no free slot within AGG_PROBE probes
+// goes to the global counter directly, so any input still works.
+constexpr int AGG_TB = 256;
+constexpr int AGG_EPT = 4;
+constexpr int AGG_LOG = 11;
+constexpr int AGG_HT = 1 << AGG_LOG;  // hash slots
+constexpr int AGG_PROBE = 16;
+
+// slot of node v in the block's table (inserting it), or -1 if the probe
+// sequence is full
+__device__ __forceinline__ int agg_slot(int32_t *hk, int32_t v) {
+  uint32_t h = ((uint32_t)v * 2654435761u) >> (32 - AGG_LOG);
+#pragma unroll 1
+  for (int p = 0; p < AGG_PROBE; ++p) {
+    const int32_t prev = atomicCAS(&hk[h], -1, v);
+    if (prev == -1 || prev == v) return (int)h;
+    h = (h + 1) & (AGG_HT - 1);
   }
-  V3 P[D + 1];
-#pragma unroll
-  for (int i = 0; i <= D; ++i) P[i] = load_pt<D>(X, v[i]);
-  double det;
-  if constexpr (D == 3)
-    det = dot(P[1] - P[0], cross(P[2] - P[0], P[3] - P[0]));
-  else
-    det = (P[1].x - P[0].x) * (P[2].y - P[0].y) - (P[1].y - P[0].y) * (P[2].x - P[0].x);
-  if (det == 0.0) raise_status(st, EB_EDEGENERATE, e);
-#pragma unroll
-  for (int i = 0; i <= D; ++i) atomicAdd(&cnt[v[i]], 1);
+  return -1;
 }
 
-// cur holds inclusive (end) offsets; each slot taken decrements it, so it
-// ends as the exclusive (start) offsets
 template <int D>
-__global__ void k_scatter_nodes(const int32_t *__restrict__ elem, int64_t nelem, int64_t nv,
-                                int32_t *cur, int32_t *node_inc) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nelem) return;
-  int32_t v[D + 1];
-  load_conn<D>(elem, e, v);
-  if (!conn_valid<D>(v, nv)) return;
+__global__ __launch_bounds__(AGG_TB) void k_count_nodes(const int32_t *__restrict__ elem,
+                                                        int64_t nelem, int64_t nv, Coords X,
+                                                        int32_t *cnt, StatusBlock *st) {
+  __shared__ int32_t hk[AGG_HT], hc[AGG_HT];
+  for (int i = threadIdx.x; i < AGG_HT; i += AGG_TB) {
+    hk[i] = -1;
+    hc[i] = 0;
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * AGG_TB * AGG_EPT + threadIdx.x;
+#pragma unroll 1
+  for (int k = 0; k < AGG_EPT; ++k) {
+    const int64_t e = base + (int64_t)k * AGG_TB;
+    if (e >= nelem) break;
+    int32_t v[D + 1];
+    load_conn<D>(elem, e, v);
+    if (!conn_valid<D>(v, nv)) {
+      raise_status(st, EB_ERANGE, e);
+      continue;
+    }
+    V3 P[D + 1];
 #pragma unroll
-  for (int i = 0; i <= D; ++i) {
-    int32_t pos = atomicSub(&cur[v[i]], 1) - 1;
-    node_inc[pos] = (int32_t)(e * (D + 1) + i);
+    for (int i = 0; i <= D; ++i) P[i] = load_pt<D>(X, v[i]);
+    double det;
+    if constexpr (D == 3)
+      det = dot(P[1] - P[0], cross(P[2] - P[0], P[3] - P[0]));
+    else
+      det = (P[1].x - P[0].x) * (P[2].y - P[0].y) - (P[1].y - P[0].y) * (P[2].x - P[0].x);
+    if (det == 0.0) raise_status(st, EB_EDEGENERATE, e);
+#pragma unroll
+    for (int i = 0; i <= D; ++i) {
+      const int h = agg_slot(hk, v[i]);
+      if (h >= 0) atomicAdd(&hc[h], 1);
+      else atomicAdd(&cnt[v[i]], 1);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < AGG_HT; i += AGG_TB)
+    if (hk[i] >= 0) atomicAdd(&cnt[hk[i]], hc[i]);
+}
+
+// cur holds inclusive (end) offsets; each block takes its nodes' ranges off
+// their ends, so cur ends as the exclusive (start) offsets.  The order inside
+// a row depends on scheduling; the rows are sorted afterwards.
+template <int D>
+__device__ __forceinline__ int4 inc_entry(const int32_t (&v)[D + 1], int l, int64_t e) {
+  int32_t o[D];
+  others_of<D>(v, l, o);
+  return make_int4((int32_t)(e * (D + 1) + l), o[0], o[1], D == 3 ? o[D - 1] : 0);
+}
+
+template <int D>
+__global__ __launch_bounds__(AGG_TB) void k_scatter_nodes(const int32_t *__restrict__ elem,
+                                                          int64_t nelem, int64_t nv, int32_t *cur,
+                                                          int4 *rows4) {
+  __shared__ int32_t hk[AGG_HT], hc[AGG_HT];
+  for (int i = threadIdx.x; i < AGG_HT; i += AGG_TB) {
+    hk[i] = -1;
+    hc[i] = 0;
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * AGG_TB * AGG_EPT + threadIdx.x;
+  int32_t slot[AGG_EPT][D + 1], rank[AGG_EPT][D + 1];
+  int32_t v[AGG_EPT][D + 1];
+#pragma unroll
+  for (int k = 0; k < AGG_EPT; ++k) {
+    const int64_t e = base + (int64_t)k * AGG_TB;
+    bool ok = e < nelem;
+    if (ok) {
+      load_conn<D>(elem, e, v[k]);
+      ok = conn_valid<D>(v[k], nv);
+    }
+#pragma unroll
+    for (int i = 0; i <= D; ++i) {
+      slot[k][i] = -1;
+      if (!ok) continue;
+      const int h = agg_slot(hk, v[k][i]);
+      if (h >= 0) {
+        slot[k][i] = h;
+        rank[k][i] = atomicAdd(&hc[h], 1);
+      } else {
+        const int32_t pos = atomicSub(&cur[v[k][i]], 1) - 1;
+        rows4[pos] = inc_entry<D>(v[k], i, e);
+      }
+    }
+  }
+  __syncthreads();
+  // one range per (block, node): hc becomes the range's first position
+  for (int i = threadIdx.x; i < AGG_HT; i += AGG_TB)
+    if (hk[i] >= 0) {
+      const int32_t c = hc[i];
+      hc[i] = atomicSub(&cur[hk[i]], c) - c;
+    }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < AGG_EPT; ++k) {
+    const int64_t e = base + (int64_t)k * AGG_TB;
+#pragma unroll
+    for (int i = 0; i <= D; ++i)
+      if (slot[k][i] >= 0) rows4[hc[slot[k][i]] + rank[k][i]] = inc_entry<D>(v[k], i, e);
   }
 }
 
@@ -98,7 +190,9 @@ struct TopoArgs {
   int64_t nv;
   const int32_t *elem;
   Coords X;
-  const int32_t *node_inc_off, *node_inc;
+  const int32_t *node_inc_off;
+  int32_t *node_inc;     // written (sorted) by the emit pass
+  const int32_t *rows4;  // workspace: Inc4 per incidence, rows of node_inc_off
   // count pass (workspace)
   int32_t *outdeg, *fmin, *bflag, *bfn, *ein;
   // emit pass
@@ -109,56 +203,131 @@ struct TopoArgs {
   int32_t *bf_cur, *bnode_face;
   const int32_t *node_sell_off;
   uint64_t *node_sell;
-  int32_t *inc_sell;  // optional inverse of the sliced layout
   int sell_wide;
   int32_t *queue;  // nodes beyond the fast kernel's capacities
   StatusBlock *st;
 };
 
-// slot of head k in the thread's sorted head column (k must be present)
-template <int TBK>
-__device__ __forceinline__ int head_slot(const int32_t (*hs)[TBK], int t, int nh, int32_t k) {
-  int s = 0;
-  while (s < nh - 1 && hs[s][t] != k) ++s;
-  return s;
+// A node's distinct neighbours, ascending.  The fast kernel keeps them in
+// registers (a fixed-size sorted array updated with predicated moves, no
+// indexed access); the queued kernel in LDS, one column per thread.
+template <int NR>
+struct RegSet {
+  static constexpr int CAP = NR;
+  int32_t a[NR];
+  __device__ __forceinline__ RegSet() {
+#pragma unroll
+    for (int s = 0; s < NR; ++s) a[s] = INT32_MAX;
+  }
+  // false when full (k not already present)
+  __device__ __forceinline__ bool insert(int32_t k) {
+    bool dup = false;
+#pragma unroll
+    for (int s = 0; s < NR; ++s) dup = dup || a[s] == k;
+    if (dup) return true;
+    if (a[NR - 1] != INT32_MAX) return false;
+#pragma unroll
+    for (int s = NR - 1; s > 0; --s) a[s] = a[s] < k ? a[s] : (a[s - 1] < k ? k : a[s - 1]);
+    a[0] = a[0] < k ? a[0] : k;
+    return true;
+  }
+  // entries below k (the slot of k when present)
+  __device__ __forceinline__ int rank(int32_t k) const {
+    int r = 0;
+#pragma unroll
+    for (int s = 0; s < NR; ++s) r += a[s] < k ? 1 : 0;
+    return r;
+  }
+  __device__ __forceinline__ int size() const { return rank(INT32_MAX); }
+  __device__ __forceinline__ int32_t at(int i) const {
+    int32_t r = 0;
+#pragma unroll
+    for (int s = 0; s < NR; ++s) r = s == i ? a[s] : r;
+    return r;
+  }
+  template <class F> __device__ __forceinline__ void each(int lo, int hi, F f) const {
+#pragma unroll
+    for (int s = 0; s < NR; ++s)
+      if (s >= lo && s < hi) f(s, a[s]);
+  }
+};
+
+template <int TBK, int NR>
+struct LdsSet {
+  static constexpr int CAP = NR;
+  int32_t (*hs)[TBK];
+  int t, n;
+  __device__ __forceinline__ LdsSet(int32_t (*h)[TBK], int t_) : hs(h), t(t_), n(0) {}
+  __device__ __forceinline__ bool insert(int32_t k) {
+    int pos = 0;
+    while (pos < n && hs[pos][t] < k) ++pos;
+    if (pos < n && hs[pos][t] == k) return true;
+    if (n == NR) return false;
+    for (int s = n; s > pos; --s) hs[s][t] = hs[s - 1][t];
+    hs[pos][t] = k;
+    ++n;
+    return true;
+  }
+  __device__ __forceinline__ int rank(int32_t k) const {
+    int r = 0;
+    while (r < n && hs[r][t] < k) ++r;
+    return r;
+  }
+  __device__ __forceinline__ int size() const { return n; }
+  __device__ __forceinline__ int32_t at(int i) const { return hs[i][t]; }
+  template <class F> __device__ __forceinline__ void each(int lo, int hi, F f) const {
+    for (int s = lo; s < hi; ++s) f(s, hs[s][t]);
+  }
+};
+
+// One incidence as the scatter pass stores it in the workspace: the
+// incidence elem*(D+1)+local and the element's other vertices o_m (o_m =
+// elem[m] for m < D, except that j's own place is taken by elem[D]); rows are
+// in scheduling order until the emit pass ranks them.
+struct Inc4 {
+  int32_t inc, o0, o1, o2;
+};
+
+template <int D>
+__device__ __forceinline__ void inc_others(const int4 &q, int32_t (&o)[D]) {
+  o[0] = q.y;
+  o[1] = q.z;
+  if constexpr (D == 3) o[2] = q.w;
 }
 
-template <int D, bool EMIT, int TBK, int MH, int MF, bool SLOW>
-__device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, int32_t (*hs)[TBK],
-                               uint16_t (*fc)[TBK]) {
+// Per node j: 1. its distinct neighbours and candidate faces; 2. (emit)
+// its sorted node_inc row and sliced entries; 3. face multiplicities;
+// 4. (emit) its boundary faces.  RC is the longest row the fast kernel ranks
+// in LDS (ri); the queued kernel ranks from global memory.
+template <int D, bool EMIT, int TBK, class Set, int MF, int RC, bool SLOW>
+__device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
+                               uint16_t (*fc)[TBK], int32_t (*ri)[TBK]) {
+  constexpr int MH = Set::CAP;
   const int32_t r0 = a.node_inc_off[j], r1 = a.node_inc_off[j + 1];
+  const int4 *__restrict__ row = reinterpret_cast<const int4 *>(a.rows4) + r0;
+  const int32_t len = r1 - r0;
 
-  // 1. distinct higher-numbered neighbours, ascending, and the number of
+  // 1. distinct neighbours (lower and higher), ascending, and the number of
   //    candidate faces with j as smallest vertex; nothing is written before
   //    both are known to fit (a node beyond the capacities is queued whole).
+  //    The neighbours below j are j's in-edges, those above its out-edges.
   //    The count pass also notes the largest |neighbour - j| (sliced-ELL
   //    format).
-  int nh = 0, nfc = 0;
-  bool overflow = false;
+  int nfc = 0;
+  bool overflow = !SLOW && len > RC;
   int32_t maxdelta = 0;
-  for (int32_t r = r0; r < r1; ++r) {
-    const int32_t inc = a.node_inc[r];
-    const int64_t e = inc / (D + 1);
-    const int l = inc - (int)(e * (D + 1));
-    int32_t v[D + 1];
-    load_conn<D>(a.elem, e, v);
+  for (int32_t i = 0; i < len && !overflow; ++i) {
+    const int4 q = row[i];
+    if (EMIT && !SLOW) ri[i][t] = q.x;
+    int32_t o[D];
+    inc_others<D>(q, o);
     int higher = 0;
 #pragma unroll
-    for (int q = 0; q <= D; ++q) {
-      const int32_t k = v[q];
+    for (int m = 0; m < D; ++m) {
+      const int32_t k = o[m];
       if (!EMIT) maxdelta = max(maxdelta, k > j ? k - j : j - k);
-      if (q == l || k <= j) continue;
-      ++higher;
-      int pos = 0;
-      while (pos < nh && hs[pos][t] < k) ++pos;
-      if (pos < nh && hs[pos][t] == k) continue;
-      if (nh == MH) {
-        overflow = true;
-        continue;
-      }
-      for (int s = nh; s > pos; --s) hs[s][t] = hs[s - 1][t];
-      hs[pos][t] = k;
-      ++nh;
+      if (k > j) ++higher;
+      if (!hs.insert(k)) overflow = true;
     }
     nfc += D == 3 ? higher * (higher - 1) / 2 : higher;
   }
@@ -166,52 +335,63 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, int32_t (*hs
     if constexpr (SLOW) {
       raise_status(a.st, EB_ECAPACITY, j);
     } else if constexpr (!EMIT) {
-      const int32_t q = atomicAdd(&a.st->totals[T_QUEUE], 1);
-      a.queue[q] = j;
+      const int32_t qi = atomicAdd(&a.st->totals[T_QUEUE], 1);
+      a.queue[qi] = j;
     }
     return;
   }
+  const int nh = hs.size();
+  const int nlow = hs.rank(j);  // neighbours below j come first
+  const int nout = nh - nlow;
   if constexpr (!EMIT) {
-    a.outdeg[j] = nh;
-    for (int s = 0; s < nh; ++s) atomicAdd(&a.ein[hs[s][t]], 1);
+    a.outdeg[j] = nout;
+    a.ein[j] = nlow;
     // only whether some neighbour lies beyond int16 range, or some node has
     // more than 31 out-edges, matters (either selects the wide format)
     if (maxdelta > 32767) atomicMax(&a.st->totals[T_MAXDELTA], maxdelta);
-    if (nh > 31) atomicMax(&a.st->totals[T_MAXOUT], nh);
+    if (nout > 31) atomicMax(&a.st->totals[T_MAXOUT], nout);
   } else {
-    const int32_t e0 = a.eoff[j];
-    for (int s = 0; s < nh; ++s) {
-      const int32_t k = hs[s][t];
+    const int32_t e0 = a.eoff[j] - nlow;
+    hs.each(nlow, nh, [&](int s, int32_t k) {
       a.edge_tail[e0 + s] = j;
       a.edge_head[e0 + s] = k;
-      const int32_t pos = atomicSub(&a.in_cur[k], 1) - 1;
-      a.node_in_edge[pos] = e0 + s;
-    }
+    });
+    // in-edges: the lower neighbours, ascending (= ascending edge id); their
+    // ids are filled in once every tail's edges exist (k_node_in_ids)
+    const int32_t i0 = a.in_cur[j] - nlow;
+    hs.each(0, nlow, [&](int s, int32_t k) { a.node_in_edge[i0 + s] = k; });
+    a.in_cur[j] = i0;
   }
 
-  // 2. out-edge slot of each other vertex of every element of j (emitted as
-  //    in node_sell) and the candidate faces with j as smallest vertex,
-  //    coded by the slots of their two other vertices
+  // 2. slot of each other vertex of every element of j in j's neighbour list
+  //    (its out-edge slot is that minus nlow); the emit pass writes the row in
+  //    ascending incidence order (rank = number of smaller incidences) and
+  //    the sliced entry at that rank; both passes note the candidate faces
+  //    with j as smallest vertex, coded by their two other vertices' slots
   int nf = 0;
-  for (int32_t r = r0; r < r1; ++r) {
-    const int32_t inc = a.node_inc[r];
-    const int64_t e = inc / (D + 1);
-    const int l = inc - (int)(e * (D + 1));
-    int32_t v[D + 1], o[D];
-    load_conn<D>(a.elem, e, v);
-    others_of<D>(v, l, o);
-    // slot of each other vertex among j's out-edges, -1 below j
-    const int s0 = o[0] > j ? head_slot<TBK>(hs, t, nh, o[0]) : -1;
-    const int s1 = o[1] > j ? head_slot<TBK>(hs, t, nh, o[1]) : -1;
+  const int64_t sbase = (int64_t)a.node_sell_off[j / SELL] + (j % SELL);
+  for (int32_t i = 0; i < len; ++i) {
+    const int4 q = row[i];
+    int32_t o[D];
+    inc_others<D>(q, o);
+    const int s0 = o[0] > j ? hs.rank(o[0]) : -1;
+    const int s1 = o[1] > j ? hs.rank(o[1]) : -1;
     int s2 = -1;
-    if constexpr (D == 3) s2 = o[2] > j ? head_slot<TBK>(hs, t, nh, o[2]) : -1;
+    if constexpr (D == 3) s2 = o[2] > j ? hs.rank(o[2]) : -1;
     if constexpr (EMIT) {
+      int32_t rank = 0;
+      if constexpr (SLOW) {
+        for (int32_t i2 = 0; i2 < len; ++i2) rank += row[i2].x < q.x ? 1 : 0;
+      } else {
+        for (int32_t i2 = 0; i2 < len; ++i2) rank += ri[i2][t] < q.x ? 1 : 0;
+      }
+      a.node_inc[r0 + rank] = q.x;
       const int B = a.sell_wide ? 10 : 5;
       const int none = (1 << B) - 1;
-      const uint64_t code = (uint64_t)((s0 < 0 ? none : s0) | ((s1 < 0 ? none : s1) << B) |
-                                       (D == 3 ? (s2 < 0 ? none : s2) << (2 * B) : 0));
-      const int64_t pos = (int64_t)a.node_sell_off[j / SELL] + (int64_t)SELL * (r - r0) + (j % SELL);
-      if (a.inc_sell) a.inc_sell[inc] = (int32_t)pos;
+      const int u0 = s0 < 0 ? none : s0 - nlow, u1 = s1 < 0 ? none : s1 - nlow;
+      const int u2 = s2 < 0 ? none : s2 - nlow;
+      const uint64_t code = (uint64_t)(u0 | (u1 << B) | (D == 3 ? u2 << (2 * B) : 0));
+      const int64_t pos = sbase + (int64_t)SELL * rank;
       if (!a.sell_wide) {
         uint64_t w = code << 48;
 #pragma unroll
@@ -222,9 +402,9 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, int32_t (*hs
         a.node_sell[2 * pos + 1] = (uint64_t)(uint32_t)(D == 3 ? o[D - 1] : 0) | (code << 32);
       }
     }
-    auto add_face = [&](int p, int q) {
-      if (p < 0 || q < 0) return;
-      const int lo = p < q ? p : q, hi = p < q ? q : p;
+    auto add_face = [&](int p, int qq) {
+      if (p < 0 || qq < 0) return;
+      const int lo = p < qq ? p : qq, hi = p < qq ? qq : p;
       fc[nf++][t] = (uint16_t)(lo * MH + hi);
     };
     if constexpr (D == 3) {
@@ -239,8 +419,8 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, int32_t (*hs
   if constexpr (EMIT) {  // zero the slice entries past j's row
     const int32_t sl0 = a.node_sell_off[j / SELL], sl1 = a.node_sell_off[j / SELL + 1];
     const int32_t slen = (sl1 - sl0) / SELL;
-    for (int32_t rl = r1 - r0; rl < slen; ++rl) {
-      const int64_t pos = (int64_t)sl0 + (int64_t)SELL * rl + (j % SELL);
+    for (int32_t rl = len; rl < slen; ++rl) {
+      const int64_t pos = sbase + (int64_t)SELL * rl;
       if (!a.sell_wide) {
         a.node_sell[pos] = 0;
       } else {
@@ -273,10 +453,10 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, int32_t (*hs
       int32_t fv[D];
       fv[0] = j;
       if constexpr (D == 3) {
-        fv[1] = hs[(c & 0x7fff) / MH][t];
-        fv[2] = hs[(c & 0x7fff) % MH][t];
+        fv[1] = hs.at((c & 0x7fff) / MH);
+        fv[2] = hs.at((c & 0x7fff) % MH);
       } else {
-        fv[1] = hs[c & 0x7fff][t];
+        fv[1] = hs.at(c & 0x7fff);
       }
 #pragma unroll
       for (int s = 0; s < D; ++s) {
@@ -300,39 +480,43 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, int32_t (*hs
       int32_t fv[D];
       fv[0] = j;
       if constexpr (D == 3) {
-        fv[1] = hs[best / MH][t];
-        fv[2] = hs[best % MH][t];
+        fv[1] = hs.at(best / MH);
+        fv[2] = hs.at(best % MH);
       } else {
-        fv[1] = hs[best][t];
+        fv[1] = hs.at(best);
       }
-      // owner: the one element of j holding the face; opposite = its other vertex
+      // owner: the one element of j holding the face; opposite = its vertex
+      // off the face
       int64_t own = -1;
-      int opp = -1;
       int32_t vo = -1;
-      for (int32_t r = r0; r < r1 && own < 0; ++r) {
-        const int32_t inc = a.node_inc[r];
-        const int64_t e = inc / (D + 1);
-        int32_t v[D + 1];
-        load_conn<D>(a.elem, e, v);
-        int hit = 0, o = -1;
+      for (int32_t i = 0; i < len && own < 0; ++i) {
+        const int4 q = row[i];
+        int32_t o[D];
+        inc_others<D>(q, o);
+        int hit = 0;
+        int32_t off = -1;
 #pragma unroll
-        for (int q = 0; q <= D; ++q) {
+        for (int m = 0; m < D; ++m) {
           bool in = false;
 #pragma unroll
-          for (int s = 0; s < D; ++s) in = in || v[q] == fv[s];
+          for (int s = 1; s < D; ++s) in = in || o[m] == fv[s];
           if (in) ++hit;
-          else o = q;
+          else off = o[m];
         }
-        if (hit == D) {
-          own = e;
-          opp = o;
-          vo = v[o];
+        if (hit == D - 1) {
+          own = q.x / (D + 1);
+          vo = off;
         }
       }
-      if (own < 0) {  // cannot happen for a consistent node_inc
+      if (own < 0) {  // cannot happen for a consistent build
         raise_status(a.st, EB_EINVAL, j);
         return;
       }
+      int32_t v[D + 1];
+      load_conn<D>(a.elem, own, v);
+      int opp = 0;
+#pragma unroll
+      for (int qq = 0; qq <= D; ++qq) opp = v[qq] == vo ? qq : opp;
       // outward orientation: the expression, operand order and FP64 rounding
       // of the definition in eb.h (v0 = smallest id), without contraction
       {
@@ -341,19 +525,19 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, int32_t (*hs
         const V3 Xo = load_pt<D>(a.X, vo);
         if constexpr (D == 3) {
           const V3 C = load_pt<D>(a.X, fv[2]);
-          const V3 u = B - A, v = C - A, w = A - Xo;
-          const double cx = u.y * v.z - u.z * v.y;
-          const double cy = u.z * v.x - u.x * v.z;
-          const double cz = u.x * v.y - u.y * v.x;
-          const double s = cx * w.x + cy * w.y + cz * w.z;
-          const bool keep = s > 0;
+          const V3 u = B - A, w2 = C - A, w = A - Xo;
+          const double cx = u.y * w2.z - u.z * w2.y;
+          const double cy = u.z * w2.x - u.x * w2.z;
+          const double cz = u.x * w2.y - u.y * w2.x;
+          const double sg = cx * w.x + cy * w.y + cz * w.z;
+          const bool keep = sg > 0;
           a.bface[(int64_t)f * 3 + 0] = fv[0];
           a.bface[(int64_t)f * 3 + 1] = keep ? fv[1] : fv[2];
           a.bface[(int64_t)f * 3 + 2] = keep ? fv[2] : fv[1];
         } else {
           const V3 d = B - A, w = A - Xo;
-          const double s = d.y * w.x - d.x * w.y;
-          const bool keep = s > 0;
+          const double sg = d.y * w.x - d.x * w.y;
+          const bool keep = sg > 0;
           a.bface[(int64_t)f * 2 + 0] = keep ? fv[0] : fv[1];
           a.bface[(int64_t)f * 2 + 1] = keep ? fv[1] : fv[0];
         }
@@ -371,8 +555,8 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, int32_t (*hs
 
 template <int D, bool EMIT>
 __global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
-  __shared__ int32_t hs[MAXH][TB];
   __shared__ uint16_t fc[MAXF][TB];
+  __shared__ int32_t ri[EMIT ? MAXR : 1][TB];
   const int t = threadIdx.x;
   const int64_t j64 = (int64_t)blockIdx.x * TB + t;
   if (build_failed(a.st)) return;
@@ -388,7 +572,8 @@ __global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
     }
     return;
   }
-  node_topo_body<D, EMIT, TB, MAXH, MAXF, false>(a, (int32_t)j64, t, hs, fc);
+  RegSet<MAXH> hs;
+  node_topo_body<D, EMIT, TB, RegSet<MAXH>, MAXF, MAXR, false>(a, (int32_t)j64, t, hs, fc, ri);
 }
 
 // the queued nodes, with the large capacities
@@ -398,8 +583,13 @@ __global__ __launch_bounds__(TBS) void k_node_topo_queued(TopoArgs a) {
   __shared__ uint16_t fc[MAXF_S][TBS];
   if (build_failed(a.st)) return;
   const int32_t n = *reinterpret_cast<const volatile int32_t *>(&a.st->totals[T_QUEUE]);
-  for (int64_t i = (int64_t)blockIdx.x * TBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * TBS)
-    node_topo_body<D, EMIT, TBS, MAXH_S, MAXF_S, true>(a, a.queue[i], threadIdx.x, hs, fc);
+  for (int64_t i = (int64_t)blockIdx.x * TBS + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * TBS) {
+    LdsSet<TBS, MAXH_S> set(hs, threadIdx.x);
+    node_topo_body<D, EMIT, TBS, LdsSet<TBS, MAXH_S>, MAXF_S, 0, true>(a, a.queue[i],
+                                                                         threadIdx.x, set, fc,
+                                                                         nullptr);
+  }
 }
 
 // longest node_inc row of every 64-node slice
@@ -464,25 +654,90 @@ __device__ __forceinline__ int32_t find_edge(const int32_t *__restrict__ node_ed
   return (lo < node_edge_off[t + 1] && head[lo] == h) ? lo : -1;
 }
 
-template <int D>
-__global__ void k_elem_edge(const int32_t *__restrict__ elem, int64_t nelem,
-                            const int32_t *__restrict__ node_edge_off,
-                            const int32_t *__restrict__ head, int32_t *elem_edge,
-                            int8_t *elem_edge_sign, int32_t *edge_cnt, StatusBlock *st) {
+// node_in_edge holds each node's lower neighbours, ascending; replace each
+// by the id of the edge (neighbour, node)
+__global__ void k_node_in_ids(int64_t nv, const int32_t *__restrict__ node_in_off,
+                              const int32_t *__restrict__ node_edge_off,
+                              const int32_t *__restrict__ head, int32_t *node_in_edge,
+                              StatusBlock *st) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nv || build_failed(st)) return;
+  for (int32_t r = node_in_off[j]; r < node_in_off[j + 1]; ++r) {
+    const int32_t id = find_edge(node_edge_off, head, node_in_edge[r], (int32_t)j);
+    if (id < 0) raise_status(st, EB_EINVAL, j);  // cannot happen for a consistent build
+    node_in_edge[r] = id;
+  }
+}
+
+// local edge index of the local vertex pair (p, q), p < q
+template <int D> __host__ __device__ constexpr int pair_index(int p, int q) {
+  return D == 3 ? (p == 0 ? q - 1 : (p == 1 ? q + 1 : 5)) : p + q - 1;
+}
+
+// Per element, once the sorted rows and the sliced entries exist: the sliced
+// position of each incidence (binary search for it in its vertex's node_inc
+// row) -> inc_sell; the out-edge slots of that entry -> the ids of the local
+// edges whose tail is that vertex; signs from the vertex order.  All writes
+// are per element, contiguous across threads.
+template <int D, bool WIDE>
+__global__ void k_elem_maps(const int32_t *__restrict__ elem, int64_t nelem,
+                            const int32_t *__restrict__ node_inc_off,
+                            const int32_t *__restrict__ node_inc,
+                            const int32_t *__restrict__ node_sell_off,
+                            const uint64_t *__restrict__ node_sell,
+                            const int32_t *__restrict__ node_edge_off, int32_t *elem_edge,
+                            int8_t *elem_edge_sign, int32_t *inc_sell, const StatusBlock *st) {
+  constexpr int NE = EL<D>::NE;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nelem || build_failed(st)) return;
-  int32_t v[D + 1];
+  int32_t v[D + 1], ps[D + 1], ee[NE];
   load_conn<D>(elem, e, v);
-  constexpr int NE = EL<D>::NE;
+#pragma unroll
+  for (int le = 0; le < NE; ++le) ee[le] = -1;
+#pragma unroll
+  for (int l = 0; l <= D; ++l) {
+    const int32_t j = v[l], key = (int32_t)(e * (D + 1) + l);
+    const int32_t r0 = node_inc_off[j];
+    int32_t lo = r0, hi = node_inc_off[j + 1];
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (node_inc[mid] < key) lo = mid + 1;
+      else hi = mid;
+    }
+    const int64_t pos = (int64_t)node_sell_off[j / SELL] + (int64_t)SELL * (lo - r0) + (j % SELL);
+    ps[l] = (int32_t)pos;
+    const uint32_t code = WIDE ? (uint32_t)(node_sell[2 * pos + 1] >> 32)
+                               : (uint32_t)(node_sell[pos] >> 48) & 0x7fffu;
+    const int32_t base = node_edge_off[j];
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+      const int slot = slot_of<WIDE>(code, m);
+      const int lm = m == l ? D : m;  // local index of the m-th other vertex
+      const int le = pair_index<D>(l < lm ? l : lm, l < lm ? lm : l);
+      if (slot != no_slot<WIDE>()) ee[le] = base + slot;
+    }
+  }
 #pragma unroll
   for (int le = 0; le < NE; ++le) {
-    const int32_t p = v[pair_p<D>(le)], q = v[pair_q<D>(le)];
-    const int32_t id = find_edge(node_edge_off, head, p, q);
-    elem_edge[e * NE + le] = id;
-    elem_edge_sign[e * NE + le] = p < q ? 1 : -1;
-    if (id < 0) raise_status(st, EB_EINVAL, e);
-    else if (edge_cnt) atomicAdd(&edge_cnt[id], 1);
+    elem_edge[e * NE + le] = ee[le];
+    elem_edge_sign[e * NE + le] = (int8_t)(v[pair_p<D>(le)] < v[pair_q<D>(le)] ? 1 : -1);
   }
+  if (inc_sell) {
+    if constexpr (D == 3)
+      reinterpret_cast<int4 *>(inc_sell)[e] = make_int4(ps[0], ps[1], ps[2], ps[3]);
+    else
+#pragma unroll
+      for (int l = 0; l < 3; ++l) inc_sell[e * 3 + l] = ps[l];
+  }
+}
+
+// elements per edge, for the optional edge -> element lists
+template <int D>
+__global__ void k_edge_inc_count(int64_t nelem, const int32_t *__restrict__ elem_edge,
+                                 int32_t *cnt, const StatusBlock *st) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nelem * EL<D>::NE || build_failed(st)) return;
+  atomicAdd(&cnt[elem_edge[i]], 1);
 }
 
 template <int D>
@@ -534,19 +789,19 @@ int build_edges_impl(int64_t nv, int64_t nelem, const int32_t *elem, const doubl
 
   // node -> element lists
   if (nelem > 0) {
-    hipLaunchKernelGGL(k_count_nodes<D>, dim3(grid_for(nelem, 256)), dim3(256), 0, s, elem,
-                       nelem, nv, X, node_inc_off, st);
+    hipLaunchKernelGGL(k_count_nodes<D>, dim3(grid_for(nelem, AGG_TB * AGG_EPT)), dim3(AGG_TB),
+                       0, s, elem, nelem, nv, X, node_inc_off, st);
     EB_LAUNCH_CHECK();
   }
   // the row ends must be the scan total of what was counted: elements
   // rejected above are neither counted nor scattered
   EB_TRY(scan_inclusive(node_inc_off, node_inc_off, nv, node_inc_off + nv, tmp, s));
   if (nelem > 0) {
-    hipLaunchKernelGGL(k_scatter_nodes<D>, dim3(grid_for(nelem, 256)), dim3(256), 0, s, elem,
-                       nelem, nv, node_inc_off, node_inc);
+    hipLaunchKernelGGL(k_scatter_nodes<D>, dim3(grid_for(nelem, AGG_TB * AGG_EPT)),
+                       dim3(AGG_TB), 0, s, elem, nelem, nv, node_inc_off,
+                       ws_at<int4>(ws, L.rows4));
     EB_LAUNCH_CHECK();
   }
-  EB_TRY(rowsort(node_inc_off, node_inc, nv, s));
 
   // per-node counts of edges, boundary faces, boundary nodes
   TopoArgs ta{};
@@ -555,6 +810,7 @@ int build_edges_impl(int64_t nv, int64_t nelem, const int32_t *elem, const doubl
   ta.X = X;
   ta.node_inc_off = node_inc_off;
   ta.node_inc = node_inc;
+  ta.rows4 = ws_at<const int32_t>(ws, L.rows4);
   ta.outdeg = eoff;
   ta.fmin = foff;
   ta.bflag = bidx;
@@ -625,6 +881,7 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
   ta.X = coords_rows(coords, D, nv);
   ta.node_inc_off = tp->node_inc_off;
   ta.node_inc = tp->node_inc;
+  ta.rows4 = ws_at<const int32_t>(ws, L.rows4);
   ta.eoff = eoff;
   ta.foff = foff;
   ta.edge_tail = tp->edge;
@@ -637,7 +894,6 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
   ta.bnode_face = tp->bnode_face;
   ta.node_sell_off = tp->node_sell_off;
   ta.node_sell = tp->node_sell;
-  ta.inc_sell = tp->inc_sell;
   ta.sell_wide = sz->sell_wide;
   ta.queue = ws_at<int32_t>(ws, L.queue);
   ta.st = st;
@@ -645,17 +901,37 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
   EB_LAUNCH_CHECK();
   hipLaunchKernelGGL((k_node_topo_queued<D, true>), dim3(256), dim3(TBS), 0, s, ta);
   EB_LAUNCH_CHECK();
-  EB_TRY(rowsort(tp->node_in_off, tp->node_in_edge, nv, s));
+  if (sz->n_edges > 0) {
+    hipLaunchKernelGGL(k_node_in_ids, dim3(grid_for(nv, 256)), dim3(256), 0, s, nv,
+                       (const int32_t *)tp->node_in_off, (const int32_t *)tp->node_edge_off,
+                       (const int32_t *)(tp->edge + sz->n_edges), tp->node_in_edge, st);
+    EB_LAUNCH_CHECK();
+  }
   EB_TRY(rowsort(tp->bnode_face_off, tp->bnode_face, sz->n_bnodes, s));
+  if (nelem > 0) {
+    if (sz->sell_wide)
+      hipLaunchKernelGGL((k_elem_maps<D, true>), dim3(grid_for(nelem, 256)), dim3(256), 0, s,
+                         elem, nelem, (const int32_t *)tp->node_inc_off,
+                         (const int32_t *)tp->node_inc, (const int32_t *)tp->node_sell_off,
+                         (const uint64_t *)tp->node_sell, (const int32_t *)tp->node_edge_off,
+                         tp->elem_edge, tp->elem_edge_sign, tp->inc_sell, (const StatusBlock *)st);
+    else
+      hipLaunchKernelGGL((k_elem_maps<D, false>), dim3(grid_for(nelem, 256)), dim3(256), 0, s,
+                         elem, nelem, (const int32_t *)tp->node_inc_off,
+                         (const int32_t *)tp->node_inc, (const int32_t *)tp->node_sell_off,
+                         (const uint64_t *)tp->node_sell, (const int32_t *)tp->node_edge_off,
+                         tp->elem_edge, tp->elem_edge_sign, tp->inc_sell, (const StatusBlock *)st);
+    EB_LAUNCH_CHECK();
+  }
 
   const bool want_inc = tp->edge_inc_off && tp->edge_inc;
-  if (want_inc) EB_TRY(fill_i32(tp->edge_inc_off, sz->n_edges + 1, 0, s));
-  if (nelem > 0) {
-    hipLaunchKernelGGL(k_elem_edge<D>, dim3(grid_for(nelem, 256)), dim3(256), 0, s, elem,
-                       nelem, (const int32_t *)tp->node_edge_off,
-                       (const int32_t *)(tp->edge + sz->n_edges), tp->elem_edge,
-                       tp->elem_edge_sign, want_inc ? tp->edge_inc_off : nullptr, st);
-    EB_LAUNCH_CHECK();
+  if (want_inc) {
+    EB_TRY(fill_i32(tp->edge_inc_off, sz->n_edges + 1, 0, s));
+    if (nelem > 0) {
+      hipLaunchKernelGGL(k_edge_inc_count<D>, dim3(grid_for(nelem * NE, 256)), dim3(256), 0, s,
+                         nelem, (const int32_t *)tp->elem_edge, tp->edge_inc_off, st);
+      EB_LAUNCH_CHECK();
+    }
   }
   if (sz->n_bfaces > 0) {
     hipLaunchKernelGGL(k_bface_edge<D>, dim3(grid_for(sz->n_bfaces, 256)), dim3(256), 0, s,
@@ -734,6 +1010,10 @@ int eb_build_edges_emit(const eb_sizes *sizes, const int32_t *elem, const double
       (has_f && (!t.bface || !t.bface_owner || !t.bface_edge)) ||
       (has_bn && (!t.bnode || !t.bnode_face))) {
     set_detail("a required topology array is null");
+    return EB_EINVAL;
+  }
+  if (!aligned16(t.inc_sell)) {
+    set_detail("inc_sell must be 16-byte aligned");
     return EB_EINVAL;
   }
   if ((t.edge_inc_off == nullptr) != (t.edge_inc == nullptr)) {
