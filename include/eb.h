@@ -224,8 +224,9 @@ int eb_directed_areas(const eb_sizes *sizes, const eb_topology *topo, const int3
  *   EB_VOL_EDGE: the edge loop V_j = (1/(2D)) sum_k (x_k - x_j).n_jk over the
  *     edges of j (Section 4.1), from the boundary-corrected n_edge
  *     [dim][n_edges] of eb_directed_areas.  ATOMIC: thread per edge, FP64
- *     atomics to both ends; GATHER: thread per node over node_edge_off and
- *     node_in rows. */
+ *     atomics to both ends; GATHER: each edge's term once into ws, then one
+ *     thread per node sums its out-edges (node_edge_off) and in-edges
+ *     (node_in rows) in that order. */
 int eb_dual_volumes(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
                     const double *coords, int mode, const double *n_edge, int reduce,
                     double *vol, void *ws, size_t ws_bytes, hipStream_t stream);

@@ -181,8 +181,12 @@ int eb_dual_volumes(const eb_sizes *sizes, const eb_topology *topo, const int32_
       return EB_EINVAL;
     }
     EB_TRY(need(a.edge_tail && a.edge_head, "edge"));
-    if (reduce == EB_REDUCE_GATHER)
+    if (reduce == EB_REDUCE_GATHER) {
       EB_TRY(need(a.node_edge_off && a.node_in_off && a.node_in_edge, "node_edge_off, node_in"));
+      // per-edge terms in the workspace's incidence-row region (8 bytes per
+      // edge fit: it holds 16 (dim+1) bytes per element)
+      a.vterm = ws_at<double>(ws, ws_layout(sizes->dim, sizes->n_nodes, sizes->n_elems).rows4);
+    }
   } else if (reduce == EB_REDUCE_GATHER) {
     EB_TRY(need(a.node_inc_off && a.node_inc, "node_inc"));
   }

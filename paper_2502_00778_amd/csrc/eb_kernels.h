@@ -31,6 +31,7 @@ struct FwdArgs {
   const double *c;                   // dL/dV
   double *g_x, *g_y, *g_z;           // dL/dx rows
   double *gpiece;  // workspace: per-incidence gradient pieces at node_sell positions
+  double *vterm;   // workspace: per-edge terms of the edge loop
   StatusBlock *st;
   int xcd_remap;
 };

@@ -140,24 +140,27 @@ __global__ __launch_bounds__(256) void k_vol_edge_atomic(FwdArgs a, const double
   unsafeAtomicAdd(&a.vol[k], s);
 }
 
+// Edge loop in two passes: each edge's term t_e = (x_k - x_j).n_jk / (2D)
+// once (coalesced over edges), then each node sums the terms of its out-edges
+// (a contiguous range) and in-edges (node_in order): fixed order, no atomics.
 template <int D>
-__global__ __launch_bounds__(256) void k_vol_edge_gather(FwdArgs a, const double *__restrict__ nx,
-                                                         const double *__restrict__ ny,
-                                                         const double *__restrict__ nz) {
+__global__ __launch_bounds__(256) void k_vol_edge_terms(FwdArgs a, const double *__restrict__ nx,
+                                                        const double *__restrict__ ny,
+                                                        const double *__restrict__ nz,
+                                                        double *__restrict__ term) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nedge) return;
+  const V3 d = load_pt<D>(a.X, a.edge_head[e]) - load_pt<D>(a.X, a.edge_tail[e]);
+  term[e] = (d.x * nx[e] + d.y * ny[e] + (D == 3 ? d.z * nz[e] : 0.0)) * (1.0 / (2 * D));
+}
+
+__global__ __launch_bounds__(256) void k_vol_edge_sum(FwdArgs a, const double *__restrict__ term) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.nv) return;
-  const V3 xj = load_pt<D>(a.X, (int32_t)j);
   double s = 0.0;
-  for (int32_t e = a.node_edge_off[j]; e < a.node_edge_off[j + 1]; ++e) {
-    const V3 d = load_pt<D>(a.X, a.edge_head[e]) - xj;
-    s += d.x * nx[e] + d.y * ny[e] + (D == 3 ? d.z * nz[e] : 0.0);
-  }
-  for (int32_t r = a.node_in_off[j]; r < a.node_in_off[j + 1]; ++r) {
-    const int32_t e = a.node_in_edge[r];
-    const V3 d = xj - load_pt<D>(a.X, a.edge_tail[e]);
-    s += d.x * nx[e] + d.y * ny[e] + (D == 3 ? d.z * nz[e] : 0.0);
-  }
-  a.vol[j] = s * (1.0 / (2 * D));
+  for (int32_t e = a.node_edge_off[j]; e < a.node_edge_off[j + 1]; ++e) s += term[e];
+  for (int32_t r = a.node_in_off[j]; r < a.node_in_off[j + 1]; ++r) s += term[a.node_in_edge[r]];
+  a.vol[j] = s;
 }
 
 // ------------------------------------------------------------- launchers
@@ -261,8 +264,17 @@ int volumes_impl(const FwdArgs &a, int mode, int reduce, const double *n_edge, h
     }
     return EB_OK;
   }
-  launch_principal(k_vol_edge_gather<D>, dim3(grid_for(a.nv, 256)), dim3(256), 0, s, a, nx,
-                     ny, nz);
+  if (!a.vterm) {
+    set_detail("the gather edge loop needs the workspace's term buffer");
+    return EB_EINVAL;
+  }
+  if (a.nedge > 0) {
+    launch_principal(k_vol_edge_terms<D>, dim3(grid_for(a.nedge, 256)), dim3(256), 0, s, a, nx,
+                     ny, nz, a.vterm);
+    EB_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_vol_edge_sum, dim3(grid_for(a.nv, 256)), dim3(256), 0, s, a,
+                     (const double *)a.vterm);
   EB_LAUNCH_CHECK();
   return EB_OK;
 }
