@@ -84,6 +84,7 @@ typedef enum {
 
 typedef enum { EB_REDUCE_ATOMIC = 0, EB_REDUCE_GATHER = 1 } eb_reduce;
 typedef enum { EB_VOL_ELEMENT = 0, EB_VOL_EDGE = 1 } eb_vol_mode;
+typedef enum { EB_BFLUX_NODE = 0, EB_BFLUX_LINEAR = 1 } eb_bflux;
 
 /* Sizes of one grid; filled by eb_build_edges.  n_sell counts the entries
  * of node_sell (padding included); sell_wide selects its entry format. */
@@ -230,6 +231,26 @@ int eb_directed_areas(const eb_sizes *sizes, const eb_topology *topo, const int3
 int eb_dual_volumes(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
                     const double *coords, int mode, const double *n_edge, int reduce,
                     double *vol, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Edge-loop residual, the consumer of the metrics (the edge-based
+ * discretization of Section 2): given nodal flux values flux [dim][n_nodes]
+ * (F_j), res [n_nodes] (overwritten) = sum over the edges (j,k) of node j of
+ * +-(F_j + F_k)/2 . n_jk (+ at the tail, - at the head) plus the boundary
+ * flux of j:
+ *   EB_BFLUX_NODE    F_j . b_j (b_node [dim][n_bnodes] required);
+ *   EB_BFLUX_LINEAR  per boundary face B of j, n_B/dim . (weighted F of B's
+ *                    nodes: 2D 5/6 own + 1/6 other, 3D 6/8 own + 1/8 each
+ *                    other), computed from coords; with the lumped n of
+ *                    eb_directed_areas this makes res_j = (div F) V_j exactly
+ *                    for every linear F, at every node.
+ * Constant F gives res = 0 (closure).  Two passes like the edge loop (edge
+ * terms into ws, ordered node sums), then the boundary nodes; bitwise
+ * reproducible.  Needs edge, node_edge_off, node_in_off/node_in_edge, bnode
+ * (and bnode_face, bface for LINEAR). */
+int eb_edge_residual(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
+                     const double *coords, const double *n_edge, const double *b_node,
+                     const double *flux, int bflux, double *res, void *ws, size_t ws_bytes,
+                     hipStream_t stream);
 
 /* Adjoint: given grad_n = dL/dn [dim][n_edges], grad_b = dL/db [dim][n_bnodes]
  * and grad_vol = dL/dV [n_nodes] (any may be NULL = zero), writes

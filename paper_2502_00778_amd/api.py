@@ -17,11 +17,12 @@ from ._lib import EbSizes, EbTopology, check, lib
 
 __all__ = ["Topology", "build_edges", "directed_areas", "dual_volumes",
            "directed_areas_backward", "check_errors", "set_gather_shape",
-           "get_gather_shape", "workspace_bytes", "time_next_launch", "REDUCE",
-           "VOL_MODE"]
+           "get_gather_shape", "workspace_bytes", "time_next_launch", "edge_residual",
+           "REDUCE", "VOL_MODE", "BFLUX"]
 
 REDUCE = {"atomic": _lib.EB_REDUCE_ATOMIC, "gather": _lib.EB_REDUCE_GATHER}
 VOL_MODE = {"element": _lib.EB_VOL_ELEMENT, "edge": _lib.EB_VOL_EDGE}
+BFLUX = {"node": 0, "linear": 1}
 
 
 def _stream_ptr(stream=None):
@@ -244,3 +245,22 @@ def time_next_launch(start, stop):
     The events must already exist on the device (record each once)."""
     check(lib().eb_time_next_launch(ctypes.c_void_p(start.cuda_event),
                                     ctypes.c_void_p(stop.cuda_event)), "eb_time_next_launch")
+
+
+def edge_residual(coords: torch.Tensor, topo: Topology, elems: torch.Tensor, n: torch.Tensor,
+                  flux: torch.Tensor, b: torch.Tensor | None = None, bflux: str = "linear",
+                  out=None, stream=None):
+    """eb_edge_residual: res [Nv] of the edge loop with nodal flux [D, Nv]."""
+    D = topo.dim
+    _need(coords, "coords", torch.float64, (D, topo.n_nodes))
+    _need(elems, "elems", torch.int32, (topo.n_elems, D + 1))
+    _need(n, "n", torch.float64, (D, topo.n_edges))
+    _need(flux, "flux", torch.float64, (D, topo.n_nodes))
+    if b is not None:
+        _need(b, "b", torch.float64, (D, topo.n_bnodes))
+    res = _out((topo.n_nodes,), coords, out)
+    check(lib().eb_edge_residual(ctypes.byref(topo.sizes), ctypes.byref(topo.struct),
+                                 _ptr(elems), _ptr(coords), _ptr(n), _ptr(b), _ptr(flux),
+                                 BFLUX[bflux], _ptr(res), _ptr(topo.ws), topo.ws.numel(),
+                                 _stream_ptr(stream)), "eb_edge_residual")
+    return res

@@ -195,6 +195,32 @@ int eb_dual_volumes(const eb_sizes *sizes, const eb_topology *topo, const int32_
                          : volumes_impl<3>(a, mode, reduce, n_edge, stream);
 }
 
+int eb_edge_residual(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
+                     const double *coords, const double *n_edge, const double *b_node,
+                     const double *flux, int bflux, double *res, void *ws, size_t ws_bytes,
+                     hipStream_t stream) {
+  PrincipalScope scope;
+  clear_detail();
+  FwdArgs a;
+  EB_TRY(pack(sizes, topo, elem, coords, ws, ws_bytes, a));
+  if (!n_edge || !flux || !res || (bflux != EB_BFLUX_NODE && bflux != EB_BFLUX_LINEAR) ||
+      (bflux == EB_BFLUX_NODE && sizes->n_bnodes > 0 && !b_node)) {
+    set_detail("n_edge, flux and res are required; b_node for EB_BFLUX_NODE; bflux 0 or 1");
+    return EB_EINVAL;
+  }
+  EB_TRY(need(a.edge_tail && a.edge_head && a.node_edge_off && a.node_in_off && a.node_in_edge,
+              "edge, node_edge_off, node_in"));
+  if (sizes->n_bnodes > 0)
+    EB_TRY(need(a.bnode && (bflux == EB_BFLUX_NODE || (a.bnode_face_off && a.bnode_face && a.bface)),
+                "bnode, bnode_face, bface"));
+  const int D = sizes->dim;
+  rows(sizes->n_bnodes > 0 ? const_cast<double *>(b_node) : nullptr, D, sizes->n_bnodes, a.b_x,
+       a.b_y, a.b_z);
+  a.vterm = ws_at<double>(ws, ws_layout(D, sizes->n_nodes, sizes->n_elems).rows4);
+  return D == 2 ? residual_impl<2>(a, n_edge, flux, bflux, res, stream)
+                : residual_impl<3>(a, n_edge, flux, bflux, res, stream);
+}
+
 int eb_directed_areas_backward(const eb_sizes *sizes, const eb_topology *topo,
                                const int32_t *elem, const double *coords, const double *grad_n,
                                const double *grad_b, const double *grad_vol, int reduce,

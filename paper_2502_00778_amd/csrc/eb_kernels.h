@@ -97,6 +97,9 @@ int check_bwd_gather(const eb_sizes *sizes, FwdArgs &a, void *ws, size_t ws_byte
 template <int D> int forward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_t s);
 template <int D>
 int volumes_impl(const FwdArgs &a, int mode, int reduce, const double *n_edge, hipStream_t s);
+template <int D>
+int residual_impl(const FwdArgs &a, const double *n_edge, const double *F, int linear,
+                  double *res, hipStream_t s);
 template <int D> int backward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_t s);
 
 }  // namespace eb

@@ -163,6 +163,109 @@ __global__ __launch_bounds__(256) void k_vol_edge_sum(FwdArgs a, const double *_
   a.vol[j] = s;
 }
 
+// ------------------------------------------------- edge-loop residual
+// The consumer of the metrics (the edge-based discretization of Section 2):
+// Res_j = sum over edges (j,k) of phi_jk, with phi_jk = (F_j + F_k)/2 . n_jk
+// added at the tail and subtracted at the head, plus the boundary flux of
+// j's boundary faces.  Two passes like the edge loop: per-edge phi_e, then
+// per node the ordered sum; then boundary nodes add their faces in order.
+
+template <int D>
+__global__ __launch_bounds__(256) void k_res_edge_terms(FwdArgs a, const double *__restrict__ nx,
+                                                        const double *__restrict__ ny,
+                                                        const double *__restrict__ nz,
+                                                        const double *__restrict__ F,
+                                                        double *__restrict__ term) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nedge) return;
+  const int32_t j = a.edge_tail[e], k = a.edge_head[e];
+  const int64_t nv = a.nv;
+  double s = (F[j] + F[k]) * nx[e] + (F[nv + j] + F[nv + k]) * ny[e];
+  if (D == 3) s += (F[2 * nv + j] + F[2 * nv + k]) * nz[e];
+  term[e] = 0.5 * s;
+}
+
+__global__ __launch_bounds__(256) void k_res_node_sum(FwdArgs a, const double *__restrict__ term,
+                                                      double *__restrict__ res) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.nv) return;
+  double s = 0.0;
+  for (int32_t e = a.node_edge_off[j]; e < a.node_edge_off[j + 1]; ++e) s += term[e];
+  for (int32_t r = a.node_in_off[j]; r < a.node_in_off[j + 1]; ++r) s -= term[a.node_in_edge[r]];
+  res[j] = s;
+}
+
+// Boundary flux of boundary node bj.  NODE: F_j . b_j.  LINEAR: per face B,
+// n_B/D times F at the weights (2D: 5/6 own, 1/6 other; 3D: 6/8 own, 1/8 each
+// other), which makes the residual exact for linear F at every node.
+template <int D, bool LINEAR>
+__global__ __launch_bounds__(256) void k_res_boundary(FwdArgs a, const double *__restrict__ F,
+                                                      double *__restrict__ res) {
+  const int64_t bj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (bj >= a.nbnode) return;
+  const int32_t j = a.bnode[bj];
+  const int64_t nv = a.nv;
+  auto Fat = [&](int32_t i) {
+    return V3{F[i], F[nv + i], D == 3 ? F[2 * nv + i] : 0.0};
+  };
+  double s = 0.0;
+  if constexpr (!LINEAR) {
+    const V3 b = {a.b_x[bj], a.b_y[bj], D == 3 ? a.b_z[bj] : 0.0};
+    s = dot(Fat(j), b);
+  } else {
+    for (int32_t r = a.bnode_face_off[bj]; r < a.bnode_face_off[bj + 1]; ++r) {
+      const int32_t f = a.bnode_face[r];
+      int32_t fv[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) fv[q] = a.bface[(int64_t)f * D + q];
+      V3 nB, Fq;
+      if constexpr (D == 3) {
+        const V3 A = load_pt<D>(a.X, fv[0]), B = load_pt<D>(a.X, fv[1]), C = load_pt<D>(a.X, fv[2]);
+        nB = (1.0 / 6.0) * cross(B - A, C - A);  // n_B / D
+        const V3 F0 = Fat(fv[0]), F1 = Fat(fv[1]), F2 = Fat(fv[2]);
+        const V3 sum = F0 + F1 + F2, own = fv[0] == j ? F0 : (fv[1] == j ? F1 : F2);
+        Fq = 0.125 * (sum + 5.0 * own);
+      } else {
+        nB = 0.5 * rot2(load_pt<D>(a.X, fv[1]) - load_pt<D>(a.X, fv[0]));  // n_B / D
+        const V3 F0 = Fat(fv[0]), F1 = Fat(fv[1]);
+        const V3 own = fv[0] == j ? F0 : F1, other = fv[0] == j ? F1 : F0;
+        Fq = (1.0 / 6.0) * (5.0 * own + other);
+      }
+      s += dot(Fq, nB);
+    }
+  }
+  res[j] += s;
+}
+
+template <int D>
+int residual_impl(const FwdArgs &a, const double *n_edge, const double *F, int linear,
+                  double *res, hipStream_t s) {
+  const double *nx = n_edge, *ny = n_edge + a.nedge, *nz = D == 3 ? n_edge + 2 * a.nedge : nullptr;
+  if (a.nedge > 0) {
+    launch_principal(k_res_edge_terms<D>, dim3(grid_for(a.nedge, 256)), dim3(256), 0, s, a, nx,
+                     ny, nz, F, a.vterm);
+    EB_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_res_node_sum, dim3(grid_for(a.nv, 256)), dim3(256), 0, s, a,
+                     (const double *)a.vterm, res);
+  EB_LAUNCH_CHECK();
+  if (a.nbnode > 0) {
+    if (linear)
+      hipLaunchKernelGGL((k_res_boundary<D, true>), dim3(grid_for(a.nbnode, 256)), dim3(256), 0,
+                         s, a, F, res);
+    else
+      hipLaunchKernelGGL((k_res_boundary<D, false>), dim3(grid_for(a.nbnode, 256)), dim3(256), 0,
+                         s, a, F, res);
+    EB_LAUNCH_CHECK();
+  }
+  return EB_OK;
+}
+
+template int residual_impl<2>(const FwdArgs &, const double *, const double *, int, double *,
+                              hipStream_t);
+template int residual_impl<3>(const FwdArgs &, const double *, const double *, int, double *,
+                              hipStream_t);
+
 // ------------------------------------------------------------- launchers
 
 template <int D> int launch_fwd_boundary(const FwdArgs &a, hipStream_t s);
