@@ -330,7 +330,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phase-reps", type=int, default=10)
     ap.add_argument("--only", default="", help="profiling: run only this phase "
-                    "(topo|fwd|fwd_atomic|vol_edge|bwd|bwd_atomic|fused) --steps times")
+                    "(topo|fwd|fwd_atomic|vol_edge|bwd|bwd_atomic|fused|fwd_edge_normals|"
+                    "fwd_dual_faces) --steps times")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-deforming", action="store_true")
@@ -394,9 +395,16 @@ def main():
     def ph_fused():
         eb.forward_backward(X, topo, E, W, B, C, out=fouts)
 
+    def ph_fwd_edge_normals():
+        eb.directed_areas_variant(X, topo, E, "edge_normals", n_out=n, b_out=b, v_out=V)
+
+    def ph_fwd_dual_faces():
+        eb.directed_areas_variant(X, topo, E, "dual_faces", n_out=n, b_out=b, v_out=V)
+
     phases = {"topo": ph_topo, "fwd": ph_fwd, "fwd_atomic": ph_fwd_atomic,
               "vol_edge": ph_vol_edge, "bwd": ph_bwd, "bwd_atomic": ph_bwd_atomic,
-              "fused": ph_fused}
+              "fused": ph_fused, "fwd_edge_normals": ph_fwd_edge_normals,
+              "fwd_dual_faces": ph_fwd_dual_faces}
 
     if args.only:
         fn = phases[args.only]
@@ -433,7 +441,8 @@ def main():
         log(f"[bench] phase {name}: mean {res[name][0]:.3f} ms, median {res[name][1]:.3f}, "
             f"min {res[name][2]:.3f}")
     kern = {}
-    for name in ("fwd", "fwd_atomic", "vol_edge", "bwd", "bwd_atomic", "fused"):
+    for name in ("fwd", "fwd_atomic", "vol_edge", "bwd", "bwd_atomic", "fused",
+                 "fwd_edge_normals", "fwd_dual_faces"):
         kern[name] = tm.time_principal(eb, phases[name], args.phase_reps)
         log(f"[bench] principal kernel of {name}: mean {kern[name][0]:.4f} ms, "
             f"median {kern[name][1]:.4f}, min {kern[name][2]:.4f}")
@@ -501,7 +510,16 @@ def main():
             f"adjoint_{bwd_reduce}": ph("bwd", bb_),
             "adjoint_atomic": ph("bwd_atomic", bb_),
             "fused_forward_adjoint": ph("fused", alg_bytes_fused(dim, nv, nel, ne_, nb, nbn)),
+            "forward_edge_normals": ph("fwd_edge_normals", bf),
+            "forward_dual_faces": ph("fwd_dual_faces", bf),
         },
+    }
+    # the paper's Table 3 asks how much the dual-face construction costs over
+    # the proposed formula (2.16x for n_jk on its serial tet run); on this GPU:
+    line["traditional_vs_proposed"] = {
+        "dual_faces_over_node_normals": round(kern["fwd_dual_faces"][0] / kern["fwd"][0], 3),
+        "edge_normals_over_node_normals": round(kern["fwd_edge_normals"][0] / kern["fwd"][0], 3),
+        "paper_serial_tet_njk_ratio": 2.16,
     }
     if not args.no_batched:
         line["batched"] = bench_batched(torch, eb, meshgen, args.seed, args.phase_reps, tm)

@@ -219,6 +219,28 @@ int eb_directed_areas(const eb_sizes *sizes, const eb_topology *topo, const int3
                       const double *coords, int reduce, double *n_edge, double *b_node,
                       double *vol, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Forward-pass variants, for measuring what the paper's operation counts
+ * cost on this hardware (Table 3; the remark that one area vector n_j^E
+ * serves every edge with tail j).  Same outputs and requirements as
+ * eb_directed_areas with EB_REDUCE_GATHER; results agree with it to rounding:
+ *   EB_VARIANT_NODE_NORMALS  exactly eb_directed_areas (one n_j^E per node
+ *                            and element);
+ *   EB_VARIANT_EDGE_NORMALS  n_j^E formed again for every edge with tail j
+ *                            (one normal per local edge, 6 per tet);
+ *   EB_VARIANT_DUAL_FACES    the traditional construction (Section 3.1): each
+ *                            edge's median-dual face in each element from the
+ *                            edge midpoint, face and element centroids, and
+ *                            b from the boundary faces' median-dual pieces. */
+typedef enum {
+  EB_VARIANT_NODE_NORMALS = 0,
+  EB_VARIANT_EDGE_NORMALS = 1,
+  EB_VARIANT_DUAL_FACES = 2
+} eb_variant;
+int eb_directed_areas_variant(const eb_sizes *sizes, const eb_topology *topo,
+                              const int32_t *elem, const double *coords, int variant,
+                              double *n_edge, double *b_node, double *vol, void *ws,
+                              size_t ws_bytes, hipStream_t stream);
+
 /* Dual volumes vol [n_nodes].
  *   EB_VOL_ELEMENT: sum of |E|/(D+1) over the elements of each node
  *     (Section 4.2); n_edge unused.

@@ -25,7 +25,8 @@ EXPORTS = ("eb_workspace_bytes", "eb_backward_workspace_bytes", "eb_build_edges"
            "eb_status_string", "eb_last_error_detail", "eb_version",
            "eb_batch_offsets", "eb_batch_forward_backward", "eb_batch_graph_create",
            "eb_graph_launch", "eb_graph_destroy", "eb_set_fused_shape", "eb_get_fused_shape",
-           "eb_set_fused_wait_limit", "eb_autotune", "eb_edge_residual")
+           "eb_set_fused_wait_limit", "eb_autotune", "eb_edge_residual",
+           "eb_directed_areas_variant")
 
 TOPO_FIELDS = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign",
                "edge_inc_off", "edge_inc", "node_inc_off", "node_inc", "node_sell_off",
@@ -113,6 +114,7 @@ def lib():
     L.eb_autotune.argtypes = [SZ, TP, P, P, P, P, P, P, P, P, P, P, sz, i32, P,
                               ctypes.POINTER(EbTuning)]
     L.eb_edge_residual.argtypes = [SZ, TP, P, P, P, P, P, i32, P, P, sz, P]
+    L.eb_directed_areas_variant.argtypes = [SZ, TP, P, P, i32, P, P, P, P, sz, P]
     L.eb_status_string.argtypes = [i32]
     L.eb_status_string.restype = ctypes.c_char_p
     L.eb_last_error_detail.restype = ctypes.c_char_p

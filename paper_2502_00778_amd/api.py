@@ -18,11 +18,12 @@ from ._lib import EbSizes, EbTopology, check, lib
 __all__ = ["Topology", "build_edges", "directed_areas", "dual_volumes",
            "directed_areas_backward", "check_errors", "set_gather_shape",
            "get_gather_shape", "workspace_bytes", "time_next_launch", "edge_residual",
-           "REDUCE", "VOL_MODE", "BFLUX"]
+           "directed_areas_variant", "REDUCE", "VOL_MODE", "BFLUX", "VARIANT"]
 
 REDUCE = {"atomic": _lib.EB_REDUCE_ATOMIC, "gather": _lib.EB_REDUCE_GATHER}
 VOL_MODE = {"element": _lib.EB_VOL_ELEMENT, "edge": _lib.EB_VOL_EDGE}
 BFLUX = {"node": 0, "linear": 1}
+VARIANT = {"node_normals": 0, "edge_normals": 1, "dual_faces": 2}
 
 
 def _stream_ptr(stream=None):
@@ -264,3 +265,19 @@ def edge_residual(coords: torch.Tensor, topo: Topology, elems: torch.Tensor, n: 
                                  BFLUX[bflux], _ptr(res), _ptr(topo.ws), topo.ws.numel(),
                                  _stream_ptr(stream)), "eb_edge_residual")
     return res
+
+
+def directed_areas_variant(coords: torch.Tensor, topo: Topology, elems: torch.Tensor,
+                           variant: str, n_out=None, b_out=None, v_out=None, stream=None):
+    """eb_directed_areas_variant: (n, b, V) by the chosen construction."""
+    D = topo.dim
+    _need(coords, "coords", torch.float64, (D, topo.n_nodes))
+    _need(elems, "elems", torch.int32, (topo.n_elems, D + 1))
+    n = _out((D, topo.n_edges), coords, n_out)
+    b = _out((D, topo.n_bnodes), coords, b_out)
+    V = _out((topo.n_nodes,), coords, v_out)
+    check(lib().eb_directed_areas_variant(ctypes.byref(topo.sizes), ctypes.byref(topo.struct),
+                                          _ptr(elems), _ptr(coords), VARIANT[variant], _ptr(n),
+                                          _ptr(b), _ptr(V), _ptr(topo.ws), topo.ws.numel(),
+                                          _stream_ptr(stream)), "eb_directed_areas_variant")
+    return n, b, V

@@ -163,6 +163,29 @@ int eb_directed_areas(const eb_sizes *sizes, const eb_topology *topo, const int3
   return D == 2 ? forward_impl<2>(a, reduce, cfg, stream) : forward_impl<3>(a, reduce, cfg, stream);
 }
 
+int eb_directed_areas_variant(const eb_sizes *sizes, const eb_topology *topo,
+                              const int32_t *elem, const double *coords, int variant,
+                              double *n_edge, double *b_node, double *vol, void *ws,
+                              size_t ws_bytes, hipStream_t stream) {
+  PrincipalScope scope;
+  clear_detail();
+  FwdArgs a;
+  EB_TRY(pack(sizes, topo, elem, coords, ws, ws_bytes, a));
+  if (variant < EB_VARIANT_NODE_NORMALS || variant > EB_VARIANT_DUAL_FACES || !n_edge) {
+    set_detail("variant must be 0, 1 or 2 and n_edge non-null");
+    return EB_EINVAL;
+  }
+  const int D = sizes->dim;
+  rows(n_edge, D, sizes->n_edges, a.n_x, a.n_y, a.n_z);
+  rows(sizes->n_bnodes > 0 ? b_node : nullptr, D, sizes->n_bnodes, a.b_x, a.b_y, a.b_z);
+  a.vol = vol;
+  EB_TRY(check_fwd_gather(sizes, a));
+  const LaunchCfg cfg = default_cfg();
+  a.xcd_remap = cfg.xcd_remap;
+  return D == 2 ? forward_variant_impl<2>(a, variant, cfg, stream)
+                : forward_variant_impl<3>(a, variant, cfg, stream);
+}
+
 int eb_dual_volumes(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
                     const double *coords, int mode, const double *n_edge, int reduce,
                     double *vol, void *ws, size_t ws_bytes, hipStream_t stream) {

@@ -2,6 +2,8 @@
 // kernels and the fused forward + adjoint kernel.
 #pragma once
 
+#include <type_traits>
+
 #include "eb_geom.h"
 #include "eb_kernels.h"
 
@@ -71,10 +73,48 @@ __device__ __forceinline__ void sell_entry(const uint64_t *__restrict__ sell, in
 
 // One tile of TN consecutive nodes, by a block of TN threads (called by the
 // whole block; acc is the block's LDS accumulator).
-template <int D, int TN, int CAP, int U, bool WIDE>
+// How the contribution of element E to an edge (j, k) with tail j is formed
+// (all give n to rounding; the alternatives exist to measure what the
+// paper's flop counts cost on this hardware):
+//   VAR_NODE   one face vector n_j^E per (node, element), reused for every
+//              edge leaving j in E (the remark that one area vector serves
+//              all edges with the same tail);
+//   VAR_EDGE   n_j^E formed again for each such edge, from a rotated vertex
+//              order (one normal per local edge, 6 per tet);
+//   VAR_DUAL   the traditional median-dual face of the edge in E from the
+//              edge midpoint, the face centroids and the element centroid
+//              (Section 3.1), oriented from j to k.
+enum FwdVariant { VAR_NODE = 0, VAR_EDGE = 1, VAR_DUAL = 2 };
+
+// the traditional dual-face piece of edge (j, P[m]) in the element of j
+// whose other vertices are P[] (oriented from j to P[m])
+template <int D, int M>
+__device__ __forceinline__ V3 dual_piece(const V3 &xj, const V3 (&P)[D]) {
+  const V3 xk = P[M];
+  const V3 mid = 0.5 * (xj + xk), ejk = xk - xj;
+  if constexpr (D == 3) {
+    const V3 xa = P[(M + 1) % 3], xb = P[(M + 2) % 3];
+    const V3 C = 0.25 * (xj + xk + xa + xb);
+    const V3 F1 = (1.0 / 3.0) * (xj + xk + xa), F2 = (1.0 / 3.0) * (xj + xk + xb);
+    V3 t1 = 0.5 * cross(F1 - mid, C - mid), t2 = 0.5 * cross(C - mid, F2 - mid);
+    if (dot(t1, ejk) < 0.0) t1 = -t1;
+    if (dot(t2, ejk) < 0.0) t2 = -t2;
+    return t1 + t2;
+  } else {
+    const V3 C = (1.0 / 3.0) * (xj + xk + P[1 - M]);
+    const V3 g = C - mid;
+    V3 t = {-g.y, g.x, 0.0};
+    if (dot(t, ejk) < 0.0) t = -t;
+    return t;
+  }
+}
+
+template <int D, int TN, int CAP, int U, bool WIDE, int VAR = VAR_NODE>
 __device__ __forceinline__ void fwd_node_tile(const FwdArgs &a, int64_t tile,
                                               double (&acc)[D][CAP]) {
   static_assert(TN % SELL == 0, "a tile is whole slices");
+  // accumulator units: cross products (VAR_NODE / VAR_EDGE), pieces (VAR_DUAL)
+  constexpr double kOut = VAR == VAR_DUAL ? 1.0 : GK<D>::kN;
   const int t = threadIdx.x;
   const int64_t j0 = tile * TN;
   if (j0 >= a.nv) return;  // whole block leaves together
@@ -151,6 +191,7 @@ __device__ __forceinline__ void fwd_node_tile(const FwdArgs &a, int64_t tile,
         else
           c = rot2(P[u][1] - P[u][0]);
         double d = dot(c, P[u][0] - xj);
+        const double sg = d < 0.0 ? -1.0 : 1.0;  // the flip applied to c
         if (d < 0.0) {
           c = -c;
           d = -d;
@@ -158,27 +199,49 @@ __device__ __forceinline__ void fwd_node_tile(const FwdArgs &a, int64_t tile,
           raise_status(a.st, EB_EDEGENERATE, j);
         }
         vs += d;
+        if constexpr (VAR == VAR_NODE) {
 #pragma unroll
-        for (int m = 0; m < D; ++m) {
-          const int s = slot_of<WIDE>(code[u], m);
-          if (s != no_slot<WIDE>()) add(s, c);
+          for (int m = 0; m < D; ++m) {
+            const int s = slot_of<WIDE>(code[u], m);
+            if (s != no_slot<WIDE>()) add(s, c);
+          }
+        } else {
+          auto edge_term = [&](auto mm) {
+            constexpr int m = decltype(mm)::value;
+            const int s = slot_of<WIDE>(code[u], m);
+            if (s == no_slot<WIDE>()) return;
+            if constexpr (VAR == VAR_EDGE) {
+              // the same face vector from the vertex order rotated by m
+              V3 ce;
+              if constexpr (D == 3)
+                ce = cross(P[u][(m + 1) % 3] - P[u][m], P[u][(m + 2) % 3] - P[u][m]);
+              else
+                ce = m == 0 ? rot2(P[u][1] - P[u][0]) : -rot2(P[u][0] - P[u][1]);
+              add(s, sg * ce);
+            } else {
+              add(s, dual_piece<D, m>(xj, P[u]));
+            }
+          };
+          edge_term(std::integral_constant<int, 0>{});
+          edge_term(std::integral_constant<int, 1>{});
+          if constexpr (D == 3) edge_term(std::integral_constant<int, 2>{});
         }
       }
     }
     if (a.vol) a.vol[j] = vs * GK<D>::kV;
     if (!in_lds)
       for (int32_t ed = my0; ed < my1; ++ed) {
-        nx[ed] *= GK<D>::kN;
-        ny[ed] *= GK<D>::kN;
-        if (D == 3) nz[ed] *= GK<D>::kN;
+        nx[ed] *= kOut;
+        ny[ed] *= kOut;
+        if (D == 3) nz[ed] *= kOut;
       }
   }
   if (in_lds) {
     __syncthreads();
     for (int i = t; i < cnt; i += TN) {
-      nx[e0 + i] = acc[0][i] * GK<D>::kN;
-      ny[e0 + i] = acc[1][i] * GK<D>::kN;
-      if (D == 3) nz[e0 + i] = acc[2][i] * GK<D>::kN;
+      nx[e0 + i] = acc[0][i] * kOut;
+      ny[e0 + i] = acc[1][i] * kOut;
+      if (D == 3) nz[e0 + i] = acc[2][i] * kOut;
     }
   }
 }

@@ -98,6 +98,8 @@ template <int D> int forward_impl(const FwdArgs &a, int reduce, const LaunchCfg 
 template <int D>
 int volumes_impl(const FwdArgs &a, int mode, int reduce, const double *n_edge, hipStream_t s);
 template <int D>
+int forward_variant_impl(const FwdArgs &a, int variant, const LaunchCfg &cfg, hipStream_t s);
+template <int D>
 int residual_impl(const FwdArgs &a, const double *n_edge, const double *F, int linear,
                   double *res, hipStream_t s);
 template <int D> int backward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_t s);

@@ -100,6 +100,51 @@ __global__ __launch_bounds__(TN) void k_fwd_gather(FwdArgs a) {
   fwd_node_tile<D, TN, CAP, U, WIDE>(a, tile_of_block(gridDim.x, a.xcd_remap), acc);
 }
 
+template <int D, int TN, int CAP, int U, bool WIDE, int VAR>
+__global__ __launch_bounds__(TN) void k_fwd_gather_variant(FwdArgs a) {
+  __shared__ double acc[D][CAP];
+  fwd_node_tile<D, TN, CAP, U, WIDE, VAR>(a, tile_of_block(gridDim.x, a.xcd_remap), acc);
+}
+
+// Traditional boundary loop: b_j from node j's share of each boundary face
+// built from the edge midpoints and the face centroid (Section 3.2), each
+// piece oriented like the face's outward normal.  The dual-face pieces of
+// the interior loop already sum to the corrected n, so n is left alone.
+template <int D>
+__global__ __launch_bounds__(256) void k_fwd_boundary_dual(FwdArgs a) {
+  const int64_t bj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (bj >= a.nbnode || !a.b_x) return;
+  const int32_t j = a.bnode[bj];
+  V3 bs = {0.0, 0.0, 0.0};
+  for (int32_t r = a.bnode_face_off[bj]; r < a.bnode_face_off[bj + 1]; ++r) {
+    const int32_t f = a.bnode_face[r];
+    int32_t fv[D];
+#pragma unroll
+    for (int s = 0; s < D; ++s) fv[s] = a.bface[(int64_t)f * D + s];
+    if constexpr (D == 3) {
+      const V3 A = load_pt<D>(a.X, fv[0]), B = load_pt<D>(a.X, fv[1]), C = load_pt<D>(a.X, fv[2]);
+      const V3 nB = cross(B - A, C - A);
+      const V3 xi = fv[0] == j ? A : (fv[1] == j ? B : C);
+      const V3 xa = fv[0] == j ? B : A, xb = fv[2] == j ? B : C;
+      const V3 G = (1.0 / 3.0) * (A + B + C), ma = 0.5 * (xi + xa), mb = 0.5 * (xi + xb);
+      V3 t1 = 0.5 * cross(ma - xi, G - xi), t2 = 0.5 * cross(G - xi, mb - xi);
+      if (dot(t1, nB) < 0.0) t1 = -t1;
+      if (dot(t2, nB) < 0.0) t2 = -t2;
+      bs = bs + t1 + t2;
+    } else {
+      const V3 A = load_pt<D>(a.X, fv[0]), B = load_pt<D>(a.X, fv[1]);
+      const V3 nB = rot2(B - A);
+      const V3 xi = fv[0] == j ? A : B, xo = fv[0] == j ? B : A;
+      V3 t = rot2(0.5 * (xi + xo) - xi);
+      if (dot(t, nB) < 0.0) t = -t;
+      bs = bs + t;
+    }
+  }
+  a.b_x[bj] = bs.x;
+  a.b_y[bj] = bs.y;
+  if (D == 3) a.b_z[bj] = bs.z;
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_fwd_boundary_gather(FwdArgs a) {
   const int64_t bj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -305,6 +350,38 @@ int launch_fwd_boundary(const FwdArgs &a, hipStream_t s) {
   EB_LAUNCH_CHECK();
   return EB_OK;
 }
+
+template <int D>
+int forward_variant_impl(const FwdArgs &a, int variant, const LaunchCfg &cfg, hipStream_t s) {
+  const int64_t ntiles = (a.nv + cfg.tile - 1) / cfg.tile;
+  const dim3 grid((unsigned)ntiles);
+  if (variant == 0) return launch_fwd_gather<D>(a, cfg, s);
+  // one shape (128 nodes, 2 loads in flight): these variants are for comparison
+  if (a.sell_wide) {
+    if (variant == 1)
+      launch_principal((k_fwd_gather_variant<D, 128, 1024, 2, true, VAR_EDGE>), grid, dim3(128), 0,
+                       s, a);
+    else
+      launch_principal((k_fwd_gather_variant<D, 128, 1024, 2, true, VAR_DUAL>), grid, dim3(128), 0,
+                       s, a);
+  } else {
+    if (variant == 1)
+      launch_principal((k_fwd_gather_variant<D, 128, 1024, 2, false, VAR_EDGE>), grid, dim3(128),
+                       0, s, a);
+    else
+      launch_principal((k_fwd_gather_variant<D, 128, 1024, 2, false, VAR_DUAL>), grid, dim3(128),
+                       0, s, a);
+  }
+  EB_LAUNCH_CHECK();
+  if (a.nbnode <= 0) return EB_OK;
+  if (variant == 1) return launch_fwd_boundary<D>(a, s);
+  hipLaunchKernelGGL(k_fwd_boundary_dual<D>, dim3(grid_for(a.nbnode, 256)), dim3(256), 0, s, a);
+  EB_LAUNCH_CHECK();
+  return EB_OK;
+}
+
+template int forward_variant_impl<2>(const FwdArgs &, int, const LaunchCfg &, hipStream_t);
+template int forward_variant_impl<3>(const FwdArgs &, int, const LaunchCfg &, hipStream_t);
 
 template <int D>
 int forward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_t s) {

@@ -449,3 +449,31 @@ def test_full_scale_161(scale161):
         Ve = eb().dual_volumes(X, gt, E, mode="edge", n=n, reduce=reduce)
         assert_vol_close(Ve.cpu().numpy(), V0, f"edge V {reduce}")
         del n, b, V, Ve
+
+
+@pytest.mark.parametrize("name", ["3d-41", "2d-33", "3d-33-relabel", "3d-scale-33", "2d-single",
+                                  "3d-single"])
+@pytest.mark.parametrize("variant", ["edge_normals", "dual_faces"])
+def test_forward_variants_match_oracle(name, variant):
+    """The comparison variants (a normal per edge; the traditional dual-face
+    construction) give the oracle's n, b, V to the same tolerance."""
+    mesh, ot, n0, b0, V0 = case(name)
+    X, E = dev(mesh)
+    gt = eb().build_edges(E, X)
+    S_e, S_b = piece_scales(ot, mesh.coords, mesh.elems)
+    n, b, V = (t.cpu().numpy() for t in eb().directed_areas_variant(X, gt, E, variant))
+    eb().check_errors(gt)
+    c1, w1 = assert_vec_close(n, n0, S_e, f"n {variant}")
+    assert_vec_close(b, b0, S_b, f"b {variant}")
+    assert_vol_close(V, V0, f"V {variant}")
+    say(f"[variant] {name} {variant}: worst rel n {w1:.2e}")
+
+
+def test_variant_node_normals_is_directed_areas():
+    mesh, *_ = case("3d-41")
+    X, E = dev(mesh)
+    gt = eb().build_edges(E, X)
+    a = eb().directed_areas(X, gt, E, "gather")
+    v = eb().directed_areas_variant(X, gt, E, "node_normals")
+    for x, y in zip(a, v):
+        assert torch.equal(x, y)
