@@ -184,22 +184,21 @@ size_t eb_workspace_bytes(int dim, int64_t n_nodes, int64_t n_elems);
 size_t eb_backward_workspace_bytes(const eb_sizes *sizes);
 
 /* Edge extraction, phase 1 (Section 2: the edge array; Section 3.2: boundary
- * elements).  Validates the grid, fills the caller's node_inc_off [n_nodes+1]
- * (their sizes are known in advance) and keeps the node -> element lists in
- * ws, counts unique edges, boundary faces and boundary nodes into ws, and
- * fills *sizes_host.  node_inc [(dim+1)*n_elems] is written by phase 2.
- * Synchronizes `stream` once and returns the sticky device status.  coords
- * [dim][n_nodes] are needed to orient boundary faces outward and to reject
- * zero-measure elements. */
+ * elements).  Validates the grid, builds the node -> element lists into the
+ * caller's node_inc_off [n_nodes+1] and node_inc [(dim+1)*n_elems] (their
+ * sizes are known in advance; ws keeps a richer copy for phase 2), counts
+ * unique edges, boundary faces and boundary nodes into ws, and fills
+ * *sizes_host.  Synchronizes `stream` once and returns the sticky device
+ * status.  coords [dim][n_nodes] are needed to orient boundary faces outward
+ * and to reject zero-measure elements. */
 int eb_build_edges(int dim, int64_t n_nodes, int64_t n_elems, const int32_t *elem,
                    const double *coords, int32_t *node_inc_off, int32_t *node_inc,
                    void *ws, size_t ws_bytes, eb_sizes *sizes_host, hipStream_t stream);
 
 /* Edge extraction, phase 2: writes every other eb_topology array (sized from
- * *sizes), node_inc included, from what eb_build_edges left in ws (the same
- * ws, untouched in between).  topo->node_inc_off must be the array phase 1
- * filled and topo->node_inc the one passed to it.  edge_inc_off/edge_inc and
- * inc_sell may be NULL. */
+ * *sizes) from what eb_build_edges left in ws (the same ws, untouched in
+ * between).  topo->node_inc_off and topo->node_inc must be the arrays phase 1
+ * filled.  edge_inc_off/edge_inc and inc_sell may be NULL. */
 int eb_build_edges_emit(const eb_sizes *sizes, const int32_t *elem, const double *coords,
                         const eb_topology *topo, void *ws, size_t ws_bytes,
                         hipStream_t stream);

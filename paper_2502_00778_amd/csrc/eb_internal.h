@@ -42,7 +42,8 @@ __device__ inline void raise_status(StatusBlock *st, int code, int64_t detail) {
 // [incidence rows (build) | gradient pieces (gather adjoint)]
 // Each per-node array holds n_nodes+1 int32 and starts on a 256-byte line.
 struct WsLayout {
-  size_t eoff, foff, bidx, bfn, bfn_scan, ein_scan, slen, queue, scan_tmp, rows4, total;
+  size_t eoff, foff, bidx, bfn, bfn_scan, ein_scan, slen, queue, scan_tmp, rows4, inc_pos,
+      row_rank, total;
   int64_t scan_tmp_count;
 };
 
@@ -69,8 +70,12 @@ inline WsLayout ws_layout(int dim, int64_t n_nodes, int64_t n_elems) {
   int64_t longest = std::max<int64_t>(n_nodes + 1, ne * n_elems + 1);
   L.scan_tmp_count = (longest + SCAN_TILE - 1) / SCAN_TILE + 64;
   L.scan_tmp = off; off += align256(sizeof(int32_t) * (size_t)L.scan_tmp_count);
-  // build only: one 16-byte entry per incidence (the adjoint reuses the space)
-  L.rows4 = off; off += align256(16 * (size_t)(dim + 1) * (size_t)n_elems);
+  // build only (the adjoint reuses the space): per incidence a 16-byte row
+  // entry, its position in the unsorted rows, and its rank within its row
+  const size_t ninc = (size_t)(dim + 1) * (size_t)n_elems;
+  L.rows4 = off; off += align256(16 * ninc);
+  L.inc_pos = off; off += align256(4 * ninc);
+  L.row_rank = off; off += align256(2 * ninc);
   L.total = off;
   return L;
 }

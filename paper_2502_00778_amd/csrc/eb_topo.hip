@@ -135,7 +135,8 @@ __device__ __forceinline__ int4 inc_entry(const int32_t (&v)[D + 1], int l, int6
 template <int D>
 __global__ __launch_bounds__(AGG_TB) void k_scatter_nodes(const int32_t *__restrict__ elem,
                                                           int64_t nelem, int64_t nv, int32_t *cur,
-                                                          int4 *rows4) {
+                                                          int4 *rows4, int32_t *inc_pos,
+                                                          int32_t *node_inc) {
   __shared__ int32_t hk[AGG_HT], hc[AGG_HT];
   for (int i = threadIdx.x; i < AGG_HT; i += AGG_TB) {
     hk[i] = -1;
@@ -164,6 +165,8 @@ __global__ __launch_bounds__(AGG_TB) void k_scatter_nodes(const int32_t *__restr
       } else {
         const int32_t pos = atomicSub(&cur[v[k][i]], 1) - 1;
         rows4[pos] = inc_entry<D>(v[k], i, e);
+        inc_pos[e * (D + 1) + i] = pos;
+        node_inc[pos] = (int32_t)(e * (D + 1) + i);
       }
     }
   }
@@ -180,7 +183,12 @@ __global__ __launch_bounds__(AGG_TB) void k_scatter_nodes(const int32_t *__restr
     const int64_t e = base + (int64_t)k * AGG_TB;
 #pragma unroll
     for (int i = 0; i <= D; ++i)
-      if (slot[k][i] >= 0) rows4[hc[slot[k][i]] + rank[k][i]] = inc_entry<D>(v[k], i, e);
+      if (slot[k][i] >= 0) {
+        const int32_t pos = hc[slot[k][i]] + rank[k][i];
+        rows4[pos] = inc_entry<D>(v[k], i, e);
+        inc_pos[e * (D + 1) + i] = pos;
+        node_inc[pos] = (int32_t)(e * (D + 1) + i);
+      }
   }
 }
 
@@ -191,8 +199,9 @@ struct TopoArgs {
   const int32_t *elem;
   Coords X;
   const int32_t *node_inc_off;
-  int32_t *node_inc;     // written (sorted) by the emit pass
+  const int32_t *node_inc;
   const int32_t *rows4;  // workspace: Inc4 per incidence, rows of node_inc_off
+  const uint16_t *row_rank;  // workspace: rank of each row entry within its row
   // count pass (workspace)
   int32_t *outdeg, *fmin, *bflag, *bfn, *ein;
   // emit pass
@@ -295,13 +304,49 @@ __device__ __forceinline__ void inc_others(const int4 &q, int32_t (&o)[D]) {
   if constexpr (D == 3) o[2] = q.w;
 }
 
+// Rank of every entry of every row (the number of smaller incidences in the
+// row), and node_inc sorted in place (the scatter pass wrote it in row
+// order).  A thread per node; rows up to RK_CAP entries are ranked from an
+// LDS column, longer ones from the workspace rows (which keep the order).
+constexpr int RK_TB = 128;
+constexpr int RK_CAP = 32;
+
+__global__ __launch_bounds__(RK_TB) void k_row_rank(int64_t nv, const int32_t *__restrict__ off,
+                                                   const int4 *__restrict__ rows4,
+                                                   int32_t *node_inc, uint16_t *row_rank,
+                                                   const StatusBlock *st) {
+  __shared__ int32_t col[RK_CAP][RK_TB];
+  const int t = threadIdx.x;
+  const int64_t j = (int64_t)blockIdx.x * RK_TB + t;
+  if (j >= nv || build_failed(st)) return;
+  const int32_t r0 = off[j], len = off[j + 1] - r0;
+  if (len <= RK_CAP) {
+    for (int32_t i = 0; i < len; ++i) col[i][t] = node_inc[r0 + i];
+    for (int32_t i = 0; i < len; ++i) {
+      const int32_t x = col[i][t];
+      int32_t rank = 0;
+      for (int32_t i2 = 0; i2 < len; ++i2) rank += col[i2][t] < x ? 1 : 0;
+      row_rank[r0 + i] = (uint16_t)rank;
+      node_inc[r0 + rank] = x;
+    }
+  } else {
+    for (int32_t i = 0; i < len; ++i) {
+      const int32_t x = rows4[r0 + i].x;
+      int32_t rank = 0;
+      for (int32_t i2 = 0; i2 < len; ++i2) rank += rows4[r0 + i2].x < x ? 1 : 0;
+      row_rank[r0 + i] = (uint16_t)rank;
+      node_inc[r0 + rank] = x;
+    }
+  }
+}
+
 // Per node j: 1. its distinct neighbours and candidate faces; 2. (emit)
 // its sorted node_inc row and sliced entries; 3. face multiplicities;
 // 4. (emit) its boundary faces.  RC is the longest row the fast kernel ranks
 // in LDS (ri); the queued kernel ranks from global memory.
 template <int D, bool EMIT, int TBK, class Set, int MF, int RC, bool SLOW>
 __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
-                               uint16_t (*fc)[TBK], int32_t (*ri)[TBK]) {
+                               uint16_t (*fc)[TBK], uint8_t (*pr)[TBK]) {
   constexpr int MH = Set::CAP;
   const int32_t r0 = a.node_inc_off[j], r1 = a.node_inc_off[j + 1];
   const int4 *__restrict__ row = reinterpret_cast<const int4 *>(a.rows4) + r0;
@@ -318,7 +363,6 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
   int32_t maxdelta = 0;
   for (int32_t i = 0; i < len && !overflow; ++i) {
     const int4 q = row[i];
-    if (EMIT && !SLOW) ri[i][t] = q.x;
     int32_t o[D];
     inc_others<D>(q, o);
     int higher = 0;
@@ -370,7 +414,14 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
   //    with j as smallest vertex, coded by their two other vertices' slots
   int nf = 0;
   const int64_t sbase = (int64_t)a.node_sell_off[j / SELL] + (j % SELL);
-  for (int32_t i = 0; i < len; ++i) {
+  if constexpr (EMIT && !SLOW) {
+    // the entry at each rank, so the row is visited in ascending order below
+    // (the stores of a wave then fall on one column of the slice)
+    for (int32_t i = 0; i < len; ++i) pr[a.row_rank[r0 + i]][t] = (uint8_t)i;
+  }
+  for (int32_t c = 0; c < len; ++c) {
+    int32_t i = c;
+    if constexpr (EMIT && !SLOW) i = pr[c][t];
     const int4 q = row[i];
     int32_t o[D];
     inc_others<D>(q, o);
@@ -379,13 +430,8 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
     int s2 = -1;
     if constexpr (D == 3) s2 = o[2] > j ? hs.rank(o[2]) : -1;
     if constexpr (EMIT) {
-      int32_t rank = 0;
-      if constexpr (SLOW) {
-        for (int32_t i2 = 0; i2 < len; ++i2) rank += row[i2].x < q.x ? 1 : 0;
-      } else {
-        for (int32_t i2 = 0; i2 < len; ++i2) rank += ri[i2][t] < q.x ? 1 : 0;
-      }
-      a.node_inc[r0 + rank] = q.x;
+      // rows beyond the fast capacity are visited unsorted
+      const int32_t rank = SLOW ? (int32_t)a.row_rank[r0 + i] : c;
       const int B = a.sell_wide ? 10 : 5;
       const int none = (1 << B) - 1;
       const int u0 = s0 < 0 ? none : s0 - nlow, u1 = s1 < 0 ? none : s1 - nlow;
@@ -556,7 +602,7 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
 template <int D, bool EMIT>
 __global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
   __shared__ uint16_t fc[MAXF][TB];
-  __shared__ int32_t ri[EMIT ? MAXR : 1][TB];
+  __shared__ uint8_t pr[EMIT ? MAXR : 1][TB];
   const int t = threadIdx.x;
   const int64_t j64 = (int64_t)blockIdx.x * TB + t;
   if (build_failed(a.st)) return;
@@ -573,7 +619,7 @@ __global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
     return;
   }
   RegSet<MAXH> hs;
-  node_topo_body<D, EMIT, TB, RegSet<MAXH>, MAXF, MAXR, false>(a, (int32_t)j64, t, hs, fc, ri);
+  node_topo_body<D, EMIT, TB, RegSet<MAXH>, MAXF, MAXR, false>(a, (int32_t)j64, t, hs, fc, pr);
 }
 
 // the queued nodes, with the large capacities
@@ -674,15 +720,16 @@ template <int D> __host__ __device__ constexpr int pair_index(int p, int q) {
   return D == 3 ? (p == 0 ? q - 1 : (p == 1 ? q + 1 : 5)) : p + q - 1;
 }
 
-// Per element, once the sorted rows and the sliced entries exist: the sliced
-// position of each incidence (binary search for it in its vertex's node_inc
-// row) -> inc_sell; the out-edge slots of that entry -> the ids of the local
-// edges whose tail is that vertex; signs from the vertex order.  All writes
-// are per element, contiguous across threads.
+// Per element, once the sliced entries exist: the sliced position of each
+// incidence (its node's slice, column = its rank in the node's row, from
+// the positions the scatter pass and the ranks the emit pass recorded) ->
+// inc_sell; the out-edge slots of that entry -> the ids of the local edges
+// whose tail is that vertex; signs from the vertex order.  All writes are
+// per element, contiguous across threads.
 template <int D, bool WIDE>
 __global__ void k_elem_maps(const int32_t *__restrict__ elem, int64_t nelem,
-                            const int32_t *__restrict__ node_inc_off,
-                            const int32_t *__restrict__ node_inc,
+                            const int32_t *__restrict__ inc_pos,
+                            const uint16_t *__restrict__ row_rank,
                             const int32_t *__restrict__ node_sell_off,
                             const uint64_t *__restrict__ node_sell,
                             const int32_t *__restrict__ node_edge_off, int32_t *elem_edge,
@@ -690,21 +737,16 @@ __global__ void k_elem_maps(const int32_t *__restrict__ elem, int64_t nelem,
   constexpr int NE = EL<D>::NE;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nelem || build_failed(st)) return;
-  int32_t v[D + 1], ps[D + 1], ee[NE];
+  int32_t v[D + 1], ip[D + 1], ps[D + 1], ee[NE];
   load_conn<D>(elem, e, v);
+  load_conn<D>(inc_pos, e, ip);
 #pragma unroll
   for (int le = 0; le < NE; ++le) ee[le] = -1;
 #pragma unroll
   for (int l = 0; l <= D; ++l) {
-    const int32_t j = v[l], key = (int32_t)(e * (D + 1) + l);
-    const int32_t r0 = node_inc_off[j];
-    int32_t lo = r0, hi = node_inc_off[j + 1];
-    while (lo < hi) {
-      const int32_t mid = (lo + hi) >> 1;
-      if (node_inc[mid] < key) lo = mid + 1;
-      else hi = mid;
-    }
-    const int64_t pos = (int64_t)node_sell_off[j / SELL] + (int64_t)SELL * (lo - r0) + (j % SELL);
+    const int32_t j = v[l];
+    const int64_t pos =
+        (int64_t)node_sell_off[j / SELL] + (int64_t)SELL * row_rank[ip[l]] + (j % SELL);
     ps[l] = (int32_t)pos;
     const uint32_t code = WIDE ? (uint32_t)(node_sell[2 * pos + 1] >> 32)
                                : (uint32_t)(node_sell[pos] >> 48) & 0x7fffu;
@@ -799,7 +841,11 @@ int build_edges_impl(int64_t nv, int64_t nelem, const int32_t *elem, const doubl
   if (nelem > 0) {
     hipLaunchKernelGGL(k_scatter_nodes<D>, dim3(grid_for(nelem, AGG_TB * AGG_EPT)),
                        dim3(AGG_TB), 0, s, elem, nelem, nv, node_inc_off,
-                       ws_at<int4>(ws, L.rows4));
+                       ws_at<int4>(ws, L.rows4), ws_at<int32_t>(ws, L.inc_pos), node_inc);
+    EB_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_row_rank, dim3(grid_for(nv, RK_TB)), dim3(RK_TB), 0, s, nv,
+                       (const int32_t *)node_inc_off, (const int4 *)ws_at<int4>(ws, L.rows4),
+                       node_inc, ws_at<uint16_t>(ws, L.row_rank), (const StatusBlock *)st);
     EB_LAUNCH_CHECK();
   }
 
@@ -811,6 +857,7 @@ int build_edges_impl(int64_t nv, int64_t nelem, const int32_t *elem, const doubl
   ta.node_inc_off = node_inc_off;
   ta.node_inc = node_inc;
   ta.rows4 = ws_at<const int32_t>(ws, L.rows4);
+  ta.row_rank = ws_at<const uint16_t>(ws, L.row_rank);
   ta.outdeg = eoff;
   ta.fmin = foff;
   ta.bflag = bidx;
@@ -882,6 +929,7 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
   ta.node_inc_off = tp->node_inc_off;
   ta.node_inc = tp->node_inc;
   ta.rows4 = ws_at<const int32_t>(ws, L.rows4);
+  ta.row_rank = ws_at<const uint16_t>(ws, L.row_rank);
   ta.eoff = eoff;
   ta.foff = foff;
   ta.edge_tail = tp->edge;
@@ -911,14 +959,16 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
   if (nelem > 0) {
     if (sz->sell_wide)
       hipLaunchKernelGGL((k_elem_maps<D, true>), dim3(grid_for(nelem, 256)), dim3(256), 0, s,
-                         elem, nelem, (const int32_t *)tp->node_inc_off,
-                         (const int32_t *)tp->node_inc, (const int32_t *)tp->node_sell_off,
+                         elem, nelem, (const int32_t *)ws_at<int32_t>(ws, L.inc_pos),
+                         (const uint16_t *)ws_at<uint16_t>(ws, L.row_rank),
+                         (const int32_t *)tp->node_sell_off,
                          (const uint64_t *)tp->node_sell, (const int32_t *)tp->node_edge_off,
                          tp->elem_edge, tp->elem_edge_sign, tp->inc_sell, (const StatusBlock *)st);
     else
       hipLaunchKernelGGL((k_elem_maps<D, false>), dim3(grid_for(nelem, 256)), dim3(256), 0, s,
-                         elem, nelem, (const int32_t *)tp->node_inc_off,
-                         (const int32_t *)tp->node_inc, (const int32_t *)tp->node_sell_off,
+                         elem, nelem, (const int32_t *)ws_at<int32_t>(ws, L.inc_pos),
+                         (const uint16_t *)ws_at<uint16_t>(ws, L.row_rank),
+                         (const int32_t *)tp->node_sell_off,
                          (const uint64_t *)tp->node_sell, (const int32_t *)tp->node_edge_off,
                          tp->elem_edge, tp->elem_edge_sign, tp->inc_sell, (const StatusBlock *)st);
     EB_LAUNCH_CHECK();

@@ -46,9 +46,9 @@ def test_workspace_bytes(L):
     small = L.eb_workspace_bytes(3, 100, 300)
     big = L.eb_workspace_bytes(3, 161 ** 3, 6 * 160 ** 3)
     assert 256 < small < big
-    # per-node arrays plus scan scratch (well under 64 B per node) and one
-    # 16-byte entry per incidence
-    assert big < 161 ** 3 * 64 + 16 * 4 * 6 * 160 ** 3
+    # per-node arrays plus scan scratch (well under 64 B per node) and 22
+    # bytes per incidence
+    assert big < 161 ** 3 * 64 + 22 * 4 * 6 * 160 ** 3
 
 
 def test_backward_workspace_bytes(L):
@@ -58,10 +58,12 @@ def test_backward_workspace_bytes(L):
                      n_bnodes=10, n_sell=64 * 400, sell_wide=0)
         base = L.eb_workspace_bytes(dim, 1000, 5000)
         got = L.eb_backward_workspace_bytes(ctypes.byref(sz))
-        # the build keeps one 16-byte entry per incidence at the end of its
-        # layout; the adjoint's padded gradient pieces (one per sliced entry)
-        # take that place
-        rows = -(-16 * (dim + 1) * 5000 // 256) * 256
+        # the build keeps 22 bytes per incidence (row entry, position, rank) at
+        # the end of its layout; the adjoint's padded gradient pieces (one per
+        # sliced entry) take that place
+        up = lambda x: -(-x // 256) * 256
+        ninc = (dim + 1) * 5000
+        rows = up(16 * ninc) + up(4 * ninc) + up(2 * ninc)
         pieces = -(-per * 64 * 400 // 256) * 256
         assert got == max(base, base - rows + pieces)
     bad = EbSizes(dim=4, n_nodes=10, n_elems=10)
