@@ -377,6 +377,16 @@ int eb_graph_destroy(eb_graph graph);
 int eb_set_fused_shape(int tile, int unroll, int blocks_per_cu);
 void eb_get_fused_shape(int *tile, int *unroll, int *blocks_per_cu);
 
+/* How eb_batch_forward_backward runs: EB_FUSED_PERSISTENT (default) the one
+ * persistent kernel described there; EB_FUSED_SEPARATE the gather forward
+ * and the gather adjoint kernels one after the other (same results up to
+ * rounding, also capturable; faster where the persistent kernel's shared
+ * occupancy limit costs more than the launches it saves).  Process-wide;
+ * eb_autotune picks it. */
+typedef enum { EB_FUSED_PERSISTENT = 0, EB_FUSED_SEPARATE = 1 } eb_fused_mode;
+int eb_set_fused_mode(int mode);
+int eb_get_fused_mode(void);
+
 /* Bound of the fused kernel's phase waits, in polls of about a microsecond
  * (0 restores the default of 2^22).  A wait that runs out records
  * EB_ETIMEOUT and its block exits; every wave still ends. */
@@ -385,9 +395,9 @@ int eb_set_fused_wait_limit(int64_t spins);
 /* Launch-shape tuner.  Times (reps runs each, after one warm-up, hipEvents
  * on `stream`) every gather shape of eb_directed_areas (tile x unroll x
  * xcd_remap) and every fused shape of eb_batch_forward_backward (tile x
- * unroll x blocks_per_cu in {1,2,4,8,0}) on the caller's grid and buffers,
- * sets the fastest of each (eb_set_gather_shape / eb_set_fused_shape) and
- * reports them.  Outputs hold valid results afterwards (all shapes give the
+ * unroll x blocks_per_cu in {1,2,4,8,0}) and EB_FUSED_SEPARATE on the
+ * caller's grid and buffers, sets the fastest of each (eb_set_gather_shape,
+ * eb_set_fused_shape, eb_set_fused_mode) and reports them.  Outputs hold valid results afterwards (all shapes give the
  * same bits).  Synchronizes `stream`. */
 typedef struct {
   int32_t gather_tile, gather_unroll, gather_xcd_remap;
@@ -395,6 +405,8 @@ typedef struct {
   int32_t fused_tile, fused_unroll, fused_blocks_per_cu;
   float fused_ms;
   int32_t n_tried;
+  int32_t fused_separate;  /* 1 if EB_FUSED_SEPARATE was faster and is set */
+  float separate_ms;
 } eb_tuning;
 int eb_autotune(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
                 const double *coords, const double *grad_n, const double *grad_b,

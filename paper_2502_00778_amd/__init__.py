@@ -15,7 +15,7 @@ from .api import (REDUCE, VOL_MODE, Topology, build_edges, check_errors,  # noqa
 from ._lib import EbError  # noqa: F401
 from .autograd import EdgeMetrics, edge_metrics  # noqa: F401
 from .batch import (Batch, ForwardBackwardGraph, autotune, batch_offsets,  # noqa: F401
-                    concat_host, forward_backward, get_fused_shape, set_fused_shape,
-                    set_fused_wait_limit)
+                    concat_host, forward_backward, get_fused_mode, get_fused_shape,
+                    set_fused_mode, set_fused_shape, set_fused_wait_limit)
 
 __version__ = "0.1.0"

@@ -26,7 +26,7 @@ EXPORTS = ("eb_workspace_bytes", "eb_backward_workspace_bytes", "eb_build_edges"
            "eb_batch_offsets", "eb_batch_forward_backward", "eb_batch_graph_create",
            "eb_graph_launch", "eb_graph_destroy", "eb_set_fused_shape", "eb_get_fused_shape",
            "eb_set_fused_wait_limit", "eb_autotune", "eb_edge_residual",
-           "eb_directed_areas_variant")
+           "eb_directed_areas_variant", "eb_set_fused_mode", "eb_get_fused_mode")
 
 TOPO_FIELDS = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign",
                "edge_inc_off", "edge_inc", "node_inc_off", "node_inc", "node_sell_off",
@@ -52,7 +52,8 @@ class EbTuning(ctypes.Structure):
                 ("gather_xcd_remap", ctypes.c_int32), ("gather_ms", ctypes.c_float),
                 ("fused_tile", ctypes.c_int32), ("fused_unroll", ctypes.c_int32),
                 ("fused_blocks_per_cu", ctypes.c_int32), ("fused_ms", ctypes.c_float),
-                ("n_tried", ctypes.c_int32)]
+                ("n_tried", ctypes.c_int32), ("fused_separate", ctypes.c_int32),
+                ("separate_ms", ctypes.c_float)]
 
 
 class EbError(RuntimeError):
@@ -111,6 +112,8 @@ def lib():
     L.eb_get_fused_shape.argtypes = [ctypes.POINTER(ctypes.c_int)] * 3
     L.eb_get_fused_shape.restype = None
     L.eb_set_fused_wait_limit.argtypes = [i64]
+    L.eb_set_fused_mode.argtypes = [i32]
+    L.eb_get_fused_mode.restype = i32
     L.eb_autotune.argtypes = [SZ, TP, P, P, P, P, P, P, P, P, P, P, sz, i32, P,
                               ctypes.POINTER(EbTuning)]
     L.eb_edge_residual.argtypes = [SZ, TP, P, P, P, P, P, i32, P, P, sz, P]

@@ -22,7 +22,10 @@ from . import api
 from ._lib import EbTuning, check, lib
 
 __all__ = ["concat_host", "Batch", "batch_offsets", "forward_backward", "ForwardBackwardGraph",
-           "set_fused_shape", "get_fused_shape", "set_fused_wait_limit", "autotune"]
+           "set_fused_shape", "get_fused_shape", "set_fused_mode", "get_fused_mode",
+           "set_fused_wait_limit", "autotune"]
+
+FUSED_MODE = {"persistent": 0, "separate": 1}
 
 
 def concat_host(meshes):
@@ -160,6 +163,15 @@ def get_fused_shape():
     return a.value, b.value, c.value
 
 
+def set_fused_mode(mode: str):
+    """eb_set_fused_mode: 'persistent' (one persistent kernel) or 'separate'."""
+    check(lib().eb_set_fused_mode(FUSED_MODE[mode]), "eb_set_fused_mode")
+
+
+def get_fused_mode() -> str:
+    return {v: k for k, v in FUSED_MODE.items()}[int(lib().eb_get_fused_mode())]
+
+
 def set_fused_wait_limit(spins: int):
     check(lib().eb_set_fused_wait_limit(int(spins)), "eb_set_fused_wait_limit")
 
@@ -183,6 +195,7 @@ def autotune(coords, topo, elems, grad_n=None, grad_b=None, grad_vol=None, reps:
             r = db[key]
             api.set_gather_shape(r["gather_tile"], r["gather_unroll"], r["gather_xcd_remap"])
             set_fused_shape(r["fused_tile"], r["fused_unroll"], r["fused_blocks_per_cu"])
+            set_fused_mode("separate" if r.get("fused_separate") else "persistent")
             return dict(r, cached=True)
     args, _ = _fb_args(coords, topo, elems, grad_n, grad_b, grad_vol, out)
     t = EbTuning()

@@ -162,7 +162,15 @@ int launch_fused_kernel(K kernel, int tn, const FwdArgs &a, const FusedPlan &p, 
 }
 
 template <int D>
-int fused_impl(const FwdArgs &a, const FusedCfg &cfg, hipStream_t s) {
+int fused_impl(const FwdArgs &a0, const FusedCfg &cfg, hipStream_t s) {
+  if (cfg.separate) {  // the same work as the gather calls, one after the other
+    const LaunchCfg g = default_cfg();
+    FwdArgs a = a0;
+    a.xcd_remap = g.xcd_remap;
+    EB_TRY(forward_impl<D>(a, EB_REDUCE_GATHER, g, s));
+    return backward_impl<D>(a, EB_REDUCE_GATHER, g, s);
+  }
+  const FwdArgs &a = a0;
   const int64_t tn = cfg.tile;
   FusedPlan p{};
   p.nF = (a.nv + tn - 1) / tn;
@@ -442,7 +450,7 @@ int eb_set_fused_shape(int tile, int unroll, int blocks_per_cu) {
     set_detail("tile must be 64/128/256, unroll 1/2/4, blocks_per_cu 0..32");
     return EB_EINVAL;
   }
-  FusedCfg c;
+  FusedCfg c = fused_cfg();
   c.tile = tile;
   c.unroll = unroll;
   c.blocks_per_cu = blocks_per_cu;
@@ -456,6 +464,20 @@ void eb_get_fused_shape(int *tile, int *unroll, int *blocks_per_cu) {
   if (unroll) *unroll = c.unroll;
   if (blocks_per_cu) *blocks_per_cu = c.blocks_per_cu;
 }
+
+int eb_set_fused_mode(int mode) {
+  clear_detail();
+  if (mode != EB_FUSED_PERSISTENT && mode != EB_FUSED_SEPARATE) {
+    set_detail("mode must be EB_FUSED_PERSISTENT or EB_FUSED_SEPARATE");
+    return EB_EINVAL;
+  }
+  FusedCfg c = fused_cfg();
+  c.separate = mode == EB_FUSED_SEPARATE;
+  set_fused_cfg(c);
+  return EB_OK;
+}
+
+int eb_get_fused_mode(void) { return fused_cfg().separate ? EB_FUSED_SEPARATE : EB_FUSED_PERSISTENT; }
 
 int eb_set_fused_wait_limit(int64_t spins) {
   clear_detail();
@@ -533,6 +555,7 @@ int eb_autotune(const eb_sizes *sizes, const eb_topology *topo, const int32_t *e
     for (int ui = 0; ui < 3 && rc == EB_OK; ++ui)
       for (int pi = 0; pi < 5 && rc == EB_OK; ++pi) {
         FusedCfg c;
+        c.separate = 0;
         c.tile = tiles[ti];
         c.unroll = unrolls[ui];
         c.blocks_per_cu = per_cu[pi];
@@ -553,6 +576,29 @@ int eb_autotune(const eb_sizes *sizes, const eb_topology *topo, const int32_t *e
           best.fused_blocks_per_cu = c.blocks_per_cu;
         }
       }
+  // the gather kernels in sequence (with the best gather shape) as one more
+  // candidate for the whole enqueue
+  if (rc == EB_OK) {
+    LaunchCfg g;
+    g.tile = best.gather_tile;
+    g.unroll = best.gather_unroll;
+    g.xcd_remap = best.gather_xcd_remap;
+    set_gather_cfg(g);
+    FusedCfg c;
+    c.separate = 1;
+    set_fused_cfg(c);
+    float ms = 0.f;
+    rc = time_it(
+        [&]() {
+          return eb_batch_forward_backward(sizes, topo, elem, coords, grad_n, grad_b, grad_vol,
+                                           n_edge, b_node, vol, grad_coords, ws, ws_bytes,
+                                           stream);
+        },
+        ms);
+    ++tried;
+    best.separate_ms = ms;
+    best.fused_separate = ms < best.fused_ms ? 1 : 0;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != EB_OK) {
@@ -569,6 +615,7 @@ int eb_autotune(const eb_sizes *sizes, const eb_topology *topo, const int32_t *e
   f.tile = best.fused_tile;
   f.unroll = best.fused_unroll;
   f.blocks_per_cu = best.fused_blocks_per_cu;
+  f.separate = best.fused_separate;
   set_fused_cfg(f);
   best.n_tried = tried;
   *out = best;

@@ -40,7 +40,7 @@ struct FwdArgs {
 // (64/128/256), loads in flight per thread (1/2/4), XCD-aware tile order.
 struct LaunchCfg {
   int tile = 128;
-  int unroll = 2;
+  int unroll = 4;
   int xcd_remap = 1;
 };
 
@@ -51,6 +51,7 @@ struct FusedCfg {
   int tile = 128;
   int unroll = 2;
   int blocks_per_cu = 0;
+  int separate = 0;  // 1: the gather forward and adjoint kernels in sequence instead
 };
 FusedCfg fused_cfg();
 void set_fused_cfg(const FusedCfg &c);
@@ -94,6 +95,7 @@ int check_fwd_gather(const eb_sizes *sizes, const FwdArgs &a);
 // also points a.gpiece into the workspace
 int check_bwd_gather(const eb_sizes *sizes, FwdArgs &a, void *ws, size_t ws_bytes);
 
+template <int D> int launch_fwd_nodes(const FwdArgs &a, const LaunchCfg &cfg, hipStream_t s);
 template <int D> int forward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_t s);
 template <int D>
 int volumes_impl(const FwdArgs &a, int mode, int reduce, const double *n_edge, hipStream_t s);

@@ -94,12 +94,6 @@ __global__ __launch_bounds__(256) void k_fwd_atomic_bface(FwdArgs a) {
 // ------------------------------------------------------------- gather path
 // (device bodies in eb_gather.h)
 
-template <int D, int TN, int CAP, int U, bool WIDE>
-__global__ __launch_bounds__(TN) void k_fwd_gather(FwdArgs a) {
-  __shared__ double acc[D][CAP];
-  fwd_node_tile<D, TN, CAP, U, WIDE>(a, tile_of_block(gridDim.x, a.xcd_remap), acc);
-}
-
 template <int D, int TN, int CAP, int U, bool WIDE, int VAR>
 __global__ __launch_bounds__(TN) void k_fwd_gather_variant(FwdArgs a) {
   __shared__ double acc[D][CAP];
@@ -317,29 +311,8 @@ template <int D> int launch_fwd_boundary(const FwdArgs &a, hipStream_t s);
 
 template <int D>
 int launch_fwd_gather(const FwdArgs &a, const LaunchCfg &cfg, hipStream_t s) {
-  const int64_t ntiles = (a.nv + cfg.tile - 1) / cfg.tile;
-  const dim3 grid((unsigned)ntiles);
-#define EB_GATHER_CASE(TN_, CAP_, U_)                                                   \
-  if (cfg.tile == TN_ && cfg.unroll == U_) {                                            \
-    if (a.sell_wide)                                                                    \
-      launch_principal((k_fwd_gather<D, TN_, CAP_, U_, true>), grid, dim3(TN_), 0, s, a); \
-    else                                                                                \
-      launch_principal((k_fwd_gather<D, TN_, CAP_, U_, false>), grid, dim3(TN_), 0, s, a); \
-    EB_LAUNCH_CHECK();                                                                  \
-    return launch_fwd_boundary<D>(a, s);                                                \
-  }
-  EB_GATHER_CASE(64, 512, 1)
-  EB_GATHER_CASE(64, 512, 2)
-  EB_GATHER_CASE(64, 512, 4)
-  EB_GATHER_CASE(128, 1024, 1)
-  EB_GATHER_CASE(128, 1024, 2)
-  EB_GATHER_CASE(128, 1024, 4)
-  EB_GATHER_CASE(256, 2048, 1)
-  EB_GATHER_CASE(256, 2048, 2)
-  EB_GATHER_CASE(256, 2048, 4)
-#undef EB_GATHER_CASE
-  set_detail("unsupported gather tile %d / unroll %d", cfg.tile, cfg.unroll);
-  return EB_EINVAL;
+  EB_TRY(launch_fwd_nodes<D>(a, cfg, s));
+  return launch_fwd_boundary<D>(a, s);
 }
 
 template <int D>
@@ -356,20 +329,20 @@ int forward_variant_impl(const FwdArgs &a, int variant, const LaunchCfg &cfg, hi
   const int64_t ntiles = (a.nv + cfg.tile - 1) / cfg.tile;
   const dim3 grid((unsigned)ntiles);
   if (variant == 0) return launch_fwd_gather<D>(a, cfg, s);
-  // one shape (128 nodes, 2 loads in flight): these variants are for comparison
+  // one shape (128 nodes, 4 loads in flight, as the default): for comparison
   if (a.sell_wide) {
     if (variant == 1)
-      launch_principal((k_fwd_gather_variant<D, 128, 1024, 2, true, VAR_EDGE>), grid, dim3(128), 0,
+      launch_principal((k_fwd_gather_variant<D, 128, 1024, 4, true, VAR_EDGE>), grid, dim3(128), 0,
                        s, a);
     else
-      launch_principal((k_fwd_gather_variant<D, 128, 1024, 2, true, VAR_DUAL>), grid, dim3(128), 0,
+      launch_principal((k_fwd_gather_variant<D, 128, 1024, 4, true, VAR_DUAL>), grid, dim3(128), 0,
                        s, a);
   } else {
     if (variant == 1)
-      launch_principal((k_fwd_gather_variant<D, 128, 1024, 2, false, VAR_EDGE>), grid, dim3(128),
+      launch_principal((k_fwd_gather_variant<D, 128, 1024, 4, false, VAR_EDGE>), grid, dim3(128),
                        0, s, a);
     else
-      launch_principal((k_fwd_gather_variant<D, 128, 1024, 2, false, VAR_DUAL>), grid, dim3(128),
+      launch_principal((k_fwd_gather_variant<D, 128, 1024, 4, false, VAR_DUAL>), grid, dim3(128),
                        0, s, a);
   }
   EB_LAUNCH_CHECK();

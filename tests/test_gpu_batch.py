@@ -181,7 +181,31 @@ def test_fused_bitwise_across_shapes(small3):
                 for a, r in zip(got, ref):
                     assert torch.equal(a, r), (tile, unroll, per_cu)
     eb().set_fused_shape(128, 2, 0)
+    eb().set_fused_mode("separate")
+    got = bc.fused()
+    eb().set_fused_mode("persistent")
+    for a, r in zip(got, ref):
+        assert torch.equal(a, r), "separate mode"
     eb().check_errors(bc.topo)
+
+
+@pytest.mark.parametrize("mode", ["persistent", "separate"])
+def test_graph_modes_equal_eager(small2, mode):
+    """Both forms of the enqueue capture into a graph that replays the eager
+    result."""
+    bc = small2
+    eb().set_fused_mode(mode)
+    try:
+        ref = bc.fused()
+        gr = eb().ForwardBackwardGraph(bc.X, bc.topo, bc.E, bc.W, bc.B, bc.C)
+        for _ in range(2):
+            outs = gr.launch()
+            torch.cuda.synchronize()
+            for a, b in zip(outs, ref):
+                assert torch.equal(a, b)
+        gr.close()
+    finally:
+        eb().set_fused_mode("persistent")
 
 
 def test_graph_replays_equal_eager(small3):
@@ -221,7 +245,7 @@ def test_autotune_and_cache(small3, tmp_path):
     cache = str(tmp_path / "tune.json")
     r = eb().autotune(bc.X, bc.topo, bc.E, bc.W, bc.B, bc.C, reps=2, cache=cache)
     say(f"[autotune] {r}")
-    assert not r["cached"] and r["n_tried"] == 18 + 45
+    assert not r["cached"] and r["n_tried"] == 18 + 45 + 1
     assert r["gather_tile"] in (64, 128, 256) and r["fused_tile"] in (64, 128, 256)
     assert eb().get_fused_shape() == (r["fused_tile"], r["fused_unroll"],
                                       r["fused_blocks_per_cu"])
@@ -231,7 +255,8 @@ def test_autotune_and_cache(small3, tmp_path):
     r2 = eb().autotune(bc.X, bc.topo, bc.E, bc.W, bc.B, bc.C, cache=cache)
     assert r2["cached"] and json.load(open(cache))
     eb().set_fused_shape(128, 2, 0)
-    eb().set_gather_shape(128, 2, 1)
+    eb().set_fused_mode("persistent")
+    eb().set_gather_shape(128, 4, 1)
 
 
 def test_offsets_reject_cross_mesh_element(small3):
