@@ -117,14 +117,29 @@ typedef struct {
  *                                 node_inc row, column-major: entry (r, lane)
  *                                 at node_sell_off[slice] + 64 r + lane for
  *                                 r < L (entries past a node's row are 0).
- *                                 Entry r of node j describes node_inc row
- *                                 entry r (element E, local l): for m < dim
- *                                 let o_m = elem[E][m], except o_l =
- *                                 elem[E][dim] (j's place taken by the last
- *                                 vertex), and let slot_m = the position of
- *                                 edge (j, o_m) among j's out-edges (those
- *                                 with tail j, in node_edge_off order), or the
- *                                 field's all-ones value when o_m < j; code =
+ *                                 The entries of node j are its node_inc
+ *                                 row's incidences.  A row of at most 32
+ *                                 is stored as a strip: first its smallest
+ *                                 incidence, then repeatedly, of those not
+ *                                 yet stored in ascending order, the first
+ *                                 that shares at least dim-1 distinct other
+ *                                 vertices with the last stored, else the
+ *                                 first sharing the most; a longer row is
+ *                                 stored ascending.  For incidence (element
+ *                                 E, local l), local order of the other
+ *                                 vertices: p_m = elem[E][m] for m < dim,
+ *                                 except p_l = elem[E][dim].  In a strip they
+ *                                 take places: a vertex the previous entry
+ *                                 holds keeps its place there (place k is
+ *                                 matched to the first unmatched p_m equal
+ *                                 to it), the rest fill the free places in
+ *                                 local order; the first entry, and every
+ *                                 entry of a longer row, keep local order.
+ *                                 o_m = the vertex in place m; slot_m = the
+ *                                 position of edge (j, o_m) among j's
+ *                                 out-edges (those with tail j, in
+ *                                 node_edge_off order), or the field's
+ *                                 all-ones value when o_m < j; code =
  *                                 sum_m slot_m << (B m).  Narrow (sell_wide =
  *                                 0): B = 5, one word, bits 16m..16m+15 =
  *                                 o_m - j as int16, bits 48..62 = code.  Wide
@@ -133,10 +148,17 @@ typedef struct {
  *                                 B = 10, two words per entry (entry index
  *                                 times 2), word 0 = o_0 | o_1 << 32, word 1
  *                                 = o_2 | code << 32 (o_2 = 0 in 2D).
+ *                                 (Consecutive entries of a strip differ in
+ *                                 one place, so a reader walking a row keeps
+ *                                 the other points.)
  *   inc_sell       [(dim+1)*n_elems]  optional (NULL skips; the gather
- *                                 adjoint needs it): entry index in node_sell
- *                                 of incidence elem*(dim+1) + local, i.e. the
- *                                 inverse of the sliced layout
+ *                                 adjoint needs it): slot of incidence
+ *                                 elem*(dim+1) + local in the sliced layout
+ *                                 with rows in ascending order, i.e.
+ *                                 node_sell_off[j/64] + 64 r + j%64 for the
+ *                                 incidence's rank r in node j's node_inc
+ *                                 row (the adjoint's per-incidence pieces
+ *                                 live there)
  *   node_in_off    [n_nodes+1]    ids of edges whose head is the node,
  *   node_in_edge   [n_edges]        ascending per node
  *   bface          [n_bfaces][dim] boundary elements (faces of exactly one

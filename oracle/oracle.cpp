@@ -43,18 +43,29 @@
 //   edge_inc    CSR over edges of elem*ne+local, ascending
 //   node_inc    CSR over nodes of elem*(D+1)+local, ascending
 //   node_sell   node_inc rows in sliced ELL form: slices of 64 nodes, each
-//               as long as its longest row, column-major (entry (r, lane) at
-//               slice offset + 64 r + lane, zero past a row's end).  Entry r
-//               of node j (element E, local l): o_m = E's vertex m for m < D,
-//               except that j's own place l is taken by vertex D; slot_m =
-//               rank of edge (j, o_m) among the edges whose tail is j, or 31
-//               (all ones) when o_m < j; code = sum slot_m << (B m).  Narrow
+//               as long as its longest row, column-major (entry (c, lane) at
+//               slice offset + 64 c + lane, zero past a row's end).  A row of
+//               at most 32 incidences is stored as a strip: first its
+//               smallest incidence, then repeatedly, of those not yet stored
+//               in ascending order, the first sharing at least D-1 distinct
+//               other vertices with the last stored, else the first sharing
+//               the most; a longer row is stored ascending.
+//               The other vertices of incidence (element E, local l) in
+//               local order are E's vertices m < D with j's place l taken by
+//               vertex D.  In a strip they go to D places: a vertex that the
+//               previous entry holds keeps its place there, the others fill
+//               the free places in local order (the first entry, and every
+//               entry of a longer row, keeps local order).  o_m is the vertex
+//               in place m; s_m = rank of edge (j, o_m) among the edges whose
+//               tail is j, or 31 (all ones) when o_m < j;
+//               code = sum s_m << (B m).  Narrow
 //               (B = 5): one word with o_m - j as int16 in bits 16m.. and
 //               code in bits 48..; wide (B = 10; when some |o_m - j| >
 //               32767 or some node has more than 31 out-edges): two words
 //               o_0 | o_1 << 32 and o_2 | code << 32
-//   inc_sell    [(D+1) NE] entry index in node_sell of each incidence
-//               e*(D+1)+l (the inverse of the sliced layout)
+//   inc_sell    [(D+1) NE] slot of each incidence e*(D+1)+l in the sliced
+//               layout with rows in ascending order (column = rank of the
+//               incidence in node_inc's row), whatever order node_sell uses
 //   node_edge_off  CSR offsets of edges by tail
 //   node_in     CSR over nodes of the ids of edges whose head is the node
 //   bface       [NB][D] faces owned by one element, in ascending sorted-id
@@ -73,6 +84,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <iterator>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -277,6 +289,9 @@ template <class It, class Cmp> void sort_range(It b, It e, Cmp c) {
 #endif
 }
 
+// longest node_inc row stored as a strip in the sliced layout
+constexpr int32_t kStripMax = 32;
+
 struct KeyPay {
   uint64_t key;
   uint32_t pay;
@@ -406,15 +421,72 @@ int build_topology(Topo &t, int dim, int64_t nv, int64_t nelem, const int32_t *e
     t.sell_wide = (maxdelta > 32767 || maxout > 31) ? 1 : 0;
     const int B = t.sell_wide ? 10 : 5;
     const uint32_t none = (1u << B) - 1;
+    // each row's storage order and each entry's vertex order (see the
+    // layout notes at the top)
     std::vector<int32_t> others((size_t)t.node_inc.size() * dim);
+    std::vector<int32_t> column(t.node_inc.size());  // storage rank in the row
     std::vector<uint32_t> codes(t.node_inc.size());
-    for (int64_t v = 0; v < nv; ++v)
-      for (int32_t r = t.node_inc_off[v]; r < t.node_inc_off[v + 1]; ++r) {
-        const int64_t e = t.node_inc[r] / nn;
-        const int l = t.node_inc[r] % nn;
+    for (int64_t v = 0; v < nv; ++v) {
+      const int32_t r0 = t.node_inc_off[v], len = t.node_inc_off[v + 1] - r0;
+      std::vector<std::vector<int32_t>> loc(len);
+      for (int32_t i = 0; i < len; ++i) {
+        const int64_t e = t.node_inc[r0 + i] / nn;
+        const int l = t.node_inc[r0 + i] % nn;
+        for (int m = 0; m < dim; ++m) loc[i].push_back(elem[e * nn + (m == l ? dim : m)]);
+      }
+      std::vector<int32_t> order(len);
+      for (int32_t i = 0; i < len; ++i) order[i] = i;
+      if (len <= kStripMax && len > 0) {
+        std::vector<char> taken(len, 0);
+        taken[0] = 1;
+        for (int32_t c = 1; c < len; ++c) {
+          int best = -1, shared_best = -1;
+          for (int32_t i = 0; i < len; ++i) {
+            if (taken[i]) continue;
+            // distinct vertices in common
+            std::vector<int32_t> p = loc[i], q = loc[order[c - 1]], both;
+            std::sort(p.begin(), p.end());
+            std::sort(q.begin(), q.end());
+            std::set_intersection(p.begin(), p.end(), q.begin(), q.end(),
+                                  std::back_inserter(both));
+            const int shared = (int)(std::unique(both.begin(), both.end()) - both.begin());
+            if (shared > shared_best) {
+              shared_best = shared;
+              best = i;
+              if (shared >= dim - 1) break;
+            }
+          }
+          order[c] = best;
+          taken[best] = 1;
+        }
+      }
+      std::vector<int32_t> slots(dim, -1);
+      for (int32_t c = 0; c < len; ++c) {
+        const int32_t i = order[c];
+        const std::vector<int32_t> &o = loc[i];
+        std::vector<int32_t> next = o;
+        if (len <= kStripMax) {
+          // place k keeps its vertex when the first unmatched o_m equal to
+          // it exists; unmatched o_m then fill the other places in order
+          std::vector<char> matched(dim, 0), kept(dim, 0);
+          for (int k = 0; k < dim; ++k)
+            for (int m = 0; m < dim && !kept[k]; ++m)
+              if (!matched[m] && o[m] == slots[k]) kept[k] = matched[m] = 1;
+          int k = 0;
+          for (int m = 0; m < dim; ++m) {
+            if (matched[m]) continue;
+            while (kept[k]) ++k;
+            next[k++] = o[m];
+          }
+          for (int kk = 0; kk < dim; ++kk)
+            if (kept[kk]) next[kk] = slots[kk];
+        }
+        slots = next;
+        const int32_t r = r0 + i;
+        column[r] = c;
         uint32_t code = 0;
         for (int m = 0; m < dim; ++m) {
-          const int32_t om = elem[e * nn + (m == l ? dim : m)];
+          const int32_t om = next[m];
           uint32_t rank = none;
           if (om > v) rank = (uint32_t)(find_edge(t, (int32_t)v, om) - t.node_edge_off[v]);
           code |= rank << (B * m);
@@ -422,12 +494,14 @@ int build_topology(Topo &t, int dim, int64_t nv, int64_t nelem, const int32_t *e
         }
         codes[r] = code;
       }
+    }
     t.node_sell.assign((size_t)t.n_sell * (t.sell_wide ? 2 : 1), 0);
     t.inc_sell.assign(t.node_inc.size(), -1);
     for (int64_t v = 0; v < nv; ++v)
       for (int32_t r = t.node_inc_off[v]; r < t.node_inc_off[v + 1]; ++r) {
-        const int64_t pos = t.node_sell_off[v / 64] + 64 * (r - t.node_inc_off[v]) + v % 64;
-        t.inc_sell[t.node_inc[r]] = (int32_t)pos;
+        const int64_t pos = t.node_sell_off[v / 64] + 64 * column[r] + v % 64;
+        t.inc_sell[t.node_inc[r]] =
+            (int32_t)(t.node_sell_off[v / 64] + 64 * (r - t.node_inc_off[v]) + v % 64);
         const int32_t *o = &others[(size_t)r * dim];
         if (!t.sell_wide) {
           uint64_t w = (uint64_t)codes[r] << 48;

@@ -136,10 +136,10 @@ __device__ __forceinline__ void bface_grad_all(const V3 (&P)[D], V3 W, V3 (&G)[D
 // ------------------------------------------------------------- gather path
 //
 // Two passes, no atomics.  The element pass forms dL_E/dx_i for every vertex
-// i of element E once and stores it at the node_sell position of incidence
-// (E, i) (inc_sell), so the pieces of node j's column sit where the sliced
-// layout puts j's elements: slice-major, 64 lanes side by side.  The node
-// pass then sums j's column in node_inc order with coalesced loads, and the
+// i of element E once and stores it at the sliced slot of incidence (E, i)
+// (inc_sell: column = rank of the incidence in node_inc's row), so the pieces
+// of node j's column sit slice-major, 64 lanes side by side.  The node pass
+// then sums j's column in node_inc order with coalesced loads, and the
 // boundary pass adds j's boundary faces in bnode_face order.
 
 template <int D> struct GP {  // one gradient piece: 3D double4 (pad), 2D double2

@@ -109,6 +109,12 @@ __device__ __forceinline__ V3 dual_piece(const V3 &xj, const V3 (&P)[D]) {
   }
 }
 
+// c ? a : b by component (a select of whole structs can become a select of
+// their addresses, which sends both to scratch memory)
+__device__ __forceinline__ V3 pick(bool c, const V3 &a, const V3 &b) {
+  return V3{c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z};
+}
+
 template <int D, int TN, int CAP, int U, bool WIDE, int VAR = VAR_NODE>
 __device__ __forceinline__ void fwd_node_tile(const FwdArgs &a, int64_t tile,
                                               double (&acc)[D][CAP]) {
@@ -154,8 +160,58 @@ __device__ __forceinline__ void fwd_node_tile(const FwdArgs &a, int64_t tile,
     double vs = 0.0;
     const int32_t len = a.node_inc_off[j + 1] - a.node_inc_off[j];
     const int64_t p0 = (int64_t)a.node_sell_off[j / SELL] + (j % SELL);
-    // chunks of U incidences; the next chunk's entries are loaded while the
-    // current chunk's coordinates are in flight
+    // One incidence with the points of its other vertices by place.
+    auto form = [&](const V3 (&P)[D], uint32_t code) __attribute__((always_inline)) {
+      V3 c;
+      if constexpr (D == 3)
+        c = cross(P[1] - P[0], P[2] - P[0]);
+      else
+        c = rot2(P[1] - P[0]);
+      double d = dot(c, P[0] - xj);
+      const double sg = d < 0.0 ? -1.0 : 1.0;  // the flip applied to c
+      if (d < 0.0) {
+        c = -c;
+        d = -d;
+      } else if (d == 0.0) {
+        raise_status(a.st, EB_EDEGENERATE, j);
+      }
+      vs += d;
+      if constexpr (VAR == VAR_NODE) {
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+          const int s = slot_of<WIDE>(code, m);
+          if (s != no_slot<WIDE>()) add(s, c);
+        }
+      } else {
+        auto edge_term = [&](auto mm) {
+          constexpr int m = decltype(mm)::value;
+          const int s = slot_of<WIDE>(code, m);
+          if (s == no_slot<WIDE>()) return;
+          if constexpr (VAR == VAR_EDGE) {
+            // the same face vector from the vertex order rotated by m
+            V3 ce;
+            if constexpr (D == 3)
+              ce = cross(P[(m + 1) % 3] - P[m], P[(m + 2) % 3] - P[m]);
+            else
+              ce = m == 0 ? rot2(P[1] - P[0]) : -rot2(P[0] - P[1]);
+            add(s, sg * ce);
+          } else {
+            add(s, dual_piece<D, m>(xj, P));
+          }
+        };
+        edge_term(std::integral_constant<int, 0>{});
+        edge_term(std::integral_constant<int, 1>{});
+        if constexpr (D == 3) edge_term(std::integral_constant<int, 2>{});
+      }
+    };
+    // Chunks of U entries in storage order; the next chunk's entries are
+    // read while the current chunk's coordinates are in flight.  Consecutive
+    // entries of a strip differ in one place, whose point alone is loaded
+    // (the others stay in registers), so a chunk issues U points instead of
+    // U D.  A chunk in which some lane's entry changes more than one place
+    // (a row start, a break in the strip) loads every place of every entry;
+    // the choice is made for the whole wave, so each path waits exactly for
+    // its own loads.
     int32_t on[U][D];
     uint32_t cn[U];
     if (len > 0)
@@ -163,70 +219,66 @@ __device__ __forceinline__ void fwd_node_tile(const FwdArgs &a, int64_t tile,
       for (int u = 0; u < U; ++u)
         sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(u, len - 1), (int32_t)j, on[u],
                             cn[u]);
+    int32_t S[D];  // the previous entry's vertices by place, and their points
+    V3 P[D];
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+      S[m] = -1;
+      P[m] = V3{0.0, 0.0, 0.0};
+    }
+    // waves whose lanes all end early skip the loop together
     for (int32_t r = 0; r < len; r += U) {
       int32_t o[U][D];
       uint32_t code[U];
+      bool multi = false;
+      bool pk[U][D];  // the place entry u changes (the first, if several)
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         code[u] = cn[u];
+        bool seen = false;
 #pragma unroll
-        for (int m = 0; m < D; ++m) o[u][m] = on[u][m];
+        for (int m = 0; m < D; ++m) {
+          o[u][m] = on[u][m];
+          const bool ch = o[u][m] != (u == 0 ? S[m] : o[u - 1][m]);
+          pk[u][m] = ch && !seen;
+          multi = multi || (ch && seen);
+          seen = seen || ch;
+        }
       }
-      V3 P[U][D];
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int m = 0; m < D; ++m) P[u][m] = load_pt<D>(a.X, o[u][m]);
       if (r + U < len)
 #pragma unroll
         for (int u = 0; u < U; ++u)
           sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(r + U + u, len - 1),
                               (int32_t)j, on[u], cn[u]);
+      if (__builtin_amdgcn_ballot_w64(multi) == 0) {
+        V3 L[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (r + u >= len) break;
-        V3 c;
-        if constexpr (D == 3)
-          c = cross(P[u][1] - P[u][0], P[u][2] - P[u][0]);
-        else
-          c = rot2(P[u][1] - P[u][0]);
-        double d = dot(c, P[u][0] - xj);
-        const double sg = d < 0.0 ? -1.0 : 1.0;  // the flip applied to c
-        if (d < 0.0) {
-          c = -c;
-          d = -d;
-        } else if (d == 0.0) {
-          raise_status(a.st, EB_EDEGENERATE, j);
-        }
-        vs += d;
-        if constexpr (VAR == VAR_NODE) {
+        for (int u = 0; u < U; ++u) {
+          int32_t id = o[u][0];  // (an unchanged entry reloads place 0)
 #pragma unroll
-          for (int m = 0; m < D; ++m) {
-            const int s = slot_of<WIDE>(code[u], m);
-            if (s != no_slot<WIDE>()) add(s, c);
-          }
-        } else {
-          auto edge_term = [&](auto mm) {
-            constexpr int m = decltype(mm)::value;
-            const int s = slot_of<WIDE>(code[u], m);
-            if (s == no_slot<WIDE>()) return;
-            if constexpr (VAR == VAR_EDGE) {
-              // the same face vector from the vertex order rotated by m
-              V3 ce;
-              if constexpr (D == 3)
-                ce = cross(P[u][(m + 1) % 3] - P[u][m], P[u][(m + 2) % 3] - P[u][m]);
-              else
-                ce = m == 0 ? rot2(P[u][1] - P[u][0]) : -rot2(P[u][0] - P[u][1]);
-              add(s, sg * ce);
-            } else {
-              add(s, dual_piece<D, m>(xj, P[u]));
-            }
-          };
-          edge_term(std::integral_constant<int, 0>{});
-          edge_term(std::integral_constant<int, 1>{});
-          if constexpr (D == 3) edge_term(std::integral_constant<int, 2>{});
+          for (int m = 1; m < D; ++m) id = pk[u][m] ? o[u][m] : id;
+          L[u] = load_pt<D>(a.X, id);
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+          for (int m = 0; m < D; ++m) P[m] = pick(pk[u][m], L[u], P[m]);
+          if (r + u < len) form(P, code[u]);
+        }
+      } else {
+        V3 Q[U][D];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int m = 0; m < D; ++m) Q[u][m] = load_pt<D>(a.X, o[u][m]);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (r + u < len) form(Q[u], code[u]);
+#pragma unroll
+        for (int m = 0; m < D; ++m) P[m] = Q[U - 1][m];
       }
+#pragma unroll
+      for (int m = 0; m < D; ++m) S[m] = o[U - 1][m];
     }
     if (a.vol) a.vol[j] = vs * GK<D>::kV;
     if (!in_lds)

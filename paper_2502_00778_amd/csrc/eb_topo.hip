@@ -773,6 +773,214 @@ __global__ void k_elem_maps(const int32_t *__restrict__ elem, int64_t nelem,
   }
 }
 
+// ------------------------------------------------ strip order of the rows
+//
+// Once the element maps have read the rows in ascending order, each row of
+// at most STRIP entries is rewritten as a strip: first its smallest
+// incidence, then repeatedly, of those not yet taken in ascending order, the
+// first that shares at least D-1 distinct other vertices with the last taken
+// (a face of the node's link), else the first sharing the most.  Each
+// entry's other vertices (and their out-edge slots with them) are then put
+// in places: a vertex the previous entry holds keeps its place there, the
+// others fill the free places in order.  Consecutive entries of a strip thus
+// differ in one place, which the forward pass exploits (it loads only the
+// changed point).  inc_sell keeps the ascending positions: it addresses the
+// adjoint's per-incidence pieces, whose node sums do not depend on the order
+// of the entries.  One thread per node; its row is staged in LDS.
+
+constexpr int SP_TB = 64;
+constexpr int STRIP = 32;  // longest row stored as a strip
+static_assert(STRIP <= 32, "the taken set is one 32-bit mask");
+
+template <int D, bool WIDE> struct SellEntry {
+  int32_t o[D];
+  uint32_t code;
+  static constexpr int B = WIDE ? 10 : 5;
+  __device__ __forceinline__ void decode(const uint64_t *w, int32_t j) {
+    if constexpr (WIDE) {
+      o[0] = (int32_t)(uint32_t)w[0];
+      o[1] = (int32_t)(uint32_t)(w[0] >> 32);
+      if constexpr (D == 3) o[2] = (int32_t)(uint32_t)w[1];
+      code = (uint32_t)(w[1] >> 32);
+    } else {
+#pragma unroll
+      for (int m = 0; m < D; ++m) o[m] = j + (int32_t)(int16_t)(uint16_t)(w[0] >> (16 * m));
+      code = (uint32_t)(w[0] >> 48) & 0x7fffu;
+    }
+  }
+  __device__ __forceinline__ void encode(uint64_t *w, int32_t j) const {
+    if constexpr (WIDE) {
+      w[0] = (uint64_t)(uint32_t)o[0] | ((uint64_t)(uint32_t)o[1] << 32);
+      w[1] = (uint64_t)(uint32_t)(D == 3 ? o[D - 1] : 0) | ((uint64_t)code << 32);
+    } else {
+      uint64_t x = (uint64_t)code << 48;
+#pragma unroll
+      for (int m = 0; m < D; ++m) x |= (uint64_t)(uint16_t)(int16_t)(o[m] - j) << (16 * m);
+      w[0] = x;
+    }
+  }
+  // places (see above): S holds the previous entry's vertices by place; place
+  // k keeps its vertex when an o_m not yet matched (the first such m) equals
+  // it, the unmatched o_m fill the other places in ascending order, and the
+  // slot fields move with their vertices
+  __device__ __forceinline__ void place(const int32_t (&S)[D]) {
+    constexpr uint32_t F = (1u << B) - 1u;
+    bool mt[D], kp[D];
+#pragma unroll
+    for (int m = 0; m < D; ++m) mt[m] = false;
+    int32_t no[D];
+    uint32_t nc[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      kp[k] = false;
+      no[k] = S[k];
+      nc[k] = F;
+#pragma unroll
+      for (int m = 0; m < D; ++m) {
+        const bool hit = !kp[k] && !mt[m] && o[m] == S[k];
+        nc[k] = hit ? (code >> (B * m)) & F : nc[k];
+        kp[k] = kp[k] || hit;
+        mt[m] = mt[m] || hit;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+      bool done = mt[m];
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const bool put = !done && !kp[k];
+        no[k] = put ? o[m] : no[k];
+        nc[k] = put ? (code >> (B * m)) & F : nc[k];
+        kp[k] = kp[k] || put;
+        done = done || put;
+      }
+    }
+    uint32_t c2 = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      o[k] = no[k];
+      c2 |= nc[k] << (B * k);
+    }
+    code = c2;
+  }
+};
+
+template <int D, bool WIDE>
+__global__ __launch_bounds__(SP_TB) void k_strip(int64_t nv, const int32_t *__restrict__ node_inc_off,
+                                                 const int32_t *__restrict__ node_sell_off,
+                                                 uint64_t *node_sell, const StatusBlock *st) {
+  constexpr int W = WIDE ? 2 : 1;
+  __shared__ uint64_t row[STRIP][W][SP_TB];
+  __shared__ uint8_t seq[STRIP][SP_TB];
+  const int t = threadIdx.x;
+  const int64_t j64 = (int64_t)blockIdx.x * SP_TB + t;
+  if (j64 >= nv || build_failed(st)) return;
+  const int32_t j = (int32_t)j64;
+  const int32_t len = node_inc_off[j + 1] - node_inc_off[j];
+  if (len > STRIP || len < 2) return;
+  const int64_t base = (int64_t)node_sell_off[j / SELL] + (j % SELL);
+  // the row into LDS, eight entries in flight (the tail rereads the last)
+  for (int32_t c0 = 0; c0 < len; c0 += 8) {
+    uint64_t w[8][W];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int k = 0; k < W; ++k)
+        w[u][k] = node_sell[W * (base + (int64_t)SELL * min(c0 + u, len - 1)) + k];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int k = 0; k < W; ++k) row[min(c0 + u, len - 1)][k][t] = w[u][k];
+  }
+  using E = SellEntry<D, WIDE>;
+  auto entry = [&](int32_t q) {
+    uint64_t w[2] = {row[q][0][t], WIDE ? row[q][W - 1][t] : 0};
+    E x;
+    x.decode(w, j);
+    return x;
+  };
+  // the strip (vertices compared as stored: offsets from j, or ids)
+  struct Key {
+    int32_t v[D];
+  };
+  auto key = [&](int32_t q) {
+    Key k;
+    if constexpr (WIDE) {
+      const uint64_t w0 = row[q][0][t];
+      k.v[0] = (int32_t)(uint32_t)w0;
+      k.v[1] = (int32_t)(uint32_t)(w0 >> 32);
+      if constexpr (D == 3) k.v[2] = (int32_t)(uint32_t)row[q][W - 1][t];
+    } else {
+      const uint64_t w0 = row[q][0][t];
+#pragma unroll
+      for (int m = 0; m < D; ++m) k.v[m] = (int32_t)(int16_t)(uint16_t)(w0 >> (16 * m));
+    }
+    return k;
+  };
+  auto shared = [](const Key &x, const Key &y) {
+    int n = 0;
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+      bool dup = false, in = false;
+#pragma unroll
+      for (int m2 = 0; m2 < m; ++m2) dup = dup || x.v[m2] == x.v[m];
+#pragma unroll
+      for (int k = 0; k < D; ++k) in = in || y.v[k] == x.v[m];
+      n += (!dup && in) ? 1 : 0;
+    }
+    return n;
+  };
+  Key cur = key(0);
+  seq[0][t] = 0;
+  uint32_t rest = (len >= 32 ? 0xffffffffu : (1u << len) - 1u) & ~1u;
+  for (int32_t c = 1; c < len; ++c) {
+    int best = 0, most = -1;
+    Key bk = cur;
+    // two candidates per round, both read before either is tested
+    for (uint32_t it = rest; it != 0u;) {
+      const int q0 = __builtin_ctz(it);
+      it &= it - 1u;
+      const int q1 = it != 0u ? __builtin_ctz(it) : q0;
+      const Key x0 = key(q0), x1 = key(q1);
+      const int s0 = shared(x0, cur);
+      if (s0 > most) {
+        most = s0;
+        best = q0;
+#pragma unroll
+        for (int m = 0; m < D; ++m) bk.v[m] = x0.v[m];
+        if (s0 >= D - 1) break;
+      }
+      if (it == 0u) break;
+      it &= it - 1u;
+      const int s1 = shared(x1, cur);
+      if (s1 > most) {
+        most = s1;
+        best = q1;
+#pragma unroll
+        for (int m = 0; m < D; ++m) bk.v[m] = x1.v[m];
+        if (s1 >= D - 1) break;
+      }
+    }
+    rest &= ~(1u << best);
+    cur = bk;
+    seq[c][t] = (uint8_t)best;
+  }
+  // places, written back in strip order
+  int32_t S[D];
+#pragma unroll
+  for (int m = 0; m < D; ++m) S[m] = -1;
+  for (int32_t c = 0; c < len; ++c) {
+    E x = entry(seq[c][t]);
+    x.place(S);
+#pragma unroll
+    for (int m = 0; m < D; ++m) S[m] = x.o[m];
+    uint64_t w[2];
+    x.encode(w, j);
+#pragma unroll
+    for (int k = 0; k < W; ++k) node_sell[W * (base + (int64_t)SELL * c) + k] = w[k];
+  }
+}
+
 // elements per edge, for the optional edge -> element lists
 template <int D>
 __global__ void k_edge_inc_count(int64_t nelem, const int32_t *__restrict__ elem_edge,
@@ -971,6 +1179,18 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
                          (const int32_t *)tp->node_sell_off,
                          (const uint64_t *)tp->node_sell, (const int32_t *)tp->node_edge_off,
                          tp->elem_edge, tp->elem_edge_sign, tp->inc_sell, (const StatusBlock *)st);
+    EB_LAUNCH_CHECK();
+  }
+
+  if (nelem > 0) {  // rows in strip order (after the element maps read them ascending)
+    if (sz->sell_wide)
+      hipLaunchKernelGGL((k_strip<D, true>), dim3(grid_for(nv, SP_TB)), dim3(SP_TB), 0, s, nv,
+                         (const int32_t *)tp->node_inc_off, (const int32_t *)tp->node_sell_off,
+                         (uint64_t *)tp->node_sell, (const StatusBlock *)st);
+    else
+      hipLaunchKernelGGL((k_strip<D, false>), dim3(grid_for(nv, SP_TB)), dim3(SP_TB), 0, s, nv,
+                         (const int32_t *)tp->node_inc_off, (const int32_t *)tp->node_sell_off,
+                         (uint64_t *)tp->node_sell, (const StatusBlock *)st);
     EB_LAUNCH_CHECK();
   }
 

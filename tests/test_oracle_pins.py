@@ -233,7 +233,8 @@ def test_efficient_formula_exact(dim, seed):
 
 def _brute_sell(dim, nv, elems, edges):
     """Sliced-ELL layout written out from its definition (the node_sell and
-    inc_sell entries of eb.h): rows of elements per node, other vertices with
+    inc_sell entries of eb.h): rows of elements per node stored as strips
+    (rows up to 32) with shared vertices kept in place, other vertices with
     j's place taken by the last vertex, out-edge ranks, 64-node slices."""
     nn = dim + 1
     rows = [[] for _ in range(nv)]
@@ -255,16 +256,47 @@ def _brute_sell(dim, nv, elems, edges):
     B = 10 if wide else 5
     none = (1 << B) - 1
     entries, inc_sell = {}, {}
+
+    def local(inc):
+        e, l = divmod(inc, nn)
+        return [int(elems[e][dim if m == l else m]) for m in range(dim)]
+
     for j in range(nv):
-        for r, inc in enumerate(rows[j]):
-            e, l = divmod(inc, nn)
-            o = [int(elems[e][dim if m == l else m]) for m in range(dim)]
+        row = sorted(rows[j])
+        if len(row) <= 32:  # a strip: a face of the link shared with the last if any
+            order = row[:1]
+            rest = row[1:]
+            while rest:
+                last = set(local(order[-1]))
+                shared = [len(set(local(i)) & last) for i in rest]
+                face = [i for i, n in zip(rest, shared) if n >= dim - 1]
+                best = face[0] if face else rest[shared.index(max(shared))]
+                order.append(best)
+                rest.remove(best)
+        else:
+            order = row
+        prev = None
+        for c, inc in enumerate(order):
+            o = local(inc)
+            if prev is not None and len(row) <= 32:
+                # keep a vertex in the place the previous entry had it
+                placed = [None] * dim
+                left = list(o)
+                for k in range(dim):
+                    if prev[k] in left:
+                        placed[k] = prev[k]
+                        left.remove(prev[k])
+                free = [k for k in range(dim) if placed[k] is None]
+                for k, v in zip(free, left):
+                    placed[k] = v
+                o = placed
+            prev = o
             code = 0
             for m, om in enumerate(o):
                 code |= (outs[j].index(om) if om > j else none) << (B * m)
-            pos = off[j // 64] + 64 * r + j % 64
+            pos = off[j // 64] + 64 * c + j % 64
             entries[pos] = (o, code)
-            inc_sell[inc] = pos
+            inc_sell[inc] = off[j // 64] + 64 * row.index(inc) + j % 64
     return wide, off, entries, inc_sell
 
 
