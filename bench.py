@@ -456,6 +456,15 @@ def main():
         log(f"[bench] principal kernel of {name}: mean {kern[name][0]:.4f} ms, "
             f"median {kern[name][1]:.4f}, min {kern[name][2]:.4f}")
     eb.check_errors(topo)
+    # a plain device copy on the same box, in the same run: the bandwidth an
+    # HBM-bound kernel can reach in practice (read + write bytes / time)
+    cp_n = 1 << 30
+    cp_a = torch.empty(cp_n // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    cp_b = torch.empty_like(cp_a)
+    cp_ms = tm.time(lambda: cp_b.copy_(cp_a), args.phase_reps)[1]
+    copy_gbs = 2 * cp_n / (cp_ms * 1e-3) / 1e9
+    del cp_a, cp_b
+    log(f"[bench] device copy of 1 GiB: {cp_ms:.3f} ms = {copy_gbs:.0f} GB/s")
 
     bf = alg_bytes_forward(dim, nv, nel, ne_, nb, nbn)
     bb_ = alg_bytes_backward(dim, nv, nel, ne_, nb, nbn)
@@ -511,6 +520,8 @@ def main():
             "traffic": traffic,
             "alg_bytes": bf_main,
             "kernel_ms": round(kern["fwd"][0], 4),
+            "copy_GBps": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
         },
         "phases": {
             "edge_extraction": ph("topo", None),

@@ -39,10 +39,24 @@ __device__ __forceinline__ void elem_weights(const FwdArgs &a, int64_t e, const 
 #pragma unroll
   for (int t = 0; t <= D; ++t) W[t] = {0.0, 0.0, 0.0};
   if (a.w_x) {
+    // the element's edge ids (3D: 24 bytes, 8-byte aligned: three 2-word loads)
+    int32_t eid[NE];
+    if constexpr (D == 3) {
+      const int2 *q2 = reinterpret_cast<const int2 *>(a.elem_edge + e * NE);
+#pragma unroll
+      for (int k = 0; k < NE / 2; ++k) {
+        const int2 x = q2[k];
+        eid[2 * k] = x.x;
+        eid[2 * k + 1] = x.y;
+      }
+    } else {
+#pragma unroll
+      for (int le = 0; le < NE; ++le) eid[le] = a.elem_edge[e * NE + le];
+    }
 #pragma unroll
     for (int le = 0; le < NE; ++le) {
       const int p = pair_p<D>(le), q = pair_q<D>(le);
-      const int32_t ed = a.elem_edge[e * NE + le];
+      const int32_t ed = eid[le];
       const V3 w = kN * load_row3<D>(a.w_x, a.w_y, a.w_z, ed);
       const V3 z = {0.0, 0.0, 0.0};
       const bool tail_p = v[p] < v[q];

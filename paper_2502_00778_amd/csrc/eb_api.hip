@@ -105,9 +105,19 @@ int check_fwd_gather(const eb_sizes *sizes, const FwdArgs &a) {
   return EB_OK;
 }
 
+// the adjoint's element pieces read a tet's six edge ids as three 8-byte words
+int check_elem_edge_aligned(const eb_sizes *sizes, const FwdArgs &a) {
+  if (a.w_x && sizes->dim == 3 && !aligned8(a.elem_edge)) {
+    set_detail("elem_edge must be 8-byte aligned");
+    return EB_EINVAL;
+  }
+  return EB_OK;
+}
+
 int check_bwd_gather(const eb_sizes *sizes, FwdArgs &a, void *ws, size_t ws_bytes) {
   const int D = sizes->dim;
   if (a.w_x) EB_TRY(need(a.elem_edge != nullptr, "elem_edge"));
+  EB_TRY(check_elem_edge_aligned(sizes, a));
   EB_TRY(need(a.node_inc_off && a.node_sell_off && (sizes->n_elems == 0 || a.inc_sell),
               "node_inc_off, node_sell_off, inc_sell"));
   if (!aligned16(a.inc_sell)) {
@@ -263,6 +273,7 @@ int eb_directed_areas_backward(const eb_sizes *sizes, const eb_topology *topo,
   a.c = grad_vol;
   rows(grad_coords, D, sizes->n_nodes, a.g_x, a.g_y, a.g_z);
   if (a.w_x) EB_TRY(need(a.elem_edge != nullptr, "elem_edge"));
+  EB_TRY(check_elem_edge_aligned(sizes, a));
   if (sizes->n_bfaces > 0 && (a.w_x || a.be_x))
     EB_TRY(need(a.bface && a.bface_edge && a.node_bnode, "bface, bface_edge, node_bnode"));
   if (reduce == EB_REDUCE_GATHER) EB_TRY(check_bwd_gather(sizes, a, ws, ws_bytes));

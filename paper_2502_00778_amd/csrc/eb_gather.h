@@ -204,81 +204,114 @@ __device__ __forceinline__ void fwd_node_tile(const FwdArgs &a, int64_t tile,
         if constexpr (D == 3) edge_term(std::integral_constant<int, 2>{});
       }
     };
-    // Chunks of U entries in storage order; the next chunk's entries are
-    // read while the current chunk's coordinates are in flight.  Consecutive
-    // entries of a strip differ in one place, whose point alone is loaded
-    // (the others stay in registers), so a chunk issues U points instead of
-    // U D.  A chunk in which some lane's entry changes more than one place
-    // (a row start, a break in the strip) loads every place of every entry;
-    // the choice is made for the whole wave, so each path waits exactly for
-    // its own loads.
-    int32_t on[U][D];
-    uint32_t cn[U];
-    if (len > 0)
+    // Chunks of U entries in storage order.  Consecutive entries of a strip
+    // differ in one place, whose point alone is loaded (the others stay in
+    // registers): each entry loads the point of the first place it changes.
+    // A chunk's points load while the chunk before it is formed, and its
+    // entries are read one chunk earlier still, so each round of a wave waits
+    // once, for loads issued a whole chunk of work before.  An entry that
+    // changes more than one place (a row start, a break in the strip)
+    // reloads all its points when it is formed, in a branch taken for the
+    // wave only when some lane needs it.
+    int32_t oB[U][D], oC[U][D];  // the next chunk's entries, the one after
+    uint32_t cB[U], cC[U];
+    V3 LB[U];                    // the next chunk's loaded points
+    bool fB[U][D], xB[U];        // first place each next entry changes; more than one
+    auto changes = [&](const int32_t (&prev)[D], const int32_t (&o)[D], bool (&f)[D], bool &x)
+        __attribute__((always_inline)) {
+      bool seen = false;
+      x = false;
+#pragma unroll
+      for (int m = 0; m < D; ++m) {
+        const bool ch = o[m] != prev[m];
+        f[m] = ch && !seen;
+        x = x || (ch && seen);
+        seen = seen || ch;
+      }
+    };
+    auto first_point = [&](const int32_t (&o)[D], const bool (&f)[D]) __attribute__((always_inline)) {
+      // by masks: a chain of selects can be turned into an indexed (scratch)
+      // access; an unchanged entry reloads place 0
+      int32_t rest = 0, id = 0;
+#pragma unroll
+      for (int m = 1; m < D; ++m) {
+        const int32_t k = f[m] ? -1 : 0;
+        id |= o[m] & k;
+        rest |= k;
+      }
+      id |= o[0] & ~rest;
+      return load_pt<D>(a.X, id);
+    };
+    V3 P[D];  // the current entry's points by place
+#pragma unroll
+    for (int m = 0; m < D; ++m) P[m] = V3{0.0, 0.0, 0.0};
+    if (len > 0) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(u, len - 1), (int32_t)j, on[u],
-                            cn[u]);
-    int32_t S[D];  // the previous entry's vertices by place, and their points
-    V3 P[D];
+        sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(u, len - 1), (int32_t)j, oB[u],
+                            cB[u]);
 #pragma unroll
-    for (int m = 0; m < D; ++m) {
-      S[m] = -1;
-      P[m] = V3{0.0, 0.0, 0.0};
+      for (int u = 0; u < U; ++u)
+        sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(U + u, len - 1), (int32_t)j,
+                            oC[u], cC[u]);
+      int32_t none[D];
+#pragma unroll
+      for (int m = 0; m < D; ++m) none[m] = -1;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        int32_t prev[D];  // (values: a select of arrays would go through memory)
+#pragma unroll
+        for (int m = 0; m < D; ++m) prev[m] = u == 0 ? none[m] : oB[u > 0 ? u - 1 : 0][m];
+        changes(prev, oB[u], fB[u], xB[u]);
+        LB[u] = first_point(oB[u], fB[u]);
+      }
     }
     // waves whose lanes all end early skip the loop together
     for (int32_t r = 0; r < len; r += U) {
-      int32_t o[U][D];
-      uint32_t code[U];
-      bool multi = false;
-      bool pk[U][D];  // the place entry u changes (the first, if several)
+      // this chunk
+      int32_t oA[U][D];
+      uint32_t cA[U];
+      V3 LA[U];
+      bool fA[U][D], xA[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        code[u] = cn[u];
-        bool seen = false;
+        cA[u] = cB[u];
+        LA[u] = LB[u];
+        xA[u] = xB[u];
 #pragma unroll
         for (int m = 0; m < D; ++m) {
-          o[u][m] = on[u][m];
-          const bool ch = o[u][m] != (u == 0 ? S[m] : o[u - 1][m]);
-          pk[u][m] = ch && !seen;
-          multi = multi || (ch && seen);
-          seen = seen || ch;
+          oA[u][m] = oB[u][m];
+          fA[u][m] = fB[u][m];
         }
       }
-      if (r + U < len)
+      // the next chunk's points, and the entries of the one after
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-          sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(r + U + u, len - 1),
-                              (int32_t)j, on[u], cn[u]);
-      if (__builtin_amdgcn_ballot_w64(multi) == 0) {
-        V3 L[U];
+      for (int u = 0; u < U; ++u) {
+        cB[u] = cC[u];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          int32_t id = o[u][0];  // (an unchanged entry reloads place 0)
+        for (int m = 0; m < D; ++m) oB[u][m] = oC[u][m];
+        int32_t prev[D];
 #pragma unroll
-          for (int m = 1; m < D; ++m) id = pk[u][m] ? o[u][m] : id;
-          L[u] = load_pt<D>(a.X, id);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-#pragma unroll
-          for (int m = 0; m < D; ++m) P[m] = pick(pk[u][m], L[u], P[m]);
-          if (r + u < len) form(P, code[u]);
-        }
-      } else {
-        V3 Q[U][D];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-          for (int m = 0; m < D; ++m) Q[u][m] = load_pt<D>(a.X, o[u][m]);
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-          if (r + u < len) form(Q[u], code[u]);
-#pragma unroll
-        for (int m = 0; m < D; ++m) P[m] = Q[U - 1][m];
+        for (int m = 0; m < D; ++m) prev[m] = u == 0 ? oA[U - 1][m] : oB[u > 0 ? u - 1 : 0][m];
+        changes(prev, oB[u], fB[u], xB[u]);
+        LB[u] = first_point(oB[u], fB[u]);
       }
+      if (r + 2 * U < len)
 #pragma unroll
-      for (int m = 0; m < D; ++m) S[m] = o[U - 1][m];
+        for (int u = 0; u < U; ++u)
+          sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(r + 2 * U + u, len - 1),
+                              (int32_t)j, oC[u], cC[u]);
+      // form this chunk
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int m = 0; m < D; ++m) P[m] = pick(fA[u][m], LA[u], P[m]);
+        if (__builtin_amdgcn_ballot_w64(xA[u]) != 0 && xA[u]) {
+#pragma unroll
+          for (int m = 0; m < D; ++m) P[m] = load_pt<D>(a.X, oA[u][m]);
+        }
+        if (r + u < len) form(P, cA[u]);
+      }
     }
     if (a.vol) a.vol[j] = vs * GK<D>::kV;
     if (!in_lds)

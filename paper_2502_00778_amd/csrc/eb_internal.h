@@ -41,8 +41,12 @@ __device__ inline void raise_status(StatusBlock *st, int code, int64_t detail) {
 // [status 256 B][eoff][foff][bidx][bfn][bfn_scan][ein_scan][slen][queue][scan scratch]
 // [incidence rows (build) | gradient pieces (gather adjoint)]
 // Each per-node array holds n_nodes+1 int32 and starts on a 256-byte line.
+// neighbours per node the build's fast node passes keep (the count pass
+// stores each node's sorted set for the emit pass)
+constexpr int NSET = 24;
+
 struct WsLayout {
-  size_t eoff, foff, bidx, bfn, bfn_scan, ein_scan, slen, queue, scan_tmp, rows4, inc_pos,
+  size_t eoff, foff, bidx, bfn, bfn_scan, ein_scan, slen, queue, scan_tmp, nset, rows4, inc_pos,
       row_rank, total;
   int64_t scan_tmp_count;
 };
@@ -70,6 +74,9 @@ inline WsLayout ws_layout(int dim, int64_t n_nodes, int64_t n_elems) {
   int64_t longest = std::max<int64_t>(n_nodes + 1, ne * n_elems + 1);
   L.scan_tmp_count = (longest + SCAN_TILE - 1) / SCAN_TILE + 64;
   L.scan_tmp = off; off += align256(sizeof(int32_t) * (size_t)L.scan_tmp_count);
+  // each node's neighbour set, slice-major (slot s of node j at
+  // slice(j) * NSET * 64 + 64 s + lane(j))
+  L.nset = off; off += align256(sizeof(int32_t) * (size_t)NSET * 64 * (size_t)n_slices(n_nodes));
   // build only (the adjoint reuses the space): per incidence a 16-byte row
   // entry, its position in the unsorted rows, and its rank within its row
   const size_t ninc = (size_t)(dim + 1) * (size_t)n_elems;
@@ -128,6 +135,7 @@ void clear_detail();
   } while (0)
 
 inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+inline bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
 int check_ws(int dim, int64_t n_nodes, int64_t n_elems, const void *ws, size_t ws_bytes);
 int check_sizes(const eb_sizes *s);

@@ -94,6 +94,7 @@ void crows(const double *p, int dim, int64_t n, const double *&x, const double *
 int check_fwd_gather(const eb_sizes *sizes, const FwdArgs &a);
 // also points a.gpiece into the workspace
 int check_bwd_gather(const eb_sizes *sizes, FwdArgs &a, void *ws, size_t ws_bytes);
+int check_elem_edge_aligned(const eb_sizes *sizes, const FwdArgs &a);
 
 template <int D> int launch_fwd_nodes(const FwdArgs &a, const LaunchCfg &cfg, hipStream_t s);
 template <int D> int forward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_t s);

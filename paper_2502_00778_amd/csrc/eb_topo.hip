@@ -18,6 +18,8 @@
 //   4. in-edge ids by binary search in each tail's out-edges; the other CSR
 //      lists by count / scan / scatter / row sort.
 // Every integer output is thus uniquely defined (bit-exact across runs).
+#include <type_traits>
+
 #include "eb_geom.h"
 
 namespace eb {
@@ -29,7 +31,7 @@ namespace {
 // handles almost every node; nodes beyond them are queued and handled by a
 // second kernel with large capacities (a few threads per block).
 constexpr int TB = 128;                   // fast kernel: threads per block
-constexpr int MAXH = 24;                  //   neighbours per node (registers)
+constexpr int MAXH = NSET;                //   neighbours per node (registers)
 constexpr int MAXF = 64;                  //   candidate faces per node
 constexpr int MAXR = 32;                  //   incidences per node (emit ranking)
 constexpr int TBS = 32;                   // queued nodes: threads per block
@@ -201,6 +203,8 @@ struct TopoArgs {
   const int32_t *node_inc_off;
   const int32_t *node_inc;
   const int32_t *rows4;  // workspace: Inc4 per incidence, rows of node_inc_off
+  int32_t *nset;         // workspace: the fast count pass's neighbour sets (first
+                         // slot -1: the node is queued)
   const uint16_t *row_rank;  // workspace: rank of each row entry within its row
   // count pass (workspace)
   int32_t *outdeg, *fmin, *bflag, *bfn, *ein;
@@ -259,6 +263,15 @@ struct RegSet {
     for (int s = 0; s < NR; ++s)
       if (s >= lo && s < hi) f(s, a[s]);
   }
+  // the set as stored by store(): slot s at p[64 s]
+  __device__ __forceinline__ void load(const int32_t *p) {
+#pragma unroll
+    for (int s = 0; s < NR; ++s) a[s] = p[64 * s];
+  }
+  __device__ __forceinline__ void store(int32_t *p) const {
+#pragma unroll
+    for (int s = 0; s < NR; ++s) p[64 * s] = a[s];
+  }
 };
 
 template <int TBK, int NR>
@@ -306,8 +319,10 @@ __device__ __forceinline__ void inc_others(const int4 &q, int32_t (&o)[D]) {
 
 // Rank of every entry of every row (the number of smaller incidences in the
 // row), and node_inc sorted in place (the scatter pass wrote it in row
-// order).  A thread per node; rows up to RK_CAP entries are ranked from an
-// LDS column, longer ones from the workspace rows (which keep the order).
+// order).  A thread per node; rows up to RK_CAP entries are sorted by
+// insertion in an LDS column (the scatter pass leaves rows nearly ascending,
+// so the cost follows the few inversions), longer ones ranked from the
+// workspace rows (which keep the order).
 constexpr int RK_TB = 128;
 constexpr int RK_CAP = 32;
 
@@ -316,18 +331,27 @@ __global__ __launch_bounds__(RK_TB) void k_row_rank(int64_t nv, const int32_t *_
                                                    int32_t *node_inc, uint16_t *row_rank,
                                                    const StatusBlock *st) {
   __shared__ int32_t col[RK_CAP][RK_TB];
+  __shared__ uint8_t at[RK_CAP][RK_TB];
   const int t = threadIdx.x;
   const int64_t j = (int64_t)blockIdx.x * RK_TB + t;
   if (j >= nv || build_failed(st)) return;
   const int32_t r0 = off[j], len = off[j + 1] - r0;
   if (len <= RK_CAP) {
-    for (int32_t i = 0; i < len; ++i) col[i][t] = node_inc[r0 + i];
     for (int32_t i = 0; i < len; ++i) {
-      const int32_t x = col[i][t];
-      int32_t rank = 0;
-      for (int32_t i2 = 0; i2 < len; ++i2) rank += col[i2][t] < x ? 1 : 0;
-      row_rank[r0 + i] = (uint16_t)rank;
-      node_inc[r0 + rank] = x;
+      const int32_t x = node_inc[r0 + i];
+      int32_t k = i;
+      for (; k > 0; --k) {
+        const int32_t y = col[k - 1][t];
+        if (y < x) break;
+        col[k][t] = y;
+        at[k][t] = at[k - 1][t];
+      }
+      col[k][t] = x;
+      at[k][t] = (uint8_t)i;
+    }
+    for (int32_t k = 0; k < len; ++k) {
+      node_inc[r0 + k] = col[k][t];
+      row_rank[r0 + at[k][t]] = (uint16_t)k;
     }
   } else {
     for (int32_t i = 0; i < len; ++i) {
@@ -361,7 +385,16 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
   int nfc = 0;
   bool overflow = !SLOW && len > RC;
   int32_t maxdelta = 0;
-  for (int32_t i = 0; i < len && !overflow; ++i) {
+  int32_t *const nset = SLOW ? nullptr : a.nset + (int64_t)(j / SELL) * NSET * SELL + (j % SELL);
+  bool have = false;
+  if constexpr (EMIT && !SLOW) {  // the count pass's set, unless it queued the node
+    if (nset[0] == -1) return;
+    if constexpr (std::is_same<Set, RegSet<NSET>>::value) {
+      hs.load(nset);
+      have = true;
+    }
+  }
+  for (int32_t i = 0; i < len && !overflow && !have; ++i) {
     const int4 q = row[i];
     int32_t o[D];
     inc_others<D>(q, o);
@@ -381,8 +414,12 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
     } else if constexpr (!EMIT) {
       const int32_t qi = atomicAdd(&a.st->totals[T_QUEUE], 1);
       a.queue[qi] = j;
+      nset[0] = -1;
     }
     return;
+  }
+  if constexpr (!EMIT && !SLOW) {
+    if constexpr (std::is_same<Set, RegSet<NSET>>::value) hs.store(nset);
   }
   const int nh = hs.size();
   const int nlow = hs.rank(j);  // neighbours below j come first
@@ -1065,6 +1102,7 @@ int build_edges_impl(int64_t nv, int64_t nelem, const int32_t *elem, const doubl
   ta.node_inc_off = node_inc_off;
   ta.node_inc = node_inc;
   ta.rows4 = ws_at<const int32_t>(ws, L.rows4);
+  ta.nset = ws_at<int32_t>(ws, L.nset);
   ta.row_rank = ws_at<const uint16_t>(ws, L.row_rank);
   ta.outdeg = eoff;
   ta.fmin = foff;
@@ -1137,6 +1175,7 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
   ta.node_inc_off = tp->node_inc_off;
   ta.node_inc = tp->node_inc;
   ta.rows4 = ws_at<const int32_t>(ws, L.rows4);
+  ta.nset = ws_at<int32_t>(ws, L.nset);
   ta.row_rank = ws_at<const uint16_t>(ws, L.row_rank);
   ta.eoff = eoff;
   ta.foff = foff;

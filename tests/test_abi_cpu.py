@@ -46,9 +46,10 @@ def test_workspace_bytes(L):
     small = L.eb_workspace_bytes(3, 100, 300)
     big = L.eb_workspace_bytes(3, 161 ** 3, 6 * 160 ** 3)
     assert 256 < small < big
-    # per-node arrays plus scan scratch (well under 64 B per node) and 22
-    # bytes per incidence
-    assert big < 161 ** 3 * 64 + 22 * 4 * 6 * 160 ** 3
+    # per-node arrays plus scan scratch (well under 64 B per node), the kept
+    # neighbour sets (96 B per node, rounded up to whole 64-node slices) and
+    # 22 bytes per incidence
+    assert big < 161 ** 3 * (64 + 97) + 22 * 4 * 6 * 160 ** 3
 
 
 def test_backward_workspace_bytes(L):
