@@ -156,10 +156,6 @@ __device__ __forceinline__ void bface_grad_all(const V3 (&P)[D], V3 W, V3 (&G)[D
 // then sums j's column in node_inc order with coalesced loads, and the
 // boundary pass adds j's boundary faces in bnode_face order.
 
-template <int D> struct GP {  // one gradient piece: 3D double4 (pad), 2D double2
-  static constexpr int W = D == 3 ? 4 : 2;
-};
-
 // element pass: the pieces of element e
 template <int D>
 __device__ __forceinline__ void bwd_elem_piece(const FwdArgs &a, int64_t e) {
@@ -174,14 +170,13 @@ __device__ __forceinline__ void bwd_elem_piece(const FwdArgs &a, int64_t e) {
   elem_weights<D>(a, e, v, W, C);
   V3 G[D + 1];
   elem_grad_all<D>(P, n, det, W, C, G);
+  // one row per component: 8 bytes a slot, no padding
 #pragma unroll
   for (int l = 0; l <= D; ++l) {
-    double *q = a.gpiece + (int64_t)GP<D>::W * pos[l];
-    if constexpr (D == 3) {
-      *reinterpret_cast<double4 *>(q) = make_double4(G[l].x, G[l].y, G[l].z, 0.0);
-    } else {
-      *reinterpret_cast<double2 *>(q) = make_double2(G[l].x, G[l].y);
-    }
+    double *q = a.gpiece + pos[l];
+    q[0] = G[l].x;
+    q[a.gstride] = G[l].y;
+    if constexpr (D == 3) q[2 * a.gstride] = G[l].z;
   }
 }
 
@@ -189,19 +184,14 @@ __device__ __forceinline__ void bwd_elem_piece(const FwdArgs &a, int64_t e) {
 template <int D>
 __device__ __forceinline__ void bwd_node_sum(const FwdArgs &a, int64_t j) {
   const int32_t len = a.node_inc_off[j + 1] - a.node_inc_off[j];
-  const double *q = a.gpiece + (int64_t)GP<D>::W * ((int64_t)a.node_sell_off[j / SELL] + (j % SELL));
-  constexpr int64_t step = (int64_t)GP<D>::W * SELL;
+  const double *q = a.gpiece + ((int64_t)a.node_sell_off[j / SELL] + (j % SELL));
+  const int64_t gs = a.gstride;
   V3 g = {0.0, 0.0, 0.0};
   // one accumulator, fixed order: the result does not depend on unrolling
 #pragma unroll 4
   for (int32_t r = 0; r < len; ++r) {
-    if constexpr (D == 3) {
-      const double4 p = *reinterpret_cast<const double4 *>(q + step * r);
-      g = g + V3{p.x, p.y, p.z};
-    } else {
-      const double2 p = *reinterpret_cast<const double2 *>(q + step * r);
-      g = g + V3{p.x, p.y, 0.0};
-    }
+    const int64_t k = (int64_t)SELL * r;
+    g = g + V3{q[k], q[gs + k], D == 3 ? q[2 * gs + k] : 0.0};
   }
   a.g_x[j] = g.x;
   a.g_y[j] = g.y;

@@ -134,6 +134,7 @@ int check_bwd_gather(const eb_sizes *sizes, FwdArgs &a, void *ws, size_t ws_byte
     return EB_EWORKSPACE;
   }
   a.gpiece = ws_at<double>(ws, gpiece_offset(D, sizes->n_nodes, sizes->n_elems));
+  a.gstride = sizes->n_sell;
   return EB_OK;
 }
 

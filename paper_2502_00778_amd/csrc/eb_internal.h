@@ -88,7 +88,7 @@ inline WsLayout ws_layout(int dim, int64_t n_nodes, int64_t n_elems) {
 }
 
 // The gather adjoint's per-incidence gradient pieces follow the layout above:
-// 2 (2D) or 4 (3D, padded) doubles per node_sell entry.
+// D rows of n_sell doubles (one per sliced slot).
 // The build's incidence rows are dead once the emit pass is done, so the
 // pieces take their place.
 inline size_t gpiece_offset(int dim, int64_t n_nodes, int64_t n_elems) {
@@ -97,7 +97,7 @@ inline size_t gpiece_offset(int dim, int64_t n_nodes, int64_t n_elems) {
 inline size_t backward_ws_total(int dim, int64_t n_nodes, int64_t n_elems, int64_t n_sell) {
   const WsLayout L = ws_layout(dim, n_nodes, n_elems);
   return std::max(L.total,
-                  L.rows4 + align256(sizeof(double) * (size_t)(dim == 3 ? 4 : 2) * (size_t)n_sell));
+                  L.rows4 + align256(sizeof(double) * (size_t)dim * (size_t)n_sell));
 }
 
 template <class T> inline T *ws_at(void *ws, size_t off) {

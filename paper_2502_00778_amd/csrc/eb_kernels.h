@@ -30,7 +30,8 @@ struct FwdArgs {
   const double *be_x, *be_y, *be_z;  // dL/db rows
   const double *c;                   // dL/dV
   double *g_x, *g_y, *g_z;           // dL/dx rows
-  double *gpiece;  // workspace: per-incidence gradient pieces at node_sell positions
+  double *gpiece;  // workspace: per-incidence gradient pieces, D rows of gstride
+  int64_t gstride;  // (the sliced slots: node_sell_off[n_slices])
   double *vterm;   // workspace: per-edge terms of the edge loop
   StatusBlock *st;
   int xcd_remap;

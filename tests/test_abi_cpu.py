@@ -54,13 +54,13 @@ def test_workspace_bytes(L):
 
 def test_backward_workspace_bytes(L):
     from paper_2502_00778_amd._lib import EbSizes
-    for dim, per in ((3, 32), (2, 16)):
+    for dim, per in ((3, 24), (2, 16)):
         sz = EbSizes(dim=dim, n_nodes=1000, n_elems=5000, n_edges=6000, n_bfaces=10,
                      n_bnodes=10, n_sell=64 * 400, sell_wide=0)
         base = L.eb_workspace_bytes(dim, 1000, 5000)
         got = L.eb_backward_workspace_bytes(ctypes.byref(sz))
         # the build keeps 22 bytes per incidence (row entry, position, rank) at
-        # the end of its layout; the adjoint's padded gradient pieces (one per
+        # the end of its layout; the adjoint's gradient pieces (D doubles per
         # sliced entry) take that place
         up = lambda x: -(-x // 256) * 256
         ninc = (dim + 1) * 5000
