@@ -52,7 +52,9 @@ __global__ __launch_bounds__(256) void k_bwd_atomic_bface(FwdArgs a) {
 
 template <int D>
 __global__ __launch_bounds__(256) void k_bwd_elem_pieces(FwdArgs a) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // XCD-aware order: neighbouring element ranges share vertices and edges,
+  // so each XCD takes one contiguous run of them (one L2)
+  const int64_t e = tile_of_block(gridDim.x, 1) * blockDim.x + threadIdx.x;
   if (e < a.nelem) bwd_elem_piece<D>(a, e);
 }
 

@@ -23,18 +23,6 @@ template <int D> struct GK {
   static constexpr double kV = D == 3 ? 1.0 / 24.0 : 1.0 / 6.0;
 };
 
-// The tile of nodes a block handles.  Blocks are dealt round-robin to the 8
-// XCDs (block b runs on XCD b % 8); with remapping, XCD x takes one
-// contiguous run of tiles in order, so neighbouring tiles (which share
-// elements and coordinates) meet in the same L2.  A bijection for any count.
-__device__ __forceinline__ int64_t tile_of_block(int64_t nblocks, int xcd_remap) {
-  const int64_t b = blockIdx.x;
-  if (!xcd_remap || nblocks < 16) return b;
-  const int64_t per = nblocks >> 3, rem = nblocks & 7;
-  const int64_t x = b & 7, k = b >> 3;
-  return x * per + (x < rem ? x : rem) + k;
-}
-
 // Add to a thread-owned LDS accumulator.  Only the owning thread ever adds
 // to a slot, and one wave's LDS operations complete in issue order, so the
 // sum is taken in program order (deterministic); the atomic form lets the

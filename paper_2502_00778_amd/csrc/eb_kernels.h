@@ -37,6 +37,18 @@ struct FwdArgs {
   int xcd_remap;
 };
 
+// The tile (of nodes or elements) a block handles.  Blocks are dealt round-robin to the 8
+// XCDs (block b runs on XCD b % 8); with remapping, XCD x takes one
+// contiguous run of tiles in order, so neighbouring tiles (which share
+// elements and coordinates) meet in the same L2.  A bijection for any count.
+__device__ __forceinline__ int64_t tile_of_block(int64_t nblocks, int xcd_remap) {
+  const int64_t b = blockIdx.x;
+  if (!xcd_remap || nblocks < 16) return b;
+  const int64_t per = nblocks >> 3, rem = nblocks & 7;
+  const int64_t x = b & 7, k = b >> 3;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
 // Launch shape of the node-centred (gather) kernels: nodes per block
 // (64/128/256), loads in flight per thread (1/2/4), XCD-aware tile order.
 struct LaunchCfg {

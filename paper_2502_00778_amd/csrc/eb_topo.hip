@@ -126,7 +126,11 @@ __global__ __launch_bounds__(AGG_TB) void k_count_nodes(const int32_t *__restric
 
 // cur holds inclusive (end) offsets; each block takes its nodes' ranges off
 // their ends, so cur ends as the exclusive (start) offsets.  The order inside
-// a row depends on scheduling; the rows are sorted afterwards.
+// a row depends on scheduling; the rows are sorted afterwards.  Blocks that
+// finish earlier (mostly the earlier elements) take ranges nearer the row's
+// end, so each range is placed at its mirror image within the row (from the
+// row's fixed ends, a copy of cur before the pass): the ranges then come in
+// roughly ascending element order and the sort has little to do.
 template <int D>
 __device__ __forceinline__ int4 inc_entry(const int32_t (&v)[D + 1], int l, int64_t e) {
   int32_t o[D];
@@ -137,8 +141,14 @@ __device__ __forceinline__ int4 inc_entry(const int32_t (&v)[D + 1], int l, int6
 template <int D>
 __global__ __launch_bounds__(AGG_TB) void k_scatter_nodes(const int32_t *__restrict__ elem,
                                                           int64_t nelem, int64_t nv, int32_t *cur,
+                                                          const int32_t *__restrict__ ends,
                                                           int4 *rows4, int32_t *inc_pos,
                                                           int32_t *node_inc) {
+  // mirror image of range [p, p + c) within node v's row
+  auto mirror = [&](int32_t v, int32_t p, int32_t c) {
+    const int32_t row0 = v > 0 ? ends[v - 1] : 0;
+    return row0 + ends[v] - p - c;
+  };
   __shared__ int32_t hk[AGG_HT], hc[AGG_HT];
   for (int i = threadIdx.x; i < AGG_HT; i += AGG_TB) {
     hk[i] = -1;
@@ -165,7 +175,7 @@ __global__ __launch_bounds__(AGG_TB) void k_scatter_nodes(const int32_t *__restr
         slot[k][i] = h;
         rank[k][i] = atomicAdd(&hc[h], 1);
       } else {
-        const int32_t pos = atomicSub(&cur[v[k][i]], 1) - 1;
+        const int32_t pos = mirror(v[k][i], atomicSub(&cur[v[k][i]], 1) - 1, 1);
         rows4[pos] = inc_entry<D>(v[k], i, e);
         inc_pos[e * (D + 1) + i] = pos;
         node_inc[pos] = (int32_t)(e * (D + 1) + i);
@@ -177,7 +187,7 @@ __global__ __launch_bounds__(AGG_TB) void k_scatter_nodes(const int32_t *__restr
   for (int i = threadIdx.x; i < AGG_HT; i += AGG_TB)
     if (hk[i] >= 0) {
       const int32_t c = hc[i];
-      hc[i] = atomicSub(&cur[hk[i]], c) - c;
+      hc[i] = mirror(hk[i], atomicSub(&cur[hk[i]], c) - c, c);
     }
   __syncthreads();
 #pragma unroll
@@ -337,8 +347,7 @@ __global__ __launch_bounds__(RK_TB) void k_row_rank(int64_t nv, const int32_t *_
   if (j >= nv || build_failed(st)) return;
   const int32_t r0 = off[j], len = off[j + 1] - r0;
   if (len <= RK_CAP) {
-    for (int32_t i = 0; i < len; ++i) {
-      const int32_t x = node_inc[r0 + i];
+    auto insert = [&](int32_t i, int32_t x) {
       int32_t k = i;
       for (; k > 0; --k) {
         const int32_t y = col[k - 1][t];
@@ -348,10 +357,52 @@ __global__ __launch_bounds__(RK_TB) void k_row_rank(int64_t nv, const int32_t *_
       }
       col[k][t] = x;
       at[k][t] = (uint8_t)i;
+    };
+    // the row read in aligned 16-byte pieces (the array's length is a
+    // multiple of four in 3D; otherwise the last piece is read word by word)
+    const int32_t r1 = r0 + len, n_all = off[nv];
+    for (int32_t q = r0 & ~3; q < r1; q += 4) {
+      int32_t w[4];
+      if (q + 4 <= n_all) {
+        const int4 x = *reinterpret_cast<const int4 *>(node_inc + q);
+        w[0] = x.x;
+        w[1] = x.y;
+        w[2] = x.z;
+        w[3] = x.w;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w[u] = q + u < n_all ? node_inc[q + u] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (q + u >= r0 && q + u < r1) insert(q + u - r0, w[u]);
     }
-    for (int32_t k = 0; k < len; ++k) {
-      node_inc[r0 + k] = col[k][t];
-      row_rank[r0 + at[k][t]] = (uint16_t)k;
+    // the sorted row, in aligned 16-byte pieces inside it and words at its
+    // ends (neighbouring rows belong to other threads)
+    for (int32_t q = r0 & ~3; q < r1; q += 4) {
+      if (q >= r0 && q + 4 <= r1) {
+        *reinterpret_cast<int4 *>(node_inc + q) =
+            make_int4(col[q - r0][t], col[q - r0 + 1][t], col[q - r0 + 2][t], col[q - r0 + 3][t]);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (q + u >= r0 && q + u < r1) node_inc[q + u] = col[q + u - r0][t];
+      }
+    }
+    // ranks by position (col is free now), eight 16-bit ranks a piece
+    for (int32_t k = 0; k < len; ++k) col[at[k][t]][t] = k;
+    for (int32_t q = r0 & ~7; q < r1; q += 8) {
+      if (q >= r0 && q + 8 <= r1) {
+        uint32_t w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          w[u] = (uint32_t)col[q - r0 + 2 * u][t] | ((uint32_t)col[q - r0 + 2 * u + 1][t] << 16);
+        *reinterpret_cast<uint4 *>(row_rank + q) = make_uint4(w[0], w[1], w[2], w[3]);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (q + u >= r0 && q + u < r1) row_rank[q + u] = (uint16_t)col[q + u - r0][t];
+      }
     }
   } else {
     for (int32_t i = 0; i < len; ++i) {
@@ -1084,8 +1135,13 @@ int build_edges_impl(int64_t nv, int64_t nelem, const int32_t *elem, const doubl
   // rejected above are neither counted nor scattered
   EB_TRY(scan_inclusive(node_inc_off, node_inc_off, nv, node_inc_off + nv, tmp, s));
   if (nelem > 0) {
+    // the row ends, fixed for the scatter (the edge-offset array is free until
+    // the count pass)
+    int32_t *ends = ws_at<int32_t>(ws, L.eoff);
+    EB_HIP_CHECK(hipMemcpyAsync(ends, node_inc_off, sizeof(int32_t) * (size_t)nv,
+                                hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_scatter_nodes<D>, dim3(grid_for(nelem, AGG_TB * AGG_EPT)),
-                       dim3(AGG_TB), 0, s, elem, nelem, nv, node_inc_off,
+                       dim3(AGG_TB), 0, s, elem, nelem, nv, node_inc_off, (const int32_t *)ends,
                        ws_at<int4>(ws, L.rows4), ws_at<int32_t>(ws, L.inc_pos), node_inc);
     EB_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_row_rank, dim3(grid_for(nv, RK_TB)), dim3(RK_TB), 0, s, nv,
