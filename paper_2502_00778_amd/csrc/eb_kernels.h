@@ -52,7 +52,7 @@ __device__ __forceinline__ int64_t tile_of_block(int64_t nblocks, int xcd_remap)
 // Launch shape of the node-centred (gather) kernels: nodes per block
 // (64/128/256), loads in flight per thread (1/2/4), XCD-aware tile order.
 struct LaunchCfg {
-  int tile = 128;
+  int tile = 64;
   int unroll = 4;
   int xcd_remap = 1;
 };

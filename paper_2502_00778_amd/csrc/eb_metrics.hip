@@ -326,10 +326,9 @@ int launch_fwd_boundary(const FwdArgs &a, hipStream_t s) {
 
 template <int D>
 int forward_variant_impl(const FwdArgs &a, int variant, const LaunchCfg &cfg, hipStream_t s) {
-  const int64_t ntiles = (a.nv + cfg.tile - 1) / cfg.tile;
-  const dim3 grid((unsigned)ntiles);
   if (variant == 0) return launch_fwd_gather<D>(a, cfg, s);
-  // one shape (128 nodes, 4 loads in flight, as the default): for comparison
+  // one shape (128 nodes, chunks of 4, XCD order as set): for comparison
+  const dim3 grid((unsigned)((a.nv + 127) / 128));
   if (a.sell_wide) {
     if (variant == 1)
       launch_principal((k_fwd_gather_variant<D, 128, 1024, 4, true, VAR_EDGE>), grid, dim3(128), 0,
