@@ -35,6 +35,7 @@ constexpr int MAXH = NSET;                //   neighbours per node (registers)
 constexpr int MAXF = 64;                  //   candidate faces per node
 constexpr int MAXR = 32;                  //   incidences per node (emit ranking)
 constexpr int TBS = 32;                   // queued nodes: threads per block
+constexpr int RB = 8;                     // row entries a thread reads at once
 constexpr int MAXH_S = EB_MAX_NEIGHBOURS; //   neighbours per node
 constexpr int MAXF_S = EB_MAX_NODE_FACES; //   candidate faces per node
 static_assert(MAXH_S * MAXH_S <= 0x8000, "face codes fit 15 bits");
@@ -445,19 +446,27 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
       have = true;
     }
   }
-  for (int32_t i = 0; i < len && !overflow && !have; ++i) {
-    const int4 q = row[i];
-    int32_t o[D];
-    inc_others<D>(q, o);
-    int higher = 0;
+  // (a thread's RB next entries are read together: one 128-byte line is
+  // used up at once, before other lanes' rows evict it)
+  for (int32_t i0 = 0; i0 < len && !overflow && !have; i0 += RB) {
+    int4 qb[RB];
 #pragma unroll
-    for (int m = 0; m < D; ++m) {
-      const int32_t k = o[m];
-      if (!EMIT) maxdelta = max(maxdelta, k > j ? k - j : j - k);
-      if (k > j) ++higher;
-      if (!hs.insert(k)) overflow = true;
+    for (int u = 0; u < RB; ++u) qb[u] = row[min(i0 + u, len - 1)];
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      if (i0 + u >= len) break;
+      int32_t o[D];
+      inc_others<D>(qb[u], o);
+      int higher = 0;
+#pragma unroll
+      for (int m = 0; m < D; ++m) {
+        const int32_t k = o[m];
+        if (!EMIT) maxdelta = max(maxdelta, k > j ? k - j : j - k);
+        if (k > j) ++higher;
+        if (!hs.insert(k)) overflow = true;
+      }
+      nfc += D == 3 ? higher * (higher - 1) / 2 : higher;
     }
-    nfc += D == 3 ? higher * (higher - 1) / 2 : higher;
   }
   if (overflow || nfc > MF) {
     if constexpr (SLOW) {
@@ -507,10 +516,21 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
     // (the stores of a wave then fall on one column of the slice)
     for (int32_t i = 0; i < len; ++i) pr[a.row_rank[r0 + i]][t] = (uint8_t)i;
   }
-  for (int32_t c = 0; c < len; ++c) {
-    int32_t i = c;
-    if constexpr (EMIT && !SLOW) i = pr[c][t];
-    const int4 q = row[i];
+  for (int32_t c0 = 0; c0 < len; c0 += RB) {
+   int4 qb[RB];
+   int32_t ib[RB];
+#pragma unroll
+   for (int u = 0; u < RB; ++u) {
+     ib[u] = min(c0 + u, len - 1);
+     if constexpr (EMIT && !SLOW) ib[u] = pr[ib[u]][t];
+     qb[u] = row[ib[u]];
+   }
+#pragma unroll
+   for (int u = 0; u < RB; ++u) {
+    const int32_t c = c0 + u;
+    if (c >= len) break;
+    const int32_t i = ib[u];
+    const int4 q = qb[u];
     int32_t o[D];
     inc_others<D>(q, o);
     const int s0 = o[0] > j ? hs.rank(o[0]) : -1;
@@ -549,6 +569,7 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
       if (s0 >= 0) fc[nf++][t] = (uint16_t)s0;
       if (s1 >= 0) fc[nf++][t] = (uint16_t)s1;
     }
+   }
   }
   if constexpr (EMIT) {  // zero the slice entries past j's row
     const int32_t sl0 = a.node_sell_off[j / SELL], sl1 = a.node_sell_off[j / SELL + 1];
