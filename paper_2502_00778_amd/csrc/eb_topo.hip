@@ -1045,29 +1045,33 @@ __global__ __launch_bounds__(SP_TB) void k_strip(int64_t nv, const int32_t *__re
   for (int32_t c = 1; c < len; ++c) {
     int best = 0, most = -1;
     Key bk = cur;
-    // two candidates per round, both read before either is tested
-    for (uint32_t it = rest; it != 0u;) {
-      const int q0 = __builtin_ctz(it);
-      it &= it - 1u;
-      const int q1 = it != 0u ? __builtin_ctz(it) : q0;
-      const Key x0 = key(q0), x1 = key(q1);
-      const int s0 = shared(x0, cur);
-      if (s0 > most) {
-        most = s0;
-        best = q0;
+    // four candidates per round, all read before any is tested (the same
+    // choice as testing them one by one in ascending order)
+    constexpr int NC = 4;
+    bool done = false;
+    for (uint32_t it = rest; it != 0u && !done;) {
+      int qs[NC];
+      bool ok[NC];
 #pragma unroll
-        for (int m = 0; m < D; ++m) bk.v[m] = x0.v[m];
-        if (s0 >= D - 1) break;
+      for (int u = 0; u < NC; ++u) {
+        ok[u] = it != 0u;
+        qs[u] = ok[u] ? __builtin_ctz(it) : 0;
+        it &= it - 1u;  // (no-op once empty)
       }
-      if (it == 0u) break;
-      it &= it - 1u;
-      const int s1 = shared(x1, cur);
-      if (s1 > most) {
-        most = s1;
-        best = q1;
+      Key xs[NC];
 #pragma unroll
-        for (int m = 0; m < D; ++m) bk.v[m] = x1.v[m];
-        if (s1 >= D - 1) break;
+      for (int u = 0; u < NC; ++u) xs[u] = key(qs[u]);
+#pragma unroll
+      for (int u = 0; u < NC; ++u) {
+        if (!ok[u] || done) continue;
+        const int sh = shared(xs[u], cur);
+        if (sh > most) {
+          most = sh;
+          best = qs[u];
+#pragma unroll
+          for (int m = 0; m < D; ++m) bk.v[m] = xs[u].v[m];
+          done = sh >= D - 1;
+        }
       }
     }
     rest &= ~(1u << best);
