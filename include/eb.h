@@ -159,6 +159,16 @@ typedef struct {
  *                                 incidence's rank r in node j's node_inc
  *                                 row (the adjoint's per-incidence pieces
  *                                 live there)
+ *   node_step      [n_sell]       optional (NULL skips; narrow format only,
+ *                                 ignored when sell_wide = 1): uint32, the step
+ *                                 from node j's node_sell entry c-1 to entry c
+ *                                 at the same index.  When exactly one place k
+ *                                 changes (o_k differs): bits 0..15 = o_k - j
+ *                                 as int16, bits 16..17 = k, bits 18..22 =
+ *                                 slot_k; otherwise (c = 0, or several or no
+ *                                 places change) bit 23 set and the rest 0.
+ *                                 Past a row's end 0.  The gather forward then
+ *                                 reads 4 bytes per incidence instead of 8.
  *   node_in_off    [n_nodes+1]    ids of edges whose head is the node,
  *   node_in_edge   [n_edges]        ascending per node
  *   bface          [n_bfaces][dim] boundary elements (faces of exactly one
@@ -186,6 +196,7 @@ typedef struct {
   int32_t *node_sell_off;
   uint64_t *node_sell;
   int32_t *inc_sell;
+  uint32_t *node_step;
   int32_t *node_in_off, *node_in_edge;
   int32_t *bface;
   int32_t *bface_owner;

@@ -34,7 +34,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "node id out of range",
 
 TOPO_ARRAYS = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign",
                "edge_inc_off", "edge_inc", "node_inc_off", "node_inc", "node_sell_off",
-               "node_sell", "inc_sell",
+               "node_sell", "inc_sell", "node_step",
                "node_in_off", "node_in_edge", "bface", "bface_owner",
                "bface_edge", "bnode", "node_bnode", "bnode_face_off",
                "bnode_face")
@@ -114,7 +114,8 @@ class Topology:
         self.arrays = {}
         for name in TOPO_ARRAYS:
             cnt = L.oracle_topo_get(self._h, name.encode(), None)
-            dt = {"elem_edge_sign": np.int8, "node_sell": np.uint64}.get(name, np.int32)
+            dt = {"elem_edge_sign": np.int8, "node_sell": np.uint64,
+                  "node_step": np.uint32}.get(name, np.int32)
             a = np.empty(cnt, dtype=dt)
             L.oracle_topo_get(self._h, name.encode(), _ptr(a))
             self.arrays[name] = a

@@ -63,6 +63,10 @@
 //               code in bits 48..; wide (B = 10; when some |o_m - j| >
 //               32767 or some node has more than 31 out-edges): two words
 //               o_0 | o_1 << 32 and o_2 | code << 32
+//   node_step   [n_sell] (narrow format only, else empty) the step from
+//               entry c-1 of a row to entry c: if exactly one place k
+//               changes, o_k - j (int16) | k << 16 | slot_k << 18; else
+//               1 << 23 (c = 0, several or no places); 0 past the row
 //   inc_sell    [(D+1) NE] slot of each incidence e*(D+1)+l in the sliced
 //               layout with rows in ascending order (column = rank of the
 //               incidence in node_inc's row), whatever order node_sell uses
@@ -275,6 +279,7 @@ struct Topo {
   std::vector<int32_t> node_sell_off;
   std::vector<uint64_t> node_sell;
   std::vector<int32_t> inc_sell;
+  std::vector<uint32_t> node_step;
   int64_t n_sell = 0;
   int sell_wide = 0;
   std::vector<int32_t> bface, bface_owner, bface_edge, bnode, node_bnode;
@@ -516,6 +521,34 @@ int build_topology(Topo &t, int dim, int64_t nv, int64_t nelem, const int32_t *e
       }
   }
 
+  // steps between consecutive entries of a row (narrow format only)
+  if (!t.sell_wide) {
+    t.node_step.assign((size_t)t.n_sell, 0);
+    for (int64_t v = 0; v < nv; ++v) {
+      const int32_t len = t.node_inc_off[v + 1] - t.node_inc_off[v];
+      std::vector<int32_t> prev;
+      for (int32_t c = 0; c < len; ++c) {
+        const int64_t pos = t.node_sell_off[v / 64] + 64 * c + v % 64;
+        const uint64_t w = t.node_sell[pos];
+        std::vector<int32_t> cur(dim);
+        for (int m = 0; m < dim; ++m) cur[m] = (int32_t)(v + (int16_t)(uint16_t)(w >> (16 * m)));
+        int changed = 0, k = -1;
+        for (int m = 0; m < dim && c > 0; ++m)
+          if (cur[m] != prev[m]) {
+            ++changed;
+            if (k < 0) k = m;
+          }
+        uint32_t step = 1u << 23;
+        if (c > 0 && changed == 1) {
+          const uint32_t slot = (uint32_t)(w >> 48 >> (5 * k)) & 31u;
+          step = (uint32_t)(uint16_t)(int16_t)(cur[k] - v) | ((uint32_t)k << 16) | (slot << 18);
+        }
+        t.node_step[pos] = step;
+        prev = cur;
+      }
+    }
+  }
+
   // faces: sorted vertex ids of the face opposite each local vertex
   struct FaceKey {
     int32_t v[3];
@@ -742,6 +775,7 @@ int64_t oracle_topo_get(const void *h, const char *name, void *dst) {
       {"node_sell_off", t.node_sell_off.data(), t.node_sell_off.size(), 4},
       {"node_sell", t.node_sell.data(), t.node_sell.size(), 8},
       {"inc_sell", t.inc_sell.data(), t.inc_sell.size(), 4},
+      {"node_step", t.node_step.data(), t.node_step.size(), 4},
       {"node_in_off", t.node_in_off.data(), t.node_in_off.size(), 4},
       {"node_in_edge", t.node_in_edge.data(), t.node_in_edge.size(), 4},
       {"bface", t.bface.data(), t.bface.size(), 4},

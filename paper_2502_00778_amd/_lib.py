@@ -30,7 +30,7 @@ EXPORTS = ("eb_workspace_bytes", "eb_backward_workspace_bytes", "eb_build_edges"
 
 TOPO_FIELDS = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign",
                "edge_inc_off", "edge_inc", "node_inc_off", "node_inc", "node_sell_off",
-               "node_sell", "inc_sell",
+               "node_sell", "inc_sell", "node_step",
                "node_in_off", "node_in_edge", "bface", "bface_owner",
                "bface_edge", "bnode", "node_bnode", "bnode_face_off",
                "bnode_face")

@@ -81,7 +81,8 @@ class Topology:
         for k, v in self.arrays.items():
             if v is not None:
                 a = v.cpu().numpy()
-                out[k] = a.view("uint64") if k == "node_sell" else a
+                out[k] = (a.view("uint64") if k == "node_sell" else
+                          a.view("uint32") if k == "node_step" else a)
         return out
 
 
@@ -127,6 +128,8 @@ def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True
         node_sell=torch.empty(max(int(sizes.n_sell) * (1 + int(sizes.sell_wide)), 1),
                               dtype=torch.int64, device=dev),
         inc_sell=torch.empty(max((dim + 1) * nel, 1), **i32) if adjoint else None,
+        node_step=(torch.empty(max(int(sizes.n_sell), 1), **i32)
+                   if not int(sizes.sell_wide) else None),
         node_in_off=torch.empty(nv + 1, **i32),
         node_in_edge=torch.empty(max(ne_, 1), **i32),
         bface=torch.empty(nb, dim, **i32),
@@ -159,6 +162,8 @@ def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True
         arr["edge_inc"] = arr["edge_inc"][: ne * nel]
     if adjoint:
         arr["inc_sell"] = arr["inc_sell"][: (dim + 1) * nel]
+    if arr["node_step"] is not None:
+        arr["node_step"] = arr["node_step"][: int(sizes.n_sell)]
     return Topology(dim, nv, nel, ne_, nb, nbn, int(sizes.n_sell), int(sizes.sell_wide), arr,
                     ws, sizes, st)
 

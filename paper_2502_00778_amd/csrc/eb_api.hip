@@ -63,6 +63,7 @@ int pack(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem, const d
   a.node_sell_off = tp->node_sell_off;
   a.node_sell = tp->node_sell;
   a.inc_sell = tp->inc_sell;
+  a.node_step = sz->sell_wide ? nullptr : tp->node_step;
   a.sell_wide = sz->sell_wide;
   a.node_edge_off = tp->node_edge_off;
   a.edge_tail = tp->edge;

@@ -5,10 +5,10 @@
 
 namespace eb {
 
-template <int D, int TN, int CAP, int U, bool WIDE>
+template <int D, int TN, int CAP, int U, bool WIDE, bool STEP = false>
 __global__ __launch_bounds__(TN) void k_fwd_gather(FwdArgs a) {
   __shared__ double acc[D][CAP];
-  fwd_node_tile<D, TN, CAP, U, WIDE>(a, tile_of_block(gridDim.x, a.xcd_remap), acc);
+  fwd_node_tile<D, TN, CAP, U, WIDE, VAR_NODE, STEP>(a, tile_of_block(gridDim.x, a.xcd_remap), acc);
 }
 
 template <int D>
@@ -19,6 +19,9 @@ int launch_fwd_nodes(const FwdArgs &a, const LaunchCfg &cfg, hipStream_t s) {
   if (cfg.tile == TN_ && cfg.unroll == U_) {                                            \
     if (a.sell_wide)                                                                    \
       launch_principal((k_fwd_gather<D, TN_, CAP_, U_, true>), grid, dim3(TN_), 0, s, a); \
+    else if (a.node_step)                                                               \
+      launch_principal((k_fwd_gather<D, TN_, CAP_, U_, false, true>), grid, dim3(TN_), 0, s, \
+                       a);                                                              \
     else                                                                                \
       launch_principal((k_fwd_gather<D, TN_, CAP_, U_, false>), grid, dim3(TN_), 0, s, a); \
     EB_LAUNCH_CHECK();                                                                  \

@@ -103,10 +103,11 @@ __device__ __forceinline__ V3 pick(bool c, const V3 &a, const V3 &b) {
   return V3{c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z};
 }
 
-template <int D, int TN, int CAP, int U, bool WIDE, int VAR = VAR_NODE>
+template <int D, int TN, int CAP, int U, bool WIDE, int VAR = VAR_NODE, bool STEP = false>
 __device__ __forceinline__ void fwd_node_tile(const FwdArgs &a, int64_t tile,
                                               double (&acc)[D][CAP]) {
   static_assert(TN % SELL == 0, "a tile is whole slices");
+  static_assert(!(STEP && WIDE), "step words exist for the narrow format only");
   // accumulator units: cross products (VAR_NODE / VAR_EDGE), pieces (VAR_DUAL)
   constexpr double kOut = VAR == VAR_DUAL ? 1.0 : GK<D>::kN;
   const int t = threadIdx.x;
@@ -192,113 +193,181 @@ __device__ __forceinline__ void fwd_node_tile(const FwdArgs &a, int64_t tile,
         if constexpr (D == 3) edge_term(std::integral_constant<int, 2>{});
       }
     };
-    // Chunks of U entries in storage order.  Consecutive entries of a strip
-    // differ in one place, whose point alone is loaded (the others stay in
-    // registers): each entry loads the point of the first place it changes.
-    // A chunk's points load while the chunk before it is formed, and its
-    // entries are read one chunk earlier still, so each round of a wave waits
-    // once, for loads issued a whole chunk of work before.  An entry that
-    // changes more than one place (a row start, a break in the strip)
-    // reloads all its points when it is formed, in a branch taken for the
-    // wave only when some lane needs it.
-    int32_t oB[U][D], oC[U][D];  // the next chunk's entries, the one after
-    uint32_t cB[U], cC[U];
-    V3 LB[U];                    // the next chunk's loaded points
-    bool fB[U][D], xB[U];        // first place each next entry changes; more than one
-    auto changes = [&](const int32_t (&prev)[D], const int32_t (&o)[D], bool (&f)[D], bool &x)
-        __attribute__((always_inline)) {
-      bool seen = false;
-      x = false;
-#pragma unroll
-      for (int m = 0; m < D; ++m) {
-        const bool ch = o[m] != prev[m];
-        f[m] = ch && !seen;
-        x = x || (ch && seen);
-        seen = seen || ch;
-      }
-    };
-    auto first_point = [&](const int32_t (&o)[D], const bool (&f)[D]) __attribute__((always_inline)) {
-      // by masks: a chain of selects can be turned into an indexed (scratch)
-      // access; an unchanged entry reloads place 0
-      int32_t rest = 0, id = 0;
-#pragma unroll
-      for (int m = 1; m < D; ++m) {
-        const int32_t k = f[m] ? -1 : 0;
-        id |= o[m] & k;
-        rest |= k;
-      }
-      id |= o[0] & ~rest;
-      return load_pt<D>(a.X, id);
-    };
     V3 P[D];  // the current entry's points by place
 #pragma unroll
     for (int m = 0; m < D; ++m) P[m] = V3{0.0, 0.0, 0.0};
-    if (len > 0) {
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(u, len - 1), (int32_t)j, oB[u],
-                            cB[u]);
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(U + u, len - 1), (int32_t)j,
-                            oC[u], cC[u]);
-      int32_t none[D];
-#pragma unroll
-      for (int m = 0; m < D; ++m) none[m] = -1;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        int32_t prev[D];  // (values: a select of arrays would go through memory)
-#pragma unroll
-        for (int m = 0; m < D; ++m) prev[m] = u == 0 ? none[m] : oB[u > 0 ? u - 1 : 0][m];
-        changes(prev, oB[u], fB[u], xB[u]);
-        LB[u] = first_point(oB[u], fB[u]);
-      }
-    }
-    // waves whose lanes all end early skip the loop together
-    for (int32_t r = 0; r < len; r += U) {
-      // this chunk
-      int32_t oA[U][D];
-      uint32_t cA[U];
-      V3 LA[U];
-      bool fA[U][D], xA[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        cA[u] = cB[u];
-        LA[u] = LB[u];
-        xA[u] = xB[u];
-#pragma unroll
+    if constexpr (!STEP) {
+      // Chunks of U entries in storage order.  Consecutive entries of a strip
+      // differ in one place, whose point alone is loaded (the others stay in
+      // registers): each entry loads the point of the first place it changes.
+      // A chunk's points load while the chunk before it is formed, and its
+      // entries are read one chunk earlier still, so each round of a wave waits
+      // once, for loads issued a whole chunk of work before.  An entry that
+      // changes more than one place (a row start, a break in the strip)
+      // reloads all its points when it is formed, in a branch taken for the
+      // wave only when some lane needs it.
+      int32_t oB[U][D], oC[U][D];  // the next chunk's entries, the one after
+      uint32_t cB[U], cC[U];
+      V3 LB[U];                    // the next chunk's loaded points
+      bool fB[U][D], xB[U];        // first place each next entry changes; more than one
+      auto changes = [&](const int32_t (&prev)[D], const int32_t (&o)[D], bool (&f)[D], bool &x)
+          __attribute__((always_inline)) {
+        bool seen = false;
+        x = false;
+  #pragma unroll
         for (int m = 0; m < D; ++m) {
-          oA[u][m] = oB[u][m];
-          fA[u][m] = fB[u][m];
+          const bool ch = o[m] != prev[m];
+          f[m] = ch && !seen;
+          x = x || (ch && seen);
+          seen = seen || ch;
+        }
+      };
+      auto first_point = [&](const int32_t (&o)[D], const bool (&f)[D]) __attribute__((always_inline)) {
+        // by masks: a chain of selects can be turned into an indexed (scratch)
+        // access; an unchanged entry reloads place 0
+        int32_t rest = 0, id = 0;
+  #pragma unroll
+        for (int m = 1; m < D; ++m) {
+          const int32_t k = f[m] ? -1 : 0;
+          id |= o[m] & k;
+          rest |= k;
+        }
+        id |= o[0] & ~rest;
+        return load_pt<D>(a.X, id);
+      };
+      if (len > 0) {
+  #pragma unroll
+        for (int u = 0; u < U; ++u)
+          sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(u, len - 1), (int32_t)j, oB[u],
+                              cB[u]);
+  #pragma unroll
+        for (int u = 0; u < U; ++u)
+          sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(U + u, len - 1), (int32_t)j,
+                              oC[u], cC[u]);
+        int32_t none[D];
+  #pragma unroll
+        for (int m = 0; m < D; ++m) none[m] = -1;
+  #pragma unroll
+        for (int u = 0; u < U; ++u) {
+          int32_t prev[D];  // (values: a select of arrays would go through memory)
+  #pragma unroll
+          for (int m = 0; m < D; ++m) prev[m] = u == 0 ? none[m] : oB[u > 0 ? u - 1 : 0][m];
+          changes(prev, oB[u], fB[u], xB[u]);
+          LB[u] = first_point(oB[u], fB[u]);
         }
       }
-      // the next chunk's points, and the entries of the one after
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        cB[u] = cC[u];
-#pragma unroll
-        for (int m = 0; m < D; ++m) oB[u][m] = oC[u][m];
-        int32_t prev[D];
-#pragma unroll
-        for (int m = 0; m < D; ++m) prev[m] = u == 0 ? oA[U - 1][m] : oB[u > 0 ? u - 1 : 0][m];
-        changes(prev, oB[u], fB[u], xB[u]);
-        LB[u] = first_point(oB[u], fB[u]);
+      // waves whose lanes all end early skip the loop together
+      for (int32_t r = 0; r < len; r += U) {
+        // this chunk
+        int32_t oA[U][D];
+        uint32_t cA[U];
+        V3 LA[U];
+        bool fA[U][D], xA[U];
+  #pragma unroll
+        for (int u = 0; u < U; ++u) {
+          cA[u] = cB[u];
+          LA[u] = LB[u];
+          xA[u] = xB[u];
+  #pragma unroll
+          for (int m = 0; m < D; ++m) {
+            oA[u][m] = oB[u][m];
+            fA[u][m] = fB[u][m];
+          }
+        }
+        // the next chunk's points, and the entries of the one after
+  #pragma unroll
+        for (int u = 0; u < U; ++u) {
+          cB[u] = cC[u];
+  #pragma unroll
+          for (int m = 0; m < D; ++m) oB[u][m] = oC[u][m];
+          int32_t prev[D];
+  #pragma unroll
+          for (int m = 0; m < D; ++m) prev[m] = u == 0 ? oA[U - 1][m] : oB[u > 0 ? u - 1 : 0][m];
+          changes(prev, oB[u], fB[u], xB[u]);
+          LB[u] = first_point(oB[u], fB[u]);
+        }
+        if (r + 2 * U < len)
+  #pragma unroll
+          for (int u = 0; u < U; ++u)
+            sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(r + 2 * U + u, len - 1),
+                                (int32_t)j, oC[u], cC[u]);
+        // form this chunk
+  #pragma unroll
+        for (int u = 0; u < U; ++u) {
+  #pragma unroll
+          for (int m = 0; m < D; ++m) P[m] = pick(fA[u][m], LA[u], P[m]);
+          if (__builtin_amdgcn_ballot_w64(xA[u]) != 0 && xA[u]) {
+  #pragma unroll
+            for (int m = 0; m < D; ++m) P[m] = load_pt<D>(a.X, oA[u][m]);
+          }
+          if (r + u < len) form(P, cA[u]);
+        }
       }
-      if (r + 2 * U < len)
+    } else {
+      // The same chunk pipeline over the step words (4 bytes per entry): the
+      // words are read two chunks ahead, the point each changes one chunk
+      // ahead.  A row's first entry is read whole before the loop; an entry
+      // that changes several places (a break in the strip) reads its whole
+      // entry and all its points when it is formed, in a branch taken for
+      // the wave only when some lane needs it.
+      uint32_t wB[U], wC[U];
+      V3 LB[U];
+      uint32_t code = 0;  // the current entry's slot fields by place
+      auto step_point = [&](uint32_t w) __attribute__((always_inline)) {
+        return load_pt<D>(a.X, (int32_t)j + (int32_t)(int16_t)(uint16_t)(w & 0xffffu));
+      };
+      if (len > 0) {
+        int32_t o0[D];
+        uint32_t c0;
+        sell_entry<D, false>(a.node_sell, p0, (int32_t)j, o0, c0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) wB[u] = __builtin_nontemporal_load(a.node_step + p0 + (int64_t)SELL * min(u, len - 1));
 #pragma unroll
         for (int u = 0; u < U; ++u)
-          sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(r + 2 * U + u, len - 1),
-                              (int32_t)j, oC[u], cC[u]);
-      // form this chunk
+          wC[u] = __builtin_nontemporal_load(a.node_step + p0 + (int64_t)SELL * min(U + u, len - 1));
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+        for (int m = 0; m < D; ++m) P[m] = load_pt<D>(a.X, o0[m]);
+        code = c0;
+        // entry 0 is in place already: its word becomes "place 0 keeps its vertex"
+        wB[0] = (uint32_t)(uint16_t)(int16_t)(o0[0] - (int32_t)j) | ((c0 & 31u) << 18);
 #pragma unroll
-        for (int m = 0; m < D; ++m) P[m] = pick(fA[u][m], LA[u], P[m]);
-        if (__builtin_amdgcn_ballot_w64(xA[u]) != 0 && xA[u]) {
+        for (int u = 0; u < U; ++u) LB[u] = step_point(wB[u]);
+      }
+      for (int32_t r = 0; r < len; r += U) {
+        uint32_t wA[U];
+        V3 LA[U];
 #pragma unroll
-          for (int m = 0; m < D; ++m) P[m] = load_pt<D>(a.X, oA[u][m]);
+        for (int u = 0; u < U; ++u) {
+          wA[u] = wB[u];
+          LA[u] = LB[u];
         }
-        if (r + u < len) form(P, cA[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          wB[u] = wC[u];
+          LB[u] = step_point(wB[u]);
+        }
+        if (r + 2 * U < len)
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            wC[u] = __builtin_nontemporal_load(a.node_step + p0 +
+                                               (int64_t)SELL * min(r + 2 * U + u, len - 1));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const bool live = r + u < len;
+          const bool multi = ((wA[u] >> 23) & 1u) != 0u && live;
+          const uint32_t k = (wA[u] >> 16) & 3u;
+#pragma unroll
+          for (int m = 0; m < D; ++m) P[m] = pick(!multi && k == (uint32_t)m, LA[u], P[m]);
+          const uint32_t sh = 5u * k;
+          code = multi ? code : (code & ~(31u << sh)) | (((wA[u] >> 18) & 31u) << sh);
+          if (__builtin_amdgcn_ballot_w64(multi) != 0 && multi) {
+            int32_t o[D];
+            sell_entry<D, false>(a.node_sell, p0 + (int64_t)SELL * (r + u), (int32_t)j, o, code);
+#pragma unroll
+            for (int m = 0; m < D; ++m) P[m] = load_pt<D>(a.X, o[m]);
+          }
+          if (live) form(P, code);
+        }
       }
     }
     if (a.vol) a.vol[j] = vs * GK<D>::kV;

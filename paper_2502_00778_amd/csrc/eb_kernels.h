@@ -18,6 +18,7 @@ struct FwdArgs {
   const int32_t *node_sell_off;
   const uint64_t *node_sell;
   const int32_t *inc_sell;  // incidence -> node_sell entry index
+  const uint32_t *node_step;  // per sliced slot: the step from the previous entry (narrow)
   int sell_wide;
   const int32_t *node_edge_off, *edge_tail, *edge_head;
   const int32_t *node_in_off, *node_in_edge;

@@ -977,17 +977,61 @@ template <int D, bool WIDE> struct SellEntry {
 template <int D, bool WIDE>
 __global__ __launch_bounds__(SP_TB) void k_strip(int64_t nv, const int32_t *__restrict__ node_inc_off,
                                                  const int32_t *__restrict__ node_sell_off,
-                                                 uint64_t *node_sell, const StatusBlock *st) {
+                                                 uint64_t *node_sell, uint32_t *node_step,
+                                                 const StatusBlock *st) {
   constexpr int W = WIDE ? 2 : 1;
   __shared__ uint64_t row[STRIP][W][SP_TB];
   __shared__ uint8_t seq[STRIP][SP_TB];
   const int t = threadIdx.x;
   const int64_t j64 = (int64_t)blockIdx.x * SP_TB + t;
-  if (j64 >= nv || build_failed(st)) return;
+  static_assert(SP_TB % SELL == 0, "blocks are whole slices");
+  if (build_failed(st)) return;
+  if (j64 >= nv) {  // a lane of the last slice with no node: its steps are 0
+    if (node_step && j64 < n_slices(nv) * SELL) {
+      const int64_t sl = j64 / SELL;
+      const int32_t slen = (node_sell_off[sl + 1] - node_sell_off[sl]) / SELL;
+      for (int32_t c = 0; c < slen; ++c)
+        node_step[(int64_t)node_sell_off[sl] + j64 % SELL + (int64_t)SELL * c] = 0;
+    }
+    return;
+  }
   const int32_t j = (int32_t)j64;
   const int32_t len = node_inc_off[j + 1] - node_inc_off[j];
-  if (len > STRIP || len < 2) return;
   const int64_t base = (int64_t)node_sell_off[j / SELL] + (j % SELL);
+  using E = SellEntry<D, WIDE>;
+  // the step from the previous entry (vertices by place S) to x: see node_step
+  auto step_of = [&](const int32_t (&S)[D], const E &x) {
+    int changed = 0;
+    uint32_t w = 0;
+#pragma unroll
+    for (int m = D - 1; m >= 0; --m)
+      if (x.o[m] != S[m]) {
+        ++changed;
+        w = (uint32_t)(uint16_t)(int16_t)(x.o[m] - j) | ((uint32_t)m << 16) |
+            (((x.code >> (5 * m)) & 31u) << 18);
+      }
+    return changed == 1 ? w : (1u << 23);
+  };
+  if (node_step) {  // zero past the row's end
+    const int32_t slen = (node_sell_off[j / SELL + 1] - node_sell_off[j / SELL]) / SELL;
+    for (int32_t c = len; c < slen; ++c) node_step[base + (int64_t)SELL * c] = 0;
+  }
+  if (len > STRIP || len < 2) {  // kept as stored: only the steps
+    if (!node_step) return;
+    int32_t S[D];
+#pragma unroll
+    for (int m = 0; m < D; ++m) S[m] = -1;
+    for (int32_t c = 0; c < len; ++c) {
+      uint64_t w[2] = {node_sell[W * (base + (int64_t)SELL * c)],
+                       WIDE ? node_sell[W * (base + (int64_t)SELL * c) + W - 1] : 0};
+      E x;
+      x.decode(w, j);
+      node_step[base + (int64_t)SELL * c] = c == 0 ? (1u << 23) : step_of(S, x);
+#pragma unroll
+      for (int m = 0; m < D; ++m) S[m] = x.o[m];
+    }
+    return;
+  }
   // the row into LDS, eight entries in flight (the tail rereads the last)
   for (int32_t c0 = 0; c0 < len; c0 += 8) {
     uint64_t w[8][W];
@@ -1001,7 +1045,6 @@ __global__ __launch_bounds__(SP_TB) void k_strip(int64_t nv, const int32_t *__re
 #pragma unroll
       for (int k = 0; k < W; ++k) row[min(c0 + u, len - 1)][k][t] = w[u][k];
   }
-  using E = SellEntry<D, WIDE>;
   auto entry = [&](int32_t q) {
     uint64_t w[2] = {row[q][0][t], WIDE ? row[q][W - 1][t] : 0};
     E x;
@@ -1085,6 +1128,7 @@ __global__ __launch_bounds__(SP_TB) void k_strip(int64_t nv, const int32_t *__re
   for (int32_t c = 0; c < len; ++c) {
     E x = entry(seq[c][t]);
     x.place(S);
+    if (node_step) node_step[base + (int64_t)SELL * c] = c == 0 ? (1u << 23) : step_of(S, x);
 #pragma unroll
     for (int m = 0; m < D; ++m) S[m] = x.o[m];
     uint64_t w[2];
@@ -1306,11 +1350,13 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
     if (sz->sell_wide)
       hipLaunchKernelGGL((k_strip<D, true>), dim3(grid_for(nv, SP_TB)), dim3(SP_TB), 0, s, nv,
                          (const int32_t *)tp->node_inc_off, (const int32_t *)tp->node_sell_off,
-                         (uint64_t *)tp->node_sell, (const StatusBlock *)st);
+                         (uint64_t *)tp->node_sell, nullptr,
+                         (const StatusBlock *)st);
     else
       hipLaunchKernelGGL((k_strip<D, false>), dim3(grid_for(nv, SP_TB)), dim3(SP_TB), 0, s, nv,
                          (const int32_t *)tp->node_inc_off, (const int32_t *)tp->node_sell_off,
-                         (uint64_t *)tp->node_sell, (const StatusBlock *)st);
+                         (uint64_t *)tp->node_sell, tp->node_step,
+                         (const StatusBlock *)st);
     EB_LAUNCH_CHECK();
   }
 

@@ -359,6 +359,32 @@ def test_sliced_layout_brute(case):
         assert got[1] == ref_code, pos
     assert t["inc_sell"].tolist() == [inc_sell[i] for i in range((dim + 1) * E.shape[0])]
     assert B in (5, 10)
+    # steps between consecutive entries of a row (narrow format only)
+    steps = t["node_step"]
+    if wide:
+        assert steps.size == 0
+        return
+    assert steps.size == t.n_sell
+    want = np.zeros(t.n_sell, np.uint64)
+    for j in range(nv):
+        c = 0
+        prev = None
+        while True:
+            pos = off[j // 64] + 64 * c + j % 64
+            if pos not in entries or pos >= off[j // 64 + 1]:
+                break
+            o, code = entries[pos]
+            flag = 1 << 23
+            if prev is not None:
+                ch = [k for k in range(dim) if o[k] != prev[k]]
+                if len(ch) == 1:
+                    k = ch[0]
+                    slot = (code >> (5 * k)) & 31
+                    flag = ((o[k] - j) & 0xffff) | (k << 16) | (slot << 18)
+            want[pos] = flag
+            prev = o
+            c += 1
+    assert steps.astype(np.uint64).tolist() == want.tolist()
 
 
 def test_local_identity_fe_form():
