@@ -97,6 +97,39 @@ __device__ __forceinline__ V3 dual_piece(const V3 &xj, const V3 (&P)[D]) {
   }
 }
 
+// Wait for every vector memory load in flight (s_waitcnt vmcnt(0), the
+// other counters left alone).  Ending a rarely taken branch that loads with
+// this keeps its loads from looking pending where the branch rejoins, so the
+// path that skipped it does not wait there for loads issued for later work.
+__device__ __forceinline__ void wait_loads() { __builtin_amdgcn_s_waitcnt(0x0f70); }
+
+// v with its sign bit xor-ed with bit 31 of m (m = 0 or 0x80000000)
+__device__ __forceinline__ double flip_sign(double v, uint32_t m) {
+  return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) ^ ((uint64_t)m << 32));
+}
+
+// Points of the vertices near a tile (narrow format: within 32767 of one of
+// its nodes): each row addressed from a tile-uniform base by a 32-bit byte
+// offset, so a load needs one offset register instead of a 64-bit address
+// per row.
+template <int D> struct NearPts {
+  using GD = const __attribute__((address_space(1))) double;
+  uint64_t bx, by, bz;  // the rows at node `from` (uniform values)
+  int64_t from;
+  __device__ __forceinline__ NearPts(const Coords &X, int64_t j0) : from(j0 - 32768) {
+    bx = (uint64_t)X.x + (uint64_t)(from * 8);
+    by = (uint64_t)X.y + (uint64_t)(from * 8);
+    bz = (uint64_t)X.z + (uint64_t)(from * 8);
+  }
+  __device__ __forceinline__ V3 operator()(int32_t v) const {
+    const uint64_t off = (uint64_t)((uint32_t)(v - (int32_t)from) * 8u);
+    const double x = *reinterpret_cast<GD *>(bx + off);
+    const double y = *reinterpret_cast<GD *>(by + off);
+    const double z = D == 3 ? *reinterpret_cast<GD *>(bz + off) : 0.0;
+    return V3{x, y, z};
+  }
+};
+
 // c ? a : b by component (a select of whole structs can become a select of
 // their addresses, which sends both to scratch memory)
 __device__ __forceinline__ V3 pick(bool c, const V3 &a, const V3 &b) {
@@ -128,17 +161,6 @@ __device__ __forceinline__ void fwd_node_tile(const FwdArgs &a, int64_t tile,
     const int32_t my0 = a.node_edge_off[j], my1 = a.node_edge_off[j + 1];
     // accumulator of slot s: LDS acc[.][base + s], or the output itself
     const int32_t base = in_lds ? my0 - e0 : my0;
-    auto add = [&](int s, const V3 &c) {
-      if (in_lds) {
-        lds_add(&acc[0][base + s], c.x);
-        lds_add(&acc[1][base + s], c.y);
-        if (D == 3) lds_add(&acc[2][base + s], c.z);
-      } else {
-        nx[base + s] += c.x;
-        ny[base + s] += c.y;
-        if (D == 3) nz[base + s] += c.z;
-      }
-    };
     if (!in_lds)
       for (int32_t ed = my0; ed < my1; ++ed) {
         nx[ed] = 0.0;
@@ -149,227 +171,261 @@ __device__ __forceinline__ void fwd_node_tile(const FwdArgs &a, int64_t tile,
     double vs = 0.0;
     const int32_t len = a.node_inc_off[j + 1] - a.node_inc_off[j];
     const int64_t p0 = (int64_t)a.node_sell_off[j / SELL] + (j % SELL);
-    // One incidence with the points of its other vertices by place.
-    auto form = [&](const V3 (&P)[D], uint32_t code) __attribute__((always_inline)) {
-      V3 c;
-      if constexpr (D == 3)
-        c = cross(P[1] - P[0], P[2] - P[0]);
-      else
-        c = rot2(P[1] - P[0]);
-      double d = dot(c, P[0] - xj);
-      const double sg = d < 0.0 ? -1.0 : 1.0;  // the flip applied to c
-      if (d < 0.0) {
-        c = -c;
-        d = -d;
-      } else if (d == 0.0) {
-        raise_status(a.st, EB_EDEGENERATE, j);
-      }
-      vs += d;
-      if constexpr (VAR == VAR_NODE) {
-#pragma unroll
-        for (int m = 0; m < D; ++m) {
-          const int s = slot_of<WIDE>(code, m);
-          if (s != no_slot<WIDE>()) add(s, c);
+    // The walk over the row, compiled once for LDS accumulators and once for
+    // accumulation in the output (a tile with more out-edges than CAP), so
+    // that no add tests which it is.
+    auto walk = [&](auto lds_tag) __attribute__((always_inline)) {
+      constexpr bool L = decltype(lds_tag)::value;
+      auto add = [&](int s, const V3 &c) __attribute__((always_inline)) {
+        if constexpr (L) {
+          lds_add(&acc[0][base + s], c.x);
+          lds_add(&acc[1][base + s], c.y);
+          if (D == 3) lds_add(&acc[2][base + s], c.z);
+        } else {
+          nx[base + s] += c.x;
+          ny[base + s] += c.y;
+          if (D == 3) nz[base + s] += c.z;
         }
-      } else {
-        auto edge_term = [&](auto mm) {
-          constexpr int m = decltype(mm)::value;
-          const int s = slot_of<WIDE>(code, m);
-          if (s == no_slot<WIDE>()) return;
-          if constexpr (VAR == VAR_EDGE) {
-            // the same face vector from the vertex order rotated by m
-            V3 ce;
-            if constexpr (D == 3)
-              ce = cross(P[(m + 1) % 3] - P[m], P[(m + 2) % 3] - P[m]);
-            else
-              ce = m == 0 ? rot2(P[1] - P[0]) : -rot2(P[0] - P[1]);
-            add(s, sg * ce);
-          } else {
-            add(s, dual_piece<D, m>(xj, P));
+      };
+      // One incidence with the points of its other vertices by place.
+      auto form = [&](const V3 (&P)[D], uint32_t code) __attribute__((always_inline)) {
+        V3 c;
+        if constexpr (D == 3)
+          c = cross(P[1] - P[0], P[2] - P[0]);
+        else
+          c = rot2(P[1] - P[0]);
+        double d = dot(c, P[0] - xj);
+        const bool neg = d < 0.0;
+        const double sg = neg ? -1.0 : 1.0;  // the flip applied to c
+        if (d == 0.0) raise_status(a.st, EB_EDEGENERATE, j);
+        // c and d negated when d < 0, by their sign bits (no branch)
+        const uint32_t flip = neg ? 0x80000000u : 0u;
+        c = V3{flip_sign(c.x, flip), flip_sign(c.y, flip), flip_sign(c.z, flip)};
+        vs += flip_sign(d, flip);
+        if constexpr (VAR == VAR_NODE) {
+#pragma unroll
+          for (int m = 0; m < D; ++m) {
+            const int s = slot_of<WIDE>(code, m);
+            if (s != no_slot<WIDE>()) add(s, c);
+          }
+        } else {
+          auto edge_term = [&](auto mm) {
+            constexpr int m = decltype(mm)::value;
+            const int s = slot_of<WIDE>(code, m);
+            if (s == no_slot<WIDE>()) return;
+            if constexpr (VAR == VAR_EDGE) {
+              // the same face vector from the vertex order rotated by m
+              V3 ce;
+              if constexpr (D == 3)
+                ce = cross(P[(m + 1) % 3] - P[m], P[(m + 2) % 3] - P[m]);
+              else
+                ce = m == 0 ? rot2(P[1] - P[0]) : -rot2(P[0] - P[1]);
+              add(s, sg * ce);
+            } else {
+              add(s, dual_piece<D, m>(xj, P));
+            }
+          };
+          edge_term(std::integral_constant<int, 0>{});
+          edge_term(std::integral_constant<int, 1>{});
+          if constexpr (D == 3) edge_term(std::integral_constant<int, 2>{});
+        }
+      };
+      V3 P[D];  // the current entry's points by place
+#pragma unroll
+      for (int m = 0; m < D; ++m) P[m] = V3{0.0, 0.0, 0.0};
+      if constexpr (!STEP) {
+        // Chunks of U entries in storage order.  Consecutive entries of a strip
+        // differ in one place, whose point alone is loaded (the others stay in
+        // registers): each entry loads the point of the first place it changes.
+        // A chunk's points load while the chunk before it is formed, and its
+        // entries are read one chunk earlier still, so each round of a wave waits
+        // once, for loads issued a whole chunk of work before.  An entry that
+        // changes more than one place (a row start, a break in the strip)
+        // reloads all its points when it is formed, in a branch taken for the
+        // wave only when some lane needs it.
+        int32_t oB[U][D], oC[U][D];  // the next chunk's entries, the one after
+        uint32_t cB[U], cC[U];
+        V3 LB[U];                    // the next chunk's loaded points
+        bool fB[U][D], xB[U];        // first place each next entry changes; more than one
+        auto changes = [&](const int32_t (&prev)[D], const int32_t (&o)[D], bool (&f)[D], bool &x)
+            __attribute__((always_inline)) {
+          bool seen = false;
+          x = false;
+#pragma unroll
+          for (int m = 0; m < D; ++m) {
+            const bool ch = o[m] != prev[m];
+            f[m] = ch && !seen;
+            x = x || (ch && seen);
+            seen = seen || ch;
           }
         };
-        edge_term(std::integral_constant<int, 0>{});
-        edge_term(std::integral_constant<int, 1>{});
-        if constexpr (D == 3) edge_term(std::integral_constant<int, 2>{});
-      }
-    };
-    V3 P[D];  // the current entry's points by place
+        auto first_point = [&](const int32_t (&o)[D], const bool (&f)[D]) __attribute__((always_inline)) {
+          // by masks: a chain of selects can be turned into an indexed (scratch)
+          // access; an unchanged entry reloads place 0
+          int32_t rest = 0, id = 0;
 #pragma unroll
-    for (int m = 0; m < D; ++m) P[m] = V3{0.0, 0.0, 0.0};
-    if constexpr (!STEP) {
-      // Chunks of U entries in storage order.  Consecutive entries of a strip
-      // differ in one place, whose point alone is loaded (the others stay in
-      // registers): each entry loads the point of the first place it changes.
-      // A chunk's points load while the chunk before it is formed, and its
-      // entries are read one chunk earlier still, so each round of a wave waits
-      // once, for loads issued a whole chunk of work before.  An entry that
-      // changes more than one place (a row start, a break in the strip)
-      // reloads all its points when it is formed, in a branch taken for the
-      // wave only when some lane needs it.
-      int32_t oB[U][D], oC[U][D];  // the next chunk's entries, the one after
-      uint32_t cB[U], cC[U];
-      V3 LB[U];                    // the next chunk's loaded points
-      bool fB[U][D], xB[U];        // first place each next entry changes; more than one
-      auto changes = [&](const int32_t (&prev)[D], const int32_t (&o)[D], bool (&f)[D], bool &x)
-          __attribute__((always_inline)) {
-        bool seen = false;
-        x = false;
-  #pragma unroll
-        for (int m = 0; m < D; ++m) {
-          const bool ch = o[m] != prev[m];
-          f[m] = ch && !seen;
-          x = x || (ch && seen);
-          seen = seen || ch;
-        }
-      };
-      auto first_point = [&](const int32_t (&o)[D], const bool (&f)[D]) __attribute__((always_inline)) {
-        // by masks: a chain of selects can be turned into an indexed (scratch)
-        // access; an unchanged entry reloads place 0
-        int32_t rest = 0, id = 0;
-  #pragma unroll
-        for (int m = 1; m < D; ++m) {
-          const int32_t k = f[m] ? -1 : 0;
-          id |= o[m] & k;
-          rest |= k;
-        }
-        id |= o[0] & ~rest;
-        return load_pt<D>(a.X, id);
-      };
-      if (len > 0) {
-  #pragma unroll
-        for (int u = 0; u < U; ++u)
-          sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(u, len - 1), (int32_t)j, oB[u],
-                              cB[u]);
-  #pragma unroll
-        for (int u = 0; u < U; ++u)
-          sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(U + u, len - 1), (int32_t)j,
-                              oC[u], cC[u]);
-        int32_t none[D];
-  #pragma unroll
-        for (int m = 0; m < D; ++m) none[m] = -1;
-  #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          int32_t prev[D];  // (values: a select of arrays would go through memory)
-  #pragma unroll
-          for (int m = 0; m < D; ++m) prev[m] = u == 0 ? none[m] : oB[u > 0 ? u - 1 : 0][m];
-          changes(prev, oB[u], fB[u], xB[u]);
-          LB[u] = first_point(oB[u], fB[u]);
-        }
-      }
-      // waves whose lanes all end early skip the loop together
-      for (int32_t r = 0; r < len; r += U) {
-        // this chunk
-        int32_t oA[U][D];
-        uint32_t cA[U];
-        V3 LA[U];
-        bool fA[U][D], xA[U];
-  #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          cA[u] = cB[u];
-          LA[u] = LB[u];
-          xA[u] = xB[u];
-  #pragma unroll
-          for (int m = 0; m < D; ++m) {
-            oA[u][m] = oB[u][m];
-            fA[u][m] = fB[u][m];
+          for (int m = 1; m < D; ++m) {
+            const int32_t k = f[m] ? -1 : 0;
+            id |= o[m] & k;
+            rest |= k;
+          }
+          id |= o[0] & ~rest;
+          return load_pt<D>(a.X, id);
+        };
+        if (len > 0) {
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(u, len - 1), (int32_t)j, oB[u],
+                                cB[u]);
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(U + u, len - 1), (int32_t)j,
+                                oC[u], cC[u]);
+          int32_t none[D];
+#pragma unroll
+          for (int m = 0; m < D; ++m) none[m] = -1;
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            int32_t prev[D];  // (values: a select of arrays would go through memory)
+#pragma unroll
+            for (int m = 0; m < D; ++m) prev[m] = u == 0 ? none[m] : oB[u > 0 ? u - 1 : 0][m];
+            changes(prev, oB[u], fB[u], xB[u]);
+            LB[u] = first_point(oB[u], fB[u]);
           }
         }
-        // the next chunk's points, and the entries of the one after
-  #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          cB[u] = cC[u];
-  #pragma unroll
-          for (int m = 0; m < D; ++m) oB[u][m] = oC[u][m];
-          int32_t prev[D];
-  #pragma unroll
-          for (int m = 0; m < D; ++m) prev[m] = u == 0 ? oA[U - 1][m] : oB[u > 0 ? u - 1 : 0][m];
-          changes(prev, oB[u], fB[u], xB[u]);
-          LB[u] = first_point(oB[u], fB[u]);
-        }
-        if (r + 2 * U < len)
-  #pragma unroll
+        // waves whose lanes all end early skip the loop together
+        for (int32_t r = 0; r < len; r += U) {
+          // this chunk
+          int32_t oA[U][D];
+          uint32_t cA[U];
+          V3 LA[U];
+          bool fA[U][D], xA[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            cA[u] = cB[u];
+            LA[u] = LB[u];
+            xA[u] = xB[u];
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+              oA[u][m] = oB[u][m];
+              fA[u][m] = fB[u][m];
+            }
+          }
+          // the next chunk's points, and the entries of the one after
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            cB[u] = cC[u];
+#pragma unroll
+            for (int m = 0; m < D; ++m) oB[u][m] = oC[u][m];
+            int32_t prev[D];
+#pragma unroll
+            for (int m = 0; m < D; ++m) prev[m] = u == 0 ? oA[U - 1][m] : oB[u > 0 ? u - 1 : 0][m];
+            changes(prev, oB[u], fB[u], xB[u]);
+            LB[u] = first_point(oB[u], fB[u]);
+          }
+          // (unconditional, clamped to the row: a load issued on one path only
+          // would make the waits below count for both)
+#pragma unroll
           for (int u = 0; u < U; ++u)
             sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * min(r + 2 * U + u, len - 1),
                                 (int32_t)j, oC[u], cC[u]);
-        // form this chunk
-  #pragma unroll
-        for (int u = 0; u < U; ++u) {
-  #pragma unroll
-          for (int m = 0; m < D; ++m) P[m] = pick(fA[u][m], LA[u], P[m]);
-          if (__builtin_amdgcn_ballot_w64(xA[u]) != 0 && xA[u]) {
-  #pragma unroll
-            for (int m = 0; m < D; ++m) P[m] = load_pt<D>(a.X, oA[u][m]);
+          // form this chunk
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int m = 0; m < D; ++m) P[m] = pick(fA[u][m], LA[u], P[m]);
+            if (__builtin_amdgcn_ballot_w64(xA[u]) != 0 && xA[u]) {
+#pragma unroll
+              for (int m = 0; m < D; ++m) P[m] = load_pt<D>(a.X, oA[u][m]);
+              wait_loads();
+            }
+            if (r + u < len) form(P, cA[u]);
           }
-          if (r + u < len) form(P, cA[u]);
         }
-      }
-    } else {
-      // The same chunk pipeline over the step words (4 bytes per entry): the
-      // words are read two chunks ahead, the point each changes one chunk
-      // ahead.  A row's first entry is read whole before the loop; an entry
-      // that changes several places (a break in the strip) reads its whole
-      // entry and all its points when it is formed, in a branch taken for
-      // the wave only when some lane needs it.
-      uint32_t wB[U], wC[U];
-      V3 LB[U];
-      uint32_t code = 0;  // the current entry's slot fields by place
-      auto step_point = [&](uint32_t w) __attribute__((always_inline)) {
-        return load_pt<D>(a.X, (int32_t)j + (int32_t)(int16_t)(uint16_t)(w & 0xffffu));
-      };
-      if (len > 0) {
-        int32_t o0[D];
-        uint32_t c0;
-        sell_entry<D, false>(a.node_sell, p0, (int32_t)j, o0, c0);
+      } else {
+        // The same chunk pipeline over the step words (4 bytes per entry): the
+        // words are read two chunks ahead, the point each changes one chunk
+        // ahead.  A row's first entry is read whole before the loop; an entry
+        // that changes several places (a break in the strip) reads its whole
+        // entry and all its points when it is formed, in a branch taken for
+        // the wave only when some lane needs it.
+        uint32_t wB[U], wC[U];
+        V3 LB[U];
+        uint32_t code = 0;  // the current entry's slot fields by place
+        const NearPts<D> near(a.X, j0);
+        // this wave's slice of step words from a uniform base, by 32-bit offsets
+        using GW = const __attribute__((address_space(1))) uint32_t;
+        const uint64_t steps =
+            (uint64_t)a.node_step +
+            4u * (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(a.node_sell_off[j / SELL]);
+        const uint32_t lane = (uint32_t)(j % SELL);
+        auto step_word = [&](int32_t c) __attribute__((always_inline)) {
+          const uint32_t i = lane + (uint32_t)SELL * (uint32_t)min(c, len - 1);
+          return __builtin_nontemporal_load(reinterpret_cast<GW *>(steps + (uint64_t)(i * 4u)));
+        };
+        auto step_point = [&](uint32_t w) __attribute__((always_inline)) {
+          return near((int32_t)j + (int32_t)(int16_t)(uint16_t)(w & 0xffffu));
+        };
+        if (len > 0) {
+          int32_t o0[D];
+          uint32_t c0;
+          sell_entry<D, false>(a.node_sell, p0, (int32_t)j, o0, c0);
 #pragma unroll
-        for (int u = 0; u < U; ++u) wB[u] = __builtin_nontemporal_load(a.node_step + p0 + (int64_t)SELL * min(u, len - 1));
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-          wC[u] = __builtin_nontemporal_load(a.node_step + p0 + (int64_t)SELL * min(U + u, len - 1));
-#pragma unroll
-        for (int m = 0; m < D; ++m) P[m] = load_pt<D>(a.X, o0[m]);
-        code = c0;
-        // entry 0 is in place already: its word becomes "place 0 keeps its vertex"
-        wB[0] = (uint32_t)(uint16_t)(int16_t)(o0[0] - (int32_t)j) | ((c0 & 31u) << 18);
-#pragma unroll
-        for (int u = 0; u < U; ++u) LB[u] = step_point(wB[u]);
-      }
-      for (int32_t r = 0; r < len; r += U) {
-        uint32_t wA[U];
-        V3 LA[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          wA[u] = wB[u];
-          LA[u] = LB[u];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          wB[u] = wC[u];
-          LB[u] = step_point(wB[u]);
-        }
-        if (r + 2 * U < len)
+          for (int u = 0; u < U; ++u) wB[u] = step_word(u);
 #pragma unroll
           for (int u = 0; u < U; ++u)
-            wC[u] = __builtin_nontemporal_load(a.node_step + p0 +
-                                               (int64_t)SELL * min(r + 2 * U + u, len - 1));
+            wC[u] = step_word(U + u);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const bool live = r + u < len;
-          const bool multi = ((wA[u] >> 23) & 1u) != 0u && live;
-          const uint32_t k = (wA[u] >> 16) & 3u;
+          for (int m = 0; m < D; ++m) P[m] = near(o0[m]);
+          code = c0;
+          // entry 0 is in place already: its word becomes "place 0 keeps its vertex"
+          wB[0] = (uint32_t)(uint16_t)(int16_t)(o0[0] - (int32_t)j) | ((c0 & 31u) << 18);
 #pragma unroll
-          for (int m = 0; m < D; ++m) P[m] = pick(!multi && k == (uint32_t)m, LA[u], P[m]);
-          const uint32_t sh = 5u * k;
-          code = multi ? code : (code & ~(31u << sh)) | (((wA[u] >> 18) & 31u) << sh);
-          if (__builtin_amdgcn_ballot_w64(multi) != 0 && multi) {
-            int32_t o[D];
-            sell_entry<D, false>(a.node_sell, p0 + (int64_t)SELL * (r + u), (int32_t)j, o, code);
+          for (int u = 0; u < U; ++u) LB[u] = step_point(wB[u]);
+        }
+        for (int32_t r = 0; r < len; r += U) {
+          uint32_t wA[U];
+          V3 LA[U];
 #pragma unroll
-            for (int m = 0; m < D; ++m) P[m] = load_pt<D>(a.X, o[m]);
+          for (int u = 0; u < U; ++u) {
+            wA[u] = wB[u];
+            LA[u] = LB[u];
           }
-          if (live) form(P, code);
+          // the words first: the next round's point loads wait for them, and
+          // loads complete in order, so they must not queue behind this
+          // round's point loads (unconditional, as above)
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            wB[u] = wC[u];
+            wC[u] = step_word(r + 2 * U + u);
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) LB[u] = step_point(wB[u]);
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const bool live = r + u < len;
+            const bool multi = ((wA[u] >> 23) & 1u) != 0u && live;
+            const uint32_t k = (wA[u] >> 16) & 3u;
+#pragma unroll
+            for (int m = 0; m < D; ++m) P[m] = pick(!multi && k == (uint32_t)m, LA[u], P[m]);
+            const uint32_t sh = 5u * k;
+            code = multi ? code : (code & ~(31u << sh)) | (((wA[u] >> 18) & 31u) << sh);
+            if (__builtin_amdgcn_ballot_w64(multi) != 0 && multi) {
+              int32_t o[D];
+              sell_entry<D, false>(a.node_sell, p0 + (int64_t)SELL * (r + u), (int32_t)j, o, code);
+#pragma unroll
+              for (int m = 0; m < D; ++m) P[m] = near(o[m]);
+              wait_loads();
+            }
+            if (live) form(P, code);
+          }
         }
       }
-    }
+    };
+    if (in_lds)
+      walk(std::true_type{});
+    else
+      walk(std::false_type{});
     if (a.vol) a.vol[j] = vs * GK<D>::kV;
     if (!in_lds)
       for (int32_t ed = my0; ed < my1; ++ed) {
