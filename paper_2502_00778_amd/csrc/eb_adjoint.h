@@ -204,6 +204,9 @@ template <int D>
 __device__ __forceinline__ void bwd_boundary_node(const FwdArgs &a, int64_t bj) {
   const int32_t j = a.bnode[bj];
   V3 g = {0.0, 0.0, 0.0};
+  // (unrolled so that the loads of several faces are in flight together; the
+  // sum stays in face order)
+#pragma unroll 4
   for (int32_t r = a.bnode_face_off[bj]; r < a.bnode_face_off[bj + 1]; ++r) {
     const int32_t f = a.bnode_face[r];
     int32_t fv[D];

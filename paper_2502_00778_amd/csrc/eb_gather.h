@@ -31,12 +31,20 @@ __device__ __forceinline__ void lds_add(double *p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// position of head k among the out-edges [b, e) of a node (k is present)
+// position of head k among the out-edges [b, e) of a node (k is present;
+// heads ascend, so it is the number of heads below k), eight heads a load
+// round
 __device__ __forceinline__ int32_t find_head(const int32_t *__restrict__ head, int32_t b, int32_t e,
                                              int32_t k) {
-  int32_t s = b;
-  while (s < e - 1 && head[s] != k) ++s;
-  return s - b;
+  int32_t r = 0;
+  for (int32_t s = b; s < e; s += 8) {
+    int32_t h[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) h[u] = head[min(s + u, e - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) r += (s + u < e && h[u] < k) ? 1 : 0;
+  }
+  return r;
 }
 
 // One incidence of node j from the sliced-ELL layout: the element's other
@@ -454,26 +462,40 @@ __device__ __forceinline__ void fwd_boundary_node(const FwdArgs &a, int64_t bj) 
   const int32_t my0 = a.node_edge_off[j], my1 = a.node_edge_off[j + 1];
   constexpr double kB = 1.0 / (D * (D + 1));
   V3 bs = {0.0, 0.0, 0.0};
-  for (int32_t r = a.bnode_face_off[bj]; r < a.bnode_face_off[bj + 1]; ++r) {
-    const int32_t f = a.bnode_face[r];
-    int32_t fv[D];
+  // faces in order, four at a time: their ids, vertices and points are all
+  // loaded before the first is formed
+  constexpr int G = 4;
+  const int32_t r0 = a.bnode_face_off[bj], r1 = a.bnode_face_off[bj + 1];
+  for (int32_t r = r0; r < r1; r += G) {
+    int32_t f[G], fv[G][D];
+    V3 P[G][D];
 #pragma unroll
-    for (int s = 0; s < D; ++s) fv[s] = a.bface[(int64_t)f * D + s];
-    V3 nB;
-    if constexpr (D == 3) {
-      const V3 A = load_pt<D>(a.X, fv[0]), B = load_pt<D>(a.X, fv[1]), C = load_pt<D>(a.X, fv[2]);
-      nB = 0.5 * cross(B - A, C - A);
-    } else {
-      nB = rot2(load_pt<D>(a.X, fv[1]) - load_pt<D>(a.X, fv[0]));
-    }
-    bs = bs + nB;
+    for (int u = 0; u < G; ++u) f[u] = a.bnode_face[min(r + u, r1 - 1)];
 #pragma unroll
-    for (int s2 = 0; s2 < D; ++s2) {
-      if (fv[s2] <= j || my1 <= my0) continue;
-      const int32_t ed = my0 + find_head(a.edge_head, my0, my1, fv[s2]);
-      a.n_x[ed] += kB * nB.x;
-      a.n_y[ed] += kB * nB.y;
-      if (D == 3) a.n_z[ed] += kB * nB.z;
+    for (int u = 0; u < G; ++u)
+#pragma unroll
+      for (int s = 0; s < D; ++s) fv[u][s] = a.bface[(int64_t)f[u] * D + s];
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+#pragma unroll
+      for (int s = 0; s < D; ++s) P[u][s] = load_pt<D>(a.X, fv[u][s]);
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      if (r + u >= r1) break;
+      V3 nB;
+      if constexpr (D == 3)
+        nB = 0.5 * cross(P[u][1] - P[u][0], P[u][2] - P[u][0]);
+      else
+        nB = rot2(P[u][1] - P[u][0]);
+      bs = bs + nB;
+#pragma unroll
+      for (int s2 = 0; s2 < D; ++s2) {
+        if (fv[u][s2] <= j || my1 <= my0) continue;
+        const int32_t ed = my0 + find_head(a.edge_head, my0, my1, fv[u][s2]);
+        a.n_x[ed] += kB * nB.x;
+        a.n_y[ed] += kB * nB.y;
+        if (D == 3) a.n_z[ed] += kB * nB.z;
+      }
     }
   }
   if (a.b_x) {
