@@ -338,7 +338,7 @@ int eb_time_next_launch(hipEvent_t start, hipEvent_t stop);
 
 /* Launch shape of the node-centred (EB_REDUCE_GATHER) kernels: nodes per
  * block (64, 128 or 256; default 64), incidences per chunk (1, 2 or 4,
- * default 4: a chunk's points load while the chunk before is formed), and
+ * default 2: a chunk's points load while the chunk before is formed), and
  * whether consecutive node tiles are kept on one XCD (0/1, default 1).  Process-wide setting (the one piece of state the library keeps,
  * besides the error detail), meant to be set once from a tuning run; it
  * changes speed only, never results.  Returns EB_EINVAL for other values. */

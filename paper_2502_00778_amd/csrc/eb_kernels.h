@@ -54,7 +54,7 @@ __device__ __forceinline__ int64_t tile_of_block(int64_t nblocks, int xcd_remap)
 // (64/128/256), loads in flight per thread (1/2/4), XCD-aware tile order.
 struct LaunchCfg {
   int tile = 64;
-  int unroll = 4;
+  int unroll = 2;
   int xcd_remap = 1;
 };
 

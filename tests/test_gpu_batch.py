@@ -256,7 +256,7 @@ def test_autotune_and_cache(small3, tmp_path):
     assert r2["cached"] and json.load(open(cache))
     eb().set_fused_shape(128, 2, 0)
     eb().set_fused_mode("persistent")
-    eb().set_gather_shape(64, 4, 1)  # the defaults
+    eb().set_gather_shape(64, 2, 1)  # the defaults
 
 
 def test_offsets_reject_cross_mesh_element(small3):

@@ -245,6 +245,26 @@ def test_gather_bitwise_reproducible_across_shapes():
         eb().set_gather_shape(*keep)
 
 
+@pytest.mark.parametrize("name", ["2d-33", "3d-41"])
+def test_step_words_match_full_entries(name):
+    """The forward walk over node_step and the walk over the full node_sell
+    entries (node_step NULL) keep the same points by place and sum in the
+    same order, so they give the same bits."""
+    mesh, *_ = case(name)
+    X, E = dev(mesh)
+    gt = eb().build_edges(E, X)
+    assert gt.sell_wide == 0 and gt.struct.node_step
+    with_steps = [t.cpu().numpy() for t in eb().directed_areas(X, gt, E, "gather")]
+    keep = gt.struct.node_step
+    try:
+        gt.struct.node_step = None
+        without = [t.cpu().numpy() for t in eb().directed_areas(X, gt, E, "gather")]
+    finally:
+        gt.struct.node_step = keep
+    for a, r in zip(with_steps, without):
+        assert np.array_equal(a.view(np.uint64), r.view(np.uint64))
+
+
 def test_closure_on_gpu_outputs():
     # sum of n out of every node minus in, plus b, vanishes (Section 3.2.3)
     mesh, ot, *_ = case("3d-scale-33")
