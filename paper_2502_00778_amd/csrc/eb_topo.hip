@@ -263,6 +263,27 @@ struct RegSet {
     return r;
   }
   __device__ __forceinline__ int size() const { return rank(INT32_MAX); }
+  // rank(k) comparing only the first 8 g slots, g the same in every lane of
+  // the wave (a uniform value): enough when no lane's set is larger, since
+  // the empty slots hold INT32_MAX, which no vertex id exceeds
+  __device__ __forceinline__ int rank_upto(int32_t k, int g) const {
+    static_assert(NR % 8 == 0, "slots in groups of eight");
+    int r = 0;
+#pragma unroll
+    for (int q = 0; q < NR / 8; ++q)
+      if (q < g)
+#pragma unroll
+        for (int s = 8 * q; s < 8 * q + 8; ++s) r += a[s] < k ? 1 : 0;
+    return r;
+  }
+  // the groups of eight slots every lane's set fits in (uniform)
+  __device__ __forceinline__ int groups_used() const {
+    const int n = size();
+    int g = 1;
+#pragma unroll
+    for (int q = 1; q < NR / 8; ++q) g += __builtin_amdgcn_ballot_w64(n > 8 * q) != 0 ? 1 : 0;
+    return g;
+  }
   __device__ __forceinline__ int32_t at(int i) const {
     int32_t r = 0;
 #pragma unroll
@@ -307,6 +328,8 @@ struct LdsSet {
     return r;
   }
   __device__ __forceinline__ int size() const { return n; }
+  __device__ __forceinline__ int rank_upto(int32_t k, int) const { return rank(k); }
+  __device__ __forceinline__ int groups_used() const { return 0; }
   __device__ __forceinline__ int32_t at(int i) const { return hs[i][t]; }
   template <class F> __device__ __forceinline__ void each(int lo, int hi, F f) const {
     for (int s = lo; s < hi; ++s) f(s, hs[s][t]);
@@ -510,6 +533,7 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
   //    the sliced entry at that rank; both passes note the candidate faces
   //    with j as smallest vertex, coded by their two other vertices' slots
   int nf = 0;
+  const int ngroups = hs.groups_used();
   const int64_t sbase = (int64_t)a.node_sell_off[j / SELL] + (j % SELL);
   if constexpr (EMIT && !SLOW) {
     // the entry at each rank, so the row is visited in ascending order below
@@ -533,10 +557,10 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
     const int4 q = qb[u];
     int32_t o[D];
     inc_others<D>(q, o);
-    const int s0 = o[0] > j ? hs.rank(o[0]) : -1;
-    const int s1 = o[1] > j ? hs.rank(o[1]) : -1;
+    const int s0 = o[0] > j ? hs.rank_upto(o[0], ngroups) : -1;
+    const int s1 = o[1] > j ? hs.rank_upto(o[1], ngroups) : -1;
     int s2 = -1;
-    if constexpr (D == 3) s2 = o[2] > j ? hs.rank(o[2]) : -1;
+    if constexpr (D == 3) s2 = o[2] > j ? hs.rank_upto(o[2], ngroups) : -1;
     if constexpr (EMIT) {
       // rows beyond the fast capacity are visited unsorted
       const int32_t rank = SLOW ? (int32_t)a.row_rank[r0 + i] : c;
