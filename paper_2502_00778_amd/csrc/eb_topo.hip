@@ -239,21 +239,43 @@ template <int NR>
 struct RegSet {
   static constexpr int CAP = NR;
   int32_t a[NR];
+  int n = 0;  // entries inserted (the count pass; a loaded set leaves it 0)
   __device__ __forceinline__ RegSet() {
 #pragma unroll
     for (int s = 0; s < NR; ++s) a[s] = INT32_MAX;
   }
   // false when full (k not already present)
-  __device__ __forceinline__ bool insert(int32_t k) {
+  __device__ __forceinline__ bool insert(int32_t k) { return insert_upto(k, NR / 8); }
+  // insert touching only the first 8 g slots, g uniform across the wave and
+  // large enough that no lane's set outgrows them (the others hold
+  // INT32_MAX and stay so)
+  __device__ __forceinline__ bool insert_upto(int32_t k, int g) {
     bool dup = false;
 #pragma unroll
-    for (int s = 0; s < NR; ++s) dup = dup || a[s] == k;
+    for (int q = 0; q < NR / 8; ++q)
+      if (q < g)
+#pragma unroll
+        for (int s = 8 * q; s < 8 * q + 8; ++s) dup = dup || a[s] == k;
     if (dup) return true;
     if (a[NR - 1] != INT32_MAX) return false;
 #pragma unroll
-    for (int s = NR - 1; s > 0; --s) a[s] = a[s] < k ? a[s] : (a[s - 1] < k ? k : a[s - 1]);
-    a[0] = a[0] < k ? a[0] : k;
+    for (int q = NR / 8 - 1; q >= 0; --q)
+      if (q < g)
+#pragma unroll
+        for (int s = 8 * q + 7; s >= 8 * q; --s) {
+          const int32_t below = s > 0 ? a[s > 0 ? s - 1 : 0] : INT32_MIN;  // (a[0]: nothing below)
+          a[s] = a[s] < k ? a[s] : (below < k ? k : below);
+        }
+    ++n;
     return true;
+  }
+  // the groups of eight slots that hold every lane's set after m more
+  // inserts (uniform)
+  __device__ __forceinline__ int groups_after(int m) const {
+    int g = 1;
+#pragma unroll
+    for (int q = 1; q < NR / 8; ++q) g += __builtin_amdgcn_ballot_w64(n + m > 8 * q) != 0 ? 1 : 0;
+    return g;
   }
   // entries below k (the slot of k when present)
   __device__ __forceinline__ int rank(int32_t k) const {
@@ -329,6 +351,8 @@ struct LdsSet {
   }
   __device__ __forceinline__ int size() const { return n; }
   __device__ __forceinline__ int rank_upto(int32_t k, int) const { return rank(k); }
+  __device__ __forceinline__ bool insert_upto(int32_t k, int) { return insert(k); }
+  __device__ __forceinline__ int groups_after(int) const { return 0; }
   __device__ __forceinline__ int groups_used() const { return 0; }
   __device__ __forceinline__ int32_t at(int i) const { return hs[i][t]; }
   template <class F> __device__ __forceinline__ void each(int lo, int hi, F f) const {
@@ -481,12 +505,13 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
       int32_t o[D];
       inc_others<D>(qb[u], o);
       int higher = 0;
+      const int g = hs.groups_after(D);  // (uniform: the lanes inserting now)
 #pragma unroll
       for (int m = 0; m < D; ++m) {
         const int32_t k = o[m];
         if (!EMIT) maxdelta = max(maxdelta, k > j ? k - j : j - k);
         if (k > j) ++higher;
-        if (!hs.insert(k)) overflow = true;
+        if (!hs.insert_upto(k, g)) overflow = true;
       }
       nfc += D == 3 ? higher * (higher - 1) / 2 : higher;
     }
