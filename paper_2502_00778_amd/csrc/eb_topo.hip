@@ -559,6 +559,14 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
   //    with j as smallest vertex, coded by their two other vertices' slots
   int nf = 0;
   const int ngroups = hs.groups_used();
+  // When no lane of the wave has more than 8 out-neighbours, a candidate
+  // face is a bit of a 64-bit mask (3D: 8 (p - nlow) + q - nlow for slots
+  // p < q; 2D: p - nlow), and its multiplicity is tracked by three masks
+  // (seen once, twice, three times) instead of comparing every pair of
+  // candidates; bit order is code order.  Otherwise the candidates' codes go
+  // to LDS (fc) as below.  (The queued kernel always takes the LDS way.)
+  const bool by_mask = !SLOW && __builtin_amdgcn_ballot_w64(nh - nlow > 8) == 0;
+  uint64_t once = 0, twice = 0, thrice = 0;
   const int64_t sbase = (int64_t)a.node_sell_off[j / SELL] + (j % SELL);
   if constexpr (EMIT && !SLOW) {
     // the entry at each rank, so the row is visited in ascending order below
@@ -605,15 +613,27 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
         a.node_sell[2 * pos + 1] = (uint64_t)(uint32_t)(D == 3 ? o[D - 1] : 0) | (code << 32);
       }
     }
+    auto seen = [&](int b) {
+      const uint64_t bit = 1ull << b;
+      thrice |= twice & bit;
+      twice |= once & bit;
+      once |= bit;
+    };
     auto add_face = [&](int p, int qq) {
       if (p < 0 || qq < 0) return;
       const int lo = p < qq ? p : qq, hi = p < qq ? qq : p;
-      fc[nf++][t] = (uint16_t)(lo * MH + hi);
+      if (by_mask)
+        seen(8 * (lo - nlow) + hi - nlow);
+      else
+        fc[nf++][t] = (uint16_t)(lo * MH + hi);
     };
     if constexpr (D == 3) {
       add_face(s0, s1);
       add_face(s0, s2);
       add_face(s1, s2);
+    } else if (by_mask) {
+      if (s0 >= 0) seen(s0 - nlow);
+      if (s1 >= 0) seen(s1 - nlow);
     } else {
       if (s0 >= 0) fc[nf++][t] = (uint16_t)s0;
       if (s1 >= 0) fc[nf++][t] = (uint16_t)s1;
@@ -636,6 +656,25 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
 
   // 3. multiplicity of each candidate: 1 = boundary face, 2 = interior
   int nb = 0;
+  uint64_t bmask = 0;  // (by mask) the boundary faces
+  if (by_mask) {
+    if (thrice != 0) {
+      raise_status(a.st, EB_ENONMANIFOLD, j);
+      return;
+    }
+    bmask = once & ~twice;
+    nb = __builtin_popcountll(bmask);
+  }
+  // the slots of a boundary face's other vertices from its code or bit
+  auto face_slots = [&](int code, int &p, int &q) {
+    if (by_mask) {
+      p = nlow + (D == 3 ? code / 8 : code);
+      q = nlow + code % 8;
+    } else {
+      p = D == 3 ? code / MH : code;
+      q = code % MH;
+    }
+  };
   for (int i = 0; i < nf; ++i) {
     const uint16_t c = fc[i][t] & 0x7fff;
     int m = 0;
@@ -651,17 +690,22 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
   }
   if constexpr (!EMIT) {
     a.fmin[j] = nb;
-    for (int i = 0; i < nf; ++i) {
-      const uint16_t c = fc[i][t];
-      if (!(c & 0x8000)) continue;
+    for (int i = 0; i < (by_mask ? nb : nf); ++i) {
+      int code;
+      if (by_mask) {
+        code = __builtin_ctzll(bmask);
+        bmask &= bmask - 1;
+      } else {
+        const uint16_t c = fc[i][t];
+        if (!(c & 0x8000)) continue;
+        code = c & 0x7fff;
+      }
+      int p, q;
+      face_slots(code, p, q);
       int32_t fv[D];
       fv[0] = j;
-      if constexpr (D == 3) {
-        fv[1] = hs.at((c & 0x7fff) / MH);
-        fv[2] = hs.at((c & 0x7fff) % MH);
-      } else {
-        fv[1] = hs.at(c & 0x7fff);
-      }
+      fv[1] = hs.at(p);
+      if constexpr (D == 3) fv[2] = hs.at(q);
 #pragma unroll
       for (int s = 0; s < D; ++s) {
         a.bflag[fv[s]] = 1;
@@ -674,21 +718,24 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
     int last = -1;
     for (int done = 0; done < nb; ++done) {
       int best = 0x7fff + 1;
-      for (int i = 0; i < nf; ++i) {
-        const uint16_t c = fc[i][t];
-        if (!(c & 0x8000)) continue;
-        const int cc = c & 0x7fff;
-        if (cc > last && cc < best) best = cc;
+      if (by_mask) {
+        best = __builtin_ctzll(bmask);
+        bmask &= bmask - 1;
+      } else {
+        for (int i = 0; i < nf; ++i) {
+          const uint16_t c = fc[i][t];
+          if (!(c & 0x8000)) continue;
+          const int cc = c & 0x7fff;
+          if (cc > last && cc < best) best = cc;
+        }
       }
       last = best;
+      int p, q;
+      face_slots(best, p, q);
       int32_t fv[D];
       fv[0] = j;
-      if constexpr (D == 3) {
-        fv[1] = hs.at(best / MH);
-        fv[2] = hs.at(best % MH);
-      } else {
-        fv[1] = hs.at(best);
-      }
+      fv[1] = hs.at(p);
+      if constexpr (D == 3) fv[2] = hs.at(q);
       // owner: the one element of j holding the face; opposite = its vertex
       // off the face
       int64_t own = -1;
