@@ -94,30 +94,53 @@ __global__ __launch_bounds__(AGG_TB) void k_count_nodes(const int32_t *__restric
   }
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * AGG_TB * AGG_EPT + threadIdx.x;
-#pragma unroll 1
+  // every element's connectivity first, then the points two elements at a
+  // time, so that loads overlap instead of one element's chain at a time
+  int32_t v[AGG_EPT][D + 1];
+  bool ok[AGG_EPT];
+#pragma unroll
   for (int k = 0; k < AGG_EPT; ++k) {
     const int64_t e = base + (int64_t)k * AGG_TB;
-    if (e >= nelem) break;
-    int32_t v[D + 1];
-    load_conn<D>(elem, e, v);
-    if (!conn_valid<D>(v, nv)) {
-      raise_status(st, EB_ERANGE, e);
-      continue;
-    }
-    V3 P[D + 1];
+    ok[k] = e < nelem;
 #pragma unroll
-    for (int i = 0; i <= D; ++i) P[i] = load_pt<D>(X, v[i]);
-    double det;
-    if constexpr (D == 3)
-      det = dot(P[1] - P[0], cross(P[2] - P[0], P[3] - P[0]));
-    else
-      det = (P[1].x - P[0].x) * (P[2].y - P[0].y) - (P[1].y - P[0].y) * (P[2].x - P[0].x);
-    if (det == 0.0) raise_status(st, EB_EDEGENERATE, e);
+    for (int i = 0; i <= D; ++i) v[k][i] = 0;
+    if (ok[k]) load_conn<D>(elem, e, v[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < AGG_EPT; ++k) {
+    const int64_t e = base + (int64_t)k * AGG_TB;
+    if (ok[k] && !conn_valid<D>(v[k], nv)) {
+      raise_status(st, EB_ERANGE, e);
+      ok[k] = false;
+    }
+  }
+#pragma unroll
+  for (int k0 = 0; k0 < AGG_EPT; k0 += 2) {
+    V3 P[2][D + 1];
+#pragma unroll
+    for (int k = k0; k < k0 + 2; ++k)
+#pragma unroll
+      for (int i = 0; i <= D; ++i) P[k - k0][i] = ok[k] ? load_pt<D>(X, v[k][i]) : V3{0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = k0; k < k0 + 2; ++k) {
+      if (!ok[k]) continue;
+      const V3 *Q = P[k - k0];
+      double det;
+      if constexpr (D == 3)
+        det = dot(Q[1] - Q[0], cross(Q[2] - Q[0], Q[3] - Q[0]));
+      else
+        det = (Q[1].x - Q[0].x) * (Q[2].y - Q[0].y) - (Q[1].y - Q[0].y) * (Q[2].x - Q[0].x);
+      if (det == 0.0) raise_status(st, EB_EDEGENERATE, base + (int64_t)k * AGG_TB);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < AGG_EPT; ++k) {
+    if (!ok[k]) continue;
 #pragma unroll
     for (int i = 0; i <= D; ++i) {
-      const int h = agg_slot(hk, v[i]);
+      const int h = agg_slot(hk, v[k][i]);
       if (h >= 0) atomicAdd(&hc[h], 1);
-      else atomicAdd(&cnt[v[i]], 1);
+      else atomicAdd(&cnt[v[k][i]], 1);
     }
   }
   __syncthreads();
