@@ -321,6 +321,21 @@ struct RegSet {
         for (int s = 8 * q; s < 8 * q + 8; ++s) r += a[s] < k ? 1 : 0;
     return r;
   }
+  // h[i] = a[by + i] (INT32_MAX past the set), by a barrel shifter of
+  // selects (no indexed access)
+  __device__ __forceinline__ void window8(int by, int32_t (&h)[8]) const {
+    int32_t b[NR];
+#pragma unroll
+    for (int s = 0; s < NR; ++s) b[s] = a[s];
+#pragma unroll
+    for (int sh = 16; sh >= 1; sh >>= 1) {
+      const bool on = (by & sh) != 0;
+#pragma unroll
+      for (int s = 0; s < NR; ++s) b[s] = on ? (s + sh < NR ? b[s + sh < NR ? s + sh : 0] : INT32_MAX) : b[s];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) h[i] = b[i];
+  }
   // the groups of eight slots every lane's set fits in (uniform)
   __device__ __forceinline__ int groups_used() const {
     const int n = size();
@@ -374,6 +389,10 @@ struct LdsSet {
   }
   __device__ __forceinline__ int size() const { return n; }
   __device__ __forceinline__ int rank_upto(int32_t k, int) const { return rank(k); }
+  __device__ __forceinline__ void window8(int, int32_t (&h)[8]) const {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) h[i] = INT32_MAX;
+  }
   __device__ __forceinline__ bool insert_upto(int32_t k, int) { return insert(k); }
   __device__ __forceinline__ int groups_after(int) const { return 0; }
   __device__ __forceinline__ int groups_used() const { return 0; }
@@ -590,6 +609,19 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
   // to LDS (fc) as below.  (The queued kernel always takes the LDS way.)
   const bool by_mask = !SLOW && __builtin_amdgcn_ballot_w64(nh - nlow > 8) == 0;
   uint64_t once = 0, twice = 0, thrice = 0;
+  // (by mask) the out-neighbours, at most 8, ascending: a slot above nlow is
+  // then found with 8 comparisons instead of one per slot group
+  int32_t hi8[8];
+  if (by_mask) hs.window8(nlow, hi8);
+  auto slot_of_higher = [&](int32_t k) {
+    if (by_mask) {
+      int r = nlow;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) r += hi8[i] < k ? 1 : 0;
+      return r;
+    }
+    return hs.rank_upto(k, ngroups);
+  };
   const int64_t sbase = (int64_t)a.node_sell_off[j / SELL] + (j % SELL);
   if constexpr (EMIT && !SLOW) {
     // the entry at each rank, so the row is visited in ascending order below
@@ -613,10 +645,10 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
     const int4 q = qb[u];
     int32_t o[D];
     inc_others<D>(q, o);
-    const int s0 = o[0] > j ? hs.rank_upto(o[0], ngroups) : -1;
-    const int s1 = o[1] > j ? hs.rank_upto(o[1], ngroups) : -1;
+    const int s0 = o[0] > j ? slot_of_higher(o[0]) : -1;
+    const int s1 = o[1] > j ? slot_of_higher(o[1]) : -1;
     int s2 = -1;
-    if constexpr (D == 3) s2 = o[2] > j ? hs.rank_upto(o[2], ngroups) : -1;
+    if constexpr (D == 3) s2 = o[2] > j ? slot_of_higher(o[2]) : -1;
     if constexpr (EMIT) {
       // rows beyond the fast capacity are visited unsorted
       const int32_t rank = SLOW ? (int32_t)a.row_rank[r0 + i] : c;
