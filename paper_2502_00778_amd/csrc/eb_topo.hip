@@ -795,23 +795,31 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
       // off the face
       int64_t own = -1;
       int32_t vo = -1;
-      for (int32_t i = 0; i < len && own < 0; ++i) {
-        const int4 q = row[i];
-        int32_t o[D];
-        inc_others<D>(q, o);
-        int hit = 0;
-        int32_t off = -1;
+      // (the row read RB entries a round, the first holder in row order kept)
+      for (int32_t i0 = 0; i0 < len && own < 0; i0 += RB) {
+        int4 qb[RB];
 #pragma unroll
-        for (int m = 0; m < D; ++m) {
-          bool in = false;
+        for (int u = 0; u < RB; ++u) qb[u] = row[min(i0 + u, len - 1)];
 #pragma unroll
-          for (int s = 1; s < D; ++s) in = in || o[m] == fv[s];
-          if (in) ++hit;
-          else off = o[m];
-        }
-        if (hit == D - 1) {
-          own = q.x / (D + 1);
-          vo = off;
+        for (int u = 0; u < RB; ++u) {
+          if (own >= 0 || i0 + u >= len) break;
+          const int4 q = qb[u];
+          int32_t o[D];
+          inc_others<D>(q, o);
+          int hit = 0;
+          int32_t off = -1;
+#pragma unroll
+          for (int m = 0; m < D; ++m) {
+            bool in = false;
+#pragma unroll
+            for (int s = 1; s < D; ++s) in = in || o[m] == fv[s];
+            if (in) ++hit;
+            else off = o[m];
+          }
+          if (hit == D - 1) {
+            own = q.x / (D + 1);
+            vo = off;
+          }
         }
       }
       if (own < 0) {  // cannot happen for a consistent build
