@@ -976,10 +976,46 @@ __global__ void k_node_in_ids(int64_t nv, const int32_t *__restrict__ node_in_of
                               StatusBlock *st) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nv || build_failed(st)) return;
-  for (int32_t r = node_in_off[j]; r < node_in_off[j + 1]; ++r) {
-    const int32_t id = find_edge(node_edge_off, head, node_in_edge[r], (int32_t)j);
-    if (id < 0) raise_status(st, EB_EINVAL, j);  // cannot happen for a consistent build
-    node_in_edge[r] = id;
+  // four neighbours a round: their ids, then their out-edge ranges, then
+  // eight heads of each range at a time, so the loads of a round overlap
+  // (the edge's position is the number of the tail's heads below j)
+  constexpr int G = 4;
+  const int32_t r0 = node_in_off[j], r1 = node_in_off[j + 1];
+  for (int32_t r = r0; r < r1; r += G) {
+    int32_t nb[G], lo[G], hi[G], id[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) nb[u] = node_in_edge[min(r + u, r1 - 1)];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      lo[u] = node_edge_off[nb[u]];
+      hi[u] = node_edge_off[nb[u] + 1];
+    }
+    int32_t h[G][8];  // the first eight heads of every range, all in flight
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+#pragma unroll
+      for (int v = 0; v < 8; ++v) h[u][v] = head[hi[u] > lo[u] ? min(lo[u] + v, hi[u] - 1) : 0];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      id[u] = -1;
+#pragma unroll
+      for (int v = 0; v < 8; ++v)
+        if (lo[u] + v < hi[u] && h[u][v] == (int32_t)j) id[u] = lo[u] + v;
+      for (int32_t s = lo[u] + 8; s < hi[u]; s += 8) {  // longer ranges
+        int32_t x[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) x[v] = head[min(s + v, hi[u] - 1)];
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+          if (s + v < hi[u] && x[v] == (int32_t)j) id[u] = s + v;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      if (r + u >= r1) break;
+      if (id[u] < 0) raise_status(st, EB_EINVAL, j);  // cannot happen for a consistent build
+      node_in_edge[r + u] = id[u];
+    }
   }
 }
 
