@@ -1169,20 +1169,27 @@ template <int D, bool WIDE> struct SellEntry {
   }
 };
 
-template <int D, bool WIDE>
+// Two launches: the first (CAP = SP_SHORT) does everything except the strips
+// of more than SP_SHORT entries, which the second (CAP = STRIP) walks; the
+// smaller LDS rows of the first let more of its waves be resident.
+constexpr int SP_SHORT = 24;
+
+template <int D, bool WIDE, int CAP>
 __global__ __launch_bounds__(SP_TB) void k_strip(int64_t nv, const int32_t *__restrict__ node_inc_off,
                                                  const int32_t *__restrict__ node_sell_off,
                                                  uint64_t *node_sell, uint32_t *node_step,
                                                  const StatusBlock *st) {
   constexpr int W = WIDE ? 2 : 1;
-  __shared__ uint64_t row[STRIP][W][SP_TB];
-  __shared__ uint8_t seq[STRIP][SP_TB];
+  constexpr bool FIRST = CAP < STRIP;
+  static_assert(CAP == SP_SHORT || CAP == STRIP, "the two launches");
+  __shared__ uint64_t row[CAP][W][SP_TB];
+  __shared__ uint8_t seq[CAP][SP_TB];
   const int t = threadIdx.x;
   const int64_t j64 = (int64_t)blockIdx.x * SP_TB + t;
   static_assert(SP_TB % SELL == 0, "blocks are whole slices");
   if (build_failed(st)) return;
   if (j64 >= nv) {  // a lane of the last slice with no node: its steps are 0
-    if (node_step && j64 < n_slices(nv) * SELL) {
+    if (FIRST && node_step && j64 < n_slices(nv) * SELL) {
       const int64_t sl = j64 / SELL;
       const int32_t slen = (node_sell_off[sl + 1] - node_sell_off[sl]) / SELL;
       for (int32_t c = 0; c < slen; ++c)
@@ -1192,6 +1199,7 @@ __global__ __launch_bounds__(SP_TB) void k_strip(int64_t nv, const int32_t *__re
   }
   const int32_t j = (int32_t)j64;
   const int32_t len = node_inc_off[j + 1] - node_inc_off[j];
+  if (!FIRST && (len <= SP_SHORT || len > STRIP)) return;  // the first launch's rows
   const int64_t base = (int64_t)node_sell_off[j / SELL] + (j % SELL);
   using E = SellEntry<D, WIDE>;
   // the step from the previous entry (vertices by place S) to x: see node_step
@@ -1207,7 +1215,7 @@ __global__ __launch_bounds__(SP_TB) void k_strip(int64_t nv, const int32_t *__re
       }
     return changed == 1 ? w : (1u << 23);
   };
-  if (node_step) {  // zero past the row's end
+  if (FIRST && node_step) {  // zero past the row's end
     const int32_t slen = (node_sell_off[j / SELL + 1] - node_sell_off[j / SELL]) / SELL;
     for (int32_t c = len; c < slen; ++c) node_step[base + (int64_t)SELL * c] = 0;
   }
@@ -1227,6 +1235,7 @@ __global__ __launch_bounds__(SP_TB) void k_strip(int64_t nv, const int32_t *__re
     }
     return;
   }
+  if (len > CAP) return;  // the second launch's rows
   // the row into LDS, eight entries in flight (the tail rereads the last)
   for (int32_t c0 = 0; c0 < len; c0 += 8) {
     uint64_t w[8][W];
@@ -1543,16 +1552,21 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
 
   if (nelem > 0) {  // rows in strip order (after the element maps read them ascending)
     if (sz->sell_wide)
-      hipLaunchKernelGGL((k_strip<D, true>), dim3(grid_for(nv, SP_TB)), dim3(SP_TB), 0, s, nv,
-                         (const int32_t *)tp->node_inc_off, (const int32_t *)tp->node_sell_off,
-                         (uint64_t *)tp->node_sell, nullptr,
-                         (const StatusBlock *)st);
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(pass == 0 ? (k_strip<D, true, SP_SHORT>) : (k_strip<D, true, STRIP>),
+                           dim3(grid_for(nv, SP_TB)), dim3(SP_TB), 0, s, nv,
+                           (const int32_t *)tp->node_inc_off, (const int32_t *)tp->node_sell_off,
+                           (uint64_t *)tp->node_sell, nullptr, (const StatusBlock *)st);
+        EB_LAUNCH_CHECK();
+      }
     else
-      hipLaunchKernelGGL((k_strip<D, false>), dim3(grid_for(nv, SP_TB)), dim3(SP_TB), 0, s, nv,
-                         (const int32_t *)tp->node_inc_off, (const int32_t *)tp->node_sell_off,
-                         (uint64_t *)tp->node_sell, tp->node_step,
-                         (const StatusBlock *)st);
-    EB_LAUNCH_CHECK();
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(pass == 0 ? (k_strip<D, false, SP_SHORT>) : (k_strip<D, false, STRIP>),
+                           dim3(grid_for(nv, SP_TB)), dim3(SP_TB), 0, s, nv,
+                           (const int32_t *)tp->node_inc_off, (const int32_t *)tp->node_sell_off,
+                           (uint64_t *)tp->node_sell, tp->node_step, (const StatusBlock *)st);
+        EB_LAUNCH_CHECK();
+      }
   }
 
   const bool want_inc = tp->edge_inc_off && tp->edge_inc;

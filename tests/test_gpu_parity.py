@@ -143,6 +143,29 @@ def relabelled(mesh, seed):
     return meshgen.Mesh(mesh.dim, X, np.ascontiguousarray(lab[mesh.elems]), mesh.name + "-relab")
 
 
+def cone(k, centre=None):
+    """2k tetrahedra around one node: a ring of k nodes in a plane, an apex
+    above and below, every tet (centre, ring i, ring i+1, apex).  The centre's
+    row has 2k entries (a strip longer than 24 when k > 12)."""
+    ang = np.linspace(0, 2 * np.pi, k, endpoint=False)
+    P = np.zeros((3, k + 3))
+    P[0, :k], P[1, :k] = np.cos(ang), np.sin(ang)
+    P[2, k], P[2, k + 1] = 1.0, -1.0
+    c = k + 2
+    E = [[c, i, (i + 1) % k, k] for i in range(k)] + [[c, i, (i + 1) % k, k + 1] for i in range(k)]
+    E = np.array(E, np.int32)
+    # the centre numbered in the middle, so it has lower and higher neighbours
+    lab = np.roll(np.arange(k + 3), (k + 3) // 2 - c).astype(np.int32)
+    X = np.empty_like(P)
+    X[:, lab] = P
+    return meshgen.Mesh(3, np.ascontiguousarray(X), np.ascontiguousarray(lab[E]), f"cone{k}")
+
+
+def fan_mesh(k):
+    Xf, Ef = fan(k)
+    return meshgen.Mesh(2, np.ascontiguousarray(Xf), Ef, f"fan{k}")
+
+
 def single(dim):
     if dim == 2:
         return meshgen.Mesh(2, np.array([[0., 1, 0], [0, 0, 1]]), np.array([[0, 2, 1]], np.int32))
@@ -163,6 +186,8 @@ CASES = {
     "3d-single": lambda: single(3),
     "3d-batched-4": lambda: meshgen.batched_kuhn(4, 0, lo=3, hi=9),
     "3d-33-relabel": lambda: relabelled(meshgen.cube_kuhn(33, 1), 7),
+    "3d-cone-14": lambda: cone(14),
+    "2d-fan-28": lambda: fan_mesh(28),
 }
 
 _cache = {}
