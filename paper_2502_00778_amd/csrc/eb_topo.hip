@@ -423,20 +423,28 @@ __device__ __forceinline__ void inc_others(const int4 &q, int32_t (&o)[D]) {
 // insertion in an LDS column (the scatter pass leaves rows nearly ascending,
 // so the cost follows the few inversions), longer ones ranked from the
 // workspace rows (which keep the order).
+// Two launches, like the strip kernel's: the first sorts the rows of at most
+// RK_SHORT entries in smaller LDS columns (more resident waves) and ranks the
+// rows longer than RK_CAP; the second sorts the rows in between.
 constexpr int RK_TB = 128;
 constexpr int RK_CAP = 32;
+constexpr int RK_SHORT = 24;
 
+template <int CAP>
 __global__ __launch_bounds__(RK_TB) void k_row_rank(int64_t nv, const int32_t *__restrict__ off,
                                                    const int4 *__restrict__ rows4,
                                                    int32_t *node_inc, uint16_t *row_rank,
                                                    const StatusBlock *st) {
-  __shared__ int32_t col[RK_CAP][RK_TB];
-  __shared__ uint8_t at[RK_CAP][RK_TB];
+  static_assert(CAP == RK_SHORT || CAP == RK_CAP, "the two launches");
+  constexpr bool FIRST = CAP < RK_CAP;
+  __shared__ int32_t col[CAP][RK_TB];
+  __shared__ uint8_t at[CAP][RK_TB];
   const int t = threadIdx.x;
   const int64_t j = (int64_t)blockIdx.x * RK_TB + t;
   if (j >= nv || build_failed(st)) return;
   const int32_t r0 = off[j], len = off[j + 1] - r0;
-  if (len <= RK_CAP) {
+  if (FIRST ? (len > RK_SHORT && len <= RK_CAP) : (len <= RK_SHORT || len > RK_CAP)) return;
+  if (len <= CAP) {
     auto insert = [&](int32_t i, int32_t x) {
       int32_t k = i;
       for (; k > 0; --k) {
@@ -1417,10 +1425,13 @@ int build_edges_impl(int64_t nv, int64_t nelem, const int32_t *elem, const doubl
                        dim3(AGG_TB), 0, s, elem, nelem, nv, node_inc_off, (const int32_t *)ends,
                        ws_at<int4>(ws, L.rows4), ws_at<int32_t>(ws, L.inc_pos), node_inc);
     EB_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_row_rank, dim3(grid_for(nv, RK_TB)), dim3(RK_TB), 0, s, nv,
-                       (const int32_t *)node_inc_off, (const int4 *)ws_at<int4>(ws, L.rows4),
-                       node_inc, ws_at<uint16_t>(ws, L.row_rank), (const StatusBlock *)st);
-    EB_LAUNCH_CHECK();
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(pass == 0 ? k_row_rank<RK_SHORT> : k_row_rank<RK_CAP>,
+                         dim3(grid_for(nv, RK_TB)), dim3(RK_TB), 0, s, nv,
+                         (const int32_t *)node_inc_off, (const int4 *)ws_at<int4>(ws, L.rows4),
+                         node_inc, ws_at<uint16_t>(ws, L.row_rank), (const StatusBlock *)st);
+      EB_LAUNCH_CHECK();
+    }
   }
 
   // per-node counts of edges, boundary faces, boundary nodes
