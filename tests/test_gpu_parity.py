@@ -146,7 +146,8 @@ def relabelled(mesh, seed):
 def cone(k, centre=None):
     """2k tetrahedra around one node: a ring of k nodes in a plane, an apex
     above and below, every tet (centre, ring i, ring i+1, apex).  The centre's
-    row has 2k entries (a strip longer than 24 when k > 12)."""
+    row has 2k entries (a strip longer than 24 when k > 12) and k + 2
+    neighbours; it is numbered `centre` (default: in the middle)."""
     ang = np.linspace(0, 2 * np.pi, k, endpoint=False)
     P = np.zeros((3, k + 3))
     P[0, :k], P[1, :k] = np.cos(ang), np.sin(ang)
@@ -154,8 +155,9 @@ def cone(k, centre=None):
     c = k + 2
     E = [[c, i, (i + 1) % k, k] for i in range(k)] + [[c, i, (i + 1) % k, k + 1] for i in range(k)]
     E = np.array(E, np.int32)
-    # the centre numbered in the middle, so it has lower and higher neighbours
-    lab = np.roll(np.arange(k + 3), (k + 3) // 2 - c).astype(np.int32)
+    # the centre numbered in the middle by default, so it has lower and
+    # higher neighbours
+    lab = np.roll(np.arange(k + 3), c - ((k + 3) // 2 if centre is None else centre)).astype(np.int32)
     X = np.empty_like(P)
     X[:, lab] = P
     return meshgen.Mesh(3, np.ascontiguousarray(X), np.ascontiguousarray(lab[E]), f"cone{k}")
@@ -187,6 +189,9 @@ CASES = {
     "3d-batched-4": lambda: meshgen.batched_kuhn(4, 0, lo=3, hi=9),
     "3d-33-relabel": lambda: relabelled(meshgen.cube_kuhn(33, 1), 7),
     "3d-cone-14": lambda: cone(14),
+    # 22 neighbours (past two groups of eight set slots), 7 of them higher;
+    # a row of 40 entries (longer than a strip)
+    "3d-cone-20": lambda: cone(20, centre=15),
     "2d-fan-28": lambda: fan_mesh(28),
 }
 
