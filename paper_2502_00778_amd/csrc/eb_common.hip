@@ -96,9 +96,13 @@ __device__ inline int32_t block_excl_scan(int32_t v, int32_t *total) {
   return base + inc - v;
 }
 
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const int32_t *in, int64_t n,
+// Every scan kernel serves up to MAX_SCAN_JOBS arrays of one length at once:
+// blockIdx.y (blockIdx.x in the partials pass) picks the array, and array
+// j's block sums live at tmp + j * nb.
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(ScanJobs J, int64_t n,
                                                             int32_t *tmp) {
   __shared__ int32_t wsum[SCAN_BLOCK / 64];
+  const int32_t *in = J.in[blockIdx.y];
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
   int32_t s = 0;
 #pragma unroll
@@ -112,28 +116,32 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const int32_t *in, i
   if (threadIdx.x == 0) {
     int32_t t = 0;
     for (int w = 0; w < SCAN_BLOCK / 64; ++w) t += wsum[w];
-    tmp[blockIdx.x] = t;
+    tmp[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
   }
 }
 
-// exclusive scan of the nb block sums, in place, by one block
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_partials(int32_t *tmp, int64_t nb,
-                                                              int32_t *total_dev) {
+// exclusive scan of one array's nb block sums, in place, by one block
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_partials(ScanJobs J, int32_t *tmp,
+                                                              int64_t nb) {
+  int32_t *t = tmp + (int64_t)blockIdx.x * nb;
   int32_t carry = 0;
   for (int64_t b = 0; b < nb; b += SCAN_BLOCK) {
     int64_t i = b + threadIdx.x;
-    int32_t v = i < nb ? tmp[i] : 0;
+    int32_t v = i < nb ? t[i] : 0;
     int32_t tot;
     int32_t ex = block_excl_scan(v, &tot);
-    if (i < nb) tmp[i] = carry + ex;
+    if (i < nb) t[i] = carry + ex;
     carry += tot;
   }
-  if (threadIdx.x == 0 && total_dev) *total_dev = carry;
+  int32_t *total = J.total[blockIdx.x];
+  if (threadIdx.x == 0 && total) *total = carry;
 }
 
-template <bool INCLUSIVE>
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int32_t *in, int32_t *out,
-                                                           int64_t n, const int32_t *tmp) {
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(ScanJobs J, int64_t n,
+                                                           const int32_t *tmp) {
+  const int32_t *in = J.in[blockIdx.y];
+  int32_t *out = J.out[blockIdx.y];
+  const int32_t incl = J.inclusive[blockIdx.y] ? -1 : 0;  // mask: add the item itself
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
   // a thread's items are contiguous: whole, 16-byte aligned runs move as
   // int4 (4 loads or stores per thread instead of 16)
@@ -159,13 +167,12 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int32_t *in, in
 #pragma unroll
   for (int i = 0; i < SCAN_ITEMS; ++i) s += v[i];
   int32_t tot;
-  int32_t run = block_excl_scan(s, &tot) + tmp[blockIdx.x];
+  int32_t run = block_excl_scan(s, &tot) + tmp[(int64_t)blockIdx.y * gridDim.x + blockIdx.x];
 #pragma unroll
   for (int i = 0; i < SCAN_ITEMS; ++i) {
     const int32_t x = v[i];
-    if (INCLUSIVE) run += x;
-    v[i] = run;
-    if (!INCLUSIVE) run += x;
+    v[i] = run + (x & incl);
+    run += x;
   }
   if (vec) {
     int4 *dst = reinterpret_cast<int4 *>(out + base);
@@ -179,31 +186,42 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int32_t *in, in
   }
 }
 
-template <bool INCLUSIVE>
-static int scan_impl(const int32_t *in, int32_t *out, int64_t n, int32_t *total_dev,
-                     int32_t *tmp, hipStream_t s) {
+int scan_many(const ScanJobs &J, int count, int64_t n, int32_t *tmp, hipStream_t s) {
+  if (count < 1 || count > MAX_SCAN_JOBS) return EB_EINVAL;
   if (n <= 0) {
-    if (total_dev) return fill_i32(total_dev, 1, 0, s);
+    for (int j = 0; j < count; ++j)
+      if (J.total[j]) EB_TRY(fill_i32(J.total[j], 1, 0, s));
     return EB_OK;
   }
   const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
-  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n, tmp);
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb, (unsigned)count), dim3(SCAN_BLOCK), 0, s,
+                     J, n, tmp);
   EB_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_BLOCK), 0, s, tmp, nb, total_dev);
+  hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)count), dim3(SCAN_BLOCK), 0, s, J, tmp, nb);
   EB_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_scan_apply<INCLUSIVE>, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in,
-                     out, n, (const int32_t *)tmp);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb, (unsigned)count), dim3(SCAN_BLOCK), 0, s,
+                     J, n, (const int32_t *)tmp);
   EB_LAUNCH_CHECK();
   return EB_OK;
 }
 
+static int scan_one(const int32_t *in, int32_t *out, int64_t n, int32_t *total_dev,
+                    int32_t *tmp, bool inclusive, hipStream_t s) {
+  ScanJobs J{};
+  J.in[0] = in;
+  J.out[0] = out;
+  J.total[0] = total_dev;
+  J.inclusive[0] = inclusive;
+  return scan_many(J, 1, n, tmp, s);
+}
+
 int scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *total_dev,
                    int32_t *tmp, hipStream_t s) {
-  return scan_impl<false>(in, out, n, total_dev, tmp, s);
+  return scan_one(in, out, n, total_dev, tmp, false, s);
 }
 int scan_inclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *total_dev,
                    int32_t *tmp, hipStream_t s) {
-  return scan_impl<true>(in, out, n, total_dev, tmp, s);
+  return scan_one(in, out, n, total_dev, tmp, true, s);
 }
 
 // -------------------------------------------------------------- row sort

@@ -55,6 +55,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int SCAN_BLOCK = 256;
 constexpr int SCAN_ITEMS = 16;
+constexpr int MAX_SCAN_JOBS = 5;  // arrays one scan pass serves at most
 constexpr int64_t SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;  // items per scan block
 
 inline WsLayout ws_layout(int dim, int64_t n_nodes, int64_t n_elems) {
@@ -72,7 +73,10 @@ inline WsLayout ws_layout(int dim, int64_t n_nodes, int64_t n_elems) {
   // the longest array any call scans: ne*n_elems incidences
   const int64_t ne = dim == 2 ? 3 : 6;
   int64_t longest = std::max<int64_t>(n_nodes + 1, ne * n_elems + 1);
-  L.scan_tmp_count = (longest + SCAN_TILE - 1) / SCAN_TILE + 64;
+  // (or the node arrays' block sums, MAX_SCAN_JOBS arrays at once)
+  L.scan_tmp_count = std::max<int64_t>((longest + SCAN_TILE - 1) / SCAN_TILE,
+                                       MAX_SCAN_JOBS * ((n_nodes + SCAN_TILE) / SCAN_TILE)) +
+                     64;
   L.scan_tmp = off; off += align256(sizeof(int32_t) * (size_t)L.scan_tmp_count);
   // each node's neighbour set, slice-major (slot s of node j at
   // slice(j) * NSET * 64 + 64 s + lane(j))
@@ -148,6 +152,15 @@ int scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *total_de
                    int32_t *tmp, hipStream_t s);
 int scan_inclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *total_dev,
                    int32_t *tmp, hipStream_t s);
+// Up to MAX_SCAN_JOBS scans of arrays of the same length n in one pass (three
+// launches); tmp holds count * ceil(n / SCAN_TILE) block sums.
+struct ScanJobs {
+  const int32_t *in[MAX_SCAN_JOBS];
+  int32_t *out[MAX_SCAN_JOBS];
+  int32_t *total[MAX_SCAN_JOBS];  // device, or null
+  int32_t inclusive[MAX_SCAN_JOBS];
+};
+int scan_many(const ScanJobs &J, int count, int64_t n, int32_t *tmp, hipStream_t s);
 // Sort every CSR row of `val` ascending.
 int rowsort(const int32_t *off, int32_t *val, int64_t nrows, hipStream_t s);
 // Fill an int32 array with a value (graph-capturable; no memset nodes).

@@ -1455,11 +1455,20 @@ int build_edges_impl(int64_t nv, int64_t nelem, const int32_t *elem, const doubl
   EB_LAUNCH_CHECK();
   hipLaunchKernelGGL((k_node_topo_queued<D, false>), dim3(256), dim3(TBS), 0, s, ta);
   EB_LAUNCH_CHECK();
-  EB_TRY(scan_exclusive(eoff, eoff, nv + 1, &st->totals[T_EDGES], tmp, s));
-  EB_TRY(scan_exclusive(foff, foff, nv + 1, &st->totals[T_BFACES], tmp, s));
-  EB_TRY(scan_exclusive(bidx, bidx, nv + 1, &st->totals[T_BNODES], tmp, s));
-  EB_TRY(scan_inclusive(bfn, bfn_scan, nv + 1, nullptr, tmp, s));
-  EB_TRY(scan_inclusive(ein, ein, nv + 1, nullptr, tmp, s));
+  // the per-node counts become offsets, all five in one scan pass
+  ScanJobs J{};
+  const int32_t *sin[5] = {eoff, foff, bidx, bfn, ein};
+  int32_t *sout[5] = {eoff, foff, bidx, bfn_scan, ein};
+  int32_t *stot[5] = {&st->totals[T_EDGES], &st->totals[T_BFACES], &st->totals[T_BNODES],
+                      nullptr, nullptr};
+  const int32_t sincl[5] = {0, 0, 0, 1, 1};
+  for (int q = 0; q < 5; ++q) {
+    J.in[q] = sin[q];
+    J.out[q] = sout[q];
+    J.total[q] = stot[q];
+    J.inclusive[q] = sincl[q];
+  }
+  EB_TRY(scan_many(J, 5, nv + 1, tmp, s));
   const int64_t nsl = n_slices(nv);
   int32_t *slen = ws_at<int32_t>(ws, L.slen);
   hipLaunchKernelGGL(k_slice_len, dim3(grid_for(nsl, 256)), dim3(256), 0, s,
