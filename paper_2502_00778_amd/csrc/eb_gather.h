@@ -462,40 +462,99 @@ __device__ __forceinline__ void fwd_boundary_node(const FwdArgs &a, int64_t bj) 
   const int32_t my0 = a.node_edge_off[j], my1 = a.node_edge_off[j + 1];
   constexpr double kB = 1.0 / (D * (D + 1));
   V3 bs = {0.0, 0.0, 0.0};
-  // faces in order, four at a time: their ids, vertices and points are all
-  // loaded before the first is formed
-  constexpr int G = 4;
+  // j's out-edge heads, when there are at most 8 (padded with INT32_MAX): an
+  // edge's place is then the number of smaller heads, found without a load
+  const int32_t nout = my1 - my0;
+  const bool few = nout <= 8;
+  int32_t hd[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int32_t h = a.edge_head[nout > 0 ? my0 + min(i, nout - 1) : 0];
+    hd[i] = i < nout ? h : INT32_MAX;
+  }
+  auto place = [&](int32_t k) {
+    if (!few) return my0 + find_head(a.edge_head, my0, my1, k);
+    int32_t r = my0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) r += hd[i] < k ? 1 : 0;
+    return r;
+  };
+  // faces in order, two at a time: their ids, vertices and points are all
+  // loaded before the first is formed; then the n entries of all the round's
+  // edges are loaded together, each edge's additions chained in registers in
+  // face order, and stored (no load waits behind an earlier face's store)
+  constexpr int G = 2, H = G * (D - 1);  // a face's vertices other than j
   const int32_t r0 = a.bnode_face_off[bj], r1 = a.bnode_face_off[bj + 1];
   for (int32_t r = r0; r < r1; r += G) {
     int32_t f[G], fv[G][D];
-    V3 P[G][D];
 #pragma unroll
     for (int u = 0; u < G; ++u) f[u] = a.bnode_face[min(r + u, r1 - 1)];
 #pragma unroll
     for (int u = 0; u < G; ++u)
 #pragma unroll
       for (int s = 0; s < D; ++s) fv[u][s] = a.bface[(int64_t)f[u] * D + s];
+    V3 c[G];
+    {
+      V3 P[G][D];
 #pragma unroll
-    for (int u = 0; u < G; ++u)
+      for (int u = 0; u < G; ++u)
 #pragma unroll
-      for (int s = 0; s < D; ++s) P[u][s] = load_pt<D>(a.X, fv[u][s]);
+        for (int s = 0; s < D; ++s) P[u][s] = load_pt<D>(a.X, fv[u][s]);
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        V3 nB;
+        if constexpr (D == 3)
+          nB = 0.5 * cross(P[u][1] - P[u][0], P[u][2] - P[u][0]);
+        else
+          nB = rot2(P[u][1] - P[u][0]);
+        if (r + u < r1) bs = bs + nB;
+        c[u] = kB * nB;
+      }
+    }
+    // hit h = (face u, its (h % (D-1))-th vertex other than j, in vertex order)
+    int32_t ed[H];
+    bool hit[H];
 #pragma unroll
     for (int u = 0; u < G; ++u) {
-      if (r + u >= r1) break;
-      V3 nB;
-      if constexpr (D == 3)
-        nB = 0.5 * cross(P[u][1] - P[u][0], P[u][2] - P[u][0]);
-      else
-        nB = rot2(P[u][1] - P[u][0]);
-      bs = bs + nB;
+      // the vertices other than j, in vertex order
+      int32_t o[D - 1];
 #pragma unroll
-      for (int s2 = 0; s2 < D; ++s2) {
-        if (fv[u][s2] <= j || my1 <= my0) continue;
-        const int32_t ed = my0 + find_head(a.edge_head, my0, my1, fv[u][s2]);
-        a.n_x[ed] += kB * nB.x;
-        a.n_y[ed] += kB * nB.y;
-        if (D == 3) a.n_z[ed] += kB * nB.z;
+      for (int m = 0; m < D - 1; ++m) {
+        // m-th other vertex: skip j if it comes at or before position m
+        const bool j_before = [&] {
+          bool b = false;
+#pragma unroll
+          for (int s = 0; s <= m; ++s) b = b || fv[u][s] == j;
+          return b;
+        }();
+        o[m] = j_before ? fv[u][m + 1] : fv[u][m];
       }
+#pragma unroll
+      for (int m = 0; m < D - 1; ++m) {
+        const int h = u * (D - 1) + m;
+        hit[h] = r + u < r1 && o[m] > j && my1 > my0;
+        ed[h] = hit[h] ? place(o[m]) : 0;
+      }
+    }
+    V3 val[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h)  // (entry 0 for no hit: loaded, not used)
+      val[h] = V3{a.n_x[ed[h]], a.n_y[ed[h]], D == 3 ? a.n_z[ed[h]] : 0.0};
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      // the latest earlier hit on the same edge already holds its partial sum
+      V3 base = val[h];
+#pragma unroll
+      for (int g = 0; g < h; ++g)
+        if (hit[g] && ed[g] == ed[h]) base = val[g];
+      val[h] = base + c[h / (D - 1)];
+    }
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      if (!hit[h]) continue;
+      a.n_x[ed[h]] = val[h].x;
+      a.n_y[ed[h]] = val[h].y;
+      if (D == 3) a.n_z[ed[h]] = val[h].z;
     }
   }
   if (a.b_x) {
