@@ -199,28 +199,65 @@ __device__ __forceinline__ void bwd_node_sum(const FwdArgs &a, int64_t j) {
 }
 
 // boundary pass: the boundary faces of boundary node bj, added after the
-// node pass
+// node pass.  Faces are taken two per round with every load of a round issued
+// before the first face is formed (an absent weight array is replaced by entry
+// 0 of the coordinates, loaded and not used, so no load sits behind a branch);
+// the weights and the faces' terms are summed in the same order as face by face.
 template <int D>
 __device__ __forceinline__ void bwd_boundary_node(const FwdArgs &a, int64_t bj) {
+  constexpr int NBE = D == 2 ? 1 : 3, G = 2;
+  constexpr double kB = 1.0 / (D * (D + 1));
   const int32_t j = a.bnode[bj];
+  const int32_t r0 = a.bnode_face_off[bj], r1 = a.bnode_face_off[bj + 1];
+  const bool have_w = a.w_x != nullptr, have_be = a.be_x != nullptr;
+  const double *wx = have_w ? a.w_x : a.X.x, *wy = have_w ? a.w_y : a.X.x;
+  const double *wz = have_w ? a.w_z : a.X.x;
+  const double *bx = have_be ? a.be_x : a.X.x, *by = have_be ? a.be_y : a.X.x;
+  const double *bz = have_be ? a.be_z : a.X.x;
   V3 g = {0.0, 0.0, 0.0};
-  // (unrolled so that the loads of several faces are in flight together; the
-  // sum stays in face order)
-#pragma unroll 4
-  for (int32_t r = a.bnode_face_off[bj]; r < a.bnode_face_off[bj + 1]; ++r) {
-    const int32_t f = a.bnode_face[r];
-    int32_t fv[D];
-    V3 P[D];
-    int p = 0;
+  for (int32_t r = r0; r < r1; r += G) {
+    int32_t f[G], fv[G][D], ed[G][NBE], bi[G][D];
 #pragma unroll
-    for (int s = 0; s < D; ++s) {
-      fv[s] = a.bface[(int64_t)f * D + s];
-      P[s] = load_pt<D>(a.X, fv[s]);
-      if (fv[s] == j) p = s;
+    for (int u = 0; u < G; ++u) f[u] = a.bnode_face[min(r + u, r1 - 1)];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+#pragma unroll
+      for (int s = 0; s < D; ++s) fv[u][s] = a.bface[(int64_t)f[u] * D + s];
+#pragma unroll
+      for (int i = 0; i < NBE; ++i) ed[u][i] = a.bface_edge[(int64_t)f[u] * NBE + i];
     }
-    V3 G[D];
-    bface_grad_all<D>(P, bface_weight<D>(a, f, fv), G);
-    g = g + pick(G, p);
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+#pragma unroll
+      for (int s = 0; s < D; ++s) bi[u][s] = a.node_bnode[fv[u][s]];
+    V3 P[G][D], Wl[G][NBE], Bl[G][D];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+#pragma unroll
+      for (int s = 0; s < D; ++s) P[u][s] = load_pt<D>(a.X, fv[u][s]);
+#pragma unroll
+      for (int i = 0; i < NBE; ++i) Wl[u][i] = load_row3<D>(wx, wy, wz, have_w ? ed[u][i] : 0);
+#pragma unroll
+      for (int s = 0; s < D; ++s) Bl[u][s] = load_row3<D>(bx, by, bz, have_be ? bi[u][s] : 0);
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      if (r + u >= r1) break;
+      V3 W = {0.0, 0.0, 0.0};
+      if (have_w)
+#pragma unroll
+        for (int i = 0; i < NBE; ++i) W = W + kB * Wl[u][i];
+      if (have_be)
+#pragma unroll
+        for (int s = 0; s < D; ++s) W = W + (1.0 / D) * Bl[u][s];
+      int p = 0;
+#pragma unroll
+      for (int s = 0; s < D; ++s)
+        if (fv[u][s] == j) p = s;
+      V3 Gr[D];
+      bface_grad_all<D>(P[u], W, Gr);
+      g = g + pick(Gr, p);
+    }
   }
   a.g_x[j] += g.x;
   a.g_y[j] += g.y;
