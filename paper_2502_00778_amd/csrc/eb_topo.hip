@@ -1401,7 +1401,6 @@ int build_edges_impl(int64_t nv, int64_t nelem, const int32_t *elem, const doubl
   const Coords X = coords_rows(coords, D, nv);
 
   EB_TRY(fill_i32(reinterpret_cast<int32_t *>(st), sizeof(StatusBlock) / 4, 0, s));
-  // the six per-node arrays are contiguous lines of the workspace
   // the per-node arrays and slice lengths are contiguous lines of the workspace
   EB_TRY(fill_i32(eoff, (int64_t)((L.scan_tmp - L.eoff) / 4), 0, s));
   EB_TRY(fill_i32(node_inc_off, nv + 1, 0, s));
