@@ -42,7 +42,7 @@
  *     (bad arguments, sizes beyond int32 indexing, workspace too small) return
  *     at once and enqueue nothing.  Errors found by kernels (node id out of
  *     range, zero-measure element, a face shared by more than two elements,
- *     a node beyond the per-node capacity) set a sticky status word in `ws`;
+ *     a node beyond the plan's per-node limits) set a sticky status word in `ws`;
  *     eb_build_edges reports it, other calls leave it for eb_check_errors.
  *     Outputs are undefined after any error.  HIP failures return EB_EHIP
  *     with hipGetErrorString text in eb_last_error_detail().
@@ -70,32 +70,35 @@ typedef enum {
   EB_EWORKSPACE = -5,   /* ws_bytes below eb_workspace_bytes() */
   EB_EOVERFLOW = -6,    /* counts that would overflow int32 indexing */
   EB_EHIP = -7,         /* HIP runtime error */
-  EB_ECAPACITY = -8,    /* a node has more than EB_MAX_NEIGHBOURS distinct
-                           neighbours, or more than EB_MAX_NODE_FACES candidate
-                           faces with it as smallest vertex (faces counted once
-                           per element holding them) */
+  EB_ECAPACITY = -8,    /* a node beyond the kernel plan's per-node limits:
+                           more than EB_MAX_NODE_ELEMS elements, or more than
+                           EB_MAX_OUT_EDGES edges with it as tail (neighbours
+                           with a larger id) */
   EB_ETIMEOUT = -9      /* the fused persistent kernel gave up waiting for an
                            earlier phase (its waits are bounded; outputs are
                            then undefined) */
 } eb_status;
 
-#define EB_MAX_NEIGHBOURS 128
-#define EB_MAX_NODE_FACES 256
+/* Per-node limits of the kernel plan (eb_topology.plan).  Neither the number
+ * of distinct neighbours nor the number of faces around a node is otherwise
+ * bounded. */
+#define EB_MAX_NODE_ELEMS 65535
+#define EB_MAX_OUT_EDGES 1023
 
 typedef enum { EB_REDUCE_ATOMIC = 0, EB_REDUCE_GATHER = 1 } eb_reduce;
 typedef enum { EB_VOL_ELEMENT = 0, EB_VOL_EDGE = 1 } eb_vol_mode;
 typedef enum { EB_BFLUX_NODE = 0, EB_BFLUX_LINEAR = 1 } eb_bflux;
 
-/* Sizes of one grid; filled by eb_build_edges.  n_sell counts the entries
- * of node_sell (padding included); sell_wide selects its entry format. */
+/* Sizes of one grid; filled by eb_build_edges.  plan_bytes is the size of
+ * the kernel plan (eb_topology.plan); plan_param records the plan's layout
+ * for the library: callers copy eb_sizes whole and never set or interpret
+ * it. */
 typedef struct {
   int32_t dim;
   int64_t n_nodes, n_elems, n_edges, n_bfaces, n_bnodes;
-  int64_t n_sell;
-  int32_t sell_wide;
+  int64_t plan_bytes;
+  int64_t plan_param[2];
 } eb_sizes;
-
-#define EB_SELL_SLICE 64
 
 /* Topology arrays (device).  Every integer output is uniquely defined, so two
  * builds of the same grid give identical bits.
@@ -110,65 +113,6 @@ typedef struct {
  *   edge_inc       [ne*n_elems]     as elem*ne + local, ascending per edge
  *   node_inc_off   [n_nodes+1]    elements of each node as elem*(dim+1) +
  *   node_inc       [(dim+1)*n_elems]  local vertex, ascending per node
- *   node_sell_off  [ceil(n_nodes/64)+1]  incidences of each node in sliced
- *   node_sell      [n_sell * (1 + sell_wide)] ELL form, uint64 words: nodes are
- *                                 taken in slices of 64 (node j is lane j%64 of
- *                                 slice j/64); a slice holds L = its longest
- *                                 node_inc row, column-major: entry (r, lane)
- *                                 at node_sell_off[slice] + 64 r + lane for
- *                                 r < L (entries past a node's row are 0).
- *                                 The entries of node j are its node_inc
- *                                 row's incidences.  A row of at most 32
- *                                 is stored as a strip: first its smallest
- *                                 incidence, then repeatedly, of those not
- *                                 yet stored in ascending order, the first
- *                                 that shares at least dim-1 distinct other
- *                                 vertices with the last stored, else the
- *                                 first sharing the most; a longer row is
- *                                 stored ascending.  For incidence (element
- *                                 E, local l), local order of the other
- *                                 vertices: p_m = elem[E][m] for m < dim,
- *                                 except p_l = elem[E][dim].  In a strip they
- *                                 take places: a vertex the previous entry
- *                                 holds keeps its place there (place k is
- *                                 matched to the first unmatched p_m equal
- *                                 to it), the rest fill the free places in
- *                                 local order; the first entry, and every
- *                                 entry of a longer row, keep local order.
- *                                 o_m = the vertex in place m; slot_m = the
- *                                 position of edge (j, o_m) among j's
- *                                 out-edges (those with tail j, in
- *                                 node_edge_off order), or the field's
- *                                 all-ones value when o_m < j; code =
- *                                 sum_m slot_m << (B m).  Narrow (sell_wide =
- *                                 0): B = 5, one word, bits 16m..16m+15 =
- *                                 o_m - j as int16, bits 48..62 = code.  Wide
- *                                 (sell_wide = 1, when some |o_m - j| > 32767
- *                                 or some node has more than 31 out-edges):
- *                                 B = 10, two words per entry (entry index
- *                                 times 2), word 0 = o_0 | o_1 << 32, word 1
- *                                 = o_2 | code << 32 (o_2 = 0 in 2D).
- *                                 (Consecutive entries of a strip differ in
- *                                 one place, so a reader walking a row keeps
- *                                 the other points.)
- *   inc_sell       [(dim+1)*n_elems]  optional (NULL skips; the gather
- *                                 adjoint needs it): slot of incidence
- *                                 elem*(dim+1) + local in the sliced layout
- *                                 with rows in ascending order, i.e.
- *                                 node_sell_off[j/64] + 64 r + j%64 for the
- *                                 incidence's rank r in node j's node_inc
- *                                 row (the adjoint's per-incidence pieces
- *                                 live there)
- *   node_step      [n_sell]       optional (NULL skips; narrow format only,
- *                                 ignored when sell_wide = 1): uint32, the step
- *                                 from node j's node_sell entry c-1 to entry c
- *                                 at the same index.  When exactly one place k
- *                                 changes (o_k differs): bits 0..15 = o_k - j
- *                                 as int16, bits 16..17 = k, bits 18..22 =
- *                                 slot_k; otherwise (c = 0, or several or no
- *                                 places change) bit 23 set and the rest 0.
- *                                 Past a row's end 0.  The gather forward then
- *                                 reads 4 bytes per incidence instead of 8.
  *   node_in_off    [n_nodes+1]    ids of edges whose head is the node,
  *   node_in_edge   [n_edges]        ascending per node
  *   bface          [n_bfaces][dim] boundary elements (faces of exactly one
@@ -185,6 +129,15 @@ typedef struct {
  *   node_bnode     [n_nodes]      index into bnode, or -1 for interior nodes
  *   bnode_face_off [n_bnodes+1]   boundary faces of each boundary node,
  *   bnode_face     [dim*n_bfaces]   ascending per node
+ *   plan           [plan_bytes]   the kernel plan: the library's own
+ *                                 per-node view of the incidences (each
+ *                                 node's elements with their other vertices
+ *                                 and out-edge positions, laid out for the
+ *                                 node-centred kernels), written by
+ *                                 eb_build_edges_emit and read by the
+ *                                 EB_REDUCE_GATHER paths.  Opaque: its
+ *                                 format is private to the library and may
+ *                                 change between versions; 256-byte aligned.
  */
 typedef struct {
   int32_t *edge;
@@ -193,10 +146,6 @@ typedef struct {
   int8_t *elem_edge_sign;
   int32_t *edge_inc_off, *edge_inc;
   int32_t *node_inc_off, *node_inc;
-  int32_t *node_sell_off;
-  uint64_t *node_sell;
-  int32_t *inc_sell;
-  uint32_t *node_step;
   int32_t *node_in_off, *node_in_edge;
   int32_t *bface;
   int32_t *bface_owner;
@@ -204,14 +153,15 @@ typedef struct {
   int32_t *bnode;
   int32_t *node_bnode;
   int32_t *bnode_face_off, *bnode_face;
+  void *plan;
 } eb_topology;
 
 /* Bytes of workspace every call below needs for a grid of this size. */
 size_t eb_workspace_bytes(int dim, int64_t n_nodes, int64_t n_elems);
 
 /* Bytes of workspace eb_directed_areas_backward needs with EB_REDUCE_GATHER:
- * the above plus 8*(dim == 3 ? 4 : 2) bytes per node_sell entry for the
- * per-incidence gradients.  A workspace this large serves every call; the
+ * the above grown to hold one gradient piece (dim doubles) per incidence
+ * slot of the kernel plan.  A workspace this large serves every call; the
  * sticky status word sits at its start in either case, so the same
  * workspace is passed to every call on one grid. */
 size_t eb_backward_workspace_bytes(const eb_sizes *sizes);
@@ -231,7 +181,8 @@ int eb_build_edges(int dim, int64_t n_nodes, int64_t n_elems, const int32_t *ele
 /* Edge extraction, phase 2: writes every other eb_topology array (sized from
  * *sizes) from what eb_build_edges left in ws (the same ws, untouched in
  * between).  topo->node_inc_off and topo->node_inc must be the arrays phase 1
- * filled.  edge_inc_off/edge_inc and inc_sell may be NULL. */
+ * filled.  edge_inc_off/edge_inc may be NULL; topo->plan must hold
+ * sizes->plan_bytes bytes, 256-byte aligned. */
 int eb_build_edges_emit(const eb_sizes *sizes, const int32_t *elem, const double *coords,
                         const eb_topology *topo, void *ws, size_t ws_bytes,
                         hipStream_t stream);
@@ -313,11 +264,11 @@ int eb_edge_residual(const eb_sizes *sizes, const eb_topology *topo, const int32
  * formulas above; the orientation sign of each element is held fixed.
  * ATOMIC: thread per element/boundary face with FP64 atomics.  GATHER: an
  * element pass writes each element's gradient with respect to each of its
- * vertices into the workspace at that incidence's node_sell position
- * (topo->inc_sell), then one thread per node sums its column in node_inc
- * order and adds its boundary faces in bnode_face order: no atomics, bitwise
- * reproducible.  GATHER needs topo->inc_sell and ws_bytes >=
- * eb_backward_workspace_bytes(sizes) (else EB_EINVAL / EB_EWORKSPACE). */
+ * vertices into the workspace at that incidence's slot of the plan, then
+ * one thread per node sums its slots in node_inc order and adds its boundary
+ * faces in bnode_face order: no atomics, bitwise reproducible.  GATHER needs
+ * topo->plan and ws_bytes >= eb_backward_workspace_bytes(sizes) (else
+ * EB_EINVAL / EB_EWORKSPACE). */
 int eb_directed_areas_backward(const eb_sizes *sizes, const eb_topology *topo,
                                const int32_t *elem, const double *coords,
                                const double *grad_n, const double *grad_b,
@@ -446,6 +397,22 @@ int eb_autotune(const eb_sizes *sizes, const eb_topology *topo, const int32_t *e
                 const double *grad_vol, double *n_edge, double *b_node, double *vol,
                 double *grad_coords, void *ws, size_t ws_bytes, int reps, hipStream_t stream,
                 eb_tuning *out);
+
+/* Diagnostic view of a kernel plan, for tests and tools that check the
+ * plan against the topology it was built from.  Fills *view with device
+ * pointers into `plan` and the plan's counts; no device access.  The
+ * encoding of these arrays is private to the library (it is stated in the
+ * library source, csrc/eb_plan.h) and may change between versions; no
+ * computation needs them. */
+typedef struct {
+  const int32_t *slice_off;  /* [ceil(n_nodes/64)+1] */
+  const uint64_t *entry;     /* [n_slots * words] */
+  const uint32_t *step;      /* [n_slots], or NULL when words == 2 */
+  const int32_t *inc_slot;   /* [(dim+1)*n_elems] */
+  int64_t n_slots;
+  int32_t words;             /* 64-bit words per entry: 1 or 2 */
+} eb_plan_view;
+int eb_plan_describe(const eb_sizes *sizes, const void *plan, eb_plan_view *view);
 
 /* Synchronizes `stream`, returns the sticky device status in ws and resets it
  * to EB_OK. */

@@ -10,8 +10,11 @@ statement.  It shares no code with the GPU library.
 
 Functions
 ---------
-``topology(dim, coords, elems)``        -> dict of int arrays (the layout the
-                                          GPU must reproduce bit for bit)
+``topology(dim, coords, elems)``        -> dict of int arrays: the edge array,
+                                          element->edge map, incidence CSRs and
+                                          boundary elements, each uniquely
+                                          defined (the GPU must match them bit
+                                          for bit)
 ``metrics(topo, coords, elems)``        -> (n [D,Ne], b [D,Nbn], V [Nv])
 ``element_pieces(dim, coords, elems)``  -> per-element dual pieces
 ``bface_piece(dim, coords, face, opp)`` -> per-vertex boundary pieces
@@ -33,8 +36,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "node id out of range",
           -6: "size overflow"}
 
 TOPO_ARRAYS = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign",
-               "edge_inc_off", "edge_inc", "node_inc_off", "node_inc", "node_sell_off",
-               "node_sell", "inc_sell", "node_step",
+               "edge_inc_off", "edge_inc", "node_inc_off", "node_inc",
                "node_in_off", "node_in_edge", "bface", "bface_owner",
                "bface_edge", "bnode", "node_bnode", "bnode_face_off",
                "bnode_face")
@@ -107,15 +109,14 @@ class Topology:
             L.oracle_topo_free(self._h)
             self._h = None
             raise OracleError(rc, "topology")
-        s = np.zeros(8, dtype=np.int64)
+        s = np.zeros(6, dtype=np.int64)
         L.oracle_topo_sizes(self._h, _ptr(s))
         (_, self.n_nodes, self.n_elems, self.n_edges, self.n_bfaces,
-         self.n_bnodes, self.n_sell, self.sell_wide) = (int(x) for x in s)
+         self.n_bnodes) = (int(x) for x in s)
         self.arrays = {}
         for name in TOPO_ARRAYS:
             cnt = L.oracle_topo_get(self._h, name.encode(), None)
-            dt = {"elem_edge_sign": np.int8, "node_sell": np.uint64,
-                  "node_step": np.uint32}.get(name, np.int32)
+            dt = np.int8 if name == "elem_edge_sign" else np.int32
             a = np.empty(cnt, dtype=dt)
             L.oracle_topo_get(self._h, name.encode(), _ptr(a))
             self.arrays[name] = a

@@ -42,34 +42,6 @@
 //   elem_edge_sign [NE][ne]  +1 iff elem[p] < elem[q]
 //   edge_inc    CSR over edges of elem*ne+local, ascending
 //   node_inc    CSR over nodes of elem*(D+1)+local, ascending
-//   node_sell   node_inc rows in sliced ELL form: slices of 64 nodes, each
-//               as long as its longest row, column-major (entry (c, lane) at
-//               slice offset + 64 c + lane, zero past a row's end).  A row of
-//               at most 32 incidences is stored as a strip: first its
-//               smallest incidence, then repeatedly, of those not yet stored
-//               in ascending order, the first sharing at least D-1 distinct
-//               other vertices with the last stored, else the first sharing
-//               the most; a longer row is stored ascending.
-//               The other vertices of incidence (element E, local l) in
-//               local order are E's vertices m < D with j's place l taken by
-//               vertex D.  In a strip they go to D places: a vertex that the
-//               previous entry holds keeps its place there, the others fill
-//               the free places in local order (the first entry, and every
-//               entry of a longer row, keeps local order).  o_m is the vertex
-//               in place m; s_m = rank of edge (j, o_m) among the edges whose
-//               tail is j, or 31 (all ones) when o_m < j;
-//               code = sum s_m << (B m).  Narrow
-//               (B = 5): one word with o_m - j as int16 in bits 16m.. and
-//               code in bits 48..; wide (B = 10; when some |o_m - j| >
-//               32767 or some node has more than 31 out-edges): two words
-//               o_0 | o_1 << 32 and o_2 | code << 32
-//   node_step   [n_sell] (narrow format only, else empty) the step from
-//               entry c-1 of a row to entry c: if exactly one place k
-//               changes, o_k - j (int16) | k << 16 | slot_k << 18; else
-//               1 << 23 (c = 0, several or no places); 0 past the row
-//   inc_sell    [(D+1) NE] slot of each incidence e*(D+1)+l in the sliced
-//               layout with rows in ascending order (column = rank of the
-//               incidence in node_inc's row), whatever order node_sell uses
 //   node_edge_off  CSR offsets of edges by tail
 //   node_in     CSR over nodes of the ids of edges whose head is the node
 //   bface       [NB][D] faces owned by one element, in ascending sorted-id
@@ -88,7 +60,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
-#include <iterator>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -276,12 +247,6 @@ struct Topo {
   std::vector<int32_t> node_edge_off, elem_edge, edge_inc_off, edge_inc;
   std::vector<int8_t> elem_edge_sign;
   std::vector<int32_t> node_inc_off, node_inc, node_in_off, node_in_edge;
-  std::vector<int32_t> node_sell_off;
-  std::vector<uint64_t> node_sell;
-  std::vector<int32_t> inc_sell;
-  std::vector<uint32_t> node_step;
-  int64_t n_sell = 0;
-  int sell_wide = 0;
   std::vector<int32_t> bface, bface_owner, bface_edge, bnode, node_bnode;
   std::vector<int32_t> bnode_face_off, bnode_face;
 };
@@ -293,9 +258,6 @@ template <class It, class Cmp> void sort_range(It b, It e, Cmp c) {
   std::sort(b, e, c);
 #endif
 }
-
-// longest node_inc row stored as a strip in the sliced layout
-constexpr int32_t kStripMax = 32;
 
 struct KeyPay {
   uint64_t key;
@@ -399,154 +361,6 @@ int build_topology(Topo &t, int dim, int64_t nv, int64_t nelem, const int32_t *e
       for (int i = 0; i < nn; ++i)
         np[e * nn + i] = KeyPay{(uint64_t)elem[e * nn + i], (uint32_t)(e * nn + i)};
     csr_from_pairs(np, nv, t.node_inc_off, t.node_inc);
-  }
-
-  // node_inc rows in sliced ELL form with each entry's other vertices and
-  // their out-edge ranks
-  {
-    const int64_t nsl = (nv + 63) / 64;
-    std::vector<int64_t> slen(nsl, 0);
-    for (int64_t v = 0; v < nv; ++v)
-      slen[v / 64] = std::max<int64_t>(slen[v / 64], t.node_inc_off[v + 1] - t.node_inc_off[v]);
-    t.node_sell_off.assign(nsl + 1, 0);
-    for (int64_t sl = 0; sl < nsl; ++sl)
-      t.node_sell_off[sl + 1] = (int32_t)(t.node_sell_off[sl] + 64 * slen[sl]);
-    t.n_sell = t.node_sell_off[nsl];
-    // format: wide when a neighbour id differs by more than int16 range or a
-    // node has more than 31 out-edges; slot fields are 5 (narrow) or 10 bits
-    int64_t maxdelta = 0, maxout = 0;
-    for (int64_t v = 0; v < nv; ++v) {
-      maxout = std::max<int64_t>(maxout, t.node_edge_off[v + 1] - t.node_edge_off[v]);
-      for (int32_t r = t.node_inc_off[v]; r < t.node_inc_off[v + 1]; ++r) {
-        const int64_t e = t.node_inc[r] / nn;
-        for (int q = 0; q < nn; ++q)
-          maxdelta = std::max<int64_t>(maxdelta, std::llabs((int64_t)elem[e * nn + q] - v));
-      }
-    }
-    t.sell_wide = (maxdelta > 32767 || maxout > 31) ? 1 : 0;
-    const int B = t.sell_wide ? 10 : 5;
-    const uint32_t none = (1u << B) - 1;
-    // each row's storage order and each entry's vertex order (see the
-    // layout notes at the top)
-    std::vector<int32_t> others((size_t)t.node_inc.size() * dim);
-    std::vector<int32_t> column(t.node_inc.size());  // storage rank in the row
-    std::vector<uint32_t> codes(t.node_inc.size());
-    for (int64_t v = 0; v < nv; ++v) {
-      const int32_t r0 = t.node_inc_off[v], len = t.node_inc_off[v + 1] - r0;
-      std::vector<std::vector<int32_t>> loc(len);
-      for (int32_t i = 0; i < len; ++i) {
-        const int64_t e = t.node_inc[r0 + i] / nn;
-        const int l = t.node_inc[r0 + i] % nn;
-        for (int m = 0; m < dim; ++m) loc[i].push_back(elem[e * nn + (m == l ? dim : m)]);
-      }
-      std::vector<int32_t> order(len);
-      for (int32_t i = 0; i < len; ++i) order[i] = i;
-      if (len <= kStripMax && len > 0) {
-        std::vector<char> taken(len, 0);
-        taken[0] = 1;
-        for (int32_t c = 1; c < len; ++c) {
-          int best = -1, shared_best = -1;
-          for (int32_t i = 0; i < len; ++i) {
-            if (taken[i]) continue;
-            // distinct vertices in common
-            std::vector<int32_t> p = loc[i], q = loc[order[c - 1]], both;
-            std::sort(p.begin(), p.end());
-            std::sort(q.begin(), q.end());
-            std::set_intersection(p.begin(), p.end(), q.begin(), q.end(),
-                                  std::back_inserter(both));
-            const int shared = (int)(std::unique(both.begin(), both.end()) - both.begin());
-            if (shared > shared_best) {
-              shared_best = shared;
-              best = i;
-              if (shared >= dim - 1) break;
-            }
-          }
-          order[c] = best;
-          taken[best] = 1;
-        }
-      }
-      std::vector<int32_t> slots(dim, -1);
-      for (int32_t c = 0; c < len; ++c) {
-        const int32_t i = order[c];
-        const std::vector<int32_t> &o = loc[i];
-        std::vector<int32_t> next = o;
-        if (len <= kStripMax) {
-          // place k keeps its vertex when the first unmatched o_m equal to
-          // it exists; unmatched o_m then fill the other places in order
-          std::vector<char> matched(dim, 0), kept(dim, 0);
-          for (int k = 0; k < dim; ++k)
-            for (int m = 0; m < dim && !kept[k]; ++m)
-              if (!matched[m] && o[m] == slots[k]) kept[k] = matched[m] = 1;
-          int k = 0;
-          for (int m = 0; m < dim; ++m) {
-            if (matched[m]) continue;
-            while (kept[k]) ++k;
-            next[k++] = o[m];
-          }
-          for (int kk = 0; kk < dim; ++kk)
-            if (kept[kk]) next[kk] = slots[kk];
-        }
-        slots = next;
-        const int32_t r = r0 + i;
-        column[r] = c;
-        uint32_t code = 0;
-        for (int m = 0; m < dim; ++m) {
-          const int32_t om = next[m];
-          uint32_t rank = none;
-          if (om > v) rank = (uint32_t)(find_edge(t, (int32_t)v, om) - t.node_edge_off[v]);
-          code |= rank << (B * m);
-          others[(size_t)r * dim + m] = om;
-        }
-        codes[r] = code;
-      }
-    }
-    t.node_sell.assign((size_t)t.n_sell * (t.sell_wide ? 2 : 1), 0);
-    t.inc_sell.assign(t.node_inc.size(), -1);
-    for (int64_t v = 0; v < nv; ++v)
-      for (int32_t r = t.node_inc_off[v]; r < t.node_inc_off[v + 1]; ++r) {
-        const int64_t pos = t.node_sell_off[v / 64] + 64 * column[r] + v % 64;
-        t.inc_sell[t.node_inc[r]] =
-            (int32_t)(t.node_sell_off[v / 64] + 64 * (r - t.node_inc_off[v]) + v % 64);
-        const int32_t *o = &others[(size_t)r * dim];
-        if (!t.sell_wide) {
-          uint64_t w = (uint64_t)codes[r] << 48;
-          for (int m = 0; m < dim; ++m)
-            w |= (uint64_t)(uint16_t)(int16_t)(o[m] - v) << (16 * m);
-          t.node_sell[pos] = w;
-        } else {
-          t.node_sell[2 * pos] = (uint64_t)(uint32_t)o[0] | ((uint64_t)(uint32_t)o[1] << 32);
-          t.node_sell[2 * pos + 1] =
-              (uint64_t)(uint32_t)(dim == 3 ? o[2] : 0) | ((uint64_t)codes[r] << 32);
-        }
-      }
-  }
-
-  // steps between consecutive entries of a row (narrow format only)
-  if (!t.sell_wide) {
-    t.node_step.assign((size_t)t.n_sell, 0);
-    for (int64_t v = 0; v < nv; ++v) {
-      const int32_t len = t.node_inc_off[v + 1] - t.node_inc_off[v];
-      std::vector<int32_t> prev;
-      for (int32_t c = 0; c < len; ++c) {
-        const int64_t pos = t.node_sell_off[v / 64] + 64 * c + v % 64;
-        const uint64_t w = t.node_sell[pos];
-        std::vector<int32_t> cur(dim);
-        for (int m = 0; m < dim; ++m) cur[m] = (int32_t)(v + (int16_t)(uint16_t)(w >> (16 * m)));
-        int changed = 0, k = -1;
-        for (int m = 0; m < dim && c > 0; ++m)
-          if (cur[m] != prev[m]) {
-            ++changed;
-            if (k < 0) k = m;
-          }
-        uint32_t step = 1u << 23;
-        if (c > 0 && changed == 1) {
-          const uint32_t slot = (uint32_t)(w >> 48 >> (5 * k)) & 31u;
-          step = (uint32_t)(uint16_t)(int16_t)(cur[k] - v) | ((uint32_t)k << 16) | (slot << 18);
-        }
-        t.node_step[pos] = step;
-        prev = cur;
-      }
-    }
   }
 
   // faces: sorted vertex ids of the face opposite each local vertex
@@ -741,7 +555,7 @@ int oracle_topology(void *h, int dim, int64_t nv, int64_t nelem, const int32_t *
   return build_topology(*static_cast<Topo *>(h), dim, nv, nelem, elem, X);
 }
 
-// sizes: dim, nv, nelem, nedge, nbface, nbnode, n_sell, sell_wide
+// sizes: dim, nv, nelem, nedge, nbface, nbnode
 void oracle_topo_sizes(const void *h, int64_t *out) {
   const Topo &t = *static_cast<const Topo *>(h);
   out[0] = t.dim;
@@ -750,8 +564,6 @@ void oracle_topo_sizes(const void *h, int64_t *out) {
   out[3] = t.nedge;
   out[4] = t.nbface;
   out[5] = t.nbnode;
-  out[6] = t.n_sell;
-  out[7] = t.sell_wide;
 }
 
 // Copy one named array out; returns element count, or -1 for an unknown name.
@@ -772,10 +584,6 @@ int64_t oracle_topo_get(const void *h, const char *name, void *dst) {
       {"edge_inc", t.edge_inc.data(), t.edge_inc.size(), 4},
       {"node_inc_off", t.node_inc_off.data(), t.node_inc_off.size(), 4},
       {"node_inc", t.node_inc.data(), t.node_inc.size(), 4},
-      {"node_sell_off", t.node_sell_off.data(), t.node_sell_off.size(), 4},
-      {"node_sell", t.node_sell.data(), t.node_sell.size(), 8},
-      {"inc_sell", t.inc_sell.data(), t.inc_sell.size(), 4},
-      {"node_step", t.node_step.data(), t.node_step.size(), 4},
       {"node_in_off", t.node_in_off.data(), t.node_in_off.size(), 4},
       {"node_in_edge", t.node_in_edge.data(), t.node_in_edge.size(), 4},
       {"bface", t.bface.data(), t.bface.size(), 4},

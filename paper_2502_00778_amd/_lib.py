@@ -26,25 +26,31 @@ EXPORTS = ("eb_workspace_bytes", "eb_backward_workspace_bytes", "eb_build_edges"
            "eb_batch_offsets", "eb_batch_forward_backward", "eb_batch_graph_create",
            "eb_graph_launch", "eb_graph_destroy", "eb_set_fused_shape", "eb_get_fused_shape",
            "eb_set_fused_wait_limit", "eb_autotune", "eb_edge_residual",
-           "eb_directed_areas_variant", "eb_set_fused_mode", "eb_get_fused_mode")
+           "eb_directed_areas_variant", "eb_set_fused_mode", "eb_get_fused_mode",
+           "eb_plan_describe")
 
 TOPO_FIELDS = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign",
-               "edge_inc_off", "edge_inc", "node_inc_off", "node_inc", "node_sell_off",
-               "node_sell", "inc_sell", "node_step",
+               "edge_inc_off", "edge_inc", "node_inc_off", "node_inc",
                "node_in_off", "node_in_edge", "bface", "bface_owner",
                "bface_edge", "bnode", "node_bnode", "bnode_face_off",
-               "bnode_face")
+               "bnode_face", "plan")
 
 
 class EbSizes(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n_nodes", ctypes.c_int64),
                 ("n_elems", ctypes.c_int64), ("n_edges", ctypes.c_int64),
                 ("n_bfaces", ctypes.c_int64), ("n_bnodes", ctypes.c_int64),
-                ("n_sell", ctypes.c_int64), ("sell_wide", ctypes.c_int32)]
+                ("plan_bytes", ctypes.c_int64), ("plan_param", ctypes.c_int64 * 2)]
 
 
 class EbTopology(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p) for name in TOPO_FIELDS]
+
+
+class EbPlanView(ctypes.Structure):
+    _fields_ = [("slice_off", ctypes.c_void_p), ("entry", ctypes.c_void_p),
+                ("step", ctypes.c_void_p), ("inc_slot", ctypes.c_void_p),
+                ("n_slots", ctypes.c_int64), ("words", ctypes.c_int32)]
 
 
 class EbTuning(ctypes.Structure):
@@ -118,6 +124,7 @@ def lib():
                               ctypes.POINTER(EbTuning)]
     L.eb_edge_residual.argtypes = [SZ, TP, P, P, P, P, P, i32, P, P, sz, P]
     L.eb_directed_areas_variant.argtypes = [SZ, TP, P, P, i32, P, P, P, P, sz, P]
+    L.eb_plan_describe.argtypes = [SZ, P, ctypes.POINTER(EbPlanView)]
     L.eb_status_string.argtypes = [i32]
     L.eb_status_string.restype = ctypes.c_char_p
     L.eb_last_error_detail.restype = ctypes.c_char_p

@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 from dataclasses import dataclass, field
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -62,8 +63,6 @@ class Topology:
     n_edges: int
     n_bfaces: int
     n_bnodes: int
-    n_sell: int
-    sell_wide: int
     arrays: dict
     ws: torch.Tensor
     sizes: EbSizes = field(repr=False, default=None)
@@ -77,21 +76,39 @@ class Topology:
         return 3 if self.dim == 2 else 6
 
     def to_numpy(self):
-        out = {}
-        for k, v in self.arrays.items():
-            if v is not None:
-                a = v.cpu().numpy()
-                out[k] = (a.view("uint64") if k == "node_sell" else
-                          a.view("uint32") if k == "node_step" else a)
-        return out
+        """Host copies of the topology arrays (the opaque plan excluded)."""
+        return {k: v.cpu().numpy() for k, v in self.arrays.items()
+                if v is not None and k != "plan"}
+
+    def plan_view(self):
+        """eb_plan_describe: host copies of the kernel plan's arrays, for
+        tests that check the plan against the topology (its encoding is the
+        library's private one, stated in csrc/eb_plan.h)."""
+        v = _lib.EbPlanView()
+        plan = self.arrays["plan"]
+        check(lib().eb_plan_describe(ctypes.byref(self.sizes), _ptr(plan), ctypes.byref(v)),
+              "eb_plan_describe")
+        host, base = plan.cpu().numpy(), plan.data_ptr()
+
+        def part(ptr, count, dtype):
+            if not ptr:
+                return None
+            off = ptr - base
+            return host[off: off + count * np.dtype(dtype).itemsize].view(dtype)
+
+        return dict(slice_off=part(v.slice_off, (self.n_nodes + 63) // 64 + 1, np.int32),
+                    entry=part(v.entry, v.n_slots * v.words, np.uint64),
+                    step=part(v.step, v.n_slots, np.uint32),
+                    inc_slot=part(v.inc_slot, (self.dim + 1) * self.n_elems, np.int32),
+                    n_slots=int(v.n_slots), words=int(v.words))
 
 
 def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True,
                 adjoint: bool = True, stream=None) -> Topology:
     """Edge extraction and boundary elements (eb_build_edges + _emit).
 
-    ``adjoint`` also builds inc_sell and sizes the workspace for the gather
-    adjoint (eb_backward_workspace_bytes)."""
+    ``adjoint`` also sizes the workspace for the gather adjoint
+    (eb_backward_workspace_bytes)."""
     if elems.dim() != 2 or elems.shape[1] not in (3, 4):
         raise ValueError("elems must be [NE, D+1] with D in {2, 3}")
     dim = int(elems.shape[1]) - 1
@@ -124,12 +141,6 @@ def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True
         edge_inc=torch.empty(max(ne * nel, 1), **i32) if edge_inc else None,
         node_inc_off=node_inc_off,
         node_inc=node_inc,
-        node_sell_off=torch.empty((nv + 63) // 64 + 1, **i32),
-        node_sell=torch.empty(max(int(sizes.n_sell) * (1 + int(sizes.sell_wide)), 1),
-                              dtype=torch.int64, device=dev),
-        inc_sell=torch.empty(max((dim + 1) * nel, 1), **i32) if adjoint else None,
-        node_step=(torch.empty(max(int(sizes.n_sell), 1), **i32)
-                   if not int(sizes.sell_wide) else None),
         node_in_off=torch.empty(nv + 1, **i32),
         node_in_edge=torch.empty(max(ne_, 1), **i32),
         bface=torch.empty(nb, dim, **i32),
@@ -139,6 +150,7 @@ def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True
         node_bnode=torch.empty(nv, **i32),
         bnode_face_off=torch.empty(nbn + 1, **i32),
         bnode_face=torch.empty(max(dim * nb, 1), **i32),
+        plan=torch.empty(int(sizes.plan_bytes), dtype=torch.uint8, device=dev),
     )
     st = EbTopology(**{k: (v.data_ptr() if v is not None else None) for k, v in arr.items()})
     check(L.eb_build_edges_emit(ctypes.byref(sizes), _ptr(elems), _ptr(coords),
@@ -155,17 +167,11 @@ def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True
             ws, wsb = ws2, wsb2
     # trim the placeholder lengths used for empty arrays
     arr["node_inc"] = arr["node_inc"][: (dim + 1) * nel]
-    arr["node_sell"] = arr["node_sell"][: int(sizes.n_sell) * (1 + int(sizes.sell_wide))]
     arr["node_in_edge"] = arr["node_in_edge"][:ne_]
     arr["bnode_face"] = arr["bnode_face"][: dim * nb]
     if edge_inc:
         arr["edge_inc"] = arr["edge_inc"][: ne * nel]
-    if adjoint:
-        arr["inc_sell"] = arr["inc_sell"][: (dim + 1) * nel]
-    if arr["node_step"] is not None:
-        arr["node_step"] = arr["node_step"][: int(sizes.n_sell)]
-    return Topology(dim, nv, nel, ne_, nb, nbn, int(sizes.n_sell), int(sizes.sell_wide), arr,
-                    ws, sizes, st)
+    return Topology(dim, nv, nel, ne_, nb, nbn, arr, ws, sizes, st)
 
 
 def _out(shape, like, out):

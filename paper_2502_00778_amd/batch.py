@@ -179,7 +179,7 @@ def set_fused_wait_limit(spins: int):
 def _cache_key(topo):
     name = torch.cuda.get_device_name(torch.cuda.current_device())
     return (f"{name}|D{topo.dim}|v{topo.n_nodes}|E{topo.n_elems}|e{topo.n_edges}"
-            f"|s{topo.n_sell}|w{topo.sell_wide}")
+            f"|p{int(topo.sizes.plan_bytes)}")
 
 
 def autotune(coords, topo, elems, grad_n=None, grad_b=None, grad_vol=None, reps: int = 3,

@@ -40,6 +40,14 @@ TimedLaunch take_principal_events() {
 int pack(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem, const double *coords,
          void *ws, size_t ws_bytes, FwdArgs &a) {
   EB_TRY(check_sizes(sz));
+  EB_TRY(check_ws(sz->dim, sz->n_nodes, sz->n_elems, ws, ws_bytes));
+  EB_TRY(pack_arrays(sz, tp, elem, coords, a));
+  a.st = ws_at<StatusBlock>(ws, 0);
+  return EB_OK;
+}
+
+int pack_arrays(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
+                const double *coords, FwdArgs &a) {
   if (!tp || !coords || (sz->n_elems > 0 && !elem)) {
     set_detail("null pointer");
     return EB_EINVAL;
@@ -48,7 +56,10 @@ int pack(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem, const d
     set_detail("arrays must be 16-byte aligned");
     return EB_EINVAL;
   }
-  EB_TRY(check_ws(sz->dim, sz->n_nodes, sz->n_elems, ws, ws_bytes));
+  if ((reinterpret_cast<uintptr_t>(tp->plan) & 255u) != 0) {
+    set_detail("the plan must be 256-byte aligned");
+    return EB_EINVAL;
+  }
   a = FwdArgs{};
   a.nv = sz->n_nodes;
   a.nelem = sz->n_elems;
@@ -60,11 +71,12 @@ int pack(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem, const d
   a.elem_edge = tp->elem_edge;
   a.node_inc_off = tp->node_inc_off;
   a.node_inc = tp->node_inc;
-  a.node_sell_off = tp->node_sell_off;
-  a.node_sell = tp->node_sell;
-  a.inc_sell = tp->inc_sell;
-  a.node_step = sz->sell_wide ? nullptr : tp->node_step;
-  a.sell_wide = sz->sell_wide;
+  const PlanPtrs pl = plan_ptrs(sz, tp->plan);
+  a.node_sell_off = pl.slice_off;
+  a.node_sell = pl.entry;
+  a.inc_sell = pl.inc_slot;
+  a.node_step = pl.step;
+  a.sell_wide = plan_wide(sz);
   a.node_edge_off = tp->node_edge_off;
   a.edge_tail = tp->edge;
   a.edge_head = tp->edge ? tp->edge + sz->n_edges : nullptr;
@@ -76,7 +88,6 @@ int pack(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem, const d
   a.bnode = tp->bnode;
   a.bnode_face_off = tp->bnode_face_off;
   a.bnode_face = tp->bnode_face;
-  a.st = ws_at<StatusBlock>(ws, 0);
   return EB_OK;
 }
 
@@ -99,9 +110,9 @@ void crows(const double *p, int dim, int64_t n, const double *&x, const double *
 }
 
 int check_fwd_gather(const eb_sizes *sizes, const FwdArgs &a) {
-  EB_TRY(need(a.node_inc_off && a.node_sell_off && (a.node_sell || sizes->n_elems == 0) &&
-                  a.node_edge_off && a.edge_head && a.bnode_face_off,
-              "node_inc_off, node_sell, node_edge_off, edge, bnode_face_off"));
+  EB_TRY(need(a.node_inc_off && a.node_sell_off && a.node_edge_off && a.edge_head &&
+                  a.bnode_face_off,
+              "node_inc_off, plan, node_edge_off, edge, bnode_face_off"));
   if (sizes->n_bfaces > 0) EB_TRY(need(a.bface && a.bnode && a.bnode_face, "bface, bnode, bnode_face"));
   return EB_OK;
 }
@@ -119,23 +130,22 @@ int check_bwd_gather(const eb_sizes *sizes, FwdArgs &a, void *ws, size_t ws_byte
   const int D = sizes->dim;
   if (a.w_x) EB_TRY(need(a.elem_edge != nullptr, "elem_edge"));
   EB_TRY(check_elem_edge_aligned(sizes, a));
-  EB_TRY(need(a.node_inc_off && a.node_sell_off && (sizes->n_elems == 0 || a.inc_sell),
-              "node_inc_off, node_sell_off, inc_sell"));
-  if (!aligned16(a.inc_sell)) {
-    set_detail("inc_sell must be 16-byte aligned");
+  EB_TRY(need(a.node_inc_off && a.node_sell_off, "node_inc_off, plan"));
+  if (!aligned16(a.node_sell_off)) {
+    set_detail("the plan must be 256-byte aligned");
     return EB_EINVAL;
   }
   if (sizes->n_bfaces > 0 && (a.w_x || a.be_x))
     EB_TRY(need(a.bface && a.bface_edge && a.node_bnode && a.bnode && a.bnode_face_off &&
                     a.bnode_face,
                 "bface, bface_edge, node_bnode, bnode, bnode_face"));
-  const size_t want = backward_ws_total(D, sizes->n_nodes, sizes->n_elems, sizes->n_sell);
+  const size_t want = backward_ws_total(D, sizes->n_nodes, sizes->n_elems, plan_slots(sizes));
   if (ws_bytes < want) {
     set_detail("the gather adjoint needs %zu workspace bytes, got %zu", want, ws_bytes);
     return EB_EWORKSPACE;
   }
   a.gpiece = ws_at<double>(ws, gpiece_offset(D, sizes->n_nodes, sizes->n_elems));
-  a.gstride = sizes->n_sell;
+  a.gstride = plan_slots(sizes);
   return EB_OK;
 }
 

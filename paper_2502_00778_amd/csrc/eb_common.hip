@@ -3,7 +3,7 @@
 #include <cstdarg>
 #include <cstring>
 
-#include "eb_internal.h"
+#include "eb_plan.h"
 
 namespace eb {
 
@@ -54,6 +54,10 @@ int check_sizes(const eb_sizes *s) {
   if (ne * s->n_elems >= (int64_t(1) << 31) || s->n_nodes >= (int64_t(1) << 31) - 1) {
     set_detail("grid too large for int32 indexing");
     return EB_EOVERFLOW;
+  }
+  if (!plan_params_valid(s)) {
+    set_detail("eb_sizes does not come from eb_build_edges (plan fields)");
+    return EB_EINVAL;
   }
   return EB_OK;
 }
@@ -303,7 +307,25 @@ size_t eb_workspace_bytes(int dim, int64_t n_nodes, int64_t n_elems) {
 
 size_t eb_backward_workspace_bytes(const eb_sizes *sizes) {
   if (eb::check_sizes(sizes) != EB_OK) return 0;
-  return eb::backward_ws_total(sizes->dim, sizes->n_nodes, sizes->n_elems, sizes->n_sell);
+  return eb::backward_ws_total(sizes->dim, sizes->n_nodes, sizes->n_elems,
+                               eb::plan_slots(sizes));
+}
+
+int eb_plan_describe(const eb_sizes *sizes, const void *plan, eb_plan_view *view) {
+  eb::clear_detail();
+  EB_TRY(eb::check_sizes(sizes));
+  if (!plan || !view) {
+    eb::set_detail("null pointer");
+    return EB_EINVAL;
+  }
+  const eb::PlanPtrs p = eb::plan_ptrs(sizes, const_cast<void *>(plan));
+  view->slice_off = p.slice_off;
+  view->entry = p.entry;
+  view->step = p.step;
+  view->inc_slot = p.inc_slot;
+  view->n_slots = eb::plan_slots(sizes);
+  view->words = eb::plan_wide(sizes) ? 2 : 1;
+  return EB_OK;
 }
 
 int eb_check_errors(void *ws, hipStream_t stream) {
@@ -332,7 +354,7 @@ const char *eb_status_string(int status) {
     case EB_EWORKSPACE: return "workspace too small";
     case EB_EOVERFLOW: return "sizes overflow int32 indexing";
     case EB_EHIP: return "HIP runtime error";
-    case EB_ECAPACITY: return "node exceeds the per-node neighbour capacity";
+    case EB_ECAPACITY: return "node beyond the kernel plan's per-node limits";
     case EB_ETIMEOUT: return "a persistent kernel's bounded wait ran out";
     default: return "unknown status";
   }

@@ -27,10 +27,10 @@ static_assert(sizeof(StatusBlock) == 256, "status block is 256 bytes");
 
 enum TotalSlot {
   T_EDGES = 0, T_BFACES = 1, T_BNODES = 2, T_SELL_ROWS = 3, T_MAXDELTA = 4, T_MAXOUT = 5,
-  T_QUEUE = 6
+  T_QUEUE = 6, T_MAXROW = 7
 };
 
-constexpr int SELL = EB_SELL_SLICE;  // nodes per sliced-ELL slice (one wave)
+constexpr int SELL = 64;  // nodes per slice of the kernel plan (one wave)
 __host__ __device__ inline int64_t n_slices(int64_t n_nodes) { return (n_nodes + SELL - 1) / SELL; }
 
 __device__ inline void raise_status(StatusBlock *st, int code, int64_t detail) {
@@ -92,16 +92,16 @@ inline WsLayout ws_layout(int dim, int64_t n_nodes, int64_t n_elems) {
 }
 
 // The gather adjoint's per-incidence gradient pieces follow the layout above:
-// D rows of n_sell doubles (one per sliced slot).
+// D rows of n_slots doubles (one per slot of the kernel plan).
 // The build's incidence rows are dead once the emit pass is done, so the
 // pieces take their place.
 inline size_t gpiece_offset(int dim, int64_t n_nodes, int64_t n_elems) {
   return ws_layout(dim, n_nodes, n_elems).rows4;
 }
-inline size_t backward_ws_total(int dim, int64_t n_nodes, int64_t n_elems, int64_t n_sell) {
+inline size_t backward_ws_total(int dim, int64_t n_nodes, int64_t n_elems, int64_t n_slots) {
   const WsLayout L = ws_layout(dim, n_nodes, n_elems);
   return std::max(L.total,
-                  L.rows4 + align256(sizeof(double) * (size_t)dim * (size_t)n_sell));
+                  L.rows4 + align256(sizeof(double) * (size_t)dim * (size_t)n_slots));
 }
 
 template <class T> inline T *ws_at(void *ws, size_t off) {

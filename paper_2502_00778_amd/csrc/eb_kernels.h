@@ -3,7 +3,7 @@
 
 #include <hip/hip_ext.h>
 
-#include "eb_internal.h"
+#include "eb_plan.h"
 
 namespace eb {
 
@@ -15,10 +15,11 @@ struct FwdArgs {
   Coords X;
   const int32_t *elem_edge;
   const int32_t *node_inc_off, *node_inc;
-  const int32_t *node_sell_off;
-  const uint64_t *node_sell;
-  const int32_t *inc_sell;  // incidence -> node_sell entry index
-  const uint32_t *node_step;  // per sliced slot: the step from the previous entry (narrow)
+  // the kernel plan (layout in eb_plan.h)
+  const int32_t *node_sell_off;  // slice offsets
+  const uint64_t *node_sell;     // per-slot entries
+  const int32_t *inc_sell;       // incidence -> slot
+  const uint32_t *node_step;     // per slot: the step from the previous entry (narrow)
   int sell_wide;
   const int32_t *node_edge_off, *edge_tail, *edge_head;
   const int32_t *node_in_off, *node_in_edge;
@@ -32,7 +33,7 @@ struct FwdArgs {
   const double *c;                   // dL/dV
   double *g_x, *g_y, *g_z;           // dL/dx rows
   double *gpiece;  // workspace: per-incidence gradient pieces, D rows of gstride
-  int64_t gstride;  // (the sliced slots: node_sell_off[n_slices])
+  int64_t gstride;  // (the plan's slots: node_sell_off[n_slices])
   double *vterm;   // workspace: per-edge terms of the edge loop
   StatusBlock *st;
   int xcd_remap;
@@ -101,6 +102,9 @@ void launch_principal(K kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream
 // Host-side argument packing and validation shared by the entry points.
 int pack(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem, const double *coords,
          void *ws, size_t ws_bytes, FwdArgs &a);
+// the array pointers alone (no workspace, a.st left null); sizes checked by the caller
+int pack_arrays(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
+                const double *coords, FwdArgs &a);
 int need(bool ok, const char *what);
 void rows(double *p, int dim, int64_t n, double *&x, double *&y, double *&z);
 void crows(const double *p, int dim, int64_t n, const double *&x, const double *&y,

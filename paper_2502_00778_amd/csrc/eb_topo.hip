@@ -21,25 +21,23 @@
 #include <type_traits>
 
 #include "eb_geom.h"
+#include "eb_plan.h"
 
 namespace eb {
 
 namespace {
 
-// Per-node topology work keeps each node's sorted neighbour list and its
-// candidate faces in LDS.  A fast kernel with small per-node capacities
-// handles almost every node; nodes beyond them are queued and handled by a
-// second kernel with large capacities (a few threads per block).
+// Per-node topology work: a fast kernel (a thread per node) keeps each
+// node's sorted neighbour list in registers and its candidate faces in LDS,
+// with small per-node capacities that hold almost every node; the nodes
+// beyond them are queued and handled by a general kernel (a wavefront per
+// node) that has no capacity at all.
 constexpr int TB = 128;                   // fast kernel: threads per block
 constexpr int MAXH = NSET;                //   neighbours per node (registers)
 constexpr int MAXF = 64;                  //   candidate faces per node
 constexpr int MAXR = 32;                  //   incidences per node (emit ranking)
-constexpr int TBS = 32;                   // queued nodes: threads per block
 constexpr int RB = 8;                     // row entries a thread reads at once
-constexpr int MAXH_S = EB_MAX_NEIGHBOURS; //   neighbours per node
-constexpr int MAXF_S = EB_MAX_NODE_FACES; //   candidate faces per node
-static_assert(MAXH_S * MAXH_S <= 0x8000, "face codes fit 15 bits");
-static_assert(MAXH <= MAXH_S && MAXF <= MAXF_S, "queued capacities are the larger");
+static_assert(MAXH * MAXH <= 0x8000, "face codes fit 15 bits");
 
 // ----------------------------------------------------- node incidences
 
@@ -244,6 +242,7 @@ struct TopoArgs {
   int32_t *outdeg, *fmin, *bflag, *bfn, *ein;
   // emit pass
   const int32_t *eoff, *foff;
+  const int32_t *ein_scan;  // inclusive scan of the in-degrees (general kernel)
   int32_t *edge_tail, *edge_head;
   int32_t *bface, *bface_owner;
   int32_t *in_cur, *node_in_edge;
@@ -255,9 +254,8 @@ struct TopoArgs {
   StatusBlock *st;
 };
 
-// A node's distinct neighbours, ascending.  The fast kernel keeps them in
-// registers (a fixed-size sorted array updated with predicated moves, no
-// indexed access); the queued kernel in LDS, one column per thread.
+// A node's distinct neighbours, ascending, kept in registers (a fixed-size
+// sorted array updated with predicated moves, no indexed access).
 template <int NR>
 struct RegSet {
   static constexpr int CAP = NR;
@@ -363,42 +361,6 @@ struct RegSet {
   __device__ __forceinline__ void store(int32_t *p) const {
 #pragma unroll
     for (int s = 0; s < NR; ++s) p[64 * s] = a[s];
-  }
-};
-
-template <int TBK, int NR>
-struct LdsSet {
-  static constexpr int CAP = NR;
-  int32_t (*hs)[TBK];
-  int t, n;
-  __device__ __forceinline__ LdsSet(int32_t (*h)[TBK], int t_) : hs(h), t(t_), n(0) {}
-  __device__ __forceinline__ bool insert(int32_t k) {
-    int pos = 0;
-    while (pos < n && hs[pos][t] < k) ++pos;
-    if (pos < n && hs[pos][t] == k) return true;
-    if (n == NR) return false;
-    for (int s = n; s > pos; --s) hs[s][t] = hs[s - 1][t];
-    hs[pos][t] = k;
-    ++n;
-    return true;
-  }
-  __device__ __forceinline__ int rank(int32_t k) const {
-    int r = 0;
-    while (r < n && hs[r][t] < k) ++r;
-    return r;
-  }
-  __device__ __forceinline__ int size() const { return n; }
-  __device__ __forceinline__ int rank_upto(int32_t k, int) const { return rank(k); }
-  __device__ __forceinline__ void window8(int, int32_t (&h)[8]) const {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) h[i] = INT32_MAX;
-  }
-  __device__ __forceinline__ bool insert_upto(int32_t k, int) { return insert(k); }
-  __device__ __forceinline__ int groups_after(int) const { return 0; }
-  __device__ __forceinline__ int groups_used() const { return 0; }
-  __device__ __forceinline__ int32_t at(int i) const { return hs[i][t]; }
-  template <class F> __device__ __forceinline__ void each(int lo, int hi, F f) const {
-    for (int s = lo; s < hi; ++s) f(s, hs[s][t]);
   }
 };
 
@@ -513,11 +475,56 @@ __global__ __launch_bounds__(RK_TB) void k_row_rank(int64_t nv, const int32_t *_
   }
 }
 
+// Boundary face f: vertices fv (fv[0] = j, its smallest), owned by element
+// `own`, whose vertex off the face is vo.  Writes the face in outward vertex
+// order, its owner, and its id into its vertices' bnode_face rows.
+template <int D>
+__device__ void write_bface(const TopoArgs &a, int32_t f, const int32_t (&fv)[D], int64_t own,
+                            int32_t vo) {
+  int32_t v[D + 1];
+  load_conn<D>(a.elem, own, v);
+  int opp = 0;
+#pragma unroll
+  for (int qq = 0; qq <= D; ++qq) opp = v[qq] == vo ? qq : opp;
+  // outward orientation: the expression, operand order and FP64 rounding
+  // of the definition in eb.h (v0 = smallest id), without contraction
+  {
+#pragma clang fp contract(off)
+    const V3 A = load_pt<D>(a.X, fv[0]), B = load_pt<D>(a.X, fv[1]);
+    const V3 Xo = load_pt<D>(a.X, vo);
+    if constexpr (D == 3) {
+      const V3 C = load_pt<D>(a.X, fv[2]);
+      const V3 u = B - A, w2 = C - A, w = A - Xo;
+      const double cx = u.y * w2.z - u.z * w2.y;
+      const double cy = u.z * w2.x - u.x * w2.z;
+      const double cz = u.x * w2.y - u.y * w2.x;
+      const double sg = cx * w.x + cy * w.y + cz * w.z;
+      const bool keep = sg > 0;
+      a.bface[(int64_t)f * 3 + 0] = fv[0];
+      a.bface[(int64_t)f * 3 + 1] = keep ? fv[1] : fv[2];
+      a.bface[(int64_t)f * 3 + 2] = keep ? fv[2] : fv[1];
+    } else {
+      const V3 d = B - A, w = A - Xo;
+      const double sg = d.y * w.x - d.x * w.y;
+      const bool keep = sg > 0;
+      a.bface[(int64_t)f * 2 + 0] = keep ? fv[0] : fv[1];
+      a.bface[(int64_t)f * 2 + 1] = keep ? fv[1] : fv[0];
+    }
+  }
+  a.bface_owner[f] = (int32_t)(own * (D + 1) + opp);
+#pragma unroll
+  for (int s = 0; s < D; ++s) {
+    const int32_t pos = atomicSub(&a.bf_cur[fv[s]], 1) - 1;
+    a.bnode_face[pos] = f;
+  }
+}
+
 // Per node j: 1. its distinct neighbours and candidate faces; 2. (emit)
 // its sorted node_inc row and sliced entries; 3. face multiplicities;
-// 4. (emit) its boundary faces.  RC is the longest row the fast kernel ranks
-// in LDS (ri); the queued kernel ranks from global memory.
-template <int D, bool EMIT, int TBK, class Set, int MF, int RC, bool SLOW>
+// 4. (emit) its boundary faces.  RC is the longest row the kernel ranks in
+// LDS (pr); a node beyond RC, the set's capacity or MF candidate faces is
+// queued for the general kernel.
+template <int D, bool EMIT, int TBK, class Set, int MF, int RC>
 __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
                                uint16_t (*fc)[TBK], uint8_t (*pr)[TBK]) {
   constexpr int MH = Set::CAP;
@@ -532,11 +539,11 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
   //    The count pass also notes the largest |neighbour - j| (sliced-ELL
   //    format).
   int nfc = 0;
-  bool overflow = !SLOW && len > RC;
+  bool overflow = len > RC;
   int32_t maxdelta = 0;
-  int32_t *const nset = SLOW ? nullptr : a.nset + (int64_t)(j / SELL) * NSET * SELL + (j % SELL);
+  int32_t *const nset = a.nset + (int64_t)(j / SELL) * NSET * SELL + (j % SELL);
   bool have = false;
-  if constexpr (EMIT && !SLOW) {  // the count pass's set, unless it queued the node
+  if constexpr (EMIT) {  // the count pass's set, unless it queued the node
     if (nset[0] == -1) return;
     if constexpr (std::is_same<Set, RegSet<NSET>>::value) {
       hs.load(nset);
@@ -567,16 +574,14 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
     }
   }
   if (overflow || nfc > MF) {
-    if constexpr (SLOW) {
-      raise_status(a.st, EB_ECAPACITY, j);
-    } else if constexpr (!EMIT) {
+    if constexpr (!EMIT) {
       const int32_t qi = atomicAdd(&a.st->totals[T_QUEUE], 1);
       a.queue[qi] = j;
       nset[0] = -1;
     }
     return;
   }
-  if constexpr (!EMIT && !SLOW) {
+  if constexpr (!EMIT) {
     if constexpr (std::is_same<Set, RegSet<NSET>>::value) hs.store(nset);
   }
   const int nh = hs.size();
@@ -614,8 +619,8 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
   // p < q; 2D: p - nlow), and its multiplicity is tracked by three masks
   // (seen once, twice, three times) instead of comparing every pair of
   // candidates; bit order is code order.  Otherwise the candidates' codes go
-  // to LDS (fc) as below.  (The queued kernel always takes the LDS way.)
-  const bool by_mask = !SLOW && __builtin_amdgcn_ballot_w64(nh - nlow > 8) == 0;
+  // to LDS (fc) as below.
+  const bool by_mask = __builtin_amdgcn_ballot_w64(nh - nlow > 8) == 0;
   uint64_t once = 0, twice = 0, thrice = 0;
   // (by mask) the out-neighbours, at most 8, ascending: a slot above nlow is
   // then found with 8 comparisons instead of one per slot group
@@ -631,7 +636,7 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
     return hs.rank_upto(k, ngroups);
   };
   const int64_t sbase = (int64_t)a.node_sell_off[j / SELL] + (j % SELL);
-  if constexpr (EMIT && !SLOW) {
+  if constexpr (EMIT) {
     // the entry at each rank, so the row is visited in ascending order below
     // (the stores of a wave then fall on one column of the slice)
     for (int32_t i = 0; i < len; ++i) pr[a.row_rank[r0 + i]][t] = (uint8_t)i;
@@ -642,14 +647,13 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
 #pragma unroll
    for (int u = 0; u < RB; ++u) {
      ib[u] = min(c0 + u, len - 1);
-     if constexpr (EMIT && !SLOW) ib[u] = pr[ib[u]][t];
+     if constexpr (EMIT) ib[u] = pr[ib[u]][t];
      qb[u] = row[ib[u]];
    }
 #pragma unroll
    for (int u = 0; u < RB; ++u) {
     const int32_t c = c0 + u;
     if (c >= len) break;
-    const int32_t i = ib[u];
     const int4 q = qb[u];
     int32_t o[D];
     inc_others<D>(q, o);
@@ -658,8 +662,7 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
     int s2 = -1;
     if constexpr (D == 3) s2 = o[2] > j ? slot_of_higher(o[2]) : -1;
     if constexpr (EMIT) {
-      // rows beyond the fast capacity are visited unsorted
-      const int32_t rank = SLOW ? (int32_t)a.row_rank[r0 + i] : c;
+      const int32_t rank = c;
       const int B = a.sell_wide ? 10 : 5;
       const int none = (1 << B) - 1;
       const int u0 = s0 < 0 ? none : s0 - nlow, u1 = s1 < 0 ? none : s1 - nlow;
@@ -834,42 +837,7 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
         raise_status(a.st, EB_EINVAL, j);
         return;
       }
-      int32_t v[D + 1];
-      load_conn<D>(a.elem, own, v);
-      int opp = 0;
-#pragma unroll
-      for (int qq = 0; qq <= D; ++qq) opp = v[qq] == vo ? qq : opp;
-      // outward orientation: the expression, operand order and FP64 rounding
-      // of the definition in eb.h (v0 = smallest id), without contraction
-      {
-#pragma clang fp contract(off)
-        const V3 A = load_pt<D>(a.X, fv[0]), B = load_pt<D>(a.X, fv[1]);
-        const V3 Xo = load_pt<D>(a.X, vo);
-        if constexpr (D == 3) {
-          const V3 C = load_pt<D>(a.X, fv[2]);
-          const V3 u = B - A, w2 = C - A, w = A - Xo;
-          const double cx = u.y * w2.z - u.z * w2.y;
-          const double cy = u.z * w2.x - u.x * w2.z;
-          const double cz = u.x * w2.y - u.y * w2.x;
-          const double sg = cx * w.x + cy * w.y + cz * w.z;
-          const bool keep = sg > 0;
-          a.bface[(int64_t)f * 3 + 0] = fv[0];
-          a.bface[(int64_t)f * 3 + 1] = keep ? fv[1] : fv[2];
-          a.bface[(int64_t)f * 3 + 2] = keep ? fv[2] : fv[1];
-        } else {
-          const V3 d = B - A, w = A - Xo;
-          const double sg = d.y * w.x - d.x * w.y;
-          const bool keep = sg > 0;
-          a.bface[(int64_t)f * 2 + 0] = keep ? fv[0] : fv[1];
-          a.bface[(int64_t)f * 2 + 1] = keep ? fv[1] : fv[0];
-        }
-      }
-      a.bface_owner[f] = (int32_t)(own * (D + 1) + opp);
-#pragma unroll
-      for (int s = 0; s < D; ++s) {
-        const int32_t pos = atomicSub(&a.bf_cur[fv[s]], 1) - 1;
-        a.bnode_face[pos] = f;
-      }
+      write_bface<D>(a, f, fv, own, vo);
       ++f;
     }
   }
@@ -895,33 +863,267 @@ __global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
     return;
   }
   RegSet<MAXH> hs;
-  node_topo_body<D, EMIT, TB, RegSet<MAXH>, MAXF, MAXR, false>(a, (int32_t)j64, t, hs, fc, pr);
+  node_topo_body<D, EMIT, TB, RegSet<MAXH>, MAXF, MAXR>(a, (int32_t)j64, t, hs, fc, pr);
 }
 
-// the queued nodes, with the large capacities
-template <int D, bool EMIT>
-__global__ __launch_bounds__(TBS) void k_node_topo_queued(TopoArgs a) {
-  __shared__ int32_t hs[MAXH_S][TBS];
-  __shared__ uint16_t fc[MAXF_S][TBS];
-  if (build_failed(a.st)) return;
-  const int32_t n = *reinterpret_cast<const volatile int32_t *>(&a.st->totals[T_QUEUE]);
-  for (int64_t i = (int64_t)blockIdx.x * TBS + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * TBS) {
-    LdsSet<TBS, MAXH_S> set(hs, threadIdx.x);
-    node_topo_body<D, EMIT, TBS, LdsSet<TBS, MAXH_S>, MAXF_S, 0, true>(a, a.queue[i],
-                                                                         threadIdx.x, set, fc,
-                                                                         nullptr);
+// ------------------------------------------- general per-node kernel
+//
+// The queued nodes, any number of neighbours and faces: a wavefront per node
+// walks the node's row as often as needed and keeps nothing per node but a
+// few wave-uniform values.  Distinct neighbours come out in ascending order
+// as successive minima over the row (each a wave reduction over the row's
+// other vertices above the previous one); candidate faces with the node as
+// smallest vertex likewise as successive minima of their keys (the pair of
+// other vertices, both above the node), each counted over the row as it
+// comes up (1 = boundary face, 2 = interior, more = error).  The cost is
+// (neighbours + faces) times the row length over 64 per node, which only
+// matters for nodes of very high degree.
+
+__device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int32_t wave_sum_i32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint32_t lo = __shfl_xor((uint32_t)v, o, 64);
+    const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), o, 64);
+    const uint64_t w = (uint64_t)hi << 32 | lo;
+    v = w < v ? w : v;
+  }
+  return v;
+}
+
+// candidate face keys of one incidence of j: its pairs of other vertices
+// both above j (3D, key hi << 32 | lo of the ascending pair), or its other
+// vertices above j (2D, key = the vertex); 0 marks no candidate (a real key
+// is at least 1, since its vertices exceed j >= 0)
+template <int D>
+__device__ __forceinline__ void face_keys(const int32_t (&o)[D], int32_t j,
+                                          uint64_t (&k)[D == 3 ? 3 : 2]) {
+  if constexpr (D == 3) {
+    const int P[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int32_t x = o[P[c][0]], y = o[P[c][1]];
+      const int32_t lo = x < y ? x : y, hi = x < y ? y : x;
+      k[c] = (x > j && y > j) ? ((uint64_t)(uint32_t)lo << 32 | (uint32_t)hi) : 0;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) k[c] = o[c] > j ? (uint64_t)(uint32_t)o[c] : 0;
   }
 }
 
-// longest node_inc row of every 64-node slice
-__global__ void k_slice_len(const int32_t *__restrict__ node_inc_off, int64_t nv, int32_t *slen) {
+// position of k among the ascending heads[0, n) (k is present)
+__device__ __forceinline__ int32_t lower_bound_i32(const int32_t *heads, int32_t n, int32_t k) {
+  int32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (heads[mid] < k) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int D, bool EMIT>
+__device__ void node_topo_general(const TopoArgs &a, int32_t j, int lane) {
+  constexpr int NK = D == 3 ? 3 : 2;
+  const int32_t r0 = a.node_inc_off[j], r1 = a.node_inc_off[j + 1];
+  const int4 *__restrict__ row = reinterpret_cast<const int4 *>(a.rows4) + r0;
+  const int32_t len = r1 - r0;
+
+  // 1. distinct neighbours, ascending; the emit pass writes the out-edges
+  //    (tail j) and the in-neighbours (ids filled in later by k_node_in_ids)
+  int32_t e0 = 0, in_end = 0, nlow_known = 0;
+  if constexpr (EMIT) {
+    e0 = a.eoff[j];
+    in_end = a.in_cur[j];
+    nlow_known = a.ein_scan[j] - (j > 0 ? a.ein_scan[j - 1] : 0);
+  }
+  int32_t last = INT32_MIN, nh = 0, nlow = 0, maxdelta = 0;
+  for (;;) {
+    int32_t mn = INT32_MAX;
+    for (int32_t i = lane; i < len; i += 64) {
+      int32_t o[D];
+      inc_others<D>(row[i], o);
+#pragma unroll
+      for (int m = 0; m < D; ++m) {
+        if (o[m] > last) mn = min(mn, o[m]);
+        if (!EMIT && nh == 0) maxdelta = max(maxdelta, o[m] > j ? o[m] - j : j - o[m]);
+      }
+    }
+    mn = wave_min_i32(mn);
+    if (mn == INT32_MAX) break;
+    if constexpr (EMIT) {
+      if (lane == 0) {
+        if (mn < j) {
+          a.node_in_edge[in_end - nlow_known + nh] = mn;
+        } else {
+          a.edge_tail[e0 + nh - nlow] = j;
+          a.edge_head[e0 + nh - nlow] = mn;
+        }
+      }
+    }
+    if (mn < j) ++nlow;
+    ++nh;
+    last = mn;
+  }
+  const int32_t nout = nh - nlow;
+  if constexpr (!EMIT) {
+    maxdelta = wave_max_i32(maxdelta);
+    if (lane == 0) {
+      a.outdeg[j] = nout;
+      a.ein[j] = nlow;
+      if (maxdelta > 32767) atomicMax(&a.st->totals[T_MAXDELTA], maxdelta);
+      if (nout > 31) atomicMax(&a.st->totals[T_MAXOUT], nout);
+    }
+  } else {
+    if (lane == 0) a.in_cur[j] = in_end - nlow;
+    // the out-edge heads just written are read back below
+    __threadfence();
+    // 2. each incidence's entry at its rank (rows longer than the strip
+    //    length stay in this ascending order), slots by binary search in
+    //    the out-edge heads
+    const int32_t *heads = a.edge_head + e0;
+    const int64_t sbase = (int64_t)a.node_sell_off[j / SELL] + (j % SELL);
+    const int B = a.sell_wide ? 10 : 5;
+    const int none = (1 << B) - 1;
+    for (int32_t i = lane; i < len; i += 64) {
+      int32_t o[D];
+      inc_others<D>(row[i], o);
+      uint64_t code = 0;
+#pragma unroll
+      for (int m = 0; m < D; ++m) {
+        const int u = o[m] > j ? lower_bound_i32(heads, nout, o[m]) : none;
+        code |= (uint64_t)u << (B * m);
+      }
+      const int64_t pos = sbase + (int64_t)SELL * a.row_rank[r0 + i];
+      if (!a.sell_wide) {
+        uint64_t w = code << 48;
+#pragma unroll
+        for (int m = 0; m < D; ++m) w |= (uint64_t)(uint16_t)(int16_t)(o[m] - j) << (16 * m);
+        a.node_sell[pos] = w;
+      } else {
+        a.node_sell[2 * pos] = (uint64_t)(uint32_t)o[0] | ((uint64_t)(uint32_t)o[1] << 32);
+        a.node_sell[2 * pos + 1] = (uint64_t)(uint32_t)(D == 3 ? o[D - 1] : 0) | (code << 32);
+      }
+    }
+    // the slice entries past j's row
+    const int32_t slen = (a.node_sell_off[j / SELL + 1] - a.node_sell_off[j / SELL]) / SELL;
+    for (int32_t rl = len + lane; rl < slen; rl += 64) {
+      const int64_t pos = sbase + (int64_t)SELL * rl;
+      if (!a.sell_wide) {
+        a.node_sell[pos] = 0;
+      } else {
+        a.node_sell[2 * pos] = 0;
+        a.node_sell[2 * pos + 1] = 0;
+      }
+    }
+  }
+
+  // 3. candidate faces in ascending key order, each counted over the row in
+  //    the round after it is found (with its first holder in row order)
+  int32_t nb = 0, f = EMIT ? a.foff[j] : 0;
+  uint64_t cur = 0;
+  for (;;) {
+    uint64_t mn = ~0ull;
+    int32_t cnt = 0, holder = INT32_MAX;
+    for (int32_t i = lane; i < len; i += 64) {
+      int32_t o[D];
+      inc_others<D>(row[i], o);
+      uint64_t k[NK];
+      face_keys<D>(o, j, k);
+#pragma unroll
+      for (int c = 0; c < NK; ++c) {
+        if (k[c] > cur) mn = k[c] < mn ? k[c] : mn;
+        if (cur != 0 && k[c] == cur) {
+          ++cnt;
+          holder = min(holder, i);
+        }
+      }
+    }
+    mn = wave_min_u64(mn);
+    if (cur != 0) {
+      cnt = wave_sum_i32(cnt);
+      holder = wave_min_i32(holder);
+      if (cnt > 2) {
+        if (lane == 0) raise_status(a.st, EB_ENONMANIFOLD, j);
+        return;
+      }
+      if (cnt == 1) {
+        int32_t fv[D];
+        fv[0] = j;
+        if constexpr (D == 3) {
+          fv[1] = (int32_t)(cur >> 32);
+          fv[2] = (int32_t)(uint32_t)cur;
+        } else {
+          fv[1] = (int32_t)cur;
+        }
+        if (lane == 0) {
+          if constexpr (!EMIT) {
+#pragma unroll
+            for (int s = 0; s < D; ++s) {
+              a.bflag[fv[s]] = 1;
+              atomicAdd(&a.bfn[fv[s]], 1);
+            }
+          } else {
+            // the owner's vertex off the face
+            int32_t o[D];
+            const int4 q = row[holder];
+            inc_others<D>(q, o);
+            int32_t vo = -1;
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+              bool in = false;
+#pragma unroll
+              for (int s = 1; s < D; ++s) in = in || o[m] == fv[s];
+              if (!in) vo = o[m];
+            }
+            write_bface<D>(a, f, fv, q.x / (D + 1), vo);
+          }
+        }
+        ++nb;
+        ++f;
+      }
+    }
+    if (mn == ~0ull) break;
+    cur = mn;
+  }
+  if constexpr (!EMIT) {
+    if (lane == 0) a.fmin[j] = nb;
+  }
+}
+
+template <int D, bool EMIT>
+__global__ __launch_bounds__(64) void k_node_topo_general(TopoArgs a) {
+  if (build_failed(a.st)) return;
+  const int32_t n = *reinterpret_cast<const volatile int32_t *>(&a.st->totals[T_QUEUE]);
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x)
+    node_topo_general<D, EMIT>(a, a.queue[i], (int)threadIdx.x);
+}
+
+// longest node_inc row of every 64-node slice, and of the grid
+__global__ void k_slice_len(const int32_t *__restrict__ node_inc_off, int64_t nv, int32_t *slen,
+                            StatusBlock *st) {
   const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (sl >= n_slices(nv)) return;
   int32_t m = 0;
   const int64_t j1 = min((sl + 1) * SELL, nv);
   for (int64_t j = sl * SELL; j < j1; ++j) m = max(m, node_inc_off[j + 1] - node_inc_off[j]);
   slen[sl] = m;
+  if (m > MAX_NODE_ELEMS) atomicMax(&st->totals[T_MAXROW], m);
 }
 
 __global__ void k_emit_slices(const int32_t *__restrict__ slen_scan, int64_t nsl,
@@ -1452,7 +1654,7 @@ int build_edges_impl(int64_t nv, int64_t nelem, const int32_t *elem, const doubl
   ta.st = st;
   hipLaunchKernelGGL((k_node_topo<D, false>), dim3(grid_for(nv, TB)), dim3(TB), 0, s, ta);
   EB_LAUNCH_CHECK();
-  hipLaunchKernelGGL((k_node_topo_queued<D, false>), dim3(256), dim3(TBS), 0, s, ta);
+  hipLaunchKernelGGL((k_node_topo_general<D, false>), dim3(1024), dim3(64), 0, s, ta);
   EB_LAUNCH_CHECK();
   // the per-node counts become offsets, all five in one scan pass
   ScanJobs J{};
@@ -1471,7 +1673,7 @@ int build_edges_impl(int64_t nv, int64_t nelem, const int32_t *elem, const doubl
   const int64_t nsl = n_slices(nv);
   int32_t *slen = ws_at<int32_t>(ws, L.slen);
   hipLaunchKernelGGL(k_slice_len, dim3(grid_for(nsl, 256)), dim3(256), 0, s,
-                     (const int32_t *)node_inc_off, nv, slen);
+                     (const int32_t *)node_inc_off, nv, slen, st);
   EB_LAUNCH_CHECK();
   EB_TRY(scan_exclusive(slen, slen, nsl + 1, &st->totals[T_SELL_ROWS], tmp, s));
 
@@ -1484,13 +1686,28 @@ int build_edges_impl(int64_t nv, int64_t nelem, const int32_t *elem, const doubl
   sizes->n_edges = h.totals[T_EDGES];
   sizes->n_bfaces = h.totals[T_BFACES];
   sizes->n_bnodes = h.totals[T_BNODES];
-  sizes->n_sell = (int64_t)SELL * h.totals[T_SELL_ROWS];
-  sizes->sell_wide = (h.totals[T_MAXDELTA] > 32767 || h.totals[T_MAXOUT] > 31) ? 1 : 0;
-  if (h.status != EB_OK)
+  // (the slice lengths sum to at most the (D+1) n_elems < 2^31 incidences,
+  // so their scan does not wrap; the slot count is 64 times that)
+  const int64_t n_slots = (int64_t)SELL * h.totals[T_SELL_ROWS];
+  sizes->plan_param[0] = n_slots;
+  sizes->plan_param[1] = (h.totals[T_MAXDELTA] > 32767 || h.totals[T_MAXOUT] > 31) ? 1 : 0;
+  sizes->plan_bytes = (int64_t)plan_bytes_of(sizes);
+  if (h.status != EB_OK) {
     set_detail("%s at %s %lld", eb_status_string(h.status),
                h.status == EB_ERANGE || h.status == EB_EDEGENERATE ? "element" : "node",
                (long long)h.detail);
-  return h.status;
+    return h.status;
+  }
+  if (h.totals[T_MAXROW] > MAX_NODE_ELEMS || h.totals[T_MAXOUT] > MAX_OUT_EDGES) {
+    set_detail("a node has %d elements (at most %d) or %d out-edges (at most %d)",
+               h.totals[T_MAXROW], MAX_NODE_ELEMS, h.totals[T_MAXOUT], MAX_OUT_EDGES);
+    return EB_ECAPACITY;
+  }
+  if (n_slots >= (int64_t(1) << 31)) {
+    set_detail("the kernel plan would have %lld slots (int32 indexing)", (long long)n_slots);
+    return EB_EOVERFLOW;
+  }
+  return EB_OK;
 }
 
 template <int D>
@@ -1510,9 +1727,10 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
   hipLaunchKernelGGL(k_emit_nodes, dim3(grid_for(nv + 1, 256)), dim3(256), 0, s, en);
   EB_LAUNCH_CHECK();
 
+  const PlanPtrs pl = plan_ptrs(sz, tp->plan);
   const int64_t nsl = n_slices(nv);
   hipLaunchKernelGGL(k_emit_slices, dim3(grid_for(nsl + 1, 256)), dim3(256), 0, s,
-                     (const int32_t *)ws_at<int32_t>(ws, L.slen), nsl, tp->node_sell_off,
+                     (const int32_t *)ws_at<int32_t>(ws, L.slen), nsl, pl.slice_off,
                      (const StatusBlock *)st);
   EB_LAUNCH_CHECK();
 
@@ -1527,6 +1745,7 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
   ta.row_rank = ws_at<const uint16_t>(ws, L.row_rank);
   ta.eoff = eoff;
   ta.foff = foff;
+  ta.ein_scan = ein;
   ta.edge_tail = tp->edge;
   ta.edge_head = tp->edge + sz->n_edges;
   ta.bface = tp->bface;
@@ -1535,14 +1754,14 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
   ta.node_in_edge = tp->node_in_edge;
   ta.bf_cur = bfn_scan;
   ta.bnode_face = tp->bnode_face;
-  ta.node_sell_off = tp->node_sell_off;
-  ta.node_sell = tp->node_sell;
-  ta.sell_wide = sz->sell_wide;
+  ta.node_sell_off = pl.slice_off;
+  ta.node_sell = pl.entry;
+  ta.sell_wide = plan_wide(sz);
   ta.queue = ws_at<int32_t>(ws, L.queue);
   ta.st = st;
   hipLaunchKernelGGL((k_node_topo<D, true>), dim3(grid_for(nv, TB)), dim3(TB), 0, s, ta);
   EB_LAUNCH_CHECK();
-  hipLaunchKernelGGL((k_node_topo_queued<D, true>), dim3(256), dim3(TBS), 0, s, ta);
+  hipLaunchKernelGGL((k_node_topo_general<D, true>), dim3(1024), dim3(64), 0, s, ta);
   EB_LAUNCH_CHECK();
   if (sz->n_edges > 0) {
     hipLaunchKernelGGL(k_node_in_ids, dim3(grid_for(nv, 256)), dim3(256), 0, s, nv,
@@ -1552,38 +1771,38 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
   }
   EB_TRY(rowsort(tp->bnode_face_off, tp->bnode_face, sz->n_bnodes, s));
   if (nelem > 0) {
-    if (sz->sell_wide)
+    if (plan_wide(sz))
       hipLaunchKernelGGL((k_elem_maps<D, true>), dim3(grid_for(nelem, 256)), dim3(256), 0, s,
                          elem, nelem, (const int32_t *)ws_at<int32_t>(ws, L.inc_pos),
                          (const uint16_t *)ws_at<uint16_t>(ws, L.row_rank),
-                         (const int32_t *)tp->node_sell_off,
-                         (const uint64_t *)tp->node_sell, (const int32_t *)tp->node_edge_off,
-                         tp->elem_edge, tp->elem_edge_sign, tp->inc_sell, (const StatusBlock *)st);
+                         (const int32_t *)pl.slice_off,
+                         (const uint64_t *)pl.entry, (const int32_t *)tp->node_edge_off,
+                         tp->elem_edge, tp->elem_edge_sign, pl.inc_slot, (const StatusBlock *)st);
     else
       hipLaunchKernelGGL((k_elem_maps<D, false>), dim3(grid_for(nelem, 256)), dim3(256), 0, s,
                          elem, nelem, (const int32_t *)ws_at<int32_t>(ws, L.inc_pos),
                          (const uint16_t *)ws_at<uint16_t>(ws, L.row_rank),
-                         (const int32_t *)tp->node_sell_off,
-                         (const uint64_t *)tp->node_sell, (const int32_t *)tp->node_edge_off,
-                         tp->elem_edge, tp->elem_edge_sign, tp->inc_sell, (const StatusBlock *)st);
+                         (const int32_t *)pl.slice_off,
+                         (const uint64_t *)pl.entry, (const int32_t *)tp->node_edge_off,
+                         tp->elem_edge, tp->elem_edge_sign, pl.inc_slot, (const StatusBlock *)st);
     EB_LAUNCH_CHECK();
   }
 
   if (nelem > 0) {  // rows in strip order (after the element maps read them ascending)
-    if (sz->sell_wide)
+    if (plan_wide(sz))
       for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(pass == 0 ? (k_strip<D, true, SP_SHORT>) : (k_strip<D, true, STRIP>),
                            dim3(grid_for(nv, SP_TB)), dim3(SP_TB), 0, s, nv,
-                           (const int32_t *)tp->node_inc_off, (const int32_t *)tp->node_sell_off,
-                           (uint64_t *)tp->node_sell, nullptr, (const StatusBlock *)st);
+                           (const int32_t *)tp->node_inc_off, (const int32_t *)pl.slice_off,
+                           pl.entry, nullptr, (const StatusBlock *)st);
         EB_LAUNCH_CHECK();
       }
     else
       for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(pass == 0 ? (k_strip<D, false, SP_SHORT>) : (k_strip<D, false, STRIP>),
                            dim3(grid_for(nv, SP_TB)), dim3(SP_TB), 0, s, nv,
-                           (const int32_t *)tp->node_inc_off, (const int32_t *)tp->node_sell_off,
-                           (uint64_t *)tp->node_sell, tp->node_step, (const StatusBlock *)st);
+                           (const int32_t *)tp->node_inc_off, (const int32_t *)pl.slice_off,
+                           pl.entry, pl.step, (const StatusBlock *)st);
         EB_LAUNCH_CHECK();
       }
   }
@@ -1669,15 +1888,14 @@ int eb_build_edges_emit(const eb_sizes *sizes, const int32_t *elem, const double
   const bool has_f = sizes->n_bfaces > 0, has_bn = sizes->n_bnodes > 0;
   if (!t.node_edge_off || !t.node_inc_off || !t.node_in_off || !t.node_bnode ||
       !t.bnode_face_off || (has_e && (!t.edge || !t.node_in_edge)) ||
-      (has_el && (!t.elem_edge || !t.elem_edge_sign || !t.node_inc || !t.node_sell)) ||
-      !t.node_sell_off ||
+      (has_el && (!t.elem_edge || !t.elem_edge_sign || !t.node_inc)) || !t.plan ||
       (has_f && (!t.bface || !t.bface_owner || !t.bface_edge)) ||
       (has_bn && (!t.bnode || !t.bnode_face))) {
     set_detail("a required topology array is null");
     return EB_EINVAL;
   }
-  if (!aligned16(t.inc_sell)) {
-    set_detail("inc_sell must be 16-byte aligned");
+  if ((reinterpret_cast<uintptr_t>(t.plan) & 255u) != 0) {
+    set_detail("the plan must be 256-byte aligned");
     return EB_EINVAL;
   }
   if ((t.edge_inc_off == nullptr) != (t.edge_inc == nullptr)) {

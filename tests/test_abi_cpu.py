@@ -52,23 +52,63 @@ def test_workspace_bytes(L):
     assert big < 161 ** 3 * (64 + 97) + 22 * 4 * 6 * 160 ** 3
 
 
+def _up(x):
+    return -(-x // 256) * 256
+
+
+def sizes(dim, nv, ne, n_edges, n_bfaces, n_bnodes, n_slots=0, wide=0):
+    """eb_sizes as eb_build_edges fills them: the plan's slot count and entry
+    format, and its byte size (four sections on 256-byte lines: slice
+    offsets, entries, step words in the narrow format, incidence slots)."""
+    from paper_2502_00778_amd._lib import EbSizes
+    nb = (_up(4 * ((nv + 63) // 64 + 1)) + _up(8 * n_slots * (1 + wide))
+          + (0 if wide else _up(4 * n_slots)) + _up(4 * (dim + 1) * ne))
+    sz = EbSizes(dim=dim, n_nodes=nv, n_elems=ne, n_edges=n_edges, n_bfaces=n_bfaces,
+                 n_bnodes=n_bnodes, plan_bytes=nb)
+    sz.plan_param[0], sz.plan_param[1] = n_slots, wide
+    return sz
+
+
 def test_backward_workspace_bytes(L):
     from paper_2502_00778_amd._lib import EbSizes
     for dim, per in ((3, 24), (2, 16)):
-        sz = EbSizes(dim=dim, n_nodes=1000, n_elems=5000, n_edges=6000, n_bfaces=10,
-                     n_bnodes=10, n_sell=64 * 400, sell_wide=0)
+        sz = sizes(dim, 1000, 5000, 6000, 10, 10, n_slots=64 * 400)
         base = L.eb_workspace_bytes(dim, 1000, 5000)
         got = L.eb_backward_workspace_bytes(ctypes.byref(sz))
         # the build keeps 22 bytes per incidence (row entry, position, rank) at
         # the end of its layout; the adjoint's gradient pieces (D doubles per
         # sliced entry) take that place
-        up = lambda x: -(-x // 256) * 256
+        up = _up
         ninc = (dim + 1) * 5000
         rows = up(16 * ninc) + up(4 * ninc) + up(2 * ninc)
         pieces = -(-per * 64 * 400 // 256) * 256
         assert got == max(base, base - rows + pieces)
     bad = EbSizes(dim=4, n_nodes=10, n_elems=10)
     assert L.eb_backward_workspace_bytes(ctypes.byref(bad)) == 0
+    # plan fields that no build produces are rejected
+    bad = sizes(3, 1000, 5000, 6000, 10, 10, n_slots=64 * 400)
+    bad.plan_bytes += 256
+    assert L.eb_backward_workspace_bytes(ctypes.byref(bad)) == 0
+    bad = sizes(3, 1000, 5000, 6000, 10, 10, n_slots=65)
+    assert L.eb_backward_workspace_bytes(ctypes.byref(bad)) == 0
+
+
+def test_plan_describe(L):
+    """eb_plan_describe points into the plan at the section offsets and
+    reads no device memory; it rejects sizes not made by a build."""
+    from paper_2502_00778_amd._lib import EbPlanView
+    for wide in (0, 1):
+        sz = sizes(3, 1000, 5000, 6000, 10, 10, n_slots=64 * 400, wide=wide)
+        v = EbPlanView()
+        base = 1 << 20
+        assert L.eb_plan_describe(ctypes.byref(sz), ctypes.c_void_p(base), ctypes.byref(v)) == 0
+        assert (v.n_slots, v.words) == (64 * 400, 1 + wide)
+        assert v.slice_off == base
+        assert v.entry == base + _up(4 * (16 + 1))
+        assert (v.step is None) == bool(wide)
+        assert v.inc_slot == base + sz.plan_bytes - _up(4 * 4 * 5000)
+    sz.plan_bytes = 7
+    assert L.eb_plan_describe(ctypes.byref(sz), ctypes.c_void_p(1 << 20), ctypes.byref(v)) == -1
 
 
 def test_host_validation(L):
@@ -89,7 +129,7 @@ def test_host_validation(L):
                           ctypes.byref(sz), None)
     assert rc == -5  # workspace too small
     assert b"workspace" in L.eb_last_error_detail()
-    sz = EbSizes(dim=3, n_nodes=8, n_elems=6, n_edges=19, n_bfaces=12, n_bnodes=8)
+    sz = sizes(3, 8, 6, 19, 12, 8)
     tp = EbTopology()
     rc = L.eb_directed_areas(ctypes.byref(sz), ctypes.byref(tp), fake, fake, 7, fake,
                              None, None, fake, 10 ** 6, None)

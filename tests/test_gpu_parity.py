@@ -16,6 +16,7 @@ import torch
 
 import meshgen
 import oracle
+from tests._plan import check_plan
 
 pytestmark = pytest.mark.gpu
 
@@ -47,27 +48,25 @@ def dev(mesh):
 
 
 TOPO_NAMES = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign", "edge_inc_off",
-              "edge_inc", "node_inc_off", "node_inc", "node_sell_off", "node_sell", "inc_sell", "node_step", "node_in_off",
-              "node_in_edge",
+              "edge_inc", "node_inc_off", "node_inc", "node_in_off", "node_in_edge",
               "bface", "bface_owner", "bface_edge", "bnode", "node_bnode",
               "bnode_face_off", "bnode_face")
 
 
-def assert_topo_equal(gt, ot):
-    assert (gt.n_edges, gt.n_bfaces, gt.n_bnodes, gt.n_sell, gt.sell_wide) == (
-        ot.n_edges, ot.n_bfaces, ot.n_bnodes, ot.n_sell, ot.sell_wide)
+def assert_topo_equal(gt, ot, elems):
+    """Every topology array bit-exact against the oracle, and the kernel
+    plan a faithful view of that topology (tests/_plan.py)."""
+    assert (gt.n_edges, gt.n_bfaces, gt.n_bnodes) == (ot.n_edges, ot.n_bfaces, ot.n_bnodes)
     g = gt.to_numpy()
     for name in TOPO_NAMES:
         b = ot[name].reshape(-1)
-        if name == "node_step" and gt.sell_wide:  # narrow format only
-            assert name not in g and b.size == 0
-            continue
         a = g[name].reshape(-1)
         assert a.shape == b.shape, (name, a.shape, b.shape)
         if not np.array_equal(a, b):
             bad = np.nonzero(a != b)[0]
             raise AssertionError(f"{name}: {bad.size} entries differ, first at {bad[:5]}: "
                                  f"gpu {a[bad[:5]]} oracle {b[bad[:5]]}")
+    return check_plan(gt, ot, np.asarray(elems))
 
 
 def bface_normals(ot, coords):
@@ -193,6 +192,13 @@ CASES = {
     # a row of 40 entries (longer than a strip)
     "3d-cone-20": lambda: cone(20, centre=15),
     "2d-fan-28": lambda: fan_mesh(28),
+    # nodes of high degree (the general per-node kernel): 140 and 400
+    # neighbours above the centre (wide entries), a centre with 152
+    # neighbours and 300 tetrahedra numbered in the middle and first
+    "2d-fan-140": lambda: fan_mesh(140),
+    "2d-fan-400": lambda: fan_mesh(400),
+    "3d-cone-150": lambda: cone(150),
+    "3d-cone-150-low": lambda: cone(150, centre=0),
 }
 
 _cache = {}
@@ -215,9 +221,10 @@ def test_topology_bit_exact(name):
     say(f"[topology] {name} nv={mesh.n_nodes} ne={mesh.n_elems}")
     X, E = dev(mesh)
     gt = eb().build_edges(E, X)
-    assert_topo_equal(gt, ot)
-    if name.endswith("relabel"):
-        assert gt.sell_wide == 1
+    info = assert_topo_equal(gt, ot, mesh.elems)
+    say(f"    plan: {info}")
+    if name.endswith("relabel") or name in ("2d-fan-140", "2d-fan-400", "3d-cone-150-low"):
+        assert info["wide"]
 
 
 @pytest.mark.parametrize("reduce", ["gather", "atomic"])
@@ -273,26 +280,6 @@ def test_gather_bitwise_reproducible_across_shapes():
                         assert np.array_equal(a.view(np.uint64), r.view(np.uint64))
     finally:
         eb().set_gather_shape(*keep)
-
-
-@pytest.mark.parametrize("name", ["2d-33", "3d-41"])
-def test_step_words_match_full_entries(name):
-    """The forward walk over node_step and the walk over the full node_sell
-    entries (node_step NULL) keep the same points by place and sum in the
-    same order, so they give the same bits."""
-    mesh, *_ = case(name)
-    X, E = dev(mesh)
-    gt = eb().build_edges(E, X)
-    assert gt.sell_wide == 0 and gt.struct.node_step
-    with_steps = [t.cpu().numpy() for t in eb().directed_areas(X, gt, E, "gather")]
-    keep = gt.struct.node_step
-    try:
-        gt.struct.node_step = None
-        without = [t.cpu().numpy() for t in eb().directed_areas(X, gt, E, "gather")]
-    finally:
-        gt.struct.node_step = keep
-    for a, r in zip(with_steps, without):
-        assert np.array_equal(a.view(np.uint64), r.view(np.uint64))
 
 
 def test_closure_on_gpu_outputs():
@@ -378,18 +365,27 @@ def test_backward_gather_bitwise_reproducible():
     assert torch.equal(g1, g2)
 
 
-def test_backward_fd_81():
-    """81^3 adjoint config: GPU gradient vs patch-local central differences
-    of the oracle's loss on 64 seeded nodes (step 1e-6 h)."""
+@pytest.fixture(scope="module")
+def adjoint81():
     mesh = meshgen.cube_kuhn(81, 0)
     say("[backward-fd] 81^3 oracle topology")
     ot = oracle.topology(3, mesh.coords, mesh.elems)
+    return mesh, ot
+
+
+@pytest.mark.parametrize("reduce", ["atomic", "gather"])
+def test_backward_fd_81(adjoint81, reduce):
+    """81^3 adjoint config: GPU gradient vs patch-local central differences
+    of the oracle's loss on 64 seeded nodes (step 1e-6 h), for both
+    reductions (the gather one is what bench.py times and autograd uses)."""
+    mesh, ot = adjoint81
+    say(f"[backward-fd] 81^3 reduce={reduce}")
     w, c, _ = meshgen.loss_weights(0, 3, ot.n_edges, ot.n_nodes)
     nodes = meshgen.fd_nodes(0, ot.n_nodes, 64)
     X, E = dev(mesh)
     gt = eb().build_edges(E, X)
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    g = eb().directed_areas_backward(X, gt, E, T(w), None, T(c), reduce="atomic").cpu().numpy()
+    g = eb().directed_areas_backward(X, gt, E, T(w), None, T(c), reduce=reduce).cpu().numpy()
     _, gref = oracle.node_grad(ot, mesh.coords, mesh.elems, w, c, None, nodes)
     h = 1e-6 / 80
     fd = np.empty((nodes.size, 3))
@@ -431,9 +427,9 @@ def test_errors_reported():
         eb().build_edges(torch.tensor([[0, 1, 2, 3], [0, 1, 2, 4], [0, 2, 1, 5]],
                                       dtype=torch.int32, device="cuda"), X)
     assert e.value.code == -4
-    say("[errors] capacity: a node with 140 higher neighbours")
+    say("[errors] capacity: a node with 1100 out-edges, beyond the plan's slot fields")
     with pytest.raises(EbError) as e:
-        Xf, Ef = fan(140)
+        Xf, Ef = fan(1100)
         eb().build_edges(torch.from_numpy(Ef).cuda(), torch.from_numpy(Xf).cuda())
     assert e.value.code == -8
 
@@ -450,15 +446,14 @@ def fan(k):
 
 def test_high_degree_node_queued():
     """A node beyond the fast kernel's per-node capacities (40 out-edges) is
-    handled by the queued kernel, and its 40 out-edges select the wide
-    sliced-ELL format; results match the oracle."""
+    handled by the general kernel, and its 40 out-edges select the wide plan
+    entries; results match the oracle."""
     Xf, Ef = fan(40)
     mesh = meshgen.Mesh(2, Xf, Ef, "fan40")
     ot = oracle.topology(2, Xf, Ef)
     X, E = dev(mesh)
     gt = eb().build_edges(E, X)
-    assert gt.sell_wide == 1
-    assert_topo_equal(gt, ot)
+    assert assert_topo_equal(gt, ot, Ef)["wide"]
     n0, b0, V0 = oracle.metrics(ot, Xf, Ef)
     S_e, S_b = piece_scales(ot, Xf, Ef)
     for reduce in ("gather", "atomic"):
@@ -487,7 +482,8 @@ def test_full_scale_161(scale161):
     X, E = dev(mesh)
     say("[161^3] GPU build")
     gt = eb().build_edges(E, X)
-    assert_topo_equal(gt, ot)
+    say("[161^3] topology and plan checks")
+    assert_topo_equal(gt, ot, mesh.elems)
     del gt.arrays["edge_inc"]
     say("[161^3] oracle piece scales")
     S_e, S_b = piece_scales(ot, mesh.coords, mesh.elems)

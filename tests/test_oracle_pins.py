@@ -22,7 +22,7 @@ from __future__ import annotations
 import json
 import os
 from fractions import Fraction as Fr
-from itertools import permutations
+from itertools import combinations, permutations
 
 import numpy as np
 import pytest
@@ -231,160 +231,94 @@ def test_efficient_formula_exact(dim, seed):
         np.testing.assert_allclose(nb, ref, atol=1e-15)
 
 
-def _brute_sell(dim, nv, elems, edges):
-    """Sliced-ELL layout written out from its definition (the node_sell and
-    inc_sell entries of eb.h): rows of elements per node stored as strips
-    (rows up to 32) with shared vertices kept in place, other vertices with
-    j's place taken by the last vertex, out-edge ranks, 64-node slices."""
-    nn = dim + 1
-    rows = [[] for _ in range(nv)]
-    for e, el in enumerate(elems):
-        for l, v in enumerate(el):
-            rows[v].append(e * nn + l)
-    outs = [[] for _ in range(nv)]
-    for a, b in edges:
-        outs[a].append(b)
-    nsl = (nv + 63) // 64
-    slen = [max([len(rows[j]) for j in range(64 * s, min(64 * s + 64, nv))] + [0])
-            for s in range(nsl)]
-    off = [0]
-    for s in range(nsl):
-        off.append(off[-1] + 64 * slen[s])
-    maxdelta = max([abs(int(v) - j) for j in range(nv) for inc in rows[j]
-                    for v in elems[inc // nn]] + [0])
-    wide = maxdelta > 32767 or max(len(o) for o in outs) > 31
-    B = 10 if wide else 5
-    none = (1 << B) - 1
-    entries, inc_sell = {}, {}
-
-    def local(inc):
-        e, l = divmod(inc, nn)
-        return [int(elems[e][dim if m == l else m]) for m in range(dim)]
-
-    for j in range(nv):
-        row = sorted(rows[j])
-        if len(row) <= 32:  # a strip: a face of the link shared with the last if any
-            order = row[:1]
-            rest = row[1:]
-            while rest:
-                last = set(local(order[-1]))
-                shared = [len(set(local(i)) & last) for i in rest]
-                face = [i for i, n in zip(rest, shared) if n >= dim - 1]
-                best = face[0] if face else rest[shared.index(max(shared))]
-                order.append(best)
-                rest.remove(best)
+def _brute_csrs(dim, nv, elems, X):
+    """Every topology array written out from its definition with plain loops
+    on a tiny grid: the edge array and element->edge map (Section 2), the
+    incidence lists, the in-edge lists, and the boundary elements
+    (Section 3.2: faces met by one element) with their outward vertex order,
+    owners, edge ids and boundary-node lists."""
+    nn, pairs = dim + 1, list(combinations(range(dim + 1), 2))
+    edges = sorted({tuple(sorted((el[p], el[q]))) for el in elems for p, q in pairs})
+    eid = {e: i for i, e in enumerate(edges)}
+    out = {}
+    out["edge"] = [[a for a, _ in edges], [b for _, b in edges]]
+    out["node_edge_off"] = [sum(1 for a, _ in edges if a < j) for j in range(nv + 1)]
+    out["elem_edge"] = [[eid[tuple(sorted((el[p], el[q])))] for p, q in pairs] for el in elems]
+    out["elem_edge_sign"] = [[1 if el[p] < el[q] else -1 for p, q in pairs] for el in elems]
+    inc = [[i * len(pairs) + le for i, el in enumerate(elems) for le, (p, q) in enumerate(pairs)
+            if tuple(sorted((el[p], el[q]))) == e] for e in edges]
+    node_inc = [[i * nn + l for i, el in enumerate(elems) for l in range(nn) if el[l] == j]
+                for j in range(nv)]
+    node_in = [[i for i, (_, b) in enumerate(edges) if b == j] for j in range(nv)]
+    for name, rows in (("edge_inc", inc), ("node_inc", node_inc), ("node_in", node_in)):
+        off = [0]
+        for r in rows:
+            off.append(off[-1] + len(r))
+        out[name + "_off"] = off
+        out[name if name != "node_in" else "node_in_edge"] = [x for r in rows for x in r]
+    faces = {}
+    for i, el in enumerate(elems):
+        for f in range(nn):
+            faces.setdefault(tuple(sorted(el[m] for m in range(nn) if m != f)), []).append((i, f))
+    bkeys = sorted(k for k, v in faces.items() if len(v) == 1)
+    bface, owner = [], []
+    for k in bkeys:
+        (i, f), = faces[k]
+        P = X[:, list(k)].T
+        xo = X[:, elems[i][f]]
+        if dim == 2:
+            d = P[1] - P[0]
+            out_ok = d[1] * (P[0][0] - xo[0]) - d[0] * (P[0][1] - xo[1]) > 0
+            v = list(k) if out_ok else [k[1], k[0]]
         else:
-            order = row
-        prev = None
-        for c, inc in enumerate(order):
-            o = local(inc)
-            if prev is not None and len(row) <= 32:
-                # keep a vertex in the place the previous entry had it
-                placed = [None] * dim
-                left = list(o)
-                for k in range(dim):
-                    if prev[k] in left:
-                        placed[k] = prev[k]
-                        left.remove(prev[k])
-                free = [k for k in range(dim) if placed[k] is None]
-                for k, v in zip(free, left):
-                    placed[k] = v
-                o = placed
-            prev = o
-            code = 0
-            for m, om in enumerate(o):
-                code |= (outs[j].index(om) if om > j else none) << (B * m)
-            pos = off[j // 64] + 64 * c + j % 64
-            entries[pos] = (o, code)
-            inc_sell[inc] = off[j // 64] + 64 * row.index(inc) + j % 64
-    return wide, off, entries, inc_sell
+            c = np.cross(P[1] - P[0], P[2] - P[0])
+            v = list(k) if c @ (P[0] - xo) > 0 else [k[0], k[2], k[1]]
+        bface.append(v)
+        owner.append(i * nn + f)
+    out["bface"], out["bface_owner"] = bface, owner
+    fp = [(0, 1)] if dim == 2 else [(0, 1), (0, 2), (1, 2)]
+    out["bface_edge"] = [[eid[tuple(sorted((f[p], f[q])))] for p, q in fp] for f in bface]
+    bnode = sorted({v for f in bface for v in f})
+    out["bnode"] = bnode
+    out["node_bnode"] = [bnode.index(j) if j in bnode else -1 for j in range(nv)]
+    bf = [[fi for fi, f in enumerate(bface) if j in f] for j in bnode]
+    out["bnode_face_off"] = [0] + list(np.cumsum([len(r) for r in bf]))
+    out["bnode_face"] = [x for r in bf for x in r]
+    return out
 
 
-@pytest.mark.parametrize("case", ["3d-kuhn", "2d-tri", "2d-fan-wide", "3d-relabel"])
-def test_sliced_layout_brute(case):
-    """node_sell_off / node_sell / inc_sell against a plain re-statement of
-    the layout; narrow and wide formats, padding zero."""
-    rng = np.random.default_rng(7)
-    if case == "3d-kuhn":
-        m = meshgen.cube_kuhn(5, 1)
-        dim, X, E = 3, m.coords, m.elems
-    elif case == "3d-relabel":
-        m = meshgen.cube_kuhn(4, 2)
-        perm = rng.permutation(m.n_nodes)
-        dim, X, E = 3, np.empty_like(m.coords), perm[m.elems].astype(np.int32)
-        X[:, perm] = m.coords
-    elif case == "2d-tri":
-        m = meshgen.square_tri(7, 1)
-        dim, X, E = 2, m.coords, m.elems
-    else:  # 34 triangles around node 0: 34 out-edges select the wide format
-        k = 34
-        ang = np.linspace(0, 2 * np.pi, k, endpoint=False)
-        X = np.zeros((2, k + 1))
-        X[:, 1:] = 1 + np.stack([np.cos(ang), np.sin(ang)])
-        X[:, 0] = 1
-        E = np.array([[0, 1 + i, 1 + (i + 1) % k] for i in range(k)], np.int32)
-        dim = 2
+def _fan(k):
+    ang = np.linspace(0, 2 * np.pi, k, endpoint=False)
+    X = np.zeros((2, k + 1))
+    X[:, 1:] = np.stack([np.cos(ang), np.sin(ang)])
+    return X, np.array([[0, 1 + i, 1 + (i + 1) % k] for i in range(k)], np.int32)
+
+
+@pytest.mark.parametrize("case", ["3d-kuhn-shuf", "2d-tri-shuf", "2d-fan", "3d-relabel"])
+def test_topology_arrays_brute(case):
+    """Every array the oracle's sort-based topology produces, bface_edge and
+    the in-edge lists included, equals the plain-loop statement of its
+    definition on tiny grids (shuffled local orders, relabelled ids, a node
+    of high degree)."""
+    if case == "3d-kuhn-shuf":
+        m = meshgen.cube_kuhn(3, 1)
+        dim, X, E = 3, m.coords, shuffle_local(m.elems, 3)
+    elif case == "2d-tri-shuf":
+        m = meshgen.square_tri(4, 2)
+        dim, X, E = 2, m.coords, shuffle_local(m.elems, 5)
+    elif case == "2d-fan":
+        dim, (X, E) = 2, _fan(9)
+    else:
+        m = meshgen.cube_kuhn(3, 0)
+        lab = np.random.default_rng(4).permutation(m.n_nodes)
+        X = np.empty_like(m.coords)
+        X[:, lab] = m.coords
+        dim, E = 3, lab[m.elems].astype(np.int32)
     t = oracle.topology(dim, X, E)
-    nv = X.shape[1]
-    edges = [tuple(x) for x in t["edge"].T.tolist()]
-    wide, off, entries, inc_sell = _brute_sell(dim, nv, E.tolist(), edges)
-    assert t.sell_wide == int(wide)
-    assert t["node_sell_off"].tolist() == off
-    assert t.n_sell == off[-1]
-    words = t["node_sell"]
-    assert words.size == t.n_sell * (2 if wide else 1)
-    B = 10 if wide else 5
-    for pos in range(t.n_sell):
-        if wide:
-            w0, w1 = int(words[2 * pos]), int(words[2 * pos + 1])
-            o = [w0 & 0xffffffff, w0 >> 32, w1 & 0xffffffff][:dim]
-            code = w1 >> 32
-            got = ([np.int32(np.uint32(x)) for x in o], code)
-            if pos not in entries:
-                assert w0 == 0 and w1 == 0
-                continue
-        else:
-            w = int(words[pos])
-            if pos not in entries:
-                assert w == 0
-                continue
-            j = (pos - off[max(i for i in range(len(off)) if off[i] <= pos and
-                                i < len(off) - 1)]) % 64
-            j += 64 * max(i for i in range(len(off) - 1) if off[i] <= pos)
-            o = [j + int(np.int16(np.uint16((w >> (16 * m)) & 0xffff))) for m in range(dim)]
-            code = (w >> 48) & 0x7fff
-            got = (o, code)
-        ref_o, ref_code = entries[pos]
-        assert [int(x) for x in got[0]] == ref_o, pos
-        assert got[1] == ref_code, pos
-    assert t["inc_sell"].tolist() == [inc_sell[i] for i in range((dim + 1) * E.shape[0])]
-    assert B in (5, 10)
-    # steps between consecutive entries of a row (narrow format only)
-    steps = t["node_step"]
-    if wide:
-        assert steps.size == 0
-        return
-    assert steps.size == t.n_sell
-    want = np.zeros(t.n_sell, np.uint64)
-    for j in range(nv):
-        c = 0
-        prev = None
-        while True:
-            pos = off[j // 64] + 64 * c + j % 64
-            if pos not in entries or pos >= off[j // 64 + 1]:
-                break
-            o, code = entries[pos]
-            flag = 1 << 23
-            if prev is not None:
-                ch = [k for k in range(dim) if o[k] != prev[k]]
-                if len(ch) == 1:
-                    k = ch[0]
-                    slot = (code >> (5 * k)) & 31
-                    flag = ((o[k] - j) & 0xffff) | (k << 16) | (slot << 18)
-            want[pos] = flag
-            prev = o
-            c += 1
-    assert steps.astype(np.uint64).tolist() == want.tolist()
+    want = _brute_csrs(dim, X.shape[1], E.tolist(), X)
+    for name, ref in want.items():
+        got = np.asarray(t[name]).reshape(-1)
+        assert got.tolist() == np.asarray(ref, dtype=np.int64).reshape(-1).tolist(), name
 
 
 def test_local_identity_fe_form():
