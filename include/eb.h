@@ -237,6 +237,24 @@ int eb_dual_volumes(const eb_sizes *sizes, const eb_topology *topo, const int32_
                     const double *coords, int mode, const double *n_edge, int reduce,
                     double *vol, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the edge loop of
+ * eb_dual_volumes (EB_VOL_EDGE, same results, same kernels) without a
+ * workspace.  EB_REDUCE_GATHER keeps its per-edge terms in a fixed device
+ * array of the library, EB_NOALLOC_SCRATCH_BYTES on every GPU the library
+ * runs on, held until the process ends; grids with more than
+ * EB_NOALLOC_SCRATCH_BYTES / 8 edges get EB_EWORKSPACE.  Every term is
+ * written before it is read, so nothing is cleared.  No device memory is
+ * allocated or freed.  All calls on one GPU share its array: calls that
+ * overlap on one GPU (different streams or threads) race.  The first call on
+ * a device looks the array's address up (hipGetSymbolAddress) with that
+ * device current.  No kernel of the edge loop detects errors, so there is
+ * no status word either. */
+#define EB_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int eb_dual_volumes_noalloc(const eb_sizes *sizes, const eb_topology *topo,
+                            const double *coords, const double *n_edge, int reduce,
+                            double *vol, hipStream_t stream);
+
 /* Edge-loop residual, the consumer of the metrics (the edge-based
  * discretization of Section 2): given nodal flux values flux [dim][n_nodes]
  * (F_j), res [n_nodes] (overwritten) = sum over the edges (j,k) of node j of

@@ -27,7 +27,7 @@ EXPORTS = ("eb_workspace_bytes", "eb_backward_workspace_bytes", "eb_build_edges"
            "eb_graph_launch", "eb_graph_destroy", "eb_set_fused_shape", "eb_get_fused_shape",
            "eb_set_fused_wait_limit", "eb_autotune", "eb_edge_residual",
            "eb_directed_areas_variant", "eb_set_fused_mode", "eb_get_fused_mode",
-           "eb_plan_describe")
+           "eb_plan_describe", "eb_dual_volumes_noalloc")
 
 TOPO_FIELDS = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign",
                "edge_inc_off", "edge_inc", "node_inc_off", "node_inc",
@@ -125,6 +125,7 @@ def lib():
     L.eb_edge_residual.argtypes = [SZ, TP, P, P, P, P, P, i32, P, P, sz, P]
     L.eb_directed_areas_variant.argtypes = [SZ, TP, P, P, i32, P, P, P, P, sz, P]
     L.eb_plan_describe.argtypes = [SZ, P, ctypes.POINTER(EbPlanView)]
+    L.eb_dual_volumes_noalloc.argtypes = [SZ, TP, P, P, i32, P, P]
     L.eb_status_string.argtypes = [i32]
     L.eb_status_string.restype = ctypes.c_char_p
     L.eb_last_error_detail.restype = ctypes.c_char_p

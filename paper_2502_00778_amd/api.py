@@ -19,7 +19,8 @@ from ._lib import EbSizes, EbTopology, check, lib
 __all__ = ["Topology", "build_edges", "directed_areas", "dual_volumes",
            "directed_areas_backward", "check_errors", "set_gather_shape",
            "get_gather_shape", "workspace_bytes", "time_next_launch", "edge_residual",
-           "directed_areas_variant", "REDUCE", "VOL_MODE", "BFLUX", "VARIANT"]
+           "directed_areas_variant", "dual_volumes_noalloc", "REDUCE", "VOL_MODE", "BFLUX",
+           "VARIANT"]
 
 REDUCE = {"atomic": _lib.EB_REDUCE_ATOMIC, "gather": _lib.EB_REDUCE_GATHER}
 VOL_MODE = {"element": _lib.EB_VOL_ELEMENT, "edge": _lib.EB_VOL_EDGE}
@@ -210,6 +211,20 @@ def dual_volumes(coords: torch.Tensor, topo: Topology, elems: torch.Tensor,
                                 _ptr(elems), _ptr(coords), VOL_MODE[mode], _ptr(n),
                                 REDUCE[reduce], _ptr(V), _ptr(topo.ws), topo.ws.numel(),
                                 _stream_ptr(stream)), "eb_dual_volumes")
+    return V
+
+
+def dual_volumes_noalloc(coords: torch.Tensor, topo: Topology, n: torch.Tensor,
+                         reduce: str = "gather", out=None, stream=None):
+    """eb_dual_volumes_noalloc: the edge-loop V_j without a workspace (the
+    library's fixed device array holds the per-edge terms)."""
+    D = topo.dim
+    _need(coords, "coords", torch.float64, (D, topo.n_nodes))
+    _need(n, "n", torch.float64, (D, topo.n_edges))
+    V = _out((topo.n_nodes,), coords, out)
+    check(lib().eb_dual_volumes_noalloc(ctypes.byref(topo.sizes), ctypes.byref(topo.struct),
+                                        _ptr(coords), _ptr(n), REDUCE[reduce], _ptr(V),
+                                        _stream_ptr(stream)), "eb_dual_volumes_noalloc")
     return V
 
 

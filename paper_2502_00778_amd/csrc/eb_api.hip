@@ -41,14 +41,14 @@ int pack(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem, const d
          void *ws, size_t ws_bytes, FwdArgs &a) {
   EB_TRY(check_sizes(sz));
   EB_TRY(check_ws(sz->dim, sz->n_nodes, sz->n_elems, ws, ws_bytes));
-  EB_TRY(pack_arrays(sz, tp, elem, coords, a));
+  EB_TRY(pack_arrays(sz, tp, elem, coords, true, a));
   a.st = ws_at<StatusBlock>(ws, 0);
   return EB_OK;
 }
 
 int pack_arrays(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
-                const double *coords, FwdArgs &a) {
-  if (!tp || !coords || (sz->n_elems > 0 && !elem)) {
+                const double *coords, bool need_elem, FwdArgs &a) {
+  if (!tp || !coords || (need_elem && sz->n_elems > 0 && !elem)) {
     set_detail("null pointer");
     return EB_EINVAL;
   }

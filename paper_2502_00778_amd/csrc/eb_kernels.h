@@ -102,9 +102,10 @@ void launch_principal(K kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream
 // Host-side argument packing and validation shared by the entry points.
 int pack(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem, const double *coords,
          void *ws, size_t ws_bytes, FwdArgs &a);
-// the array pointers alone (no workspace, a.st left null); sizes checked by the caller
+// the array pointers alone (no workspace, a.st left null); sizes checked by
+// the caller; elem may be null unless need_elem
 int pack_arrays(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
-                const double *coords, FwdArgs &a);
+                const double *coords, bool need_elem, FwdArgs &a);
 int need(bool ok, const char *what);
 void rows(double *p, int dim, int64_t n, double *&x, double *&y, double *&z);
 void crows(const double *p, int dim, int64_t n, const double *&x, const double *&y,
