@@ -60,6 +60,24 @@ def alg_bytes_edge_volume(dim, nv, ne_):
     return 8 * ne_ + 8 * dim * ne_ + 8 * dim * nv + 8 * nv
 
 
+def alg_bytes_build(dim, nv, nel, ne_, nb, nbn, plan_bytes):
+    """Edge extraction and boundary elements: connectivity and coordinates
+    read once, every topology array and the kernel plan written once (the
+    optional edge->element CSR excluded, as in the timed build)."""
+    ne = 3 if dim == 2 else 6
+    neb = 1 if dim == 2 else 3
+    reads = 4 * (dim + 1) * nel + 8 * dim * nv
+    writes = (8 * ne_ + 4 * (nv + 1)                 # edge, node_edge_off
+              + 4 * ne * nel + ne * nel               # elem_edge, signs
+              + 4 * (dim + 1) * nel + 4 * (nv + 1)    # node_inc (+off)
+              + 4 * ne_ + 4 * (nv + 1)                # node_in (+off)
+              + 4 * dim * nb + 4 * nb + 4 * neb * nb  # bface, owner, bface_edge
+              + 4 * nbn + 4 * nv                      # bnode, node_bnode
+              + 4 * dim * nb + 4 * (nbn + 1)          # bnode_face (+off)
+              + plan_bytes)
+    return reads + writes
+
+
 def source_digest(*names):
     h = hashlib.sha256()
     for n in names:
@@ -99,6 +117,24 @@ class Timer:
         ms = np.array([a.elapsed_time(b) for a, b in ev])
         return float(np.mean(ms)), float(np.median(ms)), float(np.min(ms))
 
+    def time_call(self, eb, fn, reps):
+        """Kernel time of a forward call: the library records the armed
+        events before its first kernel and after its last
+        (eb_time_next_call)."""
+        t = self.torch
+        ev = [(t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            b.record()
+        t.cuda.synchronize()
+        for a, b in ev:
+            eb.time_next_call(a, b)
+            fn()
+        t.cuda.synchronize()
+        ms = np.array([a.elapsed_time(b) for a, b in ev])
+        return float(np.mean(ms)), float(np.median(ms)), float(np.min(ms))
+
     def time_principal(self, eb, fn, reps):
         """Duration of the call's principal kernel alone: the library records
         the armed events around that one launch (eb_time_next_launch)."""
@@ -117,17 +153,42 @@ class Timer:
         return float(np.mean(ms)), float(np.median(ms)), float(np.min(ms))
 
 
-def cpu_baseline(mesh_full, n_layers=24, target_s=15.0):
+def cpu_model():
+    """The host CPU's model name (lscpu), for the record."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    for ln in out.splitlines():
+        if ln.startswith("Model name:"):
+            return ln.split(":", 1)[1].strip()
+    return None
+
+
+def cpu_baseline(mesh_full, n_layers=24, target_s=12.0, single_layers=6):
     """The oracle on a slab of the same grid: the first node layers in z (all
     tets between them), grown from n_layers until one run takes about
-    target_s.  Same rows as a GPU step: topology, n, b, V, and the gradient
-    of the same loss (all nodes)."""
+    target_s, on all host threads; then single-threaded (the paper's serial
+    setting) on a thinner slab.  Same rows as a GPU step: topology, n, b, V,
+    and the gradient of the same loss (all nodes)."""
+    import oracle
     n = mesh_full.meta["n"]
     r = _cpu_slab(mesh_full, n_layers)
     if r["seconds"] < target_s / 1.5 and n_layers < n:
         grow = int(np.ceil(n_layers * target_s / max(r["seconds"], 1e-3)))
         r = _cpu_slab(mesh_full, min(n, max(grow, n_layers + 1)))
     r.pop("seconds")
+    threads = oracle.num_threads()
+    oracle.set_threads(1)
+    try:
+        r1 = _cpu_slab(mesh_full, single_layers)
+    finally:
+        oracle.set_threads(threads)
+    r1.pop("seconds")
+    r["single_thread"] = {k: r1[k] for k in ("value", "unit", "cores", "sample")}
+    r["cpu_model"] = cpu_model()
+    r["os_cpu_count"] = os.cpu_count()
     return r
 
 
@@ -256,7 +317,9 @@ def bench_batched(torch, eb, meshgen, seed, reps, tm):
     return res
 
 
-PAPER_NJK_PROPOSED_TET_S = 13.5  # serial CPU, 257^3 Kuhn-type grid, one n_jk evaluation
+# context only (another machine, serial CPU): the paper's time for one n_jk
+# evaluation on its 257^3 tet grid (Table 3)
+PAPER_NJK_PROPOSED_TET_S = 13.5
 
 
 def bench_deforming(torch, eb, meshgen, seed, steps, tm):
@@ -311,22 +374,67 @@ def bench_deforming(torch, eb, meshgen, seed, steps, tm):
         "Melements_per_s": round(m.n_elems / (t_ms * 1e-3) / 1e6, 1),
         "steps": steps,
         "replay_equals_eager": same,
-        "paper_serial_njk_s_per_step": PAPER_NJK_PROPOSED_TET_S,
-        "ratio_vs_paper_njk_only": round(PAPER_NJK_PROPOSED_TET_S * 1e3 / t_ms, 1),
+        "paper_serial_njk_s_per_step_context": PAPER_NJK_PROPOSED_TET_S,
     }
     log(f"[bench] deforming: {res}")
     return res
 
 
-def calibrate_copy(nbytes=1 << 30, reps=5):
-    """A plain device copy of known size (for scaling the HBM counters)."""
+def bench_2d(torch, eb, meshgen, seed, reps, tm):
+    """The triangle grids: the 33 x 33 config and a 256 x 256 grid of the
+    paper's size (130,050 triangles): build, forward (gather), edge-based V
+    and adjoint (gather), each timed on the stream (these grids are
+    launch-bound, far below the HBM roofline)."""
+    out = {}
+    for name, mesh in (("2d-33", meshgen.square_tri(33, seed)),
+                       ("2d-256", meshgen.square_tri(256, seed))):
+        X = torch.from_numpy(mesh.coords).cuda()
+        E = torch.from_numpy(mesh.elems).cuda()
+        topo = eb.build_edges(E, X, edge_inc=False)
+        w, c, beta = meshgen.loss_weights(seed, 2, topo.n_edges, topo.n_nodes, topo.n_bnodes)
+        W, C, B = (torch.from_numpy(a).cuda() for a in (w, c, beta))
+        n, b, V = eb.directed_areas(X, topo, E, "gather")
+        fns = {
+            "build": lambda: eb.build_edges(E, X, edge_inc=False),
+            "forward_gather": lambda: eb.directed_areas(X, topo, E, "gather", n_out=n, b_out=b,
+                                                        v_out=V),
+            "edge_volume_gather": lambda: eb.dual_volumes(X, topo, E, "edge", n=n,
+                                                          reduce="gather"),
+            "adjoint_gather": lambda: eb.directed_areas_backward(X, topo, E, W, B, C,
+                                                                 reduce="gather"),
+        }
+        r = {"elements": mesh.n_elems, "nodes": mesh.n_nodes, "edges": topo.n_edges}
+        for k, fn in fns.items():
+            fn()
+            ms = tm.time(fn, reps)[0]
+            r[k] = {"ms": round(ms, 4), "Melements_per_s": round(mesh.n_elems / (ms * 1e-3) / 1e6, 1)}
+        eb.check_errors(topo)
+        out[name] = r
+    log(f"[bench] 2d: {out}")
+    return out
+
+
+def calibrate(nbytes=1 << 30, reps=5):
+    """Kernels of known traffic for scaling the HBM counters: a read-only
+    reduction (torch.sum over nbytes of float64: reads nbytes), an
+    elementwise product into another array (reads and writes nbytes), and
+    a fill and a copy (runtime kernels or DMA), reps times each."""
     import torch
-    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     for _ in range(reps):
+        a.fill_(1.0)
+    for _ in range(reps):
         b.copy_(a)
+    s = None
+    for _ in range(reps):
+        s = a.sum()
+    for _ in range(reps):
+        torch.mul(a, 2.0, out=b)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
+    print(json.dumps({"bytes": nbytes, "reps": reps, "sum": float(s),
+                      "fill": "write", "copy": "read+write", "sum_kernel": "read",
+                      "mul_kernel": "read+write"}))
 
 
 def main():
@@ -341,17 +449,19 @@ def main():
     ap.add_argument("--only", default="", help="profiling: run only this phase "
                     "(topo|fwd|fwd_atomic|vol_edge|bwd|bwd_atomic|fused|fwd_edge_normals|"
                     "fwd_dual_faces) --steps times")
-    ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="run only kernels of known traffic (HBM counter scaling)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-deforming", action="store_true")
+    ap.add_argument("--no-2d", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding "
                           "is a design note, not an implementation", "n_gpus": args.gpus}))
         sys.exit(2)
-    if args.calibrate_copy:
-        calibrate_copy()
+    if args.calibrate:
+        calibrate()
         return
 
     import torch
@@ -421,6 +531,12 @@ def main():
             fn()
         torch.cuda.synchronize()
         log(f"[bench] ran {args.only} x{args.steps}")
+        if args.only == "fwd":
+            # the forward call's kernel time by events in this same process
+            # (under a profiler: the profiler's own view beside it)
+            t = Timer(torch).time_call(eb, fn, args.steps)
+            log(f"[bench] forward call kernels by events: mean {t[0]:.4f} ms, "
+                f"median {t[1]:.4f}, min {t[2]:.4f}")
         return
 
     def step():
@@ -455,6 +571,9 @@ def main():
         kern[name] = tm.time_principal(eb, phases[name], args.phase_reps)
         log(f"[bench] principal kernel of {name}: mean {kern[name][0]:.4f} ms, "
             f"median {kern[name][1]:.4f}, min {kern[name][2]:.4f}")
+    fwd_call = tm.time_call(eb, phases["fwd"], args.phase_reps)
+    log(f"[bench] forward call kernels (node + boundary pass): mean {fwd_call[0]:.4f} ms, "
+        f"median {fwd_call[1]:.4f}, min {fwd_call[2]:.4f}")
     eb.check_errors(topo)
     # a plain device copy on the same box, in the same run: the bandwidth an
     # HBM-bound kernel can reach in practice (read + write bytes / time)
@@ -469,16 +588,16 @@ def main():
     bf = alg_bytes_forward(dim, nv, nel, ne_, nb, nbn)
     bb_ = alg_bytes_backward(dim, nv, nel, ne_, nb, nbn)
     bv = alg_bytes_edge_volume(dim, nv, ne_)
-    # roofline of the dominant kernel: the forward node pass alone; its
-    # algorithmic bytes exclude the boundary-element terms, which the small
-    # boundary kernel after it handles
-    neb = 1 if dim == 2 else 3
-    bf_main = bf - 8 * dim * nbn - 4 * (dim + neb) * nb
-    t_fwd = kern["fwd"][0] * 1e-3
-    achieved = bf_main / t_fwd / 1e9
+    bbuild = alg_bytes_build(dim, nv, nel, ne_, nb, nbn, int(topo.sizes.plan_bytes))
+    # roofline of the forward call (eb_directed_areas, gather): its two
+    # kernels, the node pass and the boundary pass, from the start of the
+    # first to the end of the second (eb_time_next_call); algorithmic bytes
+    # B_fwd
+    t_call = fwd_call[0] * 1e-3
+    achieved = bf / t_call / 1e9
     digest = source_digest("eb_forward.hip", "eb_gather.h", "eb_geom.h", "eb_kernels.h",
-                           "eb_internal.h")
-    traffic = read_traffic("fwd_gather_161", digest)
+                           "eb_internal.h", "eb_metrics.hip", "eb_plan.h")
+    traffic = read_traffic("fwd_call_161", digest)
 
     def ph(name, bytes_):
         ms = res[name][0]
@@ -511,20 +630,30 @@ def main():
         },
         "gather_shape": list(eb.get_gather_shape()),
         "roofline": {
-            "kernel": "k_fwd_gather (eb_directed_areas, gather: n and V fused, node pass)",
+            "kernel": ("eb_directed_areas gather forward call: k_fwd_gather (node pass, n and V) "
+                       "+ k_fwd_boundary_gather (boundary pass, n_B terms and b)"),
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "alg_bytes": bf_main,
-            "kernel_ms": round(kern["fwd"][0], 4),
+            "alg_bytes": bf,
+            "kernels_ms": round(fwd_call[0], 4),
+            "node_pass_ms": round(kern["fwd"][0], 4),
+            "call_ms_events_around": round(res["fwd"][0], 4),
+            "measured_GBps": (round(traffic / t_call / 1e9, 1) if traffic else None),
             "copy_GBps": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
         },
         "phases": {
-            "edge_extraction": ph("topo", None),
+            "edge_extraction": dict(
+                ph("topo", None),
+                keys=(3 if dim == 2 else 6) * nel,
+                Mkeys_per_s=round((3 if dim == 2 else 6) * nel / (res["topo"][0] * 1e-3) / 1e6, 1),
+                alg_bytes=bbuild,
+                alg_GBps=round(bbuild / (res["topo"][0] * 1e-3) / 1e9, 1),
+                frac_hbm_peak=round(bbuild / (res["topo"][0] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)),
             "forward_gather": ph("fwd", bf),
             "forward_atomic": ph("fwd_atomic", bf),
             "edge_volume_gather": ph("vol_edge", bv),
@@ -544,6 +673,8 @@ def main():
     }
     if not args.no_batched:
         line["batched"] = bench_batched(torch, eb, meshgen, args.seed, args.phase_reps, tm)
+    if not args.no_2d:
+        line["triangles"] = bench_2d(torch, eb, meshgen, args.seed, args.phase_reps, tm)
     if not args.no_deforming:
         # free the 161^3 working set first
         del topo, X, E, W, C, B, n, b, V, Ve, g, fouts

@@ -1,8 +1,9 @@
 /*
  * eb.h — edge-based grid metrics on one MI355X (gfx950), C ABI.
  *
- * Computes, for a triangle (dim = 2) or tetrahedral (dim = 3) grid, the
- * metrics of the node-centred edge-based discretization (Nishikawa,
+ * Computes, for a triangle (dim = 2), tetrahedral (dim = 3) or pentatope
+ * (dim = 4) grid, the metrics of the node-centred edge-based discretization
+ * (Nishikawa,
  * "An Efficient Implementation of Edge-Based Discretization without Forming
  * Dual Control Volumes", Section 2, eq. threed_fv_semidiscrete_system_00)
  * directly from element geometry, never forming a median dual:
@@ -29,8 +30,13 @@
  *   - coords is structure-of-arrays FP64 [dim][n_nodes]; elem is int32
  *     [n_elems][dim+1] with any local vertex order (either orientation).
  *   - All outputs are overwritten, never accumulated into; inputs are const.
- *   - ne = 3 (dim 2) or 6 (dim 3) local edges per element, in the local pair
- *     order 2D (0,1)(0,2)(1,2); 3D (0,1)(0,2)(0,3)(1,2)(1,3)(2,3).
+ *   - ne = dim(dim+1)/2 local edges per element (3, 6 or 10), in lexicographic
+ *     local pair order: 2D (0,1)(0,2)(1,2); 3D (0,1)(0,2)(0,3)(1,2)(1,3)(2,3);
+ *     4D (0,1)(0,2)(0,3)(0,4)(1,2)(1,3)(1,4)(2,3)(2,4)(3,4).
+ *   - dim 4 (the general-D formula of Section 3.2.3 with D = 4, which the
+ *     paper leaves to future work) is supported by eb_build_edges,
+ *     eb_build_edges_emit, eb_directed_areas and eb_dual_volumes; the other
+ *     calls return EB_EINVAL for it.
  *   - Calls enqueue work on `stream` and return at once, except
  *     eb_build_edges and eb_check_errors, which synchronize `stream`.
  *   - The caller owns every buffer.  The library allocates no device memory
@@ -120,11 +126,15 @@ typedef struct {
  *                                 vertices ordered so that the area vector
  *                                 2D (dy,-dx) of v0->v1, 3D (1/2)(v1-v0)x(v2-v0)
  *                                 points out of the domain; 3D rotated so the
- *                                 smallest id comes first
+ *                                 smallest id comes first; 4D ascending, the
+ *                                 last two swapped when the area vector
+ *                                 (1/6) N(v1-v0, v2-v0, v3-v0) of that order
+ *                                 points into the domain (N(u,v,w).x =
+ *                                 det[x; u; v; w])
  *   bface_owner    [n_bfaces]     elem*(dim+1) + local index of the owner's
  *                                 vertex opposite the face
- *   bface_edge     [n_bfaces][dim*(dim-1)/2]  edge ids of (v0,v1) | (v0,v1),
- *                                 (v0,v2), (v1,v2)
+ *   bface_edge     [n_bfaces][dim*(dim-1)/2]  edge ids of the face's vertex
+ *                                 pairs (vp,vq), p < q, in lexicographic order
  *   bnode          [n_bnodes]     ascending ids of nodes on boundary faces
  *   node_bnode     [n_nodes]      index into bnode, or -1 for interior nodes
  *   bnode_face_off [n_bnodes+1]   boundary faces of each boundary node,
@@ -138,6 +148,7 @@ typedef struct {
  *                                 EB_REDUCE_GATHER paths.  Opaque: its
  *                                 format is private to the library and may
  *                                 change between versions; 256-byte aligned.
+ *                                 (dim 4 makes no plan: one placeholder line.)
  */
 typedef struct {
   int32_t *edge;
@@ -192,12 +203,15 @@ int eb_build_edges_emit(const eb_sizes *sizes, const int32_t *elem, const double
  * 3.2.3), boundary dual-face normals b_node [dim][n_bnodes] (NULL to skip)
  * and element-based dual volumes vol [n_nodes] (Section 4.2; NULL to skip),
  * in one pass over the grid.
- *   EB_REDUCE_ATOMIC: one thread per element, FP64 atomic adds into zeroed
- *     outputs (summation order varies from run to run).
+ *   EB_REDUCE_ATOMIC: one thread per element; each block sums its elements'
+ *     contributions per edge and per node in LDS, then adds each sum to the
+ *     zeroed outputs with one FP64 atomic (summation order varies from run
+ *     to run).  dim 4: plain per-element atomics.
  *   EB_REDUCE_GATHER: one thread per node gathers over its elements in
  *     node_inc order and owns the edges it is the tail of; every output is
  *     written once, bitwise reproducible.  Needs node_inc, node_edge_off,
- *     edge, node_bnode, bnode_face_off/bnode_face, bface. */
+ *     edge, node_bnode, bnode_face_off/bnode_face, bface.  dim 4: one thread
+ *     per node walks its node_inc row (no plan), then one per boundary node. */
 int eb_directed_areas(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
                       const double *coords, int reduce, double *n_edge, double *b_node,
                       double *vol, void *ws, size_t ws_bytes, hipStream_t stream);
@@ -280,7 +294,8 @@ int eb_edge_residual(const eb_sizes *sizes, const eb_topology *topo, const int32
  * grad_coords = dL/dx [dim][n_nodes] for the metrics eb_directed_areas
  * computes (element-based V).  Derivative of the element and boundary
  * formulas above; the orientation sign of each element is held fixed.
- * ATOMIC: thread per element/boundary face with FP64 atomics.  GATHER: an
+ * ATOMIC: thread per element (each block's per-node sums first gathered in
+ * LDS, one FP64 atomic per node and component) and per boundary face.  GATHER: an
  * element pass writes each element's gradient with respect to each of its
  * vertices into the workspace at that incidence's slot of the plan, then
  * one thread per node sums its slots in node_inc order and adds its boundary
@@ -304,6 +319,18 @@ int eb_directed_areas_backward(const eb_sizes *sizes, const eb_topology *topo,
  * own duration.  The next such call consumes the events whether or not it
  * launches; NULL, NULL disarms.  Returns EB_EINVAL if only one is NULL. */
 int eb_time_next_launch(hipEvent_t start, hipEvent_t stop);
+
+/* Profiling aid.  Arms two events that bracket the kernels of the next
+ * eb_directed_areas call made on this thread: `start` is recorded just
+ * before its first kernel (gather: the node pass; atomic: the element pass)
+ * and `stop` just after its last (the boundary pass), on the call's stream
+ * (hipExtLaunchKernelGGL), so hipEventElapsedTime gives the call's kernel
+ * time, the zero fills of the atomic path excluded.  Consumed like
+ * eb_time_next_launch's events by the next call that takes those (another
+ * call brackets only its principal kernel with them), and taking
+ * precedence over them; NULL, NULL disarms.  Returns EB_EINVAL if only one
+ * is NULL. */
+int eb_time_next_call(hipEvent_t start, hipEvent_t stop);
 
 /* Launch shape of the node-centred (EB_REDUCE_GATHER) kernels: nodes per
  * block (64, 128 or 256; default 64), incidences per chunk (1, 2 or 4,

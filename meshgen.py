@@ -33,7 +33,7 @@ import numpy as np
 __all__ = [
     "Mesh", "BatchedMesh", "streams", "square_tri", "cube_kuhn", "scale_cube",
     "batched_kuhn", "loss_weights", "fd_nodes", "make", "CONFIGS",
-    "kuhn_counts", "tri_counts",
+    "kuhn_counts", "tri_counts", "hypercube_kuhn", "kuhn4_counts",
 ]
 
 _STREAM_NAMES = ("jitter", "diag", "sizes", "permesh", "loss", "fd")
@@ -284,6 +284,61 @@ def batched_kuhn(n_mesh: int = 64, seed: int = 0, lo: int = 9, hi: int = 65,
 
 
 # --------------------------------------------------------------------------
+# four dimensions: the Kuhn split of a 4-cube into 24 pentatopes
+# --------------------------------------------------------------------------
+
+_KUHN4_PERMS = list(permutations(range(4)))  # lexicographic order
+
+
+def kuhn4_counts(n: int) -> dict:
+    """Counts of an n^4 node grid with the 24-pentatope Kuhn split of every
+    cell: edges run from a node to each of the 15 nonempty corner offsets of
+    its cell, (2n-1)^4 - n^4 in all; the boundary is 8 cubic facets of
+    (n-1)^3 cells, 6 tetrahedra each."""
+    c = n - 1
+    return dict(n_nodes=n ** 4, n_elems=24 * c ** 4, n_edges=(2 * n - 1) ** 4 - n ** 4,
+                n_bfaces=48 * c ** 3, n_bnodes=n ** 4 - max(n - 2, 0) ** 4)
+
+
+def _kuhn4_elems(n: int) -> np.ndarray:
+    c = n - 1
+    cell = np.arange(c, dtype=np.int64)
+    c0 = (cell[None, None, None, :] + n * cell[None, None, :, None]
+          + n * n * cell[None, :, None, None] + n ** 3 * cell[:, None, None, None]).reshape(-1)
+    step = np.array([1, n, n * n, n ** 3], dtype=np.int64)
+    offs = np.empty((24, 5), dtype=np.int64)
+    for t, (pa, pb, pc, _) in enumerate(_KUHN4_PERMS):
+        offs[t] = (0, step[pa], step[pa] + step[pb], step[pa] + step[pb] + step[pc], step.sum())
+    if c0.size and c0[-1] + offs.max() >= 2 ** 31:
+        raise OverflowError("node ids exceed int32")
+    out = c0.astype(np.int32)[:, None, None] + offs.astype(np.int32)[None]
+    return out.reshape(-1, 5)
+
+
+def hypercube_kuhn(n: int = 9, seed: int = 0, jitter: float = 0.1) -> Mesh:
+    """Unit 4-cube, ``n^4`` nodes (id = i + n j + n^2 k + n^3 l), each cell
+    split along its main diagonal into the 24 pentatopes (c0, c0+e_a,
+    c0+e_a+e_b, c0+e_a+e_b+e_c, c0+(1,1,1,1)) over the permutations (a,b,c,d)
+    of the axes (odd ones have negative signed measure), interior nodes
+    jittered uniformly +-jitter*h per axis.  With jitter 0.1 a node moves at
+    most 0.2h, and two at most 0.4h closer, below the smallest height h/sqrt 2
+    of the split's pentatopes, so none is inverted."""
+    h = 1.0 / (n - 1)
+    xs = _axis_nodes_uniform(n)
+    L, K, J, I = np.meshgrid(xs, xs, xs, xs, indexing="ij")
+    coords = np.stack([I.reshape(-1), J.reshape(-1), K.reshape(-1), L.reshape(-1)])
+    if jitter:
+        r = _gen(streams(seed)["jitter"]).uniform(-jitter * h, jitter * h, size=(n ** 4, 4))
+        a = np.arange(n)
+        l, k, j, i = np.meshgrid(a, a, a, a, indexing="ij")
+        inner = ((i > 0) & (i < n - 1) & (j > 0) & (j < n - 1) & (k > 0) & (k < n - 1)
+                 & (l > 0) & (l < n - 1)).reshape(-1)
+        coords[:, inner] += r[inner].T
+    return Mesh(4, np.ascontiguousarray(coords), _kuhn4_elems(n), name=f"kuhn4d{n}",
+                meta=dict(n=n, seed=seed, jitter=jitter))
+
+
+# --------------------------------------------------------------------------
 # adjoint inputs
 # --------------------------------------------------------------------------
 
@@ -312,6 +367,7 @@ CONFIGS = {
     "3d-scale": lambda seed=0: scale_cube(161, seed),
     "3d-adjoint": lambda seed=0: cube_kuhn(81, seed),
     "batched": lambda seed=0: batched_kuhn(64, seed),
+    "4d": lambda seed=0: hypercube_kuhn(9, seed),
 }
 
 

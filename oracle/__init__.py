@@ -120,13 +120,13 @@ class Topology:
             a = np.empty(cnt, dtype=dt)
             L.oracle_topo_get(self._h, name.encode(), _ptr(a))
             self.arrays[name] = a
-        ne = 3 if self.dim == 2 else 6
+        ne = self.dim * (self.dim + 1) // 2
         a = self.arrays
         a["edge"] = a["edge"].reshape(2, self.n_edges)
         a["elem_edge"] = a["elem_edge"].reshape(self.n_elems, ne)
         a["elem_edge_sign"] = a["elem_edge_sign"].reshape(self.n_elems, ne)
         a["bface"] = a["bface"].reshape(self.n_bfaces, self.dim)
-        nbe = 1 if self.dim == 2 else 3
+        nbe = self.dim * (self.dim - 1) // 2
         a["bface_edge"] = a["bface_edge"].reshape(self.n_bfaces, nbe)
 
     def __getitem__(self, k):
@@ -167,7 +167,7 @@ def element_pieces(dim, coords, elems, e0=0, e1=None):
     coords = _f64(coords)
     elems = _i32(elems)
     e1 = elems.shape[0] if e1 is None else e1
-    ne = 3 if dim == 2 else 6
+    ne = dim * (dim + 1) // 2
     npc = np.empty((e1 - e0, ne, dim))
     vpc = np.empty((e1 - e0, dim + 1))
     rc = lib().oracle_element_pieces(dim, coords.shape[1], _ptr(coords), e0,

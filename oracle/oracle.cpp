@@ -137,9 +137,13 @@ struct Neumaier {
 
 const int PAIR2[3][2] = {{0, 1}, {0, 2}, {1, 2}};
 const int PAIR3[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+const int PAIR4[10][2] = {{0, 1}, {0, 2}, {0, 3}, {0, 4}, {1, 2},
+                          {1, 3}, {1, 4}, {2, 3}, {2, 4}, {3, 4}};
 
-inline int n_local_edges(int dim) { return dim == 2 ? 3 : 6; }
-inline const int (*local_pairs(int dim))[2] { return dim == 2 ? PAIR2 : PAIR3; }
+inline int n_local_edges(int dim) { return dim == 2 ? 3 : (dim == 3 ? 6 : 10); }
+inline const int (*local_pairs(int dim))[2] {
+  return dim == 2 ? PAIR2 : (dim == 3 ? PAIR3 : PAIR4);
+}
 
 template <class T> inline P3<T> point(const T *const *X, int dim, int64_t v) {
   P3<T> p;
@@ -238,6 +242,129 @@ P3<T> bface_piece(int dim, const P3<T> *V, int s, P3<T> Xo) {
   return t1 + t2;
 }
 
+// ------------------------------------------------ four dimensions (D = 4)
+//
+// The same traditional construction one dimension up (the paper derives the
+// efficient formula for general D, Section 3.2.3, and leaves D = 4 to future
+// work).  The median dual cuts an element along the barycentres of its
+// faces: the part of E where lambda_p = lambda_q >= every other barycentric
+// coordinate is the dual face between p and q, and the part where lambda_i
+// is largest is i's sub-cell.  Both are unions of simplices of the
+// barycentric subdivision, one per chain of faces:
+//   dual face (p,q):  {m_pq, F_pqa, T_pqab, C} over ordered pairs (a,b) of
+//                     the other three vertices (six tetrahedra, all in the
+//                     hyperplane lambda_p = lambda_q);
+//   sub-cell of i:    {x_i, m_ia, F_iab, T_iabc, C} over ordered triples
+//                     (a,b,c) of the other four (24 pentatopes);
+//   boundary piece of vertex s of a boundary tetrahedron B:
+//                     {x_s, m_sa, F_sab, C_B} over ordered pairs (a,b) of
+//                     B's other vertices (six tetrahedra in B's hyperplane);
+// with m, F, T, C the barycentres of edges, triangles, tetrahedra and the
+// element.  The area vector of a tetrahedron {y0,y1,y2,y3} in R^4 is
+// (1/6) N(y1-y0, y2-y0, y3-y0), where N(u,v,w) is the vector with
+// N(u,v,w).x = det[x; u; v; w] for every x (the four-dimensional cross
+// product); it is oriented here by a dot product, like the 2D/3D pieces.
+
+struct Q4 {
+  double c[4];
+};
+inline Q4 q4_add(const Q4 &a, const Q4 &b) {
+  return {{a.c[0] + b.c[0], a.c[1] + b.c[1], a.c[2] + b.c[2], a.c[3] + b.c[3]}};
+}
+inline Q4 q4_sub(const Q4 &a, const Q4 &b) {
+  return {{a.c[0] - b.c[0], a.c[1] - b.c[1], a.c[2] - b.c[2], a.c[3] - b.c[3]}};
+}
+inline Q4 q4_scale(double s, const Q4 &a) {
+  return {{s * a.c[0], s * a.c[1], s * a.c[2], s * a.c[3]}};
+}
+inline double q4_dot(const Q4 &a, const Q4 &b) {
+  return a.c[0] * b.c[0] + a.c[1] * b.c[1] + a.c[2] * b.c[2] + a.c[3] * b.c[3];
+}
+// 3x3 determinant of columns (i, j, k) of the rows u, v, w
+inline double minor3(const Q4 &u, const Q4 &v, const Q4 &w, int i, int j, int k) {
+  return u.c[i] * (v.c[j] * w.c[k] - v.c[k] * w.c[j]) -
+         u.c[j] * (v.c[i] * w.c[k] - v.c[k] * w.c[i]) +
+         u.c[k] * (v.c[i] * w.c[j] - v.c[j] * w.c[i]);
+}
+// N(u,v,w): cofactor expansion of det[x; u; v; w] along its first row
+inline Q4 q4_cross(const Q4 &u, const Q4 &v, const Q4 &w) {
+  return {{minor3(u, v, w, 1, 2, 3), -minor3(u, v, w, 0, 2, 3), minor3(u, v, w, 0, 1, 3),
+           -minor3(u, v, w, 0, 1, 2)}};
+}
+inline double q4_det(const Q4 &a, const Q4 &b, const Q4 &c, const Q4 &d) {
+  return q4_dot(a, q4_cross(b, c, d));
+}
+inline Q4 q4_along(const Q4 &t, const Q4 &dir) {
+  return q4_dot(t, dir) < 0 ? q4_scale(-1.0, t) : t;
+}
+inline Q4 point4(const double *const *X, int64_t v) {
+  return {{X[0][v], X[1][v], X[2][v], X[3][v]}};
+}
+// area vector of the tetrahedron {y0, y1, y2, y3}, up to orientation
+inline Q4 tet_area4(const Q4 &y0, const Q4 &y1, const Q4 &y2, const Q4 &y3) {
+  return q4_scale(1.0 / 6.0, q4_cross(q4_sub(y1, y0), q4_sub(y2, y0), q4_sub(y3, y0)));
+}
+
+void pent_pieces(const Q4 P[5], const int32_t id[5], Q4 npiece[10], double vpiece[5]) {
+  const Q4 C = q4_scale(0.2, q4_add(q4_add(q4_add(P[0], P[1]), q4_add(P[2], P[3])), P[4]));
+  for (int le = 0; le < 10; ++le) {
+    const int p = PAIR4[le][0], q = PAIR4[le][1];
+    int o[3], no = 0;
+    for (int r = 0; r < 5; ++r)
+      if (r != p && r != q) o[no++] = r;
+    const int j = id[p] < id[q] ? p : q, k = j == p ? q : p;
+    const Q4 m = q4_scale(0.5, q4_add(P[p], P[q]));
+    const Q4 dir = q4_sub(P[k], P[j]);
+    Q4 sum = {{0, 0, 0, 0}};
+    for (int ia = 0; ia < 3; ++ia)
+      for (int ib = 0; ib < 3; ++ib) {
+        if (ib == ia) continue;
+        const int a = o[ia], b = o[ib];
+        const Q4 F = q4_scale(1.0 / 3.0, q4_add(q4_add(P[p], P[q]), P[a]));
+        const Q4 T = q4_scale(0.25, q4_add(q4_add(P[p], P[q]), q4_add(P[a], P[b])));
+        sum = q4_add(sum, q4_along(tet_area4(m, F, T, C), dir));
+      }
+    npiece[le] = sum;
+  }
+  for (int i = 0; i < 5; ++i) {
+    double acc = 0.0;
+    for (int a = 0; a < 5; ++a) {
+      if (a == i) continue;
+      const Q4 m = q4_scale(0.5, q4_add(P[i], P[a]));
+      for (int b = 0; b < 5; ++b) {
+        if (b == i || b == a) continue;
+        const Q4 F = q4_scale(1.0 / 3.0, q4_add(q4_add(P[i], P[a]), P[b]));
+        for (int c = 0; c < 5; ++c) {
+          if (c == i || c == a || c == b) continue;
+          const Q4 T = q4_scale(0.25, q4_add(q4_add(P[i], P[a]), q4_add(P[b], P[c])));
+          const double det = q4_det(q4_sub(m, P[i]), q4_sub(F, P[i]), q4_sub(T, P[i]),
+                                    q4_sub(C, P[i]));
+          acc += std::fabs(det) / 24.0;
+        }
+      }
+    }
+    vpiece[i] = acc;
+  }
+}
+
+// Boundary piece of vertex s of the boundary tetrahedron V[0..3] (Xo: the
+// owner's vertex opposite it), oriented out of the domain.
+Q4 bface_piece4(const Q4 V[4], int s, const Q4 &Xo) {
+  const Q4 CB = q4_scale(0.25, q4_add(q4_add(V[0], V[1]), q4_add(V[2], V[3])));
+  const Q4 out = q4_sub(V[s], Xo);
+  Q4 sum = {{0, 0, 0, 0}};
+  for (int a = 0; a < 4; ++a) {
+    if (a == s) continue;
+    const Q4 m = q4_scale(0.5, q4_add(V[s], V[a]));
+    for (int b = 0; b < 4; ++b) {
+      if (b == s || b == a) continue;
+      const Q4 F = q4_scale(1.0 / 3.0, q4_add(q4_add(V[s], V[a]), V[b]));
+      sum = q4_add(sum, q4_along(tet_area4(V[s], m, F, CB), out));
+    }
+  }
+  return sum;
+}
+
 // --------------------------------------------------------------- topology
 
 struct Topo {
@@ -304,10 +431,17 @@ int build_topology(Topo &t, int dim, int64_t nv, int64_t nelem, const int32_t *e
     }
   for (int64_t e = 0; e < nelem; ++e) {
     const int32_t *c = elem + e * nn;
-    P3<double> P[4];
-    for (int i = 0; i < nn; ++i) P[i] = point(X, dim, c[i]);
-    double det = dim == 2 ? (P[1].x - P[0].x) * (P[2].y - P[0].y) - (P[1].y - P[0].y) * (P[2].x - P[0].x)
-                          : dot(P[1] - P[0], cross(P[2] - P[0], P[3] - P[0]));
+    double det;
+    if (dim == 4) {
+      Q4 Q[5];
+      for (int i = 0; i < 5; ++i) Q[i] = point4(X, c[i]);
+      det = q4_det(q4_sub(Q[1], Q[0]), q4_sub(Q[2], Q[0]), q4_sub(Q[3], Q[0]), q4_sub(Q[4], Q[0]));
+    } else {
+      P3<double> P[4];
+      for (int i = 0; i < nn; ++i) P[i] = point(X, dim, c[i]);
+      det = dim == 2 ? (P[1].x - P[0].x) * (P[2].y - P[0].y) - (P[1].y - P[0].y) * (P[2].x - P[0].x)
+                     : dot(P[1] - P[0], cross(P[2] - P[0], P[3] - P[0]));
+    }
     if (det == 0.0) return OR_EDEGENERATE;
   }
 
@@ -365,19 +499,18 @@ int build_topology(Topo &t, int dim, int64_t nv, int64_t nelem, const int32_t *e
 
   // faces: sorted vertex ids of the face opposite each local vertex
   struct FaceKey {
-    int32_t v[3];
+    int32_t v[4];  // ascending; unused places -1
     uint32_t pay;
   };
   auto face_less = [](const FaceKey &a, const FaceKey &b) {
-    if (a.v[0] != b.v[0]) return a.v[0] < b.v[0];
-    if (a.v[1] != b.v[1]) return a.v[1] < b.v[1];
-    if (a.v[2] != b.v[2]) return a.v[2] < b.v[2];
+    for (int i = 0; i < 4; ++i)
+      if (a.v[i] != b.v[i]) return a.v[i] < b.v[i];
     return a.pay < b.pay;
   };
   std::vector<FaceKey> fk((size_t)nelem * nn);
   for (int64_t e = 0; e < nelem; ++e)
     for (int f = 0; f < nn; ++f) {
-      FaceKey k{{-1, -1, -1}, (uint32_t)(e * nn + f)};
+      FaceKey k{{-1, -1, -1, -1}, (uint32_t)(e * nn + f)};
       int c = 0;
       for (int i = 0; i < nn; ++i)
         if (i != f) k.v[c++] = elem[e * nn + i];
@@ -389,12 +522,30 @@ int build_topology(Topo &t, int dim, int64_t nv, int64_t nelem, const int32_t *e
   t.bface_owner.clear();
   for (size_t i = 0; i < fk.size();) {
     size_t j = i + 1;
-    while (j < fk.size() && std::equal(fk[j].v, fk[j].v + 3, fk[i].v)) ++j;
+    while (j < fk.size() && std::equal(fk[j].v, fk[j].v + 4, fk[i].v)) ++j;
     if (j - i > 2) return OR_ENONMANIFOLD;
     if (j - i == 1) {
       uint32_t pay = fk[i].pay;
       int64_t e = pay / nn;
       int f = pay % nn;
+      if (dim == 4) {
+        // keep the ascending order when its area vector N(b-a, c-a, d-a)
+        // points away from the opposite vertex, else swap the last two (an
+        // odd permutation flips it); the smallest id stays first
+        const int32_t *v = fk[i].v;
+        const Q4 A = point4(X, v[0]), Xo4 = point4(X, elem[e * nn + f]);
+        const double s4 = q4_dot(q4_cross(q4_sub(point4(X, v[1]), A), q4_sub(point4(X, v[2]), A),
+                                          q4_sub(point4(X, v[3]), A)),
+                                 q4_sub(A, Xo4));
+        if (s4 == 0) return OR_EDEGENERATE;
+        t.bface.push_back(v[0]);
+        t.bface.push_back(v[1]);
+        t.bface.push_back(s4 > 0 ? v[2] : v[3]);
+        t.bface.push_back(s4 > 0 ? v[3] : v[2]);
+        t.bface_owner.push_back((int32_t)pay);
+        i = j;
+        continue;
+      }
       P3<double> Xo = point(X, dim, elem[e * nn + f]);
       P3<double> A = point(X, dim, fk[i].v[0]), B = point(X, dim, fk[i].v[1]);
       bool keep;
@@ -424,16 +575,17 @@ int build_topology(Topo &t, int dim, int64_t nv, int64_t nelem, const int32_t *e
     i = j;
   }
   t.nbface = (int64_t)t.bface_owner.size();
-  const int nbe = dim == 2 ? 1 : 3;
+  // edges of each boundary element: its vertex pairs in lexicographic order
+  const int nbe = dim * (dim - 1) / 2;
+  const int (*bpairs)[2] = local_pairs(dim - 1);
   t.bface_edge.resize(t.nbface * nbe);
   for (int64_t f = 0; f < t.nbface; ++f) {
     const int32_t *v = &t.bface[f * dim];
     if (dim == 2) {
       t.bface_edge[f] = find_edge(t, v[0], v[1]);
     } else {
-      t.bface_edge[f * 3 + 0] = find_edge(t, v[0], v[1]);
-      t.bface_edge[f * 3 + 1] = find_edge(t, v[0], v[2]);
-      t.bface_edge[f * 3 + 2] = find_edge(t, v[1], v[2]);
+      for (int i = 0; i < nbe; ++i)
+        t.bface_edge[f * nbe + i] = find_edge(t, v[bpairs[i][0]], v[bpairs[i][1]]);
     }
   }
   // boundary nodes
@@ -460,6 +612,14 @@ void element_pieces_d(int dim, const double *const *X, const int32_t *elem, int6
                       double *np_out /*[ne][dim]*/, double *vp_out /*[dim+1]*/) {
   const int nn = dim + 1;
   const int32_t *c = elem + e * nn;
+  if (dim == 4) {
+    Q4 Q[5], nq[10];
+    for (int i = 0; i < 5; ++i) Q[i] = point4(X, c[i]);
+    pent_pieces(Q, c, nq, vp_out);
+    for (int l = 0; l < 10; ++l)
+      for (int k = 0; k < 4; ++k) np_out[l * 4 + k] = nq[l].c[k];
+    return;
+  }
   P3<double> P[4], npc[6];
   double vpc[4];
   for (int i = 0; i < nn; ++i) P[i] = point(X, dim, c[i]);
@@ -479,6 +639,17 @@ void element_pieces_d(int dim, const double *const *X, const int32_t *elem, int6
 void bface_pieces_d(int dim, const double *const *X, const Topo &t, const int32_t *elem,
                     int64_t f, double *out /*[dim][dim]: vertex s, component*/) {
   const int nn = dim + 1;
+  if (dim == 4) {
+    Q4 V4[4];
+    for (int s = 0; s < 4; ++s) V4[s] = point4(X, t.bface[f * 4 + s]);
+    const int32_t own4 = t.bface_owner[f];
+    const Q4 Xo4 = point4(X, elem[(int64_t)(own4 / nn) * nn + own4 % nn]);
+    for (int s = 0; s < 4; ++s) {
+      const Q4 p = bface_piece4(V4, s, Xo4);
+      for (int k = 0; k < 4; ++k) out[s * 4 + k] = p.c[k];
+    }
+    return;
+  }
   P3<double> V[3];
   for (int s = 0; s < dim; ++s) V[s] = point(X, dim, t.bface[f * dim + s]);
   int32_t own = t.bface_owner[f];
@@ -516,8 +687,9 @@ void oracle_set_threads(int n) {
 // Element pieces of elements [e0, e1): npiece [e1-e0][ne][dim], vpiece [e1-e0][dim+1].
 int oracle_element_pieces(int dim, int64_t nv, const double *coords, int64_t e0, int64_t e1,
                           const int32_t *elem, double *npiece, double *vpiece) {
-  if (dim != 2 && dim != 3) return OR_EINVAL;
-  const double *X[3] = {coords, coords + nv, dim == 3 ? coords + 2 * nv : coords};
+  if (dim < 2 || dim > 4) return OR_EINVAL;
+  const double *X[4] = {coords, coords + nv, dim >= 3 ? coords + 2 * nv : coords,
+                        dim == 4 ? coords + 3 * nv : coords};
   const int ne = n_local_edges(dim), nn = dim + 1;
 #pragma omp parallel for schedule(static)
   for (int64_t e = e0; e < e1; ++e)
@@ -530,7 +702,8 @@ int oracle_element_pieces(int dim, int64_t nv, const double *coords, int64_t e0,
 int oracle_bface_piece(int dim, int64_t nv, const double *coords, const int32_t *face,
                        int32_t opp, double *out /*[dim][dim]*/) {
   if (dim != 2 && dim != 3) return OR_EINVAL;
-  const double *X[3] = {coords, coords + nv, dim == 3 ? coords + 2 * nv : coords};
+  const double *X[4] = {coords, coords + nv, dim >= 3 ? coords + 2 * nv : coords,
+                        dim == 4 ? coords + 3 * nv : coords};
   P3<double> V[3];
   for (int s = 0; s < dim; ++s) V[s] = point(X, dim, face[s]);
   P3<double> Xo = point(X, dim, opp);
@@ -548,10 +721,11 @@ void oracle_topo_free(void *h) { delete static_cast<Topo *>(h); }
 
 int oracle_topology(void *h, int dim, int64_t nv, int64_t nelem, const int32_t *elem,
                     const double *coords) {
-  if (!h || (dim != 2 && dim != 3) || nv <= 0 || nelem < 0) return OR_EINVAL;
+  if (!h || dim < 2 || dim > 4 || nv <= 0 || nelem < 0) return OR_EINVAL;
   if ((int64_t)n_local_edges(dim) * nelem >= ((int64_t)1 << 31)) return OR_EOVERFLOW;
   if (nv >= ((int64_t)1 << 31)) return OR_EOVERFLOW;
-  const double *X[3] = {coords, coords + nv, dim == 3 ? coords + 2 * nv : coords};
+  const double *X[4] = {coords, coords + nv, dim >= 3 ? coords + 2 * nv : coords,
+                        dim == 4 ? coords + 3 * nv : coords};
   return build_topology(*static_cast<Topo *>(h), dim, nv, nelem, elem, X);
 }
 
@@ -612,7 +786,8 @@ int oracle_metrics(const void *h, const double *coords, const int32_t *elem, dou
                    double *b, double *V) {
   const Topo &t = *static_cast<const Topo *>(h);
   const int dim = t.dim, ne = n_local_edges(dim), nn = dim + 1;
-  const double *X[3] = {coords, coords + t.nv, dim == 3 ? coords + 2 * t.nv : coords};
+  const double *X[4] = {coords, coords + t.nv, dim >= 3 ? coords + 2 * t.nv : coords,
+                        dim == 4 ? coords + 3 * t.nv : coords};
   std::vector<double> npc, vpc;
   try {
     npc.resize((size_t)t.nelem * ne * dim);
@@ -625,7 +800,7 @@ int oracle_metrics(const void *h, const double *coords, const int32_t *elem, dou
     element_pieces_d(dim, X, elem, e, &npc[(size_t)e * ne * dim], &vpc[(size_t)e * nn]);
 #pragma omp parallel for schedule(static)
   for (int64_t ed = 0; ed < t.nedge; ++ed) {
-    Neumaier acc[3];
+    Neumaier acc[4];
     for (int32_t r = t.edge_inc_off[ed]; r < t.edge_inc_off[ed + 1]; ++r) {
       const double *p = &npc[(size_t)t.edge_inc[r] * dim];
       for (int c = 0; c < dim; ++c) acc[c].add(p[c]);
@@ -646,7 +821,7 @@ int oracle_metrics(const void *h, const double *coords, const int32_t *elem, dou
     for (int64_t f = 0; f < t.nbface; ++f) bface_pieces_d(dim, X, t, elem, f, &bpc[(size_t)f * dim * dim]);
 #pragma omp parallel for schedule(static)
     for (int64_t bi = 0; bi < t.nbnode; ++bi) {
-      Neumaier acc[3];
+      Neumaier acc[4];
       int32_t node = t.bnode[bi];
       for (int32_t r = t.bnode_face_off[bi]; r < t.bnode_face_off[bi + 1]; ++r) {
         int32_t f = t.bnode_face[r];
@@ -671,9 +846,11 @@ int oracle_node_grad(const void *h, const double *coords, const int32_t *elem, c
                      const double *c, const double *beta, const int32_t *nodes, int64_t nlist,
                      double *loss_out, double *grad_out) {
   const Topo &t = *static_cast<const Topo *>(h);
+  if (t.dim == 4) return OR_EINVAL;  // reference gradients are for D = 2, 3
   const int dim = t.dim, ne = n_local_edges(dim), nn = dim + 1;
   const int (*pairs)[2] = local_pairs(dim);
-  const double *X[3] = {coords, coords + t.nv, dim == 3 ? coords + 2 * t.nv : coords};
+  const double *X[4] = {coords, coords + t.nv, dim >= 3 ? coords + 2 * t.nv : coords,
+                        dim == 4 ? coords + 3 * t.nv : coords};
   (void)pairs;
   int status = OR_OK;
 #pragma omp parallel for schedule(dynamic, 16)

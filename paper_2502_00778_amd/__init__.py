@@ -10,7 +10,7 @@ package does not touch the GPU.
 from .api import (REDUCE, VOL_MODE, Topology, build_edges, check_errors,  # noqa: F401
                   directed_areas, directed_areas_backward, dual_volumes,
                   dual_volumes_noalloc, directed_areas_variant, edge_residual, get_gather_shape,
-                  set_gather_shape,
+                  set_gather_shape, time_next_call,
                   time_next_launch, workspace_bytes)
 from ._lib import EbError  # noqa: F401
 from .autograd import EdgeMetrics, edge_metrics  # noqa: F401

@@ -27,7 +27,7 @@ EXPORTS = ("eb_workspace_bytes", "eb_backward_workspace_bytes", "eb_build_edges"
            "eb_graph_launch", "eb_graph_destroy", "eb_set_fused_shape", "eb_get_fused_shape",
            "eb_set_fused_wait_limit", "eb_autotune", "eb_edge_residual",
            "eb_directed_areas_variant", "eb_set_fused_mode", "eb_get_fused_mode",
-           "eb_plan_describe", "eb_dual_volumes_noalloc")
+           "eb_plan_describe", "eb_dual_volumes_noalloc", "eb_time_next_call")
 
 TOPO_FIELDS = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign",
                "edge_inc_off", "edge_inc", "node_inc_off", "node_inc",
@@ -106,6 +106,7 @@ def lib():
     L.eb_get_gather_shape.restype = None
     L.eb_check_errors.argtypes = [P, P]
     L.eb_time_next_launch.argtypes = [P, P]
+    L.eb_time_next_call.argtypes = [P, P]
     SZ, TP = ctypes.POINTER(EbSizes), ctypes.POINTER(EbTopology)
     I64P = ctypes.POINTER(ctypes.c_int64)
     L.eb_batch_offsets.argtypes = [SZ, TP, P, i32, I64P, I64P, I64P, I64P, I64P, P, sz, P]

@@ -18,7 +18,8 @@ from ._lib import EbSizes, EbTopology, check, lib
 
 __all__ = ["Topology", "build_edges", "directed_areas", "dual_volumes",
            "directed_areas_backward", "check_errors", "set_gather_shape",
-           "get_gather_shape", "workspace_bytes", "time_next_launch", "edge_residual",
+           "get_gather_shape", "workspace_bytes", "time_next_launch", "time_next_call",
+           "edge_residual",
            "directed_areas_variant", "dual_volumes_noalloc", "REDUCE", "VOL_MODE", "BFLUX",
            "VARIANT"]
 
@@ -74,7 +75,7 @@ class Topology:
 
     @property
     def ne(self):
-        return 3 if self.dim == 2 else 6
+        return self.dim * (self.dim + 1) // 2
 
     def to_numpy(self):
         """Host copies of the topology arrays (the opaque plan excluded)."""
@@ -110,8 +111,8 @@ def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True
 
     ``adjoint`` also sizes the workspace for the gather adjoint
     (eb_backward_workspace_bytes)."""
-    if elems.dim() != 2 or elems.shape[1] not in (3, 4):
-        raise ValueError("elems must be [NE, D+1] with D in {2, 3}")
+    if elems.dim() != 2 or elems.shape[1] not in (3, 4, 5):
+        raise ValueError("elems must be [NE, D+1] with D in {2, 3, 4}")
     dim = int(elems.shape[1]) - 1
     _need(elems, "elems", torch.int32)
     _need(coords, "coords", torch.float64)
@@ -131,8 +132,8 @@ def build_edges(elems: torch.Tensor, coords: torch.Tensor, edge_inc: bool = True
                            _ptr(node_inc), _ptr(ws), wsb, ctypes.byref(sizes), s),
           "eb_build_edges")
     ne_, nb, nbn = int(sizes.n_edges), int(sizes.n_bfaces), int(sizes.n_bnodes)
-    ne = 3 if dim == 2 else 6
-    nbe = 1 if dim == 2 else 3
+    ne = dim * (dim + 1) // 2
+    nbe = dim * (dim - 1) // 2
     arr = dict(
         edge=torch.empty(2, ne_, **i32),
         node_edge_off=torch.empty(nv + 1, **i32),
@@ -272,6 +273,13 @@ def time_next_launch(start, stop):
     The events must already exist on the device (record each once)."""
     check(lib().eb_time_next_launch(ctypes.c_void_p(start.cuda_event),
                                     ctypes.c_void_p(stop.cuda_event)), "eb_time_next_launch")
+
+
+def time_next_call(start, stop):
+    """Arm two ``torch.cuda.Event(enable_timing=True)`` to bracket the
+    kernels of the next eb_directed_areas call (eb_time_next_call)."""
+    check(lib().eb_time_next_call(ctypes.c_void_p(start.cuda_event),
+                                  ctypes.c_void_p(stop.cuda_event)), "eb_time_next_call")
 
 
 def edge_residual(coords: torch.Tensor, topo: Topology, elems: torch.Tensor, n: torch.Tensor,

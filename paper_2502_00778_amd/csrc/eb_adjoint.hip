@@ -5,26 +5,42 @@ namespace eb {
 
 // ------------------------------------------------------------- atomic path
 
+// One thread per element: dL_E/dx_i for each vertex, summed per node in the
+// block's LDS table and added to the zeroed gradient with one FP64 atomic
+// per distinct node and component.
 template <int D>
-__global__ __launch_bounds__(256) void k_bwd_atomic_elem(FwdArgs a) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= a.nelem) return;
-  int32_t v[D + 1];
-  load_conn<D>(a.elem, e, v);
-  V3 P[D + 1], n[D + 1], W[D + 1];
+__global__ __launch_bounds__(ATOMIC_TB) void k_bwd_atomic_elem(FwdArgs a) {
+  __shared__ LdsAcc<ATOMIC_HV, D> tg;
+  const int t = threadIdx.x;
+  double *const gout[3] = {a.g_x, a.g_y, a.g_z};
+  lds_acc_init<ATOMIC_TB>(tg, t);
+  __syncthreads();
+  const int64_t e0 = (int64_t)blockIdx.x * ATOMIC_TB * ATOMIC_EPT;
 #pragma unroll
-  for (int i = 0; i <= D; ++i) P[i] = load_pt<D>(a.X, v[i]);
-  const double det = elem_normals<D>(P, n);
-  double C;
-  elem_weights<D>(a, e, v, W, C);
-  V3 G[D + 1];
-  elem_grad_all<D>(P, n, det, W, C, G);
+  for (int k = 0; k < ATOMIC_EPT; ++k) {
+    const int64_t e = e0 + (int64_t)k * ATOMIC_TB + t;
+    if (e >= a.nelem) break;
+    int32_t v[D + 1];
+    load_conn<D>(a.elem, e, v);
+    V3 P[D + 1], n[D + 1], W[D + 1];
 #pragma unroll
-  for (int l = 0; l <= D; ++l) {
-    unsafeAtomicAdd(&a.g_x[v[l]], G[l].x);
-    unsafeAtomicAdd(&a.g_y[v[l]], G[l].y);
-    if (D == 3) unsafeAtomicAdd(&a.g_z[v[l]], G[l].z);
+    for (int i = 0; i <= D; ++i) P[i] = load_pt<D>(a.X, v[i]);
+    const double det = elem_normals<D>(P, n);
+    double C;
+    elem_weights<D>(a, e, v, W, C);
+    V3 G[D + 1];
+    elem_grad_all<D>(P, n, det, W, C, G);
+#pragma unroll
+    for (int l = 0; l <= D; ++l) {
+      double c[D];
+      c[0] = G[l].x;
+      c[1] = G[l].y;
+      if constexpr (D == 3) c[D - 1] = G[l].z;
+      lds_acc_add(tg, gout, v[l], c);
+    }
   }
+  __syncthreads();
+  lds_acc_flush<ATOMIC_TB>(tg, gout, t);
 }
 
 template <int D>
@@ -78,8 +94,8 @@ int backward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_
     EB_TRY(fill_f64(a.g_y, a.nv, 0.0, s));
     if (D == 3) EB_TRY(fill_f64(a.g_z, a.nv, 0.0, s));
     if (a.nelem > 0 && (a.w_x || a.c)) {
-      launch_principal(k_bwd_atomic_elem<D>, dim3(grid_for(a.nelem, 256)), dim3(256), 0, s,
-                         a);
+      launch_principal(k_bwd_atomic_elem<D>, dim3(grid_for(a.nelem, ATOMIC_TB * ATOMIC_EPT)),
+                       dim3(ATOMIC_TB), 0, s, a);
       EB_LAUNCH_CHECK();
     }
     if (a.nbface > 0 && (a.w_x || a.be_x)) {

@@ -18,8 +18,11 @@ FusedCfg fused_cfg() { return g_fused; }
 void set_fused_cfg(const FusedCfg &c) { g_fused = c; }
 
 namespace {
-thread_local TimedLaunch t_armed;    // set by eb_time_next_launch
-thread_local TimedLaunch t_current;  // the events of the call in progress
+thread_local TimedLaunch t_armed;       // set by eb_time_next_launch
+thread_local TimedLaunch t_current;     // the events of the call in progress
+thread_local TimedLaunch t_span_armed;  // set by eb_time_next_call
+thread_local TimedLaunch t_span;        // the span events of the call in progress
+thread_local bool t_span_started = false;
 }  // namespace
 
 // The armed events move to the call in progress; whatever the call does not
@@ -27,13 +30,34 @@ thread_local TimedLaunch t_current;  // the events of the call in progress
 void principal_begin() {
   t_current = t_armed;
   t_armed = TimedLaunch{};
+  t_span = t_span_armed;
+  t_span_armed = TimedLaunch{};
+  t_span_started = false;
 }
-void principal_end() { t_current = TimedLaunch{}; }
-void clear_armed_events() { t_armed = TimedLaunch{}; }
+void principal_end() {
+  t_current = TimedLaunch{};
+  t_span = TimedLaunch{};
+}
+void clear_armed_events() {
+  t_armed = TimedLaunch{};
+  t_span_armed = TimedLaunch{};
+}
 
 TimedLaunch take_principal_events() {
   const TimedLaunch t = t_current;
   t_current = TimedLaunch{};
+  return t;
+}
+
+// Span events of the next launch of the call: the start event on its first
+// launch only, the stop event on every launch (each overwrites it, so it
+// ends at the last kernel).
+TimedLaunch take_span_events() {
+  TimedLaunch t = t_span;
+  if (t.stop) {
+    if (t_span_started) t.start = nullptr;
+    t_span_started = true;
+  }
   return t;
 }
 
@@ -160,6 +184,8 @@ int eb_directed_areas(const eb_sizes *sizes, const eb_topology *topo, const int3
                       double *vol, void *ws, size_t ws_bytes, hipStream_t stream) {
   PrincipalScope scope;
   clear_detail();
+  if (sizes && sizes->dim == 4)
+    return forward4(sizes, topo, elem, coords, reduce, n_edge, b_node, vol, ws, ws_bytes, stream);
   FwdArgs a;
   EB_TRY(pack(sizes, topo, elem, coords, ws, ws_bytes, a));
   if (reduce != EB_REDUCE_ATOMIC && reduce != EB_REDUCE_GATHER) {
@@ -191,6 +217,7 @@ int eb_directed_areas_variant(const eb_sizes *sizes, const eb_topology *topo,
                               size_t ws_bytes, hipStream_t stream) {
   PrincipalScope scope;
   clear_detail();
+  EB_TRY(only_dims23(sizes));
   FwdArgs a;
   EB_TRY(pack(sizes, topo, elem, coords, ws, ws_bytes, a));
   if (variant < EB_VARIANT_NODE_NORMALS || variant > EB_VARIANT_DUAL_FACES || !n_edge) {
@@ -213,6 +240,8 @@ int eb_dual_volumes(const eb_sizes *sizes, const eb_topology *topo, const int32_
                     double *vol, void *ws, size_t ws_bytes, hipStream_t stream) {
   PrincipalScope scope;
   clear_detail();
+  if (sizes && sizes->dim == 4)
+    return volumes4(sizes, topo, elem, coords, mode, n_edge, reduce, vol, ws, ws_bytes, stream);
   FwdArgs a;
   EB_TRY(pack(sizes, topo, elem, coords, ws, ws_bytes, a));
   if ((mode != EB_VOL_ELEMENT && mode != EB_VOL_EDGE) ||
@@ -246,6 +275,7 @@ int eb_edge_residual(const eb_sizes *sizes, const eb_topology *topo, const int32
                      hipStream_t stream) {
   PrincipalScope scope;
   clear_detail();
+  EB_TRY(only_dims23(sizes));
   FwdArgs a;
   EB_TRY(pack(sizes, topo, elem, coords, ws, ws_bytes, a));
   if (!n_edge || !flux || !res || (bflux != EB_BFLUX_NODE && bflux != EB_BFLUX_LINEAR) ||
@@ -273,6 +303,7 @@ int eb_directed_areas_backward(const eb_sizes *sizes, const eb_topology *topo,
                                hipStream_t stream) {
   PrincipalScope scope;
   clear_detail();
+  EB_TRY(only_dims23(sizes));
   FwdArgs a;
   EB_TRY(pack(sizes, topo, elem, coords, ws, ws_bytes, a));
   if ((reduce != EB_REDUCE_ATOMIC && reduce != EB_REDUCE_GATHER) || !grad_coords) {
@@ -292,6 +323,17 @@ int eb_directed_areas_backward(const eb_sizes *sizes, const eb_topology *topo,
   const LaunchCfg cfg = default_cfg();
   a.xcd_remap = cfg.xcd_remap;
   return D == 2 ? backward_impl<2>(a, reduce, cfg, stream) : backward_impl<3>(a, reduce, cfg, stream);
+}
+
+int eb_time_next_call(hipEvent_t start, hipEvent_t stop) {
+  clear_detail();
+  if ((start == nullptr) != (stop == nullptr)) {
+    set_detail("start and stop must both be set or both be null");
+    return EB_EINVAL;
+  }
+  t_span_armed.start = start;
+  t_span_armed.stop = stop;
+  return EB_OK;
 }
 
 int eb_time_next_launch(hipEvent_t start, hipEvent_t stop) {

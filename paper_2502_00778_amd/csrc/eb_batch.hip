@@ -299,6 +299,7 @@ int eb_batch_forward_backward(const eb_sizes *sizes, const eb_topology *topo,
                               size_t ws_bytes, hipStream_t stream) {
   PrincipalScope scope;
   clear_detail();
+  EB_TRY(only_dims23(sizes));
   FwdArgs a;
   EB_TRY(pack_fused(sizes, topo, elem, coords, grad_n, grad_b, grad_vol, n_edge, b_node, vol,
                     grad_coords, ws, ws_bytes, a));
@@ -312,6 +313,7 @@ int eb_batch_offsets(const eb_sizes *sizes, const eb_topology *topo, const int32
                      void *ws, size_t ws_bytes, hipStream_t stream) {
   clear_detail();
   EB_TRY(check_sizes(sizes));
+  EB_TRY(only_dims23(sizes));
   if (!topo || !node_off_host || !elem_off_host || !edge_off_host || !bnode_off_host ||
       !bface_off_host || n_mesh <= 0 || (sizes->n_elems > 0 && !elem)) {
     set_detail("null pointer or n_mesh <= 0");
@@ -389,6 +391,7 @@ int eb_batch_graph_create(const eb_sizes *sizes, const eb_topology *topo, const 
     return EB_EINVAL;
   }
   *out = nullptr;
+  EB_TRY(only_dims23(sizes));
   clear_armed_events();  // a captured launch records no timing events
   hipStream_t cs = nullptr;
   EB_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -495,6 +498,7 @@ int eb_autotune(const eb_sizes *sizes, const eb_topology *topo, const int32_t *e
                 double *grad_coords, void *ws, size_t ws_bytes, int reps, hipStream_t stream,
                 eb_tuning *out) {
   clear_detail();
+  EB_TRY(only_dims23(sizes));
   if (!out || reps < 1 || reps > 100) {
     set_detail("out is null or reps outside 1..100");
     return EB_EINVAL;

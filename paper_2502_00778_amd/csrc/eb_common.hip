@@ -36,13 +36,22 @@ int check_ws(int dim, int64_t n_nodes, int64_t n_elems, const void *ws, size_t w
   return EB_OK;
 }
 
+int only_dims23(const eb_sizes *s) {
+  if (s && s->dim == 4) {
+    set_detail("this call supports dim 2 and 3 (dim 4: eb_build_edges, eb_directed_areas and "
+               "eb_dual_volumes)");
+    return EB_EINVAL;
+  }
+  return EB_OK;
+}
+
 int check_sizes(const eb_sizes *s) {
   if (!s) {
     set_detail("sizes pointer is null");
     return EB_EINVAL;
   }
-  if (s->dim != 2 && s->dim != 3) {
-    set_detail("dim must be 2 or 3, got %d", s->dim);
+  if (s->dim < 2 || s->dim > 4) {
+    set_detail("dim must be 2, 3 or 4, got %d", s->dim);
     return EB_EINVAL;
   }
   if (s->n_nodes <= 0 || s->n_elems < 0 || s->n_edges < 0 || s->n_bfaces < 0 ||
@@ -50,7 +59,7 @@ int check_sizes(const eb_sizes *s) {
     set_detail("negative or empty sizes");
     return EB_EINVAL;
   }
-  const int64_t ne = s->dim == 2 ? 3 : 6;
+  const int64_t ne = (int64_t)s->dim * (s->dim + 1) / 2;
   if (ne * s->n_elems >= (int64_t(1) << 31) || s->n_nodes >= (int64_t(1) << 31) - 1) {
     set_detail("grid too large for int32 indexing");
     return EB_EOVERFLOW;
@@ -301,7 +310,7 @@ int fill_f64(double *p, int64_t n, double v, hipStream_t s) { return fill_impl(p
 extern "C" {
 
 size_t eb_workspace_bytes(int dim, int64_t n_nodes, int64_t n_elems) {
-  if ((dim != 2 && dim != 3) || n_nodes <= 0 || n_elems < 0) return 0;
+  if (dim < 2 || dim > 4 || n_nodes <= 0 || n_elems < 0) return 0;
   return eb::ws_layout(dim, n_nodes, n_elems).total;
 }
 

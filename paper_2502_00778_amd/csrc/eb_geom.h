@@ -89,7 +89,7 @@ template <bool WIDE> constexpr int no_slot() { return WIDE ? 1023 : 31; }
 
 template <int D> struct EL {
   static constexpr int NN = D + 1;
-  static constexpr int NE = D == 2 ? 3 : 6;
+  static constexpr int NE = D * (D + 1) / 2;
 };
 
 template <int D> __device__ __forceinline__ int pair_p(int le) {
@@ -125,6 +125,83 @@ __device__ __forceinline__ double elem_normals(const V3 (&P)[D + 1], V3 (&n)[D +
     n[1] = s * rot2(P[0] - P[2]);
     n[2] = s * rot2(P[1] - P[0]);
     return det;
+  }
+}
+
+// ------------------------------------------------ LDS pre-aggregation
+// The atomic paths scatter FP64 adds from elements into edges and nodes.  A
+// block first sums its own adds per target id in an LDS table (open
+// addressing, linear probing from id mod H: ids that arrive in contiguous
+// runs, as the edges of consecutive elements do, land in consecutive slots,
+// so the final device-scope adds of neighbouring slots go to neighbouring
+// addresses), then issues one device-scope atomic per occupied slot and
+// component.  An id that finds no slot within PROBES steps (a table filled
+// by a block of scattered ids) is added to global memory directly.
+// Elements per thread and LDS table sizes of the atomic element passes: a
+// block takes ATOMIC_TB * ATOMIC_EPT consecutive elements; its edge table
+// holds ATOMIC_HE slots and its node table ATOMIC_HV.
+#ifndef EB_ATOMIC_EPT
+#define EB_ATOMIC_EPT 2
+#endif
+constexpr int ATOMIC_TB = 256;
+constexpr int ATOMIC_EPT = EB_ATOMIC_EPT;
+constexpr int ATOMIC_HE = 1024 * ATOMIC_EPT;
+constexpr int ATOMIC_HV = 512 * ATOMIC_EPT;
+
+template <int H, int K> struct LdsAcc {
+  static_assert((H & (H - 1)) == 0, "table size is a power of two");
+  static constexpr int PROBES = 16;
+  int32_t key[H];
+  double acc[K][H];
+};
+
+template <int TB, int H, int K>
+__device__ __forceinline__ void lds_acc_init(LdsAcc<H, K> &T, int t) {
+  for (int s = t; s < H; s += TB) {
+    T.key[s] = -1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) T.acc[k][s] = 0.0;
+  }
+}
+
+// slot of id in the table (inserted if new), or -1 when the probes run out
+template <int H, int K>
+__device__ __forceinline__ int lds_acc_slot(LdsAcc<H, K> &T, int32_t id) {
+  int s = id & (H - 1);
+  for (int p = 0; p < LdsAcc<H, K>::PROBES; ++p) {
+    const int32_t k = __hip_atomic_load(&T.key[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (k == id) return s;
+    if (k == -1) {
+      const int32_t old = atomicCAS(&T.key[s], -1, id);
+      if (old == -1 || old == id) return s;
+    }
+    s = (s + 1) & (H - 1);
+  }
+  return -1;
+}
+
+// add v (K components) for id: into the table, or straight to out[k][id]
+template <int H, int K>
+__device__ __forceinline__ void lds_acc_add(LdsAcc<H, K> &T, double *const *out, int32_t id,
+                                            const double (&v)[K]) {
+  const int s = lds_acc_slot(T, id);
+  if (s >= 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) atomicAdd(&T.acc[k][s], v[k]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) unsafeAtomicAdd(&out[k][id], v[k]);
+  }
+}
+
+// the table's sums to global memory (after a barrier)
+template <int TB, int H, int K>
+__device__ __forceinline__ void lds_acc_flush(const LdsAcc<H, K> &T, double *const *out, int t) {
+  for (int s = t; s < H; s += TB) {
+    const int32_t id = T.key[s];
+    if (id >= 0)
+#pragma unroll
+      for (int k = 0; k < K; ++k) unsafeAtomicAdd(&out[k][id], T.acc[k][s]);
   }
 }
 

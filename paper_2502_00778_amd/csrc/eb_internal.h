@@ -71,7 +71,7 @@ inline WsLayout ws_layout(int dim, int64_t n_nodes, int64_t n_elems) {
   L.slen = off; off += align256(sizeof(int32_t) * (size_t)(n_slices(n_nodes) + 1));
   L.queue = off; off += per;
   // the longest array any call scans: ne*n_elems incidences
-  const int64_t ne = dim == 2 ? 3 : 6;
+  const int64_t ne = (int64_t)dim * (dim + 1) / 2;
   int64_t longest = std::max<int64_t>(n_nodes + 1, ne * n_elems + 1);
   // (or the node arrays' block sums, MAX_SCAN_JOBS arrays at once)
   L.scan_tmp_count = std::max<int64_t>((longest + SCAN_TILE - 1) / SCAN_TILE,
@@ -143,6 +143,9 @@ inline bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7
 
 int check_ws(int dim, int64_t n_nodes, int64_t n_elems, const void *ws, size_t ws_bytes);
 int check_sizes(const eb_sizes *s);
+// EB_EINVAL (with detail) for dim 4, which only the build, the forward and
+// the volume calls support
+int only_dims23(const eb_sizes *s);
 
 // ---------------------------------------------------------------- scans
 // Device scans of int32 arrays (n < 2^31, partial sums must fit int32).

@@ -90,8 +90,27 @@ struct PrincipalScope {
   PrincipalScope &operator=(const PrincipalScope &) = delete;
 };
 
+TimedLaunch take_span_events();  // eb_time_next_call's events for this launch
+
+// A launch that takes part in the call's span timing (eb_time_next_call).
+template <class K, class... A>
+void launch_span(K kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, A... args) {
+  const TimedLaunch t = take_span_events();
+  if (t.stop)
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, t.start, t.stop, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+}
+
+// The call's principal kernel (eb_time_next_launch); a call timed by span
+// (eb_time_next_call) takes part in that instead.
 template <class K, class... A>
 void launch_principal(K kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, A... args) {
+  const TimedLaunch sp = take_span_events();
+  if (sp.stop) {
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, sp.start, sp.stop, 0u, args...);
+    return;
+  }
   const TimedLaunch t = take_principal_events();
   if (t.start)
     hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, t.start, t.stop, 0u, args...);
@@ -125,5 +144,13 @@ template <int D>
 int residual_impl(const FwdArgs &a, const double *n_edge, const double *F, int linear,
                   double *res, hipStream_t s);
 template <int D> int backward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_t s);
+
+// dim 4 (pentatopes): eb_directed_areas and eb_dual_volumes in full
+int forward4(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
+             const double *coords, int reduce, double *n_edge, double *b_node, double *vol,
+             void *ws, size_t ws_bytes, hipStream_t s);
+int volumes4(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
+             const double *coords, int mode, const double *n_edge, int reduce, double *vol,
+             void *ws, size_t ws_bytes, hipStream_t s);
 
 }  // namespace eb

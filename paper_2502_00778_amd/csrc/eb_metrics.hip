@@ -23,35 +23,57 @@ namespace eb {
 
 // ------------------------------------------------------------- atomic path
 
+// One thread per element: the outward face normals and |E|, then
+// n_e += 2/(D(D+1)) n_tail^E for each local edge and V_i += |E|/(D+1) for
+// each vertex, summed per edge and node in the block's LDS tables and added
+// to the zeroed outputs with one FP64 atomic per distinct edge or node and
+// component.  n and vol may be null (skipped).
 template <int D>
-__global__ __launch_bounds__(256) void k_fwd_atomic_elem(FwdArgs a) {
+__global__ __launch_bounds__(ATOMIC_TB) void k_fwd_atomic_elem(FwdArgs a) {
   constexpr int NN = D + 1, NE = EL<D>::NE;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= a.nelem) return;
-  int32_t v[NN];
-  load_conn<D>(a.elem, e, v);
-  V3 P[NN], n[NN];
+  __shared__ LdsAcc<ATOMIC_HE, D> te;
+  __shared__ LdsAcc<ATOMIC_HV, 1> tv;
+  const int t = threadIdx.x;
+  const bool want_n = a.n_x != nullptr, want_v = a.vol != nullptr;
+  double *const nout[3] = {a.n_x, a.n_y, a.n_z};
+  double *const vout[1] = {a.vol};
+  if (want_n) lds_acc_init<ATOMIC_TB>(te, t);
+  if (want_v) lds_acc_init<ATOMIC_TB>(tv, t);
+  __syncthreads();
+  const int64_t e0 = (int64_t)blockIdx.x * ATOMIC_TB * ATOMIC_EPT;
 #pragma unroll
-  for (int i = 0; i < NN; ++i) P[i] = load_pt<D>(a.X, v[i]);
-  const double det = elem_normals<D>(P, n);
-  if (det == 0.0) raise_status(a.st, EB_EDEGENERATE, e);
-  constexpr double kN = 2.0 / (D * (D + 1));
-  if (a.n_x) {
+  for (int k = 0; k < ATOMIC_EPT; ++k) {
+    const int64_t e = e0 + (int64_t)k * ATOMIC_TB + t;
+    if (e >= a.nelem) break;
+    int32_t v[NN];
+    load_conn<D>(a.elem, e, v);
+    V3 P[NN], n[NN];
 #pragma unroll
-    for (int le = 0; le < NE; ++le) {
-      const int p = pair_p<D>(le), q = pair_q<D>(le);
-      const V3 nt = v[p] < v[q] ? n[p] : n[q];
-      const int32_t id = a.elem_edge[e * NE + le];
-      unsafeAtomicAdd(&a.n_x[id], kN * nt.x);
-      unsafeAtomicAdd(&a.n_y[id], kN * nt.y);
-      if (D == 3) unsafeAtomicAdd(&a.n_z[id], kN * nt.z);
+    for (int i = 0; i < NN; ++i) P[i] = load_pt<D>(a.X, v[i]);
+    const double det = elem_normals<D>(P, n);
+    if (det == 0.0) raise_status(a.st, EB_EDEGENERATE, e);
+    constexpr double kN = 2.0 / (D * (D + 1));
+    if (want_n) {
+#pragma unroll
+      for (int le = 0; le < NE; ++le) {
+        const int p = pair_p<D>(le), q = pair_q<D>(le);
+        const V3 nt = v[p] < v[q] ? n[p] : n[q];
+        double c[D];
+        c[0] = kN * nt.x;
+        c[1] = kN * nt.y;
+        if constexpr (D == 3) c[D - 1] = kN * nt.z;
+        lds_acc_add(te, nout, a.elem_edge[e * NE + le], c);
+      }
+    }
+    if (want_v) {
+      const double share[1] = {D == 3 ? fabs(det) / 24.0 : fabs(det) / 6.0};
+#pragma unroll
+      for (int i = 0; i < NN; ++i) lds_acc_add(tv, vout, v[i], share);
     }
   }
-  if (a.vol) {
-    const double share = (D == 3 ? fabs(det) / 24.0 : fabs(det) / 6.0);
-#pragma unroll
-    for (int i = 0; i < NN; ++i) unsafeAtomicAdd(&a.vol[v[i]], share);
-  }
+  __syncthreads();
+  if (want_n) lds_acc_flush<ATOMIC_TB>(te, nout, t);
+  if (want_v) lds_acc_flush<ATOMIC_TB>(tv, vout, t);
 }
 
 template <int D>
@@ -350,8 +372,7 @@ int launch_fwd_gather(const FwdArgs &a, const LaunchCfg &cfg, hipStream_t s) {
 template <int D>
 int launch_fwd_boundary(const FwdArgs &a, hipStream_t s) {
   if (a.nbnode <= 0) return EB_OK;
-  hipLaunchKernelGGL(k_fwd_boundary_gather<D>, dim3(grid_for(a.nbnode, 256)), dim3(256), 0, s,
-                     a);
+  launch_span(k_fwd_boundary_gather<D>, dim3(grid_for(a.nbnode, 256)), dim3(256), 0, s, a);
   EB_LAUNCH_CHECK();
   return EB_OK;
 }
@@ -402,13 +423,13 @@ int forward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_t
       if (D == 3) EB_TRY(fill_f64(a.b_z, a.nbnode, 0.0, s));
     }
     if (a.nelem > 0) {
-      launch_principal(k_fwd_atomic_elem<D>, dim3(grid_for(a.nelem, 256)), dim3(256), 0, s,
+      launch_principal(k_fwd_atomic_elem<D>, dim3(grid_for(a.nelem, ATOMIC_TB * ATOMIC_EPT)),
+                       dim3(ATOMIC_TB), 0, s,
                          a);
       EB_LAUNCH_CHECK();
     }
     if (a.nbface > 0 && (a.n_x || a.b_x)) {
-      hipLaunchKernelGGL(k_fwd_atomic_bface<D>, dim3(grid_for(a.nbface, 256)), dim3(256), 0, s,
-                         a);
+      launch_span(k_fwd_atomic_bface<D>, dim3(grid_for(a.nbface, 256)), dim3(256), 0, s, a);
       EB_LAUNCH_CHECK();
     }
     return EB_OK;
@@ -428,8 +449,8 @@ int volumes_impl(const FwdArgs &a, int mode, int reduce, const double *n_edge, h
       b.b_x = b.b_y = b.b_z = nullptr;
       EB_TRY(fill_f64(b.vol, b.nv, 0.0, s));
       if (b.nelem > 0) {
-        launch_principal(k_fwd_atomic_elem<D>, dim3(grid_for(b.nelem, 256)), dim3(256), 0, s,
-                           b);
+        launch_principal(k_fwd_atomic_elem<D>, dim3(grid_for(b.nelem, ATOMIC_TB * ATOMIC_EPT)),
+                         dim3(ATOMIC_TB), 0, s, b);
         EB_LAUNCH_CHECK();
       }
       return EB_OK;

@@ -47,6 +47,7 @@ extern "C" int eb_dual_volumes_noalloc(const eb_sizes *sizes, const eb_topology 
   PrincipalScope scope;
   clear_detail();
   EB_TRY(check_sizes(sizes));
+  EB_TRY(only_dims23(sizes));
   FwdArgs a;
   EB_TRY(pack_arrays(sizes, topo, nullptr, coords, false, a));
   if ((reduce != EB_REDUCE_ATOMIC && reduce != EB_REDUCE_GATHER) || !vol || !n_edge) {

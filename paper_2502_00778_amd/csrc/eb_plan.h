@@ -66,6 +66,10 @@ struct PlanLayout {
 inline PlanLayout plan_layout(int dim, int64_t n_nodes, int64_t n_elems, int64_t n_slots,
                               int wide) {
   PlanLayout P{};
+  if (dim == 4) {  // no plan in four dimensions: one placeholder line
+    P.total = 256;
+    return P;
+  }
   size_t off = 0;
   P.slice_off = off;
   off += align256(sizeof(int32_t) * (size_t)(n_slices(n_nodes) + 1));
@@ -97,7 +101,7 @@ inline PlanPtrs plan_ptrs(const eb_sizes *s, void *plan) {
   const PlanLayout P = plan_layout(s->dim, s->n_nodes, s->n_elems, plan_slots(s), plan_wide(s));
   char *b = static_cast<char *>(plan);
   PlanPtrs p{};
-  if (!b) return p;
+  if (!b || s->dim == 4) return p;
   p.slice_off = reinterpret_cast<int32_t *>(b + P.slice_off);
   p.entry = reinterpret_cast<uint64_t *>(b + P.entry);
   p.step = plan_wide(s) ? nullptr : reinterpret_cast<uint32_t *>(b + P.step);

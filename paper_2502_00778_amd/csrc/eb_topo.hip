@@ -21,6 +21,7 @@
 #include <type_traits>
 
 #include "eb_geom.h"
+#include "eb_geom4.h"
 #include "eb_plan.h"
 
 namespace eb {
@@ -232,6 +233,7 @@ struct TopoArgs {
   int64_t nv;
   const int32_t *elem;
   Coords X;
+  const double *xw;  // fourth coordinate row (dim 4)
   const int32_t *node_inc_off;
   const int32_t *node_inc;
   const int32_t *rows4;  // workspace: Inc4 per incidence, rows of node_inc_off
@@ -1571,10 +1573,16 @@ __global__ void k_bface_edge(const int32_t *__restrict__ bface, int64_t nb,
   if constexpr (D == 2) {
     bface_edge[f] = find_edge(node_edge_off, head, bface[2 * f], bface[2 * f + 1]);
   } else {
-    const int32_t a = bface[3 * f], b = bface[3 * f + 1], c = bface[3 * f + 2];
-    bface_edge[3 * f + 0] = find_edge(node_edge_off, head, a, b);
-    bface_edge[3 * f + 1] = find_edge(node_edge_off, head, a, c);
-    bface_edge[3 * f + 2] = find_edge(node_edge_off, head, b, c);
+    // the face's vertex pairs in lexicographic order
+    int32_t v[D];
+#pragma unroll
+    for (int s = 0; s < D; ++s) v[s] = bface[D * f + s];
+    int k = 0;
+#pragma unroll
+    for (int p = 0; p < D; ++p)
+#pragma unroll
+      for (int q = p + 1; q < D; ++q)
+        bface_edge[(int64_t)(D * (D - 1) / 2) * f + k++] = find_edge(node_edge_off, head, v[p], v[q]);
   }
 }
 
@@ -1588,6 +1596,259 @@ __global__ void k_scatter_edge_inc(int64_t nelem, const int32_t *__restrict__ el
   if (id < 0) return;
   const int32_t pos = atomicSub(&cur[id], 1) - 1;
   edge_inc[pos] = (int32_t)i;
+}
+
+// ------------------------------------------------ four dimensions (dim = 4)
+//
+// Pentatope grids take a plain form of the build: node rows by a counting
+// sort (global atomics), rows sorted, and every node through one wavefront
+// like the general kernel above, the other vertices of each incidence read
+// from the connectivity.  No kernel plan is made: the dim-4 metric kernels
+// walk node_inc directly.  The outputs are the same arrays, with the same
+// unique definitions; a boundary face (a tetrahedron) lists its vertices
+// ascending, with the last two swapped when that order's area vector
+// N(b-a, c-a, d-a) points into the domain.
+
+__global__ void k4_count(const int32_t *__restrict__ elem, int64_t nelem, int64_t nv,
+                         Coords4 X, int32_t *cnt, StatusBlock *st) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nelem) return;
+  int32_t v[5];
+  load_conn4(elem, e, v);
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) ok = ok && v[i] >= 0 && v[i] < nv;
+  if (!ok) {
+    raise_status(st, EB_ERANGE, e);
+    return;
+  }
+  V4 P[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) P[i] = load_pt4(X, v[i]);
+  if (pent_det(P) == 0.0) raise_status(st, EB_EDEGENERATE, e);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) atomicAdd(&cnt[v[i]], 1);
+}
+
+// cur: the rows' end offsets, taken down to their starts
+__global__ void k4_scatter(const int32_t *__restrict__ elem, int64_t nelem, int64_t nv,
+                           int32_t *cur, int32_t *node_inc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nelem) return;
+  int32_t v[5];
+  load_conn4(elem, e, v);
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) ok = ok && v[i] >= 0 && v[i] < nv;
+  if (!ok) return;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) node_inc[atomicSub(&cur[v[i]], 1) - 1] = (int32_t)(e * 5 + i);
+}
+
+// the other vertices of incidence elem*5 + l (local order, l's place taken
+// by vertex 4)
+__device__ __forceinline__ void others4(const int32_t *elem, int32_t inc, int32_t (&o)[4]) {
+  int32_t v[5];
+  load_conn4(elem, inc / 5, v);
+  const int l = inc % 5;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) o[m] = l == m ? v[4] : v[m];
+}
+
+// candidate face keys of one incidence of j: the triples of its other
+// vertices all above j, as (p << 32 | q, r) with p < q < r; (~0, ~0) marks
+// none
+__device__ __forceinline__ void face_keys4(const int32_t (&o)[4], int32_t j, uint64_t (&kh)[4],
+                                           uint64_t (&kl)[4]) {
+#pragma unroll
+  for (int drop = 0; drop < 4; ++drop) {
+    int32_t t[3];
+    int n = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if (m != drop) t[n++] = o[m];
+    // sort three
+    int32_t a = min(t[0], t[1]), b = max(t[0], t[1]), c = t[2];
+    const int32_t lo = min(a, c), hi = max(b, c), mid = max(a, min(b, c));
+    const bool ok = lo > j;
+    kh[drop] = ok ? ((uint64_t)(uint32_t)lo << 32 | (uint32_t)mid) : ~0ull;
+    kl[drop] = ok ? (uint64_t)(uint32_t)hi : ~0ull;
+  }
+}
+
+__device__ __forceinline__ bool key_less(uint64_t ah, uint64_t al, uint64_t bh, uint64_t bl) {
+  return ah < bh || (ah == bh && al < bl);
+}
+
+template <bool EMIT>
+__device__ void node_topo4(const TopoArgs &a, int32_t j, int lane) {
+  const int32_t r0 = a.node_inc_off[j], r1 = a.node_inc_off[j + 1];
+  const int32_t len = r1 - r0;
+  const Coords4 X{a.X.x, a.X.y, a.X.z, a.xw};
+
+  // 1. distinct neighbours, ascending (as in the general kernel)
+  int32_t e0 = 0, in_end = 0, nlow_known = 0;
+  if constexpr (EMIT) {
+    e0 = a.eoff[j];
+    in_end = a.in_cur[j];
+    nlow_known = a.ein_scan[j] - (j > 0 ? a.ein_scan[j - 1] : 0);
+  }
+  int32_t last = INT32_MIN, nh = 0, nlow = 0;
+  for (;;) {
+    int32_t mn = INT32_MAX;
+    for (int32_t i = lane; i < len; i += 64) {
+      int32_t o[4];
+      others4(a.elem, a.node_inc[r0 + i], o);
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        if (o[m] > last) mn = min(mn, o[m]);
+    }
+    mn = wave_min_i32(mn);
+    if (mn == INT32_MAX) break;
+    if constexpr (EMIT) {
+      if (lane == 0) {
+        if (mn < j) {
+          a.node_in_edge[in_end - nlow_known + nh] = mn;
+        } else {
+          a.edge_tail[e0 + nh - nlow] = j;
+          a.edge_head[e0 + nh - nlow] = mn;
+        }
+      }
+    }
+    if (mn < j) ++nlow;
+    ++nh;
+    last = mn;
+  }
+  if constexpr (!EMIT) {
+    if (lane == 0) {
+      a.outdeg[j] = nh - nlow;
+      a.ein[j] = nlow;
+    }
+  } else {
+    if (lane == 0) a.in_cur[j] = in_end - nlow;
+  }
+
+  // 2. candidate faces with j as smallest vertex in ascending key order,
+  //    each counted over the row the round after it is found
+  int32_t nb = 0, f = EMIT ? a.foff[j] : 0;
+  uint64_t ch = 0, cl = 0;
+  bool have = false;
+  for (;;) {
+    uint64_t bh = ~0ull, bl = ~0ull;
+    int32_t cnt = 0, holder = INT32_MAX;
+    for (int32_t i = lane; i < len; i += 64) {
+      int32_t o[4];
+      others4(a.elem, a.node_inc[r0 + i], o);
+      uint64_t kh[4], kl[4];
+      face_keys4(o, j, kh, kl);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (kh[c] == ~0ull) continue;
+        if ((!have || key_less(ch, cl, kh[c], kl[c])) && key_less(kh[c], kl[c], bh, bl)) {
+          bh = kh[c];
+          bl = kl[c];
+        }
+        if (have && kh[c] == ch && kl[c] == cl) {
+          ++cnt;
+          holder = min(holder, i);
+        }
+      }
+    }
+    const uint64_t mh = wave_min_u64(bh);
+    const uint64_t ml = wave_min_u64(bh == mh ? bl : ~0ull);
+    if (have) {
+      cnt = wave_sum_i32(cnt);
+      holder = wave_min_i32(holder);
+      if (cnt > 2) {
+        if (lane == 0) raise_status(a.st, EB_ENONMANIFOLD, j);
+        return;
+      }
+      if (cnt == 1) {
+        const int32_t fv[4] = {j, (int32_t)(ch >> 32), (int32_t)(uint32_t)ch, (int32_t)cl};
+        if (lane == 0) {
+          if constexpr (!EMIT) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              a.bflag[fv[s]] = 1;
+              atomicAdd(&a.bfn[fv[s]], 1);
+            }
+          } else {
+            const int32_t inc = a.node_inc[r0 + holder];
+            int32_t v[5];
+            load_conn4(a.elem, inc / 5, v);
+            // the owner's vertex off the face
+            int opp = 0;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+              bool on = false;
+#pragma unroll
+              for (int s = 0; s < 4; ++s) on = on || v[q] == fv[s];
+              if (!on) opp = q;
+            }
+            // outward order: the expression and operand order of the
+            // definition, FP64 without contraction
+            bool keep;
+            {
+#pragma clang fp contract(off)
+              const V4 A = load_pt4(X, fv[0]);
+              const V4 N = v4_cross(v4_sub(load_pt4(X, fv[1]), A), v4_sub(load_pt4(X, fv[2]), A),
+                                    v4_sub(load_pt4(X, fv[3]), A));
+              keep = v4_dot(N, v4_sub(A, load_pt4(X, v[opp]))) > 0;
+            }
+            int32_t *bf = a.bface + (int64_t)4 * f;
+            bf[0] = fv[0];
+            bf[1] = fv[1];
+            bf[2] = keep ? fv[2] : fv[3];
+            bf[3] = keep ? fv[3] : fv[2];
+            a.bface_owner[f] = (int32_t)((int64_t)(inc / 5) * 5 + opp);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              const int32_t pos = atomicSub(&a.bf_cur[fv[s]], 1) - 1;
+              a.bnode_face[pos] = f;
+            }
+          }
+        }
+        ++nb;
+        ++f;
+      }
+    }
+    if (mh == ~0ull) break;
+    ch = mh;
+    cl = ml;
+    have = true;
+  }
+  if constexpr (!EMIT) {
+    if (lane == 0) a.fmin[j] = nb;
+  }
+}
+
+template <bool EMIT>
+__global__ __launch_bounds__(64) void k4_node_topo(TopoArgs a) {
+  if (build_failed(a.st)) return;
+  for (int64_t j = blockIdx.x; j < a.nv; j += gridDim.x)
+    node_topo4<EMIT>(a, (int32_t)j, (int)threadIdx.x);
+}
+
+// element -> edge map and signs: the ten local pairs in lexicographic order
+__global__ void k4_elem_maps(const int32_t *__restrict__ elem, int64_t nelem,
+                             const int32_t *__restrict__ node_edge_off,
+                             const int32_t *__restrict__ head, int32_t *elem_edge,
+                             int8_t *elem_edge_sign, StatusBlock *st) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nelem || build_failed(st)) return;
+  int32_t v[5];
+  load_conn4(elem, e, v);
+  int k = 0;
+#pragma unroll
+  for (int p = 0; p < 5; ++p)
+#pragma unroll
+    for (int q = p + 1; q < 5; ++q) {
+      const int32_t id = find_edge(node_edge_off, head, v[p], v[q]);
+      if (id < 0) raise_status(st, EB_EINVAL, e);  // cannot happen for a consistent build
+      elem_edge[e * 10 + k] = id;
+      elem_edge_sign[e * 10 + k] = (int8_t)(v[p] < v[q] ? 1 : -1);
+      ++k;
+    }
 }
 
 template <int D>
@@ -1837,6 +2098,166 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
   return EB_OK;
 }
 
+
+// ---------------------------------------------------- dim 4 host side
+
+int build4_impl(int64_t nv, int64_t nelem, const int32_t *elem, const double *coords,
+                int32_t *node_inc_off, int32_t *node_inc, void *ws, eb_sizes *sizes,
+                hipStream_t s) {
+  const WsLayout L = ws_layout(4, nv, nelem);
+  StatusBlock *st = ws_at<StatusBlock>(ws, 0);
+  int32_t *eoff = ws_at<int32_t>(ws, L.eoff), *foff = ws_at<int32_t>(ws, L.foff);
+  int32_t *bidx = ws_at<int32_t>(ws, L.bidx), *bfn = ws_at<int32_t>(ws, L.bfn);
+  int32_t *bfn_scan = ws_at<int32_t>(ws, L.bfn_scan), *ein = ws_at<int32_t>(ws, L.ein_scan);
+  int32_t *tmp = ws_at<int32_t>(ws, L.scan_tmp);
+  const Coords4 X = coords4_rows(coords, nv);
+
+  EB_TRY(fill_i32(reinterpret_cast<int32_t *>(st), sizeof(StatusBlock) / 4, 0, s));
+  EB_TRY(fill_i32(eoff, (int64_t)((L.scan_tmp - L.eoff) / 4), 0, s));
+  EB_TRY(fill_i32(node_inc_off, nv + 1, 0, s));
+  if (nelem > 0) {
+    hipLaunchKernelGGL(k4_count, dim3(grid_for(nelem, 256)), dim3(256), 0, s, elem, nelem, nv, X,
+                       node_inc_off, st);
+    EB_LAUNCH_CHECK();
+  }
+  EB_TRY(scan_inclusive(node_inc_off, node_inc_off, nv, node_inc_off + nv, tmp, s));
+  if (nelem > 0) {
+    hipLaunchKernelGGL(k4_scatter, dim3(grid_for(nelem, 256)), dim3(256), 0, s, elem, nelem, nv,
+                       node_inc_off, node_inc);
+    EB_LAUNCH_CHECK();
+    EB_TRY(rowsort(node_inc_off, node_inc, nv, s));
+  }
+  TopoArgs ta{};
+  ta.nv = nv;
+  ta.elem = elem;
+  ta.X = Coords{X.x, X.y, X.z};
+  ta.xw = X.w;
+  ta.node_inc_off = node_inc_off;
+  ta.node_inc = node_inc;
+  ta.outdeg = eoff;
+  ta.fmin = foff;
+  ta.bflag = bidx;
+  ta.bfn = bfn;
+  ta.ein = ein;
+  ta.st = st;
+  hipLaunchKernelGGL((k4_node_topo<false>), dim3((unsigned)std::min<int64_t>(nv, 16384)), dim3(64),
+                     0, s, ta);
+  EB_LAUNCH_CHECK();
+  ScanJobs J{};
+  const int32_t *sin[5] = {eoff, foff, bidx, bfn, ein};
+  int32_t *sout[5] = {eoff, foff, bidx, bfn_scan, ein};
+  int32_t *stot[5] = {&st->totals[T_EDGES], &st->totals[T_BFACES], &st->totals[T_BNODES],
+                      nullptr, nullptr};
+  const int32_t sincl[5] = {0, 0, 0, 1, 1};
+  for (int q = 0; q < 5; ++q) {
+    J.in[q] = sin[q];
+    J.out[q] = sout[q];
+    J.total[q] = stot[q];
+    J.inclusive[q] = sincl[q];
+  }
+  EB_TRY(scan_many(J, 5, nv + 1, tmp, s));
+  StatusBlock h;
+  EB_HIP_CHECK(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
+  EB_HIP_CHECK(hipStreamSynchronize(s));
+  sizes->dim = 4;
+  sizes->n_nodes = nv;
+  sizes->n_elems = nelem;
+  sizes->n_edges = h.totals[T_EDGES];
+  sizes->n_bfaces = h.totals[T_BFACES];
+  sizes->n_bnodes = h.totals[T_BNODES];
+  sizes->plan_param[0] = 0;  // no kernel plan in four dimensions
+  sizes->plan_param[1] = 0;
+  sizes->plan_bytes = (int64_t)plan_bytes_of(sizes);
+  if (h.status != EB_OK) {
+    set_detail("%s at %s %lld", eb_status_string(h.status),
+               h.status == EB_ERANGE || h.status == EB_EDEGENERATE ? "element" : "node",
+               (long long)h.detail);
+    return h.status;
+  }
+  return EB_OK;
+}
+
+int emit4_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
+               const eb_topology *tp, void *ws, hipStream_t s) {
+  const int64_t nv = sz->n_nodes, nelem = sz->n_elems;
+  const WsLayout L = ws_layout(4, nv, nelem);
+  StatusBlock *st = ws_at<StatusBlock>(ws, 0);
+  int32_t *eoff = ws_at<int32_t>(ws, L.eoff), *foff = ws_at<int32_t>(ws, L.foff);
+  int32_t *bidx = ws_at<int32_t>(ws, L.bidx), *bfn = ws_at<int32_t>(ws, L.bfn);
+  int32_t *bfn_scan = ws_at<int32_t>(ws, L.bfn_scan), *ein = ws_at<int32_t>(ws, L.ein_scan);
+  int32_t *tmp = ws_at<int32_t>(ws, L.scan_tmp);
+  constexpr int NE = 10;
+  const Coords4 X = coords4_rows(coords, nv);
+
+  EmitNodeArgs en{nv, 4, eoff, bidx, bfn, bfn_scan, ein, tp->node_edge_off, tp->node_bnode,
+                  tp->bnode, tp->bnode_face_off, tp->node_in_off, st};
+  hipLaunchKernelGGL(k_emit_nodes, dim3(grid_for(nv + 1, 256)), dim3(256), 0, s, en);
+  EB_LAUNCH_CHECK();
+  TopoArgs ta{};
+  ta.nv = nv;
+  ta.elem = elem;
+  ta.X = Coords{X.x, X.y, X.z};
+  ta.xw = X.w;
+  ta.node_inc_off = tp->node_inc_off;
+  ta.node_inc = tp->node_inc;
+  ta.eoff = eoff;
+  ta.foff = foff;
+  ta.ein_scan = ein;
+  ta.edge_tail = tp->edge;
+  ta.edge_head = tp->edge + sz->n_edges;
+  ta.bface = tp->bface;
+  ta.bface_owner = tp->bface_owner;
+  ta.in_cur = tp->node_in_off;
+  ta.node_in_edge = tp->node_in_edge;
+  ta.bf_cur = bfn_scan;
+  ta.bnode_face = tp->bnode_face;
+  ta.st = st;
+  hipLaunchKernelGGL((k4_node_topo<true>), dim3((unsigned)std::min<int64_t>(nv, 16384)), dim3(64),
+                     0, s, ta);
+  EB_LAUNCH_CHECK();
+  if (sz->n_edges > 0) {
+    hipLaunchKernelGGL(k_node_in_ids, dim3(grid_for(nv, 256)), dim3(256), 0, s, nv,
+                       (const int32_t *)tp->node_in_off, (const int32_t *)tp->node_edge_off,
+                       (const int32_t *)(tp->edge + sz->n_edges), tp->node_in_edge, st);
+    EB_LAUNCH_CHECK();
+  }
+  EB_TRY(rowsort(tp->bnode_face_off, tp->bnode_face, sz->n_bnodes, s));
+  if (nelem > 0) {
+    hipLaunchKernelGGL(k4_elem_maps, dim3(grid_for(nelem, 256)), dim3(256), 0, s, elem, nelem,
+                       (const int32_t *)tp->node_edge_off,
+                       (const int32_t *)(tp->edge + sz->n_edges), tp->elem_edge,
+                       tp->elem_edge_sign, st);
+    EB_LAUNCH_CHECK();
+  }
+  const bool want_inc = tp->edge_inc_off && tp->edge_inc;
+  if (want_inc) {
+    EB_TRY(fill_i32(tp->edge_inc_off, sz->n_edges + 1, 0, s));
+    if (nelem > 0) {
+      hipLaunchKernelGGL(k_edge_inc_count<4>, dim3(grid_for(nelem * NE, 256)), dim3(256), 0, s,
+                         nelem, (const int32_t *)tp->elem_edge, tp->edge_inc_off, st);
+      EB_LAUNCH_CHECK();
+    }
+  }
+  if (sz->n_bfaces > 0) {
+    hipLaunchKernelGGL(k_bface_edge<4>, dim3(grid_for(sz->n_bfaces, 256)), dim3(256), 0, s,
+                       (const int32_t *)tp->bface, sz->n_bfaces,
+                       (const int32_t *)tp->node_edge_off,
+                       (const int32_t *)(tp->edge + sz->n_edges), tp->bface_edge, st);
+    EB_LAUNCH_CHECK();
+  }
+  if (want_inc) {
+    EB_TRY(scan_inclusive(tp->edge_inc_off, tp->edge_inc_off, sz->n_edges, nullptr, tmp, s));
+    EB_TRY(fill_i32(tp->edge_inc_off + sz->n_edges, 1, (int32_t)(NE * nelem), s));
+    if (nelem > 0) {
+      hipLaunchKernelGGL(k_scatter_edge_inc<4>, dim3(grid_for(nelem * NE, 256)), dim3(256), 0,
+                         s, nelem, (const int32_t *)tp->elem_edge, tp->edge_inc_off,
+                         tp->edge_inc, st);
+      EB_LAUNCH_CHECK();
+    }
+    EB_TRY(rowsort(tp->edge_inc_off, tp->edge_inc, sz->n_edges, s));
+  }
+  return EB_OK;
+}
 }  // namespace
 }  // namespace eb
 
@@ -1848,8 +2269,8 @@ int eb_build_edges(int dim, int64_t n_nodes, int64_t n_elems, const int32_t *ele
                    const double *coords, int32_t *node_inc_off, int32_t *node_inc, void *ws,
                    size_t ws_bytes, eb_sizes *sizes_host, hipStream_t stream) {
   clear_detail();
-  if (dim != 2 && dim != 3) {
-    set_detail("dim must be 2 or 3, got %d", dim);
+  if (dim < 2 || dim > 4) {
+    set_detail("dim must be 2, 3 or 4, got %d", dim);
     return EB_EINVAL;
   }
   if (n_nodes <= 0 || n_elems < 0 || !sizes_host || !coords || !node_inc_off ||
@@ -1857,7 +2278,7 @@ int eb_build_edges(int dim, int64_t n_nodes, int64_t n_elems, const int32_t *ele
     set_detail("null pointer or negative size");
     return EB_EINVAL;
   }
-  const int64_t ne = dim == 2 ? 3 : 6;
+  const int64_t ne = (int64_t)dim * (dim + 1) / 2;
   if (ne * n_elems >= (int64_t(1) << 31) || n_nodes >= (int64_t(1) << 31) - 1) {
     set_detail("grid too large for int32 indexing");
     return EB_EOVERFLOW;
@@ -1868,6 +2289,9 @@ int eb_build_edges(int dim, int64_t n_nodes, int64_t n_elems, const int32_t *ele
     return EB_EINVAL;
   }
   EB_TRY(check_ws(dim, n_nodes, n_elems, ws, ws_bytes));
+  if (dim == 4)
+    return build4_impl(n_nodes, n_elems, elem, coords, node_inc_off, node_inc, ws, sizes_host,
+                       stream);
   return dim == 2 ? build_edges_impl<2>(n_nodes, n_elems, elem, coords, node_inc_off, node_inc,
                                         ws, sizes_host, stream)
                   : build_edges_impl<3>(n_nodes, n_elems, elem, coords, node_inc_off, node_inc,
@@ -1903,6 +2327,7 @@ int eb_build_edges_emit(const eb_sizes *sizes, const int32_t *elem, const double
     return EB_EINVAL;
   }
   EB_TRY(check_ws(sizes->dim, sizes->n_nodes, sizes->n_elems, ws, ws_bytes));
+  if (sizes->dim == 4) return emit4_impl(sizes, elem, coords, topo, ws, stream);
   return sizes->dim == 2 ? emit_impl<2>(sizes, elem, coords, topo, ws, stream)
                          : emit_impl<3>(sizes, elem, coords, topo, ws, stream);
 }

@@ -41,7 +41,8 @@ def test_status_strings(L):
 
 
 def test_workspace_bytes(L):
-    assert L.eb_workspace_bytes(4, 10, 10) == 0
+    assert L.eb_workspace_bytes(5, 10, 10) == 0
+    assert L.eb_workspace_bytes(4, 10, 10) > 0  # pentatope grids
     assert L.eb_workspace_bytes(3, 0, 10) == 0
     small = L.eb_workspace_bytes(3, 100, 300)
     big = L.eb_workspace_bytes(3, 161 ** 3, 6 * 160 ** 3)
@@ -83,7 +84,7 @@ def test_backward_workspace_bytes(L):
         rows = up(16 * ninc) + up(4 * ninc) + up(2 * ninc)
         pieces = -(-per * 64 * 400 // 256) * 256
         assert got == max(base, base - rows + pieces)
-    bad = EbSizes(dim=4, n_nodes=10, n_elems=10)
+    bad = EbSizes(dim=5, n_nodes=10, n_elems=10)
     assert L.eb_backward_workspace_bytes(ctypes.byref(bad)) == 0
     # plan fields that no build produces are rejected
     bad = sizes(3, 1000, 5000, 6000, 10, 10, n_slots=64 * 400)
@@ -116,7 +117,7 @@ def test_host_validation(L):
     sz = EbSizes()
     P = ctypes.c_void_p
     fake = P(256)  # never dereferenced: validation fails first
-    rc = L.eb_build_edges(4, 10, 10, fake, fake, fake, fake, fake, 10 ** 6,
+    rc = L.eb_build_edges(5, 10, 10, fake, fake, fake, fake, fake, 10 ** 6,
                           ctypes.byref(sz), None)
     assert rc == -1
     rc = L.eb_build_edges(3, 10, 2 ** 30, fake, fake, fake, fake, fake, 10 ** 6,

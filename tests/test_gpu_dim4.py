@@ -1,0 +1,160 @@
+"""Pentatope grids (dim 4) on the GPU against the oracle's 4D construction.
+
+The paper derives the efficient formula for general D (Section 3.2.3) and
+leaves D = 4 to future work, printing no 4D value; the oracle's 4D median
+dual is pinned by the geometry instead (tests/test_oracle_pins.py: a
+hand-worked pentatope, the per-element finite-element identity, closure,
+total volume and boundary area of the 4-cube, counts, Euler's relation).
+Topology bit-exact; n, b, V to the same relative 1e-12 per entry as in 2D
+and 3D.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+import oracle
+from tests.test_gpu_parity import assert_vec_close, assert_vol_close
+
+pytestmark = pytest.mark.gpu
+
+TOPO_NAMES = ("edge", "node_edge_off", "elem_edge", "elem_edge_sign", "edge_inc_off",
+              "edge_inc", "node_inc_off", "node_inc", "node_in_off", "node_in_edge",
+              "bface", "bface_owner", "bface_edge", "bnode", "node_bnode",
+              "bnode_face_off", "bnode_face")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def shuffled(mesh, seed):
+    rng = np.random.default_rng(seed)
+    E = mesh.elems.copy()
+    for i in range(E.shape[0]):
+        E[i] = E[i, rng.permutation(5)]
+    return meshgen.Mesh(4, mesh.coords, np.ascontiguousarray(E), mesh.name + "-shuf")
+
+
+def relabelled(mesh, seed):
+    lab = np.random.default_rng(seed).permutation(mesh.n_nodes).astype(np.int32)
+    X = np.empty_like(mesh.coords)
+    X[:, lab] = mesh.coords
+    return meshgen.Mesh(4, X, np.ascontiguousarray(lab[mesh.elems]), mesh.name + "-relab")
+
+
+def single():
+    X = np.concatenate([np.zeros((4, 1)), np.eye(4)], axis=1)
+    return meshgen.Mesh(4, X, np.array([[3, 0, 4, 2, 1]], np.int32), "pent")
+
+
+CASES = {
+    "4d-single": single,
+    "4d-5": lambda: meshgen.hypercube_kuhn(5, 0),
+    "4d-9": lambda: meshgen.hypercube_kuhn(9, 1),
+    "4d-7-shuf": lambda: shuffled(meshgen.hypercube_kuhn(7, 2), 3),
+    "4d-6-relabel": lambda: relabelled(meshgen.hypercube_kuhn(6, 4), 5),
+}
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        m = CASES[name]()
+        ot = oracle.topology(4, m.coords, m.elems)
+        _cache[name] = (m, ot) + oracle.metrics(ot, m.coords, m.elems)
+    return _cache[name]
+
+
+def dev(m):
+    return (torch.from_numpy(np.ascontiguousarray(m.coords)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(m.elems)).cuda())
+
+
+def scales(ot, coords, elems):
+    npc, _ = oracle.element_pieces(4, coords, elems)
+    S_e = np.bincount(ot["elem_edge"].reshape(-1), weights=np.linalg.norm(npc, axis=2).reshape(-1),
+                      minlength=ot.n_edges)
+    # boundary pieces: |n_B|/4 per face at each of its nodes
+    P = coords[:, ot["bface"]]  # [4, NB, 4]
+    u, v, w = (P[:, :, k] - P[:, :, 0] for k in (1, 2, 3))
+    M = np.stack([u.T, v.T, w.T], axis=1)  # [NB, 3, 4]
+    area = np.zeros(ot.n_bfaces)
+    for c in range(4):
+        cols = [k for k in range(4) if k != c]
+        area += np.linalg.det(M[:, :, cols]) ** 2
+    area = np.sqrt(area) / 6.0
+    S_b = np.zeros(ot.n_bnodes)
+    for s in range(4):
+        S_b += np.bincount(ot["node_bnode"][ot["bface"][:, s]], weights=area / 4, minlength=ot.n_bnodes)
+    return S_e, S_b
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_dim4_topology_bit_exact(name):
+    import paper_2502_00778_amd as eb
+    m, ot, *_ = case(name)
+    say(f"[4d topology] {name}: {m.n_elems} pentatopes")
+    X, E = dev(m)
+    gt = eb.build_edges(E, X)
+    assert (gt.n_edges, gt.n_bfaces, gt.n_bnodes) == (ot.n_edges, ot.n_bfaces, ot.n_bnodes)
+    g = gt.to_numpy()
+    for k in TOPO_NAMES:
+        a, b = g[k].reshape(-1), ot[k].reshape(-1)
+        assert a.shape == b.shape and np.array_equal(a, b), k
+
+
+@pytest.mark.parametrize("reduce", ["gather", "atomic"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_dim4_metrics_parity(name, reduce):
+    import paper_2502_00778_amd as eb
+    m, ot, n0, b0, V0 = case(name)
+    say(f"[4d metrics] {name} {reduce}")
+    X, E = dev(m)
+    gt = eb.build_edges(E, X)
+    n, b, V = eb.directed_areas(X, gt, E, reduce=reduce)
+    eb.check_errors(gt)
+    S_e, S_b = scales(ot, m.coords, m.elems)
+    assert_vec_close(n.cpu().numpy(), n0, S_e, "n")
+    assert_vec_close(b.cpu().numpy(), b0, S_b, "b")
+    assert_vol_close(V.cpu().numpy(), V0, "V")
+    for mode in ("element", "edge"):
+        Vm = eb.dual_volumes(X, gt, E, mode=mode, n=n, reduce=reduce)
+        assert_vol_close(Vm.cpu().numpy(), V0, f"V {mode}")
+
+
+def test_dim4_gather_reproducible_and_closure():
+    import paper_2502_00778_amd as eb
+    m, ot, *_ = case("4d-9")
+    X, E = dev(m)
+    gt = eb.build_edges(E, X)
+    r1 = [t.clone() for t in eb.directed_areas(X, gt, E, "gather")]
+    r2 = eb.directed_areas(X, gt, E, "gather")
+    for a, b in zip(r1, r2):
+        assert torch.equal(a, b)
+    n, b, V = (t.cpu().numpy() for t in r1)
+    a = np.zeros((4, m.n_nodes))
+    for c in range(4):
+        np.add.at(a[c], ot["edge"][0], n[c])
+        np.add.at(a[c], ot["edge"][1], -n[c])
+        np.add.at(a[c], ot["bnode"], b[c])
+    assert np.abs(a).max() < 1e-14 * np.abs(n).max()
+    assert abs(V.sum() - 1.0) < 1e-13
+
+
+def test_dim4_unsupported_calls_refused():
+    import paper_2502_00778_amd as eb
+    m, ot, *_ = case("4d-5")
+    X, E = dev(m)
+    gt = eb.build_edges(E, X)
+    w = torch.zeros(4, gt.n_edges, dtype=torch.float64, device="cuda")
+    with pytest.raises(eb.EbError) as e:
+        eb.directed_areas_backward(X, gt, E, w, None, None)
+    assert e.value.code == -1
+    with pytest.raises(eb.EbError):
+        eb.directed_areas_variant(X, gt, E, "edge_normals")

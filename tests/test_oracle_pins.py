@@ -270,13 +270,16 @@ def _brute_csrs(dim, nv, elems, X):
             d = P[1] - P[0]
             out_ok = d[1] * (P[0][0] - xo[0]) - d[0] * (P[0][1] - xo[1]) > 0
             v = list(k) if out_ok else [k[1], k[0]]
-        else:
+        elif dim == 3:
             c = np.cross(P[1] - P[0], P[2] - P[0])
             v = list(k) if c @ (P[0] - xo) > 0 else [k[0], k[2], k[1]]
+        else:  # the sign of det[a - xo; b - a; c - a; d - a]
+            s4 = np.linalg.det(np.stack([P[0] - xo, P[1] - P[0], P[2] - P[0], P[3] - P[0]]))
+            v = list(k) if s4 > 0 else [k[0], k[1], k[3], k[2]]
         bface.append(v)
         owner.append(i * nn + f)
     out["bface"], out["bface_owner"] = bface, owner
-    fp = [(0, 1)] if dim == 2 else [(0, 1), (0, 2), (1, 2)]
+    fp = [(0, 1)] if dim == 2 else list(combinations(range(dim), 2))
     out["bface_edge"] = [[eid[tuple(sorted((f[p], f[q])))] for p, q in fp] for f in bface]
     bnode = sorted({v for f in bface for v in f})
     out["bnode"] = bnode
@@ -294,7 +297,8 @@ def _fan(k):
     return X, np.array([[0, 1 + i, 1 + (i + 1) % k] for i in range(k)], np.int32)
 
 
-@pytest.mark.parametrize("case", ["3d-kuhn-shuf", "2d-tri-shuf", "2d-fan", "3d-relabel"])
+@pytest.mark.parametrize("case", ["3d-kuhn-shuf", "2d-tri-shuf", "2d-fan", "3d-relabel",
+                                  "4d-kuhn-shuf"])
 def test_topology_arrays_brute(case):
     """Every array the oracle's sort-based topology produces, bface_edge and
     the in-edge lists included, equals the plain-loop statement of its
@@ -308,6 +312,9 @@ def test_topology_arrays_brute(case):
         dim, X, E = 2, m.coords, shuffle_local(m.elems, 5)
     elif case == "2d-fan":
         dim, (X, E) = 2, _fan(9)
+    elif case == "4d-kuhn-shuf":
+        m = meshgen.hypercube_kuhn(3, 1)
+        dim, X, E = 4, m.coords, shuffle_local(m.elems, 6)
     else:
         m = meshgen.cube_kuhn(3, 0)
         lab = np.random.default_rng(4).permutation(m.n_nodes)
@@ -519,7 +526,7 @@ def test_errors():
         oracle.topology(3, X5, E)
     assert e.value.code == -4
     with pytest.raises(oracle.OracleError) as e:
-        oracle.topology(4, X, np.array([[0, 1, 2, 3]]))
+        oracle.topology(5, X, np.array([[0, 1, 2, 3, 0, 1]]))
     assert e.value.code == -1
 
 
@@ -584,3 +591,109 @@ def test_grad_volume_interior_zero():
     inner = meshgen._interior_mask_3d(5)
     assert np.abs(g[inner]).max() < 1e-15
     assert np.abs(g[~inner]).max() > 1e-3
+
+
+# ------------------------------------------------ four dimensions (D = 4)
+#
+# The paper derives the efficient formula for general D (Section 3.2.3) and
+# leaves D = 4 to future work; it gives no 4D value to compare with.  The
+# oracle's 4D construction (barycentric subdivision of each pentatope) is
+# pinned here by what the geometry fixes: a hand-worked single pentatope,
+# the finite-element identity per element, closure at every node, the total
+# volume and boundary area of the unit 4-cube, unjittered interior volumes,
+# closed-form counts, Euler's relation and brute-force topology.
+
+def _face_normals_4d(P):
+    """Outward area vectors n_i of the faces of pentatopes P [NE, 5, 4]
+    (numpy, independent of the oracle): (1/6) N(b-a, c-a, d-a) of the face
+    opposite i, with N(u,v,w).x = det[x; u; v; w], oriented away from
+    vertex i."""
+    NE = P.shape[0]
+    n = np.empty((NE, 5, 4))
+    eye = np.eye(4)
+    for i in range(5):
+        o = [r for r in range(5) if r != i]
+        u, v, w = (P[:, o[k]] - P[:, o[0]] for k in (1, 2, 3))
+        N = np.stack([np.linalg.det(np.stack([np.broadcast_to(eye[c], u.shape), u, v, w], axis=1))
+                      for c in range(4)], axis=1) / 6.0
+        sgn = np.sign(np.einsum("ec,ec->e", N, P[:, o[0]] - P[:, i]))
+        n[:, i] = N * sgn[:, None]
+    return n
+
+
+def test_4d_single_pentatope_closed_form():
+    """Unit pentatope {0, e1, e2, e3, e4}: outward face vectors n_0 =
+    (1,1,1,1)/6, n_i = -e_i/6; every face is a boundary face, so the edge
+    (j,k), j < k, gets n_j/10 from the element and -(n_j + n_k)/20 from the
+    three boundary faces holding it: (n_j - n_k)/20; V_i = (1/24)/5; b_j =
+    (1/4) sum of the four faces at j = -n_j/4.  Any local order."""
+    X = np.concatenate([np.zeros((4, 1)), np.eye(4)], axis=1)
+    nf = np.concatenate([np.full((4, 1), 1 / 6), -np.eye(4) / 6], axis=1)  # [4, 5]
+    for perm in ([0, 1, 2, 3, 4], [3, 0, 4, 2, 1], [1, 0, 2, 3, 4]):
+        E = np.array([perm], np.int32)
+        t, n, b, V = run(4, X, E)
+        assert t.n_edges == 10 and t.n_bfaces == 5 and t.n_bnodes == 5
+        for e in range(10):
+            j, k = t["edge"][:, e]
+            np.testing.assert_allclose(n[:, e], (nf[:, j] - nf[:, k]) / 20, atol=1e-16)
+        np.testing.assert_allclose(V, np.full(5, 1 / 120), rtol=1e-14)
+        np.testing.assert_allclose(b[:, t["node_bnode"]], -nf / 4, atol=1e-16)
+
+
+def test_4d_fe_identity_per_element():
+    """Each element's dual-face pieces equal (n_j^E - n_k^E)/20 (tail j) and
+    each vertex's sub-cell |E|/5, with n^E and |E| from numpy determinants."""
+    m = meshgen.hypercube_kuhn(4, 2)
+    E = shuffle_local(m.elems, 11)
+    npc, vpc = oracle.element_pieces(4, m.coords, E)
+    P = m.coords.T[E]  # [NE, 5, 4]
+    nf = _face_normals_4d(P)
+    vol = np.abs(np.linalg.det(P[:, 1:] - P[:, :1])) / 24.0
+    pairs = list(combinations(range(5), 2))
+    for le, (p, q) in enumerate(pairs):
+        tail_p = E[:, p] < E[:, q]
+        ref = np.where(tail_p[:, None], nf[:, p] - nf[:, q], nf[:, q] - nf[:, p]) / 20.0
+        np.testing.assert_allclose(npc[:, le], ref, atol=1e-15 * np.abs(ref).max())
+    np.testing.assert_allclose(vpc, np.repeat(vol[:, None] / 5, 5, axis=1), rtol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_4d_closure_volume_boundary(seed):
+    """Jittered 4-cube: closure at every node (Section 3.2.3), total volume
+    1, and per axis the boundary normals' positive parts sum to the area 1
+    of the facet x_a = 1 and their negative parts to -1."""
+    m = meshgen.hypercube_kuhn(5, seed)
+    t, n, b, V = run(4, m.coords, m.elems)
+    a = closure(t, n, b)
+    assert np.abs(a).max() < 1e-15
+    assert abs(V.sum() - 1.0) < 1e-14
+    for ax in range(4):
+        assert abs(np.clip(b[ax], 0, None).sum() - 1.0) < 1e-14
+        assert abs(np.clip(b[ax], None, 0).sum() + 1.0) < 1e-14
+
+
+def test_4d_unjittered_interior_volume():
+    """Unjittered grid: every interior node's dual cell is one cell, h^4."""
+    n = 5
+    m = meshgen.hypercube_kuhn(n, 0, jitter=0.0)
+    t, _, _, V = run(4, m.coords, m.elems)
+    a = np.arange(n)
+    l, k, j, i = np.meshgrid(a, a, a, a, indexing="ij")
+    inner = ((i > 0) & (i < n - 1) & (j > 0) & (j < n - 1) & (k > 0) & (k < n - 1)
+             & (l > 0) & (l < n - 1)).reshape(-1)
+    np.testing.assert_allclose(V[inner], (1 / (n - 1)) ** 4, rtol=1e-13)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_4d_counts_and_euler(n):
+    """Closed-form counts of the split, and V - E + F - T + P = 1 for the
+    4-ball (triangles and tetrahedra counted by brute force)."""
+    m = meshgen.hypercube_kuhn(n, 0)
+    t = oracle.topology(4, m.coords, m.elems)
+    cnt = meshgen.kuhn4_counts(n)
+    assert (t.n_nodes, t.n_elems, t.n_edges, t.n_bfaces, t.n_bnodes) == (
+        cnt["n_nodes"], cnt["n_elems"], cnt["n_edges"], cnt["n_bfaces"], cnt["n_bnodes"])
+    tris = {tuple(sorted(c)) for el in m.elems.tolist() for c in combinations(el, 3)}
+    tets = {tuple(sorted(c)) for el in m.elems.tolist() for c in combinations(el, 4)}
+    assert t.n_nodes - t.n_edges + len(tris) - len(tets) + t.n_elems == 1
+    assert len(tets) == (5 * t.n_elems + t.n_bfaces) // 2
