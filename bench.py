@@ -5,8 +5,10 @@ One step = the whole hot path over the 161^3 stretched Kuhn grid
 (24,576,000 tets): edge extraction and boundary elements (eb_build_edges +
 eb_build_edges_emit), the fused forward pass n, b, V (eb_directed_areas,
 deterministic gather), the edge-loop dual volumes (eb_dual_volumes EDGE) and
-the adjoint dL/dx (eb_directed_areas_backward).  Inputs are resident in HBM
-before the timed region.  Prints one JSON line.
+the adjoint dL/dx (eb_directed_areas_backward; FP64 atomics after per-block
+sums in LDS by default, the faster of the two reductions here, or the
+deterministic gather with --bwd-reduce gather; both are timed as phases).
+Inputs are resident in HBM before the timed region.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -264,6 +266,9 @@ def bench_batched(torch, eb, meshgen, seed, reps, tm):
     eb.set_fused_mode("separate")    # the gather kernels one after another
     fused()
     t_sep = tm.time(fused, reps)
+    eb.set_fused_mode("persistent_atomic")  # one persistent launch, atomic adjoint
+    fused()
+    t_atomic = tm.time(fused, reps)
     eb.set_fused_mode(tuned_mode)
     gr = eb.ForwardBackwardGraph(X, topo, E, W, B, C)
     gr.launch()
@@ -300,6 +305,7 @@ def bench_batched(torch, eb, meshgen, seed, reps, tm):
         "persistent_ms": round(t_fused[0], 4),
         "persistent_kernel_ms": round(k_fused[0], 4),
         "separate_kernels_ms": round(t_sep[0], 4),
+        "persistent_atomic_ms": round(t_atomic[0], 4),
         "tuned_mode": tuned_mode,
         "graph_ms": round(t_graph[0], 4),
         "per_mesh_plain_ms": round(t_plain[0], 4),
@@ -454,6 +460,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-deforming", action="store_true")
     ap.add_argument("--no-2d", action="store_true")
+    ap.add_argument("--bwd-reduce", default="atomic", choices=("atomic", "gather"),
+                    help="the adjoint's reduction in the timed step (both are timed as phases)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -489,7 +497,7 @@ def main():
     V = torch.empty(nv, dtype=torch.float64, device="cuda")
     Ve = torch.empty(nv, dtype=torch.float64, device="cuda")
     g = torch.empty(dim, nv, dtype=torch.float64, device="cuda")
-    bwd_reduce = "gather"
+    bwd_reduce = args.bwd_reduce
 
     def ph_topo():
         eb.build_edges(E, X, edge_inc=False)
@@ -504,7 +512,7 @@ def main():
         eb.dual_volumes(X, topo, E, "edge", n=n, reduce="gather", out=Ve)
 
     def ph_bwd():
-        eb.directed_areas_backward(X, topo, E, W, B, C, reduce=bwd_reduce, out=g)
+        eb.directed_areas_backward(X, topo, E, W, B, C, reduce="gather", out=g)
 
     def ph_bwd_atomic():
         eb.directed_areas_backward(X, topo, E, W, B, C, reduce="atomic", out=g)
@@ -514,6 +522,13 @@ def main():
     def ph_fused():
         eb.forward_backward(X, topo, E, W, B, C, out=fouts)
 
+    def ph_fused_atomic():
+        eb.set_fused_mode("persistent_atomic")
+        try:
+            eb.forward_backward(X, topo, E, W, B, C, out=fouts)
+        finally:
+            eb.set_fused_mode("persistent")
+
     def ph_fwd_edge_normals():
         eb.directed_areas_variant(X, topo, E, "edge_normals", n_out=n, b_out=b, v_out=V)
 
@@ -522,7 +537,8 @@ def main():
 
     phases = {"topo": ph_topo, "fwd": ph_fwd, "fwd_atomic": ph_fwd_atomic,
               "vol_edge": ph_vol_edge, "bwd": ph_bwd, "bwd_atomic": ph_bwd_atomic,
-              "fused": ph_fused, "fwd_edge_normals": ph_fwd_edge_normals,
+              "fused": ph_fused, "fused_atomic": ph_fused_atomic,
+              "fwd_edge_normals": ph_fwd_edge_normals,
               "fwd_dual_faces": ph_fwd_dual_faces}
 
     if args.only:
@@ -566,7 +582,7 @@ def main():
         log(f"[bench] phase {name}: mean {res[name][0]:.3f} ms, median {res[name][1]:.3f}, "
             f"min {res[name][2]:.3f}")
     kern = {}
-    for name in ("fwd", "fwd_atomic", "vol_edge", "bwd", "bwd_atomic", "fused",
+    for name in ("fwd", "fwd_atomic", "vol_edge", "bwd", "bwd_atomic", "fused", "fused_atomic",
                  "fwd_edge_normals", "fwd_dual_faces"):
         kern[name] = tm.time_principal(eb, phases[name], args.phase_reps)
         log(f"[bench] principal kernel of {name}: mean {kern[name][0]:.4f} ms, "
@@ -657,9 +673,11 @@ def main():
             "forward_gather": ph("fwd", bf),
             "forward_atomic": ph("fwd_atomic", bf),
             "edge_volume_gather": ph("vol_edge", bv),
-            f"adjoint_{bwd_reduce}": ph("bwd", bb_),
+            "adjoint_gather": ph("bwd", bb_),
             "adjoint_atomic": ph("bwd_atomic", bb_),
             "fused_forward_adjoint": ph("fused", alg_bytes_fused(dim, nv, nel, ne_, nb, nbn)),
+            "fused_forward_adjoint_atomic": ph("fused_atomic",
+                                               alg_bytes_fused(dim, nv, nel, ne_, nb, nbn)),
             "forward_edge_normals": ph("fwd_edge_normals", bf),
             "forward_dual_faces": ph("fwd_dual_faces", bf),
         },

@@ -370,12 +370,14 @@ int eb_batch_offsets(const eb_sizes *sizes, const eb_topology *topo, const int32
  * with EB_REDUCE_GATHER, and grad_coords as eb_directed_areas_backward with
  * EB_REDUCE_GATHER, for the loss weights grad_n / grad_b / grad_vol (any may
  * be NULL = zero; the loss is linear, so its adjoint needs no forward
- * output).  One persistent kernel takes work items from a counter in ws:
- * forward node tiles and adjoint element tiles, then forward boundary and
- * adjoint node tiles, then adjoint boundary tiles; a block entering a later
- * phase waits (bounded, EB_ETIMEOUT) for the earlier one.  A small reset
- * kernel runs first, so the enqueue is two kernels and no memset (safe to
- * capture in a graph).  Same bits as the two separate gather calls up to
+ * output).  One persistent kernel, no larger than the grid that is resident
+ * at once, runs three phases (forward node tiles and adjoint element tiles,
+ * then forward boundary and adjoint node tiles, then adjoint boundary
+ * tiles), block b taking items b, b + grid, ... of each; a block with work
+ * in a later phase waits (bounded, EB_ETIMEOUT) until every block has
+ * finished the earlier one (counters in ws).  A small reset kernel runs
+ * first, so the enqueue is two kernels and no memset (safe to capture in a
+ * graph).  Same bits as the two separate gather calls up to
  * floating-point contraction; bitwise reproducible for any launch shape.
  * Needs everything both gather calls need, including ws_bytes >=
  * eb_backward_workspace_bytes(sizes).  Calls on one ws must not overlap. */
@@ -410,9 +412,20 @@ void eb_get_fused_shape(int *tile, int *unroll, int *blocks_per_cu);
  * persistent kernel described there; EB_FUSED_SEPARATE the gather forward
  * and the gather adjoint kernels one after the other (same results up to
  * rounding, also capturable; faster where the persistent kernel's shared
- * occupancy limit costs more than the launches it saves).  Process-wide;
- * eb_autotune picks it. */
-typedef enum { EB_FUSED_PERSISTENT = 0, EB_FUSED_SEPARATE = 1 } eb_fused_mode;
+ * occupancy limit costs more than the launches it saves);
+ * EB_FUSED_PERSISTENT_ATOMIC one persistent kernel whose adjoint sums with
+ * FP64 atomics after per-block sums in LDS, as eb_directed_areas_backward's
+ * EB_REDUCE_ATOMIC (two phases: forward node tiles with the adjoint's
+ * element and boundary blocks, then forward boundary tiles; a fill kernel
+ * zeroes grad_coords first): n, b and V as in the other modes, grad_coords
+ * equal to rounding but not bitwise reproducible.  Process-wide;
+ * eb_autotune picks between the first two, or, when the third is in force,
+ * tunes its shape and keeps it. */
+typedef enum {
+  EB_FUSED_PERSISTENT = 0,
+  EB_FUSED_SEPARATE = 1,
+  EB_FUSED_PERSISTENT_ATOMIC = 2
+} eb_fused_mode;
 int eb_set_fused_mode(int mode);
 int eb_get_fused_mode(void);
 
@@ -426,8 +439,12 @@ int eb_set_fused_wait_limit(int64_t spins);
  * xcd_remap) and every fused shape of eb_batch_forward_backward (tile x
  * unroll x blocks_per_cu in {1,2,4,8,0}) and EB_FUSED_SEPARATE on the
  * caller's grid and buffers, sets the fastest of each (eb_set_gather_shape,
- * eb_set_fused_shape, eb_set_fused_mode) and reports them.  Outputs hold valid results afterwards (all shapes give the
- * same bits).  Synchronizes `stream`. */
+ * eb_set_fused_shape, eb_set_fused_mode) and reports them.  With
+ * EB_FUSED_PERSISTENT_ATOMIC in force it times that kernel's shapes instead
+ * of the gather persistent kernel's, keeps the mode and does not time
+ * EB_FUSED_SEPARATE (separate_ms 0).  Outputs hold valid results afterwards
+ * (all shapes give the same bits, but for the atomic mode's grad_coords).
+ * Synchronizes `stream`. */
 typedef struct {
   int32_t gather_tile, gather_unroll, gather_xcd_remap;
   float gather_ms;

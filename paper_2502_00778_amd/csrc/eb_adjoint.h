@@ -264,4 +264,63 @@ __device__ __forceinline__ void bwd_boundary_node(const FwdArgs &a, int64_t bj) 
   if (D == 3) a.g_z[j] += g.z;
 }
 
+// Elements [blk * TB * EPT, (blk + 1) * TB * EPT) by a block of TB threads:
+// dL_E/dx_i for each vertex, summed per node in the LDS table T (barriers
+// inside: the whole block calls it) and added to the zeroed gradient with
+// one FP64 atomic per distinct node and component.
+template <int D, int TB, int EPT_, int H>
+__device__ __forceinline__ void bwd_atomic_elem_block(const FwdArgs &a, int64_t blk,
+                                                      LdsAcc<H, D> &T) {
+  const int t = threadIdx.x;
+  double *const gout[3] = {a.g_x, a.g_y, a.g_z};
+  lds_acc_init<TB>(T, t);
+  __syncthreads();
+  const int64_t e0 = blk * TB * EPT_;
+#pragma unroll
+  for (int k = 0; k < EPT_; ++k) {
+    const int64_t e = e0 + (int64_t)k * TB + t;
+    if (e >= a.nelem) break;
+    int32_t v[D + 1];
+    load_conn<D>(a.elem, e, v);
+    V3 P[D + 1], n[D + 1], W[D + 1];
+#pragma unroll
+    for (int i = 0; i <= D; ++i) P[i] = load_pt<D>(a.X, v[i]);
+    const double det = elem_normals<D>(P, n);
+    double C;
+    elem_weights<D>(a, e, v, W, C);
+    V3 G[D + 1];
+    elem_grad_all<D>(P, n, det, W, C, G);
+#pragma unroll
+    for (int l = 0; l <= D; ++l) {
+      double c[D];
+      c[0] = G[l].x;
+      c[1] = G[l].y;
+      if constexpr (D == 3) c[D - 1] = G[l].z;
+      lds_acc_add(T, gout, v[l], c);
+    }
+  }
+  __syncthreads();
+  lds_acc_flush<TB>(T, gout, t);
+}
+
+// One boundary face's adjoint terms, added with FP64 atomics.
+template <int D>
+__device__ __forceinline__ void bwd_atomic_bface_one(const FwdArgs &a, int64_t f) {
+  int32_t fv[D];
+  V3 P[D];
+#pragma unroll
+  for (int s = 0; s < D; ++s) {
+    fv[s] = a.bface[f * D + s];
+    P[s] = load_pt<D>(a.X, fv[s]);
+  }
+  V3 G[D];
+  bface_grad_all<D>(P, bface_weight<D>(a, f, fv), G);
+#pragma unroll
+  for (int p = 0; p < D; ++p) {
+    unsafeAtomicAdd(&a.g_x[fv[p]], G[p].x);
+    unsafeAtomicAdd(&a.g_y[fv[p]], G[p].y);
+    if (D == 3) unsafeAtomicAdd(&a.g_z[fv[p]], G[p].z);
+  }
+}
+
 }  // namespace eb

@@ -7,61 +7,17 @@ namespace eb {
 
 // One thread per element: dL_E/dx_i for each vertex, summed per node in the
 // block's LDS table and added to the zeroed gradient with one FP64 atomic
-// per distinct node and component.
+// per distinct node and component (eb_adjoint.h).
 template <int D>
 __global__ __launch_bounds__(ATOMIC_TB) void k_bwd_atomic_elem(FwdArgs a) {
   __shared__ LdsAcc<ATOMIC_HV, D> tg;
-  const int t = threadIdx.x;
-  double *const gout[3] = {a.g_x, a.g_y, a.g_z};
-  lds_acc_init<ATOMIC_TB>(tg, t);
-  __syncthreads();
-  const int64_t e0 = (int64_t)blockIdx.x * ATOMIC_TB * ATOMIC_EPT;
-#pragma unroll
-  for (int k = 0; k < ATOMIC_EPT; ++k) {
-    const int64_t e = e0 + (int64_t)k * ATOMIC_TB + t;
-    if (e >= a.nelem) break;
-    int32_t v[D + 1];
-    load_conn<D>(a.elem, e, v);
-    V3 P[D + 1], n[D + 1], W[D + 1];
-#pragma unroll
-    for (int i = 0; i <= D; ++i) P[i] = load_pt<D>(a.X, v[i]);
-    const double det = elem_normals<D>(P, n);
-    double C;
-    elem_weights<D>(a, e, v, W, C);
-    V3 G[D + 1];
-    elem_grad_all<D>(P, n, det, W, C, G);
-#pragma unroll
-    for (int l = 0; l <= D; ++l) {
-      double c[D];
-      c[0] = G[l].x;
-      c[1] = G[l].y;
-      if constexpr (D == 3) c[D - 1] = G[l].z;
-      lds_acc_add(tg, gout, v[l], c);
-    }
-  }
-  __syncthreads();
-  lds_acc_flush<ATOMIC_TB>(tg, gout, t);
+  bwd_atomic_elem_block<D, ATOMIC_TB, ATOMIC_EPT>(a, blockIdx.x, tg);
 }
 
 template <int D>
 __global__ __launch_bounds__(256) void k_bwd_atomic_bface(FwdArgs a) {
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= a.nbface) return;
-  int32_t fv[D];
-  V3 P[D];
-#pragma unroll
-  for (int s = 0; s < D; ++s) {
-    fv[s] = a.bface[f * D + s];
-    P[s] = load_pt<D>(a.X, fv[s]);
-  }
-  V3 G[D];
-  bface_grad_all<D>(P, bface_weight<D>(a, f, fv), G);
-#pragma unroll
-  for (int p = 0; p < D; ++p) {
-    unsafeAtomicAdd(&a.g_x[fv[p]], G[p].x);
-    unsafeAtomicAdd(&a.g_y[fv[p]], G[p].y);
-    if (D == 3) unsafeAtomicAdd(&a.g_z[fv[p]], G[p].z);
-  }
+  if (f < a.nbface) bwd_atomic_bface_one<D>(a, f);
 }
 
 // ------------------------------------------------------------- gather path

@@ -9,14 +9,22 @@
 //
 // The fused kernel runs the deterministic forward (n, b, V) and the gather
 // adjoint (dL/dx for a loss linear in n, b, V, whose weights do not depend on
-// the forward outputs) as one stream of work items taken from a counter:
+// the forward outputs) as phases of one persistent launch:
 //   phase 0: forward node tiles, interleaved with adjoint element-piece tiles
 //   phase 1: forward boundary tiles, interleaved with adjoint node tiles
 //   phase 2: adjoint boundary tiles
-// A block that takes its first item of a later phase waits (bounded) until
-// every item of the earlier phase is complete.  Items are handed out in
-// increasing order, so every earlier item was already taken by a running
-// block that waits on nothing later: the waits always end.
+// With the adjoint's FP64 atomics instead (EB_FUSED_PERSISTENT_ATOMIC) the
+// adjoint needs no second pass and nothing of the forward:
+//   phase 0: forward node tiles, interleaved with adjoint element blocks
+//            (per-node sums in LDS, then atomics) and boundary-face blocks
+//   phase 1: forward boundary tiles
+// Block b of a grid of G takes items b, b + G, b + 2G, ... of each phase
+// (a fixed assignment: a shared work counter costs one same-address device
+// atomic per item, which serializes at about 10 ns each).  At the end of a
+// phase every block publishes (one counted release per block), and a block
+// with work in a later phase waits, bounded, until all G blocks have
+// published.  The grid never exceeds what is resident at once (occupancy x
+// compute units), so every block it waits for is running and the waits end.
 #include <hip/hip_runtime.h>
 
 #include "eb_adjoint.h"
@@ -32,6 +40,7 @@ int64_t g_spin_limit = kDefaultSpinLimit;
 struct FusedPlan {
   int64_t nF, nP, nB, nG, nH;  // item counts of each kind
   int64_t spin_limit;
+  int64_t nQ;                  // (atomic adjoint) boundary-face blocks
 };
 
 __global__ void k_fused_reset(StatusBlock *st) {
@@ -50,86 +59,109 @@ __device__ __forceinline__ bool first_kind(int64_t k, int64_t nX, int64_t nXY, i
   return false;
 }
 
+// End of a phase for the calling block: publish its writes of the phase
+// (every wave's stores visible on all XCDs, then one counted release by
+// thread 0) and, when the block has work in a later phase, wait until all
+// blocks of the grid have published.  False (in every thread) when the wait
+// ran out of polls: EB_ETIMEOUT is recorded and the block must exit.
+__device__ __forceinline__ bool phase_end(StatusBlock *st, uint32_t *ctr, bool wait,
+                                          int64_t spin_limit) {
+  __shared__ int s_stop;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int stop = 0;
+    if (wait) {
+      int64_t spins = 0;
+      while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x) {
+        __builtin_amdgcn_s_sleep(8);
+        if (++spins > spin_limit) {
+          raise_status(st, EB_ETIMEOUT, blockIdx.x);
+          stop = 1;
+          break;
+        }
+      }
+    }
+    s_stop = stop;
+  }
+  __syncthreads();
+  if (s_stop) return false;
+  // see every write of the completed phase, made on any XCD
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return true;
+}
+
 template <int D, int TN, int CAP, int U, bool WIDE>
 __global__ __launch_bounds__(TN) void k_fused(FwdArgs a, FusedPlan p) {
   __shared__ double acc[D][CAP];
-  __shared__ int64_t s_item;
-  __shared__ int s_phase, s_stop;
-  uint32_t *const q = a.st->fq;  // q[0] next item; q[1 + ph] completed items of phase ph
+  uint32_t *const q = a.st->fq;  // q[ph]: blocks that have finished phase ph
   const int t = threadIdx.x;
-  const int64_t nA = p.nF + p.nP, nB = p.nB + p.nG, total = nA + nB + p.nH;
-  const uint32_t target[2] = {(uint32_t)nA, (uint32_t)nB};
-  int cur = 0;             // phase of this block's current items (same in every thread)
-  uint32_t done_here = 0;  // thread 0: items of phase cur this block has completed
-  int known = 0;           // thread 0: phases seen complete
-  for (;;) {
-    if (t == 0) {
-      const int64_t item =
-          __hip_atomic_fetch_add(&q[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_item = item;
-      s_phase = item >= total ? 3 : (item < nA ? 0 : (item < nA + nB ? 1 : 2));
-    }
-    __syncthreads();
-    const int64_t item = s_item;
-    const int ph = s_phase;
-    if (ph != cur) {
-      // Leaving phase cur: publish this block's completed items of it (every
-      // wave's writes made visible on all XCDs, then one counted release),
-      // then wait until every earlier phase is complete.
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __syncthreads();
-      if (t == 0) {
-        if (done_here)
-          __hip_atomic_fetch_add(&q[1 + cur], done_here, __ATOMIC_RELEASE,
-                                 __HIP_MEMORY_SCOPE_AGENT);
-        done_here = 0;
-        int stop = 0;
-        for (; ph < 3 && known < ph && !stop; ++known) {
-          int64_t spins = 0;
-          while (__hip_atomic_load(&q[1 + known], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                 target[known]) {
-            __builtin_amdgcn_s_sleep(8);
-            if (++spins > p.spin_limit) {
-              raise_status(a.st, EB_ETIMEOUT, item);
-              stop = 1;
-              break;
-            }
-          }
-        }
-        s_stop = stop;
-      }
-      __syncthreads();
-      if (ph == 3 || s_stop) break;
-      // see every write of the completed phases, made on any XCD
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      cur = ph;
-    }
+  const int64_t G = gridDim.x, b = blockIdx.x;
+  const int64_t nA = p.nF + p.nP, nB = p.nB + p.nG, nC = p.nH;
+  for (int64_t k = b; k < nA; k += G) {
     int64_t idx;
-    if (ph == 0) {
-      if (first_kind(item, p.nF, nA, idx)) {
-        fwd_node_tile<D, TN, CAP, U, WIDE>(a, idx, acc);
-      } else {
-        const int64_t e0 = idx * (int64_t)TN * EPT;
-#pragma unroll
-        for (int k = 0; k < EPT; ++k) {
-          const int64_t e = e0 + (int64_t)k * TN + t;
-          if (e < a.nelem) bwd_elem_piece<D>(a, e);
-        }
-      }
-    } else if (ph == 1) {
-      if (first_kind(item - nA, p.nB, nB, idx)) {
-        const int64_t bj = idx * TN + t;
-        if (bj < a.nbnode) fwd_boundary_node<D>(a, bj);
-      } else {
-        const int64_t j = idx * TN + t;
-        if (j < a.nv) bwd_node_sum<D>(a, j);
-      }
+    if (first_kind(k, p.nF, nA, idx)) {
+      fwd_node_tile<D, TN, CAP, U, WIDE, VAR_NODE, !WIDE>(a, idx, acc);
     } else {
-      const int64_t bj = (item - nA - nB) * TN + t;
-      if (bj < a.nbnode) bwd_boundary_node<D>(a, bj);
+      const int64_t e0 = idx * (int64_t)TN * EPT;
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) {
+        const int64_t e = e0 + (int64_t)m * TN + t;
+        if (e < a.nelem) bwd_elem_piece<D>(a, e);
+      }
     }
-    if (t == 0) ++done_here;
-    __syncthreads();  // the LDS accumulator and s_item are free again
+    __syncthreads();  // the LDS accumulator is free again
+  }
+  if (!phase_end(a.st, &q[0], b < nB || b < nC, p.spin_limit)) return;
+  for (int64_t k = b; k < nB; k += G) {
+    int64_t idx;
+    if (first_kind(k, p.nB, nB, idx)) {
+      const int64_t bj = idx * TN + t;
+      if (bj < a.nbnode) fwd_boundary_node<D>(a, bj);
+    } else {
+      const int64_t j = idx * TN + t;
+      if (j < a.nv) bwd_node_sum<D>(a, j);
+    }
+  }
+  if (!phase_end(a.st, &q[1], b < nC, p.spin_limit)) return;
+  for (int64_t k = b; k < nC; k += G) {
+    const int64_t bj = k * TN + t;
+    if (bj < a.nbnode) bwd_boundary_node<D>(a, bj);
+  }
+}
+
+// Elements per thread of an adjoint element item of the atomic form, and its
+// LDS node slots (two per element, as in the separate atomic kernel).
+constexpr int EPA = 2;
+
+template <int D, int TN, int CAP, int U, bool WIDE>
+__global__ __launch_bounds__(TN) void k_fused_atomic(FwdArgs a, FusedPlan p) {
+  constexpr int HA = 2 * TN * EPA;
+  __shared__ union {
+    double acc[D][CAP];    // forward node tile
+    LdsAcc<HA, D> tg;      // adjoint element block
+  } sm;
+  uint32_t *const q = a.st->fq;  // q[0]: blocks that have finished phase 0
+  const int t = threadIdx.x;
+  const int64_t G = gridDim.x, b = blockIdx.x;
+  const int64_t nR = p.nP + p.nQ, nA = p.nF + nR;
+  for (int64_t k = b; k < nA; k += G) {
+    int64_t idx;
+    if (first_kind(k, p.nF, nA, idx)) {
+      fwd_node_tile<D, TN, CAP, U, WIDE, VAR_NODE, !WIDE>(a, idx, sm.acc);
+    } else if (first_kind(idx, p.nP, nR, idx)) {
+      bwd_atomic_elem_block<D, TN, EPA>(a, idx, sm.tg);
+    } else {
+      const int64_t f = idx * TN + t;
+      if (f < a.nbface) bwd_atomic_bface_one<D>(a, f);
+    }
+    __syncthreads();  // the LDS is free again
+  }
+  if (!phase_end(a.st, &q[0], b < p.nB, p.spin_limit)) return;
+  for (int64_t k = b; k < p.nB; k += G) {
+    const int64_t bj = k * TN + t;
+    if (bj < a.nbnode) fwd_boundary_node<D>(a, bj);
   }
 }
 
@@ -154,11 +186,51 @@ int launch_fused_kernel(K kernel, int tn, const FwdArgs &a, const FusedPlan &p, 
   EB_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, tn, 0));
   if (occ <= 0) occ = 1;
   const int per_cu = blocks_per_cu > 0 ? std::min(blocks_per_cu, occ) : occ;
-  const int64_t total = p.nF + p.nP + p.nB + p.nG + p.nH;
+  const int64_t total = p.nF + p.nP + p.nB + p.nG + p.nH + p.nQ;
   const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(total, (int64_t)per_cu * num_cus()));
   launch_principal(kernel, dim3((unsigned)grid), dim3(tn), 0, s, a, p);
   EB_LAUNCH_CHECK();
   return EB_OK;
+}
+
+template <int D>
+int fused_atomic_impl(const FwdArgs &a, const FusedCfg &cfg, hipStream_t s) {
+  const int64_t tn = cfg.tile;
+  FusedPlan p{};
+  p.nF = (a.nv + tn - 1) / tn;
+  p.nP = (a.w_x || a.c) ? (a.nelem + tn * EPA - 1) / (tn * EPA) : 0;
+  p.nQ = (a.w_x || a.be_x) ? (a.nbface + tn - 1) / tn : 0;
+  p.nB = (a.nbnode + tn - 1) / tn;
+  p.spin_limit = g_spin_limit;
+  if (p.nF + p.nP + p.nQ + p.nB >= (int64_t)1 << 31) {
+    set_detail("too many work items for the fused kernel");
+    return EB_EOVERFLOW;
+  }
+  // the gradient is summed with atomics: zeroed first (a fill kernel, no
+  // memset node), with the work counters
+  EB_TRY(fill_f64(a.g_x, D * a.nv, 0.0, s));
+  hipLaunchKernelGGL(k_fused_reset, dim3(1), dim3(64), 0, s, a.st);
+  EB_LAUNCH_CHECK();
+#define EB_FUSED_CASE(TN_, CAP_, U_)                                                        \
+  if (cfg.tile == TN_ && cfg.unroll == U_) {                                                \
+    if (a.sell_wide)                                                                        \
+      return launch_fused_kernel(k_fused_atomic<D, TN_, CAP_, U_, true>, TN_, a, p,          \
+                                 cfg.blocks_per_cu, s);                                     \
+    return launch_fused_kernel(k_fused_atomic<D, TN_, CAP_, U_, false>, TN_, a, p,           \
+                               cfg.blocks_per_cu, s);                                       \
+  }
+  EB_FUSED_CASE(64, 512, 1)
+  EB_FUSED_CASE(64, 512, 2)
+  EB_FUSED_CASE(64, 512, 4)
+  EB_FUSED_CASE(128, 1024, 1)
+  EB_FUSED_CASE(128, 1024, 2)
+  EB_FUSED_CASE(128, 1024, 4)
+  EB_FUSED_CASE(256, 2048, 1)
+  EB_FUSED_CASE(256, 2048, 2)
+  EB_FUSED_CASE(256, 2048, 4)
+#undef EB_FUSED_CASE
+  set_detail("unsupported fused tile %d / unroll %d", cfg.tile, cfg.unroll);
+  return EB_EINVAL;
 }
 
 template <int D>
@@ -172,6 +244,7 @@ int fused_impl(const FwdArgs &a0, const FusedCfg &cfg, hipStream_t s) {
   }
   const FwdArgs &a = a0;
   const int64_t tn = cfg.tile;
+  if (cfg.atomic) return fused_atomic_impl<D>(a, cfg, s);
   FusedPlan p{};
   p.nF = (a.nv + tn - 1) / tn;
   p.nP = (a.nelem + tn * EPT - 1) / (tn * EPT);
@@ -470,17 +543,23 @@ void eb_get_fused_shape(int *tile, int *unroll, int *blocks_per_cu) {
 
 int eb_set_fused_mode(int mode) {
   clear_detail();
-  if (mode != EB_FUSED_PERSISTENT && mode != EB_FUSED_SEPARATE) {
-    set_detail("mode must be EB_FUSED_PERSISTENT or EB_FUSED_SEPARATE");
+  if (mode != EB_FUSED_PERSISTENT && mode != EB_FUSED_SEPARATE &&
+      mode != EB_FUSED_PERSISTENT_ATOMIC) {
+    set_detail("mode must be EB_FUSED_PERSISTENT, EB_FUSED_SEPARATE or "
+               "EB_FUSED_PERSISTENT_ATOMIC");
     return EB_EINVAL;
   }
   FusedCfg c = fused_cfg();
   c.separate = mode == EB_FUSED_SEPARATE;
+  c.atomic = mode == EB_FUSED_PERSISTENT_ATOMIC;
   set_fused_cfg(c);
   return EB_OK;
 }
 
-int eb_get_fused_mode(void) { return fused_cfg().separate ? EB_FUSED_SEPARATE : EB_FUSED_PERSISTENT; }
+int eb_get_fused_mode(void) {
+  const FusedCfg c = fused_cfg();
+  return c.separate ? EB_FUSED_SEPARATE : (c.atomic ? EB_FUSED_PERSISTENT_ATOMIC : EB_FUSED_PERSISTENT);
+}
 
 int eb_set_fused_wait_limit(int64_t spins) {
   clear_detail();
@@ -560,6 +639,7 @@ int eb_autotune(const eb_sizes *sizes, const eb_topology *topo, const int32_t *e
       for (int pi = 0; pi < 5 && rc == EB_OK; ++pi) {
         FusedCfg c;
         c.separate = 0;
+        c.atomic = f0.atomic;
         c.tile = tiles[ti];
         c.unroll = unrolls[ui];
         c.blocks_per_cu = per_cu[pi];
@@ -581,8 +661,9 @@ int eb_autotune(const eb_sizes *sizes, const eb_topology *topo, const int32_t *e
         }
       }
   // the gather kernels in sequence (with the best gather shape) as one more
-  // candidate for the whole enqueue
-  if (rc == EB_OK) {
+  // candidate for the whole enqueue (not when the caller chose the atomic
+  // persistent kernel, whose mode is kept)
+  if (rc == EB_OK && !f0.atomic) {
     LaunchCfg g;
     g.tile = best.gather_tile;
     g.unroll = best.gather_unroll;
@@ -620,10 +701,12 @@ int eb_autotune(const eb_sizes *sizes, const eb_topology *topo, const int32_t *e
   f.unroll = best.fused_unroll;
   f.blocks_per_cu = best.fused_blocks_per_cu;
   f.separate = best.fused_separate;
+  f.atomic = f0.atomic;
   set_fused_cfg(f);
   best.n_tried = tried;
   *out = best;
-  // leave the outputs as the chosen shape computes them (identical bits)
+  // leave the outputs as the chosen shape computes them (identical bits, but
+  // for grad_coords of the atomic mode)
   return eb_batch_forward_backward(sizes, topo, elem, coords, grad_n, grad_b, grad_vol, n_edge,
                                    b_node, vol, grad_coords, ws, ws_bytes, stream);
 }

@@ -20,7 +20,7 @@ struct StatusBlock {
   int32_t pad;
   int64_t detail;       // e.g. the offending element or node id
   int32_t totals[8];    // device-side totals of the last scans
-  uint32_t fq[4];       // fused kernel: item counter, completed items per phase
+  uint32_t fq[4];       // fused kernel: blocks that have finished each phase
   int32_t _reserved[48];
 };
 static_assert(sizeof(StatusBlock) == 256, "status block is 256 bytes");

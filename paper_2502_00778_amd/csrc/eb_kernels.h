@@ -67,6 +67,7 @@ struct FusedCfg {
   int unroll = 2;
   int blocks_per_cu = 0;
   int separate = 0;  // 1: the gather forward and adjoint kernels in sequence instead
+  int atomic = 0;    // 1: one persistent kernel with the adjoint's FP64 atomics
 };
 FusedCfg fused_cfg();
 void set_fused_cfg(const FusedCfg &c);
