@@ -38,6 +38,8 @@ constexpr int MAXH = NSET;                //   neighbours per node (registers)
 constexpr int MAXF = 64;                  //   candidate faces per node
 constexpr int MAXR = 32;                  //   incidences per node (emit ranking)
 constexpr int RB = 8;                     // row entries a thread reads at once
+constexpr int HT_LOG = 5;                 // count pass: hash slots per node
+constexpr int HT = 1 << HT_LOG;
 static_assert(MAXH * MAXH <= 0x8000, "face codes fit 15 bits");
 
 // ----------------------------------------------------- node incidences
@@ -366,6 +368,33 @@ struct RegSet {
   }
 };
 
+// Ascending sort of N values in registers by a bitonic network: merge
+// stage K (sorted runs of K/2 become runs of K), distance H; every index is
+// a compile-time constant (no indexed access).
+template <int N, int K, int H>
+__device__ __forceinline__ void bitonic_step(int32_t (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int p = i ^ H;
+    if (p > i) {
+      const int32_t x = v[i], y = v[p];
+      const bool up = (i & K) == 0;
+      v[i] = up ? min(x, y) : max(x, y);
+      v[p] = up ? max(x, y) : min(x, y);
+    }
+  }
+  if constexpr (H > 1)
+    bitonic_step<N, K, H / 2>(v);
+  else if constexpr (K < N)
+    bitonic_step<N, 2 * K, K>(v);
+}
+
+template <int N>
+__device__ __forceinline__ void sort_net(int32_t (&v)[N]) {
+  static_assert((N & (N - 1)) == 0 && N >= 2, "a power of two");
+  bitonic_step<N, 2, 1>(v);
+}
+
 // One incidence as the scatter pass stores it in the workspace: the
 // incidence elem*(D+1)+local and the element's other vertices o_m (o_m =
 // elem[m] for m < D, except that j's own place is taken by elem[D]); rows are
@@ -527,7 +556,7 @@ __device__ void write_bface(const TopoArgs &a, int32_t f, const int32_t (&fv)[D]
 // LDS (pr); a node beyond RC, the set's capacity or MF candidate faces is
 // queued for the general kernel.
 template <int D, bool EMIT, int TBK, class Set, int MF, int RC>
-__device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
+__device__ __forceinline__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
                                uint16_t (*fc)[TBK], uint8_t (*pr)[TBK]) {
   constexpr int MH = Set::CAP;
   const int32_t r0 = a.node_inc_off[j], r1 = a.node_inc_off[j + 1];
@@ -543,36 +572,114 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
   int nfc = 0;
   bool overflow = len > RC;
   int32_t maxdelta = 0;
+  // (count pass) per incidence c, 16 bits at rec[c / 2] >> 16 (c % 2): the
+  // table slots of its other vertices (5 bits each), then their ranks in
+  // the sorted set; the row is read once
+  static_assert(RC % RB == 0 && RC <= 32, "the row fits the records");
+  uint32_t rec[RC / 2];
+#pragma unroll
+  for (int i = 0; i < RC / 2; ++i) rec[i] = 0;
   int32_t *const nset = a.nset + (int64_t)(j / SELL) * NSET * SELL + (j % SELL);
-  bool have = false;
   if constexpr (EMIT) {  // the count pass's set, unless it queued the node
     if (nset[0] == -1) return;
-    if constexpr (std::is_same<Set, RegSet<NSET>>::value) {
-      hs.load(nset);
-      have = true;
-    }
+    hs.load(nset);
   }
-  // (a thread's RB next entries are read together: one 128-byte line is
-  // used up at once, before other lanes' rows evict it)
-  for (int32_t i0 = 0; i0 < len && !overflow && !have; i0 += RB) {
-    int4 qb[RB];
+  if constexpr (!EMIT) {
+    // The distinct other vertices go into an open-addressing table of HT
+    // slots (empty = INT32_MAX, which no vertex id reaches) held in this
+    // thread's wave's part of the face-code LDS, which step 2 only writes
+    // once the table has been read out; the table is then sorted by a
+    // network.  Slot h of lane l sits in face-code row 2h + l/32, in the
+    // two u16 columns of the wave at 2 (l % 32): the 32-bit accesses of a
+    // wave fall on distinct banks.
+    static_assert(MH <= HT && 2 * HT <= MF, "the table fits the face-code rows");
+    const int l = t & 63;
+    int32_t *const tab =
+        reinterpret_cast<int32_t *>(&fc[l >> 5][(t & ~63) + 2 * (l & 31)]);
+    auto slot = [&](uint32_t h) __attribute__((always_inline)) { return tab + (size_t)h * TBK; };
 #pragma unroll
-    for (int u = 0; u < RB; ++u) qb[u] = row[min(i0 + u, len - 1)];
-#pragma unroll
-    for (int u = 0; u < RB; ++u) {
-      if (i0 + u >= len) break;
-      int32_t o[D];
-      inc_others<D>(qb[u], o);
-      int higher = 0;
-      const int g = hs.groups_after(D);  // (uniform: the lanes inserting now)
-#pragma unroll
-      for (int m = 0; m < D; ++m) {
-        const int32_t k = o[m];
-        if (!EMIT) maxdelta = max(maxdelta, k > j ? k - j : j - k);
-        if (k > j) ++higher;
-        if (!hs.insert_upto(k, g)) overflow = true;
+    for (int h = 0; h < HT; ++h) *slot(h) = INT32_MAX;
+    int cnt = 0;
+    bool full = false;
+    auto hash = [](int32_t k) __attribute__((always_inline)) {
+      return ((uint32_t)k * 0x9E3779B1u) >> (32 - HT_LOG);
+    };
+    // the slot holding k, k inserted if absent (0 with `full` set when the
+    // table has no room)
+    auto insert = [&](int32_t k) __attribute__((always_inline)) -> uint32_t {
+      uint32_t h = hash(k);
+      for (int p = 0; p < HT; ++p) {
+        int32_t *const q = slot(h);
+        const int32_t x = *q;
+        if (x == k) return h;
+        if (x == INT32_MAX) {
+          *q = k;
+          ++cnt;
+          return h;
+        }
+        h = (h + 1) & (HT - 1);
       }
-      nfc += D == 3 ? higher * (higher - 1) / 2 : higher;
+      full = true;
+      return 0;
+    };
+    // (a thread's RB next entries are read together: one 128-byte line is
+    // used up at once, before other lanes' rows evict it)
+#pragma unroll
+    for (int c0 = 0; c0 < RC; c0 += RB) {
+      if (c0 < len && !overflow) {
+      int4 qb[RB];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) qb[u] = row[min(c0 + u, len - 1)];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int c = c0 + u;
+        if (c >= len) continue;
+        int32_t o[D];
+        inc_others<D>(qb[u], o);
+        int higher = 0;
+        uint32_t code = 0;
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+          const int32_t k = o[m];
+          maxdelta = max(maxdelta, k > j ? k - j : j - k);
+          if (k > j) ++higher;
+          code |= insert(k) << (5 * m);
+        }
+        rec[c >> 1] |= code << (16 * (c & 1));
+        nfc += D == 3 ? higher * (higher - 1) / 2 : higher;
+      }
+      overflow = full || cnt > MH;
+      }
+    }
+    if (!overflow) {
+      int32_t v[HT];
+#pragma unroll
+      for (int h = 0; h < HT; ++h) v[h] = *slot(h);
+      sort_net(v);
+#pragma unroll
+      for (int s2 = 0; s2 < MH; ++s2) hs.a[s2] = v[s2];
+      hs.n = cnt;
+      // each present value's slot now holds ~rank (negative: no vertex id,
+      // so later searches pass over it), then the records' slots become
+      // ranks; the table's LDS is free afterwards
+#pragma unroll
+      for (int r = 0; r < MH; ++r) {
+        const int32_t x = v[r];
+        if (x != INT32_MAX) {
+          uint32_t h = hash(x);
+          for (int p = 0; p < HT && *slot(h) != x; ++p) h = (h + 1) & (HT - 1);
+          *slot(h) = ~r;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < RC; ++c) {
+        if (c >= len) continue;
+        const uint32_t code = (rec[c >> 1] >> (16 * (c & 1))) & 0xffffu;
+        uint32_t rk = 0;
+#pragma unroll
+        for (int m = 0; m < D; ++m) rk |= (uint32_t)~*slot((code >> (5 * m)) & 31u) << (5 * m);
+        rec[c >> 1] = (rec[c >> 1] & ~(0xffffu << (16 * (c & 1)))) | (rk << (16 * (c & 1)));
+      }
     }
   }
   if (overflow || nfc > MF) {
@@ -583,9 +690,7 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
     }
     return;
   }
-  if constexpr (!EMIT) {
-    if constexpr (std::is_same<Set, RegSet<NSET>>::value) hs.store(nset);
-  }
+  if constexpr (!EMIT) hs.store(nset);
   const int nh = hs.size();
   const int nlow = hs.rank(j);  // neighbours below j come first
   const int nout = nh - nlow;
@@ -643,44 +748,9 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
     // (the stores of a wave then fall on one column of the slice)
     for (int32_t i = 0; i < len; ++i) pr[a.row_rank[r0 + i]][t] = (uint8_t)i;
   }
-  for (int32_t c0 = 0; c0 < len; c0 += RB) {
-   int4 qb[RB];
-   int32_t ib[RB];
-#pragma unroll
-   for (int u = 0; u < RB; ++u) {
-     ib[u] = min(c0 + u, len - 1);
-     if constexpr (EMIT) ib[u] = pr[ib[u]][t];
-     qb[u] = row[ib[u]];
-   }
-#pragma unroll
-   for (int u = 0; u < RB; ++u) {
-    const int32_t c = c0 + u;
-    if (c >= len) break;
-    const int4 q = qb[u];
-    int32_t o[D];
-    inc_others<D>(q, o);
-    const int s0 = o[0] > j ? slot_of_higher(o[0]) : -1;
-    const int s1 = o[1] > j ? slot_of_higher(o[1]) : -1;
-    int s2 = -1;
-    if constexpr (D == 3) s2 = o[2] > j ? slot_of_higher(o[2]) : -1;
-    if constexpr (EMIT) {
-      const int32_t rank = c;
-      const int B = a.sell_wide ? 10 : 5;
-      const int none = (1 << B) - 1;
-      const int u0 = s0 < 0 ? none : s0 - nlow, u1 = s1 < 0 ? none : s1 - nlow;
-      const int u2 = s2 < 0 ? none : s2 - nlow;
-      const uint64_t code = (uint64_t)(u0 | (u1 << B) | (D == 3 ? u2 << (2 * B) : 0));
-      const int64_t pos = sbase + (int64_t)SELL * rank;
-      if (!a.sell_wide) {
-        uint64_t w = code << 48;
-#pragma unroll
-        for (int m = 0; m < D; ++m) w |= (uint64_t)(uint16_t)(int16_t)(o[m] - j) << (16 * m);
-        a.node_sell[pos] = w;
-      } else {
-        a.node_sell[2 * pos] = (uint64_t)(uint32_t)o[0] | ((uint64_t)(uint32_t)o[1] << 32);
-        a.node_sell[2 * pos + 1] = (uint64_t)(uint32_t)(D == 3 ? o[D - 1] : 0) | (code << 32);
-      }
-    }
+  // the candidate faces of one incidence from its other vertices' slots
+  // (-1: the vertex is below j)
+  auto faces_of = [&](int s0, int s1, int s2) __attribute__((always_inline)) {
     auto seen = [&](int b) {
       const uint64_t bit = 1ull << b;
       thrice |= twice & bit;
@@ -706,6 +776,59 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
       if (s0 >= 0) fc[nf++][t] = (uint16_t)s0;
       if (s1 >= 0) fc[nf++][t] = (uint16_t)s1;
     }
+  };
+  if constexpr (!EMIT) {
+#pragma unroll
+    for (int c = 0; c < RC; ++c) {
+      if (c >= len) continue;
+      const uint32_t rk = (rec[c >> 1] >> (16 * (c & 1))) & 0xffffu;
+      int sl[3] = {-1, -1, -1};
+#pragma unroll
+      for (int m = 0; m < D; ++m) {
+        const int r = (int)((rk >> (5 * m)) & 31u);
+        sl[m] = r >= nlow ? r : -1;
+      }
+      faces_of(sl[0], sl[1], sl[2]);
+    }
+  }
+  for (int32_t c0 = 0; EMIT && c0 < len; c0 += RB) {
+   int4 qb[RB];
+   int32_t ib[RB];
+#pragma unroll
+   for (int u = 0; u < RB; ++u) {
+     ib[u] = pr[min(c0 + u, len - 1)][t];
+     qb[u] = row[ib[u]];
+   }
+#pragma unroll
+   for (int u = 0; u < RB; ++u) {
+    const int32_t c = c0 + u;
+    if (c >= len) break;
+    const int4 q = qb[u];
+    int32_t o[D];
+    inc_others<D>(q, o);
+    const int s0 = o[0] > j ? slot_of_higher(o[0]) : -1;
+    const int s1 = o[1] > j ? slot_of_higher(o[1]) : -1;
+    int s2 = -1;
+    if constexpr (D == 3) s2 = o[2] > j ? slot_of_higher(o[2]) : -1;
+    {
+      const int32_t rank = c;
+      const int B = a.sell_wide ? 10 : 5;
+      const int none = (1 << B) - 1;
+      const int u0 = s0 < 0 ? none : s0 - nlow, u1 = s1 < 0 ? none : s1 - nlow;
+      const int u2 = s2 < 0 ? none : s2 - nlow;
+      const uint64_t code = (uint64_t)(u0 | (u1 << B) | (D == 3 ? u2 << (2 * B) : 0));
+      const int64_t pos = sbase + (int64_t)SELL * rank;
+      if (!a.sell_wide) {
+        uint64_t w = code << 48;
+#pragma unroll
+        for (int m = 0; m < D; ++m) w |= (uint64_t)(uint16_t)(int16_t)(o[m] - j) << (16 * m);
+        a.node_sell[pos] = w;
+      } else {
+        a.node_sell[2 * pos] = (uint64_t)(uint32_t)o[0] | ((uint64_t)(uint32_t)o[1] << 32);
+        a.node_sell[2 * pos + 1] = (uint64_t)(uint32_t)(D == 3 ? o[D - 1] : 0) | (code << 32);
+      }
+    }
+    faces_of(s0, s1, s2);
    }
   }
   if constexpr (EMIT) {  // zero the slice entries past j's row
@@ -847,7 +970,7 @@ __device__ void node_topo_body(const TopoArgs &a, int32_t j, int t, Set &hs,
 
 template <int D, bool EMIT>
 __global__ __launch_bounds__(TB) void k_node_topo(TopoArgs a) {
-  __shared__ uint16_t fc[MAXF][TB];
+  __shared__ __align__(16) uint16_t fc[MAXF][TB];
   __shared__ uint8_t pr[EMIT ? MAXR : 1][TB];
   const int t = threadIdx.x;
   const int64_t j64 = (int64_t)blockIdx.x * TB + t;
@@ -1485,16 +1608,16 @@ __global__ __launch_bounds__(SP_TB) void k_strip(int64_t nv, const int32_t *__re
     }
     return k;
   };
+  // (an element's vertices are distinct: the build has stopped at any
+  // element with a repeated vertex, whose measure is zero)
   auto shared = [](const Key &x, const Key &y) {
     int n = 0;
 #pragma unroll
     for (int m = 0; m < D; ++m) {
-      bool dup = false, in = false;
-#pragma unroll
-      for (int m2 = 0; m2 < m; ++m2) dup = dup || x.v[m2] == x.v[m];
+      bool in = false;
 #pragma unroll
       for (int k = 0; k < D; ++k) in = in || y.v[k] == x.v[m];
-      n += (!dup && in) ? 1 : 0;
+      n += in ? 1 : 0;
     }
     return n;
   };
