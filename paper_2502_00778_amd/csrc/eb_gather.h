@@ -479,11 +479,11 @@ __device__ __forceinline__ void fwd_boundary_node(const FwdArgs &a, int64_t bj) 
     for (int i = 0; i < 8; ++i) r += hd[i] < k ? 1 : 0;
     return r;
   };
-  // faces in order, two at a time: their ids, vertices and points are all
+  // faces in order, three at a time: their ids, vertices and points are all
   // loaded before the first is formed; then the n entries of all the round's
   // edges are loaded together, each edge's additions chained in registers in
   // face order, and stored (no load waits behind an earlier face's store)
-  constexpr int G = 2, H = G * (D - 1);  // a face's vertices other than j
+  constexpr int G = 3, H = G * (D - 1);  // a face's vertices other than j
   const int32_t r0 = a.bnode_face_off[bj], r1 = a.bnode_face_off[bj + 1];
   for (int32_t r = r0; r < r1; r += G) {
     int32_t f[G], fv[G][D];

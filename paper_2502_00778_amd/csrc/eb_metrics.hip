@@ -162,7 +162,7 @@ __global__ __launch_bounds__(256) void k_fwd_boundary_dual(FwdArgs a) {
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_fwd_boundary_gather(FwdArgs a) {
+__global__ __launch_bounds__(64) void k_fwd_boundary_gather(FwdArgs a) {
   const int64_t bj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (bj < a.nbnode) fwd_boundary_node<D>(a, bj);
 }
@@ -372,7 +372,8 @@ int launch_fwd_gather(const FwdArgs &a, const LaunchCfg &cfg, hipStream_t s) {
 template <int D>
 int launch_fwd_boundary(const FwdArgs &a, hipStream_t s) {
   if (a.nbnode <= 0) return EB_OK;
-  launch_span(k_fwd_boundary_gather<D>, dim3(grid_for(a.nbnode, 256)), dim3(256), 0, s, a);
+  // (blocks of one wave: the few boundary nodes spread over every CU)
+  launch_span(k_fwd_boundary_gather<D>, dim3(grid_for(a.nbnode, 64)), dim3(64), 0, s, a);
   EB_LAUNCH_CHECK();
   return EB_OK;
 }
