@@ -1365,51 +1365,63 @@ template <int D> __host__ __device__ constexpr int pair_index(int p, int q) {
 // inc_sell; the out-edge slots of that entry -> the ids of the local edges
 // whose tail is that vertex; signs from the vertex order.  All writes are
 // per element, contiguous across threads.
+constexpr int EM_TB = 256;  // element maps: threads (elements) per block
+
 template <int D, bool WIDE>
-__global__ void k_elem_maps(const int32_t *__restrict__ elem, int64_t nelem,
-                            const int32_t *__restrict__ inc_pos,
-                            const uint16_t *__restrict__ row_rank,
-                            const int32_t *__restrict__ node_sell_off,
-                            const uint64_t *__restrict__ node_sell,
-                            const int32_t *__restrict__ node_edge_off, int32_t *elem_edge,
-                            int8_t *elem_edge_sign, int32_t *inc_sell, const StatusBlock *st) {
+__global__ __launch_bounds__(EM_TB) void k_elem_maps(
+    const int32_t *__restrict__ elem, int64_t nelem, const int32_t *__restrict__ inc_pos,
+    const uint16_t *__restrict__ row_rank, const int32_t *__restrict__ node_sell_off,
+    const uint64_t *__restrict__ node_sell, const int32_t *__restrict__ node_edge_off,
+    int32_t *elem_edge, int8_t *elem_edge_sign, int32_t *inc_sell, const StatusBlock *st) {
   constexpr int NE = EL<D>::NE;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nelem || build_failed(st)) return;
-  int32_t v[D + 1], ip[D + 1], ps[D + 1], ee[NE];
-  load_conn<D>(elem, e, v);
-  load_conn<D>(inc_pos, e, ip);
+  // the block's rows of elem_edge and elem_edge_sign, staged so that they
+  // leave in whole contiguous lines (a thread's own 24 + 6 bytes would be
+  // twelve narrow strided stores)
+  __shared__ int32_t s_ee[EM_TB * NE];
+  __shared__ int8_t s_sg[EM_TB * NE];
+  if (build_failed(st)) return;  // (uniform: only earlier kernels set it)
+  const int t = threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * EM_TB, e = e0 + t;
+  const int nb = (int)min((int64_t)EM_TB, nelem - e0);
+  if (e < nelem) {
+    int32_t v[D + 1], ip[D + 1], ps[D + 1], ee[NE];
+    load_conn<D>(elem, e, v);
+    load_conn<D>(inc_pos, e, ip);
 #pragma unroll
-  for (int le = 0; le < NE; ++le) ee[le] = -1;
+    for (int le = 0; le < NE; ++le) ee[le] = -1;
 #pragma unroll
-  for (int l = 0; l <= D; ++l) {
-    const int32_t j = v[l];
-    const int64_t pos =
-        (int64_t)node_sell_off[j / SELL] + (int64_t)SELL * row_rank[ip[l]] + (j % SELL);
-    ps[l] = (int32_t)pos;
-    const uint32_t code = WIDE ? (uint32_t)(node_sell[2 * pos + 1] >> 32)
-                               : (uint32_t)(node_sell[pos] >> 48) & 0x7fffu;
-    const int32_t base = node_edge_off[j];
+    for (int l = 0; l <= D; ++l) {
+      const int32_t j = v[l];
+      const int64_t pos =
+          (int64_t)node_sell_off[j / SELL] + (int64_t)SELL * row_rank[ip[l]] + (j % SELL);
+      ps[l] = (int32_t)pos;
+      const uint32_t code = WIDE ? (uint32_t)(node_sell[2 * pos + 1] >> 32)
+                                 : (uint32_t)(node_sell[pos] >> 48) & 0x7fffu;
+      const int32_t base = node_edge_off[j];
 #pragma unroll
-    for (int m = 0; m < D; ++m) {
-      const int slot = slot_of<WIDE>(code, m);
-      const int lm = m == l ? D : m;  // local index of the m-th other vertex
-      const int le = pair_index<D>(l < lm ? l : lm, l < lm ? lm : l);
-      if (slot != no_slot<WIDE>()) ee[le] = base + slot;
+      for (int m = 0; m < D; ++m) {
+        const int slot = slot_of<WIDE>(code, m);
+        const int lm = m == l ? D : m;  // local index of the m-th other vertex
+        const int le = pair_index<D>(l < lm ? l : lm, l < lm ? lm : l);
+        if (slot != no_slot<WIDE>()) ee[le] = base + slot;
+      }
+    }
+#pragma unroll
+    for (int le = 0; le < NE; ++le) {
+      s_ee[t * NE + le] = ee[le];
+      s_sg[t * NE + le] = (int8_t)(v[pair_p<D>(le)] < v[pair_q<D>(le)] ? 1 : -1);
+    }
+    if (inc_sell) {
+      if constexpr (D == 3)
+        reinterpret_cast<int4 *>(inc_sell)[e] = make_int4(ps[0], ps[1], ps[2], ps[3]);
+      else
+#pragma unroll
+        for (int l = 0; l < 3; ++l) inc_sell[e * 3 + l] = ps[l];
     }
   }
-#pragma unroll
-  for (int le = 0; le < NE; ++le) {
-    elem_edge[e * NE + le] = ee[le];
-    elem_edge_sign[e * NE + le] = (int8_t)(v[pair_p<D>(le)] < v[pair_q<D>(le)] ? 1 : -1);
-  }
-  if (inc_sell) {
-    if constexpr (D == 3)
-      reinterpret_cast<int4 *>(inc_sell)[e] = make_int4(ps[0], ps[1], ps[2], ps[3]);
-    else
-#pragma unroll
-      for (int l = 0; l < 3; ++l) inc_sell[e * 3 + l] = ps[l];
-  }
+  __syncthreads();
+  for (int i = t; i < nb * NE; i += EM_TB) elem_edge[e0 * NE + i] = s_ee[i];
+  for (int i = t; i < nb * NE; i += EM_TB) elem_edge_sign[e0 * NE + i] = s_sg[i];
 }
 
 // ------------------------------------------------ strip order of the rows
@@ -2156,14 +2168,14 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
   EB_TRY(rowsort(tp->bnode_face_off, tp->bnode_face, sz->n_bnodes, s));
   if (nelem > 0) {
     if (plan_wide(sz))
-      hipLaunchKernelGGL((k_elem_maps<D, true>), dim3(grid_for(nelem, 256)), dim3(256), 0, s,
+      hipLaunchKernelGGL((k_elem_maps<D, true>), dim3(grid_for(nelem, EM_TB)), dim3(EM_TB), 0, s,
                          elem, nelem, (const int32_t *)ws_at<int32_t>(ws, L.inc_pos),
                          (const uint16_t *)ws_at<uint16_t>(ws, L.row_rank),
                          (const int32_t *)pl.slice_off,
                          (const uint64_t *)pl.entry, (const int32_t *)tp->node_edge_off,
                          tp->elem_edge, tp->elem_edge_sign, pl.inc_slot, (const StatusBlock *)st);
     else
-      hipLaunchKernelGGL((k_elem_maps<D, false>), dim3(grid_for(nelem, 256)), dim3(256), 0, s,
+      hipLaunchKernelGGL((k_elem_maps<D, false>), dim3(grid_for(nelem, EM_TB)), dim3(EM_TB), 0, s,
                          elem, nelem, (const int32_t *)ws_at<int32_t>(ws, L.inc_pos),
                          (const uint16_t *)ws_at<uint16_t>(ws, L.row_rank),
                          (const int32_t *)pl.slice_off,
