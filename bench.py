@@ -386,6 +386,44 @@ def bench_deforming(torch, eb, meshgen, seed, steps, tm):
     return res
 
 
+def bench_relabelled(torch, eb, meshgen, mesh, seed, reps, tm):
+    """The 161^3 grid with its node ids randomly permuted (seeded; elements
+    keep their order and local vertex order): a numbering with no locality,
+    for which the kernel plan takes its wide format (neighbour ids beyond
+    int16 offsets).  Build, forward (gather), edge-based V and adjoint
+    (atomic), each timed with events around the call."""
+    nv = mesh.coords.shape[1]
+    perm = np.random.default_rng(np.random.SeedSequence([seed, 161])).permutation(nv)
+    coords = np.empty_like(mesh.coords)
+    coords[:, perm] = mesh.coords
+    elems = perm[mesh.elems].astype(np.int32)
+    X = torch.from_numpy(coords).cuda()
+    E = torch.from_numpy(elems).cuda()
+    t_build = tm.time(lambda: eb.build_edges(E, X, edge_inc=False), max(2, reps // 2))
+    topo = eb.build_edges(E, X, edge_inc=False)
+    nel, ne_ = topo.n_elems, topo.n_edges
+    w, c, beta = meshgen.loss_weights(seed, 3, ne_, topo.n_nodes, topo.n_bnodes)
+    W, C, B = (torch.from_numpy(a).cuda() for a in (w, c, beta))
+    f64 = dict(dtype=torch.float64, device="cuda")
+    n = torch.empty(3, ne_, **f64)
+    b = torch.empty(3, topo.n_bnodes, **f64)
+    V = torch.empty(topo.n_nodes, **f64)
+    g = torch.empty(3, topo.n_nodes, **f64)
+    fwd = lambda: eb.directed_areas(X, topo, E, "gather", n_out=n, b_out=b, v_out=V)
+    vol = lambda: eb.dual_volumes(X, topo, E, "edge", n=n, reduce="gather", out=V)
+    bwd = lambda: eb.directed_areas_backward(X, topo, E, W, B, C, reduce="atomic", out=g)
+    res = {"workload": (f"161^3 Kuhn grid as timed above with node ids permuted at random "
+                        f"(seed {seed}): {nel} tets, {ne_} edges"),
+           "wide_plan": bool(topo.sizes.plan_param[1])}
+    for name, fn in (("forward_gather", fwd), ("edge_volume_gather", vol), ("adjoint_atomic", bwd)):
+        fn()
+        res[name + "_ms"] = round(tm.time(fn, reps)[0], 4)
+    res["build_ms"] = round(t_build[0], 4)
+    eb.check_errors(topo)
+    log(f"[bench] relabelled: {res}")
+    return res
+
+
 def bench_2d(torch, eb, meshgen, seed, reps, tm):
     """The triangle grids: the 33 x 33 config and a 256 x 256 grid of the
     paper's size (130,050 triangles): build, forward (gather), edge-based V
@@ -459,6 +497,7 @@ def main():
                     help="run only kernels of known traffic (HBM counter scaling)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-deforming", action="store_true")
+    ap.add_argument("--no-relabelled", action="store_true")
     ap.add_argument("--no-2d", action="store_true")
     ap.add_argument("--bwd-reduce", default="atomic", choices=("atomic", "gather"),
                     help="the adjoint's reduction in the timed step (both are timed as phases)")
@@ -693,6 +732,9 @@ def main():
         line["batched"] = bench_batched(torch, eb, meshgen, args.seed, args.phase_reps, tm)
     if not args.no_2d:
         line["triangles"] = bench_2d(torch, eb, meshgen, args.seed, args.phase_reps, tm)
+    if not args.no_relabelled:
+        line["relabelled"] = bench_relabelled(torch, eb, meshgen, mesh, args.seed, args.phase_reps,
+                                              tm)
     if not args.no_deforming:
         # free the 161^3 working set first
         del topo, X, E, W, C, B, n, b, V, Ve, g, fouts
