@@ -469,7 +469,7 @@ int eb_autotune(const eb_sizes *sizes, const eb_topology *topo, const int32_t *e
 typedef struct {
   const int32_t *slice_off;  /* [ceil(n_nodes/64)+1] */
   const uint64_t *entry;     /* [n_slots * words] */
-  const uint32_t *step;      /* [n_slots], or NULL when words == 2 */
+  const uint32_t *step;      /* [n_slots], or NULL (some wide plans) */
   const int32_t *inc_slot;   /* [(dim+1)*n_elems] */
   int64_t n_slots;
   int32_t words;             /* 64-bit words per entry: 1 or 2 */

@@ -100,7 +100,7 @@ int pack_arrays(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
   a.node_sell = pl.entry;
   a.inc_sell = pl.inc_slot;
   a.node_step = pl.step;
-  a.sell_wide = plan_wide(sz);
+  a.sell_wide = plan_wide(sz);  // (1 for both wide formats)
   a.node_edge_off = tp->node_edge_off;
   a.edge_tail = tp->edge;
   a.edge_head = tp->edge ? tp->edge + sz->n_edges : nullptr;

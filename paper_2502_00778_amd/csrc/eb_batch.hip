@@ -92,7 +92,7 @@ __device__ __forceinline__ bool phase_end(StatusBlock *st, uint32_t *ctr, bool w
   return true;
 }
 
-template <int D, int TN, int CAP, int U, bool WIDE>
+template <int D, int TN, int CAP, int U, bool WIDE, bool STEP>
 __global__ __launch_bounds__(TN) void k_fused(FwdArgs a, FusedPlan p) {
   __shared__ double acc[D][CAP];
   uint32_t *const q = a.st->fq;  // q[ph]: blocks that have finished phase ph
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(TN) void k_fused(FwdArgs a, FusedPlan p) {
   for (int64_t k = b; k < nA; k += G) {
     int64_t idx;
     if (first_kind(k, p.nF, nA, idx)) {
-      fwd_node_tile<D, TN, CAP, U, WIDE, VAR_NODE, !WIDE>(a, idx, acc);
+      fwd_node_tile<D, TN, CAP, U, WIDE, VAR_NODE, STEP>(a, idx, acc);
     } else {
       const int64_t e0 = idx * (int64_t)TN * EPT;
 #pragma unroll
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(TN) void k_fused(FwdArgs a, FusedPlan p) {
 // LDS node slots (two per element, as in the separate atomic kernel).
 constexpr int EPA = 2;
 
-template <int D, int TN, int CAP, int U, bool WIDE>
+template <int D, int TN, int CAP, int U, bool WIDE, bool STEP>
 __global__ __launch_bounds__(TN) void k_fused_atomic(FwdArgs a, FusedPlan p) {
   constexpr int HA = 2 * TN * EPA;
   __shared__ union {
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(TN) void k_fused_atomic(FwdArgs a, FusedPlan p) {
   for (int64_t k = b; k < nA; k += G) {
     int64_t idx;
     if (first_kind(k, p.nF, nA, idx)) {
-      fwd_node_tile<D, TN, CAP, U, WIDE, VAR_NODE, !WIDE>(a, idx, sm.acc);
+      fwd_node_tile<D, TN, CAP, U, WIDE, VAR_NODE, STEP>(a, idx, sm.acc);
     } else if (first_kind(idx, p.nP, nR, idx)) {
       bwd_atomic_elem_block<D, TN, EPA>(a, idx, sm.tg);
     } else {
@@ -213,10 +213,13 @@ int fused_atomic_impl(const FwdArgs &a, const FusedCfg &cfg, hipStream_t s) {
   EB_LAUNCH_CHECK();
 #define EB_FUSED_CASE(TN_, CAP_, U_)                                                        \
   if (cfg.tile == TN_ && cfg.unroll == U_) {                                                \
-    if (a.sell_wide)                                                                        \
-      return launch_fused_kernel(k_fused_atomic<D, TN_, CAP_, U_, true>, TN_, a, p,          \
+    if (!a.sell_wide)                                                                       \
+      return launch_fused_kernel(k_fused_atomic<D, TN_, CAP_, U_, false, true>, TN_, a, p,   \
                                  cfg.blocks_per_cu, s);                                     \
-    return launch_fused_kernel(k_fused_atomic<D, TN_, CAP_, U_, false>, TN_, a, p,           \
+    if (a.node_step)                                                                        \
+      return launch_fused_kernel(k_fused_atomic<D, TN_, CAP_, U_, true, true>, TN_, a, p,    \
+                                 cfg.blocks_per_cu, s);                                     \
+    return launch_fused_kernel(k_fused_atomic<D, TN_, CAP_, U_, true, false>, TN_, a, p,     \
                                cfg.blocks_per_cu, s);                                       \
   }
   EB_FUSED_CASE(64, 512, 1)
@@ -260,9 +263,14 @@ int fused_impl(const FwdArgs &a0, const FusedCfg &cfg, hipStream_t s) {
   EB_LAUNCH_CHECK();
 #define EB_FUSED_CASE(TN_, CAP_, U_)                                                        \
   if (cfg.tile == TN_ && cfg.unroll == U_) {                                                \
-    if (a.sell_wide)                                                                        \
-      return launch_fused_kernel(k_fused<D, TN_, CAP_, U_, true>, TN_, a, p, cfg.blocks_per_cu, s); \
-    return launch_fused_kernel(k_fused<D, TN_, CAP_, U_, false>, TN_, a, p, cfg.blocks_per_cu, s); \
+    if (!a.sell_wide)                                                                       \
+      return launch_fused_kernel(k_fused<D, TN_, CAP_, U_, false, true>, TN_, a, p,          \
+                                 cfg.blocks_per_cu, s);                                     \
+    if (a.node_step)                                                                        \
+      return launch_fused_kernel(k_fused<D, TN_, CAP_, U_, true, true>, TN_, a, p,           \
+                                 cfg.blocks_per_cu, s);                                     \
+    return launch_fused_kernel(k_fused<D, TN_, CAP_, U_, true, false>, TN_, a, p,            \
+                               cfg.blocks_per_cu, s);                                       \
   }
   EB_FUSED_CASE(64, 512, 1)
   EB_FUSED_CASE(64, 512, 2)

@@ -17,13 +17,14 @@ int launch_fwd_nodes(const FwdArgs &a, const LaunchCfg &cfg, hipStream_t s) {
   const dim3 grid((unsigned)ntiles);
 #define EB_GATHER_CASE(TN_, CAP_, U_)                                                   \
   if (cfg.tile == TN_ && cfg.unroll == U_) {                                            \
-    if (a.sell_wide)                                                                    \
-      launch_principal((k_fwd_gather<D, TN_, CAP_, U_, true>), grid, dim3(TN_), 0, s, a); \
-    else if (a.node_step)                                                               \
+    if (!a.sell_wide) /* narrow entries always come with step words */                  \
       launch_principal((k_fwd_gather<D, TN_, CAP_, U_, false, true>), grid, dim3(TN_), 0, s, \
                        a);                                                              \
+    else if (a.node_step)                                                               \
+      launch_principal((k_fwd_gather<D, TN_, CAP_, U_, true, true>), grid, dim3(TN_), 0, s, \
+                       a);                                                              \
     else                                                                                \
-      launch_principal((k_fwd_gather<D, TN_, CAP_, U_, false>), grid, dim3(TN_), 0, s, a); \
+      launch_principal((k_fwd_gather<D, TN_, CAP_, U_, true>), grid, dim3(TN_), 0, s, a); \
     EB_LAUNCH_CHECK();                                                                  \
     return EB_OK;                                                                       \
   }

@@ -116,15 +116,16 @@ __device__ __forceinline__ double flip_sign(double v, uint32_t m) {
   return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) ^ ((uint64_t)m << 32));
 }
 
-// Points of the vertices near a tile (narrow format: within 32767 of one of
-// its nodes): each row addressed from a tile-uniform base by a 32-bit byte
-// offset, so a load needs one offset register instead of a 64-bit address
-// per row.
+// Points of the vertices near a tile (a plan with step words: within 2^19 of
+// one of its nodes): each row addressed from a tile-uniform base by a 32-bit
+// byte offset, so a load needs one offset register instead of a 64-bit
+// address per row.
 template <int D> struct NearPts {
   using GD = const __attribute__((address_space(1))) double;
   uint64_t bx, by, bz;  // the rows at node `from` (uniform values)
   int64_t from;
-  __device__ __forceinline__ NearPts(const Coords &X, int64_t j0) : from(j0 - 32768) {
+  __device__ __forceinline__ NearPts(const Coords &X, int64_t j0)
+      : from(j0 - ((int64_t)1 << (STEP_DBITS - 1))) {
     bx = (uint64_t)X.x + (uint64_t)(from * 8);
     by = (uint64_t)X.y + (uint64_t)(from * 8);
     bz = (uint64_t)X.z + (uint64_t)(from * 8);
@@ -138,6 +139,21 @@ template <int D> struct NearPts {
   }
 };
 
+// a wide entry's slot code (10-bit fields, 1023 = none) in the step words'
+// 5-bit fields (31 = none; a plan with step words has at most 31 out-edges)
+template <int D, bool WIDE> __device__ __forceinline__ uint32_t code5(uint32_t c) {
+  if constexpr (!WIDE) return c;
+  uint32_t r = 0;
+#pragma unroll
+  for (int m = 0; m < D; ++m) r |= min((c >> (10 * m)) & 1023u, 31u) << (5 * m);
+  return r;
+}
+
+// the place offset of a step word, sign-extended from its 20 bits
+__device__ __forceinline__ int32_t step_delta(uint32_t w) {
+  return (int32_t)(w << (32 - STEP_DBITS)) >> (32 - STEP_DBITS);
+}
+
 // c ? a : b by component (a select of whole structs can become a select of
 // their addresses, which sends both to scratch memory)
 __device__ __forceinline__ V3 pick(bool c, const V3 &a, const V3 &b) {
@@ -148,7 +164,8 @@ template <int D, int TN, int CAP, int U, bool WIDE, int VAR = VAR_NODE, bool STE
 __device__ __forceinline__ void fwd_node_tile(const FwdArgs &a, int64_t tile,
                                               double (&acc)[D][CAP]) {
   static_assert(TN % SELL == 0, "a tile is whole slices");
-  static_assert(!(STEP && WIDE), "step words exist for the narrow format only");
+  // the slot fields the walk keeps: the entries' own, or the step words' 5-bit
+  constexpr bool CW = WIDE && !STEP;
   // accumulator units: cross products (VAR_NODE / VAR_EDGE), pieces (VAR_DUAL)
   constexpr double kOut = VAR == VAR_DUAL ? 1.0 : GK<D>::kN;
   const int t = threadIdx.x;
@@ -213,14 +230,14 @@ __device__ __forceinline__ void fwd_node_tile(const FwdArgs &a, int64_t tile,
         if constexpr (VAR == VAR_NODE) {
 #pragma unroll
           for (int m = 0; m < D; ++m) {
-            const int s = slot_of<WIDE>(code, m);
-            if (s != no_slot<WIDE>()) add(s, c);
+            const int s = slot_of<CW>(code, m);
+            if (s != no_slot<CW>()) add(s, c);
           }
         } else {
           auto edge_term = [&](auto mm) {
             constexpr int m = decltype(mm)::value;
-            const int s = slot_of<WIDE>(code, m);
-            if (s == no_slot<WIDE>()) return;
+            const int s = slot_of<CW>(code, m);
+            if (s == no_slot<CW>()) return;
             if constexpr (VAR == VAR_EDGE) {
               // the same face vector from the vertex order rotated by m
               V3 ce;
@@ -372,12 +389,13 @@ __device__ __forceinline__ void fwd_node_tile(const FwdArgs &a, int64_t tile,
           return __builtin_nontemporal_load(reinterpret_cast<GW *>(steps + (uint64_t)(i * 4u)));
         };
         auto step_point = [&](uint32_t w) __attribute__((always_inline)) {
-          return near((int32_t)j + (int32_t)(int16_t)(uint16_t)(w & 0xffffu));
+          return near((int32_t)j + step_delta(w));
         };
         if (len > 0) {
           int32_t o0[D];
           uint32_t c0;
-          sell_entry<D, false>(a.node_sell, p0, (int32_t)j, o0, c0);
+          sell_entry<D, WIDE>(a.node_sell, p0, (int32_t)j, o0, c0);
+          c0 = code5<D, WIDE>(c0);
 #pragma unroll
           for (int u = 0; u < U; ++u) wB[u] = step_word(u);
 #pragma unroll
@@ -387,7 +405,8 @@ __device__ __forceinline__ void fwd_node_tile(const FwdArgs &a, int64_t tile,
           for (int m = 0; m < D; ++m) P[m] = near(o0[m]);
           code = c0;
           // entry 0 is in place already: its word becomes "place 0 keeps its vertex"
-          wB[0] = (uint32_t)(uint16_t)(int16_t)(o0[0] - (int32_t)j) | ((c0 & 31u) << 18);
+          wB[0] = ((uint32_t)(o0[0] - (int32_t)j) & ((1u << STEP_DBITS) - 1u)) |
+                  ((c0 & 31u) << STEP_SLOT);
 #pragma unroll
           for (int u = 0; u < U; ++u) LB[u] = step_point(wB[u]);
         }
@@ -412,15 +431,16 @@ __device__ __forceinline__ void fwd_node_tile(const FwdArgs &a, int64_t tile,
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const bool live = r + u < len;
-            const bool multi = ((wA[u] >> 23) & 1u) != 0u && live;
-            const uint32_t k = (wA[u] >> 16) & 3u;
+            const bool multi = (wA[u] & STEP_WHOLE) != 0u && live;
+            const uint32_t k = (wA[u] >> STEP_PLACE) & 3u;
 #pragma unroll
             for (int m = 0; m < D; ++m) P[m] = pick(!multi && k == (uint32_t)m, LA[u], P[m]);
             const uint32_t sh = 5u * k;
-            code = multi ? code : (code & ~(31u << sh)) | (((wA[u] >> 18) & 31u) << sh);
+            code = multi ? code : (code & ~(31u << sh)) | (((wA[u] >> STEP_SLOT) & 31u) << sh);
             if (__builtin_amdgcn_ballot_w64(multi) != 0 && multi) {
               int32_t o[D];
-              sell_entry<D, false>(a.node_sell, p0 + (int64_t)SELL * (r + u), (int32_t)j, o, code);
+              sell_entry<D, WIDE>(a.node_sell, p0 + (int64_t)SELL * (r + u), (int32_t)j, o, code);
+              code = code5<D, WIDE>(code);
 #pragma unroll
               for (int m = 0; m < D; ++m) P[m] = near(o[m]);
               wait_loads();

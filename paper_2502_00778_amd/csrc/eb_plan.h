@@ -34,17 +34,24 @@
 //             B = 10, word 0 = o_0 | o_1 << 32, word 1 = o_2 | code << 32
 //             (o_2 = 0 in 2D).  Consecutive entries of a strip differ in one
 //             place, so a reader walking a row keeps the other points.
-//   step      [n_slots] uint32, narrow format only: the step from entry c-1
-//             of node j's row to entry c, at entry c's slot.  When exactly
-//             one place k changes: bits 0..15 = o_k - j as int16, bits 16..17
-//             = k, bits 18..22 = slot_k; otherwise (c = 0, or several or no
-//             places change) bit 23 set and the rest 0.  Past a row's end 0.
-//             The gather forward reads 4 bytes per incidence instead of 8.
+//   step      [n_slots] uint32, present unless the format is wide without
+//             steps (below): the step from entry c-1 of node j's row to entry
+//             c, at entry c's slot.  When exactly one place k changes: bits
+//             0..19 = o_k - j as a 20-bit two's complement value, bits 20..21
+//             = k, bits 22..26 = slot_k (31 = none); otherwise (c = 0, or
+//             several or no places change) bit 27 set and the rest 0.  Past a
+//             row's end 0.  The gather forward reads 4 bytes per incidence
+//             instead of 8 or 16.
 //   inc_slot  [(dim+1)*n_elems] int32: slot of incidence elem*(dim+1)+local
 //             in the layout above with rows in ascending order, i.e.
 //             slice_off[j/64] + 64 r + j%64 for the incidence's rank r in node
 //             j's node_inc row (the gather adjoint's per-incidence gradient
 //             pieces live at these slots).
+//
+// Formats (eb_sizes.plan_param[1]): 0 narrow entries with step words (every
+// |o_m - j| <= 32767 and at most 31 out-edges per node); 2 wide entries with
+// step words (every |o_m - j| <= 2^19 - 1 and at most 31 out-edges: large
+// grids numbered with locality); 1 wide entries alone (any grid).
 //
 // Limits: a node's row has at most 65535 entries (its ranks are 16-bit in
 // the build) and at most 1023 out-edges (10-bit slot fields); the build
@@ -63,8 +70,16 @@ struct PlanLayout {
   size_t slice_off, entry, step, inc_slot, total;
 };
 
+constexpr int PLAN_NARROW = 0, PLAN_WIDE = 1, PLAN_WIDE_STEPS = 2;
+// step words: delta bits, the place's and the slot's shifts, the flag of an
+// entry read whole
+constexpr int STEP_DBITS = 20, STEP_PLACE = 20, STEP_SLOT = 22;
+constexpr uint32_t STEP_WHOLE = 1u << 27;
+constexpr int32_t STEP_MAX_DELTA = (1 << (STEP_DBITS - 1)) - 1;
+
 inline PlanLayout plan_layout(int dim, int64_t n_nodes, int64_t n_elems, int64_t n_slots,
-                              int wide) {
+                              int format) {
+  const bool wide = format != PLAN_NARROW, steps = format != PLAN_WIDE;
   PlanLayout P{};
   if (dim == 4) {  // no plan in four dimensions: one placeholder line
     P.total = 256;
@@ -76,7 +91,7 @@ inline PlanLayout plan_layout(int dim, int64_t n_nodes, int64_t n_elems, int64_t
   P.entry = off;
   off += align256(sizeof(uint64_t) * (size_t)n_slots * (wide ? 2 : 1));
   P.step = off;
-  off += wide ? 0 : align256(sizeof(uint32_t) * (size_t)n_slots);
+  off += steps ? align256(sizeof(uint32_t) * (size_t)n_slots) : 0;
   P.inc_slot = off;
   off += align256(sizeof(int32_t) * (size_t)(dim + 1) * (size_t)n_elems);
   P.total = off;
@@ -85,26 +100,27 @@ inline PlanLayout plan_layout(int dim, int64_t n_nodes, int64_t n_elems, int64_t
 
 // the plan's layout parameters as eb_build_edges records them in eb_sizes
 inline int64_t plan_slots(const eb_sizes *s) { return s->plan_param[0]; }
-inline int plan_wide(const eb_sizes *s) { return (int)s->plan_param[1]; }
+inline int plan_format(const eb_sizes *s) { return (int)s->plan_param[1]; }
+inline int plan_wide(const eb_sizes *s) { return plan_format(s) != PLAN_NARROW ? 1 : 0; }
 inline size_t plan_bytes_of(const eb_sizes *s) {
-  return plan_layout(s->dim, s->n_nodes, s->n_elems, plan_slots(s), plan_wide(s)).total;
+  return plan_layout(s->dim, s->n_nodes, s->n_elems, plan_slots(s), plan_format(s)).total;
 }
 
 struct PlanPtrs {
   int32_t *slice_off;
   uint64_t *entry;
-  uint32_t *step;  // null in the wide format
+  uint32_t *step;  // null in the wide format without steps
   int32_t *inc_slot;
 };
 
 inline PlanPtrs plan_ptrs(const eb_sizes *s, void *plan) {
-  const PlanLayout P = plan_layout(s->dim, s->n_nodes, s->n_elems, plan_slots(s), plan_wide(s));
+  const PlanLayout P = plan_layout(s->dim, s->n_nodes, s->n_elems, plan_slots(s), plan_format(s));
   char *b = static_cast<char *>(plan);
   PlanPtrs p{};
   if (!b || s->dim == 4) return p;
   p.slice_off = reinterpret_cast<int32_t *>(b + P.slice_off);
   p.entry = reinterpret_cast<uint64_t *>(b + P.entry);
-  p.step = plan_wide(s) ? nullptr : reinterpret_cast<uint32_t *>(b + P.step);
+  p.step = plan_format(s) == PLAN_WIDE ? nullptr : reinterpret_cast<uint32_t *>(b + P.step);
   p.inc_slot = reinterpret_cast<int32_t *>(b + P.inc_slot);
   return p;
 }
@@ -113,7 +129,8 @@ inline PlanPtrs plan_ptrs(const eb_sizes *s, void *plan) {
 inline bool plan_params_valid(const eb_sizes *s) {
   const int64_t n_slots = plan_slots(s);
   return n_slots >= 0 && n_slots % SELL == 0 && n_slots < (int64_t(1) << 31) &&
-         (s->plan_param[1] == 0 || s->plan_param[1] == 1) &&
+         (s->plan_param[1] == PLAN_NARROW || s->plan_param[1] == PLAN_WIDE ||
+          s->plan_param[1] == PLAN_WIDE_STEPS) &&
          s->plan_bytes == (int64_t)plan_bytes_of(s);
 }
 

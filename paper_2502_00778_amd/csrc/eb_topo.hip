@@ -1549,7 +1549,9 @@ __global__ __launch_bounds__(SP_TB) void k_strip(int64_t nv, const int32_t *__re
   if (!FIRST && (len <= SP_SHORT || len > STRIP)) return;  // the first launch's rows
   const int64_t base = (int64_t)node_sell_off[j / SELL] + (j % SELL);
   using E = SellEntry<D, WIDE>;
-  // the step from the previous entry (vertices by place S) to x: see node_step
+  // the step from the previous entry (vertices by place S) to x (the layout
+  // in eb_plan.h; a wide slot field past 30 is "none": a plan with step
+  // words has at most 31 out-edges per node)
   auto step_of = [&](const int32_t (&S)[D], const E &x) {
     int changed = 0;
     uint32_t w = 0;
@@ -1557,10 +1559,11 @@ __global__ __launch_bounds__(SP_TB) void k_strip(int64_t nv, const int32_t *__re
     for (int m = D - 1; m >= 0; --m)
       if (x.o[m] != S[m]) {
         ++changed;
-        w = (uint32_t)(uint16_t)(int16_t)(x.o[m] - j) | ((uint32_t)m << 16) |
-            (((x.code >> (5 * m)) & 31u) << 18);
+        const uint32_t sl = min((x.code >> (E::B * m)) & ((1u << E::B) - 1u), 31u);
+        w = ((uint32_t)(x.o[m] - j) & ((1u << STEP_DBITS) - 1u)) | ((uint32_t)m << STEP_PLACE) |
+            (sl << STEP_SLOT);
       }
-    return changed == 1 ? w : (1u << 23);
+    return changed == 1 ? w : STEP_WHOLE;
   };
   if (FIRST && node_step) {  // zero past the row's end
     const int32_t slen = (node_sell_off[j / SELL + 1] - node_sell_off[j / SELL]) / SELL;
@@ -1576,7 +1579,7 @@ __global__ __launch_bounds__(SP_TB) void k_strip(int64_t nv, const int32_t *__re
                        WIDE ? node_sell[W * (base + (int64_t)SELL * c) + W - 1] : 0};
       E x;
       x.decode(w, j);
-      node_step[base + (int64_t)SELL * c] = c == 0 ? (1u << 23) : step_of(S, x);
+      node_step[base + (int64_t)SELL * c] = c == 0 ? STEP_WHOLE : step_of(S, x);
 #pragma unroll
       for (int m = 0; m < D; ++m) S[m] = x.o[m];
     }
@@ -1679,7 +1682,7 @@ __global__ __launch_bounds__(SP_TB) void k_strip(int64_t nv, const int32_t *__re
   for (int32_t c = 0; c < len; ++c) {
     E x = entry(seq[c][t]);
     x.place(S);
-    if (node_step) node_step[base + (int64_t)SELL * c] = c == 0 ? (1u << 23) : step_of(S, x);
+    if (node_step) node_step[base + (int64_t)SELL * c] = c == 0 ? STEP_WHOLE : step_of(S, x);
 #pragma unroll
     for (int m = 0; m < D; ++m) S[m] = x.o[m];
     uint64_t w[2];
@@ -2086,7 +2089,13 @@ int build_edges_impl(int64_t nv, int64_t nelem, const int32_t *elem, const doubl
   // so their scan does not wrap; the slot count is 64 times that)
   const int64_t n_slots = (int64_t)SELL * h.totals[T_SELL_ROWS];
   sizes->plan_param[0] = n_slots;
-  sizes->plan_param[1] = (h.totals[T_MAXDELTA] > 32767 || h.totals[T_MAXOUT] > 31) ? 1 : 0;
+  // narrow entries while every neighbour offset fits int16; wide ones with
+  // step words while the offsets fit the words' 20 bits; else wide alone
+  // (more than 31 out-edges need the wide 10-bit slot fields either way)
+  sizes->plan_param[1] = h.totals[T_MAXOUT] > 31             ? PLAN_WIDE
+                         : h.totals[T_MAXDELTA] <= 32767         ? PLAN_NARROW
+                         : h.totals[T_MAXDELTA] <= STEP_MAX_DELTA ? PLAN_WIDE_STEPS
+                                                                  : PLAN_WIDE;
   sizes->plan_bytes = (int64_t)plan_bytes_of(sizes);
   if (h.status != EB_OK) {
     set_detail("%s at %s %lld", eb_status_string(h.status),
@@ -2190,7 +2199,7 @@ int emit_impl(const eb_sizes *sz, const int32_t *elem, const double *coords,
         hipLaunchKernelGGL(pass == 0 ? (k_strip<D, true, SP_SHORT>) : (k_strip<D, true, STRIP>),
                            dim3(grid_for(nv, SP_TB)), dim3(SP_TB), 0, s, nv,
                            (const int32_t *)tp->node_inc_off, (const int32_t *)pl.slice_off,
-                           pl.entry, nullptr, (const StatusBlock *)st);
+                           pl.entry, pl.step, (const StatusBlock *)st);
         EB_LAUNCH_CHECK();
       }
     else

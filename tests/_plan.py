@@ -19,8 +19,10 @@ definitions, without re-deriving the library's choices:
   with the previous one only if no later entry of the row shares D-1;
 * longer rows: the entries are the incidences in ascending order, local
   vertex order;
-* step words (narrow entries): reproduce entry c from entry c-1 (one changed
-  place: its new vertex, place and slot; else the flag word);
+* step words (narrow entries always; wide ones exactly when every offset
+  fits 20 bits and no node has more than 31 out-edges): reproduce entry c
+  from entry c-1 (one changed place: its new vertex, place and slot; else
+  the flag word);
 * each incidence's slot is its rank in node j's node_inc row.
 """
 from __future__ import annotations
@@ -139,19 +141,27 @@ def check_plan(gt, ot, elems):
         for m in range(D):
             sh += (cand[:, :, m][:, :, None] == prev[:, None, :]).any(axis=2)
         assert not ((sh >= D - 1) & valid).any(), "a strip broke although a face-sharing entry was left"
-    # step words
+    # step words: present in the narrow format always, in the wide one when
+    # every offset fits 20 bits and no node has more than 31 out-edges
+    fits = bool(ninc == 0 or (np.abs(o - jj[:, None]).max() <= (1 << 19) - 1
+                              and np.diff(eoff).max(initial=0) <= 31))
     if not wide:
+        assert pv["step"] is not None and fits, "narrow plan without step words"
+    else:
+        assert (pv["step"] is not None) == fits, "wide plan: step words iff they fit"
+    if pv["step"] is not None:
         st = pv["step"]
         assert (st[~covered] == 0).all(), "step words past a row"
         sw = st[P].astype(np.int64)
-        assert (sw[rr == 0] == 1 << 23).all(), "a row's first step word"
+        assert (sw[rr == 0] == 1 << 27).all(), "a row's first step word"
         q = np.nonzero(rr > 0)[0]
         a, b = o[q - 1], o[q]
         ch = a != b
         one = ch.sum(axis=1) == 1
         k = np.argmax(ch, axis=1)
         bk = b[np.arange(q.size), k]
-        sk = slot[q, k]
-        want = np.where(one, ((bk - jj[q]) & 0xFFFF) | (k << 16) | (sk << 18), 1 << 23)
+        sk = np.minimum(slot[q, k], 31)  # (wide "none" is 31 in a word)
+        want = np.where(one, ((bk - jj[q]) & 0xFFFFF) | (k << 20) | (sk << 22), 1 << 27)
         assert (sw[q] == want).all(), "step words"
-    return dict(n_slots=int(pv["n_slots"]), wide=bool(wide), breaks=int(brk.size))
+    return dict(n_slots=int(pv["n_slots"]), wide=bool(wide), steps=pv["step"] is not None,
+                breaks=int(brk.size))

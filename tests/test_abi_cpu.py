@@ -58,12 +58,13 @@ def _up(x):
 
 
 def sizes(dim, nv, ne, n_edges, n_bfaces, n_bnodes, n_slots=0, wide=0):
-    """eb_sizes as eb_build_edges fills them: the plan's slot count and entry
-    format, and its byte size (four sections on 256-byte lines: slice
-    offsets, entries, step words in the narrow format, incidence slots)."""
+    """eb_sizes as eb_build_edges fills them: the plan's slot count and format
+    (0 narrow entries, 1 wide entries, 2 wide entries with step words), and
+    its byte size (four sections on 256-byte lines: slice offsets, entries,
+    step words unless format 1, incidence slots)."""
     from paper_2502_00778_amd._lib import EbSizes
-    nb = (_up(4 * ((nv + 63) // 64 + 1)) + _up(8 * n_slots * (1 + wide))
-          + (0 if wide else _up(4 * n_slots)) + _up(4 * (dim + 1) * ne))
+    nb = (_up(4 * ((nv + 63) // 64 + 1)) + _up(8 * n_slots * (1 + (wide != 0)))
+          + (0 if wide == 1 else _up(4 * n_slots)) + _up(4 * (dim + 1) * ne))
     sz = EbSizes(dim=dim, n_nodes=nv, n_elems=ne, n_edges=n_edges, n_bfaces=n_bfaces,
                  n_bnodes=n_bnodes, plan_bytes=nb)
     sz.plan_param[0], sz.plan_param[1] = n_slots, wide
@@ -92,21 +93,27 @@ def test_backward_workspace_bytes(L):
     assert L.eb_backward_workspace_bytes(ctypes.byref(bad)) == 0
     bad = sizes(3, 1000, 5000, 6000, 10, 10, n_slots=65)
     assert L.eb_backward_workspace_bytes(ctypes.byref(bad)) == 0
+    bad = sizes(3, 1000, 5000, 6000, 10, 10, n_slots=64 * 400, wide=2)
+    assert L.eb_backward_workspace_bytes(ctypes.byref(bad)) > 0
+    bad.plan_param[1] = 3  # no such format
+    assert L.eb_backward_workspace_bytes(ctypes.byref(bad)) == 0
 
 
 def test_plan_describe(L):
     """eb_plan_describe points into the plan at the section offsets and
     reads no device memory; it rejects sizes not made by a build."""
     from paper_2502_00778_amd._lib import EbPlanView
-    for wide in (0, 1):
+    for wide in (0, 1, 2):
         sz = sizes(3, 1000, 5000, 6000, 10, 10, n_slots=64 * 400, wide=wide)
         v = EbPlanView()
         base = 1 << 20
         assert L.eb_plan_describe(ctypes.byref(sz), ctypes.c_void_p(base), ctypes.byref(v)) == 0
-        assert (v.n_slots, v.words) == (64 * 400, 1 + wide)
+        assert (v.n_slots, v.words) == (64 * 400, 1 + (wide != 0))
         assert v.slice_off == base
         assert v.entry == base + _up(4 * (16 + 1))
-        assert (v.step is None) == bool(wide)
+        assert (v.step is None) == (wide == 1)
+        if wide != 1:
+            assert v.step == base + _up(4 * (16 + 1)) + _up(8 * 64 * 400 * v.words)
         assert v.inc_slot == base + sz.plan_bytes - _up(4 * 4 * 5000)
     sz.plan_bytes = 7
     assert L.eb_plan_describe(ctypes.byref(sz), ctypes.c_void_p(1 << 20), ctypes.byref(v)) == -1

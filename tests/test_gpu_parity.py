@@ -245,6 +245,47 @@ def test_metrics_parity(name, reduce):
     say(f"    max rel n {nrel:.2e} (cancelling edges {ncan}), b {brel:.2e}, V {vrel:.2e}")
 
 
+@pytest.mark.parametrize("name,fmt", [("3d-41", 0), ("3d-33-relabel", 2),
+                                      ("3d-cone-150-low", 1), ("2d-fan-400", 1),
+                                      ("3d-81-relabel", 1)])
+def test_plan_formats(name, fmt):
+    """The three plan formats: narrow entries with step words, wide entries
+    with step words (offsets within 20 bits, at most 31 out-edges: a random
+    numbering of 35,937 nodes), wide entries alone (more than 31 out-edges,
+    or offsets beyond 20 bits: a random numbering of 531,441 nodes); each
+    valid against the oracle's topology, and the gather forward's n, b, V
+    in parity, bitwise equal for every launch shape."""
+    if name == "3d-81-relabel":
+        mesh = relabelled(meshgen.cube_kuhn(81, 3), 9)
+        ot = oracle.topology(3, mesh.coords, mesh.elems)
+        n0, b0, V0 = oracle.metrics(ot, mesh.coords, mesh.elems)
+    else:
+        mesh, ot, n0, b0, V0 = case(name)
+    say(f"[plan format] {name}: expect {fmt}")
+    X, E = dev(mesh)
+    gt = eb().build_edges(E, X)
+    assert int(gt.sizes.plan_param[1]) == fmt
+    info = assert_topo_equal(gt, ot, mesh.elems)
+    assert info["steps"] == (fmt != 1)
+    n, b, V = eb().directed_areas(X, gt, E, reduce="gather")
+    eb().check_errors(gt)
+    S_e, S_b = piece_scales(ot, mesh.coords, mesh.elems)
+    assert_vec_close(n.cpu().numpy(), n0, S_e, "n")
+    assert_vec_close(b.cpu().numpy(), b0, S_b, "b")
+    used = V0 > 0
+    assert_vol_close(V.cpu().numpy()[used], V0[used], "V")
+    ref = [x.clone() for x in (n, b, V)]
+    try:
+        for tile in (64, 128, 256):
+            for unroll in (1, 2, 4):
+                eb().set_gather_shape(tile, unroll, 1)
+                got = eb().directed_areas(X, gt, E, reduce="gather")
+                for x, r in zip(got, ref):
+                    assert torch.equal(x, r), (tile, unroll)
+    finally:
+        eb().set_gather_shape(64, 2, 1)
+
+
 @pytest.mark.parametrize("name", ["3d-41", "2d-33", "3d-7-iso"])
 def test_volumes_both_modes(name):
     mesh, ot, n0, b0, V0 = case(name)
