@@ -207,7 +207,7 @@ int fused_atomic_impl(const FwdArgs &a, const FusedCfg &cfg, hipStream_t s) {
     return EB_EOVERFLOW;
   }
   // the gradient is summed with atomics: zeroed first (a fill kernel, no
-  // memset node), with the work counters
+  // memset node), and the phase counters cleared
   EB_TRY(fill_f64(a.g_x, D * a.nv, 0.0, s));
   hipLaunchKernelGGL(k_fused_reset, dim3(1), dim3(64), 0, s, a.st);
   EB_LAUNCH_CHECK();
