@@ -42,8 +42,8 @@ def alg_bytes_forward(dim, nv, nel, ne_, nb, nbn):
     once, every output written once, plus one element->edge addressing array.
       coords 8D Nv + elems 4(D+1) NE + addressing 4 ne NE + n 8D Ne + V 8 Nv
       + b 8D Nbn + boundary elements 4(D + ne_B) NB"""
-    ne = 3 if dim == 2 else 6
-    neb = 1 if dim == 2 else 3
+    ne = dim * (dim + 1) // 2       # local edges of an element
+    neb = dim * (dim - 1) // 2      # edges of a boundary element
     return (8 * dim * nv + 4 * (dim + 1) * nel + 4 * ne * nel + 8 * dim * ne_ + 8 * nv
             + 8 * dim * nbn + 4 * (dim + neb) * nb)
 
@@ -234,9 +234,11 @@ def alg_bytes_fused(dim, nv, nel, ne_, nb, nbn):
 
 
 def bench_batched(torch, eb, meshgen, seed, reps, tm):
-    """The 64-mesh batch: forward + adjoint as one fused persistent launch
-    (eager and replayed from a captured graph) against 64 x (plain gather
-    forward + plain gather adjoint) on the meshes one by one."""
+    """The 64-mesh batch: forward + adjoint as one enqueue in each fused mode
+    (the tuned deterministic one also replayed from a captured graph, and the
+    persistent kernel with the atomic adjoint, eager and from a graph)
+    against 64 x (plain gather forward + plain gather adjoint) on the meshes
+    one by one."""
     t0 = time.perf_counter()
     bm = meshgen.batched_kuhn(64, seed)
     log(f"[bench] batch of 64 meshes: {bm.n_elems} tets ({time.perf_counter() - t0:.1f} s)")
@@ -269,6 +271,10 @@ def bench_batched(torch, eb, meshgen, seed, reps, tm):
     eb.set_fused_mode("persistent_atomic")  # one persistent launch, atomic adjoint
     fused()
     t_atomic = tm.time(fused, reps)
+    gr = eb.ForwardBackwardGraph(X, topo, E, W, B, C)  # (the atomic form, captured)
+    gr.launch()
+    t_graph_atomic = tm.time(gr.launch, reps)
+    gr.close()
     eb.set_fused_mode(tuned_mode)
     gr = eb.ForwardBackwardGraph(X, topo, E, W, B, C)
     gr.launch()
@@ -306,10 +312,12 @@ def bench_batched(torch, eb, meshgen, seed, reps, tm):
         "persistent_kernel_ms": round(k_fused[0], 4),
         "separate_kernels_ms": round(t_sep[0], 4),
         "persistent_atomic_ms": round(t_atomic[0], 4),
+        "graph_persistent_atomic_ms": round(t_graph_atomic[0], 4),
         "tuned_mode": tuned_mode,
         "graph_ms": round(t_graph[0], 4),
         "per_mesh_plain_ms": round(t_plain[0], 4),
         "speedup_graph_vs_per_mesh": round(t_plain[0] / t_graph[0], 2),
+        "speedup_graph_persistent_atomic_vs_per_mesh": round(t_plain[0] / t_graph_atomic[0], 2),
         "Melements_per_s_graph": round(nel / (t_graph[0] * 1e-3) / 1e6, 1),
         "Melements_per_s_per_mesh": round(nel / (t_plain[0] * 1e-3) / 1e6, 1),
         "alg_GBps_graph": round(bytes_ / (t_graph[0] * 1e-3) / 1e9, 1),
@@ -458,6 +466,48 @@ def bench_2d(torch, eb, meshgen, seed, reps, tm):
     return out
 
 
+def bench_4d(torch, eb, meshgen, seed, reps, tm, n=33):
+    """Pentatopes: the n^4 Kuhn grid (33^4: 1,185,921 nodes, 25,165,824
+    pentatopes, about the 161^3 tet grid's element count): build, forward
+    (gather and atomic), edge-based V, each timed on the stream; with the
+    checks that hold at any size (the volumes sum to the unit 4-cube's 1,
+    the edge-based V equals the element-based V)."""
+    t0 = time.perf_counter()
+    mesh = meshgen.hypercube_kuhn(n, seed)
+    log(f"[bench] 4d: {n}^4 grid, {mesh.n_elems} pentatopes ({time.perf_counter() - t0:.1f} s)")
+    X = torch.from_numpy(mesh.coords).cuda()
+    E = torch.from_numpy(mesh.elems).cuda()
+    topo = eb.build_edges(E, X, edge_inc=False, adjoint=False)
+    nv, nel, ne_, nb, nbn = (topo.n_nodes, topo.n_elems, topo.n_edges, topo.n_bfaces,
+                             topo.n_bnodes)
+    n_, b, V = eb.directed_areas(X, topo, E, "gather")
+    Ve = eb.dual_volumes(X, topo, E, "edge", n=n_, reduce="gather")
+    vol_sum = float(V.sum())
+    rel = float(((Ve - V).abs() / V.abs()).max())
+    fns = {
+        "build": lambda: eb.build_edges(E, X, edge_inc=False, adjoint=False),
+        "forward_gather": lambda: eb.directed_areas(X, topo, E, "gather", n_out=n_, b_out=b,
+                                                    v_out=V),
+        "forward_atomic": lambda: eb.directed_areas(X, topo, E, "atomic", n_out=n_, b_out=b,
+                                                    v_out=V),
+        "edge_volume_gather": lambda: eb.dual_volumes(X, topo, E, "edge", n=n_, reduce="gather",
+                                                      out=Ve),
+    }
+    bf = alg_bytes_forward(4, nv, nel, ne_, nb, nbn)
+    r = {"workload": f"{n}^4 Kuhn grid (seed {seed}): {nel} pentatopes, {nv} nodes, {ne_} edges",
+         "volume_sum": vol_sum, "edge_vs_element_V_max_rel": rel}
+    for k, fn in fns.items():
+        fn()
+        ms = tm.time(fn, max(2, reps // 2) if k == "build" else reps)[0]
+        r[k] = {"ms": round(ms, 4), "Melements_per_s": round(nel / (ms * 1e-3) / 1e6, 1)}
+        if k.startswith("forward"):
+            r[k]["alg_GBps"] = round(bf / (ms * 1e-3) / 1e9, 1)
+            r[k]["frac_hbm_peak"] = round(bf / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    eb.check_errors(topo)
+    log(f"[bench] 4d: {r}")
+    return r
+
+
 def calibrate(nbytes=1 << 30, reps=5):
     """Kernels of known traffic for scaling the HBM counters: a read-only
     reduction (torch.sum over nbytes of float64: reads nbytes), an
@@ -498,6 +548,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-deforming", action="store_true")
     ap.add_argument("--no-relabelled", action="store_true")
+    ap.add_argument("--no-4d", action="store_true")
     ap.add_argument("--no-2d", action="store_true")
     ap.add_argument("--bwd-reduce", default="atomic", choices=("atomic", "gather"),
                     help="the adjoint's reduction in the timed step (both are timed as phases)")
@@ -732,6 +783,8 @@ def main():
         line["batched"] = bench_batched(torch, eb, meshgen, args.seed, args.phase_reps, tm)
     if not args.no_2d:
         line["triangles"] = bench_2d(torch, eb, meshgen, args.seed, args.phase_reps, tm)
+    if not args.no_4d:
+        line["pentatopes"] = bench_4d(torch, eb, meshgen, args.seed, args.phase_reps, tm)
     if not args.no_relabelled:
         line["relabelled"] = bench_relabelled(torch, eb, meshgen, mesh, args.seed, args.phase_reps,
                                               tm)

@@ -7,11 +7,17 @@
 // tetrahedron) and n_B that of a boundary tetrahedron (eb_geom4.h).  The
 // paper derives D = 2 and 3 and leaves D = 4 to future work.
 //
-// Plain kernels, not tuned: the gather forward walks each node's node_inc
-// row (one thread per node, connectivity and points gathered per incidence,
-// the node's out-edges found by binary search among its edge heads and
-// accumulated in place, in row order), then a boundary pass per boundary
-// node; the atomic forward scatters per element and per boundary face.
+// The gather forward takes tiles of 64 consecutive nodes, one wave each: a
+// node's thread walks its node_inc row two incidences at a time (their
+// connectivity and points loaded together), forms the face vector opposite
+// the node, and adds it to its out-edges' accumulators in LDS (the tile's
+// out-edges are contiguous; a node's edge found among its first 16 heads,
+// held in registers, or by binary search beyond), in row order; the tile's
+// edges are written once.  A boundary pass per boundary node follows.  The
+// atomic forward sums each block's element contributions per edge and per
+// node in LDS hash tables first, then adds each sum with one FP64 atomic,
+// and scatters per boundary face.
+#include "eb_geom.h"  // (the LDS hash tables of the atomic pass)
 #include "eb_geom4.h"
 #include "eb_kernels.h"
 
@@ -49,42 +55,104 @@ __device__ __forceinline__ void others_of4(const int32_t (&v)[5], int l, int32_t
   for (int m = 0; m < 4; ++m) o[m] = l == m ? v[4] : v[m];
 }
 
-// gather forward, node pass: n over j's out-edges and V_j
-__global__ __launch_bounds__(256) void k4_fwd_node(Fwd4 a) {
-  const int64_t j64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j64 >= a.nv) return;
-  const int32_t j = (int32_t)j64;
-  const int32_t e0 = a.node_edge_off[j], nout = a.node_edge_off[j + 1] - e0;
+// gather forward, node pass by tiles: TN = 64 nodes (one wave), their
+// out-edges' raw sums (the face vectors; n = sum / 10) in LDS when the tile
+// has at most CAP of them, else in the output itself; V_j = sum d / 20
+constexpr int T4_TN = 64, T4_CAP = 1024, T4_HEADS = 16;
+
+// add to a thread-owned LDS accumulator (only the owner adds to it, and a
+// wave's LDS operations complete in order: the sum is in program order)
+__device__ __forceinline__ void lds_add4(double *p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__global__ __launch_bounds__(T4_TN) void k4_fwd_tile(Fwd4 a) {
+  __shared__ double acc[4][T4_CAP];
+  const int t = threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * T4_TN;
+  const int64_t jend = min(j0 + (int64_t)T4_TN, a.nv);
   const bool want_n = a.n[0] != nullptr;
-  if (want_n)
-    for (int32_t s = 0; s < nout; ++s)
+  const int32_t e0 = a.node_edge_off[j0];
+  const int32_t cnt = a.node_edge_off[jend] - e0;
+  const bool in_lds = want_n && cnt <= T4_CAP;
+  if (in_lds)
+    for (int i = t; i < cnt; i += T4_TN)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) a.n[c][e0 + s] = 0.0;
-  const V4 Pj = load_pt4(a.X, j);
-  double V = 0.0;
-  for (int32_t r = a.node_inc_off[j]; r < a.node_inc_off[j + 1]; ++r) {
-    const int32_t inc = a.node_inc[r];
-    int32_t v[5], o[4];
-    load_conn4(a.elem, inc / 5, v);
-    others_of4(v, inc % 5, o);
-    V4 Q[4];
+      for (int c = 0; c < 4; ++c) acc[c][i] = 0.0;
+  __syncthreads();
+  const int64_t j64 = j0 + t;
+  if (j64 < a.nv) {
+    const int32_t j = (int32_t)j64;
+    const int32_t my0 = a.node_edge_off[j], nout = a.node_edge_off[j + 1] - my0;
+    const int32_t base = in_lds ? my0 - e0 : my0;
+    if (want_n && !in_lds)
+      for (int32_t s = 0; s < nout; ++s)
 #pragma unroll
-    for (int m = 0; m < 4; ++m) Q[m] = load_pt4(a.X, o[m]);
-    double d;
-    const V4 nj = pent_face(Pj, Q, d);  // d = 4|E|
-    if (d == 0.0) raise_status(a.st, EB_EDEGENERATE, inc / 5);
-    V += d * (1.0 / 20.0);
-    if (want_n) {
+        for (int c = 0; c < 4; ++c) a.n[c][my0 + s] = 0.0;
+    // the first heads in registers: an edge's place is the number below it
+    int32_t hd[T4_HEADS];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        if (o[m] <= j) continue;
-        const int32_t e = e0 + out_slot(a.edge_head + e0, nout, o[m]);
+    for (int i = 0; i < T4_HEADS; ++i)
+      hd[i] = i < nout ? a.edge_head[my0 + i] : INT32_MAX;
+    const bool few = nout <= T4_HEADS;
+    auto place = [&](int32_t k) __attribute__((always_inline)) {
+      if (!few) return out_slot(a.edge_head + my0, nout, k);
+      int32_t r = 0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) a.n[c][e] += 0.1 * nj.c[c];
+      for (int i = 0; i < T4_HEADS; ++i) r += hd[i] < k ? 1 : 0;
+      return r;
+    };
+    auto add = [&](int32_t s, const V4 &v) __attribute__((always_inline)) {
+      if (in_lds) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) lds_add4(&acc[c][base + s], v.c[c]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a.n[c][base + s] += v.c[c];
+      }
+    };
+    const V4 Pj = load_pt4(a.X, j);
+    double V = 0.0;
+    const int32_t r0 = a.node_inc_off[j], r1 = a.node_inc_off[j + 1];
+    constexpr int U = 2;
+    for (int32_t r = r0; r < r1; r += U) {
+      int32_t inc[U], v[U][5], o[U][4];
+      V4 Q[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u) inc[u] = a.node_inc[min(r + u, r1 - 1)];
+#pragma unroll
+      for (int u = 0; u < U; ++u) load_conn4(a.elem, inc[u] / 5, v[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        others_of4(v[u], inc[u] % 5, o[u]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) Q[u][m] = load_pt4(a.X, o[u][m]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (r + u >= r1) break;
+        double d;
+        const V4 nj = pent_face(Pj, Q[u], d);  // d = 4|E|
+        if (d == 0.0) raise_status(a.st, EB_EDEGENERATE, inc[u] / 5);
+        V += d * (1.0 / 20.0);
+        if (want_n)
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+            if (o[u][m] > j) add(place(o[u][m]), nj);
       }
     }
+    if (a.vol) a.vol[j] = V;
+    if (want_n && !in_lds)
+      for (int32_t s = 0; s < nout; ++s)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a.n[c][my0 + s] *= 0.1;
   }
-  if (a.vol) a.vol[j] = V;
+  if (in_lds) {
+    __syncthreads();
+    for (int i = t; i < cnt; i += T4_TN)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a.n[c][e0 + i] = 0.1 * acc[c][i];
+  }
 }
 
 // gather forward, boundary pass: n_B/20 into j's out-edges of each boundary
@@ -123,10 +191,14 @@ __global__ __launch_bounds__(256) void k4_fwd_boundary(Fwd4 a) {
     for (int c = 0; c < 4; ++c) a.b[c][bj] = bs[c];
 }
 
-// atomic forward: one thread per element
-__global__ __launch_bounds__(256) void k4_fwd_atomic_elem(Fwd4 a) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= a.nelem) return;
+// atomic forward: one thread per element; a block's 256 consecutive
+// elements sum their contributions per edge and per node in LDS hash tables
+// (1024 edge, 256 node slots), then add each sum with one FP64 atomic
+constexpr int A4_TB = 256, A4_HE = 1024, A4_HV = 256;
+
+// one element's contributions into the block's tables
+__device__ __forceinline__ void elem4_sums(const Fwd4 &a, int64_t e, LdsAcc<A4_HE, 4> &te,
+                                           LdsAcc<A4_HV, 1> &tv) {
   int32_t v[5];
   load_conn4(a.elem, e, v);
   V4 P[5], n[5];
@@ -151,13 +223,32 @@ __global__ __launch_bounds__(256) void k4_fwd_atomic_elem(Fwd4 a) {
       for (int q = p + 1; q < 5; ++q) {
         const V4 nt = v[p] < v[q] ? n[p] : n[q];
         const int32_t id = a.elem_edge[e * 10 + k++];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) unsafeAtomicAdd(&a.n[c][id], 0.1 * nt.c[c]);
+        const double c[4] = {0.1 * nt.c[0], 0.1 * nt.c[1], 0.1 * nt.c[2], 0.1 * nt.c[3]};
+        lds_acc_add(te, a.n, id, c);
       }
   }
-  if (a.vol)
+  if (a.vol) {
+    double *const vout[1] = {a.vol};
+    const double share[1] = {d * (1.0 / 20.0)};
 #pragma unroll
-    for (int i = 0; i < 5; ++i) unsafeAtomicAdd(&a.vol[v[i]], d * (1.0 / 20.0));
+    for (int i = 0; i < 5; ++i) lds_acc_add(tv, vout, v[i], share);
+  }
+}
+
+__global__ __launch_bounds__(A4_TB) void k4_fwd_atomic_elem(Fwd4 a) {
+  __shared__ LdsAcc<A4_HE, 4> te;
+  __shared__ LdsAcc<A4_HV, 1> tv;
+  const int t = threadIdx.x;
+  const bool want_n = a.n[0] != nullptr, want_v = a.vol != nullptr;
+  double *const vout[1] = {a.vol};
+  if (want_n) lds_acc_init<A4_TB>(te, t);
+  if (want_v) lds_acc_init<A4_TB>(tv, t);
+  __syncthreads();
+  const int64_t e = (int64_t)blockIdx.x * A4_TB + t;
+  if (e < a.nelem) elem4_sums(a, e, te, tv);
+  __syncthreads();
+  if (want_n) lds_acc_flush<A4_TB>(te, a.n, t);
+  if (want_v) lds_acc_flush<A4_TB>(tv, vout, t);
 }
 
 // atomic forward: one thread per boundary face
@@ -300,7 +391,7 @@ int forward4(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
     return EB_OK;
   }
   EB_TRY(need(a.node_inc_off && a.node_inc, "node_inc"));
-  launch_principal(k4_fwd_node, dim3(grid_for(a.nv, 256)), dim3(256), 0, s, a);
+  launch_principal(k4_fwd_tile, dim3(grid_for(a.nv, T4_TN)), dim3(T4_TN), 0, s, a);
   EB_LAUNCH_CHECK();
   if (a.nbnode > 0) {
     launch_span(k4_fwd_boundary, dim3(grid_for(a.nbnode, 256)), dim3(256), 0, s, a);
@@ -331,7 +422,7 @@ int volumes4(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
       return EB_OK;
     }
     EB_TRY(need(a.node_inc_off && a.node_inc, "node_inc"));
-    launch_principal(k4_fwd_node, dim3(grid_for(a.nv, 256)), dim3(256), 0, s, a);
+    launch_principal(k4_fwd_tile, dim3(grid_for(a.nv, T4_TN)), dim3(T4_TN), 0, s, a);
     EB_LAUNCH_CHECK();
     return EB_OK;
   }
