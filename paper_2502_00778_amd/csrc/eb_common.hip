@@ -238,49 +238,79 @@ int scan_inclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *total_de
 }
 
 // -------------------------------------------------------------- row sort
-// One thread per row; rows up to RS_CAP long are sorted in LDS (column per
-// thread, conflict-free), longer rows by insertion sort in global memory.
-constexpr int RS_BLOCK = 128;
+// One wavefront per 64 consecutive rows.  Rows up to RS_CAP long are sorted
+// by their own lane, by insertion in LDS (a column per lane, conflict-free);
+// longer rows then by the whole wave in turn, with a bitonic network over the
+// row padded to a power of two in LDS, and rows beyond RS_LONG by insertion
+// in global memory (lane 0).
 constexpr int RS_CAP = 32;
+constexpr int RS_LONG = RS_CAP * 64;
 
-__global__ __launch_bounds__(RS_BLOCK) void k_rowsort(const int32_t *off, int32_t *val,
-                                                      int64_t nrows) {
-  __shared__ int32_t buf[RS_CAP][RS_BLOCK];
+__global__ __launch_bounds__(64) void k_rowsort(const int32_t *off, int32_t *val,
+                                                int64_t nrows) {
+  __shared__ int32_t buf[RS_LONG];  // [RS_CAP][64] for the short rows
   const int t = threadIdx.x;
-  const int64_t row = (int64_t)blockIdx.x * RS_BLOCK + t;
-  if (row >= nrows) return;
-  const int32_t b = off[row], e = off[row + 1];
-  const int32_t len = e - b;
-  if (len <= 1) return;
-  if (len <= RS_CAP) {
-    for (int i = 0; i < len; ++i) buf[i][t] = val[b + i];
+  const int64_t row = (int64_t)blockIdx.x * 64 + t;
+  int32_t b = 0, len = 0;
+  if (row < nrows) {
+    b = off[row];
+    len = off[row + 1] - b;
+  }
+  if (len > 1 && len <= RS_CAP) {
+    for (int i = 0; i < len; ++i) buf[i * 64 + t] = val[b + i];
     for (int i = 1; i < len; ++i) {
-      int32_t x = buf[i][t];
+      const int32_t x = buf[i * 64 + t];
       int k = i - 1;
-      while (k >= 0 && buf[k][t] > x) {
-        buf[k + 1][t] = buf[k][t];
+      while (k >= 0 && buf[k * 64 + t] > x) {
+        buf[(k + 1) * 64 + t] = buf[k * 64 + t];
         --k;
       }
-      buf[k + 1][t] = x;
+      buf[(k + 1) * 64 + t] = x;
     }
-    for (int i = 0; i < len; ++i) val[b + i] = buf[i][t];
-  } else {
-    for (int32_t i = b + 1; i < e; ++i) {
-      int32_t x = val[i];
-      int32_t k = i - 1;
-      while (k >= b && val[k] > x) {
-        val[k + 1] = val[k];
-        --k;
+    for (int i = 0; i < len; ++i) val[b + i] = buf[i * 64 + t];
+  }
+  uint64_t todo = __builtin_amdgcn_ballot_w64(len > RS_CAP);
+  while (todo) {
+    const int r = __builtin_ctzll(todo);
+    todo &= todo - 1;
+    const int32_t rb = __shfl(b, r, 64), rl = __shfl(len, r, 64);
+    __syncthreads();  // (the stage is free)
+    if (rl > RS_LONG) {
+      if (t == 0)
+        for (int32_t i = rb + 1; i < rb + rl; ++i) {
+          const int32_t x = val[i];
+          int32_t k = i - 1;
+          while (k >= rb && val[k] > x) {
+            val[k + 1] = val[k];
+            --k;
+          }
+          val[k + 1] = x;
+        }
+      continue;
+    }
+    int P = 64;
+    while (P < rl) P <<= 1;
+    for (int i = t; i < P; i += 64) buf[i] = i < rl ? val[rb + i] : INT32_MAX;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1)
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = t; i < P / 2; i += 64) {
+          const int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1)), hi = lo + j;
+          const int32_t x = buf[lo], y = buf[hi];
+          if ((x > y) == ((lo & k) == 0)) {
+            buf[lo] = y;
+            buf[hi] = x;
+          }
+        }
+        __syncthreads();
       }
-      val[k + 1] = x;
-    }
+    for (int i = t; i < rl; i += 64) val[rb + i] = buf[i];
   }
 }
 
 int rowsort(const int32_t *off, int32_t *val, int64_t nrows, hipStream_t s) {
   if (nrows <= 0) return EB_OK;
-  hipLaunchKernelGGL(k_rowsort, dim3(grid_for(nrows, RS_BLOCK)), dim3(RS_BLOCK), 0, s, off,
-                     val, nrows);
+  hipLaunchKernelGGL(k_rowsort, dim3(grid_for(nrows, 64)), dim3(64), 0, s, off, val, nrows);
   EB_LAUNCH_CHECK();
   return EB_OK;
 }

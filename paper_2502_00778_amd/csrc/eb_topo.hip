@@ -1818,11 +1818,64 @@ __device__ __forceinline__ bool key_less(uint64_t ah, uint64_t al, uint64_t bh, 
   return ah < bh || (ah == bh && al < bl);
 }
 
+// the 4D outputs of one boundary face (vertices fv ascending, fv[0] the
+// node; inc the holding incidence; f its index): vertex order, owner and
+// the rows of the face's vertices
+__device__ __forceinline__ void emit_bface4(const TopoArgs &a, const Coords4 &X,
+                                            const int32_t (&fv)[4], int32_t inc, int32_t f) {
+  int32_t v[5];
+  load_conn4(a.elem, inc / 5, v);
+  // the owner's vertex off the face
+  int opp = 0;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    bool on = false;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) on = on || v[q] == fv[s];
+    if (!on) opp = q;
+  }
+  // outward order: the expression and operand order of the definition, FP64
+  // without contraction
+  bool keep;
+  {
+#pragma clang fp contract(off)
+    const V4 A = load_pt4(X, fv[0]);
+    const V4 N = v4_cross(v4_sub(load_pt4(X, fv[1]), A), v4_sub(load_pt4(X, fv[2]), A),
+                          v4_sub(load_pt4(X, fv[3]), A));
+    keep = v4_dot(N, v4_sub(A, load_pt4(X, v[opp]))) > 0;
+  }
+  int32_t *bf = a.bface + (int64_t)4 * f;
+  bf[0] = fv[0];
+  bf[1] = fv[1];
+  bf[2] = keep ? fv[2] : fv[3];
+  bf[3] = keep ? fv[3] : fv[2];
+  a.bface_owner[f] = (int32_t)((int64_t)(inc / 5) * 5 + opp);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int32_t pos = atomicSub(&a.bf_cur[fv[s]], 1) - 1;
+    a.bnode_face[pos] = f;
+  }
+}
+
+// The per-node passes by successive minima over the row (the form of the
+// general kernel): any row length and neighbour count.  ro: the row's other
+// vertices staged in LDS, or null to read them from the connectivity.
 template <bool EMIT>
-__device__ void node_topo4(const TopoArgs &a, int32_t j, int lane) {
+__device__ void node_topo4_rounds(const TopoArgs &a, int32_t j, int lane, const int4 *ro) {
   const int32_t r0 = a.node_inc_off[j], r1 = a.node_inc_off[j + 1];
   const int32_t len = r1 - r0;
   const Coords4 X{a.X.x, a.X.y, a.X.z, a.xw};
+  auto others_at = [&](int32_t i, int32_t (&o)[4]) __attribute__((always_inline)) {
+    if (ro) {
+      const int4 q = ro[i];
+      o[0] = q.x;
+      o[1] = q.y;
+      o[2] = q.z;
+      o[3] = q.w;
+    } else {
+      others4(a.elem, a.node_inc[r0 + i], o);
+    }
+  };
 
   // 1. distinct neighbours, ascending (as in the general kernel)
   int32_t e0 = 0, in_end = 0, nlow_known = 0;
@@ -1836,7 +1889,7 @@ __device__ void node_topo4(const TopoArgs &a, int32_t j, int lane) {
     int32_t mn = INT32_MAX;
     for (int32_t i = lane; i < len; i += 64) {
       int32_t o[4];
-      others4(a.elem, a.node_inc[r0 + i], o);
+      others_at(i, o);
 #pragma unroll
       for (int m = 0; m < 4; ++m)
         if (o[m] > last) mn = min(mn, o[m]);
@@ -1876,7 +1929,7 @@ __device__ void node_topo4(const TopoArgs &a, int32_t j, int lane) {
     int32_t cnt = 0, holder = INT32_MAX;
     for (int32_t i = lane; i < len; i += 64) {
       int32_t o[4];
-      others4(a.elem, a.node_inc[r0 + i], o);
+      others_at(i, o);
       uint64_t kh[4], kl[4];
       face_keys4(o, j, kh, kl);
 #pragma unroll
@@ -1911,39 +1964,7 @@ __device__ void node_topo4(const TopoArgs &a, int32_t j, int lane) {
               atomicAdd(&a.bfn[fv[s]], 1);
             }
           } else {
-            const int32_t inc = a.node_inc[r0 + holder];
-            int32_t v[5];
-            load_conn4(a.elem, inc / 5, v);
-            // the owner's vertex off the face
-            int opp = 0;
-#pragma unroll
-            for (int q = 0; q < 5; ++q) {
-              bool on = false;
-#pragma unroll
-              for (int s = 0; s < 4; ++s) on = on || v[q] == fv[s];
-              if (!on) opp = q;
-            }
-            // outward order: the expression and operand order of the
-            // definition, FP64 without contraction
-            bool keep;
-            {
-#pragma clang fp contract(off)
-              const V4 A = load_pt4(X, fv[0]);
-              const V4 N = v4_cross(v4_sub(load_pt4(X, fv[1]), A), v4_sub(load_pt4(X, fv[2]), A),
-                                    v4_sub(load_pt4(X, fv[3]), A));
-              keep = v4_dot(N, v4_sub(A, load_pt4(X, v[opp]))) > 0;
-            }
-            int32_t *bf = a.bface + (int64_t)4 * f;
-            bf[0] = fv[0];
-            bf[1] = fv[1];
-            bf[2] = keep ? fv[2] : fv[3];
-            bf[3] = keep ? fv[3] : fv[2];
-            a.bface_owner[f] = (int32_t)((int64_t)(inc / 5) * 5 + opp);
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-              const int32_t pos = atomicSub(&a.bf_cur[fv[s]], 1) - 1;
-              a.bnode_face[pos] = f;
-            }
+            emit_bface4(a, X, fv, a.node_inc[r0 + holder], f);
           }
         }
         ++nb;
@@ -1960,11 +1981,217 @@ __device__ void node_topo4(const TopoArgs &a, int32_t j, int lane) {
   }
 }
 
+// The per-node passes over LDS sets, for rows of at most R4_CAP incidences
+// with at most H4/2 distinct neighbours and H4/2 distinct candidate faces:
+// the neighbours go into an open-addressing set and are ranked by counting;
+// a candidate face is keyed by the ranks of its three vertices above the node
+// among those neighbours (8 bits each), counted in a second set together
+// with the sum of its holders' row positions (exact when it is held once).
+// Ranks keep vertex order, so both orders are those of the rounds form.
+constexpr int R4_CAP = 256;
+constexpr int H4_LOG = 9, H4 = 1 << H4_LOG;
+constexpr uint32_t H4_EMPTY = ~0u;
+
+struct Topo4Lds {
+  int4 ro[R4_CAP];     // the row's other vertices
+  uint32_t nk[H4];     // neighbour set
+  int32_t nr[H4];      // a neighbour's rank among the distinct neighbours
+  int32_t tl[H4 / 2];  // the distinct neighbours in set order
+  int32_t ts[H4 / 2];  // and their set slots
+  int32_t sn[H4 / 2];  // the distinct neighbours ascending
+  uint32_t fk[H4];     // candidate face set (rank triples)
+  uint32_t fc[H4];     // count << 16 plus the sum of the holders' row positions
+  uint32_t bl[H4 / 2]; // faces held once: key << 8 | position
+  int32_t n_nb, n_face, over;
+};
+
+__device__ __forceinline__ uint32_t h4_slot(uint32_t k) {
+  return (k * 2654435761u) >> (32 - H4_LOG);
+}
+
+// k's slot in tab, inserted when absent (counting it in *count); -1 and
+// *over set when the set is full
+__device__ __forceinline__ int h4_insert(uint32_t *tab, uint32_t k, int32_t *count,
+                                         int32_t *over) {
+  uint32_t h = h4_slot(k);
+  for (int p = 0; p < H4; ++p) {
+    const uint32_t old = atomicCAS(&tab[h], H4_EMPTY, k);
+    if (old == H4_EMPTY) {
+      atomicAdd(count, 1);
+      return (int)h;
+    }
+    if (old == k) return (int)h;
+    h = (h + 1) & (H4 - 1);
+  }
+  *over = 1;
+  return -1;
+}
+
+// the slot of k, present in tab
+__device__ __forceinline__ int h4_find(const uint32_t *tab, uint32_t k) {
+  uint32_t h = h4_slot(k);
+  for (int p = 0; p < H4 && tab[h] != k; ++p) h = (h + 1) & (H4 - 1);
+  return (int)h;
+}
+
+// false (and nothing written) when the row does not fit the sets
+template <bool EMIT>
+__device__ bool node_topo4_sets(const TopoArgs &a, int32_t j, int lane, int32_t r0, int32_t len,
+                                Topo4Lds &L) {
+  const Coords4 X{a.X.x, a.X.y, a.X.z, a.xw};
+  const uint64_t below = (1ull << lane) - 1;
+  for (int s = lane; s < H4; s += 64) {
+    L.nk[s] = H4_EMPTY;
+    L.fk[s] = H4_EMPTY;
+    L.fc[s] = 0;
+  }
+  if (lane == 0) {
+    L.n_nb = 0;
+    L.n_face = 0;
+    L.over = 0;
+  }
+  __syncthreads();
+  // 1. the distinct neighbours
+  for (int32_t i = lane; i < len; i += 64) {
+    const int4 q = L.ro[i];
+    h4_insert(L.nk, (uint32_t)q.x, &L.n_nb, &L.over);
+    h4_insert(L.nk, (uint32_t)q.y, &L.n_nb, &L.over);
+    h4_insert(L.nk, (uint32_t)q.z, &L.n_nb, &L.over);
+    h4_insert(L.nk, (uint32_t)q.w, &L.n_nb, &L.over);
+  }
+  __syncthreads();
+  const int32_t nd = L.n_nb;
+  if (L.over || nd > H4 / 2) return false;
+  int32_t nlow = 0;
+  {
+    int32_t base = 0;
+    for (int s0 = 0; s0 < H4; s0 += 64) {
+      const uint32_t v = L.nk[s0 + lane];
+      const bool has = v != H4_EMPTY;
+      const uint64_t m = __builtin_amdgcn_ballot_w64(has);
+      const int pos = base + __builtin_popcountll(m & below);
+      if (has) {
+        L.tl[pos] = (int32_t)v;
+        L.ts[pos] = s0 + lane;
+      }
+      base += __builtin_popcountll(m);
+      nlow += __builtin_popcountll(__builtin_amdgcn_ballot_w64(has && (int32_t)v < j));
+    }
+  }
+  __syncthreads();
+  for (int32_t idx = lane; idx < nd; idx += 64) {
+    const int32_t v = L.tl[idx];
+    int32_t r = 0;
+    for (int32_t u = 0; u < nd; ++u) r += L.tl[u] < v ? 1 : 0;
+    L.nr[L.ts[idx]] = r;
+    L.sn[r] = v;
+  }
+  __syncthreads();
+  // 2. candidate faces with the node as smallest vertex
+  for (int32_t i = lane; i < len; i += 64) {
+    const int4 q = L.ro[i];
+    const int32_t o[4] = {q.x, q.y, q.z, q.w};
+    int32_t ru[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      ru[m] = o[m] > j ? L.nr[h4_find(L.nk, (uint32_t)o[m])] - nlow : -1;
+#pragma unroll
+    for (int drop = 0; drop < 4; ++drop) {
+      int32_t t[3];
+      int n = 0;
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        if (m != drop) t[n++] = ru[m];
+      const int32_t x = min(t[0], t[1]), y = max(t[0], t[1]), z = t[2];
+      const int32_t lo = min(x, z), hi = max(y, z), mid = max(x, min(y, z));
+      if (lo < 0) continue;
+      const int s = h4_insert(L.fk, (uint32_t)(lo << 16 | mid << 8 | hi), &L.n_face, &L.over);
+      if (s >= 0) atomicAdd(&L.fc[s], 0x10000u + (uint32_t)i);
+    }
+  }
+  __syncthreads();
+  if (L.over || L.n_face > H4 / 2) return false;
+
+  // the neighbours' outputs
+  if constexpr (EMIT) {
+    const int32_t e0 = a.eoff[j], in_end = a.in_cur[j];
+    const int32_t nlow_known = a.ein_scan[j] - (j > 0 ? a.ein_scan[j - 1] : 0);
+    for (int32_t r = lane; r < nd; r += 64) {
+      const int32_t v = L.sn[r];
+      if (v < j) {
+        a.node_in_edge[in_end - nlow_known + r] = v;
+      } else {
+        a.edge_tail[e0 + r - nlow] = j;
+        a.edge_head[e0 + r - nlow] = v;
+      }
+    }
+    if (lane == 0) a.in_cur[j] = in_end - nlow;
+  } else if (lane == 0) {
+    a.outdeg[j] = nd - nlow;
+    a.ein[j] = nlow;
+  }
+
+  // the faces held once, and any held more than twice
+  int32_t nb = 0;
+  bool bad = false;
+  for (int s0 = 0; s0 < H4; s0 += 64) {
+    const uint32_t k = L.fk[s0 + lane], c = L.fc[s0 + lane];
+    const bool has = k != H4_EMPTY;
+    bad = bad || (has && (c >> 16) > 2);
+    const bool once = has && (c >> 16) == 1;
+    const uint64_t m = __builtin_amdgcn_ballot_w64(once);
+    if (once) L.bl[nb + __builtin_popcountll(m & below)] = k << 8 | (c & 0xFFu);
+    nb += __builtin_popcountll(m);
+  }
+  if (__builtin_amdgcn_ballot_w64(bad) != 0) {
+    if (lane == 0) raise_status(a.st, EB_ENONMANIFOLD, j);
+    return true;
+  }
+  __syncthreads();
+  const int32_t f0 = EMIT ? a.foff[j] : 0;
+  for (int32_t idx = lane; idx < nb; idx += 64) {
+    const uint32_t b = L.bl[idx], k = b >> 8;
+    const int32_t fv[4] = {j, L.sn[nlow + (int32_t)(k >> 16)],
+                           L.sn[nlow + (int32_t)((k >> 8) & 0xFFu)],
+                           L.sn[nlow + (int32_t)(k & 0xFFu)]};
+    if constexpr (!EMIT) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        a.bflag[fv[s]] = 1;
+        atomicAdd(&a.bfn[fv[s]], 1);
+      }
+    } else {
+      int32_t r = 0;
+      for (int32_t u = 0; u < nb; ++u) r += L.bl[u] < b ? 1 : 0;
+      emit_bface4(a, X, fv, a.node_inc[r0 + (int32_t)(b & 0xFFu)], f0 + r);
+    }
+  }
+  if constexpr (!EMIT) {
+    if (lane == 0) a.fmin[j] = nb;
+  }
+  return true;
+}
+
 template <bool EMIT>
 __global__ __launch_bounds__(64) void k4_node_topo(TopoArgs a) {
+  __shared__ Topo4Lds L;
   if (build_failed(a.st)) return;
-  for (int64_t j = blockIdx.x; j < a.nv; j += gridDim.x)
-    node_topo4<EMIT>(a, (int32_t)j, (int)threadIdx.x);
+  const int lane = (int)threadIdx.x;
+  for (int64_t jj = blockIdx.x; jj < a.nv; jj += gridDim.x) {
+    const int32_t j = (int32_t)jj;
+    const int32_t r0 = a.node_inc_off[j], len = a.node_inc_off[j + 1] - r0;
+    const bool staged = len <= R4_CAP;
+    __syncthreads();  // (the previous node is done with the LDS)
+    if (staged)
+      for (int32_t i = lane; i < len; i += 64) {
+        int32_t o[4];
+        others4(a.elem, a.node_inc[r0 + i], o);
+        L.ro[i] = make_int4(o[0], o[1], o[2], o[3]);
+      }
+    __syncthreads();
+    if (!staged || !node_topo4_sets<EMIT>(a, j, lane, r0, len, L))
+      node_topo4_rounds<EMIT>(a, j, lane, staged ? L.ro : nullptr);
+  }
 }
 
 // element -> edge map and signs: the ten local pairs in lexicographic order

@@ -53,12 +53,43 @@ def single():
     return meshgen.Mesh(4, X, np.array([[3, 0, 4, 2, 1]], np.int32), "pent")
 
 
+def cone(n, seed, apex_first):
+    """Pentatopes coning the tetrahedra of an n^3 cube grid to one apex: the
+    apex's row holds every tetrahedron and, as node 0, every triangle makes a
+    candidate face of it (the kernel's row-length and face-count limits)."""
+    m3 = meshgen.cube_kuhn(n, seed)
+    nv = m3.n_nodes
+    a = 0 if apex_first else nv
+    rest = np.arange(1, nv + 1) if apex_first else np.arange(nv)
+    X = np.zeros((4, nv + 1))
+    X[:3, rest] = m3.coords
+    X[:, a] = (0.5, 0.5, 0.5, 1.0)
+    E = np.concatenate([np.full((m3.n_elems, 1), a), m3.elems[:, ::-1] + (1 if apex_first else 0)],
+                       axis=1)
+    return meshgen.Mesh(4, X, np.ascontiguousarray(E, dtype=np.int32), f"cone{n}")
+
+
+def star(k, seed):
+    """k pentatopes sharing only node 0, each with four vertices of its own
+    at random: 4k distinct neighbours (the kernel's neighbour-count limit)."""
+    rng = np.random.default_rng(seed)
+    X = np.concatenate([np.zeros((4, 1)), rng.normal(size=(4, 4 * k))], axis=1)
+    E = np.concatenate([np.zeros((k, 1), np.int64), 1 + np.arange(4 * k).reshape(k, 4)], axis=1)
+    return meshgen.Mesh(4, X, np.ascontiguousarray(E, dtype=np.int32), f"star{k}")
+
+
 CASES = {
     "4d-single": single,
     "4d-5": lambda: meshgen.hypercube_kuhn(5, 0),
     "4d-9": lambda: meshgen.hypercube_kuhn(9, 1),
     "4d-7-shuf": lambda: shuffled(meshgen.hypercube_kuhn(7, 2), 3),
     "4d-6-relabel": lambda: relabelled(meshgen.hypercube_kuhn(6, 4), 5),
+    # node rows beyond the LDS limits: 162 incidences with 378 candidate
+    # faces; 384 incidences; 280 distinct neighbours; the apex as last node
+    "4d-cone-4": lambda: cone(4, 6, True),
+    "4d-cone-5": lambda: cone(5, 7, True),
+    "4d-star-70": lambda: star(70, 8),
+    "4d-cone-5-last": lambda: cone(5, 9, False),
 }
 _cache = {}
 
