@@ -13,10 +13,10 @@
 // the node, and adds it to its out-edges' accumulators in LDS (the tile's
 // out-edges are contiguous; a node's edge found among its first 16 heads,
 // held in registers, or by binary search beyond), in row order; the tile's
-// edges are written once.  A boundary pass per boundary node follows.  The
-// atomic forward sums each block's element contributions per edge and per
-// node in LDS hash tables first, then adds each sum with one FP64 atomic,
-// and scatters per boundary face.
+// edges are written once.  A boundary pass, a wavefront per boundary node,
+// follows.  The atomic forward sums each block's element contributions per
+// edge and per node in LDS hash tables first, then adds each sum with one
+// FP64 atomic, and its boundary faces likewise.
 #include "eb_geom.h"  // (the LDS hash tables of the atomic pass)
 #include "eb_geom4.h"
 #include "eb_kernels.h"
@@ -155,40 +155,67 @@ __global__ __launch_bounds__(T4_TN) void k4_fwd_tile(Fwd4 a) {
   }
 }
 
-// gather forward, boundary pass: n_B/20 into j's out-edges of each boundary
-// face B of j, b_j = sum n_B/4, in bnode_face order
-__global__ __launch_bounds__(256) void k4_fwd_boundary(Fwd4 a) {
-  const int64_t bj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (bj >= a.nbnode) return;
+// gather forward, boundary pass: a wave per boundary node.  Its faces' n_B
+// are formed a lane each (B4_CAP at a time, in bnode_face order) and kept in
+// LDS; then each lane takes out-edges of the node and adds n_B/20 of the
+// faces holding the edge's head, in that order, and lanes 0..3 sum the
+// components of b_j = sum n_B/4 likewise: every output gets the additions,
+// in the order, of a walk over the node's faces.
+constexpr int B4_CAP = 64;
+
+__global__ __launch_bounds__(64) void k4_fwd_boundary(Fwd4 a) {
+  __shared__ double snb[4][B4_CAP];
+  __shared__ int32_t sfv[4][B4_CAP];
+  const int lane = threadIdx.x;
+  const int64_t bj = blockIdx.x;
   const int32_t j = a.bnode[bj];
   const int32_t e0 = a.node_edge_off[j], nout = a.node_edge_off[j + 1] - e0;
-  double bs[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int32_t r = a.bnode_face_off[bj]; r < a.bnode_face_off[bj + 1]; ++r) {
-    const int32_t f = a.bnode_face[r];
-    int32_t fv[4];
-    V4 Q[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      fv[s] = a.bface[4 * (int64_t)f + s];
-      Q[s] = load_pt4(a.X, fv[s]);
-    }
-    const V4 nB =
-        v4_scale(1.0 / 6.0, v4_cross(v4_sub(Q[1], Q[0]), v4_sub(Q[2], Q[0]), v4_sub(Q[3], Q[0])));
-#pragma unroll
-    for (int c = 0; c < 4; ++c) bs[c] += 0.25 * nB.c[c];
-    if (a.n[0]) {
+  const int32_t f0 = a.bnode_face_off[bj], nf = a.bnode_face_off[bj + 1] - f0;
+  const bool want_n = a.n[0] != nullptr;
+  double bs = 0.0;  // component `lane` of b_j (lanes 0..3)
+  for (int32_t c0 = 0; c0 < nf; c0 += B4_CAP) {
+    const int32_t m = min(nf - c0, B4_CAP);
+    __syncthreads();  // (the previous chunk is used up)
+    if (lane < m) {
+      const int32_t f = a.bnode_face[f0 + c0 + lane];
+      int32_t fv[4];
+      V4 Q[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        if (fv[s] <= j) continue;
-        const int32_t e = e0 + out_slot(a.edge_head + e0, nout, fv[s]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) a.n[c][e] += 0.05 * nB.c[c];
+        fv[s] = a.bface[4 * (int64_t)f + s];
+        Q[s] = load_pt4(a.X, fv[s]);
       }
-    }
-  }
-  if (a.b[0])
+      const V4 nB = v4_scale(
+          1.0 / 6.0, v4_cross(v4_sub(Q[1], Q[0]), v4_sub(Q[2], Q[0]), v4_sub(Q[3], Q[0])));
 #pragma unroll
-    for (int c = 0; c < 4; ++c) a.b[c][bj] = bs[c];
+      for (int c = 0; c < 4; ++c) snb[c][lane] = nB.c[c];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) sfv[s][lane] = fv[s];
+    }
+    __syncthreads();
+    if (lane < 4)
+      for (int32_t i = 0; i < m; ++i) bs += 0.25 * snb[lane][i];
+    if (want_n)
+      for (int32_t s = lane; s < nout; s += 64) {
+        const int32_t h = a.edge_head[e0 + s];
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        bool any = false;
+        for (int32_t i = 0; i < m; ++i) {
+          if (sfv[0][i] != h && sfv[1][i] != h && sfv[2][i] != h && sfv[3][i] != h) continue;
+          if (!any) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] = a.n[c][e0 + s];
+            any = true;
+          }
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[c] += 0.05 * snb[c][i];
+        }
+        if (any)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) a.n[c][e0 + s] = acc[c];
+      }
+  }
+  if (a.b[0] && lane < 4) a.b[lane][bj] = bs;
 }
 
 // atomic forward: one thread per element; a block's 256 consecutive
@@ -251,33 +278,45 @@ __global__ __launch_bounds__(A4_TB) void k4_fwd_atomic_elem(Fwd4 a) {
   if (want_v) lds_acc_flush<A4_TB>(tv, vout, t);
 }
 
-// atomic forward: one thread per boundary face
-__global__ __launch_bounds__(256) void k4_fwd_atomic_bface(Fwd4 a) {
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= a.nbface) return;
-  int32_t fv[4];
-  V4 Q[4];
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    fv[s] = a.bface[4 * f + s];
-    Q[s] = load_pt4(a.X, fv[s]);
-  }
-  const V4 nB =
-      v4_scale(1.0 / 6.0, v4_cross(v4_sub(Q[1], Q[0]), v4_sub(Q[2], Q[0]), v4_sub(Q[3], Q[0])));
-  if (a.n[0])
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const int32_t id = a.bface_edge[6 * f + k];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) unsafeAtomicAdd(&a.n[c][id], 0.05 * nB.c[c]);
-    }
-  if (a.b[0])
+// atomic forward, boundary faces: a thread per face; a block's faces (in
+// bface order, consecutive ones sharing most vertices) sum their n_B/20 per
+// edge and n_B/4 per boundary node in LDS tables first, then add each sum
+// with one FP64 atomic
+constexpr int AB4_TB = 256, AB4_HE = 1024, AB4_HB = 256;
+
+__global__ __launch_bounds__(AB4_TB) void k4_fwd_atomic_bface(Fwd4 a) {
+  __shared__ LdsAcc<AB4_HE, 4> te;
+  __shared__ LdsAcc<AB4_HB, 4> tb;
+  const int t = threadIdx.x;
+  const bool want_n = a.n[0] != nullptr, want_b = a.b[0] != nullptr;
+  if (want_n) lds_acc_init<AB4_TB>(te, t);
+  if (want_b) lds_acc_init<AB4_TB>(tb, t);
+  __syncthreads();
+  const int64_t f = (int64_t)blockIdx.x * AB4_TB + t;
+  if (f < a.nbface) {
+    int32_t fv[4];
+    V4 Q[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const int32_t bi = a.node_bnode[fv[s]];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) unsafeAtomicAdd(&a.b[c][bi], 0.25 * nB.c[c]);
+      fv[s] = a.bface[4 * f + s];
+      Q[s] = load_pt4(a.X, fv[s]);
     }
+    const V4 nB =
+        v4_scale(1.0 / 6.0, v4_cross(v4_sub(Q[1], Q[0]), v4_sub(Q[2], Q[0]), v4_sub(Q[3], Q[0])));
+    if (want_n) {
+      const double c[4] = {0.05 * nB.c[0], 0.05 * nB.c[1], 0.05 * nB.c[2], 0.05 * nB.c[3]};
+#pragma unroll
+      for (int k = 0; k < 6; ++k) lds_acc_add(te, a.n, a.bface_edge[6 * f + k], c);
+    }
+    if (want_b) {
+      const double c[4] = {0.25 * nB.c[0], 0.25 * nB.c[1], 0.25 * nB.c[2], 0.25 * nB.c[3]};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) lds_acc_add(tb, a.b, a.node_bnode[fv[s]], c);
+    }
+  }
+  __syncthreads();
+  if (want_n) lds_acc_flush<AB4_TB>(te, a.n, t);
+  if (want_b) lds_acc_flush<AB4_TB>(tb, a.b, t);
 }
 
 // edge loop: t_e = (x_head - x_tail).n_e / 8, then each node's ordered sum
@@ -394,7 +433,7 @@ int forward4(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
   launch_principal(k4_fwd_tile, dim3(grid_for(a.nv, T4_TN)), dim3(T4_TN), 0, s, a);
   EB_LAUNCH_CHECK();
   if (a.nbnode > 0) {
-    launch_span(k4_fwd_boundary, dim3(grid_for(a.nbnode, 256)), dim3(256), 0, s, a);
+    launch_span(k4_fwd_boundary, dim3((unsigned)a.nbnode), dim3(64), 0, s, a);
     EB_LAUNCH_CHECK();
   }
   return EB_OK;

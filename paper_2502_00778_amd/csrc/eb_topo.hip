@@ -1739,48 +1739,107 @@ __global__ void k_scatter_edge_inc(int64_t nelem, const int32_t *__restrict__ el
 // ------------------------------------------------ four dimensions (dim = 4)
 //
 // Pentatope grids take a plain form of the build: node rows by a counting
-// sort (global atomics), rows sorted, and every node through one wavefront
-// like the general kernel above, the other vertices of each incidence read
-// from the connectivity.  No kernel plan is made: the dim-4 metric kernels
-// walk node_inc directly.  The outputs are the same arrays, with the same
+// sort (block-aggregated atomics), rows sorted, and every node through one
+// wavefront, its row's other vertices staged in LDS and its neighbours and
+// candidate faces kept in LDS sets (the general kernel's successive minima
+// beyond the sets' limits).  No kernel plan is made: the dim-4 metric
+// kernels walk node_inc directly.  The outputs are the same arrays, with the same
 // unique definitions; a boundary face (a tetrahedron) lists its vertices
 // ascending, with the last two swapped when that order's area vector
 // N(b-a, c-a, d-a) points into the domain.
 
-__global__ void k4_count(const int32_t *__restrict__ elem, int64_t nelem, int64_t nv,
-                         Coords4 X, int32_t *cnt, StatusBlock *st) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nelem) return;
-  int32_t v[5];
-  load_conn4(elem, e, v);
-  bool ok = true;
-#pragma unroll
-  for (int i = 0; i < 5; ++i) ok = ok && v[i] >= 0 && v[i] < nv;
-  if (!ok) {
-    raise_status(st, EB_ERANGE, e);
-    return;
+// The node counts and the scatter aggregate per block in LDS like the
+// general passes above (AGG_EPT elements a thread, one global atomic per
+// distinct node of the block).
+__global__ __launch_bounds__(AGG_TB) void k4_count(const int32_t *__restrict__ elem,
+                                                   int64_t nelem, int64_t nv, Coords4 X,
+                                                   int32_t *cnt, StatusBlock *st) {
+  __shared__ int32_t hk[AGG_HT], hc[AGG_HT];
+  for (int i = threadIdx.x; i < AGG_HT; i += AGG_TB) {
+    hk[i] = -1;
+    hc[i] = 0;
   }
-  V4 P[5];
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * AGG_TB * AGG_EPT + threadIdx.x;
+#pragma unroll 1
+  for (int k = 0; k < AGG_EPT; ++k) {
+    const int64_t e = base + (int64_t)k * AGG_TB;
+    if (e >= nelem) continue;
+    int32_t v[5];
+    load_conn4(elem, e, v);
+    bool ok = true;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) P[i] = load_pt4(X, v[i]);
-  if (pent_det(P) == 0.0) raise_status(st, EB_EDEGENERATE, e);
+    for (int i = 0; i < 5; ++i) ok = ok && v[i] >= 0 && v[i] < nv;
+    if (!ok) {
+      raise_status(st, EB_ERANGE, e);
+      continue;
+    }
+    V4 P[5];
 #pragma unroll
-  for (int i = 0; i < 5; ++i) atomicAdd(&cnt[v[i]], 1);
+    for (int i = 0; i < 5; ++i) P[i] = load_pt4(X, v[i]);
+    if (pent_det(P) == 0.0) raise_status(st, EB_EDEGENERATE, e);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      const int h = agg_slot(hk, v[i]);
+      if (h >= 0) atomicAdd(&hc[h], 1);
+      else atomicAdd(&cnt[v[i]], 1);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < AGG_HT; i += AGG_TB)
+    if (hk[i] >= 0) atomicAdd(&cnt[hk[i]], hc[i]);
 }
 
-// cur: the rows' end offsets, taken down to their starts
-__global__ void k4_scatter(const int32_t *__restrict__ elem, int64_t nelem, int64_t nv,
-                           int32_t *cur, int32_t *node_inc) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nelem) return;
-  int32_t v[5];
-  load_conn4(elem, e, v);
-  bool ok = true;
+// cur: the rows' end offsets, taken down to their starts (a range per block
+// and node; the rows are sorted afterwards)
+__global__ __launch_bounds__(AGG_TB) void k4_scatter(const int32_t *__restrict__ elem,
+                                                     int64_t nelem, int64_t nv, int32_t *cur,
+                                                     int32_t *node_inc) {
+  __shared__ int32_t hk[AGG_HT], hc[AGG_HT];
+  for (int i = threadIdx.x; i < AGG_HT; i += AGG_TB) {
+    hk[i] = -1;
+    hc[i] = 0;
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * AGG_TB * AGG_EPT + threadIdx.x;
+  int32_t slot[AGG_EPT][5], rank[AGG_EPT][5];
 #pragma unroll
-  for (int i = 0; i < 5; ++i) ok = ok && v[i] >= 0 && v[i] < nv;
-  if (!ok) return;
+  for (int k = 0; k < AGG_EPT; ++k) {
+    const int64_t e = base + (int64_t)k * AGG_TB;
+    int32_t v[5];
+    bool ok = e < nelem;
+    if (ok) {
+      load_conn4(elem, e, v);
 #pragma unroll
-  for (int i = 0; i < 5; ++i) node_inc[atomicSub(&cur[v[i]], 1) - 1] = (int32_t)(e * 5 + i);
+      for (int i = 0; i < 5; ++i) ok = ok && v[i] >= 0 && v[i] < nv;
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      slot[k][i] = -1;
+      if (!ok) continue;
+      const int h = agg_slot(hk, v[i]);
+      if (h >= 0) {
+        slot[k][i] = h;
+        rank[k][i] = atomicAdd(&hc[h], 1);
+      } else {
+        node_inc[atomicSub(&cur[v[i]], 1) - 1] = (int32_t)(e * 5 + i);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < AGG_HT; i += AGG_TB)
+    if (hk[i] >= 0) {
+      const int32_t c = hc[i];
+      hc[i] = atomicSub(&cur[hk[i]], c) - c;
+    }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < AGG_EPT; ++k) {
+    const int64_t e = base + (int64_t)k * AGG_TB;
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+      if (slot[k][i] >= 0) node_inc[hc[slot[k][i]] + rank[k][i]] = (int32_t)(e * 5 + i);
+  }
 }
 
 // the other vertices of incidence elem*5 + l (local order, l's place taken
@@ -2487,14 +2546,14 @@ int build4_impl(int64_t nv, int64_t nelem, const int32_t *elem, const double *co
   EB_TRY(fill_i32(eoff, (int64_t)((L.scan_tmp - L.eoff) / 4), 0, s));
   EB_TRY(fill_i32(node_inc_off, nv + 1, 0, s));
   if (nelem > 0) {
-    hipLaunchKernelGGL(k4_count, dim3(grid_for(nelem, 256)), dim3(256), 0, s, elem, nelem, nv, X,
-                       node_inc_off, st);
+    hipLaunchKernelGGL(k4_count, dim3(grid_for(nelem, AGG_TB * AGG_EPT)), dim3(AGG_TB), 0, s,
+                       elem, nelem, nv, X, node_inc_off, st);
     EB_LAUNCH_CHECK();
   }
   EB_TRY(scan_inclusive(node_inc_off, node_inc_off, nv, node_inc_off + nv, tmp, s));
   if (nelem > 0) {
-    hipLaunchKernelGGL(k4_scatter, dim3(grid_for(nelem, 256)), dim3(256), 0, s, elem, nelem, nv,
-                       node_inc_off, node_inc);
+    hipLaunchKernelGGL(k4_scatter, dim3(grid_for(nelem, AGG_TB * AGG_EPT)), dim3(AGG_TB), 0, s,
+                       elem, nelem, nv, node_inc_off, node_inc);
     EB_LAUNCH_CHECK();
     EB_TRY(rowsort(node_inc_off, node_inc, nv, s));
   }
