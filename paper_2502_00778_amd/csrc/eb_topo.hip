@@ -2047,20 +2047,24 @@ __device__ void node_topo4_rounds(const TopoArgs &a, int32_t j, int lane, const 
 // among those neighbours (8 bits each), counted in a second set together
 // with the sum of its holders' row positions (exact when it is held once).
 // Ranks keep vertex order, so both orders are those of the rounds form.
-constexpr int R4_CAP = 256;
-constexpr int H4_LOG = 9, H4 = 1 << H4_LOG;
+// (The sizes keep a block's LDS near 9 KB: four resident waves per SIMD.)
+constexpr int R4_CAP = 192;
+constexpr int H4_LOG = 8, H4 = 1 << H4_LOG;
 constexpr uint32_t H4_EMPTY = ~0u;
 
 struct Topo4Lds {
   int4 ro[R4_CAP];     // the row's other vertices
-  uint32_t nk[H4];     // neighbour set
+  ushort4 sl[R4_CAP];  // and their slots in the neighbour set
   int32_t nr[H4];      // a neighbour's rank among the distinct neighbours
-  int32_t tl[H4 / 2];  // the distinct neighbours in set order
-  int32_t ts[H4 / 2];  // and their set slots
   int32_t sn[H4 / 2];  // the distinct neighbours ascending
-  uint32_t fk[H4];     // candidate face set (rank triples)
-  uint32_t fc[H4];     // count << 16 plus the sum of the holders' row positions
-  uint32_t bl[H4 / 2]; // faces held once: key << 8 | position
+  // the neighbour set nk [H4]; once ranked, the candidate face set fk [H4]
+  // (rank triples) and fc [H4] (count << 16 plus the sum of the holders'
+  // row positions)
+  uint32_t sets[2 * H4];
+  // the distinct neighbours in set order tl [H4/2 + 4] (padded to fours)
+  // and their slots ts [H4/2]; later the faces held once bl [H4/2]
+  // (key << 8 | position)
+  __align__(16) int32_t lists[H4 + 4];
   int32_t n_nb, n_face, over;
 };
 
@@ -2086,24 +2090,16 @@ __device__ __forceinline__ int h4_insert(uint32_t *tab, uint32_t k, int32_t *cou
   return -1;
 }
 
-// the slot of k, present in tab
-__device__ __forceinline__ int h4_find(const uint32_t *tab, uint32_t k) {
-  uint32_t h = h4_slot(k);
-  for (int p = 0; p < H4 && tab[h] != k; ++p) h = (h + 1) & (H4 - 1);
-  return (int)h;
-}
-
 // false (and nothing written) when the row does not fit the sets
 template <bool EMIT>
 __device__ bool node_topo4_sets(const TopoArgs &a, int32_t j, int lane, int32_t r0, int32_t len,
                                 Topo4Lds &L) {
   const Coords4 X{a.X.x, a.X.y, a.X.z, a.xw};
   const uint64_t below = (1ull << lane) - 1;
-  for (int s = lane; s < H4; s += 64) {
-    L.nk[s] = H4_EMPTY;
-    L.fk[s] = H4_EMPTY;
-    L.fc[s] = 0;
-  }
+  uint32_t *const nk = L.sets, *const fk = L.sets, *const fc = L.sets + H4;
+  int32_t *const tl = L.lists, *const ts = L.lists + H4 / 2 + 4;
+  uint32_t *const bl = reinterpret_cast<uint32_t *>(L.lists);
+  for (int s = lane; s < H4; s += 64) nk[s] = H4_EMPTY;
   if (lane == 0) {
     L.n_nb = 0;
     L.n_face = 0;
@@ -2113,10 +2109,11 @@ __device__ bool node_topo4_sets(const TopoArgs &a, int32_t j, int lane, int32_t 
   // 1. the distinct neighbours
   for (int32_t i = lane; i < len; i += 64) {
     const int4 q = L.ro[i];
-    h4_insert(L.nk, (uint32_t)q.x, &L.n_nb, &L.over);
-    h4_insert(L.nk, (uint32_t)q.y, &L.n_nb, &L.over);
-    h4_insert(L.nk, (uint32_t)q.z, &L.n_nb, &L.over);
-    h4_insert(L.nk, (uint32_t)q.w, &L.n_nb, &L.over);
+    // (a slot of -1, the set full, is never read: the row falls back)
+    L.sl[i] = make_ushort4((uint16_t)h4_insert(nk, (uint32_t)q.x, &L.n_nb, &L.over),
+                           (uint16_t)h4_insert(nk, (uint32_t)q.y, &L.n_nb, &L.over),
+                           (uint16_t)h4_insert(nk, (uint32_t)q.z, &L.n_nb, &L.over),
+                           (uint16_t)h4_insert(nk, (uint32_t)q.w, &L.n_nb, &L.over));
   }
   __syncthreads();
   const int32_t nd = L.n_nb;
@@ -2125,35 +2122,45 @@ __device__ bool node_topo4_sets(const TopoArgs &a, int32_t j, int lane, int32_t 
   {
     int32_t base = 0;
     for (int s0 = 0; s0 < H4; s0 += 64) {
-      const uint32_t v = L.nk[s0 + lane];
+      const uint32_t v = nk[s0 + lane];
       const bool has = v != H4_EMPTY;
       const uint64_t m = __builtin_amdgcn_ballot_w64(has);
       const int pos = base + __builtin_popcountll(m & below);
       if (has) {
-        L.tl[pos] = (int32_t)v;
-        L.ts[pos] = s0 + lane;
+        tl[pos] = (int32_t)v;
+        ts[pos] = s0 + lane;
       }
       base += __builtin_popcountll(m);
       nlow += __builtin_popcountll(__builtin_amdgcn_ballot_w64(has && (int32_t)v < j));
     }
+    if (lane < 4) tl[nd + lane] = INT32_MAX;
   }
   __syncthreads();
+  const int4 *const tl4 = reinterpret_cast<const int4 *>(tl);
   for (int32_t idx = lane; idx < nd; idx += 64) {
-    const int32_t v = L.tl[idx];
+    const int32_t v = tl[idx];
     int32_t r = 0;
-    for (int32_t u = 0; u < nd; ++u) r += L.tl[u] < v ? 1 : 0;
-    L.nr[L.ts[idx]] = r;
+    for (int32_t u = 0; u < nd; u += 4) {
+      const int4 w = tl4[u >> 2];
+      r += (w.x < v ? 1 : 0) + (w.y < v ? 1 : 0) + (w.z < v ? 1 : 0) + (w.w < v ? 1 : 0);
+    }
+    L.nr[ts[idx]] = r;
     L.sn[r] = v;
+  }
+  for (int s = lane; s < H4; s += 64) {  // (the neighbour set is read out)
+    fk[s] = H4_EMPTY;
+    fc[s] = 0;
   }
   __syncthreads();
   // 2. candidate faces with the node as smallest vertex
   for (int32_t i = lane; i < len; i += 64) {
     const int4 q = L.ro[i];
+    const ushort4 g = L.sl[i];
     const int32_t o[4] = {q.x, q.y, q.z, q.w};
+    const int32_t so[4] = {g.x, g.y, g.z, g.w};
     int32_t ru[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-      ru[m] = o[m] > j ? L.nr[h4_find(L.nk, (uint32_t)o[m])] - nlow : -1;
+    for (int m = 0; m < 4; ++m) ru[m] = o[m] > j ? L.nr[so[m]] - nlow : -1;
 #pragma unroll
     for (int drop = 0; drop < 4; ++drop) {
       int32_t t[3];
@@ -2164,8 +2171,8 @@ __device__ bool node_topo4_sets(const TopoArgs &a, int32_t j, int lane, int32_t 
       const int32_t x = min(t[0], t[1]), y = max(t[0], t[1]), z = t[2];
       const int32_t lo = min(x, z), hi = max(y, z), mid = max(x, min(y, z));
       if (lo < 0) continue;
-      const int s = h4_insert(L.fk, (uint32_t)(lo << 16 | mid << 8 | hi), &L.n_face, &L.over);
-      if (s >= 0) atomicAdd(&L.fc[s], 0x10000u + (uint32_t)i);
+      const int s = h4_insert(fk, (uint32_t)(lo << 16 | mid << 8 | hi), &L.n_face, &L.over);
+      if (s >= 0) atomicAdd(&fc[s], 0x10000u + (uint32_t)i);
     }
   }
   __syncthreads();
@@ -2194,12 +2201,12 @@ __device__ bool node_topo4_sets(const TopoArgs &a, int32_t j, int lane, int32_t 
   int32_t nb = 0;
   bool bad = false;
   for (int s0 = 0; s0 < H4; s0 += 64) {
-    const uint32_t k = L.fk[s0 + lane], c = L.fc[s0 + lane];
+    const uint32_t k = fk[s0 + lane], c = fc[s0 + lane];
     const bool has = k != H4_EMPTY;
     bad = bad || (has && (c >> 16) > 2);
     const bool once = has && (c >> 16) == 1;
     const uint64_t m = __builtin_amdgcn_ballot_w64(once);
-    if (once) L.bl[nb + __builtin_popcountll(m & below)] = k << 8 | (c & 0xFFu);
+    if (once) bl[nb + __builtin_popcountll(m & below)] = k << 8 | (c & 0xFFu);
     nb += __builtin_popcountll(m);
   }
   if (__builtin_amdgcn_ballot_w64(bad) != 0) {
@@ -2209,7 +2216,7 @@ __device__ bool node_topo4_sets(const TopoArgs &a, int32_t j, int lane, int32_t 
   __syncthreads();
   const int32_t f0 = EMIT ? a.foff[j] : 0;
   for (int32_t idx = lane; idx < nb; idx += 64) {
-    const uint32_t b = L.bl[idx], k = b >> 8;
+    const uint32_t b = bl[idx], k = b >> 8;
     const int32_t fv[4] = {j, L.sn[nlow + (int32_t)(k >> 16)],
                            L.sn[nlow + (int32_t)((k >> 8) & 0xFFu)],
                            L.sn[nlow + (int32_t)(k & 0xFFu)]};
@@ -2221,7 +2228,7 @@ __device__ bool node_topo4_sets(const TopoArgs &a, int32_t j, int lane, int32_t 
       }
     } else {
       int32_t r = 0;
-      for (int32_t u = 0; u < nb; ++u) r += L.bl[u] < b ? 1 : 0;
+      for (int32_t u = 0; u < nb; ++u) r += bl[u] < b ? 1 : 0;
       emit_bface4(a, X, fv, a.node_inc[r0 + (int32_t)(b & 0xFFu)], f0 + r);
     }
   }
