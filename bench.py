@@ -542,7 +542,7 @@ def main():
     ap.add_argument("--phase-reps", type=int, default=10)
     ap.add_argument("--only", default="", help="profiling: run only this phase "
                     "(topo|fwd|fwd_atomic|vol_edge|bwd|bwd_atomic|fused|fwd_edge_normals|"
-                    "fwd_dual_faces) --steps times")
+                    "fwd_dual_faces) --steps times, or the pentatope section (4d)")
     ap.add_argument("--calibrate", action="store_true",
                     help="run only kernels of known traffic (HBM counter scaling)")
     ap.add_argument("--no-batched", action="store_true")
@@ -568,6 +568,9 @@ def main():
     import paper_2502_00778_amd as eb
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.only == "4d":  # the pentatope section alone, each call --steps times
+        bench_4d(torch, eb, meshgen, args.seed, args.steps, Timer(torch))
+        return
     t0 = time.perf_counter()
     mesh = meshgen.make(args.config, args.seed)
     log(f"[bench] grid {mesh.name}: {mesh.n_nodes} nodes, {mesh.n_elems} elements "

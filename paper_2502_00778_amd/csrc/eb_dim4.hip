@@ -8,7 +8,7 @@
 // paper derives D = 2 and 3 and leaves D = 4 to future work.
 //
 // The gather forward takes tiles of 64 consecutive nodes, one wave each: a
-// node's thread walks its node_inc row two incidences at a time (their
+// node's thread walks its node_inc row four incidences at a time (their
 // connectivity and points loaded together), forms the face vector opposite
 // the node, and adds it to its out-edges' accumulators in LDS (the tile's
 // out-edges are contiguous; a node's edge found among its first 16 heads,
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(T4_TN) void k4_fwd_tile(Fwd4 a) {
     const V4 Pj = load_pt4(a.X, j);
     double V = 0.0;
     const int32_t r0 = a.node_inc_off[j], r1 = a.node_inc_off[j + 1];
-    constexpr int U = 2;
+    constexpr int U = 4;  // (LDS holds a CU to a few waves: more loads in flight each)
     for (int32_t r = r0; r < r1; r += U) {
       int32_t inc[U], v[U][5], o[U][4];
       V4 Q[U][4];
@@ -339,10 +339,8 @@ __global__ __launch_bounds__(256) void k4_vol_edge_terms(Fwd4 a, const double *n
 __global__ __launch_bounds__(256) void k4_vol_edge_sum(Fwd4 a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.nv) return;
-  double V = 0.0;
-  for (int32_t e = a.node_edge_off[j]; e < a.node_edge_off[j + 1]; ++e) V += a.term[e];
-  for (int32_t r = a.node_in_off[j]; r < a.node_in_off[j + 1]; ++r) V += a.term[a.node_in_edge[r]];
-  a.vol[j] = V;
+  const double V = sum_terms<false>(0.0, a.term, a.node_edge_off[j], a.node_edge_off[j + 1]);
+  a.vol[j] = sum_terms_at<false>(V, a.term, a.node_in_edge, a.node_in_off[j], a.node_in_off[j + 1]);
 }
 
 __global__ __launch_bounds__(256) void k4_vol_edge_atomic(Fwd4 a, const double *n0,

@@ -154,4 +154,39 @@ int volumes4(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
              const double *coords, int mode, const double *n_edge, int reduce, double *vol,
              void *ws, size_t ws_bytes, hipStream_t s);
 
+// ------------------------------------------------ ordered sums of terms
+// s + term[e] (or s - term[e]) over edges e = b .. e1-1, or over e = idx[b ..
+// e1-1], in that order; eight loads are issued before any is added, so a
+// node's terms arrive together instead of one round trip each
+template <bool SUB>
+__device__ __forceinline__ double sum_terms(double s, const double *__restrict__ term, int32_t b,
+                                            int32_t e1) {
+  for (int32_t i = b; i < e1; i += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = term[min(i + u, e1 - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i + u < e1) s = SUB ? s - v[u] : s + v[u];
+  }
+  return s;
+}
+template <bool SUB>
+__device__ __forceinline__ double sum_terms_at(double s, const double *__restrict__ term,
+                                               const int32_t *__restrict__ idx, int32_t b,
+                                               int32_t e1) {
+  for (int32_t i = b; i < e1; i += 8) {
+    int32_t k[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) k[u] = idx[min(i + u, e1 - 1)];
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = term[k[u]];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i + u < e1) s = SUB ? s - v[u] : s + v[u];
+  }
+  return s;
+}
+
 }  // namespace eb

@@ -215,40 +215,6 @@ __global__ __launch_bounds__(256) void k_vol_edge_terms(FwdArgs a, const double 
   term[e] = (d.x * nx[e] + d.y * ny[e] + (D == 3 ? d.z * nz[e] : 0.0)) * (1.0 / (2 * D));
 }
 
-// s + term[e] (or s - term[e]) over edges e = b .. e1-1, or over e = idx[b ..
-// e1-1], in that order; eight loads are issued before any is added, so a
-// node's terms arrive together instead of one round trip each
-template <bool SUB>
-__device__ __forceinline__ double sum_terms(double s, const double *__restrict__ term, int32_t b,
-                                            int32_t e1) {
-  for (int32_t i = b; i < e1; i += 8) {
-    double v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = term[min(i + u, e1 - 1)];
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (i + u < e1) s = SUB ? s - v[u] : s + v[u];
-  }
-  return s;
-}
-template <bool SUB>
-__device__ __forceinline__ double sum_terms_at(double s, const double *__restrict__ term,
-                                               const int32_t *__restrict__ idx, int32_t b,
-                                               int32_t e1) {
-  for (int32_t i = b; i < e1; i += 8) {
-    int32_t k[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) k[u] = idx[min(i + u, e1 - 1)];
-    double v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = term[k[u]];
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (i + u < e1) s = SUB ? s - v[u] : s + v[u];
-  }
-  return s;
-}
-
 __global__ __launch_bounds__(256) void k_vol_edge_sum(FwdArgs a, const double *__restrict__ term) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.nv) return;
