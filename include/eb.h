@@ -30,6 +30,10 @@
  *   - coords is structure-of-arrays FP64 [dim][n_nodes]; elem is int32
  *     [n_elems][dim+1] with any local vertex order (either orientation).
  *   - All outputs are overwritten, never accumulated into; inputs are const.
+ *   - A grid needs at least one node; it may have no elements.  Such a grid
+ *     has no edges, boundary faces or boundary nodes, so every per-node sum
+ *     (V, the residual, the gradient) is zero and the per-edge and
+ *     per-boundary-node outputs, having no entries, may be null.
  *   - ne = dim(dim+1)/2 local edges per element (3, 6 or 10), in lexicographic
  *     local pair order: 2D (0,1)(0,2)(1,2); 3D (0,1)(0,2)(0,3)(1,2)(1,3)(2,3);
  *     4D (0,1)(0,2)(0,3)(0,4)(1,2)(1,3)(1,4)(2,3)(2,4)(3,4).

@@ -192,6 +192,7 @@ int eb_directed_areas(const eb_sizes *sizes, const eb_topology *topo, const int3
     set_detail("reduce must be EB_REDUCE_ATOMIC or EB_REDUCE_GATHER");
     return EB_EINVAL;
   }
+  if (no_elements(sizes)) return vol ? fill_f64(vol, sizes->n_nodes, 0.0, stream) : EB_OK;
   if (!n_edge) {
     set_detail("n_edge is required");
     return EB_EINVAL;
@@ -220,8 +221,13 @@ int eb_directed_areas_variant(const eb_sizes *sizes, const eb_topology *topo,
   EB_TRY(only_dims23(sizes));
   FwdArgs a;
   EB_TRY(pack(sizes, topo, elem, coords, ws, ws_bytes, a));
-  if (variant < EB_VARIANT_NODE_NORMALS || variant > EB_VARIANT_DUAL_FACES || !n_edge) {
-    set_detail("variant must be 0, 1 or 2 and n_edge non-null");
+  if (variant < EB_VARIANT_NODE_NORMALS || variant > EB_VARIANT_DUAL_FACES) {
+    set_detail("variant must be 0, 1 or 2");
+    return EB_EINVAL;
+  }
+  if (no_elements(sizes)) return vol ? fill_f64(vol, sizes->n_nodes, 0.0, stream) : EB_OK;
+  if (!n_edge) {
+    set_detail("n_edge is required");
     return EB_EINVAL;
   }
   const int D = sizes->dim;
@@ -249,6 +255,7 @@ int eb_dual_volumes(const eb_sizes *sizes, const eb_topology *topo, const int32_
     set_detail("bad mode / reduce, or vol is null");
     return EB_EINVAL;
   }
+  if (no_elements(sizes)) return fill_f64(vol, sizes->n_nodes, 0.0, stream);
   if (mode == EB_VOL_EDGE) {
     if (!n_edge) {
       set_detail("EB_VOL_EDGE needs n_edge");
@@ -278,8 +285,12 @@ int eb_edge_residual(const eb_sizes *sizes, const eb_topology *topo, const int32
   EB_TRY(only_dims23(sizes));
   FwdArgs a;
   EB_TRY(pack(sizes, topo, elem, coords, ws, ws_bytes, a));
-  if (!n_edge || !flux || !res || (bflux != EB_BFLUX_NODE && bflux != EB_BFLUX_LINEAR) ||
-      (bflux == EB_BFLUX_NODE && sizes->n_bnodes > 0 && !b_node)) {
+  if (!flux || !res || (bflux != EB_BFLUX_NODE && bflux != EB_BFLUX_LINEAR)) {
+    set_detail("n_edge, flux and res are required; b_node for EB_BFLUX_NODE; bflux 0 or 1");
+    return EB_EINVAL;
+  }
+  if (no_elements(sizes)) return fill_f64(res, sizes->n_nodes, 0.0, stream);
+  if (!n_edge || (bflux == EB_BFLUX_NODE && sizes->n_bnodes > 0 && !b_node)) {
     set_detail("n_edge, flux and res are required; b_node for EB_BFLUX_NODE; bflux 0 or 1");
     return EB_EINVAL;
   }
@@ -311,6 +322,7 @@ int eb_directed_areas_backward(const eb_sizes *sizes, const eb_topology *topo,
     return EB_EINVAL;
   }
   const int D = sizes->dim;
+  if (no_elements(sizes)) return fill_f64(grad_coords, D * sizes->n_nodes, 0.0, stream);
   crows(grad_n, D, sizes->n_edges, a.w_x, a.w_y, a.w_z);
   crows(sizes->n_bnodes > 0 ? grad_b : nullptr, D, sizes->n_bnodes, a.be_x, a.be_y, a.be_z);
   a.c = grad_vol;

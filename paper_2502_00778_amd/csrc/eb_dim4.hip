@@ -399,7 +399,12 @@ int forward4(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
              void *ws, size_t ws_bytes, hipStream_t s) {
   Fwd4 a;
   EB_TRY(pack4(sz, tp, elem, coords, ws, ws_bytes, a));
-  if ((reduce != EB_REDUCE_ATOMIC && reduce != EB_REDUCE_GATHER) || !n_edge) {
+  if (reduce != EB_REDUCE_ATOMIC && reduce != EB_REDUCE_GATHER) {
+    set_detail("bad reduce, or n_edge is null");
+    return EB_EINVAL;
+  }
+  if (no_elements(sz)) return vol ? fill_f64(vol, sz->n_nodes, 0.0, s) : EB_OK;
+  if (!n_edge) {
     set_detail("bad reduce, or n_edge is null");
     return EB_EINVAL;
   }
@@ -443,8 +448,12 @@ int volumes4(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
   Fwd4 a;
   EB_TRY(pack4(sz, tp, elem, coords, ws, ws_bytes, a));
   if ((mode != EB_VOL_ELEMENT && mode != EB_VOL_EDGE) ||
-      (reduce != EB_REDUCE_ATOMIC && reduce != EB_REDUCE_GATHER) || !vol ||
-      (mode == EB_VOL_EDGE && !n_edge)) {
+      (reduce != EB_REDUCE_ATOMIC && reduce != EB_REDUCE_GATHER) || !vol) {
+    set_detail("bad mode / reduce, vol is null, or EB_VOL_EDGE without n_edge");
+    return EB_EINVAL;
+  }
+  if (no_elements(sz)) return fill_f64(vol, sz->n_nodes, 0.0, s);
+  if (mode == EB_VOL_EDGE && !n_edge) {
     set_detail("bad mode / reduce, vol is null, or EB_VOL_EDGE without n_edge");
     return EB_EINVAL;
   }

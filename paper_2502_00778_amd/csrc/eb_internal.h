@@ -142,6 +142,13 @@ inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 
 inline bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
 int check_ws(int dim, int64_t n_nodes, int64_t n_elems, const void *ws, size_t ws_bytes);
+// A grid without elements has no edges, boundary faces or boundary nodes (the
+// build finds none): every per-node sum a call returns is empty (zero), and
+// the per-edge and per-boundary-node outputs have no entries (their pointers
+// may be null).
+inline bool no_elements(const eb_sizes *s) {
+  return s->n_elems == 0 && s->n_edges == 0 && s->n_bfaces == 0 && s->n_bnodes == 0;
+}
 int check_sizes(const eb_sizes *s);
 // EB_EINVAL (with detail) for dim 4, which only the build, the forward and
 // the volume calls support

@@ -50,7 +50,12 @@ extern "C" int eb_dual_volumes_noalloc(const eb_sizes *sizes, const eb_topology 
   EB_TRY(only_dims23(sizes));
   FwdArgs a;
   EB_TRY(pack_arrays(sizes, topo, nullptr, coords, false, a));
-  if ((reduce != EB_REDUCE_ATOMIC && reduce != EB_REDUCE_GATHER) || !vol || !n_edge) {
+  if ((reduce != EB_REDUCE_ATOMIC && reduce != EB_REDUCE_GATHER) || !vol) {
+    set_detail("bad reduce, or vol / n_edge is null");
+    return EB_EINVAL;
+  }
+  if (no_elements(sizes)) return fill_f64(vol, sizes->n_nodes, 0.0, stream);
+  if (!n_edge) {
     set_detail("bad reduce, or vol / n_edge is null");
     return EB_EINVAL;
   }

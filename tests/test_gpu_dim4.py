@@ -178,6 +178,23 @@ def test_dim4_gather_reproducible_and_closure():
     assert abs(V.sum() - 1.0) < 1e-13
 
 
+def test_dim4_grid_without_elements():
+    """Nodes and no pentatopes: no edges or boundary; every V_j is 0."""
+    import paper_2502_00778_amd as eb
+    say("[4d empty] 6 nodes, no elements")
+    X = torch.rand(4, 6, dtype=torch.float64, device="cuda")
+    E = torch.zeros((0, 5), dtype=torch.int32, device="cuda")
+    t = eb.build_edges(E, X)
+    assert (t.n_nodes, t.n_elems, t.n_edges, t.n_bfaces, t.n_bnodes) == (6, 0, 0, 0, 0)
+    for reduce in ("gather", "atomic"):
+        n, b, V = eb.directed_areas(X, t, E, reduce)
+        assert tuple(n.shape) == (4, 0) and torch.equal(V, torch.zeros_like(V))
+        for mode in ("element", "edge"):
+            Vm = eb.dual_volumes(X, t, E, mode, n=n, reduce=reduce)
+            assert torch.equal(Vm, torch.zeros_like(Vm))
+    eb.check_errors(t)
+
+
 def test_dim4_unsupported_calls_refused():
     import paper_2502_00778_amd as eb
     m, ot, *_ = case("4d-5")

@@ -485,6 +485,37 @@ def fan(k):
     return Xf, Ef
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_grid_without_elements(dim):
+    """Nodes and no elements: no edges, boundary faces or boundary nodes;
+    every V_j is an empty sum (0), and so is every gradient entry."""
+    say(f"[empty] dim {dim}: 5 nodes, no elements")
+    X = torch.rand(dim, 5, dtype=torch.float64, device="cuda")
+    E = torch.zeros((0, dim + 1), dtype=torch.int32, device="cuda")
+    t = eb().build_edges(E, X)
+    assert (t.n_nodes, t.n_elems, t.n_edges, t.n_bfaces, t.n_bnodes) == (5, 0, 0, 0, 0)
+    for reduce in ("gather", "atomic"):
+        n, b, V = eb().directed_areas(X, t, E, reduce)
+        assert tuple(n.shape) == (dim, 0) and tuple(b.shape) == (dim, 0)
+        assert torch.equal(V, torch.zeros_like(V))
+        Ve = eb().dual_volumes(X, t, E, "edge", n=n, reduce=reduce)
+        assert torch.equal(Ve, torch.zeros_like(Ve))
+        Vv = eb().dual_volumes(X, t, E, "element", reduce=reduce)
+        assert torch.equal(Vv, torch.zeros_like(Vv))
+        g = eb().directed_areas_backward(X, t, E, grad_vol=torch.ones(5, dtype=torch.float64,
+                                                                       device="cuda"),
+                                         reduce=reduce)
+        assert torch.equal(g, torch.zeros_like(g))
+    for variant in ("edge_normals", "dual_faces"):
+        _, _, V = eb().directed_areas_variant(X, t, E, variant)
+        assert torch.equal(V, torch.zeros_like(V))
+    res = eb().edge_residual(X, t, E, n, torch.rand(dim, 5, dtype=torch.float64, device="cuda"))
+    assert torch.equal(res, torch.zeros_like(res))
+    Vn = eb().dual_volumes_noalloc(X, t, n)
+    assert torch.equal(Vn, torch.zeros_like(Vn))
+    eb().check_errors(t)
+
+
 def test_high_degree_node_queued():
     """A node beyond the fast kernel's per-node capacities (40 out-edges) is
     handled by the general kernel, and its 40 out-edges select the wide plan
