@@ -1303,6 +1303,48 @@ __device__ __forceinline__ int32_t find_edge(const int32_t *__restrict__ node_ed
   return (lo < node_edge_off[t + 1] && head[lo] == h) ? lo : -1;
 }
 
+// The ids of N edges {a[q], b[q]} (-1: no such edge) by N binary searches
+// taken in step: every active search's probe of a round is loaded before any
+// is compared, so the searches cost the round trips of the longest one
+// rather than their sum.
+template <int N>
+__device__ __forceinline__ void find_edges(const int32_t *__restrict__ node_edge_off,
+                                           const int32_t *__restrict__ head,
+                                           const int32_t (&a)[N], const int32_t (&b)[N],
+                                           int32_t (&id)[N]) {
+  int32_t lo[N], hi[N], end[N], h[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    const int32_t t = min(a[q], b[q]);
+    h[q] = max(a[q], b[q]);
+    lo[q] = node_edge_off[t];
+    hi[q] = end[q] = node_edge_off[t + 1];
+  }
+  for (;;) {
+    bool any = false;
+    int32_t x[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      const bool on = lo[q] < hi[q];
+      any = any || on;
+      x[q] = on ? head[(lo[q] + hi[q]) >> 1] : 0;
+    }
+    if (!any) break;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      if (lo[q] >= hi[q]) continue;
+      const int32_t mid = (lo[q] + hi[q]) >> 1;
+      if (x[q] < h[q]) lo[q] = mid + 1;
+      else hi[q] = mid;
+    }
+  }
+  int32_t y[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) y[q] = lo[q] < end[q] ? head[lo[q]] : -1;
+#pragma unroll
+  for (int q = 0; q < N; ++q) id[q] = y[q] == h[q] ? lo[q] : -1;
+}
+
 // node_in_edge holds each node's lower neighbours, ascending; replace each
 // by the id of the edge (neighbour, node)
 __global__ void k_node_in_ids(int64_t nv, const int32_t *__restrict__ node_in_off,
@@ -1712,15 +1754,21 @@ __global__ void k_bface_edge(const int32_t *__restrict__ bface, int64_t nb,
     bface_edge[f] = find_edge(node_edge_off, head, bface[2 * f], bface[2 * f + 1]);
   } else {
     // the face's vertex pairs in lexicographic order
-    int32_t v[D];
+    constexpr int NP = D * (D - 1) / 2;
+    int32_t v[D], pa[NP], pb[NP], id[NP];
 #pragma unroll
     for (int s = 0; s < D; ++s) v[s] = bface[D * f + s];
     int k = 0;
 #pragma unroll
     for (int p = 0; p < D; ++p)
 #pragma unroll
-      for (int q = p + 1; q < D; ++q)
-        bface_edge[(int64_t)(D * (D - 1) / 2) * f + k++] = find_edge(node_edge_off, head, v[p], v[q]);
+      for (int q = p + 1; q < D; ++q) {
+        pa[k] = v[p];
+        pb[k++] = v[q];
+      }
+    find_edges<NP>(node_edge_off, head, pa, pb, id);
+#pragma unroll
+    for (int q = 0; q < NP; ++q) bface_edge[(int64_t)NP * f + q] = id[q];
   }
 }
 
@@ -2267,19 +2315,23 @@ __global__ void k4_elem_maps(const int32_t *__restrict__ elem, int64_t nelem,
                              int8_t *elem_edge_sign, StatusBlock *st) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nelem || build_failed(st)) return;
-  int32_t v[5];
+  int32_t v[5], pa[10], pb[10], id[10];
   load_conn4(elem, e, v);
   int k = 0;
 #pragma unroll
   for (int p = 0; p < 5; ++p)
 #pragma unroll
     for (int q = p + 1; q < 5; ++q) {
-      const int32_t id = find_edge(node_edge_off, head, v[p], v[q]);
-      if (id < 0) raise_status(st, EB_EINVAL, e);  // cannot happen for a consistent build
-      elem_edge[e * 10 + k] = id;
-      elem_edge_sign[e * 10 + k] = (int8_t)(v[p] < v[q] ? 1 : -1);
-      ++k;
+      pa[k] = v[p];
+      pb[k++] = v[q];
     }
+  find_edges<10>(node_edge_off, head, pa, pb, id);
+#pragma unroll
+  for (int q = 0; q < 10; ++q) {
+    if (id[q] < 0) raise_status(st, EB_EINVAL, e);  // cannot happen for a consistent build
+    elem_edge[e * 10 + q] = id[q];
+    elem_edge_sign[e * 10 + q] = (int8_t)(pa[q] < pb[q] ? 1 : -1);
+  }
 }
 
 template <int D>
