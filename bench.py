@@ -549,7 +549,7 @@ def main():
     ap.add_argument("--config", default="3d-scale")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--phase-reps", type=int, default=10)
+    ap.add_argument("--phase-reps", type=int, default=20)
     ap.add_argument("--only", default="", help="profiling: run only this phase "
                     "(topo|fwd|fwd_atomic|vol_edge|bwd|bwd_atomic|fused|fwd_edge_normals|"
                     "fwd_dual_faces) --steps times, or the pentatope section (4d)")
@@ -680,7 +680,8 @@ def main():
     tm = Timer(torch)
     res = {}
     for name, fn in phases.items():
-        fn()
+        for _ in range(3):  # warm-up calls
+            fn()
         res[name] = tm.time(fn, args.phase_reps)
         log(f"[bench] phase {name}: mean {res[name][0]:.3f} ms, median {res[name][1]:.3f}, "
             f"min {res[name][2]:.3f}")
