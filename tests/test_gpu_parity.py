@@ -199,6 +199,10 @@ CASES = {
     "2d-fan-400": lambda: fan_mesh(400),
     "3d-cone-150": lambda: cone(150),
     "3d-cone-150-low": lambda: cone(150, centre=0),
+    # the centre numbered last: 4200 tetrahedra at one node, 2100 around each
+    # axis edge and 2100 boundary faces at each apex (CSR rows sorted by one
+    # lane beyond 2048 entries)
+    "3d-cone-2100-high": lambda: cone(2100, centre=2102),
 }
 
 _cache = {}
