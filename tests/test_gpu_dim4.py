@@ -90,6 +90,8 @@ CASES = {
     "4d-cone-5": lambda: cone(5, 7, True),
     "4d-star-70": lambda: star(70, 8),
     "4d-cone-5-last": lambda: cone(5, 9, False),
+    # 3072 incidences at the apex (its row sorted by one lane, beyond 2048)
+    "4d-cone-9-last": lambda: cone(9, 10, False),
 }
 _cache = {}
 
