@@ -236,7 +236,7 @@ def alg_bytes_fused(dim, nv, nel, ne_, nb, nbn):
 def bench_batched(torch, eb, meshgen, seed, reps, tm):
     """The 64-mesh batch: forward + adjoint as one enqueue in each fused mode
     (the tuned deterministic one also replayed from a captured graph, and the
-    persistent kernel with the atomic adjoint, eager and from a graph)
+    two forms with the atomic adjoint, eager and from a graph)
     against 64 x (plain gather forward + plain adjoint) on the meshes one by
     one, with the gather adjoint for the deterministic modes and the atomic
     one for the atomic mode."""
@@ -269,13 +269,17 @@ def bench_batched(torch, eb, meshgen, seed, reps, tm):
     eb.set_fused_mode("separate")    # the gather kernels one after another
     fused()
     t_sep = tm.time(fused, reps)
-    eb.set_fused_mode("persistent_atomic")  # one persistent launch, atomic adjoint
-    fused()
-    t_atomic = tm.time(fused, reps)
-    gr = eb.ForwardBackwardGraph(X, topo, E, W, B, C)  # (the atomic form, captured)
-    gr.launch()
-    t_graph_atomic = tm.time(gr.launch, reps)
-    gr.close()
+    atomic = {}
+    for mode in ("persistent_atomic", "separate_atomic"):  # the FP64-atomic adjoint
+        eb.set_fused_mode(mode)
+        fused()
+        t_eager = tm.time(fused, reps)
+        gr = eb.ForwardBackwardGraph(X, topo, E, W, B, C)
+        gr.launch()
+        atomic[mode] = (t_eager, tm.time(gr.launch, reps))
+        gr.close()
+    t_atomic, t_graph_atomic = atomic["persistent_atomic"]
+    t_sep_atomic, t_graph_sep_atomic = atomic["separate_atomic"]
     eb.set_fused_mode(tuned_mode)
     gr = eb.ForwardBackwardGraph(X, topo, E, W, B, C)
     gr.launch()
@@ -320,6 +324,8 @@ def bench_batched(torch, eb, meshgen, seed, reps, tm):
         "persistent_kernel_ms": round(k_fused[0], 4),
         "separate_kernels_ms": round(t_sep[0], 4),
         "persistent_atomic_ms": round(t_atomic[0], 4),
+        "separate_atomic_kernels_ms": round(t_sep_atomic[0], 4),
+        "graph_separate_atomic_ms": round(t_graph_sep_atomic[0], 4),
         "graph_persistent_atomic_ms": round(t_graph_atomic[0], 4),
         "tuned_mode": tuned_mode,
         "graph_ms": round(t_graph[0], 4),
@@ -328,6 +334,8 @@ def bench_batched(torch, eb, meshgen, seed, reps, tm):
         "speedup_graph_vs_per_mesh": round(t_plain[0] / t_graph[0], 2),
         "speedup_graph_persistent_atomic_vs_per_mesh_atomic":
             round(t_plain_atomic[0] / t_graph_atomic[0], 2),
+        "speedup_graph_separate_atomic_vs_per_mesh_atomic":
+            round(t_plain_atomic[0] / t_graph_sep_atomic[0], 2),
         "Melements_per_s_graph": round(nel / (t_graph[0] * 1e-3) / 1e6, 1),
         "Melements_per_s_per_mesh": round(nel / (t_plain[0] * 1e-3) / 1e6, 1),
         "alg_GBps_graph": round(bytes_ / (t_graph[0] * 1e-3) / 1e9, 1),

@@ -421,14 +421,17 @@ void eb_get_fused_shape(int *tile, int *unroll, int *blocks_per_cu);
  * FP64 atomics after per-block sums in LDS, as eb_directed_areas_backward's
  * EB_REDUCE_ATOMIC (two phases: forward node tiles with the adjoint's
  * element and boundary blocks, then forward boundary tiles; a fill kernel
- * zeroes grad_coords first): n, b and V as in the other modes, grad_coords
- * equal to rounding but not bitwise reproducible.  Process-wide;
- * eb_autotune picks between the first two, or, when the third is in force,
- * tunes its shape and keeps it. */
+ * zeroes grad_coords first); EB_FUSED_SEPARATE_ATOMIC the gather forward and
+ * that atomic adjoint's kernels one after the other.  With either atomic
+ * mode n, b and V are as in the others and grad_coords equal to rounding but
+ * not bitwise reproducible.  Process-wide; eb_autotune keeps the reduction
+ * in force (gather or atomic) and picks the persistent kernel's best shape
+ * or the separate kernels, whichever is faster. */
 typedef enum {
   EB_FUSED_PERSISTENT = 0,
   EB_FUSED_SEPARATE = 1,
-  EB_FUSED_PERSISTENT_ATOMIC = 2
+  EB_FUSED_PERSISTENT_ATOMIC = 2,
+  EB_FUSED_SEPARATE_ATOMIC = 3
 } eb_fused_mode;
 int eb_set_fused_mode(int mode);
 int eb_get_fused_mode(void);
@@ -441,13 +444,12 @@ int eb_set_fused_wait_limit(int64_t spins);
 /* Launch-shape tuner.  Times (reps runs each, after one warm-up, hipEvents
  * on `stream`) every gather shape of eb_directed_areas (tile x unroll x
  * xcd_remap) and every fused shape of eb_batch_forward_backward (tile x
- * unroll x blocks_per_cu in {1,2,4,8,0}) and EB_FUSED_SEPARATE on the
+ * unroll x blocks_per_cu in {1,2,4,8,0}) and the separate kernels on the
  * caller's grid and buffers, sets the fastest of each (eb_set_gather_shape,
- * eb_set_fused_shape, eb_set_fused_mode) and reports them.  With
- * EB_FUSED_PERSISTENT_ATOMIC in force it times that kernel's shapes instead
- * of the gather persistent kernel's, keeps the mode and does not time
- * EB_FUSED_SEPARATE (separate_ms 0).  Outputs hold valid results afterwards
- * (all shapes give the same bits, but for the atomic mode's grad_coords).
+ * eb_set_fused_shape, eb_set_fused_mode) and reports them.  With an atomic
+ * mode in force it times the atomic persistent kernel's shapes and
+ * EB_FUSED_SEPARATE_ATOMIC instead.  Outputs hold valid results afterwards
+ * (all shapes give the same bits, but for the atomic modes' grad_coords).
  * Synchronizes `stream`. */
 typedef struct {
   int32_t gather_tile, gather_unroll, gather_xcd_remap;
@@ -455,7 +457,7 @@ typedef struct {
   int32_t fused_tile, fused_unroll, fused_blocks_per_cu;
   float fused_ms;
   int32_t n_tried;
-  int32_t fused_separate;  /* 1 if EB_FUSED_SEPARATE was faster and is set */
+  int32_t fused_separate;  /* 1 if the separate kernels were faster and are set */
   float separate_ms;
 } eb_tuning;
 int eb_autotune(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,

@@ -25,7 +25,7 @@ __all__ = ["concat_host", "Batch", "batch_offsets", "forward_backward", "Forward
            "set_fused_shape", "get_fused_shape", "set_fused_mode", "get_fused_mode",
            "set_fused_wait_limit", "autotune"]
 
-FUSED_MODE = {"persistent": 0, "separate": 1, "persistent_atomic": 2}
+FUSED_MODE = {"persistent": 0, "separate": 1, "persistent_atomic": 2, "separate_atomic": 3}
 
 
 def concat_host(meshes):
@@ -165,9 +165,10 @@ def get_fused_shape():
 
 def set_fused_mode(mode: str):
     """eb_set_fused_mode: 'persistent' (one persistent kernel, gather adjoint),
-    'separate' (the gather kernels in sequence) or 'persistent_atomic' (one
+    'separate' (the gather kernels in sequence), 'persistent_atomic' (one
     persistent kernel, FP64-atomic adjoint: grad_coords not bitwise
-    reproducible)."""
+    reproducible) or 'separate_atomic' (the gather forward and the atomic
+    adjoint's kernels in sequence)."""
     check(lib().eb_set_fused_mode(FUSED_MODE[mode]), "eb_set_fused_mode")
 
 
@@ -181,8 +182,8 @@ def set_fused_wait_limit(spins: int):
 
 def _cache_key(topo):
     name = torch.cuda.get_device_name(torch.cuda.current_device())
-    # the atomic persistent kernel is tuned apart from the other two modes
-    kind = "atomic" if get_fused_mode() == "persistent_atomic" else "gather"
+    # the atomic modes are tuned apart from the gather ones
+    kind = "atomic" if get_fused_mode().endswith("atomic") else "gather"
     return (f"{name}|D{topo.dim}|v{topo.n_nodes}|E{topo.n_elems}|e{topo.n_edges}"
             f"|p{int(topo.sizes.plan_bytes)}|{kind}")
 
@@ -200,8 +201,9 @@ def autotune(coords, topo, elems, grad_n=None, grad_b=None, grad_vol=None, reps:
             r = db[key]
             api.set_gather_shape(r["gather_tile"], r["gather_unroll"], r["gather_xcd_remap"])
             set_fused_shape(r["fused_tile"], r["fused_unroll"], r["fused_blocks_per_cu"])
-            if get_fused_mode() != "persistent_atomic":
-                set_fused_mode("separate" if r.get("fused_separate") else "persistent")
+            atomic = get_fused_mode().endswith("atomic")
+            set_fused_mode(("separate" if r.get("fused_separate") else "persistent")
+                           + ("_atomic" if atomic else ""))
             return dict(r, cached=True)
     args, _ = _fb_args(coords, topo, elems, grad_n, grad_b, grad_vol, out)
     t = EbTuning()

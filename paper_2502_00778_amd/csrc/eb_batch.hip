@@ -238,12 +238,12 @@ int fused_atomic_impl(const FwdArgs &a, const FusedCfg &cfg, hipStream_t s) {
 
 template <int D>
 int fused_impl(const FwdArgs &a0, const FusedCfg &cfg, hipStream_t s) {
-  if (cfg.separate) {  // the same work as the gather calls, one after the other
+  if (cfg.separate) {  // the same work as the separate calls, one after the other
     const LaunchCfg g = default_cfg();
     FwdArgs a = a0;
     a.xcd_remap = g.xcd_remap;
     EB_TRY(forward_impl<D>(a, EB_REDUCE_GATHER, g, s));
-    return backward_impl<D>(a, EB_REDUCE_GATHER, g, s);
+    return backward_impl<D>(a, cfg.atomic ? EB_REDUCE_ATOMIC : EB_REDUCE_GATHER, g, s);
   }
   const FwdArgs &a = a0;
   const int64_t tn = cfg.tile;
@@ -552,21 +552,22 @@ void eb_get_fused_shape(int *tile, int *unroll, int *blocks_per_cu) {
 int eb_set_fused_mode(int mode) {
   clear_detail();
   if (mode != EB_FUSED_PERSISTENT && mode != EB_FUSED_SEPARATE &&
-      mode != EB_FUSED_PERSISTENT_ATOMIC) {
-    set_detail("mode must be EB_FUSED_PERSISTENT, EB_FUSED_SEPARATE or "
-               "EB_FUSED_PERSISTENT_ATOMIC");
+      mode != EB_FUSED_PERSISTENT_ATOMIC && mode != EB_FUSED_SEPARATE_ATOMIC) {
+    set_detail("mode must be EB_FUSED_PERSISTENT, EB_FUSED_SEPARATE, "
+               "EB_FUSED_PERSISTENT_ATOMIC or EB_FUSED_SEPARATE_ATOMIC");
     return EB_EINVAL;
   }
   FusedCfg c = fused_cfg();
-  c.separate = mode == EB_FUSED_SEPARATE;
-  c.atomic = mode == EB_FUSED_PERSISTENT_ATOMIC;
+  c.separate = mode == EB_FUSED_SEPARATE || mode == EB_FUSED_SEPARATE_ATOMIC;
+  c.atomic = mode == EB_FUSED_PERSISTENT_ATOMIC || mode == EB_FUSED_SEPARATE_ATOMIC;
   set_fused_cfg(c);
   return EB_OK;
 }
 
 int eb_get_fused_mode(void) {
   const FusedCfg c = fused_cfg();
-  return c.separate ? EB_FUSED_SEPARATE : (c.atomic ? EB_FUSED_PERSISTENT_ATOMIC : EB_FUSED_PERSISTENT);
+  if (c.separate) return c.atomic ? EB_FUSED_SEPARATE_ATOMIC : EB_FUSED_SEPARATE;
+  return c.atomic ? EB_FUSED_PERSISTENT_ATOMIC : EB_FUSED_PERSISTENT;
 }
 
 int eb_set_fused_wait_limit(int64_t spins) {
@@ -668,10 +669,10 @@ int eb_autotune(const eb_sizes *sizes, const eb_topology *topo, const int32_t *e
           best.fused_blocks_per_cu = c.blocks_per_cu;
         }
       }
-  // the gather kernels in sequence (with the best gather shape) as one more
-  // candidate for the whole enqueue (not when the caller chose the atomic
-  // persistent kernel, whose mode is kept)
-  if (rc == EB_OK && !f0.atomic) {
+  // the separate kernels in sequence (with the best gather shape, and the
+  // adjoint of the reduction in force) as one more candidate for the whole
+  // enqueue
+  if (rc == EB_OK) {
     LaunchCfg g;
     g.tile = best.gather_tile;
     g.unroll = best.gather_unroll;
@@ -679,6 +680,7 @@ int eb_autotune(const eb_sizes *sizes, const eb_topology *topo, const int32_t *e
     set_gather_cfg(g);
     FusedCfg c;
     c.separate = 1;
+    c.atomic = f0.atomic;
     set_fused_cfg(c);
     float ms = 0.f;
     rc = time_it(

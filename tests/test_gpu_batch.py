@@ -189,6 +189,31 @@ def test_fused_bitwise_across_shapes(small3):
     eb().check_errors(bc.topo)
 
 
+def test_separate_atomic_mode(small3):
+    """The gather forward and the atomic adjoint in sequence: n, b, V equal
+    the deterministic enqueue's bits, dL/dx matches it to rounding, eager and
+    from a graph."""
+    bc = small3
+    ref = bc.fused()
+    eb().set_fused_mode("separate_atomic")
+    try:
+        assert eb().get_fused_mode() == "separate_atomic"
+        gr = eb().ForwardBackwardGraph(bc.X, bc.topo, bc.E, bc.W, bc.B, bc.C)
+        for run in range(3):
+            outs = bc.fused() if run == 0 else gr.launch()
+            torch.cuda.synchronize()
+            for k, (a, b) in enumerate(zip(outs, ref)):
+                if k < 3:
+                    assert torch.equal(a, b), f"run {run} output {k}"
+                else:
+                    scale = b.abs().max().item()
+                    assert (a - b).abs().max().item() <= 1e-12 * scale, f"run {run} grad"
+        gr.close()
+        eb().check_errors(bc.topo)
+    finally:
+        eb().set_fused_mode("persistent")
+
+
 @pytest.mark.parametrize("mode", ["persistent", "separate"])
 def test_graph_modes_equal_eager(small2, mode):
     """Both forms of the enqueue capture into a graph that replays the eager
@@ -266,12 +291,16 @@ def test_atomic_mode_graph_and_tuner(small3, tmp_path):
         cache = str(tmp_path / "tune_atomic.json")
         r = eb().autotune(bc.X, bc.topo, bc.E, bc.W, bc.B, bc.C, reps=1, cache=cache)
         say(f"[autotune atomic] {r}")
-        assert not r["cached"] and r["n_tried"] == 18 + 45
-        assert r["fused_separate"] == 0
-        assert eb().get_fused_mode() == "persistent_atomic"
+        assert not r["cached"] and r["n_tried"] == 18 + 45 + 1
+        mode = "separate_atomic" if r["fused_separate"] else "persistent_atomic"
+        assert eb().get_fused_mode() == mode
         assert eb().get_fused_shape() == (r["fused_tile"], r["fused_unroll"],
                                           r["fused_blocks_per_cu"])
         assert next(iter(json.load(open(cache)))).endswith("|atomic")
+        # a cached entry restores the same choice within the atomic modes
+        eb().set_fused_mode("persistent_atomic")
+        rc = eb().autotune(bc.X, bc.topo, bc.E, bc.W, bc.B, bc.C, reps=1, cache=cache)
+        assert rc["cached"] and eb().get_fused_mode() == mode
         eb().check_errors(bc.topo)
     finally:
         eb().set_fused_shape(128, 2, 0)
