@@ -522,13 +522,14 @@ __device__ __forceinline__ void fwd_boundary_node(const FwdArgs &a, int64_t bj) 
         for (int s = 0; s < D; ++s) P[u][s] = load_pt<D>(a.X, fv[u][s]);
 #pragma unroll
       for (int u = 0; u < G; ++u) {
+        // (uncontracted: the same bits as k_fwd_boundary_gather's groups)
         V3 nB;
         if constexpr (D == 3)
-          nB = 0.5 * cross(P[u][1] - P[u][0], P[u][2] - P[u][0]);
+          nB = nc_scale(0.5, nc_cross(P[u][1] - P[u][0], P[u][2] - P[u][0]));
         else
           nB = rot2(P[u][1] - P[u][0]);
-        if (r + u < r1) bs = bs + nB;
-        c[u] = kB * nB;
+        if (r + u < r1) bs = nc_add(bs, nB);
+        c[u] = nc_scale(kB, nB);
       }
     }
     // hit h = (face u, its (h % (D-1))-th vertex other than j, in vertex order)
@@ -567,7 +568,7 @@ __device__ __forceinline__ void fwd_boundary_node(const FwdArgs &a, int64_t bj) 
 #pragma unroll
       for (int g = 0; g < h; ++g)
         if (hit[g] && ed[g] == ed[h]) base = val[g];
-      val[h] = base + c[h / (D - 1)];
+      val[h] = nc_add(base, c[h / (D - 1)]);
     }
 #pragma unroll
     for (int h = 0; h < H; ++h) {
@@ -578,10 +579,10 @@ __device__ __forceinline__ void fwd_boundary_node(const FwdArgs &a, int64_t bj) 
     }
   }
   if (a.b_x) {
-    constexpr double kb = 1.0 / D;
-    a.b_x[bj] = kb * bs.x;
-    a.b_y[bj] = kb * bs.y;
-    if (D == 3) a.b_z[bj] = kb * bs.z;
+    const V3 bo = nc_scale(1.0 / D, bs);
+    a.b_x[bj] = bo.x;
+    a.b_y[bj] = bo.y;
+    if (D == 3) a.b_z[bj] = bo.z;
   }
 }
 

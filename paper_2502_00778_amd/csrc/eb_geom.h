@@ -29,6 +29,20 @@ __device__ __forceinline__ V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b
 __device__ __forceinline__ V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
 __device__ __forceinline__ V3 operator-(V3 a) { return {-a.x, -a.y, -a.z}; }
 __device__ __forceinline__ V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+// V3 arithmetic never contracted into fused multiply-adds, so that it gives
+// the same bits in every kernel it is inlined into
+__device__ __forceinline__ V3 nc_add(V3 a, V3 b) {
+#pragma clang fp contract(off)
+  return {a.x + b.x, a.y + b.y, a.z + b.z};
+}
+__device__ __forceinline__ V3 nc_scale(double s, V3 a) {
+#pragma clang fp contract(off)
+  return {s * a.x, s * a.y, s * a.z};
+}
+__device__ __forceinline__ V3 nc_cross(V3 a, V3 b) {
+#pragma clang fp contract(off)
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
 __device__ __forceinline__ V3 cross(V3 a, V3 b) {
   return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }

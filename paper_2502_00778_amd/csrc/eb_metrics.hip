@@ -161,10 +161,89 @@ __global__ __launch_bounds__(256) void k_fwd_boundary_dual(FwdArgs a) {
   if (D == 3) a.b_z[bj] = bs.z;
 }
 
+// The boundary pass with BG lanes per boundary node: the node's faces are
+// formed a lane each, BG_FACES at a time staged in LDS; then a lane per
+// out-edge adds n_B/(D(D+1)) of the faces holding the edge's head, in face
+// order, and the group's first lane sums b_j's n_B in face order: per output
+// the operations, in the order, of fwd_boundary_node (the persistent
+// kernel's form; both uncontracted, so their bits agree).
+constexpr int BG = 8, BG_FACES = 16;
+
 template <int D>
 __global__ __launch_bounds__(64) void k_fwd_boundary_gather(FwdArgs a) {
-  const int64_t bj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (bj < a.nbnode) fwd_boundary_node<D>(a, bj);
+  __shared__ int32_t sfv[64 / BG][BG_FACES][D];
+  __shared__ double snb[64 / BG][BG_FACES][3];
+  const int t = threadIdx.x, grp = t / BG, g = t % BG;
+  const int64_t bj = (int64_t)blockIdx.x * (64 / BG) + grp;
+  const bool live = bj < a.nbnode;
+  int32_t j = 0, my0 = 0, nout = 0, r0 = 0, nf = 0;
+  if (live) {
+    j = a.bnode[bj];
+    my0 = a.node_edge_off[j];
+    nout = a.node_edge_off[j + 1] - my0;
+    r0 = a.bnode_face_off[bj];
+    nf = a.bnode_face_off[bj + 1] - r0;
+  }
+  // chunks of faces, as many as the block's longest list needs (every lane
+  // takes every barrier)
+  int32_t nch = (nf + BG_FACES - 1) / BG_FACES;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) nch = max(nch, __shfl_xor(nch, o, 64));
+  constexpr double kB = 1.0 / (D * (D + 1));
+  V3 bs = {0.0, 0.0, 0.0};
+  for (int32_t ch = 0; ch < nch; ++ch) {
+    const int32_t u0 = ch * BG_FACES, m = min(nf - u0, BG_FACES);
+    __syncthreads();  // (the previous chunk is used up)
+    for (int32_t u = g; u < m; u += BG) {
+      const int32_t f = a.bnode_face[r0 + u0 + u];
+      V3 P[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        const int32_t v = a.bface[(int64_t)f * D + q];
+        sfv[grp][u][q] = v;
+        P[q] = load_pt<D>(a.X, v);
+      }
+      V3 nB;
+      if constexpr (D == 3)
+        nB = nc_scale(0.5, nc_cross(P[1] - P[0], P[2] - P[0]));
+      else
+        nB = rot2(P[1] - P[0]);
+      snb[grp][u][0] = nB.x;
+      snb[grp][u][1] = nB.y;
+      snb[grp][u][2] = nB.z;
+    }
+    __syncthreads();
+    if (g == 0)
+      for (int32_t u = 0; u < m; ++u)
+        bs = nc_add(bs, V3{snb[grp][u][0], snb[grp][u][1], snb[grp][u][2]});
+    for (int32_t q = g; q < nout; q += BG) {
+      const int32_t e = my0 + q, h = a.edge_head[e];
+      V3 acc = {0.0, 0.0, 0.0};
+      bool any = false;
+      for (int32_t u = 0; u < m; ++u) {
+        bool on = false;
+#pragma unroll
+        for (int k = 0; k < D; ++k) on = on || sfv[grp][u][k] == h;
+        if (!on) continue;
+        if (!any) {
+          acc = V3{a.n_x[e], a.n_y[e], D == 3 ? a.n_z[e] : 0.0};
+          any = true;
+        }
+        acc = nc_add(acc, nc_scale(kB, V3{snb[grp][u][0], snb[grp][u][1], snb[grp][u][2]}));
+      }
+      if (any) {
+        a.n_x[e] = acc.x;
+        a.n_y[e] = acc.y;
+        if (D == 3) a.n_z[e] = acc.z;
+      }
+    }
+  }
+  if (live && g == 0 && a.b_x) {
+    const V3 bo = nc_scale(1.0 / D, bs);
+    a.b_x[bj] = bo.x;
+    a.b_y[bj] = bo.y;
+    if (D == 3) a.b_z[bj] = bo.z;
+  }
 }
 
 // ----------------------------------------------------- volumes on their own
@@ -339,7 +418,7 @@ template <int D>
 int launch_fwd_boundary(const FwdArgs &a, hipStream_t s) {
   if (a.nbnode <= 0) return EB_OK;
   // (blocks of one wave: the few boundary nodes spread over every CU)
-  launch_span(k_fwd_boundary_gather<D>, dim3(grid_for(a.nbnode, 64)), dim3(64), 0, s, a);
+  launch_span(k_fwd_boundary_gather<D>, dim3(grid_for(a.nbnode, 64 / BG)), dim3(64), 0, s, a);
   EB_LAUNCH_CHECK();
   return EB_OK;
 }
