@@ -303,18 +303,25 @@ __device__ __forceinline__ void bwd_atomic_elem_block(const FwdArgs &a, int64_t 
   lds_acc_flush<TB>(T, gout, t);
 }
 
-// One boundary face's adjoint terms, added with FP64 atomics.
+// One boundary face's adjoint terms G[p] for its vertices fv[p].
 template <int D>
-__device__ __forceinline__ void bwd_atomic_bface_one(const FwdArgs &a, int64_t f) {
-  int32_t fv[D];
+__device__ __forceinline__ void bwd_bface_terms(const FwdArgs &a, int64_t f, int32_t (&fv)[D],
+                                                V3 (&G)[D]) {
   V3 P[D];
 #pragma unroll
   for (int s = 0; s < D; ++s) {
     fv[s] = a.bface[f * D + s];
     P[s] = load_pt<D>(a.X, fv[s]);
   }
-  V3 G[D];
   bface_grad_all<D>(P, bface_weight<D>(a, f, fv), G);
+}
+
+// One boundary face's adjoint terms, added with FP64 atomics.
+template <int D>
+__device__ __forceinline__ void bwd_atomic_bface_one(const FwdArgs &a, int64_t f) {
+  int32_t fv[D];
+  V3 G[D];
+  bwd_bface_terms<D>(a, f, fv, G);
 #pragma unroll
   for (int p = 0; p < D; ++p) {
     unsafeAtomicAdd(&a.g_x[fv[p]], G[p].x);

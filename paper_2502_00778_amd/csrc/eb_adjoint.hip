@@ -14,10 +14,34 @@ __global__ __launch_bounds__(ATOMIC_TB) void k_bwd_atomic_elem(FwdArgs a) {
   bwd_atomic_elem_block<D, ATOMIC_TB, ATOMIC_EPT>(a, blockIdx.x, tg);
 }
 
+// One thread per boundary face; a block's 256 faces (in bface order,
+// consecutive ones sharing most vertices) sum their terms per node in an LDS
+// table first, then add each sum with one FP64 atomic per component.
+constexpr int BF_TB = 256, BF_H = 512;
+
 template <int D>
-__global__ __launch_bounds__(256) void k_bwd_atomic_bface(FwdArgs a) {
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f < a.nbface) bwd_atomic_bface_one<D>(a, f);
+__global__ __launch_bounds__(BF_TB) void k_bwd_atomic_bface(FwdArgs a) {
+  __shared__ LdsAcc<BF_H, D> T;
+  const int t = threadIdx.x;
+  double *const gout[3] = {a.g_x, a.g_y, a.g_z};
+  lds_acc_init<BF_TB>(T, t);
+  __syncthreads();
+  const int64_t f = (int64_t)blockIdx.x * BF_TB + t;
+  if (f < a.nbface) {
+    int32_t fv[D];
+    V3 G[D];
+    bwd_bface_terms<D>(a, f, fv, G);
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+      double c[D];
+      c[0] = G[p].x;
+      c[1] = G[p].y;
+      if constexpr (D == 3) c[D - 1] = G[p].z;
+      lds_acc_add(T, gout, fv[p], c);
+    }
+  }
+  __syncthreads();
+  lds_acc_flush<BF_TB>(T, gout, t);
 }
 
 // ------------------------------------------------------------- gather path
@@ -55,8 +79,8 @@ int backward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_
       EB_LAUNCH_CHECK();
     }
     if (a.nbface > 0 && (a.w_x || a.be_x)) {
-      hipLaunchKernelGGL(k_bwd_atomic_bface<D>, dim3(grid_for(a.nbface, 256)), dim3(256), 0, s,
-                         a);
+      hipLaunchKernelGGL(k_bwd_atomic_bface<D>, dim3(grid_for(a.nbface, BF_TB)), dim3(BF_TB), 0,
+                         s, a);
       EB_LAUNCH_CHECK();
     }
     return EB_OK;

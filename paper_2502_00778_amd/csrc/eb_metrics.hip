@@ -76,41 +76,58 @@ __global__ __launch_bounds__(ATOMIC_TB) void k_fwd_atomic_elem(FwdArgs a) {
   if (want_v) lds_acc_flush<ATOMIC_TB>(tv, vout, t);
 }
 
+// One thread per boundary face; a block's faces (in bface order, consecutive
+// ones sharing most vertices and edges) sum n_B/(D(D+1)) per edge and n_B/D
+// per boundary node in LDS tables first, then add each sum with one FP64
+// atomic per component.
+constexpr int AB_TB = 256, AB_HE = 1024, AB_HB = 512;
+
 template <int D>
-__global__ __launch_bounds__(256) void k_fwd_atomic_bface(FwdArgs a) {
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= a.nbface) return;
-  V3 nB;
-  int32_t fv[D];
+__global__ __launch_bounds__(AB_TB) void k_fwd_atomic_bface(FwdArgs a) {
+  __shared__ LdsAcc<AB_HE, D> te;
+  __shared__ LdsAcc<AB_HB, D> tb;
+  const int t = threadIdx.x;
+  const bool want_n = a.n_x != nullptr, want_b = a.b_x != nullptr;
+  double *const nout[3] = {a.n_x, a.n_y, a.n_z};
+  double *const bout[3] = {a.b_x, a.b_y, a.b_z};
+  if (want_n) lds_acc_init<AB_TB>(te, t);
+  if (want_b) lds_acc_init<AB_TB>(tb, t);
+  __syncthreads();
+  const int64_t f = (int64_t)blockIdx.x * AB_TB + t;
+  if (f < a.nbface) {
+    V3 nB;
+    int32_t fv[D];
 #pragma unroll
-  for (int s = 0; s < D; ++s) fv[s] = a.bface[f * D + s];
-  if constexpr (D == 3) {
-    const V3 A = load_pt<D>(a.X, fv[0]), B = load_pt<D>(a.X, fv[1]), C = load_pt<D>(a.X, fv[2]);
-    nB = 0.5 * cross(B - A, C - A);
-  } else {
-    nB = rot2(load_pt<D>(a.X, fv[1]) - load_pt<D>(a.X, fv[0]));
-  }
-  constexpr double kB = 1.0 / (D * (D + 1));
-  constexpr int NBE = D == 2 ? 1 : 3;
-  if (a.n_x) {
+    for (int s = 0; s < D; ++s) fv[s] = a.bface[f * D + s];
+    if constexpr (D == 3) {
+      const V3 A = load_pt<D>(a.X, fv[0]), B = load_pt<D>(a.X, fv[1]), C = load_pt<D>(a.X, fv[2]);
+      nB = 0.5 * cross(B - A, C - A);
+    } else {
+      nB = rot2(load_pt<D>(a.X, fv[1]) - load_pt<D>(a.X, fv[0]));
+    }
+    constexpr int NBE = D == 2 ? 1 : 3;
+    if (want_n) {
+      constexpr double kB = 1.0 / (D * (D + 1));
+      double c[D];
+      c[0] = kB * nB.x;
+      c[1] = kB * nB.y;
+      if constexpr (D == 3) c[D - 1] = kB * nB.z;
 #pragma unroll
-    for (int i = 0; i < NBE; ++i) {
-      const int32_t id = a.bface_edge[f * NBE + i];
-      unsafeAtomicAdd(&a.n_x[id], kB * nB.x);
-      unsafeAtomicAdd(&a.n_y[id], kB * nB.y);
-      if (D == 3) unsafeAtomicAdd(&a.n_z[id], kB * nB.z);
+      for (int i = 0; i < NBE; ++i) lds_acc_add(te, nout, a.bface_edge[f * NBE + i], c);
+    }
+    if (want_b) {
+      constexpr double kb = 1.0 / D;
+      double c[D];
+      c[0] = kb * nB.x;
+      c[1] = kb * nB.y;
+      if constexpr (D == 3) c[D - 1] = kb * nB.z;
+#pragma unroll
+      for (int s = 0; s < D; ++s) lds_acc_add(tb, bout, a.node_bnode[fv[s]], c);
     }
   }
-  if (a.b_x) {
-    constexpr double kb = 1.0 / D;
-#pragma unroll
-    for (int s = 0; s < D; ++s) {
-      const int32_t bi = a.node_bnode[fv[s]];
-      unsafeAtomicAdd(&a.b_x[bi], kb * nB.x);
-      unsafeAtomicAdd(&a.b_y[bi], kb * nB.y);
-      if (D == 3) unsafeAtomicAdd(&a.b_z[bi], kb * nB.z);
-    }
-  }
+  __syncthreads();
+  if (want_n) lds_acc_flush<AB_TB>(te, nout, t);
+  if (want_b) lds_acc_flush<AB_TB>(tb, bout, t);
 }
 
 // ------------------------------------------------------------- gather path
@@ -475,7 +492,7 @@ int forward_impl(const FwdArgs &a, int reduce, const LaunchCfg &cfg, hipStream_t
       EB_LAUNCH_CHECK();
     }
     if (a.nbface > 0 && (a.n_x || a.b_x)) {
-      launch_span(k_fwd_atomic_bface<D>, dim3(grid_for(a.nbface, 256)), dim3(256), 0, s, a);
+      launch_span(k_fwd_atomic_bface<D>, dim3(grid_for(a.nbface, AB_TB)), dim3(AB_TB), 0, s, a);
       EB_LAUNCH_CHECK();
     }
     return EB_OK;
