@@ -13,8 +13,8 @@
 // the node, and adds it to its out-edges' accumulators in LDS (the tile's
 // out-edges are contiguous; a node's edge found among its first 16 heads,
 // held in registers, or by binary search beyond), in row order; the tile's
-// edges are written once.  A boundary pass, a wavefront per boundary node,
-// follows.  The atomic forward sums each block's element contributions per
+// edges are written once.  A boundary pass, sixteen lanes per boundary
+// node, follows.  The atomic forward sums each block's element contributions per
 // edge and per node in LDS hash tables first, then adds each sum with one
 // FP64 atomic, and its boundary faces likewise.
 #include "eb_geom.h"  // (the LDS hash tables of the atomic pass)
@@ -155,67 +155,82 @@ __global__ __launch_bounds__(T4_TN) void k4_fwd_tile(Fwd4 a) {
   }
 }
 
-// gather forward, boundary pass: a wave per boundary node.  Its faces' n_B
-// are formed a lane each (B4_CAP at a time, in bnode_face order) and kept in
-// LDS; then each lane takes out-edges of the node and adds n_B/20 of the
-// faces holding the edge's head, in that order, and lanes 0..3 sum the
-// components of b_j = sum n_B/4 likewise: every output gets the additions,
-// in the order, of a walk over the node's faces.
-constexpr int B4_CAP = 64;
+// gather forward, boundary pass: B4_G lanes per boundary node (64 / B4_G
+// nodes a wave).  A node's faces' n_B are formed a lane each, B4_CAP at a
+// time staged in LDS; then a lane per out-edge adds n_B/20 of the faces
+// holding the edge's head, in face order, and the group's first lane sums
+// b_j = sum n_B/4 likewise: every output gets the additions, in the order,
+// of a walk over the node's faces.
+constexpr int B4_G = 16, B4_CAP = 32;
 
 __global__ __launch_bounds__(64) void k4_fwd_boundary(Fwd4 a) {
-  __shared__ double snb[4][B4_CAP];
-  __shared__ int32_t sfv[4][B4_CAP];
-  const int lane = threadIdx.x;
-  const int64_t bj = blockIdx.x;
-  const int32_t j = a.bnode[bj];
-  const int32_t e0 = a.node_edge_off[j], nout = a.node_edge_off[j + 1] - e0;
-  const int32_t f0 = a.bnode_face_off[bj], nf = a.bnode_face_off[bj + 1] - f0;
+  __shared__ double snb[64 / B4_G][B4_CAP][4];
+  __shared__ int32_t sfv[64 / B4_G][B4_CAP][4];
+  const int t = threadIdx.x, grp = t / B4_G, g = t % B4_G;
+  const int64_t bj = (int64_t)blockIdx.x * (64 / B4_G) + grp;
+  const bool live = bj < a.nbnode;
+  int32_t e0 = 0, nout = 0, f0 = 0, nf = 0;
+  if (live) {
+    const int32_t j = a.bnode[bj];
+    e0 = a.node_edge_off[j];
+    nout = a.node_edge_off[j + 1] - e0;
+    f0 = a.bnode_face_off[bj];
+    nf = a.bnode_face_off[bj + 1] - f0;
+  }
+  // as many chunks as the block's longest face list needs (every lane takes
+  // every barrier)
+  int32_t nch = (nf + B4_CAP - 1) / B4_CAP;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) nch = max(nch, __shfl_xor(nch, o, 64));
   const bool want_n = a.n[0] != nullptr;
-  double bs = 0.0;  // component `lane` of b_j (lanes 0..3)
-  for (int32_t c0 = 0; c0 < nf; c0 += B4_CAP) {
-    const int32_t m = min(nf - c0, B4_CAP);
+  double bs[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int32_t ch = 0; ch < nch; ++ch) {
+    const int32_t c0 = ch * B4_CAP, m = min(nf - c0, B4_CAP);
     __syncthreads();  // (the previous chunk is used up)
-    if (lane < m) {
-      const int32_t f = a.bnode_face[f0 + c0 + lane];
-      int32_t fv[4];
+    for (int32_t u = g; u < m; u += B4_G) {
+      const int32_t f = a.bnode_face[f0 + c0 + u];
       V4 Q[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        fv[s] = a.bface[4 * (int64_t)f + s];
-        Q[s] = load_pt4(a.X, fv[s]);
+        const int32_t v = a.bface[4 * (int64_t)f + s];
+        sfv[grp][u][s] = v;
+        Q[s] = load_pt4(a.X, v);
       }
       const V4 nB = v4_scale(
           1.0 / 6.0, v4_cross(v4_sub(Q[1], Q[0]), v4_sub(Q[2], Q[0]), v4_sub(Q[3], Q[0])));
 #pragma unroll
-      for (int c = 0; c < 4; ++c) snb[c][lane] = nB.c[c];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) sfv[s][lane] = fv[s];
+      for (int c = 0; c < 4; ++c) snb[grp][u][c] = nB.c[c];
     }
     __syncthreads();
-    if (lane < 4)
-      for (int32_t i = 0; i < m; ++i) bs += 0.25 * snb[lane][i];
+    if (g == 0)
+      for (int32_t u = 0; u < m; ++u)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bs[c] += 0.25 * snb[grp][u][c];
     if (want_n)
-      for (int32_t s = lane; s < nout; s += 64) {
+      for (int32_t s = g; s < nout; s += B4_G) {
         const int32_t h = a.edge_head[e0 + s];
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         bool any = false;
-        for (int32_t i = 0; i < m; ++i) {
-          if (sfv[0][i] != h && sfv[1][i] != h && sfv[2][i] != h && sfv[3][i] != h) continue;
+        for (int32_t u = 0; u < m; ++u) {
+          if (sfv[grp][u][0] != h && sfv[grp][u][1] != h && sfv[grp][u][2] != h &&
+              sfv[grp][u][3] != h)
+            continue;
           if (!any) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[c] = a.n[c][e0 + s];
             any = true;
           }
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acc[c] += 0.05 * snb[c][i];
+          for (int c = 0; c < 4; ++c) acc[c] += 0.05 * snb[grp][u][c];
         }
         if (any)
 #pragma unroll
           for (int c = 0; c < 4; ++c) a.n[c][e0 + s] = acc[c];
       }
   }
-  if (a.b[0] && lane < 4) a.b[lane][bj] = bs;
+  if (live && g == 0 && a.b[0])
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a.b[c][bj] = bs[c];
 }
 
 // atomic forward: one thread per element; a block's 256 consecutive
@@ -436,7 +451,7 @@ int forward4(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
   launch_principal(k4_fwd_tile, dim3(grid_for(a.nv, T4_TN)), dim3(T4_TN), 0, s, a);
   EB_LAUNCH_CHECK();
   if (a.nbnode > 0) {
-    launch_span(k4_fwd_boundary, dim3((unsigned)a.nbnode), dim3(64), 0, s, a);
+    launch_span(k4_fwd_boundary, dim3(grid_for(a.nbnode, 64 / B4_G)), dim3(64), 0, s, a);
     EB_LAUNCH_CHECK();
   }
   return EB_OK;
