@@ -207,15 +207,16 @@ int eb_build_edges_emit(const eb_sizes *sizes, const int32_t *elem, const double
  * 3.2.3), boundary dual-face normals b_node [dim][n_bnodes] (NULL to skip)
  * and element-based dual volumes vol [n_nodes] (Section 4.2; NULL to skip),
  * in one pass over the grid.
- *   EB_REDUCE_ATOMIC: one thread per element; each block sums its elements'
- *     contributions per edge and per node in LDS, then adds each sum to the
- *     zeroed outputs with one FP64 atomic (summation order varies from run
- *     to run).  dim 4: plain per-element atomics.
+ *   EB_REDUCE_ATOMIC: one thread per element, then one per boundary face;
+ *     each block sums its contributions per edge and per node in LDS, then
+ *     adds each sum to the zeroed outputs with one FP64 atomic (summation
+ *     order varies from run to run).
  *   EB_REDUCE_GATHER: one thread per node gathers over its elements in
  *     node_inc order and owns the edges it is the tail of; every output is
  *     written once, bitwise reproducible.  Needs node_inc, node_edge_off,
- *     edge, node_bnode, bnode_face_off/bnode_face, bface.  dim 4: one thread
- *     per node walks its node_inc row (no plan), then one per boundary node. */
+ *     edge, node_bnode, bnode_face_off/bnode_face, bface.  Boundary nodes
+ *     follow in a second pass, a group of lanes each.  dim 4: one thread per
+ *     node walks its node_inc row (no plan). */
 int eb_directed_areas(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
                       const double *coords, int reduce, double *n_edge, double *b_node,
                       double *vol, void *ws, size_t ws_bytes, hipStream_t stream);
@@ -298,8 +299,8 @@ int eb_edge_residual(const eb_sizes *sizes, const eb_topology *topo, const int32
  * grad_coords = dL/dx [dim][n_nodes] for the metrics eb_directed_areas
  * computes (element-based V).  Derivative of the element and boundary
  * formulas above; the orientation sign of each element is held fixed.
- * ATOMIC: thread per element (each block's per-node sums first gathered in
- * LDS, one FP64 atomic per node and component) and per boundary face.  GATHER: an
+ * ATOMIC: thread per element, then per boundary face (each block's per-node
+ * sums first gathered in LDS, one FP64 atomic per node and component).  GATHER: an
  * element pass writes each element's gradient with respect to each of its
  * vertices into the workspace at that incidence's slot of the plan, then
  * one thread per node sums its slots in node_inc order and adds its boundary
