@@ -208,3 +208,71 @@ def test_dim4_unsupported_calls_refused():
     assert e.value.code == -1
     with pytest.raises(eb.EbError):
         eb.directed_areas_variant(X, gt, E, "edge_normals")
+
+
+# ------------------------------------------------------------ full size
+
+def test_dim4_full_size_33():
+    """33^4 grid (25,165,824 pentatopes), built and run as the benchmark
+    times it.  At every entry: closure at every node, the total volume 1,
+    the atomic reduction and the edge-based V against the gather's.
+    Against the oracle: n, b and V at about 256 sampled nodes (64 of them
+    on the boundary) and every edge that ends at one, from the oracle on the union of those nodes' stars, which
+    holds every element and boundary face these outputs sum over."""
+    import paper_2502_00778_amd as eb
+    from tests._stars import edge_index, stars
+    say("[4d 33^4] grid")
+    m = meshgen.hypercube_kuhn(33, 0)
+    X, E = dev(m)
+    say("[4d 33^4] GPU build")
+    gt = eb.build_edges(E, X, edge_inc=False, adjoint=False)
+    nv = m.n_nodes
+    edge = gt["edge"].cpu().numpy()
+    bnode = gt["bnode"].cpu().numpy()
+    node_bnode = gt["node_bnode"].cpu().numpy()
+    say("[4d 33^4] forward, gather and atomic")
+    ng, bg, Vg = eb.directed_areas(X, gt, E, "gather")
+    Ve = eb.dual_volumes(X, gt, E, "edge", n=ng, reduce="gather")
+    na, ba, Va = (t.cpu().numpy() for t in eb.directed_areas(X, gt, E, "atomic"))
+    eb.check_errors(gt)
+    n, b, V, Ve = (t.cpu().numpy() for t in (ng, bg, Vg, Ve))
+    del ng, bg, Vg
+    nmax = np.linalg.norm(n, axis=0).max()
+
+    say("[4d 33^4] closure, volume, reductions and V forms at every entry")
+    for c in range(4):
+        a = (np.bincount(edge[0], weights=n[c], minlength=nv)
+             - np.bincount(edge[1], weights=n[c], minlength=nv))
+        a[bnode] += b[c]
+        assert np.abs(a).max() < 1e-13 * nmax, f"closure, component {c}"
+    assert abs(V.sum() - 1.0) < 1e-12
+    mag = np.linalg.norm(n, axis=0)
+    assert (np.linalg.norm(na - n, axis=0) <= 1e-12 * np.maximum(mag, 1e-3 * nmax)).all()
+    bmag = np.linalg.norm(b, axis=0)
+    assert (np.linalg.norm(ba - b, axis=0) <= 1e-12 * np.maximum(bmag, 1e-3 * bmag.max())).all()
+    assert_vol_close(Va, V, "V atomic")
+    assert_vol_close(Ve, V, "V edge form")
+
+    say("[4d 33^4] oracle on the stars of the sampled nodes")
+    rng = np.random.default_rng(33)
+    nodes = np.unique(np.concatenate([[0, nv - 1], bnode[rng.choice(bnode.size, 64, replace=False)],
+                                      rng.choice(nv, 192, replace=False)]))
+    ids, sm = stars(m, nodes)
+    st = oracle.topology(4, sm.coords, sm.elems)
+    n0, b0, V0 = oracle.metrics(st, sm.coords, sm.elems)
+    S_e, S_b = scales(st, sm.coords, sm.elems)
+    ge = ids[st["edge"]]
+    mine = np.isin(ge, nodes).any(axis=0)
+    idx = edge_index(edge, nv, ge[0, mine], ge[1, mine])
+    say(f"    {nodes.size} nodes, {sm.n_elems} pentatopes, {idx.size} edges compared")
+    for got, what in ((n, "n gather"), (na, "n atomic")):
+        assert_vec_close(got[:, idx], n0[:, mine], S_e[mine], what)
+    at = np.searchsorted(ids, nodes)
+    for got, what in ((V, "V gather"), (Va, "V atomic"), (Ve, "V edge form")):
+        assert_vol_close(got[nodes], V0[at], what)
+    gb = ids[st["bnode"]]
+    kb = np.isin(gb, nodes)
+    assert kb.sum() >= 64
+    assert np.array_equal(bnode[node_bnode[gb[kb]]], gb[kb])
+    for got, what in ((b, "b gather"), (ba, "b atomic")):
+        assert_vec_close(got[:, node_bnode[gb[kb]]], b0[:, kb], S_b[kb], what)

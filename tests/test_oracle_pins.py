@@ -697,3 +697,33 @@ def test_4d_counts_and_euler(n):
     tets = {tuple(sorted(c)) for el in m.elems.tolist() for c in combinations(el, 4)}
     assert t.n_nodes - t.n_edges + len(tris) - len(tets) + t.n_elems == 1
     assert len(tets) == (5 * t.n_elems + t.n_bfaces) // 2
+
+
+@pytest.mark.parametrize("dim", [3, 4])
+def test_star_union_gives_the_grids_values(dim):
+    """Locality of the formulas (Section 3.2.3): the oracle on the union of
+    some nodes' stars gives the whole grid's n at every edge with such a
+    node as an end, and its V and b at those nodes; at other edges of the
+    union the values differ (their elements are not all there)."""
+    from tests._stars import edge_index, stars
+    m = meshgen.hypercube_kuhn(7, 3) if dim == 4 else meshgen.cube_kuhn(9, 3)
+    t = oracle.topology(dim, m.coords, m.elems)
+    n0, b0, V0 = oracle.metrics(t, m.coords, m.elems)
+    rng = np.random.default_rng(11)
+    nodes = np.unique(np.concatenate([[0, m.n_nodes - 1],
+                                      rng.choice(m.n_nodes, 30, replace=False)]))
+    ids, sm = stars(m, nodes)
+    st = oracle.topology(dim, sm.coords, sm.elems)
+    n1, b1, V1 = oracle.metrics(st, sm.coords, sm.elems)
+    ge = ids[st["edge"]]
+    idx = edge_index(t["edge"], m.n_nodes, ge[0], ge[1])
+    mine = np.isin(ge, nodes).any(axis=0)
+    scale = np.abs(n0).max()
+    np.testing.assert_allclose(n1[:, mine], n0[:, idx[mine]], rtol=1e-13, atol=1e-15 * scale)
+    assert np.abs(n1[:, ~mine] - n0[:, idx[~mine]]).max() > 1e-6 * scale
+    np.testing.assert_allclose(V1[np.searchsorted(ids, nodes)], V0[nodes], rtol=1e-13)
+    gb = ids[st["bnode"]]
+    kb = np.isin(gb, nodes)
+    assert kb.sum() >= 2  # the grid's first and last nodes are corners
+    np.testing.assert_allclose(b1[:, kb], b0[:, t["node_bnode"][gb[kb]]], rtol=1e-13,
+                               atol=1e-15 * np.abs(b0).max())
