@@ -286,7 +286,11 @@ __global__ __launch_bounds__(A4_TB) void k4_fwd_atomic_elem(Fwd4 a) {
   if (want_n) lds_acc_init<A4_TB>(te, t);
   if (want_v) lds_acc_init<A4_TB>(tv, t);
   __syncthreads();
-  const int64_t e = (int64_t)blockIdx.x * A4_TB + t;
+  // a wave takes every fourth element of the block: neighbouring elements
+  // (in a structured numbering, those of one cell, which share edges and
+  // nodes) go to different waves, so fewer lanes of one LDS atomic
+  // instruction hit the same slot
+  const int64_t e = (int64_t)blockIdx.x * A4_TB + (t & 63) * (A4_TB / 64) + (t >> 6);
   if (e < a.nelem) elem4_sums(a, e, te, tv);
   __syncthreads();
   if (want_n) lds_acc_flush<A4_TB>(te, a.n, t);
