@@ -9,7 +9,8 @@
 //
 // The gather forward takes tiles of 64 consecutive nodes, one wave each: a
 // node's thread walks its node_inc row four incidences at a time (their
-// connectivity and points loaded together), forms the face vector opposite
+// connectivity and points loaded together; the points from a copy of the
+// coordinates as 32-byte rows, made first in the workspace), forms the face vector opposite
 // the node, and adds it to its out-edges' accumulators in LDS (the tile's
 // out-edges are contiguous; a node's edge found among its first 16 heads,
 // held in registers, or by binary search beyond), in row order; the tile's
@@ -35,8 +36,25 @@ struct Fwd4 {
   double *b[4];  // [4][n_bnodes] rows, or null
   double *vol;   // or null
   double *term;  // per-edge terms of the edge loop
+  const double4 *xa;  // the points as 32-byte rows (node pass), or null
   StatusBlock *st;
 };
+
+// a point from the coordinate rows, or from its 32-byte row (two 16-byte
+// loads on one line instead of four 8-byte loads on four)
+template <bool AOS> __device__ __forceinline__ V4 node_pt4(const Fwd4 &a, int32_t v) {
+  if constexpr (AOS) {
+    const double4 p = a.xa[v];
+    return {{p.x, p.y, p.z, p.w}};
+  } else {
+    return load_pt4(a.X, v);
+  }
+}
+
+__global__ __launch_bounds__(256) void k4_points_rows(Coords4 X, int64_t nv, double4 *xa) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j < nv) xa[j] = make_double4(X.x[j], X.y[j], X.z[j], X.w[j]);
+}
 
 __device__ __forceinline__ int32_t out_slot(const int32_t *heads, int32_t n, int32_t k) {
   int32_t lo = 0, hi = n;
@@ -66,6 +84,7 @@ __device__ __forceinline__ void lds_add4(double *p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+template <bool AOS>
 __global__ __launch_bounds__(T4_TN) void k4_fwd_tile(Fwd4 a) {
   __shared__ double acc[4][T4_CAP];
   const int t = threadIdx.x;
@@ -111,7 +130,7 @@ __global__ __launch_bounds__(T4_TN) void k4_fwd_tile(Fwd4 a) {
         for (int c = 0; c < 4; ++c) a.n[c][base + s] += v.c[c];
       }
     };
-    const V4 Pj = load_pt4(a.X, j);
+    const V4 Pj = node_pt4<AOS>(a, j);
     double V = 0.0;
     const int32_t r0 = a.node_inc_off[j], r1 = a.node_inc_off[j + 1];
     constexpr int U = 4;  // (LDS holds a CU to a few waves: more loads in flight each)
@@ -126,7 +145,7 @@ __global__ __launch_bounds__(T4_TN) void k4_fwd_tile(Fwd4 a) {
       for (int u = 0; u < U; ++u) {
         others_of4(v[u], inc[u] % 5, o[u]);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) Q[u][m] = load_pt4(a.X, o[u][m]);
+        for (int m = 0; m < 4; ++m) Q[u][m] = node_pt4<AOS>(a, o[u][m]);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -239,13 +258,14 @@ __global__ __launch_bounds__(64) void k4_fwd_boundary(Fwd4 a) {
 constexpr int A4_TB = 256, A4_HE = 1024, A4_HV = 256;
 
 // one element's contributions into the block's tables
+template <bool AOS>
 __device__ __forceinline__ void elem4_sums(const Fwd4 &a, int64_t e, LdsAcc<A4_HE, 4> &te,
                                            LdsAcc<A4_HV, 1> &tv) {
   int32_t v[5];
   load_conn4(a.elem, e, v);
   V4 P[5], n[5];
 #pragma unroll
-  for (int i = 0; i < 5; ++i) P[i] = load_pt4(a.X, v[i]);
+  for (int i = 0; i < 5; ++i) P[i] = node_pt4<AOS>(a, v[i]);
   double d = 0.0;
 #pragma unroll
   for (int t = 0; t < 5; ++t) {
@@ -277,6 +297,7 @@ __device__ __forceinline__ void elem4_sums(const Fwd4 &a, int64_t e, LdsAcc<A4_H
   }
 }
 
+template <bool AOS>
 __global__ __launch_bounds__(A4_TB) void k4_fwd_atomic_elem(Fwd4 a) {
   __shared__ LdsAcc<A4_HE, 4> te;
   __shared__ LdsAcc<A4_HV, 1> tv;
@@ -291,7 +312,7 @@ __global__ __launch_bounds__(A4_TB) void k4_fwd_atomic_elem(Fwd4 a) {
   // nodes) go to different waves, so fewer lanes of one LDS atomic
   // instruction hit the same slot
   const int64_t e = (int64_t)blockIdx.x * A4_TB + (t & 63) * (A4_TB / 64) + (t >> 6);
-  if (e < a.nelem) elem4_sums(a, e, te, tv);
+  if (e < a.nelem) elem4_sums<AOS>(a, e, te, tv);
   __syncthreads();
   if (want_n) lds_acc_flush<A4_TB>(te, a.n, t);
   if (want_v) lds_acc_flush<A4_TB>(tv, vout, t);
@@ -411,6 +432,42 @@ void rows4(double *p, int64_t n, double *(&r)[4]) {
   for (int c = 0; c < 4; ++c) r[c] = p ? p + c * n : nullptr;
 }
 
+// the points copied as 32-byte rows into the workspace's incidence-row
+// region (80 bytes per element, free once the build is done) when they fit
+// there (else null, and the kernels read the coordinate rows)
+const double4 *point_rows4(const eb_sizes *sz, const Fwd4 &a, void *ws, hipStream_t s) {
+  const WsLayout L = ws_layout(4, sz->n_nodes, sz->n_elems);
+  if ((size_t)32 * (size_t)sz->n_nodes > L.inc_pos - L.rows4) return nullptr;
+  double4 *xa = ws_at<double4>(ws, L.rows4);
+  launch_span(k4_points_rows, dim3(grid_for(a.nv, 256)), dim3(256), 0, s, a.X, a.nv, xa);
+  return xa;
+}
+
+// the atomic element pass
+int elem_pass4(const eb_sizes *sz, Fwd4 &a, void *ws, hipStream_t s) {
+  a.xa = point_rows4(sz, a, ws, s);
+  EB_LAUNCH_CHECK();
+  if (a.xa)
+    launch_principal(k4_fwd_atomic_elem<true>, dim3(grid_for(a.nelem, 256)), dim3(256), 0, s, a);
+  else
+    launch_principal(k4_fwd_atomic_elem<false>, dim3(grid_for(a.nelem, 256)), dim3(256), 0, s, a);
+  EB_LAUNCH_CHECK();
+  return EB_OK;
+}
+
+// the gather node pass
+int node_pass4(const eb_sizes *sz, Fwd4 &a, void *ws, hipStream_t s) {
+  a.xa = point_rows4(sz, a, ws, s);
+  EB_LAUNCH_CHECK();
+  if (a.xa) {
+    launch_principal(k4_fwd_tile<true>, dim3(grid_for(a.nv, T4_TN)), dim3(T4_TN), 0, s, a);
+  } else {
+    launch_principal(k4_fwd_tile<false>, dim3(grid_for(a.nv, T4_TN)), dim3(T4_TN), 0, s, a);
+  }
+  EB_LAUNCH_CHECK();
+  return EB_OK;
+}
+
 }  // namespace
 
 int forward4(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
@@ -441,10 +498,7 @@ int forward4(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
     if (a.b[0])
       for (int c = 0; c < 4; ++c) EB_TRY(fill_f64(a.b[c], sz->n_bnodes, 0.0, s));
     if (a.vol) EB_TRY(fill_f64(a.vol, sz->n_nodes, 0.0, s));
-    if (a.nelem > 0) {
-      launch_principal(k4_fwd_atomic_elem, dim3(grid_for(a.nelem, 256)), dim3(256), 0, s, a);
-      EB_LAUNCH_CHECK();
-    }
+    if (a.nelem > 0) EB_TRY(elem_pass4(sz, a, ws, s));
     if (a.nbface > 0) {
       launch_span(k4_fwd_atomic_bface, dim3(grid_for(a.nbface, 256)), dim3(256), 0, s, a);
       EB_LAUNCH_CHECK();
@@ -452,7 +506,7 @@ int forward4(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
     return EB_OK;
   }
   EB_TRY(need(a.node_inc_off && a.node_inc, "node_inc"));
-  launch_principal(k4_fwd_tile, dim3(grid_for(a.nv, T4_TN)), dim3(T4_TN), 0, s, a);
+  EB_TRY(node_pass4(sz, a, ws, s));
   EB_LAUNCH_CHECK();
   if (a.nbnode > 0) {
     launch_span(k4_fwd_boundary, dim3(grid_for(a.nbnode, 64 / B4_G)), dim3(64), 0, s, a);
@@ -480,16 +534,11 @@ int volumes4(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
   if (mode == EB_VOL_ELEMENT) {
     if (reduce == EB_REDUCE_ATOMIC) {
       EB_TRY(fill_f64(vol, sz->n_nodes, 0.0, s));
-      if (a.nelem > 0) {
-        launch_principal(k4_fwd_atomic_elem, dim3(grid_for(a.nelem, 256)), dim3(256), 0, s, a);
-        EB_LAUNCH_CHECK();
-      }
+      if (a.nelem > 0) EB_TRY(elem_pass4(sz, a, ws, s));
       return EB_OK;
     }
     EB_TRY(need(a.node_inc_off && a.node_inc, "node_inc"));
-    launch_principal(k4_fwd_tile, dim3(grid_for(a.nv, T4_TN)), dim3(T4_TN), 0, s, a);
-    EB_LAUNCH_CHECK();
-    return EB_OK;
+    return node_pass4(sz, a, ws, s);
   }
   EB_TRY(need(a.edge_tail && a.edge_head, "edge"));
   const double *n[4];

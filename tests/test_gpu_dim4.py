@@ -85,7 +85,9 @@ CASES = {
     "4d-7-shuf": lambda: shuffled(meshgen.hypercube_kuhn(7, 2), 3),
     "4d-6-relabel": lambda: relabelled(meshgen.hypercube_kuhn(6, 4), 5),
     # node rows beyond the LDS limits: 162 incidences with 378 candidate
-    # faces; 384 incidences; 280 distinct neighbours; the apex as last node
+    # faces; 384 incidences; 280 distinct neighbours (and more nodes than
+    # the workspace's incidence rows hold as 32-byte point rows, so that the
+    # forward kernels read the coordinate rows); the apex as last node
     "4d-cone-4": lambda: cone(4, 6, True),
     "4d-cone-5": lambda: cone(5, 7, True),
     "4d-star-70": lambda: star(70, 8),
