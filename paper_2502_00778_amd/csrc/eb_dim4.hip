@@ -182,6 +182,7 @@ __global__ __launch_bounds__(T4_TN) void k4_fwd_tile(Fwd4 a) {
 // of a walk over the node's faces.
 constexpr int B4_G = 16, B4_CAP = 32;
 
+template <bool AOS>
 __global__ __launch_bounds__(64) void k4_fwd_boundary(Fwd4 a) {
   __shared__ double snb[64 / B4_G][B4_CAP][4];
   __shared__ int32_t sfv[64 / B4_G][B4_CAP][4];
@@ -213,7 +214,7 @@ __global__ __launch_bounds__(64) void k4_fwd_boundary(Fwd4 a) {
       for (int s = 0; s < 4; ++s) {
         const int32_t v = a.bface[4 * (int64_t)f + s];
         sfv[grp][u][s] = v;
-        Q[s] = load_pt4(a.X, v);
+        Q[s] = node_pt4<AOS>(a, v);
       }
       const V4 nB = v4_scale(
           1.0 / 6.0, v4_cross(v4_sub(Q[1], Q[0]), v4_sub(Q[2], Q[0]), v4_sub(Q[3], Q[0])));
@@ -324,6 +325,7 @@ __global__ __launch_bounds__(A4_TB) void k4_fwd_atomic_elem(Fwd4 a) {
 // with one FP64 atomic
 constexpr int AB4_TB = 256, AB4_HE = 1024, AB4_HB = 256;
 
+template <bool AOS>
 __global__ __launch_bounds__(AB4_TB) void k4_fwd_atomic_bface(Fwd4 a) {
   __shared__ LdsAcc<AB4_HE, 4> te;
   __shared__ LdsAcc<AB4_HB, 4> tb;
@@ -339,7 +341,7 @@ __global__ __launch_bounds__(AB4_TB) void k4_fwd_atomic_bface(Fwd4 a) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       fv[s] = a.bface[4 * f + s];
-      Q[s] = load_pt4(a.X, fv[s]);
+      Q[s] = node_pt4<AOS>(a, fv[s]);
     }
     const V4 nB =
         v4_scale(1.0 / 6.0, v4_cross(v4_sub(Q[1], Q[0]), v4_sub(Q[2], Q[0]), v4_sub(Q[3], Q[0])));
@@ -500,7 +502,10 @@ int forward4(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
     if (a.vol) EB_TRY(fill_f64(a.vol, sz->n_nodes, 0.0, s));
     if (a.nelem > 0) EB_TRY(elem_pass4(sz, a, ws, s));
     if (a.nbface > 0) {
-      launch_span(k4_fwd_atomic_bface, dim3(grid_for(a.nbface, 256)), dim3(256), 0, s, a);
+      if (a.xa)
+        launch_span(k4_fwd_atomic_bface<true>, dim3(grid_for(a.nbface, 256)), dim3(256), 0, s, a);
+      else
+        launch_span(k4_fwd_atomic_bface<false>, dim3(grid_for(a.nbface, 256)), dim3(256), 0, s, a);
       EB_LAUNCH_CHECK();
     }
     return EB_OK;
@@ -509,7 +514,10 @@ int forward4(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
   EB_TRY(node_pass4(sz, a, ws, s));
   EB_LAUNCH_CHECK();
   if (a.nbnode > 0) {
-    launch_span(k4_fwd_boundary, dim3(grid_for(a.nbnode, 64 / B4_G)), dim3(64), 0, s, a);
+    if (a.xa)
+      launch_span(k4_fwd_boundary<true>, dim3(grid_for(a.nbnode, 64 / B4_G)), dim3(64), 0, s, a);
+    else
+      launch_span(k4_fwd_boundary<false>, dim3(grid_for(a.nbnode, 64 / B4_G)), dim3(64), 0, s, a);
     EB_LAUNCH_CHECK();
   }
   return EB_OK;
