@@ -363,19 +363,21 @@ __global__ __launch_bounds__(AB4_TB) void k4_fwd_atomic_bface(Fwd4 a) {
 
 // edge loop: t_e = (x_head - x_tail).n_e / 8, then each node's ordered sum
 // over its out-edges and in-edges (gather) or atomics at both ends
+template <bool AOS>
 __device__ __forceinline__ double edge_term4(const Fwd4 &a, const double *const *n, int64_t e) {
-  const V4 d = v4_sub(load_pt4(a.X, a.edge_head[e]), load_pt4(a.X, a.edge_tail[e]));
+  const V4 d = v4_sub(node_pt4<AOS>(a, a.edge_head[e]), node_pt4<AOS>(a, a.edge_tail[e]));
   return (d.c[0] * n[0][e] + d.c[1] * n[1][e] + d.c[2] * n[2][e] + d.c[3] * n[3][e]) *
          (1.0 / 8.0);
 }
 
+template <bool AOS>
 __global__ __launch_bounds__(256) void k4_vol_edge_terms(Fwd4 a, const double *n0,
                                                         const double *n1, const double *n2,
                                                         const double *n3) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= a.nedge) return;
   const double *n[4] = {n0, n1, n2, n3};
-  a.term[e] = edge_term4(a, n, e);
+  a.term[e] = edge_term4<AOS>(a, n, e);
 }
 
 __global__ __launch_bounds__(256) void k4_vol_edge_sum(Fwd4 a) {
@@ -385,13 +387,14 @@ __global__ __launch_bounds__(256) void k4_vol_edge_sum(Fwd4 a) {
   a.vol[j] = sum_terms_at<false>(V, a.term, a.node_in_edge, a.node_in_off[j], a.node_in_off[j + 1]);
 }
 
+template <bool AOS>
 __global__ __launch_bounds__(256) void k4_vol_edge_atomic(Fwd4 a, const double *n0,
                                                          const double *n1, const double *n2,
                                                          const double *n3) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= a.nedge) return;
   const double *n[4] = {n0, n1, n2, n3};
-  const double t = edge_term4(a, n, e);
+  const double t = edge_term4<AOS>(a, n, e);
   unsafeAtomicAdd(&a.vol[a.edge_tail[e]], t);
   unsafeAtomicAdd(&a.vol[a.edge_head[e]], t);
 }
@@ -436,11 +439,13 @@ void rows4(double *p, int64_t n, double *(&r)[4]) {
 
 // the points copied as 32-byte rows into the workspace's incidence-row
 // region (80 bytes per element, free once the build is done) when they fit
-// there (else null, and the kernels read the coordinate rows)
-const double4 *point_rows4(const eb_sizes *sz, const Fwd4 &a, void *ws, hipStream_t s) {
+// there, past its first `skip` bytes (else null, and the kernels read the
+// coordinate rows)
+const double4 *point_rows4(const eb_sizes *sz, const Fwd4 &a, void *ws, hipStream_t s,
+                           size_t skip = 0) {
   const WsLayout L = ws_layout(4, sz->n_nodes, sz->n_elems);
-  if ((size_t)32 * (size_t)sz->n_nodes > L.inc_pos - L.rows4) return nullptr;
-  double4 *xa = ws_at<double4>(ws, L.rows4);
+  if (skip + (size_t)32 * (size_t)sz->n_nodes > L.inc_pos - L.rows4) return nullptr;
+  double4 *xa = ws_at<double4>(ws, L.rows4 + skip);
   launch_span(k4_points_rows, dim3(grid_for(a.nv, 256)), dim3(256), 0, s, a.X, a.nv, xa);
   return xa;
 }
@@ -554,19 +559,31 @@ int volumes4(const eb_sizes *sz, const eb_topology *tp, const int32_t *elem,
   if (reduce == EB_REDUCE_ATOMIC) {
     EB_TRY(fill_f64(vol, sz->n_nodes, 0.0, s));
     if (a.nedge > 0) {
-      launch_principal(k4_vol_edge_atomic, dim3(grid_for(a.nedge, 256)), dim3(256), 0, s, a,
-                       n[0], n[1], n[2], n[3]);
+      a.xa = point_rows4(sz, a, ws, s);
+      EB_LAUNCH_CHECK();
+      if (a.xa)
+        launch_principal(k4_vol_edge_atomic<true>, dim3(grid_for(a.nedge, 256)), dim3(256), 0, s,
+                         a, n[0], n[1], n[2], n[3]);
+      else
+        launch_principal(k4_vol_edge_atomic<false>, dim3(grid_for(a.nedge, 256)), dim3(256), 0,
+                         s, a, n[0], n[1], n[2], n[3]);
       EB_LAUNCH_CHECK();
     }
     return EB_OK;
   }
   EB_TRY(need(a.node_edge_off && a.node_in_off && a.node_in_edge, "node_edge_off, node_in"));
   // per-edge terms in the workspace's incidence-row region (80 bytes per
-  // element there, against 8 per edge)
+  // element there, against 8 per edge), the point rows after them
   a.term = ws_at<double>(ws, ws_layout(4, sz->n_nodes, sz->n_elems).rows4);
   if (a.nedge > 0) {
-    launch_principal(k4_vol_edge_terms, dim3(grid_for(a.nedge, 256)), dim3(256), 0, s, a, n[0],
-                     n[1], n[2], n[3]);
+    a.xa = point_rows4(sz, a, ws, s, align256(sizeof(double) * (size_t)a.nedge));
+    EB_LAUNCH_CHECK();
+    if (a.xa)
+      launch_principal(k4_vol_edge_terms<true>, dim3(grid_for(a.nedge, 256)), dim3(256), 0, s, a,
+                       n[0], n[1], n[2], n[3]);
+    else
+      launch_principal(k4_vol_edge_terms<false>, dim3(grid_for(a.nedge, 256)), dim3(256), 0, s,
+                       a, n[0], n[1], n[2], n[3]);
     EB_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k4_vol_edge_sum, dim3(grid_for(a.nv, 256)), dim3(256), 0, s, a);
