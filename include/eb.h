@@ -217,10 +217,11 @@ int eb_build_edges_emit(const eb_sizes *sizes, const int32_t *elem, const double
  *     edge, node_bnode, bnode_face_off/bnode_face, bface.  Boundary nodes
  *     follow in a second pass, a group of lanes each.  dim 4: one thread per
  *     node walks its node_inc row (no plan).
- *   dim 4, both reductions (and eb_dual_volumes with EB_VOL_ELEMENT): the
- *     points are first copied as 32-byte rows into ws, in space the build
- *     uses only until eb_build_edges_emit, when 32 n_nodes bytes fit there
- *     (80 per element); otherwise the kernels read coords directly. */
+ *   dim 4, both reductions (and eb_dual_volumes, both modes): the points
+ *     are first copied as 32-byte rows into ws, in space the build uses only
+ *     until eb_build_edges_emit, when 32 n_nodes bytes fit there (80 per
+ *     element, less the edge loop's 8 per edge); otherwise the kernels read
+ *     coords directly. */
 int eb_directed_areas(const eb_sizes *sizes, const eb_topology *topo, const int32_t *elem,
                       const double *coords, int reduce, double *n_edge, double *b_node,
                       double *vol, void *ws, size_t ws_bytes, hipStream_t stream);
